@@ -1,0 +1,712 @@
+/*
+ * sdq_oracle.c -- plain, slow, FP64 CPU oracle for the stabilized DQMC
+ * Green's functions of C. Bauer, "Fast and stable determinant quantum Monte
+ * Carlo" (SciPost Phys. 2020, arXiv:2003.05286).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing here is part of the GPU library: only
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load this file's shared object.  It shares no code, header, table or helper
+ * with the HIP path, and it uses no BLAS/LAPACK: every product, pivoted QR,
+ * LU and inverse is a plain loop written here, in the order the paper states
+ * the steps, with no blocking or reordering.
+ *
+ * Conventions: every matrix is n x n, row-major, A[i*n + j].  Slice l
+ * (1-based, 1 <= l <= m) uses field row l-1:
+ *     B_l = expk * diag(exp(alpha * field[l-1][:]))          (Sec. 2, Sec. 3)
+ * expk_inv must be the inverse of expk (exp(+dtau K)).
+ *
+ * Functions and the passages they follow:
+ *   chain_udt          Sec. 4.1 (stabilized product "fact_mult", with the
+ *                      naive/stabilized mixture every k slices) and
+ *                      Sec. 4.2.2 (UDT from column-pivoted QR)
+ *   cpqr               Sec. 4.2.2 (pivoted Householder QR, as LAPACK geqp3;
+ *                      column-norm downdating after Drmac & Bujanovic 2008)
+ *   inv_one_plus_loh   Sec. 5.1, scheme inv_one_plus_loh (D = Dp * Dm split)
+ *   inv_one_plus       Sec. 5.1, scheme inv_one_plus (single decomposition)
+ *   inv_sum_loh        Sec. 6.1, scheme inv_sum_loh (time-displaced)
+ *   inv_sum            Sec. 6.1, scheme inv_sum
+ *   or_greens_slice    App. A.1 (combining two stack elements into G_l),
+ *                      G_l defined in Sec. 6 (equal-time G at slice l)
+ *   or_logdet_grad     d log|det(1+B_M..B_1)| / d f_{l,i} = alpha (1-G_l)_ii
+ *                      (Jacobi's formula; see the function comment)
+ *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
+ * Readings of passages that are ambiguous or garbled in the paper are noted
+ * where they are used.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sdq_oracle.h"
+
+/* ------------------------------------------------------------------------ */
+/* small dense helpers                                                      */
+
+static double* mat_new(int n) { return (double*)calloc((size_t)n * n, sizeof(double)); }
+
+static void mat_eye(int n, double* A) {
+  memset(A, 0, sizeof(double) * (size_t)n * n);
+  for (int i = 0; i < n; ++i) A[i * n + i] = 1.0;
+}
+
+static void mat_copy(int n, const double* A, double* B) {
+  memcpy(B, A, sizeof(double) * (size_t)n * n);
+}
+
+/* C = A * B  (C must not alias A or B) */
+static void mat_mul(int n, const double* A, const double* B, double* C) {
+  for (int i = 0; i < n; ++i) {
+    double* c = C + (size_t)i * n;
+    for (int j = 0; j < n; ++j) c[j] = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const double a = A[(size_t)i * n + p];
+      const double* b = B + (size_t)p * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
+    }
+  }
+}
+
+/* C = A^T * B */
+static void mat_mul_tn(int n, const double* A, const double* B, double* C) {
+  for (int i = 0; i < n * n; ++i) C[i] = 0.0;
+  for (int p = 0; p < n; ++p)
+    for (int i = 0; i < n; ++i) {
+      const double a = A[(size_t)p * n + i];
+      for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += a * B[(size_t)p * n + j];
+    }
+}
+
+/* C = A * B^T */
+static void mat_mul_nt(int n, const double* A, const double* B, double* C) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s += A[(size_t)i * n + p] * B[(size_t)j * n + p];
+      C[(size_t)i * n + j] = s;
+    }
+}
+
+/* A <- diag(d) * A */
+static void scale_rows(int n, double* A, const double* d) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] *= d[i];
+}
+
+/* A <- A * diag(d) */
+static void scale_cols(int n, double* A, const double* d) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] *= d[j];
+}
+
+/* Euclidean norm of x[0], x[inc], ... with the running scale/sum-of-squares
+ * update, so that entries near 1e+-200 neither overflow nor underflow. */
+static double nrm2(int len, const double* x, int inc) {
+  double scale = 0.0, ssq = 1.0;
+  for (int i = 0; i < len; ++i) {
+    const double a = fabs(x[(size_t)i * inc]);
+    if (a == 0.0) continue;
+    if (scale < a) {
+      ssq = 1.0 + ssq * (scale / a) * (scale / a);
+      scale = a;
+    } else {
+      ssq += (a / scale) * (a / scale);
+    }
+  }
+  return scale * sqrt(ssq);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Column-pivoted Householder QR (Businger-Golub), in place on a row-major
+ * n x n matrix A.  On return the upper triangle holds R, the strict lower
+ * triangle holds the Householder vectors (unit leading entry implied),
+ * tau[j] their scalars, and jpvt[j] the original index of the column moved to
+ * position j, so that  A_in * P = Q * R  with  P[jpvt[j]][j] = 1  and
+ * Q = H_0 H_1 ... H_{n-1},  H_j = I - tau_j v_j v_j^T.
+ *
+ * Pivot rule: the first column (in current order) of maximal remaining norm.
+ * Reflector: beta = -sign(alpha) ||x||, v = x / (alpha - beta), tau =
+ * (beta - alpha) / beta (tau = 0 when the column below the diagonal is zero).
+ * Norm downdating: vn1 <- vn1 sqrt(1 - (|r|/vn1)^2), with an exact recompute
+ * when (1 - (|r|/vn1)^2)(vn1/vn2)^2 <= sqrt(eps) (Drmac & Bujanovic 2008). */
+static void cpqr(int n, double* A, int* jpvt, double* tau) {
+  double* vn1 = (double*)malloc(sizeof(double) * n);
+  double* vn2 = (double*)malloc(sizeof(double) * n);
+  const double tol3z = sqrt(2.220446049250313e-16);
+  for (int j = 0; j < n; ++j) {
+    jpvt[j] = j;
+    vn1[j] = nrm2(n, A + j, n);
+    vn2[j] = vn1[j];
+  }
+  for (int i = 0; i < n; ++i) {
+    /* pivot */
+    int p = i;
+    for (int j = i + 1; j < n; ++j)
+      if (vn1[j] > vn1[p]) p = j;
+    if (p != i) {
+      for (int r = 0; r < n; ++r) {
+        double t = A[(size_t)r * n + i];
+        A[(size_t)r * n + i] = A[(size_t)r * n + p];
+        A[(size_t)r * n + p] = t;
+      }
+      int tj = jpvt[i]; jpvt[i] = jpvt[p]; jpvt[p] = tj;
+      vn1[p] = vn1[i];
+      vn2[p] = vn2[i];
+    }
+    /* reflector for A[i:, i] */
+    const double alpha = A[(size_t)i * n + i];
+    const double xnorm = (i + 1 < n) ? nrm2(n - i - 1, A + (size_t)(i + 1) * n + i, n) : 0.0;
+    double t_i = 0.0;
+    if (xnorm != 0.0) {
+      const double beta = -copysign(hypot(alpha, xnorm), alpha);
+      t_i = (beta - alpha) / beta;
+      const double s = 1.0 / (alpha - beta);
+      for (int r = i + 1; r < n; ++r) A[(size_t)r * n + i] *= s;
+      A[(size_t)i * n + i] = beta;
+    }
+    tau[i] = t_i;
+    /* apply H_i to the trailing columns */
+    if (t_i != 0.0) {
+      for (int j = i + 1; j < n; ++j) {
+        double w = A[(size_t)i * n + j];
+        for (int r = i + 1; r < n; ++r) w += A[(size_t)r * n + i] * A[(size_t)r * n + j];
+        w *= t_i;
+        A[(size_t)i * n + j] -= w;
+        for (int r = i + 1; r < n; ++r) A[(size_t)r * n + j] -= w * A[(size_t)r * n + i];
+      }
+    }
+    /* downdate the remaining column norms */
+    for (int j = i + 1; j < n; ++j) {
+      if (vn1[j] == 0.0) continue;
+      double temp = fabs(A[(size_t)i * n + j]) / vn1[j];
+      temp = 1.0 - temp * temp;
+      if (temp < 0.0) temp = 0.0;
+      const double ratio = vn1[j] / vn2[j];
+      const double temp2 = temp * ratio * ratio;
+      if (temp2 <= tol3z) {
+        vn1[j] = (i + 1 < n) ? nrm2(n - i - 1, A + (size_t)(i + 1) * n + j, n) : 0.0;
+        vn2[j] = vn1[j];
+      } else {
+        vn1[j] *= sqrt(temp);
+      }
+    }
+  }
+  free(vn1);
+  free(vn2);
+}
+
+/* Q = H_0 H_1 ... H_{n-1} from the reflectors stored by cpqr. */
+static void form_q(int n, const double* F, const double* tau, double* Q) {
+  mat_eye(n, Q);
+  for (int i = n - 1; i >= 0; --i) {
+    if (tau[i] == 0.0) continue;
+    for (int j = 0; j < n; ++j) {
+      double w = Q[(size_t)i * n + j];
+      for (int r = i + 1; r < n; ++r) w += F[(size_t)r * n + i] * Q[(size_t)r * n + j];
+      w *= tau[i];
+      Q[(size_t)i * n + j] -= w;
+      for (int r = i + 1; r < n; ++r) Q[(size_t)r * n + j] -= w * F[(size_t)r * n + i];
+    }
+  }
+}
+
+/* parity of the permutation j -> jpvt[j]: +1 or -1 */
+static double perm_sign(int n, const int* jpvt) {
+  char* seen = (char*)calloc(n, 1);
+  int cycles = 0;
+  for (int i = 0; i < n; ++i) {
+    if (seen[i]) continue;
+    ++cycles;
+    for (int j = i; !seen[j]; j = jpvt[j]) seen[j] = 1;
+  }
+  free(seen);
+  return ((n - cycles) % 2 == 0) ? 1.0 : -1.0;
+}
+
+/* UDT decomposition (Sec. 4.2.2): W P = Q R, U = Q, D = |diag R|,
+ * T = D^{-1} R P^T.  D is taken as the absolute value of diag R so that the
+ * Dp/Dm split of Sec. 5.1 sees positive scales; the signs stay in T.  With
+ * pivoting T is not triangular (the paper's "T upper triangular" holds for
+ * R, not for R P^T). */
+static void udt(int n, const double* W, double* U, double* D, double* T) {
+  double* F = mat_new(n);
+  double* tau = (double*)malloc(sizeof(double) * n);
+  int* jpvt = (int*)malloc(sizeof(int) * n);
+  mat_copy(n, W, F);
+  cpqr(n, F, jpvt, tau);
+  form_q(n, F, tau, U);
+  for (int i = 0; i < n; ++i) D[i] = fabs(F[(size_t)i * n + i]);
+  /* T[i][jpvt[j]] = R[i][j] / D[i] */
+  memset(T, 0, sizeof(double) * (size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) T[(size_t)i * n + jpvt[j]] = F[(size_t)i * n + j] / D[i];
+  free(F);
+  free(tau);
+  free(jpvt);
+}
+
+/* Inverse with log|det| and sign of det via Gaussian elimination with
+ * partial pivoting (Gauss-Jordan on [A | I]). */
+static void lu_inverse(int n, const double* A, double* Ainv, double* logabsdet, double* sgn) {
+  double* W = mat_new(n);
+  mat_copy(n, A, W);
+  mat_eye(n, Ainv);
+  double ld = 0.0, sg = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(W[(size_t)r * n + c]) > fabs(W[(size_t)p * n + c])) p = r;
+    if (p != c) {
+      for (int j = 0; j < n; ++j) {
+        double t = W[(size_t)c * n + j]; W[(size_t)c * n + j] = W[(size_t)p * n + j]; W[(size_t)p * n + j] = t;
+        t = Ainv[(size_t)c * n + j]; Ainv[(size_t)c * n + j] = Ainv[(size_t)p * n + j]; Ainv[(size_t)p * n + j] = t;
+      }
+      sg = -sg;
+    }
+    const double piv = W[(size_t)c * n + c];
+    ld += log(fabs(piv));
+    if (piv < 0) sg = -sg;
+    const double ip = 1.0 / piv;
+    for (int j = 0; j < n; ++j) { W[(size_t)c * n + j] *= ip; Ainv[(size_t)c * n + j] *= ip; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = W[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        W[(size_t)r * n + j] -= f * W[(size_t)c * n + j];
+        Ainv[(size_t)r * n + j] -= f * Ainv[(size_t)c * n + j];
+      }
+    }
+  }
+  if (logabsdet) *logabsdet = ld;
+  if (sgn) *sgn = sg;
+  free(W);
+}
+
+/* M^{-1} through the udx (pivoted QR) of M:  M P = Q R  =>
+ * M^{-1} = P R^{-1} Q^T.  Also log|det M| and sign det M
+ * (det Q = (-1)^{#reflections}, det P = permutation parity). */
+static void qr_inverse(int n, const double* M, double* Minv, double* logabsdet, double* sgn) {
+  double* F = mat_new(n);
+  double* Q = mat_new(n);
+  double* Z = mat_new(n);
+  double* tau = (double*)malloc(sizeof(double) * n);
+  int* jpvt = (int*)malloc(sizeof(int) * n);
+  mat_copy(n, M, F);
+  cpqr(n, F, jpvt, tau);
+  form_q(n, F, tau, Q);
+  /* Z = R^{-1} Q^T by back substitution, column by column of Q^T */
+  for (int c = 0; c < n; ++c) {
+    for (int i = n - 1; i >= 0; --i) {
+      double s = Q[(size_t)c * n + i]; /* (Q^T)[i][c] */
+      for (int j = i + 1; j < n; ++j) s -= F[(size_t)i * n + j] * Z[(size_t)j * n + c];
+      Z[(size_t)i * n + c] = s / F[(size_t)i * n + i];
+    }
+  }
+  /* Minv = P Z : row j of Z goes to row jpvt[j] */
+  for (int j = 0; j < n; ++j)
+    memcpy(Minv + (size_t)jpvt[j] * n, Z + (size_t)j * n, sizeof(double) * n);
+  double ld = 0.0, sg = perm_sign(n, jpvt);
+  for (int i = 0; i < n; ++i) {
+    const double r = F[(size_t)i * n + i];
+    ld += log(fabs(r));
+    if (r < 0) sg = -sg;
+    if (tau[i] != 0.0) sg = -sg;
+  }
+  if (logabsdet) *logabsdet = ld;
+  if (sgn) *sgn = sg;
+  free(F); free(Q); free(Z); free(tau); free(jpvt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* slices and stabilized chains                                             */
+
+typedef struct {
+  int n, m, k;
+  const double* expk;
+  const double* expk_inv;
+  const double* field;
+  double alpha;
+} problem;
+
+enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2 };
+
+/* W <- X_q W with X_q = B_q, B_q^{-1} or B_q^T (q is 1-based). */
+static void apply_slice(const problem* P, int kind, int q, double* W, double* tmp) {
+  const int n = P->n;
+  double* v = (double*)malloc(sizeof(double) * n);
+  for (int i = 0; i < n; ++i) v[i] = exp(P->alpha * P->field[(size_t)(q - 1) * n + i]);
+  if (kind == SLICE_B) {             /* B_q = E diag(v) */
+    scale_rows(n, W, v);
+    mat_mul(n, P->expk, W, tmp);
+    mat_copy(n, tmp, W);
+  } else if (kind == SLICE_BINV) {   /* B_q^{-1} = diag(1/v) E^{-1} */
+    mat_mul(n, P->expk_inv, W, tmp);
+    for (int i = 0; i < n; ++i) v[i] = 1.0 / v[i];
+    scale_rows(n, tmp, v);
+    mat_copy(n, tmp, W);
+  } else {                           /* B_q^T = diag(v) E^T */
+    mat_mul_tn(n, P->expk, W, tmp);
+    scale_rows(n, tmp, v);
+    mat_copy(n, tmp, W);
+  }
+  free(v);
+}
+
+/* UDT of the product X_{q_count-1} ... X_{q_1} X_{q_0} (applied in the order
+ * given by `order`), starting from U = I, D = 1, T = I.  Every k slices the
+ * naively multiplied block is folded in with the stabilized product of
+ * Sec. 4.1:  block * (U D T) = ((block U) D) T = (U' D' T') T, i.e.
+ * U <- U', D <- D', T <- T' T. */
+static void chain_udt(const problem* P, int kind, const int* order, int count,
+                      double* U, double* D, double* T) {
+  const int n = P->n;
+  double* W = mat_new(n);
+  double* tmp = mat_new(n);
+  double* Tp = mat_new(n);
+  double* T2 = mat_new(n);
+  mat_eye(n, U);
+  mat_eye(n, T);
+  for (int i = 0; i < n; ++i) D[i] = 1.0;
+  int pos = 0;
+  while (pos < count) {
+    const int end = (pos + P->k < count) ? pos + P->k : count;
+    mat_copy(n, U, W);
+    for (int s = pos; s < end; ++s) apply_slice(P, kind, order[s], W, tmp);
+    scale_cols(n, W, D);
+    udt(n, W, U, D, Tp);
+    mat_mul(n, Tp, T, T2);
+    mat_copy(n, T2, T);
+    pos = end;
+  }
+  free(W); free(tmp); free(Tp); free(T2);
+}
+
+/* forward chain B_b ... B_a  (slices a..b, a <= b; empty if a > b) */
+static void chain_fwd(const problem* P, int a, int b, double* U, double* D, double* T) {
+  const int cnt = b >= a ? b - a + 1 : 0;
+  int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
+  for (int s = 0; s < cnt; ++s) order[s] = a + s;
+  chain_udt(P, SLICE_B, order, cnt, U, D, T);
+  free(order);
+}
+
+/* B_a^{-1} ... B_b^{-1}: applied as W <- B_q^{-1} W for q = b, b-1, ..., a */
+static void chain_inv(const problem* P, int a, int b, double* U, double* D, double* T) {
+  const int cnt = b >= a ? b - a + 1 : 0;
+  int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
+  for (int s = 0; s < cnt; ++s) order[s] = b - s;
+  chain_udt(P, SLICE_BINV, order, cnt, U, D, T);
+  free(order);
+}
+
+/* B_a^T ... B_b^T = (B_b ... B_a)^T: W <- B_q^T W for q = b, ..., a */
+static void chain_trn(const problem* P, int a, int b, double* U, double* D, double* T) {
+  const int cnt = b >= a ? b - a + 1 : 0;
+  int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
+  for (int s = 0; s < cnt; ++s) order[s] = b - s;
+  chain_udt(P, SLICE_BT, order, cnt, U, D, T);
+  free(order);
+}
+
+/* ------------------------------------------------------------------------ */
+/* inversion schemes                                                        */
+
+/* Sec. 5.1, inv_one_plus_loh:  with Dp = max(D,1), Dm = min(D,1),
+ *   1 + U D X = (X^{-1} Dp^{-1} + U Dm) Dp X
+ *   G = X^{-1} Dp^{-1} M^{-1},   M = X^{-1} Dp^{-1} + U Dm,
+ * M inverted through its udx.  det(1 + UDX) = det M * prod(Dp) * det X. */
+static void inv_one_plus_loh(int n, const double* U, const double* D, const double* X,
+                             double* G, double* logdet, double* sgn) {
+  double* Xi = mat_new(n);
+  double* Mm = mat_new(n);
+  double* Mi = mat_new(n);
+  double* tmp = mat_new(n);
+  double* dpi = (double*)malloc(sizeof(double) * n);
+  double* dm = (double*)malloc(sizeof(double) * n);
+  double ldx, sx, ldm, sm, ld = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double dp = D[i] > 1.0 ? D[i] : 1.0;
+    dpi[i] = 1.0 / dp;
+    dm[i] = D[i] < 1.0 ? D[i] : 1.0;
+    ld += log(dp);
+  }
+  lu_inverse(n, X, Xi, &ldx, &sx);
+  /* M = Xi Dp^{-1} + U Dm */
+  mat_copy(n, Xi, Mm);
+  scale_cols(n, Mm, dpi);
+  mat_copy(n, U, tmp);
+  scale_cols(n, tmp, dm);
+  for (int i = 0; i < n * n; ++i) Mm[i] += tmp[i];
+  qr_inverse(n, Mm, Mi, &ldm, &sm);
+  /* G = Xi (Dp^{-1} Mi) */
+  scale_rows(n, Mi, dpi);
+  mat_mul(n, Xi, Mi, G);
+  if (logdet) *logdet = ld + ldm + ldx;
+  if (sgn) *sgn = sm * sx;
+  free(Xi); free(Mm); free(Mi); free(tmp); free(dpi); free(dm);
+}
+
+/* Sec. 5.1, inv_one_plus:  1 + U D X = U (U^T X^{-1} + D) X,
+ * G = X^{-1} (U^T X^{-1} + D)^{-1} U^T. */
+static void inv_one_plus(int n, const double* U, const double* D, const double* X,
+                         double* G, double* logdet, double* sgn) {
+  double* Xi = mat_new(n);
+  double* Mm = mat_new(n);
+  double* Mi = mat_new(n);
+  double* tmp = mat_new(n);
+  double ldx, sx, ldm, sm, ldu, su;
+  lu_inverse(n, X, Xi, &ldx, &sx);
+  mat_mul_tn(n, U, Xi, Mm);
+  for (int i = 0; i < n; ++i) Mm[(size_t)i * n + i] += D[i];
+  qr_inverse(n, Mm, Mi, &ldm, &sm);
+  mat_mul_nt(n, Mi, U, tmp);   /* Mi U^T */
+  mat_mul(n, Xi, tmp, G);
+  lu_inverse(n, U, tmp, &ldu, &su);
+  if (logdet) *logdet = ldm + ldx + ldu;
+  if (sgn) *sgn = sm * sx * su;
+  free(Xi); free(Mm); free(Mi); free(tmp);
+}
+
+/* Sec. 6.1, inv_sum_loh.  G = [U_L D_L X_L + U_R D_R X_R]^{-1} with
+ *   Mid = D_Lm (X_L X_R^{-1}) D_Rp^{-1} + D_Lp^{-1} (U_L^T U_R) D_Rm
+ *   G   = X_R^{-1} D_Rp^{-1} Mid^{-1} D_Lp^{-1} U_L^T.
+ * Reading: the printed middle matrix is garbled (fractions of diagonal
+ * matrices and a swapped "X_R D_Rp"); we read D_Lm/D_Rp as a left factor D_Lm
+ * and a right factor D_Rp^{-1} (likewise D_Rm/D_Lp), and the tail as
+ * D_Rp X_R, which is what the paper's next line requires. */
+static void inv_sum_loh(int n, const double* UL, const double* DL, const double* XL,
+                        const double* UR, const double* DR, const double* XR, double* G) {
+  double* XRi = mat_new(n);
+  double* A = mat_new(n);
+  double* B = mat_new(n);
+  double* Mi = mat_new(n);
+  double* tmp = mat_new(n);
+  double *dlm = malloc(sizeof(double) * n), *dlpi = malloc(sizeof(double) * n);
+  double *drm = malloc(sizeof(double) * n), *drpi = malloc(sizeof(double) * n);
+  for (int i = 0; i < n; ++i) {
+    dlm[i] = DL[i] < 1.0 ? DL[i] : 1.0;
+    dlpi[i] = 1.0 / (DL[i] > 1.0 ? DL[i] : 1.0);
+    drm[i] = DR[i] < 1.0 ? DR[i] : 1.0;
+    drpi[i] = 1.0 / (DR[i] > 1.0 ? DR[i] : 1.0);
+  }
+  lu_inverse(n, XR, XRi, NULL, NULL);
+  mat_mul(n, XL, XRi, A);      /* X_L X_R^{-1} */
+  scale_rows(n, A, dlm);
+  scale_cols(n, A, drpi);
+  mat_mul_tn(n, UL, UR, B);    /* U_L^T U_R */
+  scale_rows(n, B, dlpi);
+  scale_cols(n, B, drm);
+  for (int i = 0; i < n * n; ++i) A[i] += B[i];
+  qr_inverse(n, A, Mi, NULL, NULL);
+  /* G = XRi (D_Rp^{-1} (Mi (D_Lp^{-1} U_L^T))) */
+  scale_rows(n, Mi, drpi);
+  scale_cols(n, Mi, dlpi);
+  mat_mul_nt(n, Mi, UL, tmp);
+  mat_mul(n, XRi, tmp, G);
+  free(XRi); free(A); free(B); free(Mi); free(tmp);
+  free(dlm); free(dlpi); free(drm); free(drpi);
+}
+
+/* Sec. 6.1, inv_sum:  Mid = D_L X_L X_R^{-1} + U_L^T U_R D_R,
+ * G = X_R^{-1} Mid^{-1} U_L^T.  (The printed bracket carries d^{-1}; with
+ * D_r = d^{-1} the bracket holds the plain udx, which is what we use.) */
+static void inv_sum(int n, const double* UL, const double* DL, const double* XL,
+                    const double* UR, const double* DR, const double* XR, double* G) {
+  double* XRi = mat_new(n);
+  double* A = mat_new(n);
+  double* B = mat_new(n);
+  double* Mi = mat_new(n);
+  double* tmp = mat_new(n);
+  lu_inverse(n, XR, XRi, NULL, NULL);
+  mat_mul(n, XL, XRi, A);
+  scale_rows(n, A, DL);
+  mat_mul_tn(n, UL, UR, B);
+  scale_cols(n, B, DR);
+  for (int i = 0; i < n * n; ++i) A[i] += B[i];
+  qr_inverse(n, A, Mi, NULL, NULL);
+  mat_mul_nt(n, Mi, UL, tmp);
+  mat_mul(n, XRi, tmp, G);
+  free(XRi); free(A); free(B); free(Mi); free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported entry points                                                    */
+
+static int check(int n, int m, int k, const double* expk, const double* field) {
+  if (n <= 0 || m <= 0 || k <= 0 || !expk || !field) return OR_EINVAL;
+  for (size_t i = 0; i < (size_t)m * n; ++i)
+    if (!isfinite(field[i])) return OR_ERANGE;
+  return OR_OK;
+}
+
+static int finite_all(int n, const double* A) {
+  for (size_t i = 0; i < (size_t)n * n; ++i)
+    if (!isfinite(A[i])) return 0;
+  return 1;
+}
+
+int or_greens(int n, int m, int k, const double* expk, const double* field, double alpha,
+              int scheme, double* G, double* logdet, double* sign) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  problem P = {n, m, k, expk, NULL, field, alpha};
+  double* U = mat_new(n);
+  double* T = mat_new(n);
+  double* D = (double*)malloc(sizeof(double) * n);
+  chain_fwd(&P, 1, m, U, D, T);
+  if (scheme == OR_SCHEME_PLAIN)
+    inv_one_plus(n, U, D, T, G, logdet, sign);
+  else
+    inv_one_plus_loh(n, U, D, T, G, logdet, sign);
+  free(U); free(T); free(D);
+  return finite_all(n, G) ? OR_OK : OR_ERANGE;
+}
+
+/* G(tau_l, 0) for 0 <= l <= m (Sec. 6): with tau_2 = 0,
+ *   G(tau_l, 0) = [B_1^{-1} ... B_l^{-1} + B_M ... B_{l+1}]^{-1}
+ * where each of the two chains is brought to UDX form on its own (left:
+ * U_L D_L X_L, right: U_R D_R X_R) and the sum is inverted by inv_sum_loh
+ * (scheme OR_SCHEME_LOH) or inv_sum (OR_SCHEME_PLAIN). */
+int or_greens_tdisp(int n, int m, int k, const double* expk, const double* expk_inv,
+                    const double* field, double alpha, int l, int scheme, double* Gt) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  if (!expk_inv || l < 0 || l > m) return OR_EINVAL;
+  problem P = {n, m, k, expk, expk_inv, field, alpha};
+  double *UL = mat_new(n), *XL = mat_new(n), *UR = mat_new(n), *XR = mat_new(n);
+  double *DL = malloc(sizeof(double) * n), *DR = malloc(sizeof(double) * n);
+  chain_inv(&P, 1, l, UL, DL, XL);
+  chain_fwd(&P, l + 1, m, UR, DR, XR);
+  if (scheme == OR_SCHEME_PLAIN)
+    inv_sum(n, UL, DL, XL, UR, DR, XR, Gt);
+  else
+    inv_sum_loh(n, UL, DL, XL, UR, DR, XR, Gt);
+  free(UL); free(XL); free(UR); free(XR); free(DL); free(DR);
+  return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
+}
+
+/* Equal-time G at slice l, 1 <= l <= m (Sec. 6 definition),
+ *   G_l = [1 + B_{l-1} ... B_1 B_M ... B_l]^{-1},
+ * combined from two stack elements as in App. A.1:
+ *   B_{l-1}...B_1 = U_L D_L T_L,   (B_M...B_l)^T = U_R D_R T_R,
+ *   1 + U_L D_L T_L (U_R D_R T_R)^T = 1 + U_L [D_L (T_L T_R^T) D_R] U_R^T,
+ * udt of the bracket = u d t, then U = U_L u, D = d, T = t U_R^T and the
+ * equal-time scheme inv_one_plus_loh.  logdet/sign of det(1 + ...) too
+ * (the same for every l: det is invariant under the cyclic shift). */
+int or_greens_slice(int n, int m, int k, const double* expk, const double* field,
+                    double alpha, int l, double* Gl, double* logdet, double* sign) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  if (l < 1 || l > m) return OR_EINVAL;
+  problem P = {n, m, k, expk, NULL, field, alpha};
+  double *UL = mat_new(n), *TL = mat_new(n), *UR = mat_new(n), *TR = mat_new(n);
+  double *DL = malloc(sizeof(double) * n), *DR = malloc(sizeof(double) * n);
+  double *Mm = mat_new(n), *u = mat_new(n), *t = mat_new(n), *d = malloc(sizeof(double) * n);
+  double *U = mat_new(n), *T = mat_new(n);
+  chain_fwd(&P, 1, l - 1, UL, DL, TL);
+  chain_trn(&P, l, m, UR, DR, TR);
+  mat_mul_nt(n, TL, TR, Mm);
+  scale_rows(n, Mm, DL);
+  scale_cols(n, Mm, DR);
+  udt(n, Mm, u, d, t);
+  mat_mul(n, UL, u, U);
+  mat_mul_nt(n, t, UR, T);
+  inv_one_plus_loh(n, U, d, T, Gl, logdet, sign);
+  free(UL); free(TL); free(UR); free(TR); free(DL); free(DR);
+  free(Mm); free(u); free(t); free(d); free(U); free(T);
+  return finite_all(n, Gl) ? OR_OK : OR_ERANGE;
+}
+
+/* Gradient of log|det(1 + B_M ... B_1)| with respect to the field entries.
+ * dB_l / df_{l,i} = alpha B_l e_i e_i^T, and with X = B_{l-1}...B_1,
+ * Y = B_M...B_l Jacobi's formula gives
+ *   d log|det(1 + Y X)| = tr[(1 + Y X)^{-1} alpha B_M..B_l e_i e_i^T B_{l-1}..B_1]
+ *                       = alpha [X (1 + Y X)^{-1} Y]_ii = alpha (1 - G_l)_ii,
+ * using X (1 + Y X)^{-1} Y = 1 - (1 + X Y)^{-1} and G_l = (1 + X Y)^{-1}.
+ * Every requested G_l is computed from scratch by or_greens_slice.
+ * grad is [n_l][n]: row r holds the gradient for slice l_list[r]. */
+int or_logdet_grad(int n, int m, int k, const double* expk, const double* field, double alpha,
+                   const int* l_list, int n_l, double* grad) {
+  double* Gl = mat_new(n);
+  int st = OR_OK;
+  for (int r = 0; r < n_l && st == OR_OK; ++r) {
+    st = or_greens_slice(n, m, k, expk, field, alpha, l_list[r], Gl, NULL, NULL);
+    for (int i = 0; i < n; ++i) grad[(size_t)r * n + i] = alpha * (1.0 - Gl[(size_t)i * n + i]);
+  }
+  free(Gl);
+  return st;
+}
+
+/* Sec. 3: the unstabilized chain product and a plain inverse of 1 + B
+ * (negative control: fails once exp(bandwidth * beta) exceeds 1/eps). */
+int or_greens_naive(int n, int m, int k, const double* expk, const double* field,
+                    double alpha, double* G) {
+  (void)k;
+  int st = check(n, m, 1, expk, field);
+  if (st) return st;
+  problem P = {n, m, 1, expk, NULL, field, alpha};
+  double *W = mat_new(n), *tmp = mat_new(n);
+  mat_eye(n, W);
+  for (int q = 1; q <= m; ++q) apply_slice(&P, SLICE_B, q, W, tmp);
+  for (int i = 0; i < n; ++i) W[(size_t)i * n + i] += 1.0;
+  lu_inverse(n, W, G, NULL, NULL);
+  free(W); free(tmp);
+  return OR_OK;
+}
+
+/* UDT of a stabilized chain, exposed for the tests: kind 0 = B_b..B_a,
+ * 1 = B_a^{-1}..B_b^{-1}, 2 = B_a^T..B_b^T. */
+int or_chain(int n, int m, int k, const double* expk, const double* expk_inv,
+             const double* field, double alpha, int kind, int a, int b,
+             double* U, double* D, double* T) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  problem P = {n, m, k, expk, expk_inv, field, alpha};
+  if (kind == 0) chain_fwd(&P, a, b, U, D, T);
+  else if (kind == 1) chain_inv(&P, a, b, U, D, T);
+  else chain_trn(&P, a, b, U, D, T);
+  return OR_OK;
+}
+
+/* Pivoted QR exposed for the tests: A (row-major n x n) is overwritten with
+ * R in the upper triangle; Q and jpvt returned. */
+int or_cpqr(int n, double* A, double* Q, int* jpvt) {
+  double* tau = (double*)malloc(sizeof(double) * n);
+  cpqr(n, A, jpvt, tau);
+  form_q(n, A, tau, Q);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) A[(size_t)i * n + j] = 0.0;
+  free(tau);
+  return OR_OK;
+}
+
+int or_udt(int n, const double* W, double* U, double* D, double* T) {
+  udt(n, W, U, D, T);
+  return OR_OK;
+}
+
+/* exp(-s dtau K) for the periodic L x L square lattice with K_ij = -t on
+ * nearest-neighbour bonds, from the plane-wave eigenbasis (Sec. 3 gives the
+ * 1-D dispersion -2t cos k; on the square lattice it is
+ * eps_k = -2t (cos kx + cos ky), k = 2 pi (nx, ny) / L):
+ *   E_ij = (1/N) sum_k exp(-s dtau eps_k) cos(k . (r_i - r_j)). */
+int or_expk_planewave(int L, double t, double dtau, double s, double* out) {
+  if (L < 1) return OR_EINVAL;
+  const int n = L * L;
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    const int xi = i % L, yi = i / L;
+    for (int j = 0; j < n; ++j) {
+      const int dx = xi - j % L, dy = yi - j / L;
+      double acc = 0.0;
+      for (int ny = 0; ny < L; ++ny)
+        for (int nx = 0; nx < L; ++nx) {
+          const double kx = 2.0 * pi * nx / L, ky = 2.0 * pi * ny / L;
+          const double eps = -2.0 * t * (cos(kx) + cos(ky));
+          acc += exp(-s * dtau * eps) * cos(kx * dx + ky * dy);
+        }
+      out[(size_t)i * n + j] = acc / n;
+    }
+  }
+  return OR_OK;
+}

@@ -1,0 +1,353 @@
+"""Pins for the CPU oracle: closed forms, arbitrary-precision brute force,
+exact identities and the paper's negative controls.  CPU only.
+
+Each pin is chosen so that a plausible mistake in the oracle (a dropped term,
+a wrong sign or index, a transposed operand, a wrong block boundary) fails
+at least one of them:
+  * U = 0 and uniform-field closed forms (paper Sec. 3 and the constant-B
+    chain of Sec. 3; the footnote of Sec. 4.1 notes that G at U = 0 follows
+    from diagonalizing the Hamiltonian);
+  * 320-digit brute force of the plain definitions, the paper's own accuracy
+    reference (Sec. 4.3, 5.2, 6.2), including a non-symmetric hopping
+    exponential so that a transposed operand cannot hide;
+  * flavour (particle-hole) symmetry, boundary values G(0,0) = G and
+    G(beta,0) = 1 - G, cyclic invariance of the determinant, the per-slice
+    gradient sum rule and mpmath finite differences;
+  * the naive product and QR + inv_sum at tau = beta/2 must FAIL (Sec. 3,
+    Sec. 6.2).
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from _brute import Brute
+from paper_2003_05286_amd import workloads as wl
+
+
+def relF(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# --------------------------------------------------------------------------
+# inputs and building blocks
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8])
+def test_expk_generator_matches_planewave(L):
+    K = wl.hopping_matrix(L)
+    e, ei = wl.expk_pair(K, 0.1)
+    assert np.abs(e - oracle.expk_planewave(L, 1.0, 0.1, 1.0)).max() < 1e-14
+    assert np.abs(ei - oracle.expk_planewave(L, 1.0, 0.1, -1.0)).max() < 1e-14
+    assert np.abs(e @ ei - np.eye(L * L)).max() < 1e-13
+
+
+def test_hopping_matrix_structure():
+    K = wl.hopping_matrix(4)
+    assert np.allclose(K, K.T)
+    assert np.all(K.sum(axis=1) == -4.0)           # 4 neighbours, t = 1
+    assert K[wl.site(0, 0, 4), wl.site(3, 0, 4)] == -1.0  # periodic wrap in x
+    assert K[wl.site(0, 0, 4), wl.site(0, 3, 4)] == -1.0  # periodic wrap in y
+    assert K[wl.site(1, 1, 4), wl.site(2, 2, 4)] == 0.0
+    assert wl.hirsch_lambda(4.0, 0.1) == pytest.approx(0.653732997987334, abs=1e-14)
+
+
+def _graded(n, rng, spread):
+    A = rng.standard_normal((n, n))
+    d = np.exp(np.linspace(spread, -spread, n))
+    rng.shuffle(d)
+    return A * d
+
+
+@pytest.mark.parametrize("n,spread", [(5, 0.0), (16, 0.0), (16, 200.0), (33, 100.0)])
+def test_cpqr_properties(n, spread):
+    rng = np.random.default_rng(n)
+    A = _graded(n, rng, spread)
+    Q, R, jp = oracle.cpqr(A)
+    AP = A[:, jp]
+    # backward error, column by column (the columns are graded)
+    for j in range(n):
+        assert np.linalg.norm(AP[:, j] - Q @ R[:, j]) <= 1e-14 * n * np.linalg.norm(AP[:, j])
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-14 * n
+    assert np.allclose(np.triu(R), R)
+    d = np.abs(np.diag(R))
+    assert np.all(d[:-1] >= d[1:] * (1 - 1e-12))
+    # |R_ii| >= ||R[i:, j]|| for every j >= i (the pivoting invariant)
+    for i in range(n):
+        for j in range(i, n):
+            assert np.linalg.norm(R[i:, j]) <= d[i] * (1 + 1e-12)
+    # same diagonal magnitudes as LAPACK geqp3 (sorted, ties aside)
+    _, Rl, _ = scipy.linalg.qr(A, pivoting=True)
+    dl = np.abs(np.diag(Rl))
+    assert np.allclose(np.log(d), np.log(dl), atol=1e-9)
+
+
+def test_udt_reconstructs():
+    rng = np.random.default_rng(1)
+    W = rng.standard_normal((12, 12)) * np.exp(rng.uniform(-30, 30, 12))
+    U, D, T = oracle.udt(W)
+    assert np.all(D > 0)
+    assert relF((U * D) @ T, W) < 1e-14
+    assert np.abs(U.T @ U - np.eye(12)).max() < 1e-14
+
+
+def test_chain_kinds_against_plain_products():
+    """The three chain kinds on a short, well-conditioned chain (beta = 1)."""
+    inst = wl.hubbard_ising(4, 1.0, 1, 1, seed=11)[0]
+    E, Ei, f, a = inst.expk, inst.expk_inv, inst.field, inst.alpha
+    B = [E @ np.diag(np.exp(a * f[q])) for q in range(inst.m)]
+    U, D, T = oracle.chain(E, Ei, f, a, 3, 0, 2, 9)       # B_9 .. B_2
+    ref = np.eye(16)
+    for q in range(2, 10):
+        ref = B[q - 1] @ ref
+    assert relF((U * D) @ T, ref) < 1e-13
+    U, D, T = oracle.chain(E, Ei, f, a, 3, 1, 2, 9)       # B_2^{-1} .. B_9^{-1}
+    ref = np.eye(16)
+    for q in range(2, 10):
+        ref = ref @ np.linalg.inv(B[q - 1])
+    assert relF((U * D) @ T, ref) < 1e-12
+    U, D, T = oracle.chain(E, Ei, f, a, 3, 2, 2, 9)       # B_2^T .. B_9^T
+    ref = np.eye(16)
+    for q in range(2, 10):
+        ref = B[q - 1] @ ref
+    assert relF((U * D) @ T, ref.T) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# closed forms
+
+def _free_closed_form(K, beta, tau):
+    eps, V = np.linalg.eigh(K)
+    occ = 1.0 / (1.0 + np.exp(-beta * eps))
+    G = (V * occ) @ V.T
+    Gt = (V * np.exp(-tau * eps - np.logaddexp(0.0, -beta * eps))) @ V.T
+    logdet = np.sum(np.logaddexp(0.0, -beta * eps))
+    return G, Gt, logdet
+
+
+@pytest.mark.parametrize("L,beta", [(4, 40.0), (6, 10.0)])
+def test_free_fermions_closed_form(L, beta):
+    """U = 0: B(beta,0) = exp(-beta K); G and G(tau,0) are diagonal in the
+    eigenbasis of K."""
+    K = wl.hopping_matrix(L)
+    E, Ei = wl.expk_pair(K, 0.1)
+    m = int(round(beta / 0.1))
+    f = np.zeros((m, L * L))
+    G, ld, sg = oracle.greens(E, f, 0.0, 10)
+    Gx, _, ldx = _free_closed_form(K, beta, 0.0)
+    assert relF(G, Gx) < 1e-12
+    assert ld == pytest.approx(ldx, rel=1e-13)
+    assert sg == 1.0
+    for l in (0, 1, m // 4, m // 2, m - 3, m):
+        Gt = oracle.greens_tdisp(E, Ei, f, 0.0, 10, l)
+        _, Gtx, _ = _free_closed_form(K, beta, 0.1 * l)
+        assert relF(Gt, Gtx) < 1e-12, l
+
+
+def test_paper_1d_chain_closed_form():
+    """The paper's own Sec. 3 model: periodic 1-D chain, U = 0, beta = 40."""
+    K = wl.chain_hopping_matrix(8)
+    E, Ei = wl.expk_pair(K, 0.1)
+    f = np.zeros((400, 8))
+    G, ld, _ = oracle.greens(E, f, 0.0, 10)
+    Gx, Gtx, ldx = _free_closed_form(K, 40.0, 20.0)
+    assert relF(G, Gx) < 1e-12
+    assert ld == pytest.approx(ldx, rel=1e-13)
+    assert relF(oracle.greens_tdisp(E, Ei, f, 0.0, 10, 200), Gtx) < 1e-12
+
+
+@pytest.mark.parametrize("sgn", [1.0, -1.0])
+def test_uniform_field_closed_form(sgn):
+    """Constant field s = +-1 (the constant-B chain of Sec. 3):
+    B(beta,0) = exp(M lambda s) exp(-beta K); lambda M = 261.5 at beta = 40
+    pushes the scales far beyond the bandwidth."""
+    L, beta = 4, 40.0
+    K = wl.hopping_matrix(L)
+    E, Ei = wl.expk_pair(K, 0.1)
+    m = 400
+    lam = wl.hirsch_lambda(4.0, 0.1)
+    f = np.full((m, 16), sgn)
+    G, ld, _ = oracle.greens(E, f, lam, 10)
+    shifted = K - np.eye(16) * (sgn * lam / 0.1)
+    Gx, _, ldx = _free_closed_form(shifted, beta, 0.0)
+    assert np.abs(G - Gx).max() < 1e-12
+    assert ld == pytest.approx(ldx, rel=1e-13)
+    for l in (37, 200):
+        Gt = oracle.greens_tdisp(E, Ei, f, lam, 10, l)
+        _, Gtx, _ = _free_closed_form(shifted, beta, 0.1 * l)
+        assert np.abs(Gt - Gtx).max() <= 1e-12 * max(1.0, np.abs(Gtx).max())
+
+
+# --------------------------------------------------------------------------
+# brute force at beta = 40
+
+@pytest.fixture(scope="module")
+def beta40():
+    inst = wl.hubbard_ising(4, 40.0, 1, 1, seed=wl.BASE_SEED + 100)[0]
+    b = Brute(inst.expk, inst.field, inst.alpha, dps=320)
+    G, ld, sg = b.greens()
+    return inst, b, G, float(ld), sg
+
+
+def test_brute_force_greens_beta40(beta40):
+    inst, b, Gmp, ld, sg = beta40
+    G, ldo, sgo = oracle.greens(inst.expk, inst.field, inst.alpha, 10)
+    assert relF(G, Brute.to_np(Gmp)) < 1e-12
+    assert ldo == pytest.approx(ld, rel=1e-13)
+    assert sgo == sg
+
+
+@pytest.mark.parametrize("l", [1, 10, 133, 200, 390, 400])
+def test_brute_force_tdisp_beta40(beta40, l):
+    inst, b, Gmp, _, _ = beta40
+    ref = Brute.to_np(b.tdisp(l, Gmp))
+    Gt = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, l)
+    assert relF(Gt, ref) < 1e-12
+
+
+def test_negative_controls_beta40(beta40):
+    """Sec. 3: the naive product fails; Sec. 6.2: QR + inv_sum fails near
+    tau = beta/2 while QR + inv_sum_loh holds."""
+    inst, b, Gmp, _, _ = beta40
+    Gn = oracle.greens_naive(inst.expk, inst.field, inst.alpha)
+    assert not (np.all(np.isfinite(Gn)) and relF(Gn, Brute.to_np(Gmp)) < 1e-6)
+    ref = Brute.to_np(b.tdisp(200, Gmp))
+    Gp = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, 200,
+                             oracle.SCHEME_PLAIN)
+    assert relF(Gp, ref) > 1e-6
+
+
+def test_equal_time_plain_scheme_beta40(beta40):
+    """Sec. 5.2: with QR both equal-time schemes are accurate."""
+    inst, b, Gmp, ld, sg = beta40
+    G, ldp, sgp = oracle.greens(inst.expk, inst.field, inst.alpha, 10, oracle.SCHEME_PLAIN)
+    assert relF(G, Brute.to_np(Gmp)) < 1e-10
+    assert ldp == pytest.approx(ld, rel=1e-12)
+    assert sgp == sg
+
+
+def test_slice_greens_brute_force():
+    inst = wl.hubbard_ising(4, 6.0, 1, 1, seed=5)[0]
+    b = Brute(inst.expk, inst.field, inst.alpha, dps=120)
+    _, ld, sg = b.greens()
+    for l in (1, 2, 17, 31, 60):
+        Gl, ldl, sgl = oracle.greens_slice(inst.expk, inst.field, inst.alpha, 10, l)
+        assert relF(Gl, Brute.to_np(b.greens_slice(l))) < 1e-12, l
+        assert ldl == pytest.approx(float(ld), rel=1e-13)     # cyclic invariance
+        assert sgl == sg
+
+
+def test_nonsymmetric_expk_and_ragged_blocks():
+    """A non-symmetric slice exponential (so E and E^T differ) and k = 7 not
+    dividing M = 60: catches transposed operands and block-boundary slips."""
+    rng = np.random.default_rng(3)
+    n, m = 9, 60
+    K = wl.hopping_matrix(3) + 0.3 * (lambda A: A - A.T)(rng.standard_normal((n, n)))
+    w, V = np.linalg.eig(K)
+    E = np.real((V * np.exp(-0.1 * w)) @ np.linalg.inv(V))
+    Ei = np.linalg.inv(E)
+    f = wl.ising_field(rng, m, n)
+    a = 0.65
+    b = Brute(E, f, a, dps=150)
+    Gmp, ld, sg = b.greens()
+    G, ldo, sgo = oracle.greens(E, f, a, 7)
+    assert relF(G, Brute.to_np(Gmp)) < 1e-12
+    assert ldo == pytest.approx(float(ld), rel=1e-12)
+    assert sgo == sg
+    for l in (0, 6, 7, 30, 59, 60):
+        ref = Brute.to_np(b.tdisp(l, Gmp))
+        assert relF(oracle.greens_tdisp(E, Ei, f, a, 7, l), ref) < 1e-11, l
+    for l in (1, 8, 44):
+        Gl, ldl, _ = oracle.greens_slice(E, f, a, 7, l)
+        assert relF(Gl, Brute.to_np(b.greens_slice(l))) < 1e-11, l
+
+
+@pytest.mark.parametrize("k", [1, 3, 10])
+def test_stabilization_interval_edges(k):
+    inst = wl.hubbard_ising(4, 5.0, 1, 1, seed=9)[0]
+    b = Brute(inst.expk, inst.field, inst.alpha, dps=100)
+    Gmp, ld, _ = b.greens()
+    G, ldo, _ = oracle.greens(inst.expk, inst.field, inst.alpha, k)
+    assert relF(G, Brute.to_np(Gmp)) < 1e-11
+    assert ldo == pytest.approx(float(ld), rel=1e-12)
+
+
+def test_single_stabilization_degrades():
+    """k = M stabilizes only once, i.e. multiplies the whole chain naively
+    (Sec. 3): at beta = 5 on the square lattice that already loses digits,
+    so the harness must see it; at beta = 1 it is still fine."""
+    inst = wl.hubbard_ising(4, 5.0, 1, 1, seed=9)[0]
+    Gmp = Brute(inst.expk, inst.field, inst.alpha, dps=100).greens()[0]
+    G, _, _ = oracle.greens(inst.expk, inst.field, inst.alpha, inst.m)
+    assert relF(G, Brute.to_np(Gmp)) > 1e-8
+    inst = wl.hubbard_ising(4, 1.0, 1, 1, seed=9)[0]
+    Gmp = Brute(inst.expk, inst.field, inst.alpha, dps=100).greens()[0]
+    G, _, _ = oracle.greens(inst.expk, inst.field, inst.alpha, inst.m)
+    assert relF(G, Brute.to_np(Gmp)) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# identities
+
+def test_flavour_particle_hole_identity():
+    """Even L, mu = 0: with Lambda = diag((-1)^(x+y)), Lambda K Lambda = -K,
+    so B_dn(beta,0) = Lambda B_up(beta,0)^{-T} Lambda and
+    G_dn = Lambda (1 - G_up^T) Lambda, logdet_dn = logdet_up - lambda sum(s)."""
+    up, dn = wl.hubbard_ising(4, 40.0, 1, 2, seed=21)
+    Gu, lu, su = oracle.greens(up.expk, up.field, up.alpha, 10)
+    Gd, ldn, sd = oracle.greens(dn.expk, dn.field, dn.alpha, 10)
+    lam = np.array([(-1) ** (x + y) for y in range(4) for x in range(4)], dtype=float)
+    assert np.abs(Gd - lam[:, None] * (np.eye(16) - Gu.T) * lam[None, :]).max() < 1e-11
+    assert ldn == pytest.approx(lu - up.alpha * up.field.sum(), abs=1e-10 * abs(lu))
+    assert sd == su
+
+
+def test_tdisp_boundaries():
+    inst = wl.hubbard_ising(4, 20.0, 1, 1, seed=23)[0]
+    G, _, _ = oracle.greens(inst.expk, inst.field, inst.alpha, 10)
+    G0 = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, 0)
+    Gb = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, inst.m)
+    assert relF(G0, G) < 1e-12
+    assert relF(Gb, np.eye(16) - G) < 1e-12
+
+
+def test_gradient_sum_rule_and_fp64_differences():
+    """sum_i grad[l][i] = alpha (N - tr G_l) = alpha (N - tr G) for every l
+    (G_{l+1} = B_l G_l B_l^{-1} has the trace of G), and a central difference
+    of the oracle's own logdet."""
+    inst = wl.hubbard_continuous(4, 4.0, 1, seed=31)[0]
+    E, f, a = inst.expk, inst.field, inst.alpha
+    G, ld0, _ = oracle.greens(E, f, a, 10)
+    ls = [1, 2, 10, 11, 25, 40]
+    g = oracle.logdet_grad(E, f, a, 10, ls)
+    for r in range(len(ls)):
+        assert g[r].sum() == pytest.approx(a * (16 - np.trace(G)), rel=1e-12)
+    h = 1e-5
+    for (l, i) in [(1, 0), (11, 5), (40, 15)]:
+        fp, fm = f.copy(), f.copy()
+        fp[l - 1, i] += h
+        fm[l - 1, i] -= h
+        fd = (oracle.greens(E, fp, a, 10)[1] - oracle.greens(E, fm, a, 10)[1]) / (2 * h)
+        assert g[ls.index(l), i] == pytest.approx(fd, abs=1e-8)
+
+
+def test_gradient_mpmath_finite_difference():
+    """Central difference at 60 digits with h = 1e-25 (error O(h^2))."""
+    inst = wl.hubbard_continuous(4, 2.0, 1, seed=37)[0]
+    E, f, a = inst.expk, inst.field, inst.alpha
+    for (l, i) in [(1, 3), (9, 0), (20, 12)]:
+        h = "1e-25"
+        lp = Brute(E, f, a, dps=60, perturb=(l, i, h)).logdet()
+        lm = Brute(E, f, a, dps=60, perturb=(l, i, "-" + h)).logdet()
+        fd = float((lp - lm) / (2 * lp.context.mpf(h)))
+        g = oracle.logdet_grad(E, f, a, 10, [l])[0, i]
+        assert g == pytest.approx(fd, abs=1e-13), (l, i)
+
+
+def test_oracle_rejects_bad_arguments():
+    E = np.eye(4)
+    f = np.zeros((5, 4))
+    with pytest.raises(oracle.OracleError):
+        oracle.greens(E, f, 0.1, 0)
+    f[2, 1] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.greens(E, f, 0.1, 2)
