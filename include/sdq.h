@@ -1,0 +1,172 @@
+/*
+ * sdq.h -- C ABI of libsdq, stabilized determinant-QMC Green's functions on
+ * AMD MI355X (gfx950).
+ *
+ * The method is that of C. Bauer, "Fast and stable determinant quantum Monte
+ * Carlo", SciPost Phys. (2020), arXiv:2003.05286:
+ *   * slice matrices B_l = expk * diag(exp(alpha * f_l)), l = 1..m
+ *     (Sec. 2; the Hubbard model with Hirsch's discrete field of Sec. 3 sets
+ *     alpha = sigma*lambda, f = s in {+1,-1}; a continuous field uses
+ *     alpha = dtau*g, f = phi);
+ *   * the chain B(beta,0) = B_m ... B_1 is multiplied naively inside blocks of
+ *     k slices and folded into a UDT factorization between blocks
+ *     (stabilized product, Sec. 4.1; UDT from column-pivoted QR, Sec. 4.2.2);
+ *   * G = (1 + B_m ... B_1)^{-1} is inverted with the scale-separating scheme
+ *     of Loh et al. (Sec. 5.1, inv_one_plus_loh), G(tau,0) with its
+ *     time-displaced analogue (Sec. 6.1, inv_sum_loh), and the equal-time G at
+ *     an interior slice from two stored factorizations (App. A.1).
+ *
+ * Conventions for every call:
+ *   * all matrices are FP64, row-major (C / torch order), n x n, dense;
+ *   * every data pointer inside sdq_instance and every output pointer is a
+ *     DEVICE pointer on the context's device, unless marked "host";
+ *   * slice l (1-based) uses field row l-1;
+ *   * calls are asynchronous and stream-ordered on the context's stream;
+ *     argument errors are detected synchronously and returned as a negative
+ *     sdq_status with nothing enqueued; numerical conditions are written per
+ *     instance into the device array `status` (0 = ok, SDQ_ERANGE = a
+ *     non-finite input or result, or a scale that left the FP64 range);
+ *   * the caller owns every buffer it passes; the library never frees them
+ *     and does not keep them past the call, except through a checkpoint
+ *     handle (sdq_logdet) which keeps the library's own copies;
+ *   * no C++ exception crosses this boundary.
+ * Supported sizes: 1 <= n <= 128 (one workgroup per chain, factors resident
+ * in LDS); larger n returns SDQ_EUNSUPPORTED.  1 <= k <= m.
+ */
+#ifndef SDQ_H
+#define SDQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SDQ_OK = 0,
+  SDQ_EINVAL = -1,      /* bad argument (null pointer, size, range)            */
+  SDQ_ENOMEM = -2,      /* device allocation failed                            */
+  SDQ_EHIP = -3,        /* a HIP runtime call failed (message in last_error)   */
+  SDQ_ERANGE = -4,      /* per instance: non-finite data or FP64 range exceeded */
+  SDQ_EUNSUPPORTED = -5 /* valid but not implemented (e.g. n > 128)            */
+} sdq_status;
+
+typedef enum {
+  SDQ_INV_LOH = 0,   /* Sec. 5.1 inv_one_plus_loh / Sec. 6.1 inv_sum_loh (default) */
+  SDQ_INV_PLAIN = 1  /* Sec. 5.1 inv_one_plus / Sec. 6.1 inv_sum (not implemented:
+                        returns SDQ_EUNSUPPORTED)                                  */
+} sdq_scheme;
+
+typedef struct sdq_ctx sdq_ctx;
+
+/* One Markov chain / spin flavour.  B_l = expk * diag(exp(alpha * field[l-1][:])). */
+typedef struct {
+  int32_t n;              /* sites N, 1 <= n <= 128                                  */
+  int32_t m;              /* slices M = beta / dtau, m >= 1                           */
+  int32_t k;              /* stabilization interval, 1 <= k <= m (Sec. 4.1)          */
+  int32_t pad_;
+  const double* expk;     /* [n][n] exp(-dtau K)                                      */
+  const double* expk_inv; /* [n][n] exp(+dtau K) = expk^{-1}; needed by
+                             sdq_logdet_grad, may be NULL for the other calls          */
+  const double* field;    /* [m][n] auxiliary field f_{l,i}                           */
+  double alpha;           /* coupling: sigma*lambda (Ising) or dtau*g (continuous)    */
+} sdq_instance;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns SDQ_OK and *out, or an
+ * error with *out = NULL. */
+sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream);
+void sdq_destroy(sdq_ctx* ctx);
+/* Message describing the last failing call on ctx (static storage owned by
+ * ctx; valid until the next call).  Never NULL. */
+const char* sdq_last_error(const sdq_ctx* ctx);
+/* Library version string, e.g. "sdq 0.1 gfx950". */
+const char* sdq_version(void);
+
+/* Equal-time Green's function (Sec. 2, G = (1 + B_m...B_1)^{-1}) of `count`
+ * chains in one batched launch, with log|det(1 + B_m...B_1)| and its sign.
+ *   inst    host array [count]
+ *   g       host array [count] of device pointers to [n][n] outputs (an entry
+ *           may be NULL: then only logdet/sign are produced for it)
+ *   logdet, sign  device arrays [count] (may be NULL)
+ *   status  device array [count] (may be NULL)
+ * Chains of different n, m, k may be mixed in one call. */
+sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
+                      double* const* g, double* logdet, double* sign, int32_t* status);
+
+/* Time-displaced Green's functions G(tau_l, 0) = B_l ... B_1 G (Sec. 6) for
+ * every l of the host list l_list[n_l] (ascending, each 0 <= l <= m of every
+ * chain), computed directly at multiples of k by the time-displaced scheme
+ * from a forward factorization of B(tau,0) and a backward factorization of
+ * B(beta,tau), and for other l by at most k-1 further slice products from
+ * the nearest lower multiple of k (Sec. 6, propagation form).
+ *   gt  host array [count] of device pointers to [n_l][n][n] outputs
+ *   g   host array [count] of device pointers to the equal-time G (entries
+ *       or the whole array may be NULL)
+ *   logdet, sign, status  as in sdq_greens (may be NULL) */
+sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t count,
+                            sdq_scheme scheme, const int32_t* l_list, int32_t n_l,
+                            double* const* gt, double* const* g, double* logdet, double* sign,
+                            int32_t* status);
+
+/* log|det(1 + B_m...B_1)| and sign for `count` chains; if ckpt_handle is not
+ * NULL the forward factorizations are kept in library memory and *ckpt_handle
+ * identifies them for a later sdq_logdet_grad on the same instances
+ * (released by sdq_release or sdq_destroy). */
+sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* logdet,
+                      double* sign, int32_t* status, uint64_t* ckpt_handle);
+
+/* Gradient of log|det(1 + B_m...B_1)| with respect to every field entry:
+ *   grad[l-1][i] = d log|det| / d f_{l,i} = alpha * (1 - G_l)_{ii},
+ * with G_l the equal-time G at slice l (Sec. 6), obtained at every multiple
+ * of k from a forward and a backward factorization combined as in App. A.1
+ * and carried to the next k-1 slices by G_{l+1} = B_l G_l B_l^{-1}.
+ *   ckpt_handle  0, or a handle from sdq_logdet on the same instances (then
+ *                the forward sweep is not repeated)
+ *   grad   host array [count] of device pointers to [m][n] outputs
+ *   logdet, sign, status  may be NULL
+ * Requires expk_inv in every instance. */
+sdq_status sdq_logdet_grad(sdq_ctx* ctx, uint64_t ckpt_handle, const sdq_instance* inst,
+                           int32_t count, double* const* grad, double* logdet, double* sign,
+                           int32_t* status);
+
+sdq_status sdq_release(sdq_ctx* ctx, uint64_t ckpt_handle);
+
+/* UDT factorization W P = Q R, U = Q, D = |diag R|, T = D^{-1} R P^T
+ * (Sec. 4.2.2) of `count` n x n matrices stored back to back in w
+ * ([count][n][n], device); outputs u, t [count][n][n] and d [count][n]. */
+sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u,
+                   double* d, double* t);
+
+/* Stabilized chain of one instance set (Sec. 4.1): the UDT factors of
+ * B_m...B_1 for each chain, u, t [count][n][n], d [count][n] (device).
+ * All chains must share n. */
+sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
+                         double* d, double* t);
+
+/* Time every kernel variant for each n of n_list[count] (host) on the
+ * device, keep the fastest per n in ctx, and if cache_path is not NULL
+ * append the choices to that JSON-lines file (read back by later contexts
+ * through the same call; an existing entry for (arch, n) is used without
+ * re-timing). */
+sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const char* cache_path);
+
+/* Capture later batched calls in HIP graphs and replay them when the same
+ * instance set (pointers and shapes) is seen again (enable = 1), or launch
+ * directly (enable = 0, the default). */
+sdq_status sdq_set_graphs(sdq_ctx* ctx, int enable);
+
+/* Record HIP events around every kernel launch (enable = 1); the per-kernel
+ * launch count and summed device milliseconds are then read with
+ * sdq_kernel_stats (names: "sweep", "pair", "udt").  Resets the counters. */
+sdq_status sdq_set_profiling(sdq_ctx* ctx, int enable);
+sdq_status sdq_kernel_stats(sdq_ctx* ctx, const char* name, int64_t* launches, double* ms);
+
+/* Wait for all work enqueued by ctx and report an asynchronous HIP error. */
+sdq_status sdq_sync(sdq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDQ_H */

@@ -1,0 +1,302 @@
+"""Python binding of libsdq (include/sdq.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module turns torch
+tensors into device pointers, calls the C ABI on torch's current stream and
+returns torch tensors.  There is no CPU fallback: if libsdq.so is missing or
+no GPU is visible the calls raise.
+
+Instances are given as `Chain` records (one Markov chain / spin flavour):
+    B_l = expk @ diag(exp(alpha * field[l-1]))      l = 1..m
+with expk, expk_inv ([n, n]) and field ([m, n]) float64 CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsdq.so")
+
+SDQ_OK, SDQ_EINVAL, SDQ_ENOMEM, SDQ_EHIP, SDQ_ERANGE, SDQ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SCHEME_LOH, SCHEME_PLAIN = 0, 1
+
+# every symbol include/sdq.h declares
+EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_greens",
+           "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
+           "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
+           "sdq_kernel_stats", "sdq_sync")
+
+
+class SdqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sdq status {status}: {msg}")
+        self.status = status
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("expk", ctypes.c_void_p), ("expk_inv", ctypes.c_void_p),
+                ("field", ctypes.c_void_p), ("alpha", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsdq.so and declare the C signatures (works without a GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2003_05286_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.sdq_create.argtypes = [P(vp), ctypes.c_int, vp]
+    L.sdq_destroy.argtypes = [vp]
+    L.sdq_destroy.restype = None
+    L.sdq_last_error.argtypes = [vp]
+    L.sdq_last_error.restype = ctypes.c_char_p
+    L.sdq_version.argtypes = []
+    L.sdq_version.restype = ctypes.c_char_p
+    L.sdq_greens.argtypes = [vp, P(_Instance), i32, ctypes.c_int, P(vp), vp, vp, vp]
+    L.sdq_greens_tdisp.argtypes = [vp, P(_Instance), i32, ctypes.c_int, P(i32), i32, P(vp), P(vp),
+                                   vp, vp, vp]
+    L.sdq_logdet.argtypes = [vp, P(_Instance), i32, vp, vp, vp, P(ctypes.c_uint64)]
+    L.sdq_logdet_grad.argtypes = [vp, ctypes.c_uint64, P(_Instance), i32, P(vp), vp, vp, vp]
+    L.sdq_release.argtypes = [vp, ctypes.c_uint64]
+    L.sdq_udt.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.sdq_chain_udt.argtypes = [vp, P(_Instance), i32, vp, vp, vp]
+    L.sdq_tune.argtypes = [vp, P(i32), i32, ctypes.c_char_p]
+    L.sdq_set_graphs.argtypes = [vp, ctypes.c_int]
+    L.sdq_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.sdq_kernel_stats.argtypes = [vp, ctypes.c_char_p, P(i64), P(dbl)]
+    L.sdq_sync.argtypes = [vp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def version() -> str:
+    return load_library().sdq_version().decode()
+
+
+@dataclass
+class Chain:
+    expk: torch.Tensor
+    field: torch.Tensor
+    alpha: float
+    k: int
+    expk_inv: torch.Tensor | None = None
+
+    @property
+    def n(self):
+        return self.expk.shape[0]
+
+    @property
+    def m(self):
+        return self.field.shape[0]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, name, shape, device):
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device != device or tuple(t.shape) != shape:
+        raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shape} on {device}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+class Context:
+    """An sdq context bound to one device and to torch's current stream."""
+
+    def __init__(self, device: int | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("sdq needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else device
+        self.tdev = torch.device("cuda", self.device)
+        self.stream = torch.cuda.current_stream(self.tdev)
+        h = ctypes.c_void_p()
+        st = self.lib.sdq_create(ctypes.byref(h), self.device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != SDQ_OK:
+            raise SdqError(st, "sdq_create failed")
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sdq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------
+    def _chk(self, st):
+        if st != SDQ_OK:
+            raise SdqError(st, self.lib.sdq_last_error(self.h).decode())
+
+    def _instances(self, chains, need_inv=False):
+        arr = (_Instance * max(len(chains), 1))()
+        for i, c in enumerate(chains):
+            n, m = c.n, c.m
+            _check_tensor(c.expk, "expk", (n, n), self.tdev)
+            _check_tensor(c.field, "field", (m, n), self.tdev)
+            if c.expk_inv is not None:
+                _check_tensor(c.expk_inv, "expk_inv", (n, n), self.tdev)
+            elif need_inv:
+                raise ValueError("expk_inv is required")
+            arr[i] = _Instance(n, m, int(c.k), 0, c.expk.data_ptr(),
+                               c.expk_inv.data_ptr() if c.expk_inv is not None else 0,
+                               c.field.data_ptr(), float(c.alpha))
+        return arr
+
+    def _empty(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.tdev)
+
+    @staticmethod
+    def _ptr_array(ts):
+        arr = (ctypes.c_void_p * max(len(ts), 1))()
+        for i, t in enumerate(ts):
+            arr[i] = t.data_ptr() if t is not None else 0
+        return arr
+
+    # -- calls -------------------------------------------------------------
+    def greens(self, chains, scheme=SCHEME_LOH, want_g=True):
+        """Equal-time G per chain, log|det(1+B)|, sign, status."""
+        cnt = len(chains)
+        inst = self._instances(chains)
+        gs = [self._empty(c.n, c.n) for c in chains] if want_g else [None] * cnt
+        ld, sg = self._empty(cnt), self._empty(cnt)
+        stt = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_greens(self.h, inst, cnt, scheme, self._ptr_array(gs),
+                                      _ptr(ld), _ptr(sg), _ptr(stt)))
+        return gs, ld, sg, stt
+
+    def greens_tdisp(self, chains, l_list, want_g=True, scheme=SCHEME_LOH):
+        """G(tau_l, 0) for l in l_list ([n_l, n, n] per chain), G, logdet, sign, status."""
+        cnt = len(chains)
+        inst = self._instances(chains)
+        ls = (ctypes.c_int32 * max(len(l_list), 1))(*[int(x) for x in l_list])
+        gts = [self._empty(len(l_list), c.n, c.n) for c in chains]
+        gs = [self._empty(c.n, c.n) for c in chains] if want_g else [None] * cnt
+        ld, sg = self._empty(cnt), self._empty(cnt)
+        stt = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_greens_tdisp(self.h, inst, cnt, scheme, ls, len(l_list),
+                                            self._ptr_array(gts), self._ptr_array(gs),
+                                            _ptr(ld), _ptr(sg), _ptr(stt)))
+        return gts, gs, ld, sg, stt
+
+    def logdet(self, chains, keep=False):
+        cnt = len(chains)
+        inst = self._instances(chains)
+        ld, sg = self._empty(cnt), self._empty(cnt)
+        stt = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        hnd = ctypes.c_uint64(0)
+        self._chk(self.lib.sdq_logdet(self.h, inst, cnt, _ptr(ld), _ptr(sg), _ptr(stt),
+                                      ctypes.byref(hnd) if keep else None))
+        return ld, sg, stt, hnd.value
+
+    def logdet_grad(self, chains, handle=0):
+        cnt = len(chains)
+        inst = self._instances(chains, need_inv=True)
+        grads = [self._empty(c.m, c.n) for c in chains]
+        ld, sg = self._empty(cnt), self._empty(cnt)
+        stt = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_logdet_grad(self.h, ctypes.c_uint64(handle), inst, cnt,
+                                           self._ptr_array(grads), _ptr(ld), _ptr(sg), _ptr(stt)))
+        return grads, ld, sg, stt
+
+    def release(self, handle):
+        self._chk(self.lib.sdq_release(self.h, ctypes.c_uint64(handle)))
+
+    def udt(self, w):
+        """w: [count, n, n] -> U [count,n,n], D [count,n], T [count,n,n]."""
+        cnt, n, _ = w.shape
+        _check_tensor(w, "w", (cnt, n, n), self.tdev)
+        u, t, d = self._empty(cnt, n, n), self._empty(cnt, n, n), self._empty(cnt, n)
+        self._chk(self.lib.sdq_udt(self.h, n, cnt, _ptr(w), _ptr(u), _ptr(d), _ptr(t)))
+        return u, d, t
+
+    def chain_udt(self, chains):
+        cnt = len(chains)
+        n = chains[0].n
+        inst = self._instances(chains)
+        u, t, d = self._empty(cnt, n, n), self._empty(cnt, n, n), self._empty(cnt, n)
+        self._chk(self.lib.sdq_chain_udt(self.h, inst, cnt, _ptr(u), _ptr(d), _ptr(t)))
+        return u, d, t
+
+    def tune(self, n_list, cache_path=None):
+        arr = (ctypes.c_int32 * len(n_list))(*n_list)
+        self._chk(self.lib.sdq_tune(self.h, arr, len(n_list),
+                                    cache_path.encode() if cache_path else None))
+
+    def set_graphs(self, enable: bool):
+        self._chk(self.lib.sdq_set_graphs(self.h, int(enable)))
+
+    def set_profiling(self, enable: bool):
+        self._chk(self.lib.sdq_set_profiling(self.h, int(enable)))
+
+    def kernel_stats(self, name):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0)
+        self._chk(self.lib.sdq_kernel_stats(self.h, name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def sync(self):
+        self._chk(self.lib.sdq_sync(self.h))
+
+
+_default = {}
+
+
+def context(device: int | None = None) -> Context:
+    dev = torch.cuda.current_device() if device is None else device
+    key = (dev, torch.cuda.current_stream(dev).cuda_stream)
+    if key not in _default:
+        _default[key] = Context(dev)
+    return _default[key]
+
+
+class LogDet1pB(torch.autograd.Function):
+    """log|det(1 + B_m ... B_1)| of a batch of chains with a hand-written
+    adjoint: d/d field[l-1, i] = alpha (1 - G_l)_ii (see sdq_logdet_grad).
+
+    forward(field [count, m, n], expk [n, n], expk_inv [n, n], alpha, k)
+      -> (logdet [count], sign [count]); the sign carries no gradient."""
+
+    @staticmethod
+    def forward(ctx, field, expk, expk_inv, alpha, k):
+        c = context(field.device.index)
+        chains = [Chain(expk, field[i], alpha, k, expk_inv) for i in range(field.shape[0])]
+        ld, sg, stt, hnd = c.logdet(chains, keep=True)
+        ctx.handle = hnd
+        ctx.sdq = c
+        ctx.args = (expk, expk_inv, alpha, k)
+        ctx.save_for_backward(field)
+        ctx.mark_non_differentiable(sg)
+        return ld, sg
+
+    @staticmethod
+    def backward(ctx, g_ld, g_sg):
+        (field,) = ctx.saved_tensors
+        expk, expk_inv, alpha, k = ctx.args
+        c = ctx.sdq
+        chains = [Chain(expk, field[i], alpha, k, expk_inv) for i in range(field.shape[0])]
+        try:
+            grads, _, _, _ = c.logdet_grad(chains, handle=ctx.handle)
+        finally:
+            c.release(ctx.handle)
+        grad = torch.stack(grads) * g_ld.view(-1, 1, 1)
+        return grad, None, None, None, None

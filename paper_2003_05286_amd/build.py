@@ -1,0 +1,75 @@
+"""Build libsdq.so (the HIP library) in-tree for gfx950.
+
+Compiles the per-tile-count kernel instantiations in parallel with hipcc and
+links them with the dispatch and runtime objects into
+paper_2003_05286_amd/libsdq.so.  Always recompiles.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libsdq.so")
+ARCH = "gfx950"
+NTS = range(1, 9)
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _flags():
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+            # packed FP32 instructions stay off (not used by this FP64 code
+            # either way; the host pass warns that it does not know the feature)
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def _compile(args):
+    src, obj, extra = args
+    cmd = [hipcc()] + _flags() + extra + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{err}")
+    return obj
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    tasks = []
+    for nt in NTS:
+        tasks.append((os.path.join(CSRC, "sdq_nt.hip"), os.path.join(BUILD, f"sdq_nt{nt}.o"),
+                      [f"-DSDQ_NT={nt}"]))
+    tasks.append((os.path.join(CSRC, "sdq_dispatch.hip"), os.path.join(BUILD, "sdq_dispatch.o"), []))
+    tasks.append((os.path.join(CSRC, "sdq_runtime.cpp"), os.path.join(BUILD, "sdq_runtime.o"), []))
+    jobs = jobs or min(len(tasks), os.cpu_count() or 4, 16)
+    # the largest instantiations first
+    tasks.sort(key=lambda t: -int(t[2][0].split("=")[1]) if t[2] else 0)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, tasks))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,1250 @@
+// sdq_device.hpp -- gfx950 kernels of libsdq: stabilized DQMC Green's
+// functions (C. Bauer, "Fast and stable determinant quantum Monte Carlo",
+// arXiv:2003.05286).
+//
+// Execution model.  One workgroup owns one chain (or one stage pair) at a
+// time and pulls work items from a queue in longest-first order (persistent
+// launch).  A workgroup has P = min(NT, 4) waves, NT = ceil(n/16).  The
+// working n x n matrix lives in registers, split by 16-column tiles over the
+// waves; inside a wave it is held exactly in the accumulator layout of the
+// FP64 MFMA 16x16x4 instruction:
+//     lane l, register [c][ti][r]  <->  row 16*ti + (l/16) + 4*r,
+//                                       column 16*(w + P*c) + (l%16)
+// (on gfx950 the 16x16 FP64 accumulator gives lane l the rows
+// l/16, l/16 + 4, l/16 + 8, l/16 + 12 of column l%16).
+// Each column therefore lives in the four lanes l%16 = const of one wave,
+// 16*NT/4 rows per lane.  This lets
+//   * the slice products W <- E diag(v) W run back to back on MFMA with the
+//     previous product as the B operand (no LDS round trip, no barrier),
+//   * the pivoted Householder QR work on the same registers: column norms
+//     and reflector dot products are lane-local sums plus two cross-row
+//     shuffles; the pivot column is exchanged through LDS with one barrier
+//     per column step,
+//   * Q be formed and R P^T T be multiplied in place.
+// The factor R (with the reflectors below it) is parked in LDS, column-major
+// by original column index, for Q formation, the T update and the solves.
+//
+// Paper passages per routine:
+//   slice products, stage loop ...... Sec. 4.1 (stabilized product, with the
+//                                     naive/stabilized mixture every k slices)
+//   cpqr / form_q / T update ........ Sec. 4.2.2 (UDT from pivoted QR)
+//   inv_one_plus ..................... Sec. 5.1 (Loh's Dp/Dm split)
+//   pair_tdisp ....................... Sec. 6.1 (inv_sum_loh), Sec. 6 (G(tau,0)
+//                                     by propagation inside a block)
+//   pair_grad ........................ App. A.1 (stack combination) and the
+//                                     equal-time G at slice l of Sec. 6
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sdq_internal.h"
+
+namespace sdq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// geometry
+
+template <int NT>
+struct Geo {
+  static constexpr int NP = 16 * NT;             // padded dimension
+  static constexpr int P = NT < 4 ? NT : 4;      // waves per workgroup
+  static constexpr int CT = (NT + P - 1) / P;    // column tiles per wave (max)
+  static constexpr int LDR = NP + 1;             // LDS column stride (odd: no bank conflicts)
+  static constexpr int THREADS = 64 * P;
+  static constexpr int KB = NT <= 6 ? 16 : 8;    // slices of field exponentials staged at once
+};
+
+template <int NT, bool ELDS>
+struct Smem {
+  using G = Geo<NT>;
+  double R[G::NP * G::LDR];                  // factor store, [col][row]
+  double E[ELDS ? G::NP * G::LDR : 1];       // staged slice exponential, [row][col]
+  double cand[2][G::P][G::NP];               // pivot candidate columns
+  double vbuf[G::KB][G::NP];                 // exp(alpha f) of the slices in flight
+  double tau[G::NP];
+  double dnew[G::NP];                        // |diag R| of the last QR
+  double dcur[G::NP];                        // D of the current factorization
+  double ckey[2][4];
+  double red[2][8];
+  int ccol[2][4];
+  int perm[G::NP];                           // perm[j] = column pivoted at step j
+  int sinv[G::NP];                           // sinv[c] = step at which c was pivoted
+  int ired[8];
+  int item;
+};
+
+template <int NT>
+struct RM {  // register-resident n x n matrix, column split (see header)
+  double v[Geo<NT>::CT][NT][4];
+};
+
+struct Lane {
+  int t, w, l, g, cl;
+};
+
+__device__ __forceinline__ Lane lane_id() {
+  Lane L;
+  L.t = threadIdx.x;
+  L.w = threadIdx.x >> 6;
+  L.l = threadIdx.x & 63;
+  L.g = L.l >> 4;
+  L.cl = L.l & 15;
+  return L;
+}
+
+template <int NT>
+__device__ __forceinline__ bool tile_ok(const Lane& L, int c) {
+  return L.w + Geo<NT>::P * c < NT;
+}
+template <int NT>
+__device__ __forceinline__ int col_of(const Lane& L, int c) {
+  return 16 * (L.w + Geo<NT>::P * c) + L.cl;
+}
+__device__ __forceinline__ int row_of(const Lane& L, int ti, int r) { return 16 * ti + L.g + 4 * r; }
+
+__device__ __forceinline__ double shx(double v, int m) { return __shfl_xor(v, m); }
+__device__ __forceinline__ int shx(int v, int m) { return __shfl_xor(v, m); }
+// sum over the four lanes holding one column; every one of them gets the
+// bitwise-same result (each pairwise add is commutative)
+__device__ __forceinline__ double sum_col(double v) {
+  v += shx(v, 16);
+  v += shx(v, 32);
+  return v;
+}
+__device__ __forceinline__ double max_col(double v) {
+  v = fmax(v, shx(v, 16));
+  v = fmax(v, shx(v, 32));
+  return v;
+}
+
+// exact power-of-two scale that brings x near 1 (1 for 0, inf, nan)
+__device__ __forceinline__ double pow2_scale(double x) {
+  if (!(x > 0.0) || !isfinite(x)) return 1.0;
+  return ldexp(1.0, -ilogb(x));
+}
+
+template <int NT>
+__device__ __forceinline__ void set_identity(const Lane& L, RM<NT>& A) {
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A.v[c][ti][r] = (row_of(L, ti, r) == col_of<NT>(L, c)) ? 1.0 : 0.0;
+}
+
+// value of row j of column block c, fetched from the lane group that holds it
+template <int NT>
+__device__ __forceinline__ double row_value(const Lane& L, const RM<NT>& A, int c, int j) {
+  const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
+  double s = 0.0;
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (ti == tj && r == rj) s = A.v[c][ti][r];
+  return __shfl(s, gj * 16 + L.cl);
+}
+
+// ---------------------------------------------------------------------------
+// C = A * B on FP64 MFMA.  A(i, k) is any callable returning the entry of
+// the left operand (i, k < NP); B and C are register matrices.  The B
+// operand of one 16x16x4 step is register [c][tk][r] as is: its four k
+// indices are rows 16tk + q + 4r, q = 0..3, so the A operand is fetched with
+// the same row permutation of k.
+template <int NT, class AF>
+__device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT>& B, RM<NT>& C) {
+  constexpr int CT = Geo<NT>::CT;
+  d4 acc[CT][NT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti) acc[c][ti] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int tk = 0; tk < NT; ++tk) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kk = 16 * tk + L.g + 4 * r;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti) {
+        const double a = A(16 * ti + L.cl, kk);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          if (c == 0 || tile_ok<NT>(L, c))
+            acc[c][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B.v[c][tk][r], acc[c][ti], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) C.v[c][ti][r] = acc[c][ti][r];
+}
+
+// load a row-major n x n global matrix (or its transpose) into registers,
+// zero padded; `src == nullptr` loads the identity
+template <int NT>
+__device__ __forceinline__ void load_rm(const Lane& L, RM<NT>& A, const double* src, int n, bool trans) {
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c) {
+    const int col = col_of<NT>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        double x;
+        if (src == nullptr) x = (row == col) ? 1.0 : 0.0;
+        else if (row < n && col < n && tile_ok<NT>(L, c)) x = trans ? src[col * n + row] : src[row * n + col];
+        else x = 0.0;
+        A.v[c][ti][r] = x;
+      }
+  }
+}
+
+// store the leading n x n block of a register matrix (row-major)
+template <int NT>
+__device__ __forceinline__ void store_rm(const Lane& L, const RM<NT>& A, double* dst, int n) {
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c) {
+    const int col = col_of<NT>(L, c);
+    if (!tile_ok<NT>(L, c) || col >= n) continue;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        if (row < n) dst[row * n + col] = A.v[c][ti][r];
+      }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ bool all_finite(const Lane& L, const RM<NT>& A) {
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ok = ok && isfinite(A.v[c][ti][r]);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Column-pivoted Householder QR of the register matrix A (columns >= n and
+// rows >= n are padding: padded rows are zero, padded columns never pivot).
+//   step j: pick the live column of largest remaining norm (ties: smallest
+//   column index), build the reflector that maps its rows j.. to
+//   (beta, 0, ...), beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
+//   apply it to the other live columns and downdate their norms; recompute a
+//   norm exactly when 1 - (|r|/vn1)^2 scaled by (vn1/vn2)^2 drops below
+//   sqrt(eps) (Drmac & Bujanovic).
+// Columns are not moved: on return S.R[c*LDR + i] holds, for every column
+// c, R[i][s_c] for i <= s_c and the reflector v_{s_c} below (unit entry
+// implied), with s_c = S.sinv[c] the step at which c was chosen; S.perm[j]
+// is the column chosen at step j and S.tau[j] its reflector scalar.  So
+// R P^T has column c = S.R column c masked to rows <= s_c.  Padded columns
+// are stored as unit vectors with s_c = c.  Ends with a barrier.
+template <int NT, bool ELDS>
+__device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
+  using G = Geo<NT>;
+  constexpr int CT = G::CT, P = G::P;
+  const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  double vn1[CT], vn2[CT];
+  int ps[CT];  // -1 live and not yet chosen, else the step (padding: own index)
+
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT>(L, c);
+    const bool live = tile_ok<NT>(L, c) && col < n;
+    ps[c] = live ? -1 : col;
+    double mx = 0.0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) mx = fmax(mx, fabs(A.v[c][ti][r]));
+    mx = max_col(mx);
+    const double sc = pow2_scale(mx);
+    double s = 0.0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double x = A.v[c][ti][r] * sc;
+        s = fma(x, x, s);
+      }
+    s = sum_col(s);
+    vn1[c] = sqrt(s) / sc;
+    vn2[c] = vn1[c];
+  }
+
+  int buf = 0;
+  for (int j = 0; j < n; ++j) {
+    // ---- wave-local candidate: largest norm, ties to the smaller column
+    double bk = -1.0;
+    int bc = 0x7fffffff;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      if (ps[c] < 0) {
+        const double key = (vn1[c] >= 0.0) ? vn1[c] : -0.5;  // NaN never wins but stays eligible
+        const int col = col_of<NT>(L, c);
+        if (key > bk || (key == bk && col < bc)) {
+          bk = key;
+          bc = col;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+      const double ok = shx(bk, m);
+      const int oc = shx(bc, m);
+      if (ok > bk || (ok == bk && oc < bc)) {
+        bk = ok;
+        bc = oc;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      if (ps[c] < 0 && col_of<NT>(L, c) == bc) {
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+          if (16 * ti + 15 >= j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S.cand[buf][L.w][row_of(L, ti, r)] = A.v[c][ti][r];
+      }
+    }
+    if (L.l == 0) {
+      S.ckey[buf][L.w] = bk;
+      S.ccol[buf][L.w] = bc;
+    }
+    __syncthreads();
+
+    // ---- workgroup pivot
+    double pk = S.ckey[buf][0];
+    int pc = S.ccol[buf][0], pw = 0;
+#pragma unroll
+    for (int q = 1; q < P; ++q) {
+      const double k2 = S.ckey[buf][q];
+      const int c2 = S.ccol[buf][q];
+      if (k2 > pk || (k2 == pk && c2 < pc)) {
+        pk = k2;
+        pc = c2;
+        pw = q;
+      }
+    }
+    const double* xc = S.cand[buf][pw];
+    const double alpha = xc[j];
+
+    // ---- reflector (every wave computes the same one from the same data)
+    const double sc = pow2_scale(pk);
+    double v[NT][4];
+    double s = 0.0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        double x = 0.0;
+        if (16 * ti + 15 > j && row > j && row < n) x = xc[row];
+        v[ti][r] = x;
+        const double y = x * sc;
+        s = fma(y, y, s);
+      }
+    s = sum_col(s);
+    const double xnorm = sqrt(s) / sc;
+    double tau = 0.0, beta = alpha, inv = 0.0;
+    if (xnorm != 0.0) {
+      beta = -copysign(hypot(alpha, xnorm), alpha);
+      tau = (beta - alpha) / beta;
+      inv = 1.0 / (alpha - beta);
+    }
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        v[ti][r] = (row == j) ? 1.0 : v[ti][r] * inv;
+      }
+
+    // ---- apply H_j to the other live columns, downdate their norms
+    bool need = false;
+    bool rec[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = col_of<NT>(L, c);
+      const bool upd = ps[c] < 0 && col != pc;
+      rec[c] = false;
+      const double t_eff = upd ? tau : 0.0;
+      double d = 0.0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti + 15 >= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], A.v[c][ti][r], d);
+      d = sum_col(d) * t_eff;
+      if (ps[c] < 0 && col == pc) {
+        // the pivot column becomes column j of R plus the reflector
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = row_of(L, ti, r);
+            if (row == j) A.v[c][ti][r] = beta;
+            else if (row > j) A.v[c][ti][r] = v[ti][r];
+          }
+      } else {
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+          if (16 * ti + 15 >= j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
+      }
+      const double rj = row_value<NT>(L, A, c, j);
+      if (upd && vn1[c] != 0.0) {
+        double t = fabs(rj) / vn1[c];
+        t = fmax(0.0, (1.0 - t) * (1.0 + t));
+        const double ratio = vn1[c] / vn2[c];
+        if (t * ratio * ratio <= tol3z) {
+          need = true;
+          rec[c] = true;
+        } else {
+          vn1[c] *= sqrt(t);
+        }
+      }
+    }
+    if (__any(need)) {
+      // exact recompute of the norm of rows j+1.. (rare)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        double mx = 0.0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row_of(L, ti, r) > j) mx = fmax(mx, fabs(A.v[c][ti][r]));
+        mx = max_col(mx);
+        const double sc2 = pow2_scale(mx);
+        double s2 = 0.0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (row_of(L, ti, r) > j) {
+              const double y = A.v[c][ti][r] * sc2;
+              s2 = fma(y, y, s2);
+            }
+        s2 = sum_col(s2);
+        const double nn = sqrt(s2) / sc2;
+        if (rec[c]) {
+          vn1[c] = nn;
+          vn2[c] = nn;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      if (ps[c] < 0 && col_of<NT>(L, c) == pc) ps[c] = j;
+    if (L.t == 0) {
+      S.tau[j] = tau;
+      S.perm[j] = pc;
+    }
+    buf ^= 1;
+  }
+
+  // ---- park R / reflectors in LDS
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT>(L, c)) continue;
+    const int col = col_of<NT>(L, c);
+    const bool live = col < n;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        S.R[col * G::LDR + row] = live ? A.v[c][ti][r] : (row == col ? 1.0 : 0.0);
+      }
+    if (L.g == 0) S.sinv[col] = ps[c];
+  }
+  for (int t = n + L.t; t < G::NP; t += G::THREADS) {
+    S.perm[t] = t;
+    S.tau[t] = 0.0;
+  }
+  __syncthreads();
+}
+
+// D' = |diag R| (1 on padding) into S.dnew; ends with a barrier
+template <int NT, bool ELDS>
+__device__ __forceinline__ void diag_r(const Lane& L, const int n, Smem<NT, ELDS>& S) {
+  using G = Geo<NT>;
+  for (int t = L.t; t < G::NP; t += G::THREADS)
+    S.dnew[t] = t < n ? fabs(S.R[S.perm[t] * G::LDR + t]) : 1.0;
+  __syncthreads();
+}
+
+// Q = H_0 H_1 ... H_{n-1} into registers
+template <int NT, bool ELDS>
+__device__ void form_q(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& X) {
+  using G = Geo<NT>;
+  set_identity<NT>(L, X);
+  for (int j = n - 1; j >= 0; --j) {
+    const double tau = S.tau[j];
+    if (tau == 0.0) continue;
+    const double* vc = &S.R[S.perm[j] * G::LDR];
+    double v[NT][4];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        v[ti][r] = (16 * ti + 15 >= j) ? (row > j ? vc[row] : (row == j ? 1.0 : 0.0)) : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < G::CT; ++c) {
+      double d = 0.0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti + 15 >= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], X.v[c][ti][r], d);
+      d = sum_col(d) * tau;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti + 15 >= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) X.v[c][ti][r] = fma(-d, v[ti][r], X.v[c][ti][r]);
+    }
+  }
+}
+
+// Y <- Q^T Y = H_{n-1} ... H_0 Y
+template <int NT, bool ELDS>
+__device__ void apply_qt(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& Y) {
+  using G = Geo<NT>;
+  for (int j = 0; j < n; ++j) {
+    const double tau = S.tau[j];
+    if (tau == 0.0) continue;
+    const double* vc = &S.R[S.perm[j] * G::LDR];
+    double v[NT][4];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        v[ti][r] = (16 * ti + 15 >= j) ? (row > j ? vc[row] : (row == j ? 1.0 : 0.0)) : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < G::CT; ++c) {
+      double d = 0.0;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti + 15 >= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], Y.v[c][ti][r], d);
+      d = sum_col(d) * tau;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti + 15 >= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Y.v[c][ti][r] = fma(-d, v[ti][r], Y.v[c][ti][r]);
+    }
+  }
+}
+
+// Y <- R^{-1} Y (R in pivot order: R[i][j] = S.R[perm[j]*LDR + i], i <= j)
+template <int NT, bool ELDS>
+__device__ void back_subst(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& Y) {
+  using G = Geo<NT>;
+  for (int j = n - 1; j >= 0; --j) {
+    const double* rc = &S.R[S.perm[j] * G::LDR];
+    const double rjj = rc[j];
+    double rr[NT][4];
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        rr[ti][r] = (16 * ti <= j && row < j) ? rc[row] : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < G::CT; ++c) {
+      const double zj = row_value<NT>(L, Y, c, j) / rjj;
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+        if (16 * ti <= j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = row_of(L, ti, r);
+            if (row == j) Y.v[c][ti][r] = zj;
+            else Y.v[c][ti][r] = fma(-rr[ti][r], zj, Y.v[c][ti][r]);
+          }
+    }
+  }
+}
+
+// left operand of R P^T: column c, rows <= s_c
+template <int NT, bool ELDS>
+struct RPtOp {
+  const Smem<NT, ELDS>& S;
+  __device__ double operator()(int i, int k) const {
+    return (i <= S.sinv[k]) ? S.R[k * Geo<NT>::LDR + i] : 0.0;
+  }
+};
+
+// T <- D'^{-1} (R P^T) T  with D' = S.dnew
+template <int NT, bool ELDS>
+__device__ __forceinline__ void update_t(const Lane& L, const Smem<NT, ELDS>& S, RM<NT>& T) {
+  RM<NT> Tn;
+  gemm_rb<NT>(L, RPtOp<NT, ELDS>{S}, T, Tn);
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T.v[c][ti][r] = Tn.v[c][ti][r] / S.dnew[row_of(L, ti, r)];
+}
+
+// det Q = (-1)^(number of nonzero reflectors among steps 0..n-1).  No barrier.
+template <int NT, bool ELDS>
+__device__ __forceinline__ double refl_sign(const Lane& L, const int n, const Smem<NT, ELDS>& S) {
+  int cnt = 0;
+  for (int i = L.l; i < n; i += 64) cnt += (S.tau[i] != 0.0);
+  const unsigned long long b = __ballot(cnt & 1);
+  return (__popcll(b) & 1) ? -1.0 : 1.0;
+}
+
+// parity of the pivot permutation (inversions of S.perm) as +-1.
+// Ends with a barrier.
+template <int NT, bool ELDS>
+__device__ double perm_sign(const Lane& L, const int n, Smem<NT, ELDS>& S) {
+  using G = Geo<NT>;
+  int inv = 0;
+  for (int i = L.t; i < n; i += G::THREADS) {
+    const int pi = S.perm[i];
+    for (int j = i + 1; j < n; ++j) inv += (S.perm[j] < pi);
+  }
+  const unsigned long long bi = __ballot(inv & 1);
+  if (L.l == 0) S.ired[L.w] = __popcll(bi) & 1;
+  __syncthreads();
+  int p = 0;
+  for (int q = 0; q < G::P; ++q) p ^= S.ired[q];
+  __syncthreads();
+  return p ? -1.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// (1 + U D T)^{-1} with Loh's split (Sec. 5.1).  We use the mirror image of
+// the printed factorization, which needs U^T rather than T^{-1}:
+//   1 + U Dm Dp T = U Dp (Dp^{-1} U^T + Dm T),  Dp = max(D,1), Dm = min(D,1)
+//   G = M^{-1} Dp^{-1} U^T,   M = Dp^{-1} U^T + Dm T,
+// M inverted through its pivoted QR, M P = Q R:  G = P R^{-1} Q^T Dp^{-1} U^T.
+//   det(1 + U D T) = det U * prod(Dp) * det M.
+// U, T: register matrices (padding: identity); D: S.dcur.  Returns Z with
+// G[S.perm[s]][c] = Z[s][c] (caller writes it out), and log|det|, sign.
+template <int NT, bool ELDS>
+__device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, ELDS>& S, const RM<NT>& U,
+                             const RM<NT>& T, double sgn_u, RM<NT>& Z, double* logdet,
+                             double* sign) {
+  using G = Geo<NT>;
+  constexpr int CT = G::CT;
+  // U^T via LDS
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT>(L, c)) continue;
+    const int col = col_of<NT>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.R[col * G::LDR + row_of(L, ti, r)] = U.v[c][ti][r];
+  }
+  // sum of log Dp over the live rows (wave 0), reduced through LDS
+  __syncthreads();
+  RM<NT> M;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        const double dr = S.dcur[row];
+        const double dp = dr > 1.0 ? dr : 1.0;
+        const double dm = dr < 1.0 ? dr : 1.0;
+        const double ut = tile_ok<NT>(L, c) ? S.R[row * G::LDR + col] : 0.0;
+        Z.v[c][ti][r] = ut / dp;
+        M.v[c][ti][r] = ut / dp + dm * T.v[c][ti][r];
+      }
+  }
+  double lsum = 0.0;
+  for (int t = L.t; t < n; t += G::THREADS) lsum += log(fmax(S.dcur[t], 1.0));
+  cpqr<NT, ELDS>(L, n, M, S);  // begins with barriers before S.R is overwritten
+  for (int t = L.t; t < n; t += G::THREADS) lsum += log(fabs(S.R[S.perm[t] * G::LDR + t]));
+  int neg = 0;
+  for (int t = L.t; t < n; t += G::THREADS) neg += (S.R[S.perm[t] * G::LDR + t] < 0.0);
+  // wave sums
+  for (int m = 32; m >= 1; m >>= 1) {
+    lsum += shx(lsum, m);
+    neg += shx(neg, m);
+  }
+  if (L.l == 0) {
+    S.red[0][L.w] = lsum;
+    S.ired[4 + L.w] = neg;
+  }
+  const double sq = refl_sign<NT, ELDS>(L, n, S);
+  const double sp = perm_sign<NT, ELDS>(L, n, S);  // its barrier makes S.red visible
+  double ld = 0.0;
+  int ng = 0;
+  for (int q = 0; q < G::P; ++q) {
+    ld += S.red[0][q];
+    ng += S.ired[4 + q];
+  }
+  *logdet = ld;
+  *sign = sgn_u * sq * sp * ((ng & 1) ? -1.0 : 1.0);
+  apply_qt<NT, ELDS>(L, n, S, Z);
+  back_subst<NT, ELDS>(L, n, S, Z);
+}
+
+// write G[perm[s]][c] = Z[s][c] (leading n x n block) to global memory
+template <int NT, bool ELDS>
+__device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, const Smem<NT, ELDS>& S,
+                                                const RM<NT>& Z, double* dst) {
+#pragma unroll
+  for (int c = 0; c < Geo<NT>::CT; ++c) {
+    const int col = col_of<NT>(L, c);
+    if (!tile_ok<NT>(L, c) || col >= n) continue;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = row_of(L, ti, r);
+        if (s < n) dst[S.perm[s] * n + col] = Z.v[c][ti][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// slice exponentials v_q = exp(alpha f_q) for `cnt` slices into S.vbuf.
+// slice of buffer row s: q0 + dir*s.  Ends with a barrier.
+template <int NT, bool ELDS>
+__device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, int q0,
+                                          int dir, int cnt) {
+  using G = Geo<NT>;
+  __syncthreads();
+  for (int idx = L.t; idx < cnt * G::NP; idx += G::THREADS) {
+    const int s = idx / G::NP, row = idx - s * G::NP;
+    const int q = q0 + dir * s;
+    S.vbuf[s][row] = row < I.n ? exp(I.alpha * I.field[(size_t)(q - 1) * I.n + row]) : 1.0;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void scale_rows(const Lane& L, RM<NT>& A, const double* v) {
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double s = v[row_of(L, ti, r)];
+#pragma unroll
+      for (int c = 0; c < Geo<NT>::CT; ++c) A.v[c][ti][r] *= s;
+    }
+}
+
+// left operand: the slice exponential (or its transpose), from LDS or HBM
+template <int NT, bool ELDS>
+struct EOp {
+  const double* sE;  // staged copy in LDS (ELDS)
+  const double* e;   // global n x n
+  int n;
+  bool trans;
+  __device__ double operator()(int i, int k) const {
+    if (ELDS) return sE[i * Geo<NT>::LDR + k];
+    if (i >= n || k >= n) return 0.0;
+    return trans ? e[k * n + i] : e[i * n + k];
+  }
+};
+
+template <int NT, bool ELDS>
+__device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, ELDS>& S, const double* e, int n,
+                                        bool trans) {
+  using G = Geo<NT>;
+  if (!ELDS) return;
+  for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
+    const int i = idx / G::NP, k = idx - i * G::NP;
+    double x = 0.0;
+    if (i < n && k < n) x = trans ? e[k * n + i] : e[i * n + k];
+    S.E[i * G::LDR + k] = x;
+  }
+  // visibility: the next fill_vbuf begins with a barrier
+}
+
+// store one stage U | T | D | extra
+template <int NT, bool ELDS>
+__device__ __forceinline__ void store_stage(const Lane& L, const int n, const Smem<NT, ELDS>& S,
+                                            const RM<NT>& U, const RM<NT>& T, double sgn_u,
+                                            double* dst) {
+  store_rm<NT>(L, U, dst, n);
+  store_rm<NT>(L, T, dst + (size_t)n * n, n);
+  for (int t = L.t; t < n; t += Geo<NT>::THREADS) dst[2 * (size_t)n * n + t] = S.dnew[t];
+  if (L.t == 0) dst[2 * (size_t)n * n + n] = sgn_u;
+}
+
+// ---------------------------------------------------------------------------
+// One stabilized sweep over the chain (Sec. 4.1):
+//   forward  (SW_ADJ clear):  B_m ... B_1,           blocks b = 0 .. nb-1
+//   backward (SW_ADJ set):    B_1^T ... B_m^T,        blocks b = nb-1 .. 0
+// Block b holds slices b*k+1 .. min((b+1)k, m); both directions stabilize on
+// the same slice boundaries, so forward stage j and backward stage j meet at
+// tau = min(jk, m).  Per block:  W = X_block U,  W <- W D,  W P = Q R,
+// U <- Q,  D <- |diag R|,  T <- D^{-1} R P^T T.
+template <int NT, bool ELDS>
+__device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int flags) {
+  using G = Geo<NT>;
+  constexpr int CT = G::CT;
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb;
+  const bool adj = (flags & SW_ADJ) != 0;
+  const int64_t sd = stage_doubles(n);
+  stage_e<NT, ELDS>(L, S, I.expk, n, adj);
+  // W holds U between blocks and the block product inside a block
+  RM<NT> T, W;
+  set_identity<NT>(L, W);
+  set_identity<NT>(L, T);
+  double dcol[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
+  double sgn_u = 1.0;
+  const EOp<NT, ELDS> eop{S.E, I.expk, n, adj};
+
+  for (int s = 0; s < nb; ++s) {
+    const int b = adj ? nb - 1 - s : s;
+    const int q0 = b * k + 1, q1 = (b + 1) * k < m ? (b + 1) * k : m;
+    const int cnt = q1 - q0 + 1;
+    for (int c0 = 0; c0 < cnt; c0 += G::KB) {
+      const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
+      if (adj) fill_vbuf<NT, ELDS>(L, S, I, q1 - c0, -1, cn);
+      else fill_vbuf<NT, ELDS>(L, S, I, q0 + c0, +1, cn);
+      for (int s2 = 0; s2 < cn; ++s2) {
+        if (!adj) {
+          scale_rows<NT>(L, W, S.vbuf[s2]);
+          gemm_rb<NT>(L, eop, W, W);
+        } else {
+          gemm_rb<NT>(L, eop, W, W);
+          scale_rows<NT>(L, W, S.vbuf[s2]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
+    cpqr<NT, ELDS>(L, n, W, S);
+    diag_r<NT, ELDS>(L, n, S);
+    if (s == nb - 1) sgn_u = refl_sign<NT, ELDS>(L, n, S);
+    form_q<NT, ELDS>(L, n, S, W);
+    update_t<NT, ELDS>(L, S, T);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT>(L, c)];
+    if (flags & SW_STORE) {
+      double* dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
+      store_stage<NT, ELDS>(L, n, S, W, T, 0.0, dst);
+    }
+    __syncthreads();
+  }
+
+  int bad = 0;
+  for (int t = L.t; t < n; t += G::THREADS) {
+    const double d = S.dnew[t];
+    if (!isfinite(d) || !(d > 0.0)) bad = 1;
+  }
+  if (flags & SW_FINAL) {
+    store_rm<NT>(L, W, I.u_out, n);
+    store_rm<NT>(L, T, I.t_out, n);
+    for (int t = L.t; t < n; t += G::THREADS) I.d_out[t] = S.dnew[t];
+  }
+  if (flags & SW_GREENS) {
+    for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
+    RM<NT> Z;
+    double ld, sg;
+    inv_one_plus<NT, ELDS>(L, n, S, W, T, sgn_u, Z, &ld, &sg);
+    if (!all_finite<NT>(L, Z) || !isfinite(ld)) bad = 1;
+    if (I.g) store_perm_rows<NT, ELDS>(L, n, S, Z, I.g);
+    if (L.t == 0) {
+      if (I.logdet) *I.logdet = ld;
+      if (I.sign) *I.sign = sg;
+    }
+  }
+  if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+}
+
+template <int NT, bool ELDS>
+__global__ __launch_bounds__(Geo<NT>::THREADS) void k_sweep(const Inst* __restrict__ insts,
+                                                            const SweepItem* __restrict__ items,
+                                                            int count, Queue* q) {
+  __shared__ Smem<NT, ELDS> S;
+  const Lane L = lane_id();
+  for (;;) {
+    __syncthreads();
+    if (L.t == 0) S.item = atomicAdd(&q->next, 1);
+    __syncthreads();
+    const int it = S.item;
+    if (it >= count) break;
+    const SweepItem wi = items[it];
+    const Inst I = insts[wi.inst];
+    sweep_one<NT, ELDS>(L, S, I, wi.flags);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time-displaced G(tau_j, 0) from forward stage F[j] = U1 D1 T1 (of
+// B(tau_j, 0)) and backward stage A[j] = U2 D2 T2 (of B(beta, tau_j)^T),
+// Sec. 6.1 inv_sum_loh with
+//   U_L D_L X_L = B(tau,0)^{-1} = T1^{-1} D1^{-1} U1^T,
+//   U_R D_R X_R = B(beta,tau)   = T2^T D2 U2^T,
+// i.e. D_L = D1^{-1}, D_R = D2, X_L X_R^{-1} = U1^T U2, U_L^{-1} U_R = T1 T2^T:
+//   Mid = D_Lm (U1^T U2) D_Rp^{-1} + D_Lp^{-1} (T1 T2^T) D_Rm
+//   G(tau,0) = U2 D_Rp^{-1} Mid^{-1} D_Lp^{-1} T1.
+// Then, for requested l inside the block, G(tau_l, 0) = B_l ... G(tau_j, 0)
+// (Sec. 6, propagation form), never across more than k-1 slices.
+template <int NT, bool ELDS>
+__device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int j,
+                           const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
+  using G = Geo<NT>;
+  constexpr int CT = G::CT;
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb;
+  const int64_t sd = stage_doubles(n);
+  const double* F = j > 0 ? I.ckf + (size_t)(j - 1) * sd : nullptr;
+  const double* A = j < nb ? I.cka + (size_t)j * sd : nullptr;
+  const double* U1 = F;
+  const double* T1 = F ? F + (size_t)n * n : nullptr;
+  const double* D1 = F ? F + 2 * (size_t)n * n : nullptr;
+  const double* U2 = A;
+  const double* T2 = A ? A + (size_t)n * n : nullptr;
+  const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
+
+  RM<NT> B, P1, P2;
+  load_rm<NT>(L, B, U2, n, false);
+  gemm_rb<NT>(L,
+              [&](int i, int kk) -> double {
+                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
+                return U1 ? U1[kk * n + i] : (i == kk ? 1.0 : 0.0);
+              },
+              B, P1);
+  load_rm<NT>(L, B, T2, n, true);
+  gemm_rb<NT>(L,
+              [&](int i, int kk) -> double {
+                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
+                return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+              },
+              B, P2);
+  // Mid and Y = D_Lp^{-1} T1
+  RM<NT> Y;
+  load_rm<NT>(L, Y, T1, n, false);
+  double d2c[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT>(L, c);
+    d2c[c] = (D2 && col < n) ? D2[col] : 1.0;
+  }
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+      const double lm = 1.0 / (d1 > 1.0 ? d1 : 1.0);   // D_Lm
+      const double lpi = d1 < 1.0 ? d1 : 1.0;           // D_Lp^{-1}
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const double d2 = d2c[c];
+        const double rpi = 1.0 / (d2 > 1.0 ? d2 : 1.0);  // D_Rp^{-1}
+        const double rm = d2 < 1.0 ? d2 : 1.0;            // D_Rm
+        P1.v[c][ti][r] = lm * P1.v[c][ti][r] * rpi + lpi * P2.v[c][ti][r] * rm;
+        Y.v[c][ti][r] *= lpi;
+      }
+    }
+  __syncthreads();
+  cpqr<NT, ELDS>(L, n, P1, S);
+  apply_qt<NT, ELDS>(L, n, S, Y);
+  back_subst<NT, ELDS>(L, n, S, Y);
+  // G = U2 D_Rp^{-1} P Z :  A(i, s) = U2[i][perm s] / max(D2[perm s], 1)
+  RM<NT> Gm;
+  gemm_rb<NT>(L,
+              [&](int i, int s) -> double {
+                if (i >= n || s >= n) return 0.0;
+                const int p = S.perm[s];
+                const double d2 = D2 ? D2[p] : 1.0;
+                const double u = U2 ? U2[i * n + p] : (i == p ? 1.0 : 0.0);
+                return u / (d2 > 1.0 ? d2 : 1.0);
+              },
+              Y, Gm);
+  if (!all_finite<NT>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+
+  // outputs: l_list[ilo..ihi), ascending, each in [tau_j, tau_j + k)
+  const int tj = j * k < m ? j * k : m;
+  int lc = tj;
+  const EOp<NT, false> eop{nullptr, I.expk, n, false};
+  for (int idx = ilo; idx < ihi; ++idx) {
+    const int l = l_list[idx];
+    const int steps = l - lc;
+    for (int c0 = 0; c0 < steps; c0 += G::KB) {
+      const int cn = (steps - c0) < G::KB ? (steps - c0) : G::KB;
+      fill_vbuf<NT, ELDS>(L, S, I, lc + c0 + 1, +1, cn);
+      for (int s2 = 0; s2 < cn; ++s2) {
+        RM<NT> Wn;
+        scale_rows<NT>(L, Gm, S.vbuf[s2]);
+        gemm_rb<NT>(L, eop, Gm, Wn);
+        Gm = Wn;
+      }
+    }
+    lc = l;
+    store_rm<NT>(L, Gm, I.gt + (size_t)idx * n * n, n);
+  }
+  __syncthreads();
+}
+
+// Gradient rows for slices l = j*k+1 .. min((j+1)k, m):
+//   G_{jk+1} = [1 + B(tau_j,0) B(beta,tau_j)]^{-1}
+//            = [1 + U1 (D1 (T1 T2^T) D2) U2^T]^{-1}                  (App. A.1)
+// with udt(D1 (T1 T2^T) D2) = u d t, U = U1 u, T = t U2^T and Loh's
+// equal-time inversion; then G_{l+1} = B_l G_l B_l^{-1} and
+//   grad[l-1][i] = alpha (1 - G_l)_ii.
+template <int NT, bool ELDS>
+__device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int j) {
+  using G = Geo<NT>;
+  constexpr int CT = G::CT;
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb;
+  const int64_t sd = stage_doubles(n);
+  const double* F = j > 0 ? I.ckf + (size_t)(j - 1) * sd : nullptr;
+  const double* A = j < nb ? I.cka + (size_t)j * sd : nullptr;
+  const double* U1 = F;
+  const double* T1 = F ? F + (size_t)n * n : nullptr;
+  const double* D1 = F ? F + 2 * (size_t)n * n : nullptr;
+  const double* U2 = A;
+  const double* T2 = A ? A + (size_t)n * n : nullptr;
+  const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
+
+  RM<NT> B, Mm;
+  load_rm<NT>(L, B, T2, n, true);
+  gemm_rb<NT>(L,
+              [&](int i, int kk) -> double {
+                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
+                return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+              },
+              B, Mm);
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT>(L, c);
+    const double d2 = (D2 && col < n) ? D2[col] : 1.0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+        Mm.v[c][ti][r] *= d1 * d2;
+      }
+  }
+  __syncthreads();
+  cpqr<NT, ELDS>(L, n, Mm, S);
+  diag_r<NT, ELDS>(L, n, S);
+  RM<NT> u, Tm, Um;
+  form_q<NT, ELDS>(L, n, S, u);
+  load_rm<NT>(L, B, U2, n, true);  // U2^T
+  gemm_rb<NT>(L, RPtOp<NT, ELDS>{S}, B, Tm);
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Tm.v[c][ti][r] /= S.dnew[row_of(L, ti, r)];
+  gemm_rb<NT>(L,
+              [&](int i, int kk) -> double {
+                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
+                return U1 ? U1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+              },
+              u, Um);
+  for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
+  RM<NT> Z;
+  double ld, sg;
+  inv_one_plus<NT, ELDS>(L, n, S, Um, Tm, 1.0, Z, &ld, &sg);
+  // G_l into LDS, row-major [row][col]
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT>(L, c)) continue;
+    const int col = col_of<NT>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = row_of(L, ti, r);
+        const int row = s < n ? S.perm[s] : s;
+        S.R[row * G::LDR + col] = (s < n && col < n) ? Z.v[c][ti][r] : (row == col ? 1.0 : 0.0);
+      }
+  }
+  __syncthreads();
+  const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
+  bool bad = false;
+  for (int t = L.t; t < n; t += G::THREADS) {
+    const double gii = S.R[t * G::LDR + t];
+    bad |= !isfinite(gii);
+    I.grad[(size_t)(l0 - 1) * n + t] = I.alpha * (1.0 - gii);
+  }
+  for (int l = l0; l < l1; ++l) {
+    // G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar
+    RM<NT> Bi, Yr, Gn;
+    const double* fl = I.field + (size_t)(l - 1) * n;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = col_of<NT>(L, c);
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row_of(L, ti, r);
+          double x = 0.0;
+          if (row < n && col < n && tile_ok<NT>(L, c))
+            x = I.expk_inv[row * n + col] * exp(-I.alpha * fl[row]);
+          Bi.v[c][ti][r] = x;
+        }
+    }
+    gemm_rb<NT>(L, [&](int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        const double v = row < n ? exp(I.alpha * fl[row]) : 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
+      }
+    gemm_rb<NT>(L,
+                [&](int i, int kk) -> double {
+                  return (i < n && kk < n) ? I.expk[i * n + kk] : 0.0;
+                },
+                Yr, Gn);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      if (!tile_ok<NT>(L, c)) continue;
+      const int col = col_of<NT>(L, c);
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S.R[row_of(L, ti, r) * G::LDR + col] = Gn.v[c][ti][r];
+    }
+    __syncthreads();
+    for (int t = L.t; t < n; t += G::THREADS) {
+      const double gii = S.R[t * G::LDR + t];
+      bad |= !isfinite(gii);
+      I.grad[(size_t)l * n + t] = I.alpha * (1.0 - gii);
+    }
+  }
+  if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+template <int NT, bool ELDS>
+__global__ __launch_bounds__(Geo<NT>::THREADS) void k_pair(const Inst* __restrict__ insts,
+                                                           const PairItem* __restrict__ items,
+                                                           int count, const int32_t* __restrict__ l_list,
+                                                           Queue* q, int mode) {
+  __shared__ Smem<NT, ELDS> S;
+  const Lane L = lane_id();
+  for (;;) {
+    __syncthreads();
+    if (L.t == 0) S.item = atomicAdd(&q->next, 1);
+    __syncthreads();
+    const int it = S.item;
+    if (it >= count) break;
+    const PairItem wi = items[it];
+    const Inst I = insts[wi.inst];
+    if (mode == PAIR_TDISP) pair_tdisp<NT, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else pair_grad<NT, ELDS>(L, S, I, wi.j);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plain UDT of independent matrices (Sec. 4.2.2): W P = Q R,
+// U = Q, D = |diag R|, T = D^{-1} R P^T
+template <int NT>
+__global__ __launch_bounds__(Geo<NT>::THREADS) void k_udt(int n, int count, const double* __restrict__ w,
+                                                          double* u, double* d, double* t) {
+  using G = Geo<NT>;
+  __shared__ Smem<NT, false> S;
+  const Lane L = lane_id();
+  for (int b = blockIdx.x; b < count; b += gridDim.x) {
+    const size_t off = (size_t)b * n * n;
+    RM<NT> W, Q, T;
+    load_rm<NT>(L, W, w + off, n, false);
+    __syncthreads();
+    cpqr<NT, false>(L, n, W, S);
+    diag_r<NT, false>(L, n, S);
+    form_q<NT, false>(L, n, S, Q);
+    store_rm<NT>(L, Q, u + off, n);
+    set_identity<NT>(L, T);
+    update_t<NT, false>(L, S, T);
+    store_rm<NT>(L, T, t + off, n);
+    for (int i = L.t; i < n; i += G::THREADS) d[(size_t)b * n + i] = S.dnew[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-tile-count launchers (instantiated once per NT in sdq_nt.hip)
+
+template <int NT>
+struct Launch {
+  static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
+                          int grid, hipStream_t s) {
+    constexpr bool kLds = NT >= 3 && NT <= 5;
+    if (variant == 1 && kLds)
+      hipLaunchKernelGGL((k_sweep<NT, kLds>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
+                         count, q);
+    else
+      hipLaunchKernelGGL((k_sweep<NT, false>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
+                         count, q);
+    return hipGetLastError();
+  }
+  static hipError_t pair(int mode, const Inst* inst, const PairItem* items, int count,
+                         const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair<NT, false>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
+                       count, l_list, q, mode);
+    return hipGetLastError();
+  }
+  static hipError_t udt(int n, int count, const double* w, double* u, double* d, double* t,
+                        hipStream_t s) {
+    const int grid = count < 4096 ? count : 4096;
+    hipLaunchKernelGGL((k_udt<NT>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, n, count, w, u, d, t);
+    return hipGetLastError();
+  }
+  template <class KF>
+  static hipError_t info_of(KF kern, int lds, KernelInfo* out) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, Geo<NT>::THREADS, 0);
+    out->threads = Geo<NT>::THREADS;
+    out->lds_bytes = lds;
+    out->blocks_per_cu = nb;
+    return e;
+  }
+  static hipError_t info(int kind, int variant, KernelInfo* out) {
+    constexpr bool kLds = NT >= 3 && NT <= 5;
+    if (kind == KK_SWEEP) {
+      if (variant == 1 && kLds) return info_of(k_sweep<NT, kLds>, (int)sizeof(Smem<NT, kLds>), out);
+      return info_of(k_sweep<NT, false>, (int)sizeof(Smem<NT, false>), out);
+    }
+    if (kind == KK_PAIR) return info_of(k_pair<NT, false>, (int)sizeof(Smem<NT, false>), out);
+    return info_of(k_udt<NT>, (int)sizeof(Smem<NT, false>), out);
+  }
+};
+
+}  // namespace sdq

@@ -1,0 +1,79 @@
+// sdq_dispatch.hip -- selects the per-tile-count kernel instantiation, and
+// the small queue-reset kernel.
+#include "sdq_internal.h"
+
+namespace sdq {
+
+#define SDQ_DECL(N)                                                                              \
+  hipError_t launch_sweep_nt##N(int, const Inst*, const SweepItem*, int, Queue*, int, hipStream_t); \
+  hipError_t launch_pair_nt##N(int, const Inst*, const PairItem*, int, const int32_t*, Queue*, int, \
+                               hipStream_t);                                                     \
+  hipError_t launch_udt_nt##N(int, int, const double*, double*, double*, double*, hipStream_t);  \
+  hipError_t kernel_info_nt##N(int, int, KernelInfo*);
+SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL(7) SDQ_DECL(8)
+#undef SDQ_DECL
+
+#define SDQ_SWITCH(CALL)                                   \
+  switch (nt) {                                            \
+    case 1: return CALL(1);                                \
+    case 2: return CALL(2);                                \
+    case 3: return CALL(3);                                \
+    case 4: return CALL(4);                                \
+    case 5: return CALL(5);                                \
+    case 6: return CALL(6);                                \
+    case 7: return CALL(7);                                \
+    case 8: return CALL(8);                                \
+    default: return hipErrorInvalidValue;                  \
+  }
+
+hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
+                        Queue* q, int grid, hipStream_t s) {
+#define C(N) launch_sweep_nt##N(variant, inst, items, count, q, grid, s)
+  SDQ_SWITCH(C)
+#undef C
+}
+
+hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
+                       int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
+  (void)variant;
+#define C(N) launch_pair_nt##N(mode, inst, items, count, l_list, q, grid, s)
+  SDQ_SWITCH(C)
+#undef C
+}
+
+hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, double* d, double* t,
+                      hipStream_t s) {
+#define C(N) launch_udt_nt##N(n, count, w, u, d, t, s)
+  SDQ_SWITCH(C)
+#undef C
+}
+
+hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
+#define C(N) kernel_info_nt##N(kind, variant, out)
+  SDQ_SWITCH(C)
+#undef C
+}
+
+__global__ void k_reset(Queue* q, int nq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nq) q[i].next = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(Queue* q, int nq, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reset, dim3((nq + 63) / 64), dim3(64), 0, s, q, nq);
+  return hipGetLastError();
+}
+
+}  // namespace sdq

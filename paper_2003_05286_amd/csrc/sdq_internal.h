@@ -1,0 +1,92 @@
+// sdq_internal.h -- structures shared by the host runtime and the gfx950
+// kernels of libsdq (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdq {
+
+// Largest number of 16-wide tiles per matrix dimension handled by the
+// LDS-resident kernels: n <= 16 * kMaxNT = 128.
+constexpr int kMaxNT = 8;
+
+// One stored UDT factorization ("stage") of a chain, kept in HBM:
+//   U [n*n] | T [n*n] | D [n] | extra [kStageExtra]
+// extra[0] = sign of det U.
+constexpr int kStageExtra = 8;
+__host__ __device__ inline int64_t stage_doubles(int n) {
+  return 2LL * n * n + n + kStageExtra;
+}
+
+// One chain as seen by the kernels.
+struct Inst {
+  const double* expk;      // [n][n]
+  const double* expk_inv;  // [n][n] or null
+  const double* field;     // [m][n]
+  double alpha;
+  int32_t n, m, k, nb;     // nb = ceil(m / k) stabilization blocks
+  double* g;               // equal-time G [n][n] or null
+  double* gt;              // time-displaced outputs [n_l][n][n] or null
+  double* grad;            // [m][n] or null
+  double* logdet;          // scalar or null
+  double* sign;            // scalar or null
+  int32_t* status;         // scalar or null
+  double* ckf;             // forward stages F[1..nb] (nb * stage_doubles) or null
+  double* cka;             // backward stages A[0..nb-1] or null
+  double* u_out;           // final U / D / T of the sweep, or null
+  double* d_out;
+  double* t_out;
+};
+
+enum SweepFlags : int32_t {
+  SW_ADJ = 1,     // backward sweep over B_l^T from l = m down to 1
+  SW_STORE = 2,   // store every stage (ckf for forward, cka for backward)
+  SW_GREENS = 4,  // forward only: G, logdet, sign from the final factors
+  SW_FINAL = 8,   // write the final U, D, T to u_out / d_out / t_out
+};
+
+struct SweepItem {
+  int32_t inst;
+  int32_t flags;
+};
+
+enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1 };
+
+// tdisp: stage pair j, outputs for l_list[ilo..ihi)
+// grad:  stage pair j (slices j*k+1 .. min((j+1)k, m))
+struct PairItem {
+  int32_t inst;
+  int32_t j;
+  int32_t ilo;
+  int32_t ihi;
+};
+
+struct Queue {
+  int32_t next;
+  int32_t pad[31];
+};
+
+// status bits accumulated per instance (any nonzero => SDQ_ERANGE)
+// value OR-ed into an instance status word on a numerical failure (== SDQ_ERANGE)
+constexpr int32_t kStatusRange = -4;
+
+// ---- launchers (sdq_kernels.hip) -----------------------------------------
+struct KernelInfo {
+  int threads;
+  int lds_bytes;
+  int blocks_per_cu;  // occupancy reported by the runtime
+};
+
+hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out);
+hipError_t launch_reset(Queue* q, int nq, hipStream_t s);
+hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
+                        Queue* q, int grid, hipStream_t s);
+hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
+                       int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s);
+hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, double* d, double* t,
+                      hipStream_t s);
+
+enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2 };
+
+}  // namespace sdq

@@ -97,7 +97,7 @@ class Instance:
 
     @property
     def n(self) -> int:
-        return self.L * self.L
+        return self.expk.shape[0]
 
 
 @dataclass
