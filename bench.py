@@ -1,0 +1,227 @@
+"""Benchmark: batched stabilized Green's functions on one MI355X.
+
+Workload (one "step"): 512 Hubbard chains, L = 8 (N = 64 sites), beta = 40
+(M = 400 slices, dtau = 0.1), U = 4, k = 10: 256 seeded Ising fields x both
+spin flavours.  Every step computes, for every chain, the equal-time G, its
+log|det(1 + B)| and sign, and G(tau_l, 0) at l = 10, 20, ..., 400 (40
+matrices per chain), in one batched call (forward + backward stabilized
+sweeps, then the time-displaced inversions).  Inputs are resident in HBM
+before the timed region.
+
+Printed: one JSON line with the throughput (chains per second, each chain
+with its G and 40 G(tau,0)), the roofline of the dominant kernel measured
+with HIP events over the timed region, and the CPU oracle timed on a bounded
+sample on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA = 78.6e12   # MI355X dense FP64 matrix, FLOP/s
+PEAK_HBM = 8.0e12          # bytes/s
+
+
+def sweep_flops(n, m, k):
+    """Algorithmic flops of one stabilized sweep: 2N^3 per slice product and
+    (4/3 + 4/3 + 1) N^3 per stabilization (pivoted QR, forming Q, T update)."""
+    nb = math.ceil(m / k)
+    return (2.0 * m + nb * 11.0 / 3.0) * n ** 3
+
+
+def pair_flops(n, n_direct, n_prop):
+    """Time-displaced inversions: per direct tau two products (4N^3), pivoted
+    QR of the middle matrix (4/3 N^3), Q^T applied to N right-hand sides
+    (2N^3), triangular solve (N^3) and the final product (2N^3); 2N^3 per
+    propagated slice."""
+    return n_direct * (4.0 + 4.0 / 3.0 + 2.0 + 1.0 + 2.0) * n ** 3 + n_prop * 2.0 * n ** 3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="chains in the CPU sample")
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 512 chains (tests only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the path shards by independent chains, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2003_05286_amd import binding as sdq
+    from paper_2003_05286_amd import workloads as wl
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    W = wl.workload("hubbard_L8_b40_batch512", scale=args.scale)
+    insts = W.instances
+    l_list = W.l_list
+    n, m, k = insts[0].n, insts[0].m, insts[0].k
+    cnt = len(insts)
+    print(f"[bench] {W.name}: {cnt} chains, n={n}, m={m}, k={k}, {len(l_list)} G(tau,0) each",
+          file=sys.stderr, flush=True)
+
+    # inputs resident in HBM before timing (flavours share their field tensor)
+    E = torch.from_numpy(insts[0].expk).to(dev)
+    Ei = torch.from_numpy(insts[0].expk_inv).to(dev)
+    fields = {}
+    chains = []
+    for I in insts:
+        key = id(I.field)
+        if key not in fields:
+            fields[key] = torch.from_numpy(np.ascontiguousarray(I.field)).to(dev)
+        chains.append(sdq.Chain(E, fields[key], I.alpha, I.k, Ei))
+    ctx = sdq.Context(0)
+    # outputs preallocated once
+    import ctypes
+    inst_arr = ctx._instances(chains)
+    ls = (ctypes.c_int32 * len(l_list))(*l_list)
+    gts = [torch.empty(len(l_list), n, n, dtype=torch.float64, device=dev) for _ in chains]
+    gs = [torch.empty(n, n, dtype=torch.float64, device=dev) for _ in chains]
+    ld = torch.empty(cnt, dtype=torch.float64, device=dev)
+    sg = torch.empty(cnt, dtype=torch.float64, device=dev)
+    st = torch.empty(cnt, dtype=torch.int32, device=dev)
+    gt_ptrs = ctx._ptr_array(gts)
+    g_ptrs = ctx._ptr_array(gs)
+
+    def step():
+        ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, ls, len(l_list),
+                                          gt_ptrs, g_ptrs, ctypes.c_void_p(ld.data_ptr()),
+                                          ctypes.c_void_p(sg.data_ptr()),
+                                          ctypes.c_void_p(st.data_ptr())))
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    if int((st != 0).sum().item()) != 0:
+        raise SystemExit("bench: nonzero status after warmup")
+
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_sw, ms_sw = ctx.kernel_stats("sweep")
+    n_pa, ms_pa = ctx.kernel_stats("pair")
+    ctx.set_profiling(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
+          f"{n_sw}, pair {ms_pa / max(n_pa, 1):.3f} ms x {n_pa}", file=sys.stderr, flush=True)
+    status_ok = int((st != 0).sum().item()) == 0
+
+    sweeps = 2 * cnt
+    f_sweep = sweeps * sweep_flops(n, m, k)
+    n_direct = len(l_list)
+    f_pair = cnt * pair_flops(n, n_direct, 0)
+    f_equal = cnt * (4.0 / 3.0 + 2.0 + 1.0 + 2.0) * n ** 3
+    sweep_avg_s = ms_sw / max(n_sw, 1) * 1e-3
+    pair_avg_s = ms_pa / max(n_pa, 1) * 1e-3
+    achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
+    total_flops = f_sweep + f_pair + f_equal
+
+    # equal-time only, same batch (one forward sweep per chain)
+    gs2, ld2, sg2, st2 = ctx.greens(chains)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.greens(chains)
+    torch.cuda.synchronize()
+    eq_rate = cnt * args.steps / (time.perf_counter() - t2)
+
+    # plain per-instance form on the same GPU: one chain per call, looped
+    sub = chains[: min(32, cnt)]
+    for c in sub[:2]:
+        ctx.greens_tdisp([c], l_list)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for c in sub:
+        ctx.greens_tdisp([c], l_list)
+    torch.cuda.synchronize()
+    per_inst_rate = len(sub) / (time.perf_counter() - t3)
+
+    out = {
+        "metric": "stabilized Green's functions/sec (FP64, L=8, beta=40, batched)",
+        "value": cnt / (ms_step * 1e-3),
+        "unit": "chains/s (each: G + 40 G(tau,0))",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": W.name, "chains": cnt, "n": n, "m": m, "k": k, "beta": 40.0,
+                   "dtau": 0.1, "U": 4.0, "l_list": "10,20,...,400", "scheme": "loh"},
+        "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "flops_per_launch": f_sweep, "launch_ms": sweep_avg_s * 1e3},
+        "pair_kernel": {"launch_ms": pair_avg_s * 1e3, "flops_per_launch": f_pair,
+                        "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
+        "step_tflops": total_flops / (ms_step * 1e-3) / 1e12,
+        "green_matrices_per_s": cnt * (1 + len(l_list)) / (ms_step * 1e-3),
+        "equal_time_only_per_s": eq_rate,
+        "per_instance_loop_per_s": per_inst_rate,
+        "status_ok": status_ok,
+    }
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(insts, l_list, nchains):
+    """The oracle as it stands, on a bounded sample: `nchains` chains, each
+    with its G and all G(tau_l, 0), spread over the host cores (one oracle
+    call per thread; the C oracle releases the GIL)."""
+    import oracle
+
+    sample = insts[:nchains]
+    jobs = []
+    for I in sample:
+        jobs.append(("g", I, 0))
+        for l in l_list:
+            jobs.append(("t", I, l))
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def run(job):
+        kind, I, l = job
+        if kind == "g":
+            oracle.greens(I.expk, I.field, I.alpha, I.k)
+        else:
+            oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l)
+
+    print(f"[bench] cpu oracle: {len(jobs)} calls on {threads} threads", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, jobs))
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "chains/s (each: G + 40 G(tau,0))", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(sample)} of the 512 chains, each: oracle G plus oracle G(tau_l,0) for all "
+                      f"{len(l_list)} l; {dt:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

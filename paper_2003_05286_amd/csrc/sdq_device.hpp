@@ -46,19 +46,19 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // geometry
 
-template <int NT>
+template <int NT, int P_>
 struct Geo {
   static constexpr int NP = 16 * NT;             // padded dimension
-  static constexpr int P = NT < 4 ? NT : 4;      // waves per workgroup
+  static constexpr int P = P_;                   // waves per workgroup (one chain)
   static constexpr int CT = (NT + P - 1) / P;    // column tiles per wave (max)
   static constexpr int LDR = NP + 1;             // LDS column stride (odd: no bank conflicts)
   static constexpr int THREADS = 64 * P;
-  static constexpr int KB = NT <= 6 ? 16 : 8;    // slices of field exponentials staged at once
+  static constexpr int KB = (P == 1 || NT > 6) ? 8 : 16;  // slices of exp(alpha f) staged at once
 };
 
-template <int NT, bool ELDS>
+template <int NT, int P, bool ELDS>
 struct Smem {
-  using G = Geo<NT>;
+  using G = Geo<NT, P>;
   double R[G::NP * G::LDR];                  // factor store, [col][row]
   double E[ELDS ? G::NP * G::LDR : 1];       // staged slice exponential, [row][col]
   double cand[2][G::P][G::NP];               // pivot candidate columns
@@ -75,9 +75,9 @@ struct Smem {
   int item;
 };
 
-template <int NT>
+template <int NT, int P>
 struct RM {  // register-resident n x n matrix, column split (see header)
-  double v[Geo<NT>::CT][NT][4];
+  double v[Geo<NT, P>::CT][NT][4];
 };
 
 struct Lane {
@@ -94,29 +94,80 @@ __device__ __forceinline__ Lane lane_id() {
   return L;
 }
 
-template <int NT>
+template <int NT, int P>
 __device__ __forceinline__ bool tile_ok(const Lane& L, int c) {
-  return L.w + Geo<NT>::P * c < NT;
+  return L.w + Geo<NT, P>::P * c < NT;
 }
-template <int NT>
+template <int NT, int P>
 __device__ __forceinline__ int col_of(const Lane& L, int c) {
-  return 16 * (L.w + Geo<NT>::P * c) + L.cl;
+  return 16 * (L.w + Geo<NT, P>::P * c) + L.cl;
 }
 __device__ __forceinline__ int row_of(const Lane& L, int ti, int r) { return 16 * ti + L.g + 4 * r; }
 
-__device__ __forceinline__ double shx(double v, int m) { return __shfl_xor(v, m); }
-__device__ __forceinline__ int shx(int v, int m) { return __shfl_xor(v, m); }
-// sum over the four lanes holding one column; every one of them gets the
-// bitwise-same result (each pairwise add is commutative)
-__device__ __forceinline__ double sum_col(double v) {
-  v += shx(v, 16);
-  v += shx(v, 32);
+// ---- cross-lane primitives -------------------------------------------------
+// A column lives in the four lanes l, l^16, l^32, l^48 (one lane per 16-lane
+// row).  v_permlane16_swap / v_permlane32_swap exchange whole rows, so a
+// sum over the four lanes is two swaps and two adds; every lane performs
+// the same additions in the same order, so all four get bitwise-identical
+// results (which the redundant per-wave reflector computation relies on).
+__device__ __forceinline__ double pl16_pair_sum(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  // a[0]/b[0]: the even row of the pair, a[1]/b[1]: the odd row
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double pl32_pair_sum(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double pl16_pair_max(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return fmax(__hiloint2double((int)b[0], (int)a[0]), __hiloint2double((int)b[1], (int)a[1]));
+}
+__device__ __forceinline__ double pl32_pair_max(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return fmax(__hiloint2double((int)b[0], (int)a[0]), __hiloint2double((int)b[1], (int)a[1]));
+}
+// sum / max over the four lanes holding one column
+__device__ __forceinline__ double sum_col(double v) { return pl32_pair_sum(pl16_pair_sum(v)); }
+__device__ __forceinline__ double max_col(double v) { return pl32_pair_max(pl16_pair_max(v)); }
+
+// rotate a double right by R lanes inside each 16-lane row (DPP row_ror)
+template <int R>
+__device__ __forceinline__ double row_ror(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x120 + R, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x120 + R, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// max over the 16 lanes of each row (all of them get the result)
+__device__ __forceinline__ double row_max16(double v) {
+  v = fmax(v, row_ror<8>(v));
+  v = fmax(v, row_ror<4>(v));
+  v = fmax(v, row_ror<2>(v));
+  v = fmax(v, row_ror<1>(v));
   return v;
 }
-__device__ __forceinline__ double max_col(double v) {
-  v = fmax(v, shx(v, 16));
-  v = fmax(v, shx(v, 32));
-  return v;
+
+// Pivot key: the column norm with its 7 lowest mantissa bits replaced by
+// 127 - column, so that one max over doubles picks the largest norm and,
+// among norms equal to 2^-45 relative, the smallest column index.  A NaN or
+// infinite norm is clamped (never loses eligibility); -1 marks "not a
+// candidate".
+__device__ __forceinline__ double pivot_key(double norm, int col) {
+  double x = norm >= 0.0 ? norm : 0.0;  // NaN -> 0
+  x = x < 1.0e300 ? x : 1.0e300;
+  const unsigned long long b = (__double_as_longlong(x) & ~0x7Full) | (unsigned long long)(127 - col);
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ int pivot_col(double key) {
+  return 127 - (int)(__double_as_longlong(key) & 0x7F);
 }
 
 // exact power-of-two scale that brings x near 1 (1 for 0, inf, nan)
@@ -125,38 +176,48 @@ __device__ __forceinline__ double pow2_scale(double x) {
   return ldexp(1.0, -ilogb(x));
 }
 
-template <int NT>
-__device__ __forceinline__ void set_identity(const Lane& L, RM<NT>& A) {
+template <int NT, int P>
+__device__ __forceinline__ void set_identity(const Lane& L, RM<NT, P>& A) {
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c)
+  for (int c = 0; c < Geo<NT, P>::CT; ++c)
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) A.v[c][ti][r] = (row_of(L, ti, r) == col_of<NT>(L, c)) ? 1.0 : 0.0;
+      for (int r = 0; r < 4; ++r) A.v[c][ti][r] = (row_of(L, ti, r) == col_of<NT, P>(L, c)) ? 1.0 : 0.0;
 }
 
-// value of row j of column block c, fetched from the lane group that holds it
+// entry [tj][rj] of one lane's column slice; tj, rj are wave-uniform
 template <int NT>
-__device__ __forceinline__ double row_value(const Lane& L, const RM<NT>& A, int c, int j) {
-  const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
-  double s = 0.0;
+__device__ __forceinline__ double reg_at(const double (&a)[NT][4], int tj, int rj) {
+  double t[4];
 #pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
+  for (int r = 0; r < 4; ++r) {
+    t[r] = a[0][r];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (ti == tj && r == rj) s = A.v[c][ti][r];
-  return __shfl(s, gj * 16 + L.cl);
+    for (int ti = 1; ti < NT; ++ti)
+      if (ti == tj) t[r] = a[ti][r];
+  }
+  return rj == 0 ? t[0] : rj == 1 ? t[1] : rj == 2 ? t[2] : t[3];
+}
+
+// value of row j of column block c, from the lane group that holds it,
+// broadcast to the four lanes of the column
+template <int NT, int P>
+__device__ __forceinline__ double row_value(const Lane& L, const RM<NT, P>& A, int c, int j) {
+  const double s = reg_at<NT>(A.v[c], j >> 4, (j >> 2) & 3);
+  return sum_col(L.g == (j & 3) ? s : 0.0);
 }
 
 // ---------------------------------------------------------------------------
-// C = A * B on FP64 MFMA.  A(i, k) is any callable returning the entry of
-// the left operand (i, k < NP); B and C are register matrices.  The B
+// C = A * B on FP64 MFMA.  A(ti, tk, r, i, k) is any callable returning the
+// entry (i, k) of the left operand, i = 16 ti + l%16, k = 16 tk + l/16 + 4 r
+// (i, k < NP) for the calling lane l; B and C are register matrices.  The B
 // operand of one 16x16x4 step is register [c][tk][r] as is: its four k
 // indices are rows 16tk + q + 4r, q = 0..3, so the A operand is fetched with
 // the same row permutation of k.
-template <int NT, class AF>
-__device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT>& B, RM<NT>& C) {
-  constexpr int CT = Geo<NT>::CT;
+template <int NT, int P, class AF>
+__device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT, P>& B, RM<NT, P>& C) {
+  constexpr int CT = Geo<NT, P>::CT;
   d4 acc[CT][NT];
 #pragma unroll
   for (int c = 0; c < CT; ++c)
@@ -169,10 +230,10 @@ __device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT>& B, RM
       const int kk = 16 * tk + L.g + 4 * r;
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti) {
-        const double a = A(16 * ti + L.cl, kk);
+        const double a = A(ti, tk, r, 16 * ti + L.cl, kk);
 #pragma unroll
         for (int c = 0; c < CT; ++c)
-          if (c == 0 || tile_ok<NT>(L, c))
+          if (c == 0 || tile_ok<NT, P>(L, c))
             acc[c][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B.v[c][tk][r], acc[c][ti], 0, 0, 0);
       }
     }
@@ -187,11 +248,11 @@ __device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT>& B, RM
 
 // load a row-major n x n global matrix (or its transpose) into registers,
 // zero padded; `src == nullptr` loads the identity
-template <int NT>
-__device__ __forceinline__ void load_rm(const Lane& L, RM<NT>& A, const double* src, int n, bool trans) {
+template <int NT, int P>
+__device__ __forceinline__ void load_rm(const Lane& L, RM<NT, P>& A, const double* src, int n, bool trans) {
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c) {
-    const int col = col_of<NT>(L, c);
+  for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -199,7 +260,7 @@ __device__ __forceinline__ void load_rm(const Lane& L, RM<NT>& A, const double* 
         const int row = row_of(L, ti, r);
         double x;
         if (src == nullptr) x = (row == col) ? 1.0 : 0.0;
-        else if (row < n && col < n && tile_ok<NT>(L, c)) x = trans ? src[col * n + row] : src[row * n + col];
+        else if (row < n && col < n && tile_ok<NT, P>(L, c)) x = trans ? src[col * n + row] : src[row * n + col];
         else x = 0.0;
         A.v[c][ti][r] = x;
       }
@@ -207,12 +268,12 @@ __device__ __forceinline__ void load_rm(const Lane& L, RM<NT>& A, const double* 
 }
 
 // store the leading n x n block of a register matrix (row-major)
-template <int NT>
-__device__ __forceinline__ void store_rm(const Lane& L, const RM<NT>& A, double* dst, int n) {
+template <int NT, int P>
+__device__ __forceinline__ void store_rm(const Lane& L, const RM<NT, P>& A, double* dst, int n) {
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c) {
-    const int col = col_of<NT>(L, c);
-    if (!tile_ok<NT>(L, c) || col >= n) continue;
+  for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+    if (!tile_ok<NT, P>(L, c) || col >= n) continue;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -223,11 +284,11 @@ __device__ __forceinline__ void store_rm(const Lane& L, const RM<NT>& A, double*
   }
 }
 
-template <int NT>
-__device__ __forceinline__ bool all_finite(const Lane& L, const RM<NT>& A) {
+template <int NT, int P>
+__device__ __forceinline__ bool all_finite(const Lane& L, const RM<NT, P>& A) {
   bool ok = true;
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c)
+  for (int c = 0; c < Geo<NT, P>::CT; ++c)
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -249,19 +310,20 @@ __device__ __forceinline__ bool all_finite(const Lane& L, const RM<NT>& A) {
 // implied), with s_c = S.sinv[c] the step at which c was chosen; S.perm[j]
 // is the column chosen at step j and S.tau[j] its reflector scalar.  So
 // R P^T has column c = S.R column c masked to rows <= s_c.  Padded columns
-// are stored as unit vectors with s_c = c.  Ends with a barrier.
-template <int NT, bool ELDS>
-__device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
-  using G = Geo<NT>;
-  constexpr int CT = G::CT, P = G::P;
+// are stored as unit vectors with s_c = c.  One barrier per step; ends with
+// a barrier.
+template <int NT, int P, bool ELDS>
+__device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>& S) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
   double vn1[CT], vn2[CT];
-  int ps[CT];  // -1 live and not yet chosen, else the step (padding: own index)
+  int ps[CT];  // -1: live, not yet chosen; else the step (padding: own index)
 
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT>(L, c);
-    const bool live = tile_ok<NT>(L, c) && col < n;
+    const int col = col_of<NT, P>(L, c);
+    const bool live = tile_ok<NT, P>(L, c) && col < n;
     ps[c] = live ? -1 : col;
     double mx = 0.0;
 #pragma unroll
@@ -285,128 +347,118 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
 
   int buf = 0;
   for (int j = 0; j < n; ++j) {
-    // ---- wave-local candidate: largest norm, ties to the smaller column
-    double bk = -1.0;
-    int bc = 0x7fffffff;
+    const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
+    // ---- wave-local candidate (packed key), columns of this wave
+    double key = -1.0;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      if (ps[c] < 0) key = fmax(key, pivot_key(vn1[c], col_of<NT, P>(L, c)));
+    key = row_max16(key);  // the four rows hold the same columns
+    const int bc = pivot_col(key);
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      if (ps[c] < 0) {
-        const double key = (vn1[c] >= 0.0) ? vn1[c] : -0.5;  // NaN never wins but stays eligible
-        const int col = col_of<NT>(L, c);
-        if (key > bk || (key == bk && col < bc)) {
-          bk = key;
-          bc = col;
-        }
-      }
-    }
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) {
-      const double ok = shx(bk, m);
-      const int oc = shx(bc, m);
-      if (ok > bk || (ok == bk && oc < bc)) {
-        bk = ok;
-        bc = oc;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      if (ps[c] < 0 && col_of<NT>(L, c) == bc) {
+      if (key >= 0.0 && ps[c] < 0 && col_of<NT, P>(L, c) == bc) {
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
-          if (16 * ti + 15 >= j)
+          if (ti >= tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) S.cand[buf][L.w][row_of(L, ti, r)] = A.v[c][ti][r];
       }
     }
-    if (L.l == 0) {
-      S.ckey[buf][L.w] = bk;
-      S.ccol[buf][L.w] = bc;
-    }
-    __syncthreads();
-
-    // ---- workgroup pivot
-    double pk = S.ckey[buf][0];
-    int pc = S.ccol[buf][0], pw = 0;
+    double pk = key;
+    if constexpr (P > 1) {
+      if (L.l == 0) S.ckey[buf][L.w] = key;
+      __syncthreads();
+      // workgroup pivot: the owner wave follows from the column index
+      pk = S.ckey[buf][0];
 #pragma unroll
-    for (int q = 1; q < P; ++q) {
-      const double k2 = S.ckey[buf][q];
-      const int c2 = S.ccol[buf][q];
-      if (k2 > pk || (k2 == pk && c2 < pc)) {
-        pk = k2;
-        pc = c2;
-        pw = q;
-      }
+      for (int q = 1; q < P; ++q) pk = fmax(pk, S.ckey[buf][q]);
+    } else {
+      // one wave: its own LDS writes are visible to its later reads
+      __builtin_amdgcn_wave_barrier();
     }
+    const int pc = pivot_col(pk);
+    const int pw = (pc >> 4) % P;
     const double* xc = S.cand[buf][pw];
     const double alpha = xc[j];
+    // norm estimate of the pivot column (key without the index bits)
+    const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~0x7Fll);
 
     // ---- reflector (every wave computes the same one from the same data)
-    const double sc = pow2_scale(pk);
+    const double sc = pow2_scale(vpiv);
     double v[NT][4];
     double s = 0.0;
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
+    for (int ti = 0; ti < NT; ++ti) {
+      if (ti < tj) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        double x = 0.0;
-        if (16 * ti + 15 > j && row > j && row < n) x = xc[row];
-        v[ti][r] = x;
-        const double y = x * sc;
-        s = fma(y, y, s);
+        for (int r = 0; r < 4; ++r) v[ti][r] = 0.0;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double x = xc[row_of(L, ti, r)];
+          if (ti == tj && row_of(L, ti, r) <= j) x = 0.0;
+          v[ti][r] = x;
+          const double y = x * sc;
+          s = fma(y, y, s);
+        }
       }
+    }
     s = sum_col(s);
-    const double xnorm = sqrt(s) / sc;
+    const double as = alpha * sc;
+    const double hn = sqrt(fma(as, as, s)) / sc;  // ||x[j:]||
     double tau = 0.0, beta = alpha, inv = 0.0;
-    if (xnorm != 0.0) {
-      beta = -copysign(hypot(alpha, xnorm), alpha);
+    if (s != 0.0) {
+      beta = -copysign(hn, alpha);
       tau = (beta - alpha) / beta;
       inv = 1.0 / (alpha - beta);
     }
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
+      if (ti >= tj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        v[ti][r] = (row == j) ? 1.0 : v[ti][r] * inv;
-      }
+        for (int r = 0; r < 4; ++r) {
+          const double x = v[ti][r] * inv;
+          v[ti][r] = (ti == tj && row_of(L, ti, r) == j) ? 1.0 : x;
+        }
 
     // ---- apply H_j to the other live columns, downdate their norms
     bool need = false;
     bool rec[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      const int col = col_of<NT>(L, c);
-      const bool upd = ps[c] < 0 && col != pc;
+      const int col = col_of<NT, P>(L, c);
+      const bool is_piv = ps[c] < 0 && col == pc;
+      const bool upd = ps[c] < 0 && !is_piv;
       rec[c] = false;
-      const double t_eff = upd ? tau : 0.0;
       double d = 0.0;
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti + 15 >= j)
+        if (ti >= tj)
 #pragma unroll
           for (int r = 0; r < 4; ++r) d = fma(v[ti][r], A.v[c][ti][r], d);
-      d = sum_col(d) * t_eff;
-      if (ps[c] < 0 && col == pc) {
+      d = sum_col(d) * (upd ? tau : 0.0);
+      if (is_piv) {
         // the pivot column becomes column j of R plus the reflector
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
+          if (ti >= tj)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = row_of(L, ti, r);
-            if (row == j) A.v[c][ti][r] = beta;
-            else if (row > j) A.v[c][ti][r] = v[ti][r];
-          }
+            for (int r = 0; r < 4; ++r) {
+              const int row = row_of(L, ti, r);
+              if (ti > tj || row > j) A.v[c][ti][r] = v[ti][r];
+              else if (row == j) A.v[c][ti][r] = beta;
+            }
       } else {
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
-          if (16 * ti + 15 >= j)
+          if (ti >= tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
       }
-      const double rj = row_value<NT>(L, A, c, j);
+      const double rjv = sum_col(L.g == gj ? reg_at<NT>(A.v[c], tj, rj) : 0.0);
       if (upd && vn1[c] != 0.0) {
-        double t = fabs(rj) / vn1[c];
+        double t = fabs(rjv) / vn1[c];
         t = fmax(0.0, (1.0 - t) * (1.0 + t));
         const double ratio = vn1[c] / vn2[c];
         if (t * ratio * ratio <= tol3z) {
@@ -448,7 +500,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c)
-      if (ps[c] < 0 && col_of<NT>(L, c) == pc) ps[c] = j;
+      if (ps[c] < 0 && col_of<NT, P>(L, c) == pc) ps[c] = j;
     if (L.t == 0) {
       S.tau[j] = tau;
       S.perm[j] = pc;
@@ -459,8 +511,8 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
   // ---- park R / reflectors in LDS
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    if (!tile_ok<NT>(L, c)) continue;
-    const int col = col_of<NT>(L, c);
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
     const bool live = col < n;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
@@ -479,130 +531,131 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT>& A, Smem<NT, ELDS>& S) {
 }
 
 // D' = |diag R| (1 on padding) into S.dnew; ends with a barrier
-template <int NT, bool ELDS>
-__device__ __forceinline__ void diag_r(const Lane& L, const int n, Smem<NT, ELDS>& S) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void diag_r(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
+  using G = Geo<NT, P>;
   for (int t = L.t; t < G::NP; t += G::THREADS)
     S.dnew[t] = t < n ? fabs(S.R[S.perm[t] * G::LDR + t]) : 1.0;
   __syncthreads();
 }
 
+// reflector j from the factor store, at this lane's rows (zero above row j)
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void load_reflector(const Lane& L, const Smem<NT, P, ELDS>& S, int j,
+                                               double (&v)[NT][4]) {
+  const int tj = j >> 4;
+  const double* vc = &S.R[S.perm[j] * Geo<NT, P>::LDR];
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti) {
+    if (ti < tj) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      const double x = vc[row];
+      v[ti][r] = (ti > tj || row > j) ? x : (row == j ? 1.0 : 0.0);
+    }
+  }
+}
+
+// X <- H_j X for all column blocks (rows < j untouched)
+template <int NT, int P>
+__device__ __forceinline__ void apply_reflector(const Lane& L, int j, double tau,
+                                                const double (&v)[NT][4], RM<NT, P>& X) {
+  const int tj = j >> 4;
+#pragma unroll
+  for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    double d = 0.0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+      if (ti >= tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d = fma(v[ti][r], X.v[c][ti][r], d);
+    d = sum_col(d) * tau;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+      if (ti >= tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X.v[c][ti][r] = fma(-d, v[ti][r], X.v[c][ti][r]);
+  }
+}
+
 // Q = H_0 H_1 ... H_{n-1} into registers
-template <int NT, bool ELDS>
-__device__ void form_q(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& X) {
-  using G = Geo<NT>;
-  set_identity<NT>(L, X);
+template <int NT, int P, bool ELDS>
+__device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& X) {
+  set_identity<NT, P>(L, X);
   for (int j = n - 1; j >= 0; --j) {
     const double tau = S.tau[j];
     if (tau == 0.0) continue;
-    const double* vc = &S.R[S.perm[j] * G::LDR];
     double v[NT][4];
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        v[ti][r] = (16 * ti + 15 >= j) ? (row > j ? vc[row] : (row == j ? 1.0 : 0.0)) : 0.0;
-      }
-#pragma unroll
-    for (int c = 0; c < G::CT; ++c) {
-      double d = 0.0;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti + 15 >= j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], X.v[c][ti][r], d);
-      d = sum_col(d) * tau;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti + 15 >= j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) X.v[c][ti][r] = fma(-d, v[ti][r], X.v[c][ti][r]);
-    }
+    load_reflector<NT, P, ELDS>(L, S, j, v);
+    apply_reflector<NT, P>(L, j, tau, v, X);
   }
 }
 
 // Y <- Q^T Y = H_{n-1} ... H_0 Y
-template <int NT, bool ELDS>
-__device__ void apply_qt(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& Y) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
   for (int j = 0; j < n; ++j) {
     const double tau = S.tau[j];
     if (tau == 0.0) continue;
-    const double* vc = &S.R[S.perm[j] * G::LDR];
     double v[NT][4];
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        v[ti][r] = (16 * ti + 15 >= j) ? (row > j ? vc[row] : (row == j ? 1.0 : 0.0)) : 0.0;
-      }
-#pragma unroll
-    for (int c = 0; c < G::CT; ++c) {
-      double d = 0.0;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti + 15 >= j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], Y.v[c][ti][r], d);
-      d = sum_col(d) * tau;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti + 15 >= j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Y.v[c][ti][r] = fma(-d, v[ti][r], Y.v[c][ti][r]);
-    }
+    load_reflector<NT, P, ELDS>(L, S, j, v);
+    apply_reflector<NT, P>(L, j, tau, v, Y);
   }
 }
 
 // Y <- R^{-1} Y (R in pivot order: R[i][j] = S.R[perm[j]*LDR + i], i <= j)
-template <int NT, bool ELDS>
-__device__ void back_subst(const Lane& L, const int n, const Smem<NT, ELDS>& S, RM<NT>& Y) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
+  using G = Geo<NT, P>;
   for (int j = n - 1; j >= 0; --j) {
+    const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
     const double* rc = &S.R[S.perm[j] * G::LDR];
-    const double rjj = rc[j];
+    const double rinv = 1.0 / rc[j];
     double rr[NT][4];
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
+    for (int ti = 0; ti < NT; ++ti) {
+      if (ti > tj) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
-        rr[ti][r] = (16 * ti <= j && row < j) ? rc[row] : 0.0;
+        const double x = rc[row];
+        rr[ti][r] = (ti < tj || row < j) ? x : 0.0;
       }
+    }
 #pragma unroll
     for (int c = 0; c < G::CT; ++c) {
-      const double zj = row_value<NT>(L, Y, c, j) / rjj;
+      const double zj = sum_col(L.g == gj ? reg_at<NT>(Y.v[c], tj, rj) : 0.0) * rinv;
 #pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (16 * ti <= j)
+      for (int ti = 0; ti < NT; ++ti) {
+        if (ti > tj) continue;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = row_of(L, ti, r);
-            if (row == j) Y.v[c][ti][r] = zj;
-            else Y.v[c][ti][r] = fma(-rr[ti][r], zj, Y.v[c][ti][r]);
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int row = row_of(L, ti, r);
+          if (ti == tj && row == j) Y.v[c][ti][r] = zj;
+          else Y.v[c][ti][r] = fma(-rr[ti][r], zj, Y.v[c][ti][r]);
+        }
+      }
     }
   }
 }
 
 // left operand of R P^T: column c, rows <= s_c
-template <int NT, bool ELDS>
+template <int NT, int P, bool ELDS>
 struct RPtOp {
-  const Smem<NT, ELDS>& S;
-  __device__ double operator()(int i, int k) const {
-    return (i <= S.sinv[k]) ? S.R[k * Geo<NT>::LDR + i] : 0.0;
+  const Smem<NT, P, ELDS>& S;
+  __device__ double operator()(int, int, int, int i, int k) const {
+    return (i <= S.sinv[k]) ? S.R[k * Geo<NT, P>::LDR + i] : 0.0;
   }
 };
 
 // T <- D'^{-1} (R P^T) T  with D' = S.dnew
-template <int NT, bool ELDS>
-__device__ __forceinline__ void update_t(const Lane& L, const Smem<NT, ELDS>& S, RM<NT>& T) {
-  RM<NT> Tn;
-  gemm_rb<NT>(L, RPtOp<NT, ELDS>{S}, T, Tn);
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void update_t(const Lane& L, const Smem<NT, P, ELDS>& S, RM<NT, P>& T) {
+  RM<NT, P> Tn;
+  gemm_rb<NT, P>(L, RPtOp<NT, P, ELDS>{S}, T, Tn);
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c)
+  for (int c = 0; c < Geo<NT, P>::CT; ++c)
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -610,8 +663,8 @@ __device__ __forceinline__ void update_t(const Lane& L, const Smem<NT, ELDS>& S,
 }
 
 // det Q = (-1)^(number of nonzero reflectors among steps 0..n-1).  No barrier.
-template <int NT, bool ELDS>
-__device__ __forceinline__ double refl_sign(const Lane& L, const int n, const Smem<NT, ELDS>& S) {
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ double refl_sign(const Lane& L, const int n, const Smem<NT, P, ELDS>& S) {
   int cnt = 0;
   for (int i = L.l; i < n; i += 64) cnt += (S.tau[i] != 0.0);
   const unsigned long long b = __ballot(cnt & 1);
@@ -620,9 +673,9 @@ __device__ __forceinline__ double refl_sign(const Lane& L, const int n, const Sm
 
 // parity of the pivot permutation (inversions of S.perm) as +-1.
 // Ends with a barrier.
-template <int NT, bool ELDS>
-__device__ double perm_sign(const Lane& L, const int n, Smem<NT, ELDS>& S) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ double perm_sign(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
+  using G = Geo<NT, P>;
   int inv = 0;
   for (int i = L.t; i < n; i += G::THREADS) {
     const int pi = S.perm[i];
@@ -646,18 +699,18 @@ __device__ double perm_sign(const Lane& L, const int n, Smem<NT, ELDS>& S) {
 //   det(1 + U D T) = det U * prod(Dp) * det M.
 // U, T: register matrices (padding: identity); D: S.dcur.  Returns Z with
 // G[S.perm[s]][c] = Z[s][c] (caller writes it out), and log|det|, sign.
-template <int NT, bool ELDS>
-__device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, ELDS>& S, const RM<NT>& U,
-                             const RM<NT>& T, double sgn_u, RM<NT>& Z, double* logdet,
+template <int NT, int P, bool ELDS>
+__device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, const RM<NT, P>& U,
+                             const RM<NT, P>& T, double sgn_u, RM<NT, P>& Z, double* logdet,
                              double* sign) {
-  using G = Geo<NT>;
+  using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   // U^T via LDS
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    if (!tile_ok<NT>(L, c)) continue;
-    const int col = col_of<NT>(L, c);
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -665,10 +718,10 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, ELDS>& S, cons
   }
   // sum of log Dp over the live rows (wave 0), reduced through LDS
   __syncthreads();
-  RM<NT> M;
+  RM<NT, P> M;
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT>(L, c);
+    const int col = col_of<NT, P>(L, c);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -677,28 +730,28 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, ELDS>& S, cons
         const double dr = S.dcur[row];
         const double dp = dr > 1.0 ? dr : 1.0;
         const double dm = dr < 1.0 ? dr : 1.0;
-        const double ut = tile_ok<NT>(L, c) ? S.R[row * G::LDR + col] : 0.0;
+        const double ut = tile_ok<NT, P>(L, c) ? S.R[row * G::LDR + col] : 0.0;
         Z.v[c][ti][r] = ut / dp;
         M.v[c][ti][r] = ut / dp + dm * T.v[c][ti][r];
       }
   }
   double lsum = 0.0;
   for (int t = L.t; t < n; t += G::THREADS) lsum += log(fmax(S.dcur[t], 1.0));
-  cpqr<NT, ELDS>(L, n, M, S);  // begins with barriers before S.R is overwritten
+  cpqr<NT, P, ELDS>(L, n, M, S);  // begins with barriers before S.R is overwritten
   for (int t = L.t; t < n; t += G::THREADS) lsum += log(fabs(S.R[S.perm[t] * G::LDR + t]));
   int neg = 0;
   for (int t = L.t; t < n; t += G::THREADS) neg += (S.R[S.perm[t] * G::LDR + t] < 0.0);
   // wave sums
   for (int m = 32; m >= 1; m >>= 1) {
-    lsum += shx(lsum, m);
-    neg += shx(neg, m);
+    lsum += __shfl_xor(lsum, m);
+    neg += __shfl_xor(neg, m);
   }
   if (L.l == 0) {
     S.red[0][L.w] = lsum;
     S.ired[4 + L.w] = neg;
   }
-  const double sq = refl_sign<NT, ELDS>(L, n, S);
-  const double sp = perm_sign<NT, ELDS>(L, n, S);  // its barrier makes S.red visible
+  const double sq = refl_sign<NT, P, ELDS>(L, n, S);
+  const double sp = perm_sign<NT, P, ELDS>(L, n, S);  // its barrier makes S.red visible
   double ld = 0.0;
   int ng = 0;
   for (int q = 0; q < G::P; ++q) {
@@ -707,18 +760,18 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, ELDS>& S, cons
   }
   *logdet = ld;
   *sign = sgn_u * sq * sp * ((ng & 1) ? -1.0 : 1.0);
-  apply_qt<NT, ELDS>(L, n, S, Z);
-  back_subst<NT, ELDS>(L, n, S, Z);
+  apply_qt<NT, P, ELDS>(L, n, S, Z);
+  back_subst<NT, P, ELDS>(L, n, S, Z);
 }
 
 // write G[perm[s]][c] = Z[s][c] (leading n x n block) to global memory
-template <int NT, bool ELDS>
-__device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, const Smem<NT, ELDS>& S,
-                                                const RM<NT>& Z, double* dst) {
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, const Smem<NT, P, ELDS>& S,
+                                                const RM<NT, P>& Z, double* dst) {
 #pragma unroll
-  for (int c = 0; c < Geo<NT>::CT; ++c) {
-    const int col = col_of<NT>(L, c);
-    if (!tile_ok<NT>(L, c) || col >= n) continue;
+  for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+    if (!tile_ok<NT, P>(L, c) || col >= n) continue;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -732,10 +785,10 @@ __device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, cons
 // ---------------------------------------------------------------------------
 // slice exponentials v_q = exp(alpha f_q) for `cnt` slices into S.vbuf.
 // slice of buffer row s: q0 + dir*s.  Ends with a barrier.
-template <int NT, bool ELDS>
-__device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, int q0,
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int q0,
                                           int dir, int cnt) {
-  using G = Geo<NT>;
+  using G = Geo<NT, P>;
   __syncthreads();
   for (int idx = L.t; idx < cnt * G::NP; idx += G::THREADS) {
     const int s = idx / G::NP, row = idx - s * G::NP;
@@ -745,36 +798,37 @@ __device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, ELDS>& S, cons
   __syncthreads();
 }
 
-template <int NT>
-__device__ __forceinline__ void scale_rows(const Lane& L, RM<NT>& A, const double* v) {
+template <int NT, int P>
+__device__ __forceinline__ void scale_rows(const Lane& L, RM<NT, P>& A, const double* v) {
 #pragma unroll
   for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double s = v[row_of(L, ti, r)];
 #pragma unroll
-      for (int c = 0; c < Geo<NT>::CT; ++c) A.v[c][ti][r] *= s;
+      for (int c = 0; c < Geo<NT, P>::CT; ++c) A.v[c][ti][r] *= s;
     }
 }
 
-// left operand: the slice exponential (or its transpose), from LDS or HBM
-template <int NT, bool ELDS>
+// left operand: the slice exponential (or its transpose), either staged in
+// LDS or read from its pre-swizzled, zero-padded copy in HBM, whose block
+// ((ti*NT + tk)*4 + r) holds exactly the 64 A-operand values of one MFMA step
+// (one coalesced 512-byte load).
+template <int NT, int P, bool ELDS>
 struct EOp {
-  const double* sE;  // staged copy in LDS (ELDS)
-  const double* e;   // global n x n
-  int n;
-  bool trans;
-  __device__ double operator()(int i, int k) const {
-    if (ELDS) return sE[i * Geo<NT>::LDR + k];
-    if (i >= n || k >= n) return 0.0;
-    return trans ? e[k * n + i] : e[i * n + k];
+  const double* sE;   // staged copy in LDS (ELDS), [row][col]
+  const double* esw;  // swizzled copy in HBM
+  int lane;
+  __device__ double operator()(int ti, int tk, int r, int i, int k) const {
+    if (ELDS) return sE[i * Geo<NT, P>::LDR + k];
+    return esw[((ti * NT + tk) * 4 + r) * 64 + lane];
   }
 };
 
-template <int NT, bool ELDS>
-__device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, ELDS>& S, const double* e, int n,
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, P, ELDS>& S, const double* e, int n,
                                         bool trans) {
-  using G = Geo<NT>;
+  using G = Geo<NT, P>;
   if (!ELDS) return;
   for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
     const int i = idx / G::NP, k = idx - i * G::NP;
@@ -786,13 +840,13 @@ __device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, ELDS>& S, const 
 }
 
 // store one stage U | T | D | extra
-template <int NT, bool ELDS>
-__device__ __forceinline__ void store_stage(const Lane& L, const int n, const Smem<NT, ELDS>& S,
-                                            const RM<NT>& U, const RM<NT>& T, double sgn_u,
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void store_stage(const Lane& L, const int n, const Smem<NT, P, ELDS>& S,
+                                            const RM<NT, P>& U, const RM<NT, P>& T, double sgn_u,
                                             double* dst) {
-  store_rm<NT>(L, U, dst, n);
-  store_rm<NT>(L, T, dst + (size_t)n * n, n);
-  for (int t = L.t; t < n; t += Geo<NT>::THREADS) dst[2 * (size_t)n * n + t] = S.dnew[t];
+  store_rm<NT, P>(L, U, dst, n);
+  store_rm<NT, P>(L, T, dst + (size_t)n * n, n);
+  for (int t = L.t; t < n; t += Geo<NT, P>::THREADS) dst[2 * (size_t)n * n + t] = S.dnew[t];
   if (L.t == 0) dst[2 * (size_t)n * n + n] = sgn_u;
 }
 
@@ -804,23 +858,23 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
 // the same slice boundaries, so forward stage j and backward stage j meet at
 // tau = min(jk, m).  Per block:  W = X_block U,  W <- W D,  W P = Q R,
 // U <- Q,  D <- |diag R|,  T <- D^{-1} R P^T T.
-template <int NT, bool ELDS>
-__device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int flags) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags) {
+  using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const bool adj = (flags & SW_ADJ) != 0;
   const int64_t sd = stage_doubles(n);
-  stage_e<NT, ELDS>(L, S, I.expk, n, adj);
+  stage_e<NT, P, ELDS>(L, S, I.expk, n, adj);
   // W holds U between blocks and the block product inside a block
-  RM<NT> T, W;
-  set_identity<NT>(L, W);
-  set_identity<NT>(L, T);
+  RM<NT, P> T, W;
+  set_identity<NT, P>(L, W);
+  set_identity<NT, P>(L, T);
   double dcol[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
   double sgn_u = 1.0;
-  const EOp<NT, ELDS> eop{S.E, I.expk, n, adj};
+  const EOp<NT, P, ELDS> eop{S.E, adj ? I.eswt : I.esw, L.l};
 
   for (int s = 0; s < nb; ++s) {
     const int b = adj ? nb - 1 - s : s;
@@ -828,15 +882,15 @@ __device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
     const int cnt = q1 - q0 + 1;
     for (int c0 = 0; c0 < cnt; c0 += G::KB) {
       const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
-      if (adj) fill_vbuf<NT, ELDS>(L, S, I, q1 - c0, -1, cn);
-      else fill_vbuf<NT, ELDS>(L, S, I, q0 + c0, +1, cn);
+      if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
+      else fill_vbuf<NT, P, ELDS>(L, S, I, q0 + c0, +1, cn);
       for (int s2 = 0; s2 < cn; ++s2) {
         if (!adj) {
-          scale_rows<NT>(L, W, S.vbuf[s2]);
-          gemm_rb<NT>(L, eop, W, W);
+          scale_rows<NT, P>(L, W, S.vbuf[s2]);
+          gemm_rb<NT, P>(L, eop, W, W);
         } else {
-          gemm_rb<NT>(L, eop, W, W);
-          scale_rows<NT>(L, W, S.vbuf[s2]);
+          gemm_rb<NT, P>(L, eop, W, W);
+          scale_rows<NT, P>(L, W, S.vbuf[s2]);
         }
       }
     }
@@ -846,16 +900,16 @@ __device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
       for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
-    cpqr<NT, ELDS>(L, n, W, S);
-    diag_r<NT, ELDS>(L, n, S);
-    if (s == nb - 1) sgn_u = refl_sign<NT, ELDS>(L, n, S);
-    form_q<NT, ELDS>(L, n, S, W);
-    update_t<NT, ELDS>(L, S, T);
+    cpqr<NT, P, ELDS>(L, n, W, S);
+    diag_r<NT, P, ELDS>(L, n, S);
+    if (s == nb - 1) sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
+    form_q<NT, P, ELDS>(L, n, S, W);
+    update_t<NT, P, ELDS>(L, S, T);
 #pragma unroll
-    for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT>(L, c)];
+    for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT, P>(L, c)];
     if (flags & SW_STORE) {
       double* dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
-      store_stage<NT, ELDS>(L, n, S, W, T, 0.0, dst);
+      store_stage<NT, P, ELDS>(L, n, S, W, T, 0.0, dst);
     }
     __syncthreads();
   }
@@ -866,17 +920,17 @@ __device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
     if (!isfinite(d) || !(d > 0.0)) bad = 1;
   }
   if (flags & SW_FINAL) {
-    store_rm<NT>(L, W, I.u_out, n);
-    store_rm<NT>(L, T, I.t_out, n);
+    store_rm<NT, P>(L, W, I.u_out, n);
+    store_rm<NT, P>(L, T, I.t_out, n);
     for (int t = L.t; t < n; t += G::THREADS) I.d_out[t] = S.dnew[t];
   }
   if (flags & SW_GREENS) {
     for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
-    RM<NT> Z;
+    RM<NT, P> Z;
     double ld, sg;
-    inv_one_plus<NT, ELDS>(L, n, S, W, T, sgn_u, Z, &ld, &sg);
-    if (!all_finite<NT>(L, Z) || !isfinite(ld)) bad = 1;
-    if (I.g) store_perm_rows<NT, ELDS>(L, n, S, Z, I.g);
+    inv_one_plus<NT, P, ELDS>(L, n, S, W, T, sgn_u, Z, &ld, &sg);
+    if (!all_finite<NT, P>(L, Z) || !isfinite(ld)) bad = 1;
+    if (I.g) store_perm_rows<NT, P, ELDS>(L, n, S, Z, I.g);
     if (L.t == 0) {
       if (I.logdet) *I.logdet = ld;
       if (I.sign) *I.sign = sg;
@@ -885,11 +939,11 @@ __device__ void sweep_one(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
   if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 }
 
-template <int NT, bool ELDS>
-__global__ __launch_bounds__(Geo<NT>::THREADS) void k_sweep(const Inst* __restrict__ insts,
+template <int NT, int P, bool ELDS>
+__global__ __launch_bounds__(64 * P) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
                                                             int count, Queue* q) {
-  __shared__ Smem<NT, ELDS> S;
+  __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
   for (;;) {
     __syncthreads();
@@ -899,7 +953,7 @@ __global__ __launch_bounds__(Geo<NT>::THREADS) void k_sweep(const Inst* __restri
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, ELDS>(L, S, I, wi.flags);
+    sweep_one<NT, P, ELDS>(L, S, I, wi.flags);
   }
 }
 
@@ -914,10 +968,10 @@ __global__ __launch_bounds__(Geo<NT>::THREADS) void k_sweep(const Inst* __restri
 //   G(tau,0) = U2 D_Rp^{-1} Mid^{-1} D_Lp^{-1} T1.
 // Then, for requested l inside the block, G(tau_l, 0) = B_l ... G(tau_j, 0)
 // (Sec. 6, propagation form), never across more than k-1 slices.
-template <int NT, bool ELDS>
-__device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int j,
+template <int NT, int P, bool ELDS>
+__device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                            const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
-  using G = Geo<NT>;
+  using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const int64_t sd = stage_doubles(n);
@@ -930,28 +984,28 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, cons
   const double* T2 = A ? A + (size_t)n * n : nullptr;
   const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
 
-  RM<NT> B, P1, P2;
-  load_rm<NT>(L, B, U2, n, false);
-  gemm_rb<NT>(L,
-              [&](int i, int kk) -> double {
+  RM<NT, P> B, P1, P2;
+  load_rm<NT, P>(L, B, U2, n, false);
+  gemm_rb<NT, P>(L,
+              [&](int, int, int, int i, int kk) -> double {
                 if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
                 return U1 ? U1[kk * n + i] : (i == kk ? 1.0 : 0.0);
               },
               B, P1);
-  load_rm<NT>(L, B, T2, n, true);
-  gemm_rb<NT>(L,
-              [&](int i, int kk) -> double {
+  load_rm<NT, P>(L, B, T2, n, true);
+  gemm_rb<NT, P>(L,
+              [&](int, int, int, int i, int kk) -> double {
                 if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
                 return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
               },
               B, P2);
   // Mid and Y = D_Lp^{-1} T1
-  RM<NT> Y;
-  load_rm<NT>(L, Y, T1, n, false);
+  RM<NT, P> Y;
+  load_rm<NT, P>(L, Y, T1, n, false);
   double d2c[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT>(L, c);
+    const int col = col_of<NT, P>(L, c);
     d2c[c] = (D2 && col < n) ? D2[col] : 1.0;
   }
 #pragma unroll
@@ -972,13 +1026,13 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, cons
       }
     }
   __syncthreads();
-  cpqr<NT, ELDS>(L, n, P1, S);
-  apply_qt<NT, ELDS>(L, n, S, Y);
-  back_subst<NT, ELDS>(L, n, S, Y);
+  cpqr<NT, P, ELDS>(L, n, P1, S);
+  apply_qt<NT, P, ELDS>(L, n, S, Y);
+  back_subst<NT, P, ELDS>(L, n, S, Y);
   // G = U2 D_Rp^{-1} P Z :  A(i, s) = U2[i][perm s] / max(D2[perm s], 1)
-  RM<NT> Gm;
-  gemm_rb<NT>(L,
-              [&](int i, int s) -> double {
+  RM<NT, P> Gm;
+  gemm_rb<NT, P>(L,
+              [&](int, int, int, int i, int s) -> double {
                 if (i >= n || s >= n) return 0.0;
                 const int p = S.perm[s];
                 const double d2 = D2 ? D2[p] : 1.0;
@@ -986,27 +1040,27 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, cons
                 return u / (d2 > 1.0 ? d2 : 1.0);
               },
               Y, Gm);
-  if (!all_finite<NT>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 
   // outputs: l_list[ilo..ihi), ascending, each in [tau_j, tau_j + k)
   const int tj = j * k < m ? j * k : m;
   int lc = tj;
-  const EOp<NT, false> eop{nullptr, I.expk, n, false};
+  const EOp<NT, P, false> eop{nullptr, I.esw, L.l};
   for (int idx = ilo; idx < ihi; ++idx) {
     const int l = l_list[idx];
     const int steps = l - lc;
     for (int c0 = 0; c0 < steps; c0 += G::KB) {
       const int cn = (steps - c0) < G::KB ? (steps - c0) : G::KB;
-      fill_vbuf<NT, ELDS>(L, S, I, lc + c0 + 1, +1, cn);
+      fill_vbuf<NT, P, ELDS>(L, S, I, lc + c0 + 1, +1, cn);
       for (int s2 = 0; s2 < cn; ++s2) {
-        RM<NT> Wn;
-        scale_rows<NT>(L, Gm, S.vbuf[s2]);
-        gemm_rb<NT>(L, eop, Gm, Wn);
+        RM<NT, P> Wn;
+        scale_rows<NT, P>(L, Gm, S.vbuf[s2]);
+        gemm_rb<NT, P>(L, eop, Gm, Wn);
         Gm = Wn;
       }
     }
     lc = l;
-    store_rm<NT>(L, Gm, I.gt + (size_t)idx * n * n, n);
+    store_rm<NT, P>(L, Gm, I.gt + (size_t)idx * n * n, n);
   }
   __syncthreads();
 }
@@ -1017,9 +1071,9 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, cons
 // with udt(D1 (T1 T2^T) D2) = u d t, U = U1 u, T = t U2^T and Loh's
 // equal-time inversion; then G_{l+1} = B_l G_l B_l^{-1} and
 //   grad[l-1][i] = alpha (1 - G_l)_ii.
-template <int NT, bool ELDS>
-__device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const int j) {
-  using G = Geo<NT>;
+template <int NT, int P, bool ELDS>
+__device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+  using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const int64_t sd = stage_doubles(n);
@@ -1032,17 +1086,17 @@ __device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
   const double* T2 = A ? A + (size_t)n * n : nullptr;
   const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
 
-  RM<NT> B, Mm;
-  load_rm<NT>(L, B, T2, n, true);
-  gemm_rb<NT>(L,
-              [&](int i, int kk) -> double {
+  RM<NT, P> B, Mm;
+  load_rm<NT, P>(L, B, T2, n, true);
+  gemm_rb<NT, P>(L,
+              [&](int, int, int, int i, int kk) -> double {
                 if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
                 return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
               },
               B, Mm);
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT>(L, c);
+    const int col = col_of<NT, P>(L, c);
     const double d2 = (D2 && col < n) ? D2[col] : 1.0;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
@@ -1054,34 +1108,34 @@ __device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
       }
   }
   __syncthreads();
-  cpqr<NT, ELDS>(L, n, Mm, S);
-  diag_r<NT, ELDS>(L, n, S);
-  RM<NT> u, Tm, Um;
-  form_q<NT, ELDS>(L, n, S, u);
-  load_rm<NT>(L, B, U2, n, true);  // U2^T
-  gemm_rb<NT>(L, RPtOp<NT, ELDS>{S}, B, Tm);
+  cpqr<NT, P, ELDS>(L, n, Mm, S);
+  diag_r<NT, P, ELDS>(L, n, S);
+  RM<NT, P> u, Tm, Um;
+  form_q<NT, P, ELDS>(L, n, S, u);
+  load_rm<NT, P>(L, B, U2, n, true);  // U2^T
+  gemm_rb<NT, P>(L, RPtOp<NT, P, ELDS>{S}, B, Tm);
 #pragma unroll
   for (int c = 0; c < CT; ++c)
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) Tm.v[c][ti][r] /= S.dnew[row_of(L, ti, r)];
-  gemm_rb<NT>(L,
-              [&](int i, int kk) -> double {
+  gemm_rb<NT, P>(L,
+              [&](int, int, int, int i, int kk) -> double {
                 if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
                 return U1 ? U1[i * n + kk] : (i == kk ? 1.0 : 0.0);
               },
               u, Um);
   for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
-  RM<NT> Z;
+  RM<NT, P> Z;
   double ld, sg;
-  inv_one_plus<NT, ELDS>(L, n, S, Um, Tm, 1.0, Z, &ld, &sg);
+  inv_one_plus<NT, P, ELDS>(L, n, S, Um, Tm, 1.0, Z, &ld, &sg);
   // G_l into LDS, row-major [row][col]
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    if (!tile_ok<NT>(L, c)) continue;
-    const int col = col_of<NT>(L, c);
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -1101,23 +1155,23 @@ __device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
   }
   for (int l = l0; l < l1; ++l) {
     // G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar
-    RM<NT> Bi, Yr, Gn;
+    RM<NT, P> Bi, Yr, Gn;
     const double* fl = I.field + (size_t)(l - 1) * n;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      const int col = col_of<NT>(L, c);
+      const int col = col_of<NT, P>(L, c);
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = row_of(L, ti, r);
           double x = 0.0;
-          if (row < n && col < n && tile_ok<NT>(L, c))
+          if (row < n && col < n && tile_ok<NT, P>(L, c))
             x = I.expk_inv[row * n + col] * exp(-I.alpha * fl[row]);
           Bi.v[c][ti][r] = x;
         }
     }
-    gemm_rb<NT>(L, [&](int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -1127,16 +1181,12 @@ __device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
 #pragma unroll
         for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
       }
-    gemm_rb<NT>(L,
-                [&](int i, int kk) -> double {
-                  return (i < n && kk < n) ? I.expk[i * n + kk] : 0.0;
-                },
-                Yr, Gn);
+    gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gn);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      if (!tile_ok<NT>(L, c)) continue;
-      const int col = col_of<NT>(L, c);
+      if (!tile_ok<NT, P>(L, c)) continue;
+      const int col = col_of<NT, P>(L, c);
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -1153,12 +1203,12 @@ __device__ void pair_grad(const Lane& L, Smem<NT, ELDS>& S, const Inst& I, const
   __syncthreads();
 }
 
-template <int NT, bool ELDS>
-__global__ __launch_bounds__(Geo<NT>::THREADS) void k_pair(const Inst* __restrict__ insts,
+template <int NT, int P, bool ELDS>
+__global__ __launch_bounds__(64 * P) void k_pair(const Inst* __restrict__ insts,
                                                            const PairItem* __restrict__ items,
                                                            int count, const int32_t* __restrict__ l_list,
                                                            Queue* q, int mode) {
-  __shared__ Smem<NT, ELDS> S;
+  __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
   for (;;) {
     __syncthreads();
@@ -1168,32 +1218,32 @@ __global__ __launch_bounds__(Geo<NT>::THREADS) void k_pair(const Inst* __restric
     if (it >= count) break;
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
-    if (mode == PAIR_TDISP) pair_tdisp<NT, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
-    else pair_grad<NT, ELDS>(L, S, I, wi.j);
+    if (mode == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else pair_grad<NT, P, ELDS>(L, S, I, wi.j);
   }
 }
 
 // ---------------------------------------------------------------------------
 // plain UDT of independent matrices (Sec. 4.2.2): W P = Q R,
 // U = Q, D = |diag R|, T = D^{-1} R P^T
-template <int NT>
-__global__ __launch_bounds__(Geo<NT>::THREADS) void k_udt(int n, int count, const double* __restrict__ w,
+template <int NT, int P>
+__global__ __launch_bounds__(64 * P) void k_udt(int n, int count, const double* __restrict__ w,
                                                           double* u, double* d, double* t) {
-  using G = Geo<NT>;
-  __shared__ Smem<NT, false> S;
+  using G = Geo<NT, P>;
+  __shared__ Smem<NT, P, false> S;
   const Lane L = lane_id();
   for (int b = blockIdx.x; b < count; b += gridDim.x) {
     const size_t off = (size_t)b * n * n;
-    RM<NT> W, Q, T;
-    load_rm<NT>(L, W, w + off, n, false);
+    RM<NT, P> W, Q, T;
+    load_rm<NT, P>(L, W, w + off, n, false);
     __syncthreads();
-    cpqr<NT, false>(L, n, W, S);
-    diag_r<NT, false>(L, n, S);
-    form_q<NT, false>(L, n, S, Q);
-    store_rm<NT>(L, Q, u + off, n);
-    set_identity<NT>(L, T);
-    update_t<NT, false>(L, S, T);
-    store_rm<NT>(L, T, t + off, n);
+    cpqr<NT, P, false>(L, n, W, S);
+    diag_r<NT, P, false>(L, n, S);
+    form_q<NT, P, false>(L, n, S, Q);
+    store_rm<NT, P>(L, Q, u + off, n);
+    set_identity<NT, P>(L, T);
+    update_t<NT, P, false>(L, S, T);
+    store_rm<NT, P>(L, T, t + off, n);
     for (int i = L.t; i < n; i += G::THREADS) d[(size_t)b * n + i] = S.dnew[i];
     __syncthreads();
   }
@@ -1202,48 +1252,55 @@ __global__ __launch_bounds__(Geo<NT>::THREADS) void k_udt(int n, int count, cons
 // ---------------------------------------------------------------------------
 // per-tile-count launchers (instantiated once per NT in sdq_nt.hip)
 
+// waves per chain: one per 16-column tile, at most four
+constexpr int waves_for(int nt) { return nt < 4 ? nt : 4; }
+// LDS-staged slice exponential: where it still leaves room for useful occupancy
+constexpr bool lds_variant(int nt) { return nt >= 3 && nt <= 5; }
+
 template <int NT>
 struct Launch {
+  static constexpr int P = waves_for(NT);
+  static constexpr bool kLds = lds_variant(NT);
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {
-    constexpr bool kLds = NT >= 3 && NT <= 5;
     if (variant == 1 && kLds)
-      hipLaunchKernelGGL((k_sweep<NT, kLds>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
-                         count, q);
+      hipLaunchKernelGGL((k_sweep<NT, P, kLds>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
+                         items, count, q);
     else
-      hipLaunchKernelGGL((k_sweep<NT, false>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
-                         count, q);
+      hipLaunchKernelGGL((k_sweep<NT, P, false>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
+                         items, count, q);
     return hipGetLastError();
   }
   static hipError_t pair(int mode, const Inst* inst, const PairItem* items, int count,
                          const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair<NT, false>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, inst, items,
-                       count, l_list, q, mode);
+    hipLaunchKernelGGL((k_pair<NT, P, false>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
+                       items, count, l_list, q, mode);
     return hipGetLastError();
   }
   static hipError_t udt(int n, int count, const double* w, double* u, double* d, double* t,
                         hipStream_t s) {
-    const int grid = count < 4096 ? count : 4096;
-    hipLaunchKernelGGL((k_udt<NT>), dim3(grid), dim3(Geo<NT>::THREADS), 0, s, n, count, w, u, d, t);
+    const int grid = count < 8192 ? count : 8192;
+    hipLaunchKernelGGL((k_udt<NT, P>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, n, count, w, u,
+                       d, t);
     return hipGetLastError();
   }
   template <class KF>
   static hipError_t info_of(KF kern, int lds, KernelInfo* out) {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, Geo<NT>::THREADS, 0);
-    out->threads = Geo<NT>::THREADS;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, Geo<NT, P>::THREADS, 0);
+    out->threads = Geo<NT, P>::THREADS;
     out->lds_bytes = lds;
     out->blocks_per_cu = nb;
     return e;
   }
   static hipError_t info(int kind, int variant, KernelInfo* out) {
-    constexpr bool kLds = NT >= 3 && NT <= 5;
     if (kind == KK_SWEEP) {
-      if (variant == 1 && kLds) return info_of(k_sweep<NT, kLds>, (int)sizeof(Smem<NT, kLds>), out);
-      return info_of(k_sweep<NT, false>, (int)sizeof(Smem<NT, false>), out);
+      if (variant == 1 && kLds)
+        return info_of(k_sweep<NT, P, kLds>, (int)sizeof(Smem<NT, P, kLds>), out);
+      return info_of(k_sweep<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);
     }
-    if (kind == KK_PAIR) return info_of(k_pair<NT, false>, (int)sizeof(Smem<NT, false>), out);
-    return info_of(k_udt<NT>, (int)sizeof(Smem<NT, false>), out);
+    if (kind == KK_PAIR) return info_of(k_pair<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);
+    return info_of(k_udt<NT, P>, (int)sizeof(Smem<NT, P, false>), out);
   }
 };
 

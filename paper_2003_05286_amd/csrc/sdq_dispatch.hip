@@ -70,6 +70,24 @@ hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_swizzle(const double* e, int n, int nt, int trans, double* out) {
+  const int np = 16 * nt;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= np * np) return;
+  const int l = idx & 63, b = idx >> 6;
+  const int r = b & 3, tk = (b >> 2) % nt, ti = (b >> 2) / nt;
+  const int i = 16 * ti + (l & 15), k = 16 * tk + (l >> 4) + 4 * r;
+  double x = 0.0;
+  if (i < n && k < n) x = trans ? e[(size_t)k * n + i] : e[(size_t)i * n + k];
+  out[idx] = x;
+}
+
+hipError_t launch_swizzle(const double* e, int n, int trans, double* out, hipStream_t s) {
+  const int nt = (n + 15) / 16, np = 16 * nt;
+  hipLaunchKernelGGL(k_swizzle, dim3((np * np + 255) / 256), dim3(256), 0, s, e, n, nt, trans, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset, dim3((nq + 63) / 64), dim3(64), 0, s, q, nq);

@@ -37,6 +37,8 @@ struct Inst {
   double* u_out;           // final U / D / T of the sweep, or null
   double* d_out;
   double* t_out;
+  const double* esw;       // expk, zero padded to 16*ceil(n/16) and swizzled
+  const double* eswt;      // expk^T, same layout (see launch_swizzle)
 };
 
 enum SweepFlags : int32_t {
@@ -80,6 +82,11 @@ struct KernelInfo {
 
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out);
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s);
+// Copy the n x n row-major matrix e (or its transpose) into the MFMA
+// A-operand order used by the kernels: for NT = ceil(n/16), block
+// b = (ti*NT + tk)*4 + r holds at position l the entry
+// (16 ti + l%16, 16 tk + l/16 + 4 r) of the zero-padded matrix.
+hipError_t launch_swizzle(const double* e, int n, int trans, double* out, hipStream_t s);
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
                         Queue* q, int grid, hipStream_t s);
 hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -69,7 +70,7 @@ struct sdq_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int num_cu = 256;
-  DevBuf d_upload, d_ck;
+  DevBuf d_upload, d_ck, d_swz;
   void* h_stage = nullptr;
   size_t h_cap = 0;
   hipEvent_t stage_ev = nullptr;
@@ -259,9 +260,44 @@ sdq_status timed(sdq_ctx* ctx, const char* name, F launch) {
   return SDQ_OK;
 }
 
+// Swizzled, zero-padded copies of every distinct slice exponential of the
+// plan (and of its transpose), in the MFMA operand order the kernels read.
+struct SwzJob {
+  const double* e;
+  int n;
+  int64_t off;
+};
+
+sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
+  std::map<std::pair<const double*, int>, int64_t> seen;
+  int64_t tot = 0;
+  for (const Inst& I : P.inst) {
+    auto key = std::make_pair(I.expk, I.n);
+    if (seen.count(key)) continue;
+    const int64_t np = 16LL * nt_of(I.n);
+    seen[key] = tot;
+    jobs.push_back(SwzJob{I.expk, I.n, tot});
+    tot += 2 * np * np;
+  }
+  HIP_TRY(grow(ctx->d_swz, (size_t)std::max<int64_t>(tot, 1) * sizeof(double)), "hipMalloc(swizzle)");
+  double* base = (double*)ctx->d_swz.p;
+  for (Inst& I : P.inst) {
+    const int64_t off = seen[std::make_pair(I.expk, I.n)];
+    const int64_t np = 16LL * nt_of(I.n);
+    I.esw = base + off;
+    I.eswt = base + off + np * np;
+  }
+  return SDQ_OK;
+}
+
 // Upload the plan (instances, items, l_list, zeroed queues) in one copy and
 // run it: all sweeps, then all pair items.
 sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
+  std::vector<SwzJob> swz;
+  {
+    sdq_status st = prepare_swizzle(ctx, P, swz);
+    if (st) return st;
+  }
   const size_t n_inst = P.inst.size();
   const int nq = (int)(P.sweep_ranges.size() + P.pair_ranges.size());
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -296,6 +332,12 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   ctx->stage_pending = true;
   if (status && count > 0) {
     HIP_TRY(sdq::launch_fill_i32(status, count, 0, ctx->stream), "fill(status)");
+  }
+  for (const SwzJob& j : swz) {
+    const int64_t np = 16LL * nt_of(j.n);
+    double* out = (double*)ctx->d_swz.p + j.off;
+    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 0, out, ctx->stream), "swizzle");
+    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 1, out + np * np, ctx->stream), "swizzle");
   }
   const Inst* d_inst = (const Inst*)(d + o_inst);
   const SweepItem* d_sw = (const SweepItem*)(d + o_sw);
@@ -368,7 +410,16 @@ sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cu = prop.multiProcessorCount;
-  for (int nt = 0; nt <= sdq::kMaxNT; ++nt) ctx->tune[nt] = Tune{};
+  for (int nt = 0; nt <= sdq::kMaxNT; ++nt) {
+    ctx->tune[nt] = Tune{};
+    // default: slice exponential staged in LDS where that variant exists
+    ctx->tune[nt].variant = (nt >= 3 && nt <= 5) ? 1 : 0;
+  }
+  // debug overrides (environment): SDQ_SWEEP_VARIANT, SDQ_BLOCKS_PER_CU
+  if (const char* v = getenv("SDQ_SWEEP_VARIANT"))
+    for (int nt = 0; nt <= sdq::kMaxNT; ++nt) ctx->tune[nt].variant = atoi(v);
+  if (const char* v = getenv("SDQ_BLOCKS_PER_CU"))
+    for (int nt = 0; nt <= sdq::kMaxNT; ++nt) ctx->tune[nt].blocks_per_cu = atoi(v);
   *out = ctx;
   return SDQ_OK;
 }
@@ -383,6 +434,7 @@ void sdq_destroy(sdq_ctx* ctx) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (ctx->d_upload.p) (void)hipFree(ctx->d_upload.p);
   if (ctx->d_ck.p) (void)hipFree(ctx->d_ck.p);
+  if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
