@@ -957,6 +957,40 @@ __global__ __launch_bounds__(64 * P) void k_sweep(const Inst* __restrict__ insts
   }
 }
 
+// stage the n x n row-major global matrix src (identity if null) into S.E,
+// [row][col], zero padded; all threads, no barrier
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void stage_mat(const Lane& L, Smem<NT, P, ELDS>& S, const double* src,
+                                          int n) {
+  using G = Geo<NT, P>;
+  if constexpr (ELDS) {
+    for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
+      const int i = idx / G::NP, k = idx - i * G::NP;
+      double x = 0.0;
+      if (i < n && k < n) x = src ? src[i * n + k] : (i == k ? 1.0 : 0.0);
+      S.E[i * G::LDR + k] = x;
+    }
+  }
+}
+
+// B operand from the staged matrix: B[row][col] = S.E[row][col] or its transpose
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void load_rm_staged(const Lane& L, const Smem<NT, P, ELDS>& S,
+                                               RM<NT, P>& B, bool trans) {
+  using G = Geo<NT, P>;
+#pragma unroll
+  for (int c = 0; c < G::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        B.v[c][ti][r] = tile_ok<NT, P>(L, c) ? (trans ? S.E[col * G::LDR + row] : S.E[row * G::LDR + col]) : 0.0;
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Time-displaced G(tau_j, 0) from forward stage F[j] = U1 D1 T1 (of
 // B(tau_j, 0)) and backward stage A[j] = U2 D2 T2 (of B(beta, tau_j)^T),
@@ -985,20 +1019,39 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
   const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
 
   RM<NT, P> B, P1, P2;
-  load_rm<NT, P>(L, B, U2, n, false);
-  gemm_rb<NT, P>(L,
-              [&](int, int, int, int i, int kk) -> double {
-                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
-                return U1 ? U1[kk * n + i] : (i == kk ? 1.0 : 0.0);
-              },
-              B, P1);
-  load_rm<NT, P>(L, B, T2, n, true);
-  gemm_rb<NT, P>(L,
-              [&](int, int, int, int i, int kk) -> double {
-                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
-                return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
-              },
-              B, P2);
+  if constexpr (ELDS) {
+    // operands staged through LDS with coalesced loads
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, T2, n);
+    __syncthreads();
+    load_rm_staged<NT, P, ELDS>(L, S, B, true);  // T2^T
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, T1, n);
+    __syncthreads();
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, B,
+                   P2);
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, U1, n);
+    load_rm<NT, P>(L, B, U2, n, false);
+    __syncthreads();
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[kk * G::LDR + i]; }, B,
+                   P1);
+  } else {
+    load_rm<NT, P>(L, B, U2, n, false);
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int kk) -> double {
+                     if (i >= n || kk >= n) return 0.0;
+                     return U1 ? U1[kk * n + i] : (i == kk ? 1.0 : 0.0);
+                   },
+                   B, P1);
+    load_rm<NT, P>(L, B, T2, n, true);
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int kk) -> double {
+                     if (i >= n || kk >= n) return 0.0;
+                     return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                   },
+                   B, P2);
+  }
   // Mid and Y = D_Lp^{-1} T1
   RM<NT, P> Y;
   load_rm<NT, P>(L, Y, T1, n, false);
@@ -1031,15 +1084,34 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
   back_subst<NT, P, ELDS>(L, n, S, Y);
   // G = U2 D_Rp^{-1} P Z :  A(i, s) = U2[i][perm s] / max(D2[perm s], 1)
   RM<NT, P> Gm;
-  gemm_rb<NT, P>(L,
-              [&](int, int, int, int i, int s) -> double {
-                if (i >= n || s >= n) return 0.0;
-                const int p = S.perm[s];
-                const double d2 = D2 ? D2[p] : 1.0;
-                const double u = U2 ? U2[i * n + p] : (i == p ? 1.0 : 0.0);
-                return u / (d2 > 1.0 ? d2 : 1.0);
-              },
-              Y, Gm);
+  if constexpr (ELDS) {
+    // stage U2 D_Rp^{-1} (columns scaled), then gather its columns by perm
+    for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
+      const int i = idx / G::NP, kk = idx - i * G::NP;
+      double x = 0.0;
+      if (i < n && kk < n) {
+        const double d2 = D2 ? D2[kk] : 1.0;
+        x = (U2 ? U2[i * n + kk] : (i == kk ? 1.0 : 0.0)) / (d2 > 1.0 ? d2 : 1.0);
+      }
+      S.E[i * G::LDR + kk] = x;
+    }
+    __syncthreads();
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int s) -> double {
+                     return s < n ? S.E[i * G::LDR + S.perm[s]] : 0.0;
+                   },
+                   Y, Gm);
+  } else {
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int s) -> double {
+                     if (i >= n || s >= n) return 0.0;
+                     const int p = S.perm[s];
+                     const double d2 = D2 ? D2[p] : 1.0;
+                     const double u = U2 ? U2[i * n + p] : (i == p ? 1.0 : 0.0);
+                     return u / (d2 > 1.0 ? d2 : 1.0);
+                   },
+                   Y, Gm);
+  }
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 
   // outputs: l_list[ilo..ihi), ascending, each in [tau_j, tau_j + k)
@@ -1087,13 +1159,25 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
 
   RM<NT, P> B, Mm;
-  load_rm<NT, P>(L, B, T2, n, true);
-  gemm_rb<NT, P>(L,
-              [&](int, int, int, int i, int kk) -> double {
-                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
-                return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
-              },
-              B, Mm);
+  if constexpr (ELDS) {
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, T2, n);
+    __syncthreads();
+    load_rm_staged<NT, P, ELDS>(L, S, B, true);  // T2^T
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, T1, n);
+    __syncthreads();
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, B,
+                   Mm);
+  } else {
+    load_rm<NT, P>(L, B, T2, n, true);
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int kk) -> double {
+                     if (i >= n || kk >= n) return 0.0;
+                     return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                   },
+                   B, Mm);
+  }
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     const int col = col_of<NT, P>(L, c);
@@ -1112,7 +1196,17 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   diag_r<NT, P, ELDS>(L, n, S);
   RM<NT, P> u, Tm, Um;
   form_q<NT, P, ELDS>(L, n, S, u);
-  load_rm<NT, P>(L, B, U2, n, true);  // U2^T
+  if constexpr (ELDS) {
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, U2, n);
+    __syncthreads();
+    load_rm_staged<NT, P, ELDS>(L, S, B, true);  // U2^T
+    __syncthreads();
+    stage_mat<NT, P, ELDS>(L, S, U1, n);
+    __syncthreads();
+  } else {
+    load_rm<NT, P>(L, B, U2, n, true);  // U2^T
+  }
   gemm_rb<NT, P>(L, RPtOp<NT, P, ELDS>{S}, B, Tm);
 #pragma unroll
   for (int c = 0; c < CT; ++c)
@@ -1120,12 +1214,17 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) Tm.v[c][ti][r] /= S.dnew[row_of(L, ti, r)];
-  gemm_rb<NT, P>(L,
-              [&](int, int, int, int i, int kk) -> double {
-                if (i >= n || kk >= n) return (i == kk) ? 1.0 : 0.0;
-                return U1 ? U1[i * n + kk] : (i == kk ? 1.0 : 0.0);
-              },
-              u, Um);
+  if constexpr (ELDS) {
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, u,
+                   Um);
+  } else {
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int kk) -> double {
+                     if (i >= n || kk >= n) return 0.0;
+                     return U1 ? U1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                   },
+                   u, Um);
+  }
   for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
   RM<NT, P> Z;
   double ld, sg;
@@ -1261,6 +1360,7 @@ template <int NT>
 struct Launch {
   static constexpr int P = waves_for(NT);
   static constexpr bool kLds = lds_variant(NT);
+  static constexpr bool kPairLds = NT <= 5;  // operand staging buffer fits beside the factor store
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {
     if (variant == 1 && kLds)
@@ -1273,7 +1373,7 @@ struct Launch {
   }
   static hipError_t pair(int mode, const Inst* inst, const PairItem* items, int count,
                          const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair<NT, P, false>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
+    hipLaunchKernelGGL((k_pair<NT, P, kPairLds>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
                        items, count, l_list, q, mode);
     return hipGetLastError();
   }
@@ -1299,7 +1399,8 @@ struct Launch {
         return info_of(k_sweep<NT, P, kLds>, (int)sizeof(Smem<NT, P, kLds>), out);
       return info_of(k_sweep<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);
     }
-    if (kind == KK_PAIR) return info_of(k_pair<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);
+    if (kind == KK_PAIR)
+      return info_of(k_pair<NT, P, kPairLds>, (int)sizeof(Smem<NT, P, kPairLds>), out);
     return info_of(k_udt<NT, P>, (int)sizeof(Smem<NT, P, false>), out);
   }
 };
