@@ -55,6 +55,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=8, help="chains in the CPU sample")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 512 chains (tests only)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="time the batched step only (no equal-time / per-chain extras); for profiler runs")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -69,6 +73,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written",
+              file=sys.stderr, flush=True)
+        del src, dst
     W = wl.workload("hubbard_L8_b40_batch512", scale=args.scale)
     insts = W.instances
     l_list = W.l_list
@@ -138,25 +151,27 @@ def main():
     achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
 
-    # equal-time only, same batch (one forward sweep per chain)
-    gs2, ld2, sg2, st2 = ctx.greens(chains)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
+    eq_rate = per_inst_rate = None
+    if not args.profile_only:
+        # equal-time only, same batch (one forward sweep per chain)
         ctx.greens(chains)
-    torch.cuda.synchronize()
-    eq_rate = cnt * args.steps / (time.perf_counter() - t2)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.greens(chains)
+        torch.cuda.synchronize()
+        eq_rate = cnt * args.steps / (time.perf_counter() - t2)
 
-    # plain per-instance form on the same GPU: one chain per call, looped
-    sub = chains[: min(32, cnt)]
-    for c in sub[:2]:
-        ctx.greens_tdisp([c], l_list)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for c in sub:
-        ctx.greens_tdisp([c], l_list)
-    torch.cuda.synchronize()
-    per_inst_rate = len(sub) / (time.perf_counter() - t3)
+        # plain per-instance form on the same GPU: one chain per call, looped
+        sub = chains[: min(32, cnt)]
+        for c in sub[:2]:
+            ctx.greens_tdisp([c], l_list)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for c in sub:
+            ctx.greens_tdisp([c], l_list)
+        torch.cuda.synchronize()
+        per_inst_rate = len(sub) / (time.perf_counter() - t3)
 
     out = {
         "metric": "stabilized Green's functions/sec (FP64, L=8, beta=40, batched)",
