@@ -190,7 +190,7 @@ def main():
                    "dtau": 0.1, "U": 4.0, "l_list": "10,20,...,400", "scheme": "loh"},
         "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA, "traffic": None,
+                     "frac": achieved / PEAK_FP64_MFMA, "traffic": measured_traffic(),
                      "flops_per_launch": f_sweep, "launch_ms": sweep_avg_s * 1e3},
         "pair_kernel": {"launch_ms": pair_avg_s * 1e3, "flops_per_launch": f_pair,
                         "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
@@ -204,6 +204,24 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2003_05286_amd", "csrc", "sdq_device.hpp")
+    prof = os.path.join(ROOT, "profiles", "hbm_counters_hubbard_L8_b40_batch512.md")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        text = open(prof).read()
+    except OSError:
+        return None
+    if h not in text:
+        return None
+    m = re.search(r"bench traffic line: sweep ([0-9.eE+-]+)", text)
+    return float(m.group(1)) if m else None
 
 
 def cpu_baseline(insts, l_list, nchains):
