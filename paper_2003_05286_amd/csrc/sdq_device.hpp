@@ -46,6 +46,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // geometry
 
+// workgroups per CU the register budget of a kernel targets: two for the
+// sweep and the equal-time inversion at n <= 64 (they fit 256 registers per
+// lane with little or no spilling), one otherwise
+constexpr int minb_for(int nt) { return nt <= 4 ? 2 : 1; }
+constexpr int minb_pair(int nt, int mode) { return mode == 2 ? minb_for(nt) : 1; }
+
 template <int NT, int P_>
 struct Geo {
   static constexpr int NP = 16 * NT;             // padded dimension
@@ -53,14 +59,14 @@ struct Geo {
   static constexpr int CT = (NT + P - 1) / P;    // column tiles per wave (max)
   static constexpr int LDR = NP + 1;             // LDS column stride (odd: no bank conflicts)
   static constexpr int THREADS = 64 * P;
-  static constexpr int KB = (P == 1 || NT > 6) ? 8 : 16;  // slices of exp(alpha f) staged at once
+  static constexpr int KB = 8;                   // slices of exp(alpha f) staged at once
 };
 
 template <int NT, int P, bool ELDS>
 struct Smem {
   using G = Geo<NT, P>;
   double R[G::NP * G::LDR];                  // factor store, [col][row]
-  double E[ELDS ? G::NP * G::LDR : 1];       // staged slice exponential, [row][col]
+  double E[ELDS ? G::NP * G::LDR : 1];       // staged operand (sweep: swizzled E; pair: [row][col])
   double cand[2][G::P][G::NP];               // pivot candidate columns
   double vbuf[G::KB][G::NP];                 // exp(alpha f) of the slices in flight
   double tau[G::NP];
@@ -810,32 +816,26 @@ __device__ __forceinline__ void scale_rows(const Lane& L, RM<NT, P>& A, const do
     }
 }
 
-// left operand: the slice exponential (or its transpose), either staged in
-// LDS or read from its pre-swizzled, zero-padded copy in HBM, whose block
-// ((ti*NT + tk)*4 + r) holds exactly the 64 A-operand values of one MFMA step
-// (one coalesced 512-byte load).
+// left operand: the slice exponential (or its transpose) in its swizzled,
+// zero-padded order, whose block ((ti*NT + tk)*4 + r) holds exactly the 64
+// A-operand values of one MFMA step: read from the LDS copy (ELDS; one base
+// address, immediate offsets) or from HBM (one coalesced 512-byte load).
 template <int NT, int P, bool ELDS>
 struct EOp {
-  const double* sE;   // staged copy in LDS (ELDS), [row][col]
+  const double* sE;   // staged swizzled copy in LDS (ELDS)
   const double* esw;  // swizzled copy in HBM
   int lane;
-  __device__ double operator()(int ti, int tk, int r, int i, int k) const {
-    if (ELDS) return sE[i * Geo<NT, P>::LDR + k];
+  __device__ double operator()(int ti, int tk, int r, int, int) const {
+    if (ELDS) return sE[((ti * NT + tk) * 4 + r) * 64 + lane];
     return esw[((ti * NT + tk) * 4 + r) * 64 + lane];
   }
 };
 
 template <int NT, int P, bool ELDS>
-__device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, P, ELDS>& S, const double* e, int n,
-                                        bool trans) {
+__device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, P, ELDS>& S, const double* esw) {
   using G = Geo<NT, P>;
   if (!ELDS) return;
-  for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
-    const int i = idx / G::NP, k = idx - i * G::NP;
-    double x = 0.0;
-    if (i < n && k < n) x = trans ? e[k * n + i] : e[i * n + k];
-    S.E[i * G::LDR + k] = x;
-  }
+  for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) S.E[idx] = esw[idx];
   // visibility: the next fill_vbuf begins with a barrier
 }
 
@@ -865,7 +865,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const bool adj = (flags & SW_ADJ) != 0;
   const int64_t sd = stage_doubles(n);
-  stage_e<NT, P, ELDS>(L, S, I.expk, n, adj);
+  stage_e<NT, P, ELDS>(L, S, adj ? I.eswt : I.esw);
   // W holds U between blocks and the block product inside a block
   RM<NT, P> T, W;
   set_identity<NT, P>(L, W);
@@ -873,7 +873,6 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   double dcol[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
-  double sgn_u = 1.0;
   const EOp<NT, P, ELDS> eop{S.E, adj ? I.eswt : I.esw, L.l};
 
   for (int s = 0; s < nb; ++s) {
@@ -902,15 +901,15 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
         for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
     cpqr<NT, P, ELDS>(L, n, W, S);
     diag_r<NT, P, ELDS>(L, n, S);
-    if (s == nb - 1) sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
+    const double sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
     form_q<NT, P, ELDS>(L, n, S, W);
     update_t<NT, P, ELDS>(L, S, T);
 #pragma unroll
     for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT, P>(L, c)];
-    if (flags & SW_STORE) {
-      double* dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
-      store_stage<NT, P, ELDS>(L, n, S, W, T, 0.0, dst);
-    }
+    double* dst = nullptr;
+    if (flags & SW_STORE) dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
+    else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
+    if (dst) store_stage<NT, P, ELDS>(L, n, S, W, T, sgn_u, dst);
     __syncthreads();
   }
 
@@ -924,23 +923,40 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     store_rm<NT, P>(L, T, I.t_out, n);
     for (int t = L.t; t < n; t += G::THREADS) I.d_out[t] = S.dnew[t];
   }
-  if (flags & SW_GREENS) {
-    for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
-    RM<NT, P> Z;
-    double ld, sg;
-    inv_one_plus<NT, P, ELDS>(L, n, S, W, T, sgn_u, Z, &ld, &sg);
-    if (!all_finite<NT, P>(L, Z) || !isfinite(ld)) bad = 1;
-    if (I.g) store_perm_rows<NT, P, ELDS>(L, n, S, Z, I.g);
-    if (L.t == 0) {
-      if (I.logdet) *I.logdet = ld;
-      if (I.sign) *I.sign = sg;
-    }
-  }
   if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 }
 
+// Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1).
 template <int NT, int P, bool ELDS>
-__global__ __launch_bounds__(64 * P) void k_sweep(const Inst* __restrict__ insts,
+__device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
+  using G = Geo<NT, P>;
+  const int n = I.n;
+  const double* F = I.fin;
+  RM<NT, P> U, T, Z;
+  load_rm<NT, P>(L, U, F, n, false);
+  load_rm<NT, P>(L, T, F + (size_t)n * n, n, false);
+  __syncthreads();
+  int bad = 0;
+  for (int t = L.t; t < G::NP; t += G::THREADS) {
+    const double d = t < n ? F[2 * (size_t)n * n + t] : 1.0;
+    if (!isfinite(d) || !(d > 0.0)) bad = 1;
+    S.dcur[t] = d;
+  }
+  const double sgn_u = F[2 * (size_t)n * n + n];
+  double ld, sg;
+  inv_one_plus<NT, P, ELDS>(L, n, S, U, T, sgn_u, Z, &ld, &sg);
+  if (!all_finite<NT, P>(L, Z) || !isfinite(ld)) bad = 1;
+  if (I.g) store_perm_rows<NT, P, ELDS>(L, n, S, Z, I.g);
+  if (L.t == 0) {
+    if (I.logdet) *I.logdet = ld;
+    if (I.sign) *I.sign = sg;
+  }
+  if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+template <int NT, int P, bool ELDS>
+__global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
                                                             int count, Queue* q) {
   __shared__ Smem<NT, P, ELDS> S;
@@ -1302,11 +1318,10 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   __syncthreads();
 }
 
-template <int NT, int P, bool ELDS>
-__global__ __launch_bounds__(64 * P) void k_pair(const Inst* __restrict__ insts,
-                                                           const PairItem* __restrict__ items,
-                                                           int count, const int32_t* __restrict__ l_list,
-                                                           Queue* q, int mode) {
+template <int NT, int P, bool ELDS, int MODE>
+__global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
+    const Inst* __restrict__ insts, const PairItem* __restrict__ items, int count,
+    const int32_t* __restrict__ l_list, Queue* q) {
   __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
   for (;;) {
@@ -1317,8 +1332,9 @@ __global__ __launch_bounds__(64 * P) void k_pair(const Inst* __restrict__ insts,
     if (it >= count) break;
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
-    if (mode == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
-    else pair_grad<NT, P, ELDS>(L, S, I, wi.j);
+    if constexpr (MODE == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else if constexpr (MODE == PAIR_GRAD) pair_grad<NT, P, ELDS>(L, S, I, wi.j);
+    else pair_equal<NT, P, ELDS>(L, S, I);
   }
 }
 
@@ -1373,8 +1389,13 @@ struct Launch {
   }
   static hipError_t pair(int mode, const Inst* inst, const PairItem* items, int count,
                          const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_pair<NT, P, kPairLds>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
-                       items, count, l_list, q, mode);
+    const dim3 b(Geo<NT, P>::THREADS);
+    if (mode == PAIR_TDISP)
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_TDISP>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
+    else if (mode == PAIR_GRAD)
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_GRAD>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
+    else
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_EQUAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     return hipGetLastError();
   }
   static hipError_t udt(int n, int count, const double* w, double* u, double* d, double* t,
@@ -1400,7 +1421,7 @@ struct Launch {
       return info_of(k_sweep<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);
     }
     if (kind == KK_PAIR)
-      return info_of(k_pair<NT, P, kPairLds>, (int)sizeof(Smem<NT, P, kPairLds>), out);
+      return info_of(k_pair<NT, P, kPairLds, PAIR_TDISP>, (int)sizeof(Smem<NT, P, kPairLds>), out);
     return info_of(k_udt<NT, P>, (int)sizeof(Smem<NT, P, false>), out);
   }
 };

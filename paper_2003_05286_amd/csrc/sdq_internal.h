@@ -39,12 +39,13 @@ struct Inst {
   double* t_out;
   const double* esw;       // expk, zero padded to 16*ceil(n/16) and swizzled
   const double* eswt;      // expk^T, same layout (see launch_swizzle)
+  double* fin;             // final forward stage (read by the equal-time inversion)
 };
 
 enum SweepFlags : int32_t {
   SW_ADJ = 1,     // backward sweep over B_l^T from l = m down to 1
   SW_STORE = 2,   // store every stage (ckf for forward, cka for backward)
-  SW_GREENS = 4,  // forward only: G, logdet, sign from the final factors
+  SW_LAST = 4,    // store the last stage at fin (implied by SW_STORE forward)
   SW_FINAL = 8,   // write the final U, D, T to u_out / d_out / t_out
 };
 
@@ -53,10 +54,12 @@ struct SweepItem {
   int32_t flags;
 };
 
-enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1 };
+enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2 };
+constexpr int kPairModes = 3;
 
 // tdisp: stage pair j, outputs for l_list[ilo..ihi)
 // grad:  stage pair j (slices j*k+1 .. min((j+1)k, m))
+// equal: the final forward stage -> G, logdet, sign
 struct PairItem {
   int32_t inst;
   int32_t j;

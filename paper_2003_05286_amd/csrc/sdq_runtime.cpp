@@ -50,17 +50,18 @@ struct Tune {
   int blocks_per_cu = 0;  // 0 = occupancy limit
 };
 
-// one planned batch: what gets uploaded and launched
+// one planned batch: what gets uploaded and launched.  Sweeps run first,
+// then the pair items of each mode (equal-time, time-displaced, gradient);
+// every (mode, tile class) is one persistent launch.
 struct Plan {
   std::vector<Inst> inst;
   std::vector<SweepItem> sweep;
-  std::vector<PairItem> pair;
+  std::vector<PairItem> pair[sdq::kPairModes];
   std::vector<int32_t> llist;
   struct Range {
     int nt, off, count;
   };
-  std::vector<Range> sweep_ranges, pair_ranges;
-  int pair_mode = 0;
+  std::vector<Range> sweep_ranges, pair_ranges[sdq::kPairModes];
 };
 
 }  // namespace
@@ -70,7 +71,7 @@ struct sdq_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int num_cu = 256;
-  DevBuf d_upload, d_ck, d_swz;
+  DevBuf d_upload, d_ck, d_swz, d_fin;
   void* h_stage = nullptr;
   size_t h_cap = 0;
   hipEvent_t stage_ev = nullptr;
@@ -299,14 +300,25 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
     if (st) return st;
   }
   const size_t n_inst = P.inst.size();
-  const int nq = (int)(P.sweep_ranges.size() + P.pair_ranges.size());
+  int nq = (int)P.sweep_ranges.size();
+  size_t n_pair = 0;
+  for (int md = 0; md < sdq::kPairModes; ++md) {
+    nq += (int)P.pair_ranges[md].size();
+    n_pair += P.pair[md].size();
+  }
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_inst = 0;
   const size_t o_sw = align(o_inst + n_inst * sizeof(Inst));
-  const size_t o_pa = align(o_sw + P.sweep.size() * sizeof(SweepItem));
-  const size_t o_ll = align(o_pa + P.pair.size() * sizeof(PairItem));
+  size_t o_pa[sdq::kPairModes];
+  size_t o = align(o_sw + P.sweep.size() * sizeof(SweepItem));
+  for (int md = 0; md < sdq::kPairModes; ++md) {
+    o_pa[md] = o;
+    o = align(o + P.pair[md].size() * sizeof(PairItem));
+  }
+  const size_t o_ll = o;
   const size_t o_q = align(o_ll + P.llist.size() * sizeof(int32_t));
   const size_t total = align(o_q + (size_t)std::max(nq, 1) * sizeof(Queue));
+  (void)n_pair;
 
   if (ctx->stage_pending) {
     HIP_TRY(hipEventSynchronize(ctx->stage_ev), "hipEventSynchronize(staging)");
@@ -323,7 +335,9 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   memset(h, 0, total);
   if (n_inst) memcpy(h + o_inst, P.inst.data(), n_inst * sizeof(Inst));
   if (!P.sweep.empty()) memcpy(h + o_sw, P.sweep.data(), P.sweep.size() * sizeof(SweepItem));
-  if (!P.pair.empty()) memcpy(h + o_pa, P.pair.data(), P.pair.size() * sizeof(PairItem));
+  for (int md = 0; md < sdq::kPairModes; ++md)
+    if (!P.pair[md].empty())
+      memcpy(h + o_pa[md], P.pair[md].data(), P.pair[md].size() * sizeof(PairItem));
   if (!P.llist.empty()) memcpy(h + o_ll, P.llist.data(), P.llist.size() * sizeof(int32_t));
   HIP_TRY(grow(ctx->d_upload, total), "hipMalloc(upload)");
   char* d = (char*)ctx->d_upload.p;
@@ -341,7 +355,6 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   }
   const Inst* d_inst = (const Inst*)(d + o_inst);
   const SweepItem* d_sw = (const SweepItem*)(d + o_sw);
-  const PairItem* d_pa = (const PairItem*)(d + o_pa);
   const int32_t* d_ll = (const int32_t*)(d + o_ll);
   Queue* d_q = (Queue*)(d + o_q);
   int qi = 0;
@@ -354,16 +367,43 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
     });
     if (st) return st;
   }
-  for (const auto& r : P.pair_ranges) {
-    const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, 0, r.count);
-    Queue* q = d_q + qi++;
-    sdq_status st = timed(ctx, "pair", [&] {
-      return sdq::launch_pair(r.nt, 0, P.pair_mode, d_inst, d_pa + r.off, r.count, d_ll, q, grid,
-                              ctx->stream);
-    });
-    if (st) return st;
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal"};
+  const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_GRAD};
+  for (int oi = 0; oi < sdq::kPairModes; ++oi) {
+    const int md = order[oi];
+    const PairItem* d_pa = (const PairItem*)(d + o_pa[md]);
+    for (const auto& r : P.pair_ranges[md]) {
+      const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, 0, r.count);
+      Queue* q = d_q + qi++;
+      sdq_status st = timed(ctx, names[md], [&] {
+        return sdq::launch_pair(r.nt, 0, md, d_inst, d_pa + r.off, r.count, d_ll, q, grid, ctx->stream);
+      });
+      if (st) return st;
+    }
   }
   return SDQ_OK;
+}
+
+// per-chain final-stage arena for calls that keep no stage stack
+sdq_status alloc_fin(sdq_ctx* ctx, const sdq_instance* inst, int count, std::vector<int64_t>& off) {
+  off.resize(count);
+  int64_t tot = 0;
+  for (int i = 0; i < count; ++i) {
+    off[i] = tot;
+    tot += (sdq::stage_doubles(inst[i].n) + 31) & ~(int64_t)31;
+  }
+  hipError_t e = grow(ctx->d_fin, (size_t)std::max<int64_t>(tot, 1) * sizeof(double));
+  if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "final-stage arena: " + std::string(hipGetErrorString(e)));
+  return SDQ_OK;
+}
+
+void order_all_pairs(Plan& P) {
+  for (int md = 0; md < sdq::kPairModes; ++md) {
+    order_items(P.inst, P.pair[md], P.pair_ranges[md], [&](const PairItem& w) {
+      const Inst& I = P.inst[w.inst];
+      return (double)I.n * I.n * I.n * (11.0 + (w.ihi - w.ilo) * (double)I.k);
+    });
+  }
 }
 
 // checkpoint arena: two stage stacks per instance
@@ -435,6 +475,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_upload.p) (void)hipFree(ctx->d_upload.p);
   if (ctx->d_ck.p) (void)hipFree(ctx->d_ck.p);
   if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
+  if (ctx->d_fin.p) (void)hipFree(ctx->d_fin.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
@@ -458,6 +499,9 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   if (scheme != SDQ_INV_LOH) return fail(ctx, SDQ_EUNSUPPORTED, "only SDQ_INV_LOH is implemented");
   if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<int64_t> off;
+  st = alloc_fin(ctx, inst, count, off);
+  if (st) return st;
   Plan P;
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
@@ -465,13 +509,16 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
+    I.fin = (double*)ctx->d_fin.p + off[i];
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, sdq::SW_GREENS});
+    P.sweep.push_back(SweepItem{i, sdq::SW_LAST});
+    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];
     return sweep_cost(I.n, I.m, I.k);
   });
+  order_all_pairs(P);
   ctx->err.clear();
   return run_plan(ctx, P, status, count);
 }
@@ -498,7 +545,6 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
   if (st) return st;
   double* ck = (double*)ctx->d_ck.p;
   Plan P;
-  P.pair_mode = sdq::PAIR_TDISP;
   P.llist.assign(l_list, l_list + n_l);
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
@@ -507,13 +553,15 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
-    const int64_t one = (int64_t)I.nb * sdq::stage_doubles(I.n);
+    const int64_t sd = sdq::stage_doubles(I.n);
+    const int64_t one = (int64_t)I.nb * sd;
     I.ckf = ck + off[i];
     I.cka = ck + off[i] + one;
+    I.fin = I.ckf + (I.nb - 1) * sd;
     P.inst.push_back(I);
-    const bool want_g = I.g || I.logdet || I.sign;
-    P.sweep.push_back(SweepItem{i, sdq::SW_STORE | (want_g ? sdq::SW_GREENS : 0)});
+    P.sweep.push_back(SweepItem{i, sdq::SW_STORE});
     P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ});
+    if (I.g || I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
     // group l by stage pair j: l == m -> nb, else l / k
     for (int a = 0; a < n_l;) {
       const int l = l_list[a];
@@ -525,7 +573,7 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
         if (j2 != j) break;
         ++b;
       }
-      P.pair.push_back(PairItem{i, j, a, b});
+      P.pair[sdq::PAIR_TDISP].push_back(PairItem{i, j, a, b});
       a = b;
     }
   }
@@ -533,10 +581,7 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
     const Inst& I = P.inst[w.inst];
     return sweep_cost(I.n, I.m, I.k);
   });
-  order_items(P.inst, P.pair, P.pair_ranges, [&](const PairItem& w) {
-    const Inst& I = P.inst[w.inst];
-    return (double)I.n * I.n * I.n * (11.0 + 2.0 * (w.ihi - w.ilo) * I.k / 2.0);
-  });
+  order_all_pairs(P);
   ctx->err.clear();
   return run_plan(ctx, P, status, count);
 }
@@ -549,12 +594,14 @@ sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, dou
   if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   Handle H;
-  double* ck = nullptr;
+  std::vector<int64_t> foff;
   if (ckpt_handle) {
     st = alloc_stages(ctx, H.ckf, inst, count, 1, H.off);
     if (st) return st;
-    ck = (double*)H.ckf.p;
     H.src.assign(inst, inst + count);
+  } else {
+    st = alloc_fin(ctx, inst, count, foff);
+    if (st) return st;
   }
   Plan P;
   for (int i = 0; i < count; ++i) {
@@ -562,18 +609,23 @@ sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, dou
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
-    int flags = sdq::SW_GREENS;
-    if (ck) {
-      I.ckf = ck + H.off[i];
-      flags |= sdq::SW_STORE;
+    int flags = sdq::SW_LAST;
+    if (ckpt_handle) {
+      I.ckf = (double*)H.ckf.p + H.off[i];
+      I.fin = I.ckf + (int64_t)(I.nb - 1) * sdq::stage_doubles(I.n);
+      flags = sdq::SW_STORE;
+    } else {
+      I.fin = (double*)ctx->d_fin.p + foff[i];
     }
     P.inst.push_back(I);
     P.sweep.push_back(SweepItem{i, flags});
+    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];
     return sweep_cost(I.n, I.m, I.k);
   });
+  order_all_pairs(P);
   ctx->err.clear();
   st = run_plan(ctx, P, status, count);
   if (st) {
@@ -616,34 +668,33 @@ sdq_status sdq_logdet_grad(sdq_ctx* ctx, uint64_t ckpt_handle, const sdq_instanc
   if (st) return st;
   double* ck = (double*)ctx->d_ck.p;
   Plan P;
-  P.pair_mode = sdq::PAIR_GRAD;
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
     I.grad = grad[i];
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
-    const int64_t one = (int64_t)I.nb * sdq::stage_doubles(I.n);
+    const int64_t sd = sdq::stage_doubles(I.n);
+    const int64_t one = (int64_t)I.nb * sd;
     if (H) {
       I.ckf = (double*)H->ckf.p + H->off[i];
       I.cka = ck + off[i];
     } else {
       I.ckf = ck + off[i];
       I.cka = ck + off[i] + one;
-      P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_GREENS});
+      P.sweep.push_back(SweepItem{i, sdq::SW_STORE});
     }
+    I.fin = I.ckf + (I.nb - 1) * sd;
     P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ});
     P.inst.push_back(I);
-    for (int j = 0; j < I.nb; ++j) P.pair.push_back(PairItem{i, j, 0, 0});
+    if (I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+    for (int j = 0; j < I.nb; ++j) P.pair[sdq::PAIR_GRAD].push_back(PairItem{i, j, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];
     return sweep_cost(I.n, I.m, I.k);
   });
-  order_items(P.inst, P.pair, P.pair_ranges, [&](const PairItem& w) {
-    const Inst& I = P.inst[w.inst];
-    return (double)I.n * I.n * I.n;
-  });
+  order_all_pairs(P);
   ctx->err.clear();
   return run_plan(ctx, P, status, count);
 }
