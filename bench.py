@@ -135,6 +135,7 @@ def main():
     t1 = time.perf_counter()
     n_sw, ms_sw = ctx.kernel_stats("sweep")
     n_pa, ms_pa = ctx.kernel_stats("pair")
+    n_eq, ms_eq = ctx.kernel_stats("equal")
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
@@ -194,6 +195,7 @@ def main():
                      "flops_per_launch": f_sweep, "launch_ms": sweep_avg_s * 1e3},
         "pair_kernel": {"launch_ms": pair_avg_s * 1e3, "flops_per_launch": f_pair,
                         "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
+        "equal_kernel": {"launch_ms": ms_eq / max(n_eq, 1)},
         "step_tflops": total_flops / (ms_step * 1e-3) / 1e12,
         "green_matrices_per_s": cnt * (1 + len(l_list)) / (ms_step * 1e-3),
         "equal_time_only_per_s": eq_rate,

@@ -50,7 +50,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // sweep and the equal-time inversion at n <= 64 (they fit 256 registers per
 // lane with little or no spilling), one otherwise
 constexpr int minb_for(int nt) { return nt <= 4 ? 2 : 1; }
-constexpr int minb_pair(int nt, int mode) { return mode == 2 ? minb_for(nt) : 1; }
+constexpr int minb_pair(int nt, int mode) { return mode == 1 ? 1 : minb_for(nt); }
 
 template <int NT, int P_>
 struct Geo {
@@ -1068,9 +1068,8 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
                    },
                    B, P2);
   }
-  // Mid and Y = D_Lp^{-1} T1
-  RM<NT, P> Y;
-  load_rm<NT, P>(L, Y, T1, n, false);
+  // Mid (Y = D_Lp^{-1} T1 is rebuilt from HBM after the QR, so that it is
+  // not live in registers during it)
   double d2c[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
@@ -1091,11 +1090,22 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
         const double rpi = 1.0 / (d2 > 1.0 ? d2 : 1.0);  // D_Rp^{-1}
         const double rm = d2 < 1.0 ? d2 : 1.0;            // D_Rm
         P1.v[c][ti][r] = lm * P1.v[c][ti][r] * rpi + lpi * P2.v[c][ti][r] * rm;
-        Y.v[c][ti][r] *= lpi;
       }
     }
   __syncthreads();
   cpqr<NT, P, ELDS>(L, n, P1, S);
+  RM<NT, P> Y;
+  load_rm<NT, P>(L, Y, T1, n, false);
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+      const double lpi = d1 < 1.0 ? d1 : 1.0;  // D_Lp^{-1}
+#pragma unroll
+      for (int c = 0; c < CT; ++c) Y.v[c][ti][r] *= lpi;
+    }
   apply_qt<NT, P, ELDS>(L, n, S, Y);
   back_subst<NT, P, ELDS>(L, n, S, Y);
   // G = U2 D_Rp^{-1} P Z :  A(i, s) = U2[i][perm s] / max(D2[perm s], 1)
@@ -1133,7 +1143,12 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
   // outputs: l_list[ilo..ihi), ascending, each in [tau_j, tau_j + k)
   const int tj = j * k < m ? j * k : m;
   int lc = tj;
-  const EOp<NT, P, false> eop{nullptr, I.esw, L.l};
+  if (ELDS && ihi > ilo && l_list[ihi - 1] > tj) {
+    // propagation ahead: stage the swizzled slice exponential in LDS
+    __syncthreads();
+    stage_e<NT, P, ELDS>(L, S, I.esw);
+  }
+  const EOp<NT, P, ELDS> eop{S.E, I.esw, L.l};
   for (int idx = ilo; idx < ihi; ++idx) {
     const int l = l_list[idx];
     const int steps = l - lc;
@@ -1141,10 +1156,8 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
       const int cn = (steps - c0) < G::KB ? (steps - c0) : G::KB;
       fill_vbuf<NT, P, ELDS>(L, S, I, lc + c0 + 1, +1, cn);
       for (int s2 = 0; s2 < cn; ++s2) {
-        RM<NT, P> Wn;
         scale_rows<NT, P>(L, Gm, S.vbuf[s2]);
-        gemm_rb<NT, P>(L, eop, Gm, Wn);
-        Gm = Wn;
+        gemm_rb<NT, P>(L, eop, Gm, Gm);
       }
     }
     lc = l;
