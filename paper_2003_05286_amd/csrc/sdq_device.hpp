@@ -323,7 +323,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
-  double vn1[CT], vn2[CT];
+  double vn1[CT], vn2[CT], sv2[CT];  // sv2: exact power-of-two scale of vn2
   int ps[CT];  // -1: live, not yet chosen; else the step (padding: own index)
 
 #pragma unroll
@@ -349,6 +349,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
     s = sum_col(s);
     vn1[c] = sqrt(s) / sc;
     vn2[c] = vn1[c];
+    sv2[c] = pow2_scale(vn2[c]);
   }
 
   int buf = 0;
@@ -393,7 +394,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
     // ---- reflector (every wave computes the same one from the same data)
     const double sc = pow2_scale(vpiv);
     double v[NT][4];
-    double s = 0.0;
+    double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti) {
       if (ti < tj) {
@@ -406,11 +407,11 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
           if (ti == tj && row_of(L, ti, r) <= j) x = 0.0;
           v[ti][r] = x;
           const double y = x * sc;
-          s = fma(y, y, s);
+          sp[r] = fma(y, y, sp[r]);
         }
       }
     }
-    s = sum_col(s);
+    double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
     const double as = alpha * sc;
     const double hn = sqrt(fma(as, as, s)) / sc;  // ||x[j:]||
     double tau = 0.0, beta = alpha, inv = 0.0;
@@ -437,13 +438,13 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
       const bool is_piv = ps[c] < 0 && col == pc;
       const bool upd = ps[c] < 0 && !is_piv;
       rec[c] = false;
-      double d = 0.0;
+      double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ti = 0; ti < NT; ++ti)
         if (ti >= tj)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) d = fma(v[ti][r], A.v[c][ti][r], d);
-      d = sum_col(d) * (upd ? tau : 0.0);
+          for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
+      const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * (upd ? tau : 0.0);
       if (is_piv) {
         // the pivot column becomes column j of R plus the reflector
 #pragma unroll
@@ -464,14 +465,17 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
       }
       const double rjv = sum_col(L.g == gj ? reg_at<NT>(A.v[c], tj, rj) : 0.0);
       if (upd && vn1[c] != 0.0) {
-        double t = fabs(rjv) / vn1[c];
-        t = fmax(0.0, (1.0 - t) * (1.0 + t));
-        const double ratio = vn1[c] / vn2[c];
-        if (t * ratio * ratio <= tol3z) {
+        // vn1^2 - r^2 = vn1^2 (1 - (r/vn1)^2); recompute when that falls to
+        // sqrt(eps) vn2^2 or below (same test, no division), all scaled by
+        // the exact power of two of vn2
+        const double a1 = fabs(rjv) * sv2[c], b1 = vn1[c] * sv2[c];
+        const double q = fmax(0.0, (b1 - a1) * (b1 + a1));
+        const double w2 = vn2[c] * sv2[c];
+        if (q <= tol3z * (w2 * w2)) {
           need = true;
           rec[c] = true;
         } else {
-          vn1[c] *= sqrt(t);
+          vn1[c] = sqrt(q) / sv2[c];
         }
       }
     }
@@ -501,6 +505,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         if (rec[c]) {
           vn1[c] = nn;
           vn2[c] = nn;
+          sv2[c] = pow2_scale(nn);
         }
       }
     }
@@ -570,13 +575,13 @@ __device__ __forceinline__ void apply_reflector(const Lane& L, int j, double tau
   const int tj = j >> 4;
 #pragma unroll
   for (int c = 0; c < Geo<NT, P>::CT; ++c) {
-    double d = 0.0;
+    double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
       if (ti >= tj)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d = fma(v[ti][r], X.v[c][ti][r], d);
-    d = sum_col(d) * tau;
+        for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], X.v[c][ti][r], dp[r]);
+    const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * tau;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
       if (ti >= tj)
