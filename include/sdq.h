@@ -152,13 +152,17 @@ sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, 
 sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const char* cache_path);
 
 /* Capture later batched calls in HIP graphs and replay them when the same
- * instance set (pointers and shapes) is seen again (enable = 1), or launch
- * directly (enable = 0, the default). */
+ * batch (every pointer, shape, list and scheme) is seen again (enable = 1),
+ * or launch directly (enable = 0, the default).  A replay runs on the
+ * context's stream; at most 16 graphs are kept (oldest evicted). */
 sdq_status sdq_set_graphs(sdq_ctx* ctx, int enable);
 
 /* Record HIP events around every kernel launch (enable = 1); the per-kernel
  * launch count and summed device milliseconds are then read with
- * sdq_kernel_stats (names: "sweep", "pair", "udt").  Resets the counters. */
+ * sdq_kernel_stats (names: "sweep" for the stabilized sweeps, "equal" for
+ * the equal-time inversions, "pair" for the time-displaced inversions,
+ * "grad" for the gradient, "udt", and "graph" for a replayed graph).
+ * Resets the counters. */
 sdq_status sdq_set_profiling(sdq_ctx* ctx, int enable);
 sdq_status sdq_kernel_stats(sdq_ctx* ctx, const char* name, int64_t* launches, double* ms);
 

@@ -84,9 +84,12 @@ struct sdq_ctx {
   std::map<std::string, KStat> stats;
   std::vector<hipEvent_t> ev_pool;
   bool graphs = false;
+  hipStream_t cap_stream = nullptr;  // non-null stream used only for graph capture
   struct GraphEntry {
     std::vector<char> key;
     hipGraphExec_t exec = nullptr;
+    void* h = nullptr;  // pinned copy of the upload image the graph copies from
+    void* d = nullptr;  // device upload buffer of the graph
   };
   std::vector<GraphEntry> graph_cache;
 };
@@ -291,24 +294,35 @@ sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
   return SDQ_OK;
 }
 
-// Upload the plan (instances, items, l_list, zeroed queues) in one copy and
-// run it: all sweeps, then all pair items.
-sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
+// A planned batch turned into one upload image (instances, items, l_list,
+// zeroed queue counters) and a list of launches whose pointers are offsets
+// into that image once it is on the device.
+struct LaunchRec {
+  int kind;  // KK_SWEEP or KK_PAIR
+  int nt, variant, mode, grid, count;
+  size_t items_off;  // byte offset of the first item
+  size_t queue_off;  // byte offset of this launch's queue counter
+};
+
+struct Built {
+  std::vector<char> image;
+  std::vector<LaunchRec> launches;
   std::vector<SwzJob> swz;
+  size_t o_inst = 0, o_ll = 0;
+  int32_t* status = nullptr;
+  int count = 0;
+};
+
+sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& B) {
   {
-    sdq_status st = prepare_swizzle(ctx, P, swz);
+    sdq_status st = prepare_swizzle(ctx, P, B.swz);
     if (st) return st;
   }
-  const size_t n_inst = P.inst.size();
-  int nq = (int)P.sweep_ranges.size();
-  size_t n_pair = 0;
-  for (int md = 0; md < sdq::kPairModes; ++md) {
-    nq += (int)P.pair_ranges[md].size();
-    n_pair += P.pair[md].size();
-  }
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  int nq = (int)P.sweep_ranges.size();
+  for (int md = 0; md < sdq::kPairModes; ++md) nq += (int)P.pair_ranges[md].size();
   const size_t o_inst = 0;
-  const size_t o_sw = align(o_inst + n_inst * sizeof(Inst));
+  const size_t o_sw = align(o_inst + P.inst.size() * sizeof(Inst));
   size_t o_pa[sdq::kPairModes];
   size_t o = align(o_sw + P.sweep.size() * sizeof(SweepItem));
   for (int md = 0; md < sdq::kPairModes; ++md) {
@@ -318,12 +332,138 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   const size_t o_ll = o;
   const size_t o_q = align(o_ll + P.llist.size() * sizeof(int32_t));
   const size_t total = align(o_q + (size_t)std::max(nq, 1) * sizeof(Queue));
-  (void)n_pair;
+  B.image.assign(total, 0);
+  char* h = B.image.data();
+  if (!P.inst.empty()) memcpy(h + o_inst, P.inst.data(), P.inst.size() * sizeof(Inst));
+  if (!P.sweep.empty()) memcpy(h + o_sw, P.sweep.data(), P.sweep.size() * sizeof(SweepItem));
+  for (int md = 0; md < sdq::kPairModes; ++md)
+    if (!P.pair[md].empty())
+      memcpy(h + o_pa[md], P.pair[md].data(), P.pair[md].size() * sizeof(PairItem));
+  if (!P.llist.empty()) memcpy(h + o_ll, P.llist.data(), P.llist.size() * sizeof(int32_t));
+  B.o_inst = o_inst;
+  B.o_ll = o_ll;
+  B.status = status;
+  B.count = count;
+  int qi = 0;
+  for (const auto& r : P.sweep_ranges) {
+    const int variant = ctx->tune[r.nt].variant;
+    const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
+    B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
+                                   o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
+  }
+  const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_GRAD};
+  for (int oi = 0; oi < sdq::kPairModes; ++oi) {
+    const int md = order[oi];
+    for (const auto& r : P.pair_ranges[md]) {
+      const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, 0, r.count);
+      B.launches.push_back(LaunchRec{sdq::KK_PAIR, r.nt, 0, md, grid, r.count,
+                                     o_pa[md] + r.off * sizeof(PairItem), o_q + (qi++) * sizeof(Queue)});
+    }
+  }
+  return SDQ_OK;
+}
 
+// Enqueue a built batch on stream s: upload h_src -> d, reset status, build
+// the swizzled operands, launch.  `timing` brackets launches with events.
+sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, const char* h_src,
+                         bool timing) {
+  HIP_TRY(hipMemcpyAsync(d, h_src, B.image.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync(plan)");
+  if (B.status && B.count > 0) HIP_TRY(sdq::launch_fill_i32(B.status, B.count, 0, s), "fill(status)");
+  for (const SwzJob& j : B.swz) {
+    const int64_t np = 16LL * nt_of(j.n);
+    double* out = (double*)ctx->d_swz.p + j.off;
+    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 0, out, s), "swizzle");
+    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 1, out + np * np, s), "swizzle");
+  }
+  const Inst* d_inst = (const Inst*)(d + B.o_inst);
+  const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal"};
+  for (const LaunchRec& L : B.launches) {
+    Queue* q = (Queue*)(d + L.queue_off);
+    auto go = [&]() -> hipError_t {
+      if (L.kind == sdq::KK_SWEEP)
+        return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
+                                 q, L.grid, s);
+      return sdq::launch_pair(L.nt, 0, L.mode, d_inst, (const PairItem*)(d + L.items_off), L.count,
+                              d_ll, q, L.grid, s);
+    };
+    const char* nm = L.kind == sdq::KK_SWEEP ? "sweep" : names[L.mode];
+    if (timing) {
+      sdq_status st = timed(ctx, nm, go);
+      if (st) return st;
+    } else {
+      hipError_t e = go();
+      if (e != hipSuccess) return hip_fail(ctx, e, nm);
+    }
+  }
+  return SDQ_OK;
+}
+
+// graph cache key: the upload image, the launch list, the status target and
+// the swizzle jobs (all pointers included, so any reallocation misses)
+std::vector<char> graph_key(const Built& B) {
+  std::vector<char> k(B.image);
+  auto put = [&](const void* p, size_t n) {
+    const char* c = (const char*)p;
+    k.insert(k.end(), c, c + n);
+  };
+  for (const LaunchRec& L : B.launches) put(&L, sizeof L);
+  put(&B.status, sizeof B.status);
+  put(&B.count, sizeof B.count);
+  for (const SwzJob& j : B.swz) put(&j, sizeof j);
+  return k;
+}
+
+// Upload the plan and run it: all sweeps, then all pair items.  In graph
+// mode a batch seen before (same key) replays its captured graph.
+sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
+  Built B;
+  sdq_status st = build_plan(ctx, P, status, count, B);
+  if (st) return st;
+  if (ctx->graphs) {
+    std::vector<char> key = graph_key(B);
+    sdq_ctx::GraphEntry* hit = nullptr;
+    for (auto& g : ctx->graph_cache)
+      if (g.key == key) hit = &g;
+    if (!hit) {
+      if (ctx->graph_cache.size() >= 16) {
+        auto& old = ctx->graph_cache.front();
+        HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        if (old.exec) (void)hipGraphExecDestroy(old.exec);
+        if (old.h) (void)hipHostFree(old.h);
+        if (old.d) (void)hipFree(old.d);
+        ctx->graph_cache.erase(ctx->graph_cache.begin());
+      }
+      sdq_ctx::GraphEntry g;
+      g.key = std::move(key);
+      HIP_TRY(hipHostMalloc(&g.h, B.image.size(), hipHostMallocDefault), "hipHostMalloc(graph)");
+      memcpy(g.h, B.image.data(), B.image.size());
+      HIP_TRY(hipMalloc(&g.d, B.image.size()), "hipMalloc(graph)");
+      if (!ctx->cap_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+      HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      st = enqueue_built(ctx, B, ctx->cap_stream, (char*)g.d, (const char*)g.h, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+      ctx->graph_cache.push_back(std::move(g));
+      hit = &ctx->graph_cache.back();
+    }
+    hipGraphExec_t exec = hit->exec;
+    return timed(ctx, "graph", [&] { return hipGraphLaunch(exec, ctx->stream); });
+  }
   if (ctx->stage_pending) {
     HIP_TRY(hipEventSynchronize(ctx->stage_ev), "hipEventSynchronize(staging)");
     ctx->stage_pending = false;
   }
+  const size_t total = B.image.size();
   if (total > ctx->h_cap) {
     if (ctx->h_stage) HIP_TRY(hipHostFree(ctx->h_stage), "hipHostFree");
     ctx->h_stage = nullptr;
@@ -331,56 +471,12 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
     HIP_TRY(hipHostMalloc(&ctx->h_stage, total * 2, hipHostMallocDefault), "hipHostMalloc");
     ctx->h_cap = total * 2;
   }
-  char* h = (char*)ctx->h_stage;
-  memset(h, 0, total);
-  if (n_inst) memcpy(h + o_inst, P.inst.data(), n_inst * sizeof(Inst));
-  if (!P.sweep.empty()) memcpy(h + o_sw, P.sweep.data(), P.sweep.size() * sizeof(SweepItem));
-  for (int md = 0; md < sdq::kPairModes; ++md)
-    if (!P.pair[md].empty())
-      memcpy(h + o_pa[md], P.pair[md].data(), P.pair[md].size() * sizeof(PairItem));
-  if (!P.llist.empty()) memcpy(h + o_ll, P.llist.data(), P.llist.size() * sizeof(int32_t));
+  memcpy(ctx->h_stage, B.image.data(), total);
   HIP_TRY(grow(ctx->d_upload, total), "hipMalloc(upload)");
-  char* d = (char*)ctx->d_upload.p;
-  HIP_TRY(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync(plan)");
+  st = enqueue_built(ctx, B, ctx->stream, (char*)ctx->d_upload.p, (const char*)ctx->h_stage, true);
+  if (st) return st;
   HIP_TRY(hipEventRecord(ctx->stage_ev, ctx->stream), "hipEventRecord");
   ctx->stage_pending = true;
-  if (status && count > 0) {
-    HIP_TRY(sdq::launch_fill_i32(status, count, 0, ctx->stream), "fill(status)");
-  }
-  for (const SwzJob& j : swz) {
-    const int64_t np = 16LL * nt_of(j.n);
-    double* out = (double*)ctx->d_swz.p + j.off;
-    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 0, out, ctx->stream), "swizzle");
-    HIP_TRY(sdq::launch_swizzle(j.e, j.n, 1, out + np * np, ctx->stream), "swizzle");
-  }
-  const Inst* d_inst = (const Inst*)(d + o_inst);
-  const SweepItem* d_sw = (const SweepItem*)(d + o_sw);
-  const int32_t* d_ll = (const int32_t*)(d + o_ll);
-  Queue* d_q = (Queue*)(d + o_q);
-  int qi = 0;
-  for (const auto& r : P.sweep_ranges) {
-    const int variant = ctx->tune[r.nt].variant;
-    const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
-    Queue* q = d_q + qi++;
-    sdq_status st = timed(ctx, "sweep", [&] {
-      return sdq::launch_sweep(r.nt, variant, d_inst, d_sw + r.off, r.count, q, grid, ctx->stream);
-    });
-    if (st) return st;
-  }
-  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal"};
-  const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_GRAD};
-  for (int oi = 0; oi < sdq::kPairModes; ++oi) {
-    const int md = order[oi];
-    const PairItem* d_pa = (const PairItem*)(d + o_pa[md]);
-    for (const auto& r : P.pair_ranges[md]) {
-      const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, 0, r.count);
-      Queue* q = d_q + qi++;
-      sdq_status st = timed(ctx, names[md], [&] {
-        return sdq::launch_pair(r.nt, 0, md, d_inst, d_pa + r.off, r.count, d_ll, q, grid, ctx->stream);
-      });
-      if (st) return st;
-    }
-  }
   return SDQ_OK;
 }
 
@@ -470,8 +566,12 @@ void sdq_destroy(sdq_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->handles)
     if (kv.second.ckf.p) (void)hipFree(kv.second.ckf.p);
-  for (auto& g : ctx->graph_cache)
+  for (auto& g : ctx->graph_cache) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.h) (void)hipHostFree(g.h);
+    if (g.d) (void)hipFree(g.d);
+  }
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->d_upload.p) (void)hipFree(ctx->d_upload.p);
   if (ctx->d_ck.p) (void)hipFree(ctx->d_ck.p);
   if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
@@ -748,18 +848,129 @@ sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, 
   return run_plan(ctx, P, nullptr, 0);
 }
 
+// Autotuner: for each n, time sdq_logdet on a synthetic batch (two chains
+// per CU, m = 40, k = 10, a periodic ring's second-order slice exponential,
+// +-1 field) for every sweep variant (operand in LDS or HBM) and grid shape
+// (one workgroup per CU or the occupancy limit), keep the fastest.  Results
+// are cached as JSON lines {"arch", "n", "variant", "blocks_per_cu", "ms"}.
 sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const char* cache_path) {
-  (void)n_list;
-  (void)count;
-  (void)cache_path;
   if (!ctx) return SDQ_EINVAL;
-  return fail(ctx, SDQ_EUNSUPPORTED, "autotuning is not available yet");
+  if (count < 0 || (count > 0 && !n_list)) return fail(ctx, SDQ_EINVAL, "bad n_list");
+  for (int a = 0; a < count; ++a)
+    if (n_list[a] < 1 || n_list[a] > 16 * sdq::kMaxNT) return fail(ctx, SDQ_EUNSUPPORTED, "n out of range");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "hipGetDeviceProperties");
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::map<int, Tune> cached;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        char a[64] = {0};
+        int n = 0, v = 0, b = 0;
+        if (sscanf(line, " {\"arch\": \"%63[^\"]\", \"n\": %d, \"variant\": %d, \"blocks_per_cu\": %d", a, &n, &v,
+                   &b) == 4 &&
+            arch == a)
+          cached[n] = Tune{v, b};
+      }
+      fclose(f);
+    }
+  }
+  const bool saved_graphs = ctx->graphs, saved_prof = ctx->profiling;
+  ctx->graphs = false;
+  ctx->profiling = false;
+  sdq_status result = SDQ_OK;
+  for (int a = 0; a < count && result == SDQ_OK; ++a) {
+    const int n = n_list[a], nt = nt_of(n);
+    auto hit = cached.find(n);
+    if (hit != cached.end()) {
+      ctx->tune[nt] = hit->second;
+      continue;
+    }
+    const int m = 40, k = 10, chains = 2 * ctx->num_cu;
+    std::vector<double> E((size_t)n * n, 0.0), K((size_t)n * n, 0.0), F((size_t)chains * m * n);
+    for (int i = 0; i < n; ++i) {
+      K[(size_t)i * n + (i + 1) % n] -= 1.0;
+      K[(size_t)((i + 1) % n) * n + i] -= 1.0;
+    }
+    const double dt = 0.1;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double k2 = 0.0;
+        for (int q = 0; q < n; ++q) k2 += K[(size_t)i * n + q] * K[(size_t)q * n + j];
+        E[(size_t)i * n + j] = (i == j ? 1.0 : 0.0) - dt * K[(size_t)i * n + j] + 0.5 * dt * dt * k2;
+      }
+    uint64_t x = 0x9E3779B97F4A7C15ull + n;
+    for (double& v : F) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      v = (x & 1) ? 1.0 : -1.0;
+    }
+    double *dE = nullptr, *dF = nullptr, *dL = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+      if (dE) (void)hipFree(dE);
+      if (dF) (void)hipFree(dF);
+      if (dL) (void)hipFree(dL);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&dE, E.size() * 8) != hipSuccess || hipMalloc(&dF, F.size() * 8) != hipSuccess ||
+        hipMalloc(&dL, (size_t)chains * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+      cleanup();
+      result = fail(ctx, SDQ_ENOMEM, "tune: device allocation failed");
+      break;
+    }
+    (void)hipMemcpy(dE, E.data(), E.size() * 8, hipMemcpyHostToDevice);
+    (void)hipMemcpy(dF, F.data(), F.size() * 8, hipMemcpyHostToDevice);
+    std::vector<sdq_instance> inst(chains);
+    for (int c = 0; c < chains; ++c)
+      inst[c] = sdq_instance{n, m, k, 0, dE, nullptr, dF + (size_t)c * m * n, 0.65};
+    std::vector<Tune> cands;
+    for (int v = 0; v <= ((nt >= 3 && nt <= 5) ? 1 : 0); ++v)
+      for (int b : {1, 0}) cands.push_back(Tune{v, b});
+    double best = 1e300;
+    Tune bt = ctx->tune[nt];
+    for (const Tune& c : cands) {
+      ctx->tune[nt] = c;
+      double tmin = 1e300;
+      for (int rep = 0; rep < 4 && result == SDQ_OK; ++rep) {
+        (void)hipEventRecord(e0, ctx->stream);
+        result = sdq_logdet(ctx, inst.data(), chains, dL, dL + chains, nullptr, nullptr);
+        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tmin = std::min(tmin, (double)ms);
+      }
+      if (result != SDQ_OK) break;
+      if (tmin < best) {
+        best = tmin;
+        bt = c;
+      }
+    }
+    cleanup();
+    ctx->tune[nt] = bt;
+    if (result == SDQ_OK && cache_path) {
+      if (FILE* f = fopen(cache_path, "a")) {
+        fprintf(f, "{\"arch\": \"%s\", \"n\": %d, \"variant\": %d, \"blocks_per_cu\": %d, \"ms\": %.4f}\n",
+                arch.c_str(), n, bt.variant, bt.blocks_per_cu, best);
+        fclose(f);
+      }
+    }
+  }
+  ctx->graphs = saved_graphs;
+  ctx->profiling = saved_prof;
+  return result;
 }
 
 sdq_status sdq_set_graphs(sdq_ctx* ctx, int enable) {
   if (!ctx) return SDQ_EINVAL;
-  if (enable) return fail(ctx, SDQ_EUNSUPPORTED, "graph capture is not available yet");
-  ctx->graphs = false;
+  ctx->graphs = enable != 0;
   return SDQ_OK;
 }
 

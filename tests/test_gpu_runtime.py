@@ -1,0 +1,76 @@
+"""Runtime features through the C ABI on the GPU: HIP graph replay and the
+autotuner.  Graph replays are checked one by one against the eager result,
+with the test's own eager work and synchronizations between them."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _gpu import chains_of, relF, say
+from paper_2003_05286_amd import binding as sdq
+from paper_2003_05286_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_graph_replay_matches_eager():
+    say("[gpu] graph replay: L=6 beta=10, 8 chains, G + G(tau,0)")
+    ctx = sdq.Context(0)
+    insts = wl.hubbard_ising(6, 10.0, 4, 2, seed=wl.BASE_SEED + 700)
+    ch = chains_of(insts)
+    ls = [0, 10, 35, 60, 100]
+    gts0, gs0, ld0, sg0, st0 = ctx.greens_tdisp(ch, ls)
+    torch.cuda.synchronize()
+    ctx.set_graphs(True)
+    import ctypes
+    inst_arr = ctx._instances(ch)
+    larr = (ctypes.c_int32 * len(ls))(*ls)
+    gts = [torch.empty_like(g) for g in gts0]
+    gs = [torch.empty_like(g) for g in gs0]
+    ld = torch.empty_like(ld0)
+    sg = torch.empty_like(sg0)
+    st = torch.empty_like(st0)
+    gp, g2 = ctx._ptr_array(gts), ctx._ptr_array(gs)
+    for rep in range(4):
+        for t in gts + gs:
+            t.zero_()          # eager work between replays
+        ld.zero_()
+        junk = torch.randn(1000, device="cuda").sum()  # unrelated eager kernels
+        torch.cuda.synchronize()
+        say(f"[gpu]   replay {rep}")
+        ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, len(ch), 0, larr, len(ls), gp, g2,
+                                          ctypes.c_void_p(ld.data_ptr()), ctypes.c_void_p(sg.data_ptr()),
+                                          ctypes.c_void_p(st.data_ptr())))
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a in range(len(ch)):
+            assert torch.equal(gts[a], gts0[a]), (rep, a)
+            assert torch.equal(gs[a], gs0[a]), (rep, a)
+        assert torch.equal(ld, ld0) and torch.equal(sg, sg0) and torch.equal(st, st0)
+    ctx.set_graphs(False)
+    ctx.close()
+
+
+def test_autotune_cache_and_parity(tmp_path):
+    path = str(tmp_path / "tune.jsonl")
+    ctx = sdq.Context(0)
+    say("[gpu] sdq_tune n = 36, 64")
+    ctx.tune([36, 64], path)
+    lines = [json.loads(l) for l in open(path)]
+    assert {l["n"] for l in lines} == {36, 64}
+    assert all(l["variant"] in (0, 1) and l["blocks_per_cu"] in (0, 1) for l in lines)
+    # a second call reads the cache and adds nothing
+    ctx.tune([36, 64], path)
+    assert len(open(path).read().splitlines()) == 2
+    for L, beta in ((6, 10.0), (8, 20.0)):
+        insts = wl.hubbard_ising(L, beta, 2, 1, seed=wl.BASE_SEED + 710 + L)
+        gs, ld, sg, st = ctx.greens(chains_of(insts))
+        torch.cuda.synchronize()
+        for a, I in enumerate(insts):
+            G, ldo, sgo = oracle.greens(I.expk, I.field, I.alpha, I.k)
+            assert relF(gs[a].cpu().numpy(), G) <= 1e-10
+            assert abs(ld[a].item() - ldo) <= 1e-12 * abs(ldo)
+    ctx.close()
