@@ -285,6 +285,23 @@ def test_single_stabilization_degrades():
     assert relF(G, Brute.to_np(Gmp)) < 1e-10
 
 
+def test_ill_conditioned_chain_k1_reference():
+    """The worst-conditioned chain of the mixed-size batch (L = 6, beta = 10,
+    |G| ~ 2e3): against 110-digit brute force the oracle at k = 1 is within
+    1e-11, while at k = 10 the scheme itself leaves a forward error of a few
+    1e-11 (naive products inside a block, Sec. 4.1).  The GPU comparison on
+    that batch uses the k = 1 oracle for this reason."""
+    insts = [I for I in wl.workload("hubbard_uneven_batch512", scale=0.125).instances
+             if I.label == "L6_b10_c13"]
+    assert len(insts) == 1
+    I = insts[0]
+    Gmp = Brute.to_np(Brute(I.expk, I.field, I.alpha, dps=80).greens()[0])
+    assert np.linalg.norm(Gmp) > 1e3
+    assert relF(oracle.greens(I.expk, I.field, I.alpha, 1)[0], Gmp) < 1e-11
+    e10 = relF(oracle.greens(I.expk, I.field, I.alpha, 10)[0], Gmp)
+    assert 1e-12 < e10 < 1e-10
+
+
 # --------------------------------------------------------------------------
 # identities
 
