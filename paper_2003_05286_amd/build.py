@@ -1,7 +1,8 @@
 """Build libsdq.so (the HIP library) in-tree for gfx950.
 
-Compiles the per-tile-count kernel instantiations in parallel with hipcc and
-links them with the dispatch and runtime objects into
+Compiles the per-tile-count kernel instantiations (n <= 128) and the gang
+kernels (n > 128) in parallel with hipcc and links them with the dispatch
+and runtime objects into
 paper_2003_05286_amd/libsdq.so.  Always recompiles.
 """
 from __future__ import annotations
@@ -53,6 +54,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         tasks.append((os.path.join(CSRC, "sdq_nt.hip"), os.path.join(BUILD, f"sdq_nt{nt}.o"),
                       [f"-DSDQ_NT={nt}"]))
     tasks.append((os.path.join(CSRC, "sdq_dispatch.hip"), os.path.join(BUILD, "sdq_dispatch.o"), []))
+    tasks.append((os.path.join(CSRC, "sdq_gang.hip"), os.path.join(BUILD, "sdq_gang.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_runtime.cpp"), os.path.join(BUILD, "sdq_runtime.o"), []))
     jobs = jobs or min(len(tasks), os.cpu_count() or 4, 16)
     # the largest instantiations first

@@ -1,0 +1,1093 @@
+// sdq_gang.hip -- chains with 128 < n <= 1024 on gfx950.
+//
+// An n x n FP64 matrix of such a chain no longer fits one CU (n = 256 is
+// 512 KiB, the whole register file), so a chain is owned by a gang of G
+// workgroups of 1024 threads.  Member g keeps the column slab
+// [g*w, (g+1)*w) of the working matrix in LDS (column-major, leading
+// dimension ldr = npad + 4); the geometry comes from gang_geom().  What the
+// members must share goes through a per-gang scratch area in HBM:
+//   * slice products W <- E diag(v) W (Sec. 4.1) are slab-local: each member
+//     multiplies its own columns on FP64 MFMA with E read from the swizzled,
+//     zero-padded copy in HBM (it stays in L2: all members and chains of one
+//     size read the same copy);
+//   * the column-pivoted Householder QR (Sec. 4.2.2) is distributed by
+//     columns.  At every step each member publishes its live column of
+//     largest downdated norm (rows below the step) with a pivot key; after
+//     one gang barrier every wave of every member reads the winning column
+//     and builds the same reflector from it (identical data, identical
+//     reduction order: bitwise-identical results), then applies it to its
+//     own live columns and downdates their norms.  Columns never move: the
+//     step at which a column was chosen is remembered instead;
+//   * R P^T and the reflectors are then written to HBM, and every later
+//     operation that needs whole rows (T update, Q formation, Q^T
+//     application, triangular solve, the time-displaced and gradient
+//     products) reads them from there.
+// Gang barriers are a monotonic counter in HBM with device-scope fences.
+// The launch is cooperative, so all members of every gang are resident; a
+// wait still gives up after a few seconds (abort flag, status SDQ_ERANGE)
+// instead of spinning forever.
+//
+// Paper passages: slice products and stage loop Sec. 4.1; pivoted QR and
+// UDT Sec. 4.2.2; equal-time inversion Sec. 5.1 (Loh's split, mirror form);
+// time-displaced inversion Sec. 6.1 (inv_sum_loh) and propagation Sec. 6;
+// gradient App. A.1 with the wrap G_{l+1} = B_l G_l B_l^{-1} of Sec. 6.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sdq_internal.h"
+
+namespace sdq {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = kGangThreads / 64;  // 16
+constexpr int kRL = kGangMaxN / 64;        // rows per lane in a column operation
+constexpr int kPairs = 5;                  // MFMA output tiles per wave in a slab product
+constexpr unsigned long long kSpinTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
+
+struct GLds {
+  double S[kGangSlab];       // column slab, [col][row]
+  double tau[kGangMaxN];     // reflector scalars; also a slice's exp(alpha f)
+  double beta[kGangMaxN];    // diag R of the last QR (D = |beta|)
+  int piv[kGangMaxN];        // piv[p] = global column chosen at step p
+  double vn1[kGangMaxW], vn2[kGangMaxW];
+  int posl[kGangMaxW];       // step at which a slab column was chosen; -1 live, -2 padding
+  unsigned long long wkey[kWaves];
+  double red[2 * kWaves];
+  unsigned vis[kGangMaxN / 32];
+  int ok;
+};
+
+// The workgroup's LDS block.  Declared at namespace scope (not passed by
+// reference) so that every access is compiled as an LDS access.
+__shared__ GLds L;
+
+// one workgroup's view of its gang
+struct GC {
+  GangGeom geo;
+  int n;        // matrix size of the current item
+  int g;        // member index
+  int c0;       // first global column of the slab
+  int t, w, l;  // thread, wave, lane
+  double* base; // per-gang scratch
+  unsigned* bar;
+  unsigned epoch;
+  bool ok;
+};
+
+__device__ __forceinline__ double* sc_R(const GC& c) { return c.base; }
+__device__ __forceinline__ double* sc_V(const GC& c) { return c.base + gang_mat(c.geo); }
+__device__ __forceinline__ double* sc_T(const GC& c) { return c.base + 2 * gang_mat(c.geo); }
+__device__ __forceinline__ double* sc_U(const GC& c) { return c.base + 3 * gang_mat(c.geo); }
+__device__ __forceinline__ double* sc_G(const GC& c, int b) { return c.base + (4 + b) * gang_mat(c.geo); }
+__device__ __forceinline__ double* sc_X(const GC& c) { return c.base + 6 * gang_mat(c.geo); }
+__device__ __forceinline__ double* sc_cand(const GC& c, int buf) {
+  return c.base + 7 * gang_mat(c.geo) + (int64_t)buf * c.geo.G * gang_cand_stride(c.geo);
+}
+
+// ---- wave reductions (every lane gets the same bits) -----------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long o = __shfl_xor(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ double pow2_scale(double x) {
+  if (!(x > 0.0) || !isfinite(x)) return 1.0;
+  return ldexp(1.0, -ilogb(x));
+}
+
+// Pivot key: the norm's bits with the 11 lowest mantissa bits replaced by
+// 2047 - column (largest norm wins; among norms equal to 2^-41 relative the
+// smallest column).  0 = no candidate.
+__device__ __forceinline__ unsigned long long pivot_key(double norm, int col) {
+  double x = norm >= 0.0 ? norm : 0.0;  // NaN -> 0
+  x = x < 1.0e300 ? x : 1.0e300;
+  return ((unsigned long long)__double_as_longlong(x) & ~0x7FFull) | (unsigned long long)(2047 - col);
+}
+__device__ __forceinline__ int key_col(unsigned long long k) { return 2047 - (int)(k & 0x7FF); }
+
+// ---- gang barrier ----------------------------------------------------------
+__device__ bool gang_sync(GC& c) {
+  __syncthreads();
+  c.epoch += 1;
+  if (c.t == 0) {
+    __threadfence();
+    const unsigned target = c.epoch * (unsigned)c.geo.G;
+    atomicAdd(&c.bar[0], 1u);
+    int good = 1;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      const unsigned v = __hip_atomic_load(&c.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= target) break;
+      if (__hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        good = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > kSpinTicks) {
+        atomicExch(&c.bar[1], 1u);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    L.ok = good;
+  }
+  __syncthreads();
+  const bool good = L.ok != 0;
+  c.ok = c.ok && good;
+  return good;
+}
+
+// ---- slab products -----------------------------------------------------------
+// S[:, slab] <- post(i) * sum_k A(i, k) pre(k) S[k, slab] on FP64 MFMA
+// 16x16x4.  A(ti, tk, r, l) returns the left operand entry
+// (16 ti + l%16, 16 tk + 4 r + l/16) for lane l.  Output tiles (ti, ct)
+// are spread over the 16 waves; ends with a barrier.
+template <class AF, class PRE, class POST>
+__device__ void slab_gemm(GC& c, AF A, PRE pre, POST post) {
+  const int nrt = c.geo.npad / 16, nct = c.geo.w / 16, np = nrt * nct, ldr = c.geo.ldr;
+  int ti[kPairs], ct[kPairs];
+  bool on[kPairs];
+  d4 acc[kPairs];
+#pragma unroll
+  for (int s = 0; s < kPairs; ++s) {
+    const int idx = c.w + kWaves * s;
+    on[s] = idx < np;
+    ct[s] = on[s] ? idx / nrt : 0;
+    ti[s] = on[s] ? idx - ct[s] * nrt : 0;
+    acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int lq = c.l >> 4, lc = c.l & 15;
+  if (on[0]) {
+    for (int tk = 0; tk < nrt; ++tk) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kk = 16 * tk + 4 * r + lq;
+        const double pk = pre(kk);
+        double a = 0.0;
+#pragma unroll
+        for (int s = 0; s < kPairs; ++s) {
+          if (!on[s]) continue;
+          if (s == 0 || ti[s] != ti[s - 1]) a = A(ti[s], tk, r, c.l);
+          const double b = L.S[(16 * ct[s] + lc) * ldr + kk] * pk;
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kPairs; ++s) {
+    if (!on[s]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ti[s] + lq + 4 * r;
+      L.S[(16 * ct[s] + lc) * ldr + row] = acc[s][r] * post(row);
+    }
+  }
+  __syncthreads();
+}
+
+struct One {
+  __device__ double operator()(int) const { return 1.0; }
+};
+
+// left operands
+struct ASwz {  // swizzled zero-padded copy (launch_swizzle order)
+  const double* e;
+  int nt;
+  __device__ double operator()(int ti, int tk, int r, int l) const {
+    return e[((int64_t)(ti * nt + tk) * 4 + r) * 64 + l];
+  }
+};
+struct AColMajor {  // A[i][k] = M[k*ld + i], buffer zero padded to ld x ld
+  const double* M;
+  int ld;
+  __device__ double operator()(int ti, int tk, int r, int l) const {
+    return M[(int64_t)(16 * tk + 4 * r + (l >> 4)) * ld + 16 * ti + (l & 15)];
+  }
+};
+// A[i][k] = M[i*n + k] * cs(k) (row-major n x n, identity if M is null)
+template <class CS>
+struct ARowMajor {
+  const double* M;
+  int n;
+  CS cs;
+  __device__ double operator()(int ti, int tk, int r, int l) const {
+    const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
+    if (i >= n || k >= n) return 0.0;
+    const double x = M ? M[(int64_t)i * n + k] : (i == k ? 1.0 : 0.0);
+    return x * cs(k);
+  }
+};
+// A[i][k] = M[k*n + i] (the transpose of a row-major n x n matrix)
+struct ARowMajorT {
+  const double* M;
+  int n;
+  __device__ double operator()(int ti, int tk, int r, int l) const {
+    const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
+    if (i >= n || k >= n) return 0.0;
+    return M ? M[(int64_t)k * n + i] : (i == k ? 1.0 : 0.0);
+  }
+};
+
+// ---- slab loads and stores ---------------------------------------------------
+// Slab loads and stores end with a barrier (their thread mapping differs
+// from that of the next writer of the slab).
+// S[cc][i] = f(i, gc) for every slab entry (zero outside n x n); row-wise so
+// that consecutive threads take consecutive columns of one row
+template <class F>
+__device__ void slab_fill_rows(GC& c, F f) {
+  const int w = c.geo.w, ldr = c.geo.ldr;
+  for (int idx = c.t; idx < c.geo.npad * w; idx += kGangThreads) {
+    const int i = idx / w, cc = idx - i * w, gc = c.c0 + cc;
+    L.S[cc * ldr + i] = (i < c.n && gc < c.n) ? f(i, gc) : 0.0;
+  }
+  __syncthreads();
+}
+// the same, column-wise (consecutive threads take consecutive rows)
+template <class F>
+__device__ void slab_fill_cols(GC& c, F f) {
+  const int np = c.geo.npad, ldr = c.geo.ldr;
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+    L.S[cc * ldr + i] = (i < c.n && gc < c.n) ? f(i, gc) : 0.0;
+  }
+  __syncthreads();
+}
+// dst[i*n + gc] = S[cc][i] for the leading n x n block
+__device__ void slab_store_rowmajor(GC& c, double* dst) {
+  const int w = c.geo.w, ldr = c.geo.ldr, n = c.n;
+  for (int idx = c.t; idx < n * w; idx += kGangThreads) {
+    const int i = idx / w, cc = idx - i * w, gc = c.c0 + cc;
+    if (gc < n) dst[(int64_t)i * n + gc] = L.S[cc * ldr + i];
+  }
+  __syncthreads();
+}
+// dst[piv[q]*n + gc] = S[cc][q]
+__device__ void slab_store_rowmajor_perm(GC& c, double* dst) {
+  const int w = c.geo.w, ldr = c.geo.ldr, n = c.n;
+  for (int idx = c.t; idx < n * w; idx += kGangThreads) {
+    const int q = idx / w, cc = idx - q * w, gc = c.c0 + cc;
+    int row = L.piv[q];
+    row = row < 0 ? 0 : (row >= n ? n - 1 : row);
+    if (gc < n) dst[(int64_t)row * n + gc] = L.S[cc * ldr + q];
+  }
+  __syncthreads();
+}
+// dst[gc*npad + i] = S[cc][i], whole padded slab
+__device__ void slab_store_colmajor(GC& c, double* dst) {
+  const int np = c.geo.npad, ldr = c.geo.ldr;
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np;
+    const int gc = c.c0 + cc;
+    if (gc < np) dst[(int64_t)gc * np + i] = L.S[cc * ldr + i];
+  }
+  __syncthreads();
+}
+__device__ void slab_identity(GC& c) {
+  slab_fill_cols(c, [](int i, int gc) { return i == gc ? 1.0 : 0.0; });
+}
+
+// ---- column-pivoted QR of the gang's matrix --------------------------------
+// Publish this member's best live column (rows p..n-1) and its key into
+// candidate buffer p & 1.
+__device__ void publish_candidate(GC& c, int p) {
+  unsigned long long best = 0;
+  for (int cc = c.w; cc < c.geo.w; cc += kWaves)
+    if (L.posl[cc] == -1) {
+      const unsigned long long k = pivot_key(L.vn1[cc], c.c0 + cc);
+      best = k > best ? k : best;
+    }
+  if (c.l == 0) L.wkey[c.w] = best;
+  __syncthreads();
+  if (c.w == 0) {
+    unsigned long long k = c.l < kWaves ? L.wkey[c.l] : 0ull;
+    k = wave_max_u64(k);
+    double* out = sc_cand(c, p & 1) + (int64_t)c.g * gang_cand_stride(c.geo);
+    if (k != 0ull) {
+      int cc = key_col(k) - c.c0;
+      cc = cc < 0 ? 0 : (cc >= c.geo.w ? c.geo.w - 1 : cc);
+      const double* col = L.S + cc * c.geo.ldr;
+      for (int i = p + c.l; i < c.n; i += 64) out[i] = col[i];
+    }
+    if (c.l == 0) *(unsigned long long*)(out + c.geo.npad) = k;
+  }
+}
+
+// scaled 2-norm of rows [lo, n) of one LDS column, by one wave
+__device__ double col_norm(const double* col, int lo, int n, int l) {
+  double am = 0.0;
+  for (int i = lo + l; i < n; i += 64) am = fmax(am, fabs(col[i]));
+  am = wave_max(am);
+  if (!(am > 0.0)) return 0.0;
+  const double sc = pow2_scale(am);
+  double ss = 0.0;
+  for (int i = lo + l; i < n; i += 64) {
+    const double x = col[i] * sc;
+    ss += x * x;
+  }
+  return sqrt(wave_sum(ss)) / sc;
+}
+
+// On return: L.tau / L.beta / L.piv hold the reflector scalars, diag R and
+// the pivot order; sc_R = R P^T (column gc = R column of the step at which gc
+// was chosen, rows above and on that step) and sc_V = the reflectors (column
+// gc = reflector of that step, rows below it, unit entry implied), both
+// column-major npad x npad, visible to the whole gang.
+__device__ void cpqr_gang(GC& c) {
+  const int n = c.n, ldr = c.geo.ldr, G = c.geo.G;
+  const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
+    const int gc = c.c0 + cc;
+    const double nrm = gc < n ? col_norm(L.S + cc * ldr, 0, n, c.l) : 0.0;
+    if (c.l == 0) {
+      L.vn1[cc] = nrm;
+      L.vn2[cc] = nrm;
+      L.posl[cc] = gc < n ? -1 : -2;
+    }
+  }
+  __syncthreads();
+  publish_candidate(c, 0);
+  gang_sync(c);
+  const int nrl = (n + 63) / 64;
+  for (int p = 0; p < n; ++p) {
+    const double* cb = sc_cand(c, p & 1);
+    unsigned long long key = 0ull;
+    if (c.l < G) key = *(const unsigned long long*)(cb + (int64_t)c.l * gang_cand_stride(c.geo) + c.geo.npad);
+    key = wave_max_u64(key);
+    int gw = key_col(key);
+    gw = gw < 0 ? 0 : (gw >= n ? n - 1 : gw);
+    const int owner = gw / c.geo.w;
+    const double* xs = cb + (int64_t)owner * gang_cand_stride(c.geo);
+    double x[kRL];
+    double am = 0.0, al = 0.0;
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      x[s] = (s < nrl && i >= p && i < n) ? xs[i] : 0.0;
+      if (i > p) am = fmax(am, fabs(x[s]));
+      if (i == p) al = x[s];
+    }
+    am = wave_max(am);
+    al = wave_sum(al);  // exactly the one nonzero term
+    double xnorm = 0.0;
+    if (am > 0.0) {
+      const double sc = pow2_scale(am);
+      double ss = 0.0;
+#pragma unroll
+      for (int s = 0; s < kRL; ++s) {
+        const int i = c.l + 64 * s;
+        if (i > p) {
+          const double y = x[s] * sc;
+          ss += y * y;
+        }
+      }
+      xnorm = sqrt(wave_sum(ss)) / sc;
+    }
+    double tau, beta, vsc;
+    if (xnorm == 0.0) {
+      tau = 0.0;
+      beta = al;
+      vsc = 0.0;
+    } else {
+      beta = -copysign(hypot(al, xnorm), al);
+      tau = (beta - al) / beta;
+      vsc = 1.0 / (al - beta);
+    }
+    double v[kRL];
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      v[s] = i > p ? x[s] * vsc : (i == p ? 1.0 : 0.0);
+    }
+    if (c.t == 0) {
+      L.tau[p] = tau;
+      L.beta[p] = beta;
+      L.piv[p] = gw;
+    }
+    for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
+      double* col = L.S + cc * ldr;
+      if (c.c0 + cc == gw) {
+#pragma unroll
+        for (int s = 0; s < kRL; ++s) {
+          const int i = c.l + 64 * s;
+          if (s < nrl && i >= p && i < n) col[i] = i == p ? beta : v[s];
+        }
+        if (c.l == 0) L.posl[cc] = p;
+        continue;
+      }
+      if (L.posl[cc] != -1) continue;
+      double y[kRL];
+#pragma unroll
+      for (int s = 0; s < kRL; ++s) {
+        const int i = c.l + 64 * s;
+        y[s] = (s < nrl && i >= p && i < n) ? col[i] : 0.0;
+      }
+      if (tau != 0.0) {
+        double d = 0.0;
+#pragma unroll
+        for (int s = 0; s < kRL; ++s) d += v[s] * y[s];
+        const double tv = tau * wave_sum(d);
+#pragma unroll
+        for (int s = 0; s < kRL; ++s) {
+          const int i = c.l + 64 * s;
+          if (s < nrl && i >= p && i < n) {
+            y[s] -= tv * v[s];
+            col[i] = y[s];
+          }
+        }
+      }
+      double rp = 0.0;
+#pragma unroll
+      for (int s = 0; s < kRL; ++s)
+        if (c.l + 64 * s == p) rp = y[s];
+      rp = wave_sum(rp);
+      double n1 = L.vn1[cc], n2 = L.vn2[cc];
+      if (n1 != 0.0) {
+        double tmp = fabs(rp) / n1;
+        tmp = fmax(0.0, (1.0 + tmp) * (1.0 - tmp));
+        const double q = n1 / n2;
+        if (tmp * q * q <= tol3z) {
+          double bm = 0.0;
+#pragma unroll
+          for (int s = 0; s < kRL; ++s)
+            if (c.l + 64 * s > p) bm = fmax(bm, fabs(y[s]));
+          bm = wave_max(bm);
+          double nn = 0.0;
+          if (bm > 0.0) {
+            const double sc = pow2_scale(bm);
+            double ss = 0.0;
+#pragma unroll
+            for (int s = 0; s < kRL; ++s)
+              if (c.l + 64 * s > p) {
+                const double z = y[s] * sc;
+                ss += z * z;
+              }
+            nn = sqrt(wave_sum(ss)) / sc;
+          }
+          n1 = nn;
+          n2 = nn;
+        } else {
+          n1 *= sqrt(tmp);
+        }
+      }
+      if (c.l == 0) {
+        L.vn1[cc] = n1;
+        L.vn2[cc] = n2;
+      }
+    }
+    if (p + 1 < n) {
+      publish_candidate(c, p + 1);
+      gang_sync(c);
+    }
+  }
+  __syncthreads();
+  // R P^T and the reflectors to HBM
+  {
+    const int np = c.geo.npad;
+    double* R = sc_R(c);
+    double* V = sc_V(c);
+    for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+      const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+      if (gc >= np) continue;
+      const int sc = gc < n ? L.posl[cc] : -1;
+      const double x = L.S[cc * ldr + i];
+      R[(int64_t)gc * np + i] = (gc < n && i <= sc) ? x : 0.0;
+      V[(int64_t)gc * np + i] = (gc < n && i > sc && i < n) ? x : 0.0;
+    }
+  }
+  gang_sync(c);
+}
+
+// Apply reflectors j = jlo .. jhi (ascending: Q^T, descending: Q) to the own
+// columns of the slab, one wave per column, reflector rows from sc_V.
+template <bool ASC>
+__device__ void apply_reflectors(GC& c, bool identity_cols) {
+  const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
+  const double* V = sc_V(c);
+  const int nrl = (n + 63) / 64;
+  for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
+    const int gc = c.c0 + cc;
+    if (gc >= n) continue;
+    double* col = L.S + cc * ldr;
+    double y[kRL];
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      y[s] = (s < nrl && i < n) ? col[i] : 0.0;
+    }
+    // Q e_gc needs reflectors j <= gc only (H_j fixes e_gc for j > gc)
+    const int jmax = identity_cols ? gc : n - 1;
+    for (int jj = 0; jj <= jmax; ++jj) {
+      const int j = ASC ? jj : jmax - jj;
+      const double tj = L.tau[j];
+      if (tj == 0.0) continue;
+      int pc = L.piv[j];
+      pc = pc < 0 ? 0 : (pc >= n ? n - 1 : pc);
+      const double* vc = V + (int64_t)pc * np;
+      double v[kRL];
+      double d = 0.0;
+#pragma unroll
+      for (int s = 0; s < kRL; ++s) {
+        const int i = c.l + 64 * s;
+        v[s] = (s < nrl && i > j && i < n) ? vc[i] : (i == j ? 1.0 : 0.0);
+        d += v[s] * y[s];
+      }
+      const double tv = tj * wave_sum(d);
+#pragma unroll
+      for (int s = 0; s < kRL; ++s) y[s] -= tv * v[s];
+    }
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      if (s < nrl && i < n) col[i] = y[s];
+    }
+  }
+  __syncthreads();
+}
+
+// S <- R^{-1} S (R upper triangular in pivot order: R[i][q] = sc_R[piv[q]][i]),
+// one wave per column.
+__device__ void back_subst(GC& c) {
+  const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
+  const double* R = sc_R(c);
+  const int nrl = (n + 63) / 64;
+  for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
+    const int gc = c.c0 + cc;
+    if (gc >= n) continue;
+    double* col = L.S + cc * ldr;
+    double y[kRL];
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      y[s] = (s < nrl && i < n) ? col[i] : 0.0;
+    }
+    for (int q = n - 1; q >= 0; --q) {
+      int pc = L.piv[q];
+      pc = pc < 0 ? 0 : (pc >= n ? n - 1 : pc);
+      const double* rc = R + (int64_t)pc * np;
+      double zq = 0.0;
+#pragma unroll
+      for (int s = 0; s < kRL; ++s)
+        if (c.l + 64 * s == q) zq = y[s];
+      const double xq = wave_sum(zq) / L.beta[q];
+#pragma unroll
+      for (int s = 0; s < kRL; ++s) {
+        const int i = c.l + 64 * s;
+        if (s < nrl && i < q) y[s] -= rc[i] * xq;
+        if (i == q) y[s] = xq;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kRL; ++s) {
+      const int i = c.l + 64 * s;
+      if (s < nrl && i < n) col[i] = y[s];
+    }
+  }
+  __syncthreads();
+}
+
+// sign of the permutation piv (thread 0; cycle walk over a bitmap in LDS)
+__device__ double perm_sign(GC& c) {
+  const int n = c.n;
+  for (int a = c.t; a < kGangMaxN / 32; a += kGangThreads) L.vis[a] = 0u;
+  __syncthreads();
+  if (c.t == 0) {
+    int cycles = 0;
+    for (int s = 0; s < n; ++s) {
+      if (L.vis[s >> 5] & (1u << (s & 31))) continue;
+      ++cycles;
+      int x = s;
+      for (int guard = 0; guard <= n; ++guard) {
+        if (L.vis[x >> 5] & (1u << (x & 31))) break;
+        L.vis[x >> 5] |= 1u << (x & 31);
+        int nx = L.piv[x];
+        x = nx < 0 ? 0 : (nx >= n ? n - 1 : nx);
+      }
+    }
+    L.red[0] = ((n - cycles) & 1) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  const double r = L.red[0];
+  __syncthreads();
+  return r;
+}
+
+// (-1)^(number of nontrivial reflectors) = det Q (wave reduction, every thread)
+__device__ double refl_sign(GC& c) {
+  double cnt = 0.0;
+  for (int j = c.l; j < c.n; j += 64) cnt += L.tau[j] != 0.0 ? 1.0 : 0.0;
+  cnt = wave_sum(cnt);
+  return (((long long)cnt) & 1) ? -1.0 : 1.0;
+}
+
+// ---- stage loop ----------------------------------------------------------------
+__device__ void load_slice_scale(GC& c, const Inst& I, int q) {
+  const double* f = I.field + (int64_t)(q - 1) * I.n;
+  for (int i = c.t; i < c.geo.npad; i += kGangThreads) L.tau[i] = i < c.n ? exp(I.alpha * f[i]) : 0.0;
+  __syncthreads();
+}
+
+// Stabilized chain (Sec. 4.1) with the UDT of Sec. 4.2.2 every k slices,
+// forward over B_1..B_m or, with SW_ADJ, backward over B_m^T..B_1^T; stage
+// storage as in the single-workgroup kernels (U | T | D | sgn det U).
+__device__ void sweep_gang(GC& c, const Inst& I, int flags) {
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad;
+  const bool adj = (flags & SW_ADJ) != 0;
+  const int64_t sd = stage_doubles(n);
+  double* Tg = sc_T(c);  // T of the chain, row-major n x n (own columns)
+  slab_identity(c);
+  for (int i = c.t; i < np; i += kGangThreads) L.beta[i] = 1.0;
+  __syncthreads();
+  slab_store_rowmajor(c, Tg);
+  double sgn_u = 1.0;
+  const ASwz aop{adj ? I.eswt : I.esw, np / 16};
+  auto copy_t = [&](double* dst) {
+    for (int idx = c.t; idx < n * c.geo.w; idx += kGangThreads) {
+      const int i = idx / c.geo.w, gc = c.c0 + (idx - i * c.geo.w);
+      if (gc < n) dst[(int64_t)i * n + gc] = Tg[(int64_t)i * n + gc];
+    }
+  };
+  for (int s = 0; s < nb; ++s) {
+    const int b = adj ? nb - 1 - s : s;
+    const int q0 = b * k + 1, q1 = (b + 1) * k < m ? (b + 1) * k : m;
+    // U D (column scale), then the block of slices
+    for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+      const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+      if (gc < n) L.S[cc * c.geo.ldr + i] *= fabs(L.beta[gc]);
+    }
+    __syncthreads();
+    for (int qq = 0; qq <= q1 - q0; ++qq) {
+      const int q = adj ? q1 - qq : q0 + qq;
+      load_slice_scale(c, I, q);
+      if (!adj)
+        slab_gemm(c, aop, [&](int kk) { return L.tau[kk]; }, One{});
+      else
+        slab_gemm(c, aop, One{}, [&](int row) { return L.tau[row]; });
+    }
+    cpqr_gang(c);
+    // T <- D^{-1} R P^T T with D = |diag R|
+    slab_fill_rows(c, [&](int i, int gc) { return Tg[(int64_t)i * n + gc]; });
+    __syncthreads();
+    slab_gemm(c, AColMajor{sc_R(c), np}, One{},
+              [&](int row) { return row < n ? 1.0 / fabs(L.beta[row]) : 0.0; });
+    slab_store_rowmajor(c, Tg);
+    sgn_u = refl_sign(c);
+    // U <- Q
+    slab_identity(c);
+    __syncthreads();
+    apply_reflectors<false>(c, true);
+    double* dst = nullptr;
+    if (flags & SW_STORE) dst = adj ? (I.cka + (int64_t)b * sd) : (I.ckf + (int64_t)s * sd);
+    else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
+    if (dst) {
+      slab_store_rowmajor(c, dst);
+      copy_t(dst + (int64_t)n * n);
+      if (c.g == 0) {
+        for (int i = c.t; i < n; i += kGangThreads) dst[2 * (int64_t)n * n + i] = fabs(L.beta[i]);
+        if (c.t == 0) dst[2 * (int64_t)n * n + n] = sgn_u;
+      }
+    }
+  }
+  int bad = 0;
+  for (int i = c.t; i < n; i += kGangThreads) {
+    const double d = fabs(L.beta[i]);
+    if (!isfinite(d) || !(d > 0.0)) bad = 1;
+  }
+  if (flags & SW_FINAL) {
+    slab_store_rowmajor(c, I.u_out);
+    copy_t(I.t_out);
+    if (c.g == 0)
+      for (int i = c.t; i < n; i += kGangThreads) I.d_out[i] = fabs(L.beta[i]);
+  }
+  if ((__any(bad) || !c.ok) && c.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+// Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1,
+// mirror form): M = Dp^{-1} U^T + Dm T, G = M^{-1} Dp^{-1} U^T,
+// det(1 + U D T) = det U prod(Dp) det M.
+__device__ void equal_gang(GC& c, const Inst& I) {
+  const int n = I.n;
+  const double* U = I.fin;
+  const double* T = I.fin + (int64_t)n * n;
+  const double* D = I.fin + 2 * (int64_t)n * n;
+  const double sgn_u = I.fin[2 * (int64_t)n * n + n];
+  auto dp = [&](int i) { const double d = D[i]; return d > 1.0 ? d : 1.0; };
+  auto dm = [&](int i) { const double d = D[i]; return d < 1.0 ? d : 1.0; };
+  slab_fill_rows(c, [&](int i, int gc) { return dm(i) * T[(int64_t)i * n + gc]; });
+  __syncthreads();
+  for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / c.geo.npad, i = idx - cc * c.geo.npad, gc = c.c0 + cc;
+    if (i < n && gc < n) L.S[cc * c.geo.ldr + i] += U[(int64_t)gc * n + i] / dp(i);
+  }
+  __syncthreads();
+  cpqr_gang(c);
+  slab_fill_cols(c, [&](int i, int gc) { return U[(int64_t)gc * n + i] / dp(i); });
+  __syncthreads();
+  apply_reflectors<true>(c, false);
+  back_subst(c);
+  int bad = 0;
+  for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / c.geo.npad, i = idx - cc * c.geo.npad;
+    if (i < n && c.c0 + cc < n && !isfinite(L.S[cc * c.geo.ldr + i])) bad = 1;
+  }
+  if (I.g) slab_store_rowmajor_perm(c, I.g);
+  const double sp = perm_sign(c);
+  if (c.g == 0 && c.w == 0) {
+    double ls = 0.0, ng = 0.0;
+    for (int i = c.l; i < n; i += 64) {
+      const double d = D[i];
+      if (!isfinite(d) || !(d > 0.0)) bad = 1;
+      ls += log(dp(i)) + log(fabs(L.beta[i]));
+      ng += L.beta[i] < 0.0 ? 1.0 : 0.0;
+    }
+    ls = wave_sum(ls);
+    ng = wave_sum(ng);
+    const double sq = refl_sign(c);
+    if (!isfinite(ls)) bad = 1;
+    if (c.l == 0) {
+      if (I.logdet) *I.logdet = ls;
+      if (I.sign) *I.sign = sgn_u * sq * sp * ((((long long)ng) & 1) ? -1.0 : 1.0);
+    }
+  }
+  if ((__any(bad) || !c.ok) && c.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+// Time-displaced G(tau_j, 0) from F[j] = U1 D1 T1 and A[j] = U2 D2 T2
+// (Sec. 6.1 inv_sum_loh, same algebra as the single-workgroup kernel):
+//   Mid = D_Lm (U1^T U2) D_Rp^{-1} + D_Lp^{-1} (T1 T2^T) D_Rm,
+//   G(tau,0) = U2 D_Rp^{-1} Mid^{-1} D_Lp^{-1} T1,
+// with D_L = D1^{-1}, D_R = D2; then B_l ... G(tau_j, 0) for the requested
+// l of the block (Sec. 6).
+__device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
+                           const int32_t* l_list) {
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad;
+  const int64_t sd = stage_doubles(n);
+  const double* F = j > 0 ? I.ckf + (int64_t)(j - 1) * sd : nullptr;
+  const double* A = j < nb ? I.cka + (int64_t)j * sd : nullptr;
+  const double* U1 = F;
+  const double* T1 = F ? F + (int64_t)n * n : nullptr;
+  const double* D1 = F ? F + 2 * (int64_t)n * n : nullptr;
+  const double* U2 = A;
+  const double* T2 = A ? A + (int64_t)n * n : nullptr;
+  const double* D2 = A ? A + 2 * (int64_t)n * n : nullptr;
+  auto d1 = [&](int i) { return D1 ? D1[i] : 1.0; };
+  auto d2 = [&](int i) { return D2 ? D2[i] : 1.0; };
+  double* Xg = sc_X(c);
+  // P2 = T1 T2^T (slab columns), kept in HBM while P1 = U1^T U2 is formed
+  slab_fill_cols(c, [&](int i, int gc) { return T2 ? T2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  __syncthreads();
+  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, One{});
+  slab_store_colmajor(c, Xg);
+  __syncthreads();
+  slab_fill_rows(c, [&](int i, int gc) { return U2 ? U2[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0); });
+  __syncthreads();
+  slab_gemm(c, ARowMajorT{U1, n}, One{}, One{});
+  // Mid
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+    if (i >= n || gc >= n) continue;
+    const double a = d1(i), b = d2(gc);
+    const double lm = 1.0 / (a > 1.0 ? a : 1.0);   // D_Lm
+    const double lpi = a < 1.0 ? a : 1.0;           // D_Lp^{-1}
+    const double rpi = 1.0 / (b > 1.0 ? b : 1.0);  // D_Rp^{-1}
+    const double rm = b < 1.0 ? b : 1.0;            // D_Rm
+    double* e = &L.S[cc * c.geo.ldr + i];
+    *e = lm * (*e) * rpi + lpi * Xg[(int64_t)gc * np + i] * rm;
+  }
+  __syncthreads();
+  cpqr_gang(c);
+  // Y = D_Lp^{-1} T1 -> Q^T Y -> R^{-1} (pivot order)
+  slab_fill_rows(c, [&](int i, int gc) {
+    const double a = d1(i);
+    return (T1 ? T1[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0)) * (a < 1.0 ? a : 1.0);
+  });
+  __syncthreads();
+  apply_reflectors<true>(c, false);
+  back_subst(c);
+  // undo the pivot order through HBM: X[piv[q]][:] = Z[q][:]
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, q = idx - cc * np, gc = c.c0 + cc;
+    if (gc >= np) continue;
+    if (q < n) {
+      int row = L.piv[q];
+      row = row < 0 ? 0 : (row >= n ? n - 1 : row);
+      Xg[(int64_t)gc * np + row] = gc < n ? L.S[cc * c.geo.ldr + q] : 0.0;
+    } else {
+      Xg[(int64_t)gc * np + q] = 0.0;
+    }
+  }
+  __syncthreads();
+  slab_fill_cols(c, [&](int i, int gc) { return Xg[(int64_t)gc * np + i]; });
+  __syncthreads();
+  // G = (U2 D_Rp^{-1}) X
+  struct RP {
+    const double* D2;
+    __device__ double operator()(int kk) const {
+      const double b = D2 ? D2[kk] : 1.0;
+      return 1.0 / (b > 1.0 ? b : 1.0);
+    }
+  };
+  slab_gemm(c, ARowMajor<RP>{U2, n, RP{D2}}, One{}, One{});
+  int bad = 0;
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np;
+    if (i < n && c.c0 + cc < n && !isfinite(L.S[cc * c.geo.ldr + i])) bad = 1;
+  }
+  const int tj = j * k < m ? j * k : m;
+  int lc = tj;
+  const ASwz aop{I.esw, np / 16};
+  for (int idx = ilo; idx < ihi; ++idx) {
+    const int l = l_list[idx];
+    for (int q = lc + 1; q <= l; ++q) {
+      load_slice_scale(c, I, q);
+      slab_gemm(c, aop, [&](int kk) { return L.tau[kk]; }, One{});
+    }
+    lc = l;
+    slab_store_rowmajor(c, I.gt + (int64_t)idx * n * n);
+  }
+  if ((__any(bad) || !c.ok) && c.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+// Gradient rows of the slices j*k+1 .. min((j+1)k, m) (App. A.1):
+//   G_{jk+1} = [1 + U1 (D1 (T1 T2^T) D2) U2^T]^{-1}; udt(D1 T1 T2^T D2) = u d t,
+//   U = U1 u, T = t U2^T, then the equal-time inversion (Sec. 5.1), and
+//   G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar,  grad[l-1][i] = alpha (1 - G_l)_ii.
+__device__ void grad_gang(GC& c, const Inst& I, int j) {
+  const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad, ldr = c.geo.ldr;
+  const int64_t sd = stage_doubles(n);
+  const double* F = j > 0 ? I.ckf + (int64_t)(j - 1) * sd : nullptr;
+  const double* A = j < nb ? I.cka + (int64_t)j * sd : nullptr;
+  const double* U1 = F;
+  const double* T1 = F ? F + (int64_t)n * n : nullptr;
+  const double* D1 = F ? F + 2 * (int64_t)n * n : nullptr;
+  const double* U2 = A;
+  const double* T2 = A ? A + (int64_t)n * n : nullptr;
+  const double* D2 = A ? A + 2 * (int64_t)n * n : nullptr;
+  double* Ug = sc_U(c);
+  double* Tg = sc_T(c);
+  // D1 (T1 T2^T) D2
+  slab_fill_cols(c, [&](int i, int gc) { return T2 ? T2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  __syncthreads();
+  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, [&](int row) { return D1 && row < n ? D1[row] : 1.0; });
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+    if (gc < n && D2) L.S[cc * ldr + i] *= D2[gc];
+  }
+  __syncthreads();
+  cpqr_gang(c);
+  // T = d^{-1} (R P^T) U2^T  (slab columns), to HBM
+  slab_fill_cols(c, [&](int i, int gc) { return U2 ? U2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  __syncthreads();
+  slab_gemm(c, AColMajor{sc_R(c), np}, One{},
+            [&](int row) { return row < n ? 1.0 / fabs(L.beta[row]) : 0.0; });
+  slab_store_colmajor(c, Tg);
+  // U = U1 u
+  slab_identity(c);
+  __syncthreads();
+  apply_reflectors<false>(c, true);
+  slab_gemm(c, ARowMajor<One>{U1, n, One{}}, One{}, One{});
+  slab_store_colmajor(c, Ug);
+  // D of the combined factorization: |beta| (kept in L.red-free storage: HBM)
+  double* Dg = sc_X(c);
+  if (c.g == 0)
+    for (int i = c.t; i < n; i += kGangThreads) Dg[i] = fabs(L.beta[i]);
+  gang_sync(c);
+  // M = Dp^{-1} U^T + Dm T
+  auto dp = [&](int i) { const double d = Dg[i]; return d > 1.0 ? d : 1.0; };
+  auto dm = [&](int i) { const double d = Dg[i]; return d < 1.0 ? d : 1.0; };
+  slab_fill_rows(c, [&](int i, int gc) { return Ug[(int64_t)i * np + gc] / dp(i); });
+  __syncthreads();
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
+    if (i < n && gc < n) L.S[cc * ldr + i] += dm(i) * Tg[(int64_t)gc * np + i];
+  }
+  __syncthreads();
+  cpqr_gang(c);
+  slab_fill_rows(c, [&](int i, int gc) { return Ug[(int64_t)i * np + gc] / dp(i); });
+  __syncthreads();
+  apply_reflectors<true>(c, false);
+  back_subst(c);
+  // G_{jk+1} = P X into HBM buffer 0 (column-major, rows un-permuted)
+  double* Gb[2] = {sc_G(c, 0), sc_G(c, 1)};
+  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
+    const int cc = idx / np, q = idx - cc * np, gc = c.c0 + cc;
+    if (gc >= np) continue;
+    if (q < n) {
+      int row = L.piv[q];
+      row = row < 0 ? 0 : (row >= n ? n - 1 : row);
+      Gb[0][(int64_t)gc * np + row] = gc < n ? L.S[cc * ldr + q] : 0.0;
+    } else {
+      Gb[0][(int64_t)gc * np + q] = 0.0;
+    }
+  }
+  gang_sync(c);
+  const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
+  bool bad = false;
+  for (int gc = c.c0 + c.t; gc < c.c0 + c.geo.w && gc < n; gc += kGangThreads) {
+    const double gii = Gb[0][(int64_t)gc * np + gc];
+    bad |= !isfinite(gii);
+    I.grad[(int64_t)(l0 - 1) * n + gc] = I.alpha * (1.0 - gii);
+  }
+  const ASwz aop{I.esw, np / 16};
+  int cur = 0;
+  for (int l = l0; l < l1; ++l) {
+    // slab <- diag(1/v_l) Ebar [:, slab]; G_l diag(1/v_l) Ebar; E diag(v_l) (...)
+    load_slice_scale(c, I, l);
+    slab_fill_rows(c, [&](int i, int gc) { return I.expk_inv[(int64_t)i * n + gc] / L.tau[i]; });
+    __syncthreads();
+    slab_gemm(c, AColMajor{Gb[cur], np}, One{}, One{});
+    slab_gemm(c, aop, [&](int kk) { return L.tau[kk]; }, One{});
+    slab_store_colmajor(c, Gb[cur ^ 1]);
+    for (int gc = c.c0 + c.t; gc < c.c0 + c.geo.w && gc < n; gc += kGangThreads) {
+      const double gii = L.S[(gc - c.c0) * ldr + gc];
+      bad |= !isfinite(gii);
+      I.grad[(int64_t)l * n + gc] = I.alpha * (1.0 - gii);
+    }
+    cur ^= 1;
+    gang_sync(c);
+  }
+  if ((__any(bad) || !c.ok) && c.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  __syncthreads();
+}
+
+// plain UDT (Sec. 4.2.2) of one n x n row-major matrix
+__device__ void udt_gang(GC& c, const double* w, double* u, double* d, double* t) {
+  const int n = c.n, np = c.geo.npad;
+  slab_fill_rows(c, [&](int i, int gc) { return w[(int64_t)i * n + gc]; });
+  __syncthreads();
+  cpqr_gang(c);
+  // T = D^{-1} R P^T
+  slab_fill_cols(c, [&](int i, int gc) { return sc_R(c)[(int64_t)gc * np + i] / fabs(L.beta[i]); });
+  __syncthreads();
+  slab_store_rowmajor(c, t);
+  __syncthreads();
+  slab_identity(c);
+  __syncthreads();
+  apply_reflectors<false>(c, true);
+  slab_store_rowmajor(c, u);
+  if (c.g == 0)
+    for (int i = c.t; i < n; i += kGangThreads) d[i] = fabs(L.beta[i]);
+  __syncthreads();
+}
+
+__device__ GC gang_ctx(const GangArgs& a) {
+  GC c;
+  c.geo = gang_geom(a.nt);
+  const int gang = blockIdx.x / c.geo.G;
+  c.g = blockIdx.x - gang * c.geo.G;
+  c.c0 = c.g * c.geo.w;
+  c.t = threadIdx.x;
+  c.w = threadIdx.x >> 6;
+  c.l = threadIdx.x & 63;
+  c.base = a.scratch + (int64_t)gang * gang_doubles(c.geo);
+  c.bar = a.bars + (int64_t)gang * kGangBarWords;
+  c.epoch = 0;
+  c.ok = true;
+  c.n = 0;
+  return c;
+}
+
+__global__ __launch_bounds__(kGangThreads, 1) void k_gang_sweep(const Inst* __restrict__ insts,
+                                                                 const SweepItem* __restrict__ items,
+                                                                 int count, GangArgs a) {
+  GC c = gang_ctx(a);
+  const int gang = blockIdx.x / c.geo.G;
+  for (int it = gang; it < count; it += a.ngangs) {
+    const SweepItem wi = items[it];
+    const Inst I = insts[wi.inst];
+    c.n = I.n;
+    sweep_gang(c, I, wi.flags);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kGangThreads, 1) void k_gang_pair(const Inst* __restrict__ insts,
+                                                                const PairItem* __restrict__ items,
+                                                                int count, const int32_t* __restrict__ l_list,
+                                                                GangArgs a) {
+  GC c = gang_ctx(a);
+  const int gang = blockIdx.x / c.geo.G;
+  for (int it = gang; it < count; it += a.ngangs) {
+    const PairItem wi = items[it];
+    const Inst I = insts[wi.inst];
+    c.n = I.n;
+    if (MODE == PAIR_EQUAL) equal_gang(c, I);
+    else if (MODE == PAIR_TDISP) tdisp_gang(c, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else grad_gang(c, I, wi.j);
+  }
+}
+
+__global__ __launch_bounds__(kGangThreads, 1) void k_gang_udt(int n, int count, const double* w, double* u,
+                                                               double* d, double* t, GangArgs a) {
+  GC c = gang_ctx(a);
+  c.n = n;
+  const int gang = blockIdx.x / c.geo.G;
+  for (int it = gang; it < count; it += a.ngangs) {
+    const int64_t off = (int64_t)it * n * n;
+    udt_gang(c, w + off, u + off, d + (int64_t)it * n, t + off);
+  }
+}
+
+template <class K, class... Args>
+hipError_t coop_launch(K kern, GangArgs a, hipStream_t s, Args... args) {
+  const GangGeom g = gang_geom(a.nt);
+  if (g.G == 0 || a.ngangs < 1) return hipErrorInvalidValue;
+  void* ptrs[] = {(void*)&args..., (void*)&a};
+  return hipLaunchCooperativeKernel((const void*)kern, dim3(a.ngangs * g.G), dim3(kGangThreads), ptrs, 0, s);
+}
+
+}  // namespace
+
+hipError_t gang_capacity(int nt, int num_cu, int* ngangs) {
+  const GangGeom g = gang_geom(nt);
+  if (g.G == 0) return hipErrorInvalidValue;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gang_pair<PAIR_TDISP>,
+                                                              kGangThreads, 0);
+  if (e != hipSuccess) return e;
+  int per_cu2 = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_gang_sweep, kGangThreads, 0);
+  if (e != hipSuccess) return e;
+  per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
+  *ngangs = per_cu * num_cu / g.G;
+  return hipSuccess;
+}
+
+hipError_t launch_gang_sweep(const Inst* inst, const SweepItem* items, int count, GangArgs a,
+                             hipStream_t s) {
+  return coop_launch(k_gang_sweep, a, s, inst, items, count);
+}
+
+hipError_t launch_gang_pair(int mode, const Inst* inst, const PairItem* items, int count,
+                            const int32_t* l_list, GangArgs a, hipStream_t s) {
+  if (mode == PAIR_EQUAL) return coop_launch(k_gang_pair<PAIR_EQUAL>, a, s, inst, items, count, l_list);
+  if (mode == PAIR_TDISP) return coop_launch(k_gang_pair<PAIR_TDISP>, a, s, inst, items, count, l_list);
+  return coop_launch(k_gang_pair<PAIR_GRAD>, a, s, inst, items, count, l_list);
+}
+
+hipError_t launch_gang_udt(int n, int count, const double* w, double* u, double* d, double* t,
+                           GangArgs a, hipStream_t s) {
+  return coop_launch(k_gang_udt, a, s, n, count, w, u, d, t);
+}
+
+}  // namespace sdq

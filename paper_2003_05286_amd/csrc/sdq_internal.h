@@ -99,4 +99,62 @@ hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, doub
 
 enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2 };
 
+// ---- chains with n > 128: gang kernels (sdq_gang.hip) --------------------
+// A chain is owned by a gang of G workgroups of kGangThreads threads; member
+// g keeps columns [g*w, (g+1)*w) of the working matrix in LDS, column-major
+// with leading dimension ldr.  Gangs exchange pivot candidates and operands
+// through a per-gang scratch area in HBM and synchronize with a counter.
+constexpr int kGangMaxN = 1024;
+constexpr int kGangThreads = 1024;
+constexpr int kGangSlab = 16640;  // doubles of the LDS column slab
+constexpr int kGangMaxW = 128;
+constexpr int kGangBarWords = 32;  // uint32 words per gang (counter, abort flag)
+
+struct GangGeom {
+  int npad;  // 16 * ceil(n / 16)
+  int G;     // workgroups per chain
+  int w;     // columns per workgroup (multiple of 16)
+  int ldr;   // LDS column stride
+};
+
+__host__ __device__ inline GangGeom gang_geom(int nt) {
+  GangGeom g;
+  g.npad = 16 * nt;
+  g.ldr = g.npad + 4;
+  g.G = 0;
+  g.w = 0;
+  for (int G = 2; G <= 64; ++G) {
+    const int w = 16 * (((g.npad + G - 1) / G + 15) / 16);
+    if (w <= kGangMaxW && (long long)w * g.ldr <= kGangSlab) {
+      g.G = G;
+      g.w = w;
+      break;
+    }
+  }
+  return g;
+}
+
+// per-gang scratch (doubles): R, V, T, U, two G buffers, X, candidates
+__host__ __device__ inline int64_t gang_mat(const GangGeom& g) { return (int64_t)g.npad * g.npad; }
+__host__ __device__ inline int64_t gang_cand_stride(const GangGeom& g) { return g.npad + 8; }
+__host__ __device__ inline int64_t gang_doubles(const GangGeom& g) {
+  return 7 * gang_mat(g) + 2 * g.G * gang_cand_stride(g) + 64;
+}
+
+struct GangArgs {
+  double* scratch;   // ngangs * gang_doubles(geo)
+  unsigned* bars;    // ngangs * kGangBarWords, zero at launch
+  int ngangs;
+  int nt;
+};
+
+hipError_t launch_gang_sweep(const Inst* inst, const SweepItem* items, int count, GangArgs a,
+                             hipStream_t s);
+hipError_t launch_gang_pair(int mode, const Inst* inst, const PairItem* items, int count,
+                            const int32_t* l_list, GangArgs a, hipStream_t s);
+hipError_t launch_gang_udt(int n, int count, const double* w, double* u, double* d, double* t,
+                           GangArgs a, hipStream_t s);
+// largest number of gangs of tile count nt that can be resident at once
+hipError_t gang_capacity(int nt, int num_cu, int* ngangs);
+
 }  // namespace sdq

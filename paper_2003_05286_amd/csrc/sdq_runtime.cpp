@@ -72,6 +72,8 @@ struct sdq_ctx {
   std::string err;
   int num_cu = 256;
   DevBuf d_upload, d_ck, d_swz, d_fin;
+  DevBuf d_gang;  // per-gang scratch of the n > 128 kernels (bars first)
+  std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   void* h_stage = nullptr;
   size_t h_cap = 0;
   hipEvent_t stage_ev = nullptr;
@@ -156,8 +158,8 @@ sdq_status validate(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, bool 
       snprintf(buf, sizeof buf, "instance %d: n = %d < 1", i, I.n);
       return fail(ctx, SDQ_EINVAL, buf);
     }
-    if (I.n > 16 * sdq::kMaxNT) {
-      snprintf(buf, sizeof buf, "instance %d: n = %d > %d is not supported", i, I.n, 16 * sdq::kMaxNT);
+    if (I.n > sdq::kGangMaxN) {
+      snprintf(buf, sizeof buf, "instance %d: n = %d > %d is not supported", i, I.n, sdq::kGangMaxN);
       return fail(ctx, SDQ_EUNSUPPORTED, buf);
     }
     if (I.m < 1 || I.k < 1 || I.k > I.m) {
@@ -227,9 +229,25 @@ const sdq::KernelInfo& info(sdq_ctx* ctx, int kind, int nt, int variant) {
   return it->second;
 }
 
+bool is_gang(int nt) { return nt > sdq::kMaxNT; }
+
+// gangs of tile count nt that fit the device at once (cached)
+int gang_slots(sdq_ctx* ctx, int nt) {
+  auto it = ctx->gang_cap.find(nt);
+  if (it != ctx->gang_cap.end()) return it->second;
+  int g = 0;
+  if (sdq::gang_capacity(nt, ctx->num_cu, &g) != hipSuccess) {
+    (void)hipGetLastError();
+    g = 0;
+  }
+  ctx->gang_cap[nt] = g;
+  return g;
+}
+
 int grid_for(sdq_ctx* ctx, int kind, int nt, int variant, int count) {
+  if (is_gang(nt)) return std::max(1, std::min(count, gang_slots(ctx, nt)));
   int per_cu = info(ctx, kind, nt, variant).blocks_per_cu;
-  if (kind == sdq::KK_SWEEP && ctx->tune[nt].blocks_per_cu > 0)
+  if (kind == sdq::KK_SWEEP && nt <= sdq::kMaxNT && ctx->tune[nt].blocks_per_cu > 0)
     per_cu = std::min(per_cu, ctx->tune[nt].blocks_per_cu);
   const long long g = (long long)per_cu * ctx->num_cu;
   return (int)std::max(1LL, std::min<long long>(count, g));
@@ -305,6 +323,7 @@ struct LaunchRec {
 };
 
 struct Built {
+  bool gang = false;  // has launches of the n > 128 kernels
   std::vector<char> image;
   std::vector<LaunchRec> launches;
   std::vector<SwzJob> swz;
@@ -342,11 +361,14 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   if (!P.llist.empty()) memcpy(h + o_ll, P.llist.data(), P.llist.size() * sizeof(int32_t));
   B.o_inst = o_inst;
   B.o_ll = o_ll;
+  for (const auto& r : P.sweep_ranges) B.gang |= is_gang(r.nt);
+  for (int md = 0; md < sdq::kPairModes; ++md)
+    for (const auto& r : P.pair_ranges[md]) B.gang |= is_gang(r.nt);
   B.status = status;
   B.count = count;
   int qi = 0;
   for (const auto& r : P.sweep_ranges) {
-    const int variant = ctx->tune[r.nt].variant;
+    const int variant = is_gang(r.nt) ? 0 : ctx->tune[r.nt].variant;
     const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
@@ -361,6 +383,36 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
     }
   }
   return SDQ_OK;
+}
+
+// bytes of gang scratch a launch needs: barrier words first (256-byte
+// aligned), then one scratch area per gang
+size_t gang_bars_bytes(int ngangs) {
+  return ((size_t)ngangs * sdq::kGangBarWords * sizeof(unsigned) + 255) & ~(size_t)255;
+}
+size_t gang_bytes(int nt, int ngangs) {
+  const sdq::GangGeom g = sdq::gang_geom(nt);
+  return gang_bars_bytes(ngangs) + (size_t)ngangs * (size_t)sdq::gang_doubles(g) * sizeof(double);
+}
+size_t gang_need(const Built& B) {
+  size_t need = 0;
+  for (const LaunchRec& L : B.launches)
+    if (is_gang(L.nt)) need = std::max(need, gang_bytes(L.nt, L.grid));
+  return need;
+}
+
+hipError_t launch_gang_rec(sdq_ctx* ctx, const LaunchRec& L, const Inst* d_inst, const char* d,
+                           const int32_t* d_ll, hipStream_t s) {
+  sdq::GangArgs a;
+  a.bars = (unsigned*)ctx->d_gang.p;
+  a.scratch = (double*)((char*)ctx->d_gang.p + gang_bars_bytes(L.grid));
+  a.ngangs = L.grid;
+  a.nt = L.nt;
+  hipError_t e = sdq::launch_fill_i32((int32_t*)a.bars, L.grid * sdq::kGangBarWords, 0, s);
+  if (e != hipSuccess) return e;
+  if (L.kind == sdq::KK_SWEEP)
+    return sdq::launch_gang_sweep(d_inst, (const SweepItem*)(d + L.items_off), L.count, a, s);
+  return sdq::launch_gang_pair(L.mode, d_inst, (const PairItem*)(d + L.items_off), L.count, d_ll, a, s);
 }
 
 // Enqueue a built batch on stream s: upload h_src -> d, reset status, build
@@ -381,6 +433,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
     auto go = [&]() -> hipError_t {
+      if (is_gang(L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, s);
       if (L.kind == sdq::KK_SWEEP)
         return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
                                  q, L.grid, s);
@@ -420,7 +473,13 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   Built B;
   sdq_status st = build_plan(ctx, P, status, count, B);
   if (st) return st;
-  if (ctx->graphs) {
+  if (B.gang) {
+    const size_t need = gang_need(B);
+    hipError_t e = grow(ctx->d_gang, need);
+    if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "gang scratch: " + std::string(hipGetErrorString(e)));
+  }
+  // cooperative launches (n > 128) are not captured: such batches run directly
+  if (ctx->graphs && !B.gang) {
     std::vector<char> key = graph_key(B);
     sdq_ctx::GraphEntry* hit = nullptr;
     for (auto& g : ctx->graph_cache)
@@ -576,6 +635,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_ck.p) (void)hipFree(ctx->d_ck.p);
   if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
   if (ctx->d_fin.p) (void)hipFree(ctx->d_fin.p);
+  if (ctx->d_gang.p) (void)hipFree(ctx->d_gang.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
@@ -813,12 +873,27 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
                    double* t) {
   if (!ctx) return SDQ_EINVAL;
   if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
-  if (n > 16 * sdq::kMaxNT) return fail(ctx, SDQ_EUNSUPPORTED, "n > 128 is not supported");
+  if (n > sdq::kGangMaxN) return fail(ctx, SDQ_EUNSUPPORTED, "n > 1024 is not supported");
   if (count == 0) return SDQ_OK;
   if (!w || !u || !d || !t) return fail(ctx, SDQ_EINVAL, "null pointer");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   ctx->err.clear();
-  return timed(ctx, "udt", [&] { return sdq::launch_udt(nt_of(n), n, count, w, u, d, t, ctx->stream); });
+  const int nt = nt_of(n);
+  if (is_gang(nt)) {
+    const int ng = std::max(1, std::min(count, gang_slots(ctx, nt)));
+    HIP_TRY(grow(ctx->d_gang, gang_bytes(nt, ng)), "hipMalloc(gang scratch)");
+    sdq::GangArgs a;
+    a.bars = (unsigned*)ctx->d_gang.p;
+    a.scratch = (double*)((char*)ctx->d_gang.p + gang_bars_bytes(ng));
+    a.ngangs = ng;
+    a.nt = nt;
+    return timed(ctx, "udt", [&] {
+      hipError_t e = sdq::launch_fill_i32((int32_t*)a.bars, ng * sdq::kGangBarWords, 0, ctx->stream);
+      if (e != hipSuccess) return e;
+      return sdq::launch_gang_udt(n, count, w, u, d, t, a, ctx->stream);
+    });
+  }
+  return timed(ctx, "udt", [&] { return sdq::launch_udt(nt, n, count, w, u, d, t, ctx->stream); });
 }
 
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
@@ -857,7 +932,7 @@ sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const ch
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || (count > 0 && !n_list)) return fail(ctx, SDQ_EINVAL, "bad n_list");
   for (int a = 0; a < count; ++a)
-    if (n_list[a] < 1 || n_list[a] > 16 * sdq::kMaxNT) return fail(ctx, SDQ_EUNSUPPORTED, "n out of range");
+    if (n_list[a] < 1 || n_list[a] > sdq::kGangMaxN) return fail(ctx, SDQ_EUNSUPPORTED, "n out of range");
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, ctx->device), "hipGetDeviceProperties");
@@ -884,6 +959,7 @@ sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const ch
   sdq_status result = SDQ_OK;
   for (int a = 0; a < count && result == SDQ_OK; ++a) {
     const int n = n_list[a], nt = nt_of(n);
+    if (is_gang(nt)) continue;  // one gang kernel per size: nothing to choose
     auto hit = cached.find(n);
     if (hit != cached.end()) {
       ctx->tune[nt] = hit->second;
