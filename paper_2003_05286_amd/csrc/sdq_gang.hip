@@ -42,7 +42,6 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = kGangThreads / 64;  // 16
-constexpr int kRL = kGangMaxN / 64;        // rows per lane in a column operation
 constexpr int kPairs = 5;                  // MFMA output tiles per wave in a slab product
 constexpr unsigned long long kSpinTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
 
@@ -67,6 +66,7 @@ __shared__ GLds L;
 struct GC {
   GangGeom geo;
   int n;        // matrix size of the current item
+  int gang;     // gang index
   int g;        // member index
   int c0;       // first global column of the slab
   int t, w, l;  // thread, wave, lane
@@ -86,24 +86,62 @@ __device__ __forceinline__ double* sc_cand(const GC& c, int buf) {
   return c.base + 7 * gang_mat(c.geo) + (int64_t)buf * c.geo.G * gang_cand_stride(c.geo);
 }
 
-// ---- wave reductions (every lane gets the same bits) -----------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+// ---- wave reductions ----------------------------------------------------------
+// A butterfly in which each step combines a lane with a partner that
+// combines it back (lane^1, lane^2 by quad permutation, the mirror inside 8
+// and inside 16 lanes by DPP, then whole 16-lane rows with v_permlane16_swap
+// and v_permlane32_swap): every lane adds the same two values, so all 64
+// lanes, and every wave given the same data, get bitwise-identical results,
+// which the redundant reflector computation of the gang QR relies on.  No
+// LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long bits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ __forceinline__ double dbl(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+// Combine 16-lane rows r and r^1 (R32 = false) or r and r^2 (R32 = true).
+// v_permlane{16,32}_swap with both operands v returns the even row's value
+// in its first result and the odd row's in its second, in both rows; both
+// rows then apply op(even, odd) in the same order.
+template <bool R32, class OP>
+__device__ __forceinline__ unsigned long long pair_rows(unsigned long long v, OP op) {
+  const unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  unsigned e0, e1, o0, o1;
+  if constexpr (R32) {
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    e0 = a[0]; o0 = a[1]; e1 = b[0]; o1 = b[1];
+  } else {
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    e0 = a[0]; o0 = a[1]; e1 = b[0]; o1 = b[1];
+  }
+  return op(((unsigned long long)e1 << 32) | e0, ((unsigned long long)o1 << 32) | o0);
+}
+
+template <class OP>
+__device__ __forceinline__ unsigned long long wave_reduce(unsigned long long v, OP op) {
+  v = op(v, dpp64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp64<0x141>(v));  // row_half_mirror
+  v = op(v, dpp64<0x140>(v));  // row_mirror
+  v = pair_rows<false>(v, op);
+  v = pair_rows<true>(v, op);
   return v;
+}
+// op(a, b) must be commutative in its bits: a + b, max
+__device__ __forceinline__ double wave_sum(double v) {
+  return dbl(wave_reduce(bits(v), [](unsigned long long a, unsigned long long b) { return bits(dbl(a) + dbl(b)); }));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
-  return v;
+  return dbl(wave_reduce(bits(v), [](unsigned long long a, unsigned long long b) { return bits(fmax(dbl(a), dbl(b))); }));
 }
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const unsigned long long o = __shfl_xor(v, m);
-    v = o > v ? o : v;
-  }
-  return v;
+  return wave_reduce(v, [](unsigned long long a, unsigned long long b) { return a > b ? a : b; });
 }
 __device__ __forceinline__ double pow2_scale(double x) {
   if (!(x > 0.0) || !isfinite(x)) return 1.0;
@@ -151,6 +189,52 @@ __device__ bool gang_sync(GC& c) {
   const bool good = L.ok != 0;
   c.ok = c.ok && good;
   return good;
+}
+
+// Light gang barrier for data exchanged only through device-scope atomic
+// stores and loads (they are performed at the device coherence point, so no
+// cache write-back or invalidation is needed): every wave waits for its
+// stores to complete, then one thread counts in and waits.
+__device__ bool gang_sync_light(GC& c) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  c.epoch += 1;
+  if (c.t == 0) {
+    const unsigned target = c.epoch * (unsigned)c.geo.G;
+    __hip_atomic_fetch_add(&c.bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      const unsigned v = __hip_atomic_load(&c.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= target) break;
+      if (__hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        good = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > kSpinTicks) {
+        __hip_atomic_exchange(&c.bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+    }
+    L.ok = good;
+  }
+  __syncthreads();
+  const bool good = L.ok != 0;
+  c.ok = c.ok && good;
+  return good;
+}
+__device__ __forceinline__ void st_coh(double* p, double x) {
+  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh_u64(double* p, unsigned long long x) {
+  __hip_atomic_store((unsigned long long*)p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_coh_u64(const double* p) {
+  return __hip_atomic_load((unsigned long long*)const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- slab products -----------------------------------------------------------
@@ -324,9 +408,9 @@ __device__ void publish_candidate(GC& c, int p) {
       int cc = key_col(k) - c.c0;
       cc = cc < 0 ? 0 : (cc >= c.geo.w ? c.geo.w - 1 : cc);
       const double* col = L.S + cc * c.geo.ldr;
-      for (int i = p + c.l; i < c.n; i += 64) out[i] = col[i];
+      for (int i = p + c.l; i < c.n; i += 64) st_coh(out + i, col[i]);
     }
-    if (c.l == 0) *(unsigned long long*)(out + c.geo.npad) = k;
+    if (c.l == 0) st_coh_u64(out + c.geo.npad, k);
   }
 }
 
@@ -350,6 +434,7 @@ __device__ double col_norm(const double* col, int lo, int n, int l) {
 // was chosen, rows above and on that step) and sc_V = the reflectors (column
 // gc = reflector of that step, rows below it, unit entry implied), both
 // column-major npad x npad, visible to the whole gang.
+template <int kRL>
 __device__ void cpqr_gang(GC& c) {
   const int n = c.n, ldr = c.geo.ldr, G = c.geo.G;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
@@ -364,28 +449,27 @@ __device__ void cpqr_gang(GC& c) {
   }
   __syncthreads();
   publish_candidate(c, 0);
-  gang_sync(c);
+  gang_sync_light(c);
   const int nrl = (n + 63) / 64;
   for (int p = 0; p < n; ++p) {
     const double* cb = sc_cand(c, p & 1);
     unsigned long long key = 0ull;
-    if (c.l < G) key = *(const unsigned long long*)(cb + (int64_t)c.l * gang_cand_stride(c.geo) + c.geo.npad);
+    if (c.l < G) key = ld_coh_u64(cb + (int64_t)c.l * gang_cand_stride(c.geo) + c.geo.npad);
     key = wave_max_u64(key);
     int gw = key_col(key);
     gw = gw < 0 ? 0 : (gw >= n ? n - 1 : gw);
     const int owner = gw / c.geo.w;
     const double* xs = cb + (int64_t)owner * gang_cand_stride(c.geo);
-    double x[kRL];
-    double am = 0.0, al = 0.0;
+    double v[kRL];  // the winner column below row p, then the reflector
+    double am = 0.0;
+    const double al = ld_coh(xs + p);
 #pragma unroll
     for (int s = 0; s < kRL; ++s) {
       const int i = c.l + 64 * s;
-      x[s] = (s < nrl && i >= p && i < n) ? xs[i] : 0.0;
-      if (i > p) am = fmax(am, fabs(x[s]));
-      if (i == p) al = x[s];
+      v[s] = (s < nrl && i > p && i < n) ? ld_coh(xs + i) : 0.0;
+      am = fmax(am, fabs(v[s]));
     }
     am = wave_max(am);
-    al = wave_sum(al);  // exactly the one nonzero term
     double xnorm = 0.0;
     if (am > 0.0) {
       const double sc = pow2_scale(am);
@@ -393,10 +477,8 @@ __device__ void cpqr_gang(GC& c) {
 #pragma unroll
       for (int s = 0; s < kRL; ++s) {
         const int i = c.l + 64 * s;
-        if (i > p) {
-          const double y = x[s] * sc;
-          ss += y * y;
-        }
+        const double y = v[s] * sc;
+        ss += y * y;
       }
       xnorm = sqrt(wave_sum(ss)) / sc;
     }
@@ -410,11 +492,10 @@ __device__ void cpqr_gang(GC& c) {
       tau = (beta - al) / beta;
       vsc = 1.0 / (al - beta);
     }
-    double v[kRL];
 #pragma unroll
     for (int s = 0; s < kRL; ++s) {
       const int i = c.l + 64 * s;
-      v[s] = i > p ? x[s] * vsc : (i == p ? 1.0 : 0.0);
+      v[s] = i > p ? v[s] * vsc : (i == p ? 1.0 : 0.0);
     }
     if (c.t == 0) {
       L.tau[p] = tau;
@@ -453,11 +534,7 @@ __device__ void cpqr_gang(GC& c) {
           }
         }
       }
-      double rp = 0.0;
-#pragma unroll
-      for (int s = 0; s < kRL; ++s)
-        if (c.l + 64 * s == p) rp = y[s];
-      rp = wave_sum(rp);
+      const double rp = col[p];  // row p after the update (same wave wrote it)
       double n1 = L.vn1[cc], n2 = L.vn2[cc];
       if (n1 != 0.0) {
         double tmp = fabs(rp) / n1;
@@ -494,7 +571,7 @@ __device__ void cpqr_gang(GC& c) {
     }
     if (p + 1 < n) {
       publish_candidate(c, p + 1);
-      gang_sync(c);
+      gang_sync_light(c);
     }
   }
   __syncthreads();
@@ -517,7 +594,7 @@ __device__ void cpqr_gang(GC& c) {
 
 // Apply reflectors j = jlo .. jhi (ascending: Q^T, descending: Q) to the own
 // columns of the slab, one wave per column, reflector rows from sc_V.
-template <bool ASC>
+template <bool ASC, int kRL>
 __device__ void apply_reflectors(GC& c, bool identity_cols) {
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* V = sc_V(c);
@@ -564,6 +641,7 @@ __device__ void apply_reflectors(GC& c, bool identity_cols) {
 
 // S <- R^{-1} S (R upper triangular in pivot order: R[i][q] = sc_R[piv[q]][i]),
 // one wave per column.
+template <int kRL>
 __device__ void back_subst(GC& c) {
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* R = sc_R(c);
@@ -647,6 +725,7 @@ __device__ void load_slice_scale(GC& c, const Inst& I, int q) {
 // Stabilized chain (Sec. 4.1) with the UDT of Sec. 4.2.2 every k slices,
 // forward over B_1..B_m or, with SW_ADJ, backward over B_m^T..B_1^T; stage
 // storage as in the single-workgroup kernels (U | T | D | sgn det U).
+template <int kRL>
 __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
   const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad;
   const bool adj = (flags & SW_ADJ) != 0;
@@ -681,7 +760,7 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
       else
         slab_gemm(c, aop, One{}, [&](int row) { return L.tau[row]; });
     }
-    cpqr_gang(c);
+    cpqr_gang<kRL>(c);
     // T <- D^{-1} R P^T T with D = |diag R|
     slab_fill_rows(c, [&](int i, int gc) { return Tg[(int64_t)i * n + gc]; });
     __syncthreads();
@@ -692,7 +771,7 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
     // U <- Q
     slab_identity(c);
     __syncthreads();
-    apply_reflectors<false>(c, true);
+    apply_reflectors<false, kRL>(c, true);
     double* dst = nullptr;
     if (flags & SW_STORE) dst = adj ? (I.cka + (int64_t)b * sd) : (I.ckf + (int64_t)s * sd);
     else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
@@ -723,6 +802,7 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
 // Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1,
 // mirror form): M = Dp^{-1} U^T + Dm T, G = M^{-1} Dp^{-1} U^T,
 // det(1 + U D T) = det U prod(Dp) det M.
+template <int kRL>
 __device__ void equal_gang(GC& c, const Inst& I) {
   const int n = I.n;
   const double* U = I.fin;
@@ -738,11 +818,11 @@ __device__ void equal_gang(GC& c, const Inst& I) {
     if (i < n && gc < n) L.S[cc * c.geo.ldr + i] += U[(int64_t)gc * n + i] / dp(i);
   }
   __syncthreads();
-  cpqr_gang(c);
+  cpqr_gang<kRL>(c);
   slab_fill_cols(c, [&](int i, int gc) { return U[(int64_t)gc * n + i] / dp(i); });
   __syncthreads();
-  apply_reflectors<true>(c, false);
-  back_subst(c);
+  apply_reflectors<true, kRL>(c, false);
+  back_subst<kRL>(c);
   int bad = 0;
   for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
     const int cc = idx / c.geo.npad, i = idx - cc * c.geo.npad;
@@ -777,6 +857,7 @@ __device__ void equal_gang(GC& c, const Inst& I) {
 //   G(tau,0) = U2 D_Rp^{-1} Mid^{-1} D_Lp^{-1} T1,
 // with D_L = D1^{-1}, D_R = D2; then B_l ... G(tau_j, 0) for the requested
 // l of the block (Sec. 6).
+template <int kRL>
 __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
                            const int32_t* l_list) {
   const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad;
@@ -814,15 +895,15 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
     *e = lm * (*e) * rpi + lpi * Xg[(int64_t)gc * np + i] * rm;
   }
   __syncthreads();
-  cpqr_gang(c);
+  cpqr_gang<kRL>(c);
   // Y = D_Lp^{-1} T1 -> Q^T Y -> R^{-1} (pivot order)
   slab_fill_rows(c, [&](int i, int gc) {
     const double a = d1(i);
     return (T1 ? T1[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0)) * (a < 1.0 ? a : 1.0);
   });
   __syncthreads();
-  apply_reflectors<true>(c, false);
-  back_subst(c);
+  apply_reflectors<true, kRL>(c, false);
+  back_subst<kRL>(c);
   // undo the pivot order through HBM: X[piv[q]][:] = Z[q][:]
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
     const int cc = idx / np, q = idx - cc * np, gc = c.c0 + cc;
@@ -872,6 +953,7 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
 //   G_{jk+1} = [1 + U1 (D1 (T1 T2^T) D2) U2^T]^{-1}; udt(D1 T1 T2^T D2) = u d t,
 //   U = U1 u, T = t U2^T, then the equal-time inversion (Sec. 5.1), and
 //   G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar,  grad[l-1][i] = alpha (1 - G_l)_ii.
+template <int kRL>
 __device__ void grad_gang(GC& c, const Inst& I, int j) {
   const int n = I.n, m = I.m, k = I.k, nb = I.nb, np = c.geo.npad, ldr = c.geo.ldr;
   const int64_t sd = stage_doubles(n);
@@ -894,7 +976,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
     if (gc < n && D2) L.S[cc * ldr + i] *= D2[gc];
   }
   __syncthreads();
-  cpqr_gang(c);
+  cpqr_gang<kRL>(c);
   // T = d^{-1} (R P^T) U2^T  (slab columns), to HBM
   slab_fill_cols(c, [&](int i, int gc) { return U2 ? U2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
   __syncthreads();
@@ -904,7 +986,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   // U = U1 u
   slab_identity(c);
   __syncthreads();
-  apply_reflectors<false>(c, true);
+  apply_reflectors<false, kRL>(c, true);
   slab_gemm(c, ARowMajor<One>{U1, n, One{}}, One{}, One{});
   slab_store_colmajor(c, Ug);
   // D of the combined factorization: |beta| (kept in L.red-free storage: HBM)
@@ -922,11 +1004,11 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
     if (i < n && gc < n) L.S[cc * ldr + i] += dm(i) * Tg[(int64_t)gc * np + i];
   }
   __syncthreads();
-  cpqr_gang(c);
+  cpqr_gang<kRL>(c);
   slab_fill_rows(c, [&](int i, int gc) { return Ug[(int64_t)i * np + gc] / dp(i); });
   __syncthreads();
-  apply_reflectors<true>(c, false);
-  back_subst(c);
+  apply_reflectors<true, kRL>(c, false);
+  back_subst<kRL>(c);
   // G_{jk+1} = P X into HBM buffer 0 (column-major, rows un-permuted)
   double* Gb[2] = {sc_G(c, 0), sc_G(c, 1)};
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
@@ -971,11 +1053,12 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
 }
 
 // plain UDT (Sec. 4.2.2) of one n x n row-major matrix
+template <int kRL>
 __device__ void udt_gang(GC& c, const double* w, double* u, double* d, double* t) {
   const int n = c.n, np = c.geo.npad;
   slab_fill_rows(c, [&](int i, int gc) { return w[(int64_t)i * n + gc]; });
   __syncthreads();
-  cpqr_gang(c);
+  cpqr_gang<kRL>(c);
   // T = D^{-1} R P^T
   slab_fill_cols(c, [&](int i, int gc) { return sc_R(c)[(int64_t)gc * np + i] / fabs(L.beta[i]); });
   __syncthreads();
@@ -983,7 +1066,7 @@ __device__ void udt_gang(GC& c, const double* w, double* u, double* d, double* t
   __syncthreads();
   slab_identity(c);
   __syncthreads();
-  apply_reflectors<false>(c, true);
+  apply_reflectors<false, kRL>(c, true);
   slab_store_rowmajor(c, u);
   if (c.g == 0)
     for (int i = c.t; i < n; i += kGangThreads) d[i] = fabs(L.beta[i]);
@@ -993,8 +1076,20 @@ __device__ void udt_gang(GC& c, const double* w, double* u, double* d, double* t
 __device__ GC gang_ctx(const GangArgs& a) {
   GC c;
   c.geo = gang_geom(a.nt);
-  const int gang = blockIdx.x / c.geo.G;
-  c.g = blockIdx.x - gang * c.geo.G;
+  // Workgroups are dispatched round-robin over the 8 XCDs; when the gang
+  // count allows it, the members of a gang are blocks b, b + 8, ... so that
+  // they share one XCD's L2.
+  const int b = blockIdx.x;
+  int gang;
+  if (a.ngangs % 8 == 0) {
+    const int x = b & 7, r = b >> 3;
+    c.g = r % c.geo.G;
+    gang = (r / c.geo.G) * 8 + x;
+  } else {
+    gang = b / c.geo.G;
+    c.g = b - gang * c.geo.G;
+  }
+  c.gang = gang;
   c.c0 = c.g * c.geo.w;
   c.t = threadIdx.x;
   c.w = threadIdx.x >> 6;
@@ -1007,44 +1102,43 @@ __device__ GC gang_ctx(const GangArgs& a) {
   return c;
 }
 
+template <int RL>
 __global__ __launch_bounds__(kGangThreads, 1) void k_gang_sweep(const Inst* __restrict__ insts,
                                                                  const SweepItem* __restrict__ items,
                                                                  int count, GangArgs a) {
   GC c = gang_ctx(a);
-  const int gang = blockIdx.x / c.geo.G;
-  for (int it = gang; it < count; it += a.ngangs) {
+  for (int it = c.gang; it < count; it += a.ngangs) {
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
     c.n = I.n;
-    sweep_gang(c, I, wi.flags);
+    sweep_gang<RL>(c, I, wi.flags);
   }
 }
 
-template <int MODE>
+template <int MODE, int RL>
 __global__ __launch_bounds__(kGangThreads, 1) void k_gang_pair(const Inst* __restrict__ insts,
                                                                 const PairItem* __restrict__ items,
                                                                 int count, const int32_t* __restrict__ l_list,
                                                                 GangArgs a) {
   GC c = gang_ctx(a);
-  const int gang = blockIdx.x / c.geo.G;
-  for (int it = gang; it < count; it += a.ngangs) {
+  for (int it = c.gang; it < count; it += a.ngangs) {
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
     c.n = I.n;
-    if (MODE == PAIR_EQUAL) equal_gang(c, I);
-    else if (MODE == PAIR_TDISP) tdisp_gang(c, I, wi.j, wi.ilo, wi.ihi, l_list);
-    else grad_gang(c, I, wi.j);
+    if (MODE == PAIR_EQUAL) equal_gang<RL>(c, I);
+    else if (MODE == PAIR_TDISP) tdisp_gang<RL>(c, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else grad_gang<RL>(c, I, wi.j);
   }
 }
 
+template <int RL>
 __global__ __launch_bounds__(kGangThreads, 1) void k_gang_udt(int n, int count, const double* w, double* u,
                                                                double* d, double* t, GangArgs a) {
   GC c = gang_ctx(a);
   c.n = n;
-  const int gang = blockIdx.x / c.geo.G;
-  for (int it = gang; it < count; it += a.ngangs) {
+  for (int it = c.gang; it < count; it += a.ngangs) {
     const int64_t off = (int64_t)it * n * n;
-    udt_gang(c, w + off, u + off, d + (int64_t)it * n, t + off);
+    udt_gang<RL>(c, w + off, u + off, d + (int64_t)it * n, t + off);
   }
 }
 
@@ -1058,36 +1152,54 @@ hipError_t coop_launch(K kern, GangArgs a, hipStream_t s, Args... args) {
 
 }  // namespace
 
+// rows per lane of a column operation: 4 (n <= 256), 8 (<= 512), 16
+int rl_of(int nt) { return nt <= 16 ? 4 : (nt <= 32 ? 8 : 16); }
+
 hipError_t gang_capacity(int nt, int num_cu, int* ngangs) {
   const GangGeom g = gang_geom(nt);
   if (g.G == 0) return hipErrorInvalidValue;
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_gang_pair<PAIR_TDISP>,
-                                                              kGangThreads, 0);
-  if (e != hipSuccess) return e;
-  int per_cu2 = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_gang_sweep, kGangThreads, 0);
-  if (e != hipSuccess) return e;
-  per_cu = per_cu < per_cu2 ? per_cu : per_cu2;
+  const void* ks[] = {(const void*)k_gang_sweep<16>, (const void*)k_gang_pair<PAIR_TDISP, 16>,
+                      (const void*)k_gang_pair<PAIR_GRAD, 16>, (const void*)k_gang_pair<PAIR_EQUAL, 16>};
+  int per_cu = 1 << 30;
+  for (const void* k : ks) {
+    int b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kGangThreads, 0);
+    if (e != hipSuccess) return e;
+    per_cu = b < per_cu ? b : per_cu;
+  }
   *ngangs = per_cu * num_cu / g.G;
   return hipSuccess;
 }
 
+#define SDQ_RL_SWITCH(CALL) \
+  switch (rl_of(a.nt)) {    \
+    case 4: return CALL(4); \
+    case 8: return CALL(8); \
+    default: return CALL(16); \
+  }
+
 hipError_t launch_gang_sweep(const Inst* inst, const SweepItem* items, int count, GangArgs a,
                              hipStream_t s) {
-  return coop_launch(k_gang_sweep, a, s, inst, items, count);
+#define C(R) coop_launch(k_gang_sweep<R>, a, s, inst, items, count)
+  SDQ_RL_SWITCH(C)
+#undef C
 }
 
 hipError_t launch_gang_pair(int mode, const Inst* inst, const PairItem* items, int count,
                             const int32_t* l_list, GangArgs a, hipStream_t s) {
-  if (mode == PAIR_EQUAL) return coop_launch(k_gang_pair<PAIR_EQUAL>, a, s, inst, items, count, l_list);
-  if (mode == PAIR_TDISP) return coop_launch(k_gang_pair<PAIR_TDISP>, a, s, inst, items, count, l_list);
-  return coop_launch(k_gang_pair<PAIR_GRAD>, a, s, inst, items, count, l_list);
+#define C(R)                                                                                  \
+  (mode == PAIR_EQUAL ? coop_launch(k_gang_pair<PAIR_EQUAL, R>, a, s, inst, items, count, l_list) \
+   : mode == PAIR_TDISP ? coop_launch(k_gang_pair<PAIR_TDISP, R>, a, s, inst, items, count, l_list) \
+                        : coop_launch(k_gang_pair<PAIR_GRAD, R>, a, s, inst, items, count, l_list))
+  SDQ_RL_SWITCH(C)
+#undef C
 }
 
 hipError_t launch_gang_udt(int n, int count, const double* w, double* u, double* d, double* t,
                            GangArgs a, hipStream_t s) {
-  return coop_launch(k_gang_udt, a, s, n, count, w, u, d, t);
+#define C(R) coop_launch(k_gang_udt<R>, a, s, n, count, w, u, d, t)
+  SDQ_RL_SWITCH(C)
+#undef C
 }
 
 }  // namespace sdq

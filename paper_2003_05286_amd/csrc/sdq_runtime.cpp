@@ -245,7 +245,13 @@ int gang_slots(sdq_ctx* ctx, int nt) {
 }
 
 int grid_for(sdq_ctx* ctx, int kind, int nt, int variant, int count) {
-  if (is_gang(nt)) return std::max(1, std::min(count, gang_slots(ctx, nt)));
+  if (is_gang(nt)) {
+    // a multiple of 8 gangs where the device holds them (XCD-local gangs)
+    const int cap = gang_slots(ctx, nt);
+    int ng = std::max(1, std::min(count, cap));
+    if (ng % 8 && (ng + 7) / 8 * 8 <= cap) ng = (ng + 7) / 8 * 8;
+    return ng;
+  }
   int per_cu = info(ctx, kind, nt, variant).blocks_per_cu;
   if (kind == sdq::KK_SWEEP && nt <= sdq::kMaxNT && ctx->tune[nt].blocks_per_cu > 0)
     per_cu = std::min(per_cu, ctx->tune[nt].blocks_per_cu);
@@ -880,7 +886,7 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
   ctx->err.clear();
   const int nt = nt_of(n);
   if (is_gang(nt)) {
-    const int ng = std::max(1, std::min(count, gang_slots(ctx, nt)));
+    const int ng = grid_for(ctx, sdq::KK_UDT, nt, 0, count);
     HIP_TRY(grow(ctx->d_gang, gang_bytes(nt, ng)), "hipMalloc(gang scratch)");
     sdq::GangArgs a;
     a.bars = (unsigned*)ctx->d_gang.p;
