@@ -85,9 +85,11 @@ def test_greens_ragged_sizes_mixed(ctx):
 
 
 def test_greens_large_tiles(ctx):
-    insts = wl.hubbard_ising(12, 2.0, 1, 1, seed=wl.BASE_SEED + 300)  # n = 144 -> unsupported
+    n = 1025  # above the largest supported size: rejected before any launch
+    e1025 = np.eye(n)
+    f = np.ones((2, n))
     with pytest.raises(sdq.SdqError) as e:
-        ctx.greens(chains_of(insts))
+        ctx.greens(chains_of([wl.Instance(0, 2, 1, 0.5, f, e1025, e1025)]))
     assert e.value.status == sdq.SDQ_EUNSUPPORTED
     big = []
     for n in (112, 128):
@@ -249,9 +251,10 @@ def test_grad_finite_differences_continuous_field(ctx):
         assert abs(g - fd) <= 1e-5, (c, l, i, g, fd)
 
 
-def test_uneven_batch_up_to_n100(ctx):
-    """The mixed-size batch (L in {6, 8, 10}, beta in {10, 20, 40}) in one call;
-    a sample compared with the oracle, and two chains rerun alone.
+def test_uneven_batch(ctx):
+    """The mixed-size batch (L in {6, 8, 10, 12}, beta in {10, 20, 40}) in one
+    call: single-workgroup kernels (n <= 128) and gang kernels (n = 144) in
+    one plan; a sample compared with the oracle, and two chains rerun alone.
 
     The reference here is the oracle run with k = 1.  The chains of this batch
     with the largest |G| (about 2e3, cond(G) ~ 1e18) carry a forward error of
@@ -261,13 +264,13 @@ def test_uneven_batch_up_to_n100(ctx):
     the k = 1 oracle is within 1e-12 of the exact value on the worst of them
     (pinned on the CPU).  The bar stays 1e-10."""
     W = wl.workload("hubbard_uneven_batch512", scale=0.125)
-    insts = [I for I in W.instances if I.n <= 100]
+    insts = W.instances
     say(f"[gpu] uneven batch: {len(insts)} chains, n = {sorted({I.n for I in insts})}")
     gs, ld, sg, st = ctx.greens(chains_of(insts))
     torch.cuda.synchronize()
     assert (st.cpu().numpy() == 0).all()
     order = sorted(range(len(insts)), key=lambda a: (insts[a].n, insts[a].m))
-    sample = order[:: max(1, len(order) // 6)][:6]
+    sample = order[:: max(1, len(order) // 6)][:6] + [order[-1]]
     for a in sample:
         I = insts[a]
         G, ldo, sgo = oracle.greens(I.expk, I.field, I.alpha, 1)
