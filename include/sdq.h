@@ -30,8 +30,11 @@
  *     and does not keep them past the call, except through a checkpoint
  *     handle (sdq_logdet) which keeps the library's own copies;
  *   * no C++ exception crosses this boundary.
- * Supported sizes: 1 <= n <= 128 (one workgroup per chain, factors resident
- * in LDS); larger n returns SDQ_EUNSUPPORTED.  1 <= k <= m.
+ * Supported sizes: 1 <= n <= 1024, 1 <= k <= m.  n <= 128 runs one
+ * workgroup per chain with its matrices in registers and LDS; 128 < n <= 1024
+ * runs a gang of workgroups per chain (a column slab of the matrix in each
+ * one's LDS, pivot candidates and operands exchanged through HBM) in a
+ * cooperative launch.  n > 1024 returns SDQ_EUNSUPPORTED.
  */
 #ifndef SDQ_H
 #define SDQ_H
@@ -48,7 +51,7 @@ typedef enum {
   SDQ_ENOMEM = -2,      /* device allocation failed                            */
   SDQ_EHIP = -3,        /* a HIP runtime call failed (message in last_error)   */
   SDQ_ERANGE = -4,      /* per instance: non-finite data or FP64 range exceeded */
-  SDQ_EUNSUPPORTED = -5 /* valid but not implemented (e.g. n > 128)            */
+  SDQ_EUNSUPPORTED = -5 /* valid but not implemented (e.g. n > 1024)           */
 } sdq_status;
 
 typedef enum {
@@ -61,7 +64,7 @@ typedef struct sdq_ctx sdq_ctx;
 
 /* One Markov chain / spin flavour.  B_l = expk * diag(exp(alpha * field[l-1][:])). */
 typedef struct {
-  int32_t n;              /* sites N, 1 <= n <= 128                                  */
+  int32_t n;              /* sites N, 1 <= n <= 1024                                 */
   int32_t m;              /* slices M = beta / dtau, m >= 1                           */
   int32_t k;              /* stabilization interval, 1 <= k <= m (Sec. 4.1)          */
   int32_t pad_;
@@ -134,7 +137,8 @@ sdq_status sdq_release(sdq_ctx* ctx, uint64_t ckpt_handle);
 
 /* UDT factorization W P = Q R, U = Q, D = |diag R|, T = D^{-1} R P^T
  * (Sec. 4.2.2) of `count` n x n matrices stored back to back in w
- * ([count][n][n], device); outputs u, t [count][n][n] and d [count][n]. */
+ * ([count][n][n], device); outputs u, t [count][n][n] and d [count][n].
+ * 1 <= n <= 1024. */
 sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u,
                    double* d, double* t);
 
@@ -148,13 +152,15 @@ sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, 
  * device, keep the fastest per n in ctx, and if cache_path is not NULL
  * append the choices to that JSON-lines file (read back by later contexts
  * through the same call; an existing entry for (arch, n) is used without
- * re-timing). */
+ * re-timing).  Sizes n > 128 have a single kernel and are accepted but not
+ * timed. */
 sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const char* cache_path);
 
 /* Capture later batched calls in HIP graphs and replay them when the same
  * batch (every pointer, shape, list and scheme) is seen again (enable = 1),
  * or launch directly (enable = 0, the default).  A replay runs on the
- * context's stream; at most 16 graphs are kept (oldest evicted). */
+ * context's stream; at most 16 graphs are kept (oldest evicted).  Batches
+ * with a chain of n > 128 (cooperative launches) always launch directly. */
 sdq_status sdq_set_graphs(sdq_ctx* ctx, int enable);
 
 /* Record HIP events around every kernel launch (enable = 1); the per-kernel
