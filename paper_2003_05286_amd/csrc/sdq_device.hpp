@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <utility>
+
 #include "sdq_internal.h"
 
 namespace sdq {
@@ -109,6 +111,24 @@ __device__ __forceinline__ int col_of(const Lane& L, int c) {
   return 16 * (L.w + Geo<NT, P>::P * c) + L.cl;
 }
 __device__ __forceinline__ int row_of(const Lane& L, int ti, int r) { return 16 * ti + L.g + 4 * r; }
+
+// f(std::integral_constant<int, 0>{}), ..., f(integral_constant<N - 1>): loops
+// whose tile index must be a compile-time constant (the column loops of the
+// QR and of the reflector applications run tile by tile, so that "tile below,
+// at or above the current one" is decided when compiling, not per element)
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// element r of a lane's 4-entry tile column, r wave-uniform
+__device__ __forceinline__ double pick4(const double (&a)[4], int r) {
+  return r == 0 ? a[0] : (r == 1 ? a[1] : (r == 2 ? a[2] : a[3]));
+}
 
 // ---- cross-lane primitives -------------------------------------------------
 // A column lives in the four lanes l, l^16, l^32, l^48 (one lane per 16-lane
@@ -353,171 +373,165 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
   }
 
   int buf = 0;
-  for (int j = 0; j < n; ++j) {
-    const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
-    // ---- wave-local candidate (packed key), columns of this wave
-    double key = -1.0;
+  static_for<NT>([&](auto tjc) {
+    constexpr int TJ = decltype(tjc)::value;
+    const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
+    for (int j = 16 * TJ; j < jend; ++j) {
+      const int jj = j - 16 * TJ, gj = jj & 3, rj = jj >> 2;
+      // ---- wave-local candidate (packed key), columns of this wave
+      double key = -1.0;
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      if (ps[c] < 0) key = fmax(key, pivot_key(vn1[c], col_of<NT, P>(L, c)));
-    key = row_max16(key);  // the four rows hold the same columns
-    const int bc = pivot_col(key);
+      for (int c = 0; c < CT; ++c)
+        if (ps[c] < 0) key = fmax(key, pivot_key(vn1[c], col_of<NT, P>(L, c)));
+      key = row_max16(key);  // the four rows hold the same columns
+      const int bc = pivot_col(key);
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      if (key >= 0.0 && ps[c] < 0 && col_of<NT, P>(L, c) == bc) {
+      for (int c = 0; c < CT; ++c) {
+        if (key >= 0.0 && ps[c] < 0 && col_of<NT, P>(L, c) == bc) {
 #pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-          if (ti >= tj)
+          for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
             for (int r = 0; r < 4; ++r) S.cand[buf][L.w][row_of(L, ti, r)] = A.v[c][ti][r];
+        }
       }
-    }
-    double pk = key;
-    if constexpr (P > 1) {
-      if (L.l == 0) S.ckey[buf][L.w] = key;
-      __syncthreads();
-      // workgroup pivot: the owner wave follows from the column index
-      pk = S.ckey[buf][0];
+      double pk = key;
+      if constexpr (P > 1) {
+        if (L.l == 0) S.ckey[buf][L.w] = key;
+        __syncthreads();
+        // workgroup pivot: the owner wave follows from the column index
+        pk = S.ckey[buf][0];
 #pragma unroll
-      for (int q = 1; q < P; ++q) pk = fmax(pk, S.ckey[buf][q]);
-    } else {
-      // one wave: its own LDS writes are visible to its later reads
-      __builtin_amdgcn_wave_barrier();
-    }
-    const int pc = pivot_col(pk);
-    const int pw = (pc >> 4) % P;
-    const double* xc = S.cand[buf][pw];
-    const double alpha = xc[j];
-    // norm estimate of the pivot column (key without the index bits)
-    const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~0x7Fll);
-
-    // ---- reflector (every wave computes the same one from the same data)
-    const double sc = pow2_scale(vpiv);
-    double v[NT][4];
-    double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      if (ti < tj) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[ti][r] = 0.0;
+        for (int q = 1; q < P; ++q) pk = fmax(pk, S.ckey[buf][q]);
       } else {
+        // one wave: its own LDS writes are visible to its later reads
+        __builtin_amdgcn_wave_barrier();
+      }
+      const int pc = pivot_col(pk);
+      const int pw = (pc >> 4) % P;
+      const double* xc = S.cand[buf][pw];
+      const double alpha = xc[j];
+      // norm estimate of the pivot column (key without the index bits)
+      const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~0x7Fll);
+
+      // ---- reflector (every wave computes the same one from the same data);
+      // rows <= j masked in tile TJ only, tiles below TJ never touched
+      const double sc = pow2_scale(vpiv);
+      double v[NT][4];
+      double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
+#pragma unroll
+      for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double x = xc[row_of(L, ti, r)];
-          if (ti == tj && row_of(L, ti, r) <= j) x = 0.0;
+          if (ti == TJ && L.g + 4 * r <= jj) x = 0.0;
           v[ti][r] = x;
           const double y = x * sc;
           sp[r] = fma(y, y, sp[r]);
         }
+      double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
+      const double as = alpha * sc;
+      const double hn = sqrt(fma(as, as, s)) / sc;  // ||x[j:]||
+      double tau = 0.0, beta = alpha, inv = 0.0;
+      if (s != 0.0) {
+        beta = -copysign(hn, alpha);
+        tau = (beta - alpha) / beta;
+        inv = 1.0 / (alpha - beta);
       }
-    }
-    double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
-    const double as = alpha * sc;
-    const double hn = sqrt(fma(as, as, s)) / sc;  // ||x[j:]||
-    double tau = 0.0, beta = alpha, inv = 0.0;
-    if (s != 0.0) {
-      beta = -copysign(hn, alpha);
-      tau = (beta - alpha) / beta;
-      inv = 1.0 / (alpha - beta);
-    }
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-      if (ti >= tj)
+      for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const double x = v[ti][r] * inv;
-          v[ti][r] = (ti == tj && row_of(L, ti, r) == j) ? 1.0 : x;
+          v[ti][r] = (ti == TJ && L.g + 4 * r == jj) ? 1.0 : x;
         }
 
-    // ---- apply H_j to the other live columns, downdate their norms
-    bool need = false;
-    bool rec[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int col = col_of<NT, P>(L, c);
-      const bool is_piv = ps[c] < 0 && col == pc;
-      const bool upd = ps[c] < 0 && !is_piv;
-      rec[c] = false;
-      double dp[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-        if (ti >= tj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
-      const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * (upd ? tau : 0.0);
-      if (is_piv) {
-        // the pivot column becomes column j of R plus the reflector
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-          if (ti >= tj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = row_of(L, ti, r);
-              if (ti > tj || row > j) A.v[c][ti][r] = v[ti][r];
-              else if (row == j) A.v[c][ti][r] = beta;
-            }
-      } else {
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
-          if (ti >= tj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
-      }
-      const double rjv = sum_col(L.g == gj ? reg_at<NT>(A.v[c], tj, rj) : 0.0);
-      if (upd && vn1[c] != 0.0) {
-        // vn1^2 - r^2 = vn1^2 (1 - (r/vn1)^2); recompute when that falls to
-        // sqrt(eps) vn2^2 or below (same test, no division), all scaled by
-        // the exact power of two of vn2
-        const double a1 = fabs(rjv) * sv2[c], b1 = vn1[c] * sv2[c];
-        const double q = fmax(0.0, (b1 - a1) * (b1 + a1));
-        const double w2 = vn2[c] * sv2[c];
-        if (q <= tol3z * (w2 * w2)) {
-          need = true;
-          rec[c] = true;
-        } else {
-          vn1[c] = sqrt(q) / sv2[c];
-        }
-      }
-    }
-    if (__any(need)) {
-      // exact recompute of the norm of rows j+1.. (rare)
+      // ---- apply H_j to the other live columns, downdate their norms
+      bool need = false;
+      bool rec[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        double mx = 0.0;
+        const int col = col_of<NT, P>(L, c);
+        const bool is_piv = ps[c] < 0 && col == pc;
+        const bool upd = ps[c] < 0 && !is_piv;
+        rec[c] = false;
+        double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
+        for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (row_of(L, ti, r) > j) mx = fmax(mx, fabs(A.v[c][ti][r]));
-        mx = max_col(mx);
-        const double sc2 = pow2_scale(mx);
-        double s2 = 0.0;
+          for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
+        const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * (upd ? tau : 0.0);
+        if (is_piv) {
+          // the pivot column becomes column j of R plus the reflector
 #pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
+          for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (row_of(L, ti, r) > j) {
-              const double y = A.v[c][ti][r] * sc2;
-              s2 = fma(y, y, s2);
+            for (int r = 0; r < 4; ++r) {
+              const int q = L.g + 4 * r;
+              if (ti > TJ || q > jj) A.v[c][ti][r] = v[ti][r];
+              else if (q == jj) A.v[c][ti][r] = beta;
             }
-        s2 = sum_col(s2);
-        const double nn = sqrt(s2) / sc2;
-        if (rec[c]) {
-          vn1[c] = nn;
-          vn2[c] = nn;
-          sv2[c] = pow2_scale(nn);
+        } else {
+#pragma unroll
+          for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
+        }
+        const double rjv = sum_col(L.g == gj ? pick4(A.v[c][TJ], rj) : 0.0);
+        if (upd && vn1[c] != 0.0) {
+          // vn1^2 - r^2 = vn1^2 (1 - (r/vn1)^2); recompute when that falls to
+          // sqrt(eps) vn2^2 or below (same test, no division), all scaled by
+          // the exact power of two of vn2
+          const double a1 = fabs(rjv) * sv2[c], b1 = vn1[c] * sv2[c];
+          const double q = fmax(0.0, (b1 - a1) * (b1 + a1));
+          const double w2 = vn2[c] * sv2[c];
+          if (q <= tol3z * (w2 * w2)) {
+            need = true;
+            rec[c] = true;
+          } else {
+            vn1[c] = sqrt(q) / sv2[c];
+          }
         }
       }
-    }
+      if (__any(need)) {
+        // exact recompute of the norm of rows j+1.. (rare)
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      if (ps[c] < 0 && col_of<NT, P>(L, c) == pc) ps[c] = j;
-    if (L.t == 0) {
-      S.tau[j] = tau;
-      S.perm[j] = pc;
+        for (int c = 0; c < CT; ++c) {
+          double mx = 0.0;
+#pragma unroll
+          for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (ti > TJ || L.g + 4 * r > jj) mx = fmax(mx, fabs(A.v[c][ti][r]));
+          mx = max_col(mx);
+          const double sc2 = pow2_scale(mx);
+          double s2 = 0.0;
+#pragma unroll
+          for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (ti > TJ || L.g + 4 * r > jj) {
+                const double y = A.v[c][ti][r] * sc2;
+                s2 = fma(y, y, s2);
+              }
+          s2 = sum_col(s2);
+          const double nn = sqrt(s2) / sc2;
+          if (rec[c]) {
+            vn1[c] = nn;
+            vn2[c] = nn;
+            sv2[c] = pow2_scale(nn);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        if (ps[c] < 0 && col_of<NT, P>(L, c) == pc) ps[c] = j;
+      if (L.t == 0) {
+        S.tau[j] = tau;
+        S.perm[j] = pc;
+      }
+      buf ^= 1;
     }
-    buf ^= 1;
-  }
+  });
 
   // ---- park R / reflectors in LDS
 #pragma unroll
@@ -550,105 +564,112 @@ __device__ __forceinline__ void diag_r(const Lane& L, const int n, Smem<NT, P, E
   __syncthreads();
 }
 
-// reflector j from the factor store, at this lane's rows (zero above row j)
-template <int NT, int P, bool ELDS>
+// reflector j (in tile TJ) from the factor store, at this lane's rows of
+// tiles TJ.. (zero above row j, unit at row j)
+template <int TJ, int NT, int P, bool ELDS>
 __device__ __forceinline__ void load_reflector(const Lane& L, const Smem<NT, P, ELDS>& S, int j,
                                                double (&v)[NT][4]) {
-  const int tj = j >> 4;
+  const int jj = j - 16 * TJ;
   const double* vc = &S.R[S.perm[j] * Geo<NT, P>::LDR];
 #pragma unroll
-  for (int ti = 0; ti < NT; ++ti) {
-    if (ti < tj) continue;
+  for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row_of(L, ti, r);
-      const double x = vc[row];
-      v[ti][r] = (ti > tj || row > j) ? x : (row == j ? 1.0 : 0.0);
+      const double x = vc[row_of(L, ti, r)];
+      if (ti > TJ) {
+        v[ti][r] = x;
+      } else {
+        const int q = L.g + 4 * r;
+        v[ti][r] = q > jj ? x : (q == jj ? 1.0 : 0.0);
+      }
     }
-  }
 }
 
-// X <- H_j X for all column blocks (rows < j untouched)
-template <int NT, int P>
-__device__ __forceinline__ void apply_reflector(const Lane& L, int j, double tau,
-                                                const double (&v)[NT][4], RM<NT, P>& X) {
-  const int tj = j >> 4;
+// X <- H_j X for all column blocks (tiles below TJ untouched)
+template <int TJ, int NT, int P>
+__device__ __forceinline__ void apply_reflector(const Lane& L, double tau, const double (&v)[NT][4],
+                                                RM<NT, P>& X) {
 #pragma unroll
   for (int c = 0; c < Geo<NT, P>::CT; ++c) {
     double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-      if (ti >= tj)
+    for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], X.v[c][ti][r], dp[r]);
+      for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], X.v[c][ti][r], dp[r]);
     const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * tau;
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-      if (ti >= tj)
+    for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X.v[c][ti][r] = fma(-d, v[ti][r], X.v[c][ti][r]);
+      for (int r = 0; r < 4; ++r) X.v[c][ti][r] = fma(-d, v[ti][r], X.v[c][ti][r]);
   }
 }
 
-// Q = H_0 H_1 ... H_{n-1} into registers
+// Q = H_0 H_1 ... H_{n-1} into registers (reflectors applied last to first,
+// tile by tile)
 template <int NT, int P, bool ELDS>
 __device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& X) {
   set_identity<NT, P>(L, X);
-  for (int j = n - 1; j >= 0; --j) {
-    const double tau = S.tau[j];
-    if (tau == 0.0) continue;
-    double v[NT][4];
-    load_reflector<NT, P, ELDS>(L, S, j, v);
-    apply_reflector<NT, P>(L, j, tau, v, X);
-  }
+  static_for<NT>([&](auto kc) {
+    constexpr int TJ = NT - 1 - decltype(kc)::value;
+    const int jhi = (16 * TJ + 15 < n - 1 ? 16 * TJ + 15 : n - 1);
+    for (int j = jhi; j >= 16 * TJ; --j) {
+      const double tau = S.tau[j];
+      if (tau == 0.0) continue;
+      double v[NT][4];
+      load_reflector<TJ, NT, P, ELDS>(L, S, j, v);
+      apply_reflector<TJ, NT, P>(L, tau, v, X);
+    }
+  });
 }
 
 // Y <- Q^T Y = H_{n-1} ... H_0 Y
 template <int NT, int P, bool ELDS>
 __device__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
-  for (int j = 0; j < n; ++j) {
-    const double tau = S.tau[j];
-    if (tau == 0.0) continue;
-    double v[NT][4];
-    load_reflector<NT, P, ELDS>(L, S, j, v);
-    apply_reflector<NT, P>(L, j, tau, v, Y);
-  }
+  static_for<NT>([&](auto tjc) {
+    constexpr int TJ = decltype(tjc)::value;
+    const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
+    for (int j = 16 * TJ; j < jend; ++j) {
+      const double tau = S.tau[j];
+      if (tau == 0.0) continue;
+      double v[NT][4];
+      load_reflector<TJ, NT, P, ELDS>(L, S, j, v);
+      apply_reflector<TJ, NT, P>(L, tau, v, Y);
+    }
+  });
 }
 
 // Y <- R^{-1} Y (R in pivot order: R[i][j] = S.R[perm[j]*LDR + i], i <= j)
 template <int NT, int P, bool ELDS>
 __device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
   using G = Geo<NT, P>;
-  for (int j = n - 1; j >= 0; --j) {
-    const int tj = j >> 4, gj = j & 3, rj = (j >> 2) & 3;
-    const double* rc = &S.R[S.perm[j] * G::LDR];
-    const double rinv = 1.0 / rc[j];
-    double rr[NT][4];
+  static_for<NT>([&](auto kc) {
+    constexpr int TJ = NT - 1 - decltype(kc)::value;
+    const int jhi = (16 * TJ + 15 < n - 1 ? 16 * TJ + 15 : n - 1);
+    for (int j = jhi; j >= 16 * TJ; --j) {
+      const int jj = j - 16 * TJ, gj = jj & 3, rj = jj >> 2;
+      const double* rc = &S.R[S.perm[j] * G::LDR];
+      const double rinv = 1.0 / rc[j];
+      double rr[NT][4];
 #pragma unroll
-    for (int ti = 0; ti < NT; ++ti) {
-      if (ti > tj) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        const double x = rc[row];
-        rr[ti][r] = (ti < tj || row < j) ? x : 0.0;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < G::CT; ++c) {
-      const double zj = sum_col(L.g == gj ? reg_at<NT>(Y.v[c], tj, rj) : 0.0) * rinv;
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti) {
-        if (ti > tj) continue;
+      for (int ti = 0; ti <= TJ; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = row_of(L, ti, r);
-          if (ti == tj && row == j) Y.v[c][ti][r] = zj;
-          else Y.v[c][ti][r] = fma(-rr[ti][r], zj, Y.v[c][ti][r]);
+          const double x = rc[row_of(L, ti, r)];
+          rr[ti][r] = (ti < TJ || L.g + 4 * r < jj) ? x : 0.0;
         }
+#pragma unroll
+      for (int c = 0; c < G::CT; ++c) {
+        const double zj = sum_col(L.g == gj ? pick4(Y.v[c][TJ], rj) : 0.0) * rinv;
+#pragma unroll
+        for (int ti = 0; ti <= TJ; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (ti == TJ && L.g + 4 * r == jj) Y.v[c][ti][r] = zj;
+            else Y.v[c][ti][r] = fma(-rr[ti][r], zj, Y.v[c][ti][r]);
+          }
       }
     }
-  }
+  });
 }
 
 // left operand of R P^T: column c, rows <= s_c
