@@ -47,16 +47,30 @@ def pair_flops(n, n_direct, n_prop):
     return n_direct * (4.0 + 4.0 / 3.0 + 2.0 + 1.0 + 2.0) * n ** 3 + n_prop * 2.0 * n ** 3
 
 
+def grad_flops(n, m, k):
+    """Gradient per chain: at each checkpoint the product T1 T2^T (2N^3), a
+    pivoted QR (4/3 N^3), Q formation (4/3 N^3), two products (4N^3), the
+    equal-time inversion (about 16/3 N^3); then 4N^3 per wrapped slice."""
+    nb = (m + k - 1) // k
+    return nb * (2.0 + 4.0 / 3.0 + 4.0 / 3.0 + 4.0 + 16.0 / 3.0) * n ** 3 + (m - nb) * 4.0 * n ** 3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="chains in the CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="chains in the CPU sample")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the 512 chains (tests only)")
     ap.add_argument("--profile-only", action="store_true",
                     help="time the batched step only (no equal-time / per-chain extras); for profiler runs")
+    ap.add_argument("--workload", default="hubbard_L8_b40_batch512",
+                    choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
+                             "hubbard_L8_b20_phi_batch128", "hubbard_L16_b40_batch128"],
+                    help="the default is the headline workload; the others time the same library "
+                         "on the mixed-size batch (equal-time G), the continuous-field batch "
+                         "(log|det| + gradient) and the L=16 batch (G + G(tau,0) at every slice)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -82,42 +96,52 @@ def main():
         print(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written",
               file=sys.stderr, flush=True)
         del src, dst
-    W = wl.workload("hubbard_L8_b40_batch512", scale=args.scale)
+    W = wl.workload(args.workload, scale=args.scale)
     insts = W.instances
-    l_list = W.l_list
+    l_list = W.l_list or []
+    kind = {"hubbard_L8_b40_batch512": "tdisp", "hubbard_L16_b40_batch128": "tdisp",
+            "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
-    print(f"[bench] {W.name}: {cnt} chains, n={n}, m={m}, k={k}, {len(l_list)} G(tau,0) each",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {W.name}: {cnt} chains, n={sorted({I.n for I in insts})}, m={m}, k={k}, "
+          f"{len(l_list)} G(tau,0) each", file=sys.stderr, flush=True)
 
-    # inputs resident in HBM before timing (flavours share their field tensor)
-    E = torch.from_numpy(insts[0].expk).to(dev)
-    Ei = torch.from_numpy(insts[0].expk_inv).to(dev)
-    fields = {}
-    chains = []
-    for I in insts:
-        key = id(I.field)
-        if key not in fields:
-            fields[key] = torch.from_numpy(np.ascontiguousarray(I.field)).to(dev)
-        chains.append(sdq.Chain(E, fields[key], I.alpha, I.k, Ei))
+    # inputs resident in HBM before timing (instances share their operator and
+    # field tensors where the workload shares them)
+    dcache = {}
+
+    def dev_of(a):
+        if id(a) not in dcache:
+            dcache[id(a)] = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        return dcache[id(a)]
+
+    chains = [sdq.Chain(dev_of(I.expk), dev_of(I.field), I.alpha, I.k, dev_of(I.expk_inv)) for I in insts]
     ctx = sdq.Context(0)
     # outputs preallocated once
     import ctypes
-    inst_arr = ctx._instances(chains)
-    ls = (ctypes.c_int32 * len(l_list))(*l_list)
-    gts = [torch.empty(len(l_list), n, n, dtype=torch.float64, device=dev) for _ in chains]
-    gs = [torch.empty(n, n, dtype=torch.float64, device=dev) for _ in chains]
+    inst_arr = ctx._instances(chains, need_inv=(kind == "grad"))
+    ls = (ctypes.c_int32 * max(len(l_list), 1))(*l_list)
+    gts = [torch.empty(len(l_list), I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
+        if kind == "tdisp" else []
+    gs = [torch.empty(I.n, I.n, dtype=torch.float64, device=dev) for I in insts] if kind != "grad" else []
+    grads = [torch.empty(I.m, I.n, dtype=torch.float64, device=dev) for I in insts] if kind == "grad" else []
     ld = torch.empty(cnt, dtype=torch.float64, device=dev)
     sg = torch.empty(cnt, dtype=torch.float64, device=dev)
     st = torch.empty(cnt, dtype=torch.int32, device=dev)
-    gt_ptrs = ctx._ptr_array(gts)
-    g_ptrs = ctx._ptr_array(gs)
+    gt_ptrs = ctx._ptr_array(gts) if gts else None
+    g_ptrs = ctx._ptr_array(gs) if gs else None
+    gr_ptrs = ctx._ptr_array(grads) if grads else None
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
 
     def step():
-        ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, ls, len(l_list),
-                                          gt_ptrs, g_ptrs, ctypes.c_void_p(ld.data_ptr()),
-                                          ctypes.c_void_p(sg.data_ptr()),
-                                          ctypes.c_void_p(st.data_ptr())))
+        if kind == "tdisp":
+            ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, ls, len(l_list),
+                                              gt_ptrs, g_ptrs, vp(ld), vp(sg), vp(st)))
+        elif kind == "greens":
+            ctx._chk(ctx.lib.sdq_greens(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, g_ptrs, vp(ld), vp(sg), vp(st)))
+        else:
+            ctx._chk(ctx.lib.sdq_logdet_grad(ctx.h, ctypes.c_uint64(0), inst_arr, cnt, gr_ptrs,
+                                             vp(ld), vp(sg), vp(st)))
 
     for i in range(args.warmup):
         step()
@@ -134,7 +158,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_sw, ms_sw = ctx.kernel_stats("sweep")
-    n_pa, ms_pa = ctx.kernel_stats("pair")
+    n_pa, ms_pa = ctx.kernel_stats("grad" if kind == "grad" else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -142,18 +166,24 @@ def main():
           f"{n_sw}, pair {ms_pa / max(n_pa, 1):.3f} ms x {n_pa}", file=sys.stderr, flush=True)
     status_ok = int((st != 0).sum().item()) == 0
 
-    sweeps = 2 * cnt
-    f_sweep = sweeps * sweep_flops(n, m, k)
-    n_direct = len(l_list)
-    f_pair = cnt * pair_flops(n, n_direct, 0)
-    f_equal = cnt * (4.0 / 3.0 + 2.0 + 1.0 + 2.0) * n ** 3
+    sweeps_per_chain = 1 if kind == "greens" else 2
+    f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
+    if kind == "tdisp":
+        # l a multiple of k (or m) is a direct inversion, the others propagate
+        n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
+        f_pair = sum(pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
+    elif kind == "grad":
+        f_pair = sum(grad_flops(I.n, I.m, I.k) for I in insts)
+    else:
+        f_pair = 0.0
+    f_equal = sum((4.0 / 3.0 + 2.0 + 1.0 + 2.0) * I.n ** 3 for I in insts)
     sweep_avg_s = ms_sw / max(n_sw, 1) * 1e-3
     pair_avg_s = ms_pa / max(n_pa, 1) * 1e-3
     achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
 
     eq_rate = per_inst_rate = None
-    if not args.profile_only:
+    if not args.profile_only and kind == "tdisp":
         # equal-time only, same batch (one forward sweep per chain)
         ctx.greens(chains)
         torch.cuda.synchronize()
@@ -174,10 +204,23 @@ def main():
         torch.cuda.synchronize()
         per_inst_rate = len(sub) / (time.perf_counter() - t3)
 
+    if args.workload == "hubbard_L8_b40_batch512":
+        metric = "stabilized Green's functions/sec (FP64, L=8, beta=40, batched)"
+        unit = "chains/s (each: G + 40 G(tau,0))"
+    elif kind == "tdisp":
+        metric = f"stabilized Green's functions/sec (FP64, {W.name})"
+        unit = f"chains/s (each: G + {len(l_list)} G(tau,0))"
+    elif kind == "greens":
+        metric = f"equal-time Green's functions/sec (FP64, {W.name})"
+        unit = "chains/s (each: G, log|det|, sign)"
+    else:
+        metric = f"log|det| + adjoint gradients/sec (FP64, {W.name})"
+        unit = "chains/s (each: log|det| and its gradient over all M x N field entries)"
+    betas = sorted({round(I.m * I.dtau, 6) for I in insts})
     out = {
-        "metric": "stabilized Green's functions/sec (FP64, L=8, beta=40, batched)",
+        "metric": metric,
         "value": cnt / (ms_step * 1e-3),
-        "unit": "chains/s (each: G + 40 G(tau,0))",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -187,23 +230,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": W.name, "chains": cnt, "n": n, "m": m, "k": k, "beta": 40.0,
-                   "dtau": 0.1, "U": 4.0, "l_list": "10,20,...,400", "scheme": "loh"},
+        "config": {"workload": W.name, "chains": cnt, "n": sorted({I.n for I in insts}),
+                   "m": sorted({I.m for I in insts}), "k": k, "beta": betas, "dtau": 0.1,
+                   "l_list": (f"{l_list[0]},{l_list[1]},...,{l_list[-1]}" if len(l_list) > 2 else l_list),
+                   "scheme": "loh"},
         "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_MFMA, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP64_MFMA,
+                     "traffic": measured_traffic() if args.workload == "hubbard_L8_b40_batch512" else None,
                      "flops_per_launch": f_sweep, "launch_ms": sweep_avg_s * 1e3},
         "pair_kernel": {"launch_ms": pair_avg_s * 1e3, "flops_per_launch": f_pair,
                         "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
         "equal_kernel": {"launch_ms": ms_eq / max(n_eq, 1)},
         "step_tflops": total_flops / (ms_step * 1e-3) / 1e12,
-        "green_matrices_per_s": cnt * (1 + len(l_list)) / (ms_step * 1e-3),
+        "green_matrices_per_s": (cnt * (1 + len(l_list)) / (ms_step * 1e-3)) if kind != "grad" else None,
         "equal_time_only_per_s": eq_rate,
         "per_instance_loop_per_s": per_inst_rate,
         "status_ok": status_ok,
     }
 
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512":
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

@@ -197,6 +197,11 @@ __device__ __forceinline__ int pivot_col(double key) {
 }
 
 // exact power-of-two scale that brings x near 1 (1 for 0, inf, nan)
+// its exact inverse (dividing by a power of two is a multiplication)
+__device__ __forceinline__ double pow2_unscale(double x) {
+  if (!(x > 0.0) || !isfinite(x)) return 1.0;
+  return ldexp(1.0, ilogb(x));
+}
 __device__ __forceinline__ double pow2_scale(double x) {
   if (!(x > 0.0) || !isfinite(x)) return 1.0;
   return ldexp(1.0, -ilogb(x));
@@ -343,7 +348,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
-  double vn1[CT], vn2[CT], sv2[CT];  // sv2: exact power-of-two scale of vn2
+  double vn1[CT], vn2[CT], sv2[CT], iv2[CT];  // sv2: exact power-of-two scale of vn2, iv2 = 1/sv2
   int ps[CT];  // -1: live, not yet chosen; else the step (padding: own index)
 
 #pragma unroll
@@ -357,7 +362,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
 #pragma unroll
       for (int r = 0; r < 4; ++r) mx = fmax(mx, fabs(A.v[c][ti][r]));
     mx = max_col(mx);
-    const double sc = pow2_scale(mx);
+    const double sc = pow2_scale(mx), usc = pow2_unscale(mx);
     double s = 0.0;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
@@ -367,9 +372,10 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         s = fma(x, x, s);
       }
     s = sum_col(s);
-    vn1[c] = sqrt(s) / sc;
+    vn1[c] = sqrt(s) * usc;
     vn2[c] = vn1[c];
     sv2[c] = pow2_scale(vn2[c]);
+    iv2[c] = pow2_unscale(vn2[c]);
   }
 
   int buf = 0;
@@ -415,7 +421,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
 
       // ---- reflector (every wave computes the same one from the same data);
       // rows <= j masked in tile TJ only, tiles below TJ never touched
-      const double sc = pow2_scale(vpiv);
+      const double sc = pow2_scale(vpiv), usc = pow2_unscale(vpiv);
       double v[NT][4];
       double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
 #pragma unroll
@@ -430,7 +436,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         }
       double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
       const double as = alpha * sc;
-      const double hn = sqrt(fma(as, as, s)) / sc;  // ||x[j:]||
+      const double hn = sqrt(fma(as, as, s)) * usc;  // ||x[j:]||
       double tau = 0.0, beta = alpha, inv = 0.0;
       if (s != 0.0) {
         beta = -copysign(hn, alpha);
@@ -488,7 +494,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
             need = true;
             rec[c] = true;
           } else {
-            vn1[c] = sqrt(q) / sv2[c];
+            vn1[c] = sqrt(q) * iv2[c];
           }
         }
       }
@@ -503,7 +509,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
             for (int r = 0; r < 4; ++r)
               if (ti > TJ || L.g + 4 * r > jj) mx = fmax(mx, fabs(A.v[c][ti][r]));
           mx = max_col(mx);
-          const double sc2 = pow2_scale(mx);
+          const double sc2 = pow2_scale(mx), usc2 = pow2_unscale(mx);
           double s2 = 0.0;
 #pragma unroll
           for (int ti = TJ; ti < NT; ++ti)
@@ -514,11 +520,12 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
                 s2 = fma(y, y, s2);
               }
           s2 = sum_col(s2);
-          const double nn = sqrt(s2) / sc2;
+          const double nn = sqrt(s2) * usc2;
           if (rec[c]) {
             vn1[c] = nn;
             vn2[c] = nn;
             sv2[c] = pow2_scale(nn);
+            iv2[c] = pow2_unscale(nn);
           }
         }
       }
@@ -622,18 +629,28 @@ __device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, R
   });
 }
 
-// Y <- Q^T Y = H_{n-1} ... H_0 Y
+// Y <- Q^T Y = H_{n-1} ... H_0 Y.  Inside a tile the next reflector is read
+// from LDS while the current one is applied.
 template <int NT, int P, bool ELDS>
 __device__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
   static_for<NT>([&](auto tjc) {
     constexpr int TJ = decltype(tjc)::value;
     const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
+    if (jend <= 16 * TJ) return;
+    double v[NT][4], vn[NT][4];
+    load_reflector<TJ, NT, P, ELDS>(L, S, 16 * TJ, vn);
+    double tn = S.tau[16 * TJ];
     for (int j = 16 * TJ; j < jend; ++j) {
-      const double tau = S.tau[j];
-      if (tau == 0.0) continue;
-      double v[NT][4];
-      load_reflector<TJ, NT, P, ELDS>(L, S, j, v);
-      apply_reflector<TJ, NT, P>(L, tau, v, Y);
+      const double tau = tn;
+#pragma unroll
+      for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[ti][r] = vn[ti][r];
+      if (j + 1 < jend) {
+        load_reflector<TJ, NT, P, ELDS>(L, S, j + 1, vn);
+        tn = S.tau[j + 1];
+      }
+      if (tau != 0.0) apply_reflector<TJ, NT, P>(L, tau, v, Y);
     }
   });
 }
