@@ -424,11 +424,17 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
       const double sc = pow2_scale(vpiv), usc = pow2_unscale(vpiv);
       double v[NT][4];
       double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
+      // all LDS reads of the pivot column first, one wait for them
+#pragma unroll
+      for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[ti][r] = xc[row_of(L, ti, r)];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          double x = xc[row_of(L, ti, r)];
+          double x = v[ti][r];
           if (ti == TJ && L.g + 4 * r <= jj) x = 0.0;
           v[ti][r] = x;
           const double y = x * sc;
@@ -578,18 +584,17 @@ __device__ __forceinline__ void load_reflector(const Lane& L, const Smem<NT, P, 
                                                double (&v)[NT][4]) {
   const int jj = j - 16 * TJ;
   const double* vc = &S.R[S.perm[j] * Geo<NT, P>::LDR];
+  // all LDS reads first (one wait), then the masking of tile TJ
 #pragma unroll
   for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double x = vc[row_of(L, ti, r)];
-      if (ti > TJ) {
-        v[ti][r] = x;
-      } else {
-        const int q = L.g + 4 * r;
-        v[ti][r] = q > jj ? x : (q == jj ? 1.0 : 0.0);
-      }
-    }
+    for (int r = 0; r < 4; ++r) v[ti][r] = vc[row_of(L, ti, r)];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = L.g + 4 * r;
+    v[TJ][r] = q > jj ? v[TJ][r] : (q == jj ? 1.0 : 0.0);
+  }
 }
 
 // X <- H_j X for all column blocks (tiles below TJ untouched)
@@ -670,10 +675,10 @@ __device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& 
 #pragma unroll
       for (int ti = 0; ti <= TJ; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double x = rc[row_of(L, ti, r)];
-          rr[ti][r] = (ti < TJ || L.g + 4 * r < jj) ? x : 0.0;
-        }
+        for (int r = 0; r < 4; ++r) rr[ti][r] = rc[row_of(L, ti, r)];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rr[TJ][r] = L.g + 4 * r < jj ? rr[TJ][r] : 0.0;
 #pragma unroll
       for (int c = 0; c < G::CT; ++c) {
         const double zj = sum_col(L.g == gj ? pick4(Y.v[c][TJ], rj) : 0.0) * rinv;
