@@ -442,12 +442,18 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         }
       double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
       const double as = alpha * sc;
-      const double hn = sqrt(fma(as, as, s)) * usc;  // ||x[j:]||
       double tau = 0.0, beta = alpha, inv = 0.0;
       if (s != 0.0) {
-        beta = -copysign(hn, alpha);
-        tau = (beta - alpha) / beta;
-        inv = 1.0 / (alpha - beta);
+        // with q = ||x[j:]||^2 (scaled) and r = 1/sqrt(q):  beta = -sign(alpha) q r,
+        // tau = (beta - alpha)/beta = 1 + |alpha| / ||x||, 1/(alpha - beta) =
+        // sign(alpha) / (|alpha| + ||x||): one reciprocal square root and one
+        // division on the dependency chain instead of a square root and two
+        const double q = fma(as, as, s);
+        const double r = rsqrt(q);
+        const double hq = q * r;  // ||x[j:]|| * sc
+        beta = -copysign(hq * usc, alpha);
+        tau = fma(fabs(as), r, 1.0);
+        inv = copysign(sc, alpha) / (fabs(as) + hq);
       }
 #pragma unroll
       for (int ti = TJ; ti < NT; ++ti)
