@@ -22,10 +22,14 @@
 //     operation that needs whole rows (T update, Q formation, Q^T
 //     application, triangular solve, the time-displaced and gradient
 //     products) reads them from there.
-// Gang barriers are a monotonic counter in HBM with device-scope fences.
-// The launch is cooperative, so all members of every gang are resident; a
-// wait still gives up after a few seconds (abort flag, status SDQ_ERANGE)
-// instead of spinning forever.
+// Inside a QR step the candidates go through device-scope atomic stores and
+// loads, and the published keys (tagged with the step) are the barrier:
+// every wave polls the G keys until all carry the current tag.  Bulk data
+// (R P^T, reflectors, G) is exchanged with normal stores behind a barrier on
+// a monotonic counter in HBM with device-scope fences.  The launch is
+// cooperative, so all members of every gang are resident; a wait still gives
+// up after a few seconds (abort flag, status SDQ_ERANGE) instead of spinning
+// forever.
 //
 // Paper passages: slice products and stage loop Sec. 4.1; pivoted QR and
 // UDT Sec. 4.2.2; equal-time inversion Sec. 5.1 (Loh's split, mirror form);
@@ -148,15 +152,20 @@ __device__ __forceinline__ double pow2_scale(double x) {
   return ldexp(1.0, -ilogb(x));
 }
 
-// Pivot key: the norm's bits with the 11 lowest mantissa bits replaced by
-// 2047 - column (largest norm wins; among norms equal to 2^-41 relative the
-// smallest column).  0 = no candidate.
+// Pivot key: bits 63..16 the norm's top 48 bits, bits 15..11 a step tag,
+// bits 10..0 2047 - column.  Among keys of one step the largest norm wins
+// and, among norms equal to 2^-36 relative, the smallest column.  A member
+// with no live column publishes the tag alone.
 __device__ __forceinline__ unsigned long long pivot_key(double norm, int col) {
   double x = norm >= 0.0 ? norm : 0.0;  // NaN -> 0
   x = x < 1.0e300 ? x : 1.0e300;
-  return ((unsigned long long)__double_as_longlong(x) & ~0x7FFull) | (unsigned long long)(2047 - col);
+  return ((unsigned long long)__double_as_longlong(x) & ~0xFFFFull) | (unsigned long long)(2047 - col);
 }
 __device__ __forceinline__ int key_col(unsigned long long k) { return 2047 - (int)(k & 0x7FF); }
+__device__ __forceinline__ unsigned long long tag_key(unsigned long long k, int p) {
+  return (k & ~0xF800ull) | ((unsigned long long)(p & 31) << 11);
+}
+__device__ __forceinline__ int key_tag(unsigned long long k) { return (int)((k >> 11) & 31); }
 
 // ---- gang barrier ----------------------------------------------------------
 __device__ bool gang_sync(GC& c) {
@@ -191,39 +200,9 @@ __device__ bool gang_sync(GC& c) {
   return good;
 }
 
-// Light gang barrier for data exchanged only through device-scope atomic
-// stores and loads (they are performed at the device coherence point, so no
-// cache write-back or invalidation is needed): every wave waits for its
-// stores to complete, then one thread counts in and waits.
-__device__ bool gang_sync_light(GC& c) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  c.epoch += 1;
-  if (c.t == 0) {
-    const unsigned target = c.epoch * (unsigned)c.geo.G;
-    __hip_atomic_fetch_add(&c.bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int good = 1;
-    const unsigned long long t0 = wall_clock64();
-    for (;;) {
-      const unsigned v = __hip_atomic_load(&c.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= target) break;
-      if (__hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-        good = 0;
-        break;
-      }
-      if (wall_clock64() - t0 > kSpinTicks) {
-        __hip_atomic_exchange(&c.bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        good = 0;
-        break;
-      }
-    }
-    L.ok = good;
-  }
-  __syncthreads();
-  const bool good = L.ok != 0;
-  c.ok = c.ok && good;
-  return good;
-}
+// Data exchanged between members inside a QR step goes through device-scope
+// atomic stores and loads: they are performed at the device coherence point,
+// so no cache write-back or invalidation is needed (see wait_keys).
 __device__ __forceinline__ void st_coh(double* p, double x) {
   __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -410,7 +389,35 @@ __device__ void publish_candidate(GC& c, int p) {
       const double* col = L.S + cc * c.geo.ldr;
       for (int i = p + c.l; i < c.n; i += 64) st_coh(out + i, col[i]);
     }
-    if (c.l == 0) st_coh_u64(out + c.geo.npad, k);
+    // the column is complete at the coherence point before its key appears
+    __builtin_amdgcn_s_waitcnt(0);
+    if (c.l == 0) st_coh_u64(out + c.geo.npad, tag_key(k, p));
+  }
+}
+
+// Every wave waits until all G keys of step p carry its tag (the keys are
+// both the data and the barrier of a QR step) and returns the largest.  On a
+// timeout, or when another member has given up, the gang is marked broken
+// and the (meaningless) current maximum is returned; later waits return at
+// once.
+__device__ unsigned long long wait_keys(GC& c, const double* cb, int p) {
+  const int G = c.geo.G;
+  const int64_t stride = gang_cand_stride(c.geo);
+  const unsigned long long t0 = wall_clock64();
+  for (;;) {
+    unsigned long long k = 0ull;
+    bool here = true;
+    if (c.l < G) {
+      k = ld_coh_u64(cb + (int64_t)c.l * stride + c.geo.npad);
+      here = key_tag(k) == (p & 31);
+    }
+    if (__all(here) || !c.ok) return wave_max_u64(k);
+    const bool abort = __hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (abort || wall_clock64() - t0 > kSpinTicks) {
+      if (!abort && c.l == 0) __hip_atomic_exchange(&c.bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      c.ok = false;
+      return wave_max_u64(k);
+    }
   }
 }
 
@@ -436,8 +443,18 @@ __device__ double col_norm(const double* col, int lo, int n, int l) {
 // column-major npad x npad, visible to the whole gang.
 template <int kRL>
 __device__ void cpqr_gang(GC& c) {
-  const int n = c.n, ldr = c.geo.ldr, G = c.geo.G;
+  const int n = c.n, ldr = c.geo.ldr;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  // Reset this member's two key slots to tag 31 (the slots may hold keys of
+  // an earlier QR or launch whose tags would match steps 0 and 1; tag 31 is
+  // not expected before step 31, when both slots hold this QR's keys), and
+  // make the resets visible to the gang before any step's keys are polled.
+  if (c.t == 0) {
+    const int64_t st = gang_cand_stride(c.geo);
+    st_coh_u64(sc_cand(c, 0) + (int64_t)c.g * st + c.geo.npad, tag_key(0ull, 31));
+    st_coh_u64(sc_cand(c, 1) + (int64_t)c.g * st + c.geo.npad, tag_key(0ull, 31));
+  }
+  gang_sync(c);
   for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
     const int gc = c.c0 + cc;
     const double nrm = gc < n ? col_norm(L.S + cc * ldr, 0, n, c.l) : 0.0;
@@ -449,13 +466,10 @@ __device__ void cpqr_gang(GC& c) {
   }
   __syncthreads();
   publish_candidate(c, 0);
-  gang_sync_light(c);
   const int nrl = (n + 63) / 64;
   for (int p = 0; p < n; ++p) {
     const double* cb = sc_cand(c, p & 1);
-    unsigned long long key = 0ull;
-    if (c.l < G) key = ld_coh_u64(cb + (int64_t)c.l * gang_cand_stride(c.geo) + c.geo.npad);
-    key = wave_max_u64(key);
+    const unsigned long long key = wait_keys(c, cb, p);
     int gw = key_col(key);
     gw = gw < 0 ? 0 : (gw >= n ? n - 1 : gw);
     const int owner = gw / c.geo.w;
@@ -569,10 +583,7 @@ __device__ void cpqr_gang(GC& c) {
         L.vn2[cc] = n2;
       }
     }
-    if (p + 1 < n) {
-      publish_candidate(c, p + 1);
-      gang_sync_light(c);
-    }
+    if (p + 1 < n) publish_candidate(c, p + 1);
   }
   __syncthreads();
   // R P^T and the reflectors to HBM
