@@ -280,7 +280,8 @@ class LogDet1pB(torch.autograd.Function):
     def forward(ctx, field, expk, expk_inv, alpha, k):
         c = context(field.device.index)
         chains = [Chain(expk, field[i], alpha, k, expk_inv) for i in range(field.shape[0])]
-        ld, sg, stt, hnd = c.logdet(chains, keep=True)
+        # keep the forward stages for the backward only when one will follow
+        ld, sg, stt, hnd = c.logdet(chains, keep=bool(ctx.needs_input_grad[0]))
         ctx.handle = hnd
         ctx.sdq = c
         ctx.args = (expk, expk_inv, alpha, k)
@@ -294,9 +295,15 @@ class LogDet1pB(torch.autograd.Function):
         expk, expk_inv, alpha, k = ctx.args
         c = ctx.sdq
         chains = [Chain(expk, field[i], alpha, k, expk_inv) for i in range(field.shape[0])]
-        try:
-            grads, _, _, _ = c.logdet_grad(chains, handle=ctx.handle)
-        finally:
-            c.release(ctx.handle)
+        if ctx.handle:
+            # first backward: reuse the forward stages, then free them
+            try:
+                grads, _, _, _ = c.logdet_grad(chains, handle=ctx.handle)
+            finally:
+                c.release(ctx.handle)
+                ctx.handle = 0
+        else:
+            # a repeated backward (retain_graph) recomputes the forward stages
+            grads, _, _, _ = c.logdet_grad(chains)
         grad = torch.stack(grads) * g_ld.view(-1, 1, 1)
         return grad, None, None, None, None
