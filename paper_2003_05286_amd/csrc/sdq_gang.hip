@@ -603,90 +603,151 @@ __device__ void cpqr_gang(GC& c) {
   gang_sync(c);
 }
 
-// Apply reflectors j = jlo .. jhi (ascending: Q^T, descending: Q) to the own
-// columns of the slab, one wave per column, reflector rows from sc_V.
+// Row q of a column distributed over the wave (row i in lane i % 64, slot
+// i / 64), broadcast to every lane; q is wave-uniform.
+template <int RL>
+__device__ __forceinline__ double row_of_col(const double (&y)[RL], int q) {
+  const int slot = q >> 6;
+  double x = y[0];
+#pragma unroll
+  for (int r = 1; r < RL; ++r) x = slot == r ? y[r] : x;
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), q & 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), q & 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Apply the reflectors of the last QR to the own columns of the slab:
+// ascending (Q^T) or descending (Q; with identity_cols the columns start as
+// unit vectors, and reflectors beyond the largest own column leave them
+// unchanged).  Each wave holds its own columns in registers (up to 16 / kRL
+// of them), reads each reflector once from sc_V (the next one while the
+// current one is applied) and applies it to all of them.
 template <bool ASC, int kRL>
 __device__ void apply_reflectors(GC& c, bool identity_cols) {
+  constexpr int CM = 16 / kRL;
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* V = sc_V(c);
   const int nrl = (n + 63) / 64;
-  for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
-    const int gc = c.c0 + cc;
-    if (gc >= n) continue;
-    double* col = L.S + cc * ldr;
-    double y[kRL];
+  for (int s0 = 0; c.w + kWaves * s0 < c.geo.w; s0 += CM) {
+    double y[CM][kRL];
+    int jmax = -1;
 #pragma unroll
-    for (int s = 0; s < kRL; ++s) {
-      const int i = c.l + 64 * s;
-      y[s] = (s < nrl && i < n) ? col[i] : 0.0;
+    for (int s = 0; s < CM; ++s) {
+      const int cc = c.w + kWaves * (s0 + s), gc = c.c0 + cc;
+      const bool on = cc < c.geo.w && gc < n;
+      if (on) jmax = max(jmax, identity_cols ? gc : n - 1);
+#pragma unroll
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        y[s][r] = (on && r < nrl && i < n) ? L.S[cc * ldr + i] : 0.0;
+      }
     }
-    // Q e_gc needs reflectors j <= gc only (H_j fixes e_gc for j > gc)
-    const int jmax = identity_cols ? gc : n - 1;
-    for (int jj = 0; jj <= jmax; ++jj) {
-      const int j = ASC ? jj : jmax - jj;
-      const double tj = L.tau[j];
-      if (tj == 0.0) continue;
+    auto load = [&](int j, double (&v)[kRL], double& t) {
+      t = L.tau[j];
       int pc = L.piv[j];
       pc = pc < 0 ? 0 : (pc >= n ? n - 1 : pc);
       const double* vc = V + (int64_t)pc * np;
-      double v[kRL];
-      double d = 0.0;
 #pragma unroll
-      for (int s = 0; s < kRL; ++s) {
-        const int i = c.l + 64 * s;
-        v[s] = (s < nrl && i > j && i < n) ? vc[i] : (i == j ? 1.0 : 0.0);
-        d += v[s] * y[s];
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        v[r] = (r < nrl && i > j && i < n) ? vc[i] : (i == j ? 1.0 : 0.0);
       }
-      const double tv = tj * wave_sum(d);
+    };
+    double vn[kRL], tn = 0.0;
+    if (jmax >= 0) load(ASC ? 0 : jmax, vn, tn);
+    for (int jj = 0; jj <= jmax; ++jj) {
+      double v[kRL];
 #pragma unroll
-      for (int s = 0; s < kRL; ++s) y[s] -= tv * v[s];
+      for (int r = 0; r < kRL; ++r) v[r] = vn[r];
+      const double tj = tn;
+      if (jj < jmax) load(ASC ? jj + 1 : jmax - jj - 1, vn, tn);
+      if (tj == 0.0) continue;
+      double d[CM];
+#pragma unroll
+      for (int s = 0; s < CM; ++s) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRL; ++r) a = fma(v[r], y[s][r], a);
+        d[s] = a;
+      }
+#pragma unroll
+      for (int s = 0; s < CM; ++s) d[s] = tj * wave_sum(d[s]);
+#pragma unroll
+      for (int s = 0; s < CM; ++s)
+#pragma unroll
+        for (int r = 0; r < kRL; ++r) y[s][r] = fma(-d[s], v[r], y[s][r]);
     }
 #pragma unroll
-    for (int s = 0; s < kRL; ++s) {
-      const int i = c.l + 64 * s;
-      if (s < nrl && i < n) col[i] = y[s];
+    for (int s = 0; s < CM; ++s) {
+      const int cc = c.w + kWaves * (s0 + s), gc = c.c0 + cc;
+      if (cc >= c.geo.w || gc >= n) continue;
+#pragma unroll
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        if (r < nrl && i < n) L.S[cc * ldr + i] = y[s][r];
+      }
     }
   }
   __syncthreads();
 }
 
 // S <- R^{-1} S (R upper triangular in pivot order: R[i][q] = sc_R[piv[q]][i]),
-// one wave per column.
+// own columns in registers as above, each column of R read once per wave.
 template <int kRL>
 __device__ void back_subst(GC& c) {
+  constexpr int CM = 16 / kRL;
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* R = sc_R(c);
   const int nrl = (n + 63) / 64;
-  for (int cc = c.w; cc < c.geo.w; cc += kWaves) {
-    const int gc = c.c0 + cc;
-    if (gc >= n) continue;
-    double* col = L.S + cc * ldr;
-    double y[kRL];
+  for (int s0 = 0; c.w + kWaves * s0 < c.geo.w; s0 += CM) {
+    double y[CM][kRL];
 #pragma unroll
-    for (int s = 0; s < kRL; ++s) {
-      const int i = c.l + 64 * s;
-      y[s] = (s < nrl && i < n) ? col[i] : 0.0;
+    for (int s = 0; s < CM; ++s) {
+      const int cc = c.w + kWaves * (s0 + s), gc = c.c0 + cc;
+      const bool on = cc < c.geo.w && gc < n;
+#pragma unroll
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        y[s][r] = (on && r < nrl && i < n) ? L.S[cc * ldr + i] : 0.0;
+      }
     }
-    for (int q = n - 1; q >= 0; --q) {
+    auto load = [&](int q, double (&rv)[kRL]) {
       int pc = L.piv[q];
       pc = pc < 0 ? 0 : (pc >= n ? n - 1 : pc);
       const double* rc = R + (int64_t)pc * np;
-      double zq = 0.0;
 #pragma unroll
-      for (int s = 0; s < kRL; ++s)
-        if (c.l + 64 * s == q) zq = y[s];
-      const double xq = wave_sum(zq) / L.beta[q];
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        rv[r] = (r < nrl && i < q) ? rc[i] : 0.0;
+      }
+    };
+    double rn[kRL];
+    load(n - 1, rn);
+    for (int q = n - 1; q >= 0; --q) {
+      double rv[kRL];
 #pragma unroll
-      for (int s = 0; s < kRL; ++s) {
-        const int i = c.l + 64 * s;
-        if (s < nrl && i < q) y[s] -= rc[i] * xq;
-        if (i == q) y[s] = xq;
+      for (int r = 0; r < kRL; ++r) rv[r] = rn[r];
+      if (q > 0) load(q - 1, rn);
+      const double rb = 1.0 / L.beta[q];
+#pragma unroll
+      for (int s = 0; s < CM; ++s) {
+        const double xq = row_of_col<kRL>(y[s], q) * rb;
+#pragma unroll
+        for (int r = 0; r < kRL; ++r) {
+          const int i = c.l + 64 * r;
+          y[s][r] = i == q ? xq : fma(-rv[r], xq, y[s][r]);
+        }
       }
     }
 #pragma unroll
-    for (int s = 0; s < kRL; ++s) {
-      const int i = c.l + 64 * s;
-      if (s < nrl && i < n) col[i] = y[s];
+    for (int s = 0; s < CM; ++s) {
+      const int cc = c.w + kWaves * (s0 + s), gc = c.c0 + cc;
+      if (cc >= c.geo.w || gc >= n) continue;
+#pragma unroll
+      for (int r = 0; r < kRL; ++r) {
+        const int i = c.l + 64 * r;
+        if (r < nrl && i < n) L.S[cc * ldr + i] = y[s][r];
+      }
     }
   }
   __syncthreads();
