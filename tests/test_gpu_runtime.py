@@ -74,3 +74,48 @@ def test_autotune_cache_and_parity(tmp_path):
             assert relF(gs[a].cpu().numpy(), G) <= 1e-10
             assert abs(ld[a].item() - ldo) <= 1e-12 * abs(ldo)
     ctx.close()
+
+
+def test_graph_mode_with_gang_chains_runs_directly():
+    """A batch with an n > 128 chain (cooperative launches) in graph mode is
+    launched directly; repeated calls equal the eager result."""
+    ctx = sdq.Context(0)
+    insts = wl.hubbard_ising(12, 2.0, 1, 1, seed=wl.BASE_SEED + 720) + \
+        wl.hubbard_ising(4, 2.0, 1, 1, seed=wl.BASE_SEED + 721)
+    ch = chains_of(insts)
+    say("[gpu] graph mode, mixed n = 144 and 16")
+    gs0, ld0, _, st0 = ctx.greens(ch)
+    torch.cuda.synchronize()
+    ctx.set_graphs(True)
+    for rep in range(3):
+        gs, ld, _, st = ctx.greens(ch)
+        torch.cuda.synchronize()
+        for a in range(len(ch)):
+            assert torch.equal(gs[a], gs0[a]), (rep, a)
+        assert torch.equal(ld, ld0) and (st.cpu().numpy() == 0).all()
+    ctx.set_graphs(False)
+    ctx.close()
+
+
+def test_tune_accepts_large_sizes(tmp_path):
+    """Sizes above 128 have one kernel: accepted, nothing timed or cached."""
+    path = str(tmp_path / "tune.jsonl")
+    ctx = sdq.Context(0)
+    say("[gpu] sdq_tune n = 16, 144")
+    ctx.tune([16, 144], path)
+    lines = [json.loads(l) for l in open(path)]
+    assert [l["n"] for l in lines] == [16]
+    ctx.close()
+
+
+def test_gang_status_flags_nonfinite_field():
+    ctx = sdq.Context(0)
+    I = wl.hubbard_ising(12, 2.0, 1, 1, seed=wl.BASE_SEED + 722)[0]
+    f = I.field.copy()
+    f[5, 17] = np.nan
+    I2 = wl.Instance(I.L, I.m, I.k, I.alpha, f, I.expk, I.expk_inv)
+    say("[gpu] gang sdq_greens with a NaN in the field")
+    _, _, _, st = ctx.greens(chains_of([I, I2]))
+    torch.cuda.synchronize()
+    assert st.cpu().numpy().tolist() == [0, sdq.SDQ_ERANGE]
+    ctx.close()
