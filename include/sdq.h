@@ -55,9 +55,18 @@ typedef enum {
 } sdq_status;
 
 typedef enum {
-  SDQ_INV_LOH = 0,   /* Sec. 5.1 inv_one_plus_loh / Sec. 6.1 inv_sum_loh (default) */
-  SDQ_INV_PLAIN = 1  /* Sec. 5.1 inv_one_plus / Sec. 6.1 inv_sum (not implemented:
-                        returns SDQ_EUNSUPPORTED)                                  */
+  SDQ_INV_LOH = 0,   /* Sec. 5.1 inv_one_plus_loh / Sec. 6.1 inv_sum_loh (default):
+                        the scales of D split into max(D,1) and min(D,1)         */
+  SDQ_INV_PLAIN = 1  /* Sec. 5.1 inv_one_plus / Sec. 6.1 inv_sum: one intermediate
+                        decomposition with D unsplit.  Accurate for the
+                        equal-time G; for G(tau,0) it loses accuracy away from
+                        the ends of [0, beta] (Sec. 6.2) and is provided to show
+                        that, not for production use.  sdq_greens and
+                        sdq_greens_tdisp only.  In sdq_greens_tdisp it
+                        decomposes B(tau,0)^{-1} and B(beta,tau) anew for every
+                        stage pair (O(m^2/k) slice products per chain instead of
+                        O(m)), needs expk_inv, and supports n <= 128
+                        (SDQ_EUNSUPPORTED above).                                 */
 } sdq_scheme;
 
 typedef struct sdq_ctx sdq_ctx;

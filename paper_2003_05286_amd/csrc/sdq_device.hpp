@@ -757,12 +757,15 @@ __device__ double perm_sign(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
 //   G = M^{-1} Dp^{-1} U^T,   M = Dp^{-1} U^T + Dm T,
 // M inverted through its pivoted QR, M P = Q R:  G = P R^{-1} Q^T Dp^{-1} U^T.
 //   det(1 + U D T) = det U * prod(Dp) * det M.
+// With loh = false the same code runs the single-decomposition scheme
+// (Sec. 5.1 inv_one_plus, mirrored): Dp = 1, Dm = D, M = U^T + D T.
 // U, T: register matrices (padding: identity); D: S.dcur.  Returns Z with
 // G[S.perm[s]][c] = Z[s][c] (caller writes it out), and log|det|, sign.
-template <int NT, int P, bool ELDS>
+template <int NT, int P, bool ELDS, bool LOH = true>
 __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, const RM<NT, P>& U,
                              const RM<NT, P>& T, double sgn_u, RM<NT, P>& Z, double* logdet,
                              double* sign) {
+  constexpr bool loh = LOH;
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   // U^T via LDS
@@ -788,15 +791,16 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, c
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
         const double dr = S.dcur[row];
-        const double dp = dr > 1.0 ? dr : 1.0;
-        const double dm = dr < 1.0 ? dr : 1.0;
+        const double dp = (loh && dr > 1.0) ? dr : 1.0;
+        const double dm = (loh && dr > 1.0) ? 1.0 : dr;
         const double ut = tile_ok<NT, P>(L, c) ? S.R[row * G::LDR + col] : 0.0;
         Z.v[c][ti][r] = ut / dp;
         M.v[c][ti][r] = ut / dp + dm * T.v[c][ti][r];
       }
   }
   double lsum = 0.0;
-  for (int t = L.t; t < n; t += G::THREADS) lsum += log(fmax(S.dcur[t], 1.0));
+  if constexpr (loh)
+    for (int t = L.t; t < n; t += G::THREADS) lsum += log(fmax(S.dcur[t], 1.0));
   cpqr<NT, P, ELDS>(L, n, M, S);  // begins with barriers before S.R is overwritten
   for (int t = L.t; t < n; t += G::THREADS) lsum += log(fabs(S.R[S.perm[t] * G::LDR + t]));
   int neg = 0;
@@ -843,17 +847,18 @@ __device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, cons
 }
 
 // ---------------------------------------------------------------------------
-// slice exponentials v_q = exp(alpha f_q) for `cnt` slices into S.vbuf.
-// slice of buffer row s: q0 + dir*s.  Ends with a barrier.
+// slice exponentials v_q = exp(sgn alpha f_q) for `cnt` slices into S.vbuf
+// (sgn = -1: the diagonal of B_q^{-1}).  Slice of buffer row s: q0 + dir*s.
+// Ends with a barrier.
 template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int q0,
-                                          int dir, int cnt) {
+                                          int dir, int cnt, double sgn = 1.0) {
   using G = Geo<NT, P>;
   __syncthreads();
   for (int idx = L.t; idx < cnt * G::NP; idx += G::THREADS) {
     const int s = idx / G::NP, row = idx - s * G::NP;
     const int q = q0 + dir * s;
-    S.vbuf[s][row] = row < I.n ? exp(I.alpha * I.field[(size_t)(q - 1) * I.n + row]) : 1.0;
+    S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * I.field[(size_t)(q - 1) * I.n + row]) : 1.0;
   }
   __syncthreads();
 }
@@ -912,14 +917,26 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
 // the same slice boundaries, so forward stage j and backward stage j meet at
 // tau = min(jk, m).  Per block:  W = X_block U,  W <- W D,  W P = Q R,
 // U <- Q,  D <- |diag R|,  T <- D^{-1} R P^T T.
+// The two chains of the single-decomposition G(tau_j, 0) (Sec. 6: the left
+// one is B(tau_j, 0)^{-1} decomposed as it stands, unitary factor on the left):
+//   SW_RIGHT:  B_m ... B_{tau_j+1}: the forward sweep from block j on;
+//   SW_LEFT:   B_1^{-1} ... B_{tau_j}^{-1}: W <- B_q^{-1} W for q = tau_j
+//              down to 1, B_q^{-1} = diag(exp(-alpha f_q)) expk^{-1}, folded
+//              in every k slices counted from tau_j.
 template <int NT, int P, bool ELDS>
-__device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags) {
+__device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
+                          const int jpair) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
+  const bool left = (flags & SW_LEFT) != 0, right = (flags & SW_RIGHT) != 0;
   const bool adj = (flags & SW_ADJ) != 0;
   const int64_t sd = stage_doubles(n);
-  stage_e<NT, P, ELDS>(L, S, adj ? I.eswt : I.esw);
+  const int tauj = jpair * k < m ? jpair * k : m;
+  const int s_lo = right ? jpair : 0;
+  const int s_hi = left ? (tauj + k - 1) / k : nb;
+  const double* e_op = left ? I.eswi : (adj ? I.eswt : I.esw);
+  stage_e<NT, P, ELDS>(L, S, e_op);
   // W holds U between blocks and the block product inside a block
   RM<NT, P> T, W;
   set_identity<NT, P>(L, W);
@@ -927,18 +944,23 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   double dcol[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
-  const EOp<NT, P, ELDS> eop{S.E, adj ? I.eswt : I.esw, L.l};
+  const EOp<NT, P, ELDS> eop{S.E, e_op, L.l};
 
-  for (int s = 0; s < nb; ++s) {
+  for (int s = s_lo; s < s_hi; ++s) {
     const int b = adj ? nb - 1 - s : s;
-    const int q0 = b * k + 1, q1 = (b + 1) * k < m ? (b + 1) * k : m;
+    int q0 = b * k + 1, q1 = (b + 1) * k < m ? (b + 1) * k : m;
+    if (left) {
+      q1 = tauj - s * k;
+      q0 = q1 - k + 1 > 1 ? q1 - k + 1 : 1;
+    }
     const int cnt = q1 - q0 + 1;
     for (int c0 = 0; c0 < cnt; c0 += G::KB) {
       const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
-      if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
+      if (left) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn, -1.0);
+      else if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
       else fill_vbuf<NT, P, ELDS>(L, S, I, q0 + c0, +1, cn);
       for (int s2 = 0; s2 < cn; ++s2) {
-        if (!adj) {
+        if (!adj && !left) {
           scale_rows<NT, P>(L, W, S.vbuf[s2]);
           gemm_rb<NT, P>(L, eop, W, W);
         } else {
@@ -963,6 +985,8 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     double* dst = nullptr;
     if (flags & SW_STORE) dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
     else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
+    else if (left && s == s_hi - 1) dst = I.ckf + (size_t)(jpair - 1) * sd;
+    else if (right && s == nb - 1) dst = I.cka + (size_t)jpair * sd;
     if (dst) store_stage<NT, P, ELDS>(L, n, S, W, T, sgn_u, dst);
     __syncthreads();
   }
@@ -998,7 +1022,10 @@ __device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   }
   const double sgn_u = F[2 * (size_t)n * n + n];
   double ld, sg;
-  inv_one_plus<NT, P, ELDS>(L, n, S, U, T, sgn_u, Z, &ld, &sg);
+  if (I.scheme == 0)
+    inv_one_plus<NT, P, ELDS, true>(L, n, S, U, T, sgn_u, Z, &ld, &sg);
+  else
+    inv_one_plus<NT, P, ELDS, false>(L, n, S, U, T, sgn_u, Z, &ld, &sg);
   if (!all_finite<NT, P>(L, Z) || !isfinite(ld)) bad = 1;
   if (I.g) store_perm_rows<NT, P, ELDS>(L, n, S, Z, I.g);
   if (L.t == 0) {
@@ -1023,7 +1050,7 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, P, ELDS>(L, S, I, wi.flags);
+    sweep_one<NT, P, ELDS>(L, S, I, wi.flags, wi.j);
   }
 }
 
@@ -1060,6 +1087,11 @@ __device__ __forceinline__ void load_rm_staged(const Lane& L, const Smem<NT, P, 
       }
   }
 }
+
+template <int NT, int P, bool ELDS>
+__device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+                              const int ilo, const int ihi, const int32_t* __restrict__ l_list,
+                              RM<NT, P>& Gm);
 
 // ---------------------------------------------------------------------------
 // Time-displaced G(tau_j, 0) from forward stage F[j] = U1 D1 T1 (of
@@ -1193,8 +1225,18 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
                    Y, Gm);
   }
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  tdisp_outputs<NT, P, ELDS>(L, S, I, j, ilo, ihi, l_list, Gm);
+}
 
-  // outputs: l_list[ilo..ihi), ascending, each in [tau_j, tau_j + k)
+// Outputs of stage pair j from Gm = G(tau_j, 0): l_list[ilo..ihi), ascending,
+// each in [tau_j, tau_j + k), G(tau_l, 0) = B_l ... B_{tau_j + 1} G(tau_j, 0)
+// (Sec. 6, propagation form).
+template <int NT, int P, bool ELDS>
+__device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+                              const int ilo, const int ihi, const int32_t* __restrict__ l_list,
+                              RM<NT, P>& Gm) {
+  using G = Geo<NT, P>;
+  const int n = I.n, m = I.m, k = I.k;
   const int tj = j * k < m ? j * k : m;
   int lc = tj;
   if (ELDS && ihi > ilo && l_list[ihi - 1] > tj) {
@@ -1218,6 +1260,95 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
     store_rm<NT, P>(L, Gm, I.gt + (size_t)idx * n * n, n);
   }
   __syncthreads();
+}
+
+// Time-displaced G(tau_j, 0) by the single-decomposition scheme (Sec. 6.1,
+// inv_sum), from the two chains of stage pair j built by SW_LEFT / SW_RIGHT:
+//   B(tau_j, 0)^{-1} = U_L D_L X_L   (ckf[j-1]; identity for j = 0)
+//   B(beta, tau_j)   = U_R D_R X_R   (cka[j];   identity for j = nb)
+//   G(tau_j, 0) = [U_L D_L X_L + U_R D_R X_R]^{-1} = X_R^{-1} Mid^{-1} U_L^T,
+//   Mid = D_L (X_L X_R^{-1}) + (U_L^T U_R) D_R,
+// with D_L and D_R unsplit and Mid inverted through its pivoted QR.  X_R^{-1}
+// comes from the pivoted QR of X_R and is written over X_R in the stage (this
+// item is the only reader of cka[j]).  Then the outputs of the pair as in
+// the split scheme.
+template <int NT, int P, bool ELDS>
+__device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+                                 const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  const int n = I.n, nb = I.nb;
+  const int64_t sd = stage_doubles(n);
+  const double* F = j > 0 ? I.ckf + (size_t)(j - 1) * sd : nullptr;
+  double* A = j < nb ? I.cka + (size_t)j * sd : nullptr;
+  const double* UL = F;
+  const double* XL = F ? F + (size_t)n * n : nullptr;
+  const double* DL = F ? F + 2 * (size_t)n * n : nullptr;
+  const double* UR = A;
+  double* XRi = A ? A + (size_t)n * n : nullptr;
+  const double* DR = A ? A + 2 * (size_t)n * n : nullptr;
+
+  RM<NT, P> B, P1, P2;
+  if (A) {
+    // X_R P = Q R  ->  X_R^{-1} = P R^{-1} Q^T
+    load_rm<NT, P>(L, P1, XRi, n, false);
+    __syncthreads();
+    cpqr<NT, P, ELDS>(L, n, P1, S);
+    set_identity<NT, P>(L, B);
+    apply_qt<NT, P, ELDS>(L, n, S, B);
+    back_subst<NT, P, ELDS>(L, n, S, B);
+    store_perm_rows<NT, P, ELDS>(L, n, S, B, XRi);
+    __threadfence_block();
+    __syncthreads();
+  }
+  // P1 = X_L X_R^{-1},  P2 = U_L^T U_R
+  load_rm<NT, P>(L, B, XRi, n, false);
+  gemm_rb<NT, P>(L,
+                 [&](int, int, int, int i, int kk) -> double {
+                   if (i >= n || kk >= n) return 0.0;
+                   return XL ? XL[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                 },
+                 B, P1);
+  load_rm<NT, P>(L, B, UR, n, false);
+  gemm_rb<NT, P>(L,
+                 [&](int, int, int, int i, int kk) -> double {
+                   if (i >= n || kk >= n) return 0.0;
+                   return UL ? UL[kk * n + i] : (i == kk ? 1.0 : 0.0);
+                 },
+                 B, P2);
+  double drc[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+    drc[c] = (DR && col < n) ? DR[col] : 1.0;
+  }
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      const double dl = (DL && row < n) ? DL[row] : 1.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) P1.v[c][ti][r] = dl * P1.v[c][ti][r] + P2.v[c][ti][r] * drc[c];
+    }
+  __syncthreads();
+  cpqr<NT, P, ELDS>(L, n, P1, S);
+  // Mid^{-1} U_L^T = P Z,  Z = R^{-1} Q^T U_L^T
+  RM<NT, P> Y;
+  load_rm<NT, P>(L, Y, UL, n, true);
+  apply_qt<NT, P, ELDS>(L, n, S, Y);
+  back_subst<NT, P, ELDS>(L, n, S, Y);
+  // G = X_R^{-1} P Z:  A(i, s) = X_R^{-1}[i][perm s]
+  RM<NT, P> Gm;
+  gemm_rb<NT, P>(L,
+                 [&](int, int, int, int i, int s) -> double {
+                   if (i >= n || s >= n) return 0.0;
+                   const int p = S.perm[s];
+                   return XRi ? XRi[i * n + p] : (i == p ? 1.0 : 0.0);
+                 },
+                 Y, Gm);
+  if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  tdisp_outputs<NT, P, ELDS>(L, S, I, j, ilo, ihi, l_list, Gm);
 }
 
 // Gradient rows for slices l = j*k+1 .. min((j+1)k, m):
@@ -1400,6 +1531,8 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
     if constexpr (MODE == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else if constexpr (MODE == PAIR_TDISP_PLAIN)
+      pair_tdisp_plain<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
     else if constexpr (MODE == PAIR_GRAD) pair_grad<NT, P, ELDS>(L, S, I, wi.j);
     else pair_equal<NT, P, ELDS>(L, S, I);
   }
@@ -1461,6 +1594,9 @@ struct Launch {
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_TDISP>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     else if (mode == PAIR_GRAD)
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_GRAD>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
+    else if (mode == PAIR_TDISP_PLAIN)
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_TDISP_PLAIN>), dim3(grid), b, 0, s, inst, items, count,
+                         l_list, q);
     else
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_EQUAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     return hipGetLastError();

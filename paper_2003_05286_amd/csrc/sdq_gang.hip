@@ -873,7 +873,8 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
 
 // Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1,
 // mirror form): M = Dp^{-1} U^T + Dm T, G = M^{-1} Dp^{-1} U^T,
-// det(1 + U D T) = det U prod(Dp) det M.
+// det(1 + U D T) = det U prod(Dp) det M.  The single-decomposition scheme
+// (inv_one_plus) is the same with Dp = 1, Dm = D.
 template <int kRL>
 __device__ void equal_gang(GC& c, const Inst& I) {
   const int n = I.n;
@@ -881,8 +882,9 @@ __device__ void equal_gang(GC& c, const Inst& I) {
   const double* T = I.fin + (int64_t)n * n;
   const double* D = I.fin + 2 * (int64_t)n * n;
   const double sgn_u = I.fin[2 * (int64_t)n * n + n];
-  auto dp = [&](int i) { const double d = D[i]; return d > 1.0 ? d : 1.0; };
-  auto dm = [&](int i) { const double d = D[i]; return d < 1.0 ? d : 1.0; };
+  const bool loh = I.scheme == 0;
+  auto dp = [&](int i) { const double d = D[i]; return (loh && d > 1.0) ? d : 1.0; };
+  auto dm = [&](int i) { const double d = D[i]; return (loh && d > 1.0) ? 1.0 : d; };
   slab_fill_rows(c, [&](int i, int gc) { return dm(i) * T[(int64_t)i * n + gc]; });
   __syncthreads();
   for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
@@ -907,7 +909,7 @@ __device__ void equal_gang(GC& c, const Inst& I) {
     for (int i = c.l; i < n; i += 64) {
       const double d = D[i];
       if (!isfinite(d) || !(d > 0.0)) bad = 1;
-      ls += log(dp(i)) + log(fabs(L.beta[i]));
+      ls += log(dp(i)) + log(fabs(L.beta[i]));  // dp = 1 without the split
       ng += L.beta[i] < 0.0 ? 1.0 : 0.0;
     }
     ls = wave_sum(ls);
@@ -1259,6 +1261,7 @@ hipError_t launch_gang_sweep(const Inst* inst, const SweepItem* items, int count
 
 hipError_t launch_gang_pair(int mode, const Inst* inst, const PairItem* items, int count,
                             const int32_t* l_list, GangArgs a, hipStream_t s) {
+  if (mode != PAIR_EQUAL && mode != PAIR_TDISP && mode != PAIR_GRAD) return hipErrorInvalidValue;
 #define C(R)                                                                                  \
   (mode == PAIR_EQUAL ? coop_launch(k_gang_pair<PAIR_EQUAL, R>, a, s, inst, items, count, l_list) \
    : mode == PAIR_TDISP ? coop_launch(k_gang_pair<PAIR_TDISP, R>, a, s, inst, items, count, l_list) \

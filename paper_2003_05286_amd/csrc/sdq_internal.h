@@ -26,6 +26,8 @@ struct Inst {
   const double* field;     // [m][n]
   double alpha;
   int32_t n, m, k, nb;     // nb = ceil(m / k) stabilization blocks
+  int32_t scheme;          // 0: Loh's split scales (Sec. 5.1, 6.1), 1: single decomposition
+  int32_t pad0;
   double* g;               // equal-time G [n][n] or null
   double* gt;              // time-displaced outputs [n_l][n][n] or null
   double* grad;            // [m][n] or null
@@ -40,6 +42,7 @@ struct Inst {
   const double* esw;       // expk, zero padded to 16*ceil(n/16) and swizzled
   const double* eswt;      // expk^T, same layout (see launch_swizzle)
   double* fin;             // final forward stage (read by the equal-time inversion)
+  const double* eswi;      // expk_inv in the layout of esw, or null
 };
 
 enum SweepFlags : int32_t {
@@ -47,17 +50,24 @@ enum SweepFlags : int32_t {
   SW_STORE = 2,   // store every stage (ckf for forward, cka for backward)
   SW_LAST = 4,    // store the last stage at fin (implied by SW_STORE forward)
   SW_FINAL = 8,   // write the final U, D, T to u_out / d_out / t_out
+  // chains of one stage pair j of the single-decomposition G(tau_j, 0), each
+  // started at tau_j = min(jk, m) and stabilized every k slices from there:
+  SW_LEFT = 16,   // B_1^{-1} ... B_{tau_j}^{-1}, stored at ckf[j-1]   (j >= 1)
+  SW_RIGHT = 32,  // B_m ... B_{tau_j+1},         stored at cka[j]     (j < nb)
 };
 
 struct SweepItem {
   int32_t inst;
   int32_t flags;
+  int32_t j;  // stage pair of SW_LEFT / SW_RIGHT
+  int32_t pad;
 };
 
-enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2 };
-constexpr int kPairModes = 3;
+enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2, PAIR_TDISP_PLAIN = 3 };
+constexpr int kPairModes = 4;
 
-// tdisp: stage pair j, outputs for l_list[ilo..ihi)
+// tdisp: stage pair j, outputs for l_list[ilo..ihi) (PAIR_TDISP_PLAIN: the
+//        same from the SW_LEFT / SW_RIGHT chains)
 // grad:  stage pair j (slices j*k+1 .. min((j+1)k, m))
 // equal: the final forward stage -> G, logdet, sign
 struct PairItem {

@@ -62,6 +62,7 @@ struct Plan {
     int nt, off, count;
   };
   std::vector<Range> sweep_ranges, pair_ranges[sdq::kPairModes];
+  bool swz_inv = false;  // also lay out expk_inv (chains of B^{-1} slices)
 };
 
 }  // namespace
@@ -299,13 +300,17 @@ struct SwzJob {
 sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
   std::map<std::pair<const double*, int>, int64_t> seen;
   int64_t tot = 0;
-  for (const Inst& I : P.inst) {
-    auto key = std::make_pair(I.expk, I.n);
-    if (seen.count(key)) continue;
-    const int64_t np = 16LL * nt_of(I.n);
+  auto add = [&](const double* e, int n) {
+    auto key = std::make_pair(e, n);
+    if (seen.count(key)) return;
+    const int64_t np = 16LL * nt_of(n);
     seen[key] = tot;
-    jobs.push_back(SwzJob{I.expk, I.n, tot});
+    jobs.push_back(SwzJob{e, n, tot});
     tot += 2 * np * np;
+  };
+  for (const Inst& I : P.inst) {
+    add(I.expk, I.n);
+    if (P.swz_inv && I.expk_inv) add(I.expk_inv, I.n);
   }
   HIP_TRY(grow(ctx->d_swz, (size_t)std::max<int64_t>(tot, 1) * sizeof(double)), "hipMalloc(swizzle)");
   double* base = (double*)ctx->d_swz.p;
@@ -314,6 +319,7 @@ sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
     const int64_t np = 16LL * nt_of(I.n);
     I.esw = base + off;
     I.eswt = base + off + np * np;
+    if (P.swz_inv && I.expk_inv) I.eswi = base + seen[std::make_pair(I.expk_inv, I.n)];
   }
   return SDQ_OK;
 }
@@ -379,7 +385,8 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
   }
-  const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_GRAD};
+  const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_TDISP_PLAIN,
+                                      sdq::PAIR_GRAD};
   for (int oi = 0; oi < sdq::kPairModes; ++oi) {
     const int md = order[oi];
     for (const auto& r : P.pair_ranges[md]) {
@@ -435,7 +442,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   }
   const Inst* d_inst = (const Inst*)(d + B.o_inst);
   const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
-  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal"};
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair"};
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
     auto go = [&]() -> hipError_t {
@@ -662,7 +669,7 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
                       double* const* g, double* logdet, double* sign, int32_t* status) {
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
-  if (scheme != SDQ_INV_LOH) return fail(ctx, SDQ_EUNSUPPORTED, "only SDQ_INV_LOH is implemented");
+  if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
   if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   std::vector<int64_t> off;
@@ -671,13 +678,14 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   Plan P;
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
+    I.scheme = scheme == SDQ_INV_PLAIN ? 1 : 0;
     I.g = g ? g[i] : nullptr;
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
     I.fin = (double*)ctx->d_fin.p + off[i];
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, sdq::SW_LAST});
+    P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
     P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
@@ -694,7 +702,7 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
                             double* const* g, double* logdet, double* sign, int32_t* status) {
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
-  if (scheme != SDQ_INV_LOH) return fail(ctx, SDQ_EUNSUPPORTED, "only SDQ_INV_LOH is implemented");
+  if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
   if (n_l < 0 || (n_l > 0 && (!l_list || !gt))) return fail(ctx, SDQ_EINVAL, "bad l_list / gt");
   for (int a = 0; a < n_l; ++a) {
     if (l_list[a] < 0) return fail(ctx, SDQ_EINVAL, "l_list entry < 0");
@@ -704,16 +712,30 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
     if (n_l > 0 && l_list[n_l - 1] > inst[i].m) return fail(ctx, SDQ_EINVAL, "l_list entry > m");
     if (n_l > 0 && !gt[i]) return fail(ctx, SDQ_EINVAL, "gt entry is NULL");
   }
+  const bool plain = scheme == SDQ_INV_PLAIN;
+  if (plain) {
+    // the single-decomposition G(tau,0) decomposes B(tau,0)^{-1} itself
+    st = validate(ctx, inst, count, true);
+    if (st) return st;
+    for (int i = 0; i < count; ++i)
+      if (inst[i].n > 16 * sdq::kMaxNT)
+        return fail(ctx, SDQ_EUNSUPPORTED,
+                    "the single-decomposition G(tau,0) is implemented for n <= 128 only");
+  }
   if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   std::vector<int64_t> off;
-  st = alloc_stages(ctx, ctx->d_ck, inst, count, 2, off);
+  // Loh: forward and backward stage stacks; plain: per-pair chains in the
+  // same two stacks plus a third for the final forward stage
+  st = alloc_stages(ctx, ctx->d_ck, inst, count, plain ? 3 : 2, off);
   if (st) return st;
   double* ck = (double*)ctx->d_ck.p;
   Plan P;
   P.llist.assign(l_list, l_list + n_l);
+  P.swz_inv = plain;
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
+    I.scheme = plain ? 1 : 0;
     I.g = g ? g[i] : nullptr;
     I.gt = n_l > 0 ? gt[i] : nullptr;
     I.logdet = logdet ? logdet + i : nullptr;
@@ -723,11 +745,16 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
     const int64_t one = (int64_t)I.nb * sd;
     I.ckf = ck + off[i];
     I.cka = ck + off[i] + one;
-    I.fin = I.ckf + (I.nb - 1) * sd;
+    I.fin = plain ? ck + off[i] + 2 * one : I.ckf + (I.nb - 1) * sd;
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, sdq::SW_STORE});
-    P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ});
-    if (I.g || I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+    const bool eq = I.g || I.logdet || I.sign;
+    if (!plain) {
+      P.sweep.push_back(SweepItem{i, sdq::SW_STORE, 0, 0});
+      P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ, 0, 0});
+    } else if (eq) {
+      P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
+    }
+    if (eq) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
     // group l by stage pair j: l == m -> nb, else l / k
     for (int a = 0; a < n_l;) {
       const int l = l_list[a];
@@ -739,7 +766,11 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
         if (j2 != j) break;
         ++b;
       }
-      P.pair[sdq::PAIR_TDISP].push_back(PairItem{i, j, a, b});
+      if (plain) {
+        if (j > 0) P.sweep.push_back(SweepItem{i, sdq::SW_LEFT, j, 0});
+        if (j < I.nb) P.sweep.push_back(SweepItem{i, sdq::SW_RIGHT, j, 0});
+      }
+      P.pair[plain ? sdq::PAIR_TDISP_PLAIN : sdq::PAIR_TDISP].push_back(PairItem{i, j, a, b});
       a = b;
     }
   }
@@ -784,7 +815,7 @@ sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, dou
       I.fin = (double*)ctx->d_fin.p + foff[i];
     }
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, flags});
+    P.sweep.push_back(SweepItem{i, flags, 0, 0});
     P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
@@ -848,10 +879,10 @@ sdq_status sdq_logdet_grad(sdq_ctx* ctx, uint64_t ckpt_handle, const sdq_instanc
     } else {
       I.ckf = ck + off[i];
       I.cka = ck + off[i] + one;
-      P.sweep.push_back(SweepItem{i, sdq::SW_STORE});
+      P.sweep.push_back(SweepItem{i, sdq::SW_STORE, 0, 0});
     }
     I.fin = I.ckf + (I.nb - 1) * sd;
-    P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ});
+    P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ, 0, 0});
     P.inst.push_back(I);
     if (I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
     for (int j = 0; j < I.nb; ++j) P.pair[sdq::PAIR_GRAD].push_back(PairItem{i, j, 0, 0});
@@ -919,7 +950,7 @@ sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, 
     I.t_out = t + (size_t)i * n * n;
     I.d_out = d + (size_t)i * n;
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, sdq::SW_FINAL});
+    P.sweep.push_back(SweepItem{i, sdq::SW_FINAL, 0, 0});
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];

@@ -1,0 +1,119 @@
+"""The single-decomposition schemes (Sec. 5.1 inv_one_plus, Sec. 6.1 inv_sum)
+on the GPU beside Loh's split schemes, against the oracle's plain schemes.
+
+The paper's finding (Sec. 5.2, Sec. 6.2): with QR both equal-time schemes
+are accurate; for G(tau, 0) the single decomposition loses all accuracy
+around tau = beta/2 at beta = 40 while inv_sum_loh stays at machine
+precision.  The oracle shows the same on the CPU (test_oracle_pins.py); here
+the GPU must match the oracle where the plain scheme is accurate and show the
+failure where it is not."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_05286_amd import binding as sdq
+from paper_2003_05286_amd import workloads as wl
+from _gpu import DEV, chains_of, relF, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sdq.Context(0)
+
+
+@pytest.mark.parametrize("L,beta", [(4, 40.0), (8, 40.0), (12, 10.0)])
+def test_plain_equal_time_matches_oracle(ctx, L, beta):
+    insts = wl.hubbard_ising(L, beta, 1, 2, seed=wl.BASE_SEED + 910 + L)
+    say(f"[gpu] inv_one_plus (plain) equal-time G, L={L} beta={beta}")
+    gs, ld, sg, st = ctx.greens(chains_of(insts), scheme=sdq.SCHEME_PLAIN)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for a, I in enumerate(insts):
+        G, ldo, sgo = oracle.greens(I.expk, I.field, I.alpha, I.k, oracle.SCHEME_PLAIN)
+        assert relF(gs[a].cpu().numpy(), G) <= TOL, (a, relF(gs[a].cpu().numpy(), G))
+        assert abs(ld[a].item() - ldo) <= 1e-12 * abs(ldo)
+        assert sg[a].item() == sgo
+
+
+def test_plain_equal_time_gang(ctx):
+    """n = 144 (a gang of workgroups per chain), the plain equal-time scheme."""
+    insts = wl.hubbard_ising(12, 4.0, 1, 1, seed=wl.BASE_SEED + 915)
+    say("[gpu] inv_one_plus (plain) equal-time G, n=144")
+    gs, ld, sg, st = ctx.greens(chains_of(insts), scheme=sdq.SCHEME_PLAIN)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    I = insts[0]
+    G, ldo, sgo = oracle.greens(I.expk, I.field, I.alpha, I.k, oracle.SCHEME_PLAIN)
+    assert relF(gs[0].cpu().numpy(), G) <= TOL
+    assert abs(ld.item() - ldo) <= 1e-12 * abs(ldo)
+    assert sg.item() == sgo
+
+
+@pytest.mark.parametrize("L,beta", [(4, 4.0), (4, 3.7), (10, 2.0)])
+def test_plain_tdisp_small_beta_matches_oracle(ctx, L, beta):
+    """beta small enough that inv_sum is accurate: every l (multiples of k,
+    propagated ones, and l = m with m not a multiple of k) against the
+    oracle's inv_sum; the equal-time G and logdet of the same call too."""
+    insts = wl.hubbard_ising(L, beta, 1, 1, seed=wl.BASE_SEED + 920 + L)
+    I = insts[0]
+    ls = sorted(set(list(range(0, I.m + 1, 3)) + [I.m]))
+    say(f"[gpu] inv_sum (plain) G(tau,0), L={L} beta={beta} m={I.m} l={ls}")
+    gts, gs, ld, sg, st = ctx.greens_tdisp(chains_of(insts), ls, scheme=sdq.SCHEME_PLAIN)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    for idx, l in enumerate(ls):
+        ref = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_PLAIN)
+        assert relF(gts[0][idx].cpu().numpy(), ref) <= TOL, (l, relF(gts[0][idx].cpu().numpy(), ref))
+    G, ldo, sgo = oracle.greens(I.expk, I.field, I.alpha, I.k, oracle.SCHEME_PLAIN)
+    assert relF(gs[0].cpu().numpy(), G) <= TOL
+    assert abs(ld.item() - ldo) <= 1e-12 * abs(ldo) and sg.item() == sgo
+
+
+def test_central_finding_tdisp_beta40(ctx):
+    """L = 4, beta = 40 (M = 400, k = 10): inv_sum_loh matches the oracle at
+    every tau tested; inv_sum matches the oracle's inv_sum near the ends of
+    [0, beta], where it is accurate, and is wrong by more than 1e-2 (relative,
+    Frobenius) at tau = beta/4 and beta/2, as the oracle's inv_sum is."""
+    I = wl.hubbard_ising(4, 40.0, 1, 1, seed=wl.BASE_SEED + 900)[0]
+    ls = [0, 10, 100, 200, 390, 400]
+    say(f"[gpu] inv_sum vs inv_sum_loh at L=4 beta=40, l={ls}")
+    ch = chains_of([I])
+    gl, _, _, _, stl = ctx.greens_tdisp(ch, ls, scheme=sdq.SCHEME_LOH)
+    gp, _, _, _, stp = ctx.greens_tdisp(ch, ls, scheme=sdq.SCHEME_PLAIN)
+    torch.cuda.synchronize()
+    assert stl.item() == 0
+    for idx, l in enumerate(ls):
+        loh = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_LOH)
+        assert relF(gl[0][idx].cpu().numpy(), loh) <= TOL, l
+        plain = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_PLAIN)
+        g = gp[0][idx].cpu().numpy()
+        if l in (0, 10, 390, 400):
+            assert relF(plain, loh) <= 1e-12, l     # the oracle's inv_sum is accurate here
+            assert relF(g, plain) <= TOL, (l, relF(g, plain))
+        else:
+            assert relF(plain, loh) > 1e-2, l       # and fails here
+            assert not (np.all(np.isfinite(g)) and relF(g, loh) <= 1e-2), (l, relF(g, loh))
+
+
+def test_plain_tdisp_argument_errors(ctx):
+    I = wl.hubbard_ising(4, 2.0, 1, 1, seed=wl.BASE_SEED + 930)[0]
+    ch = chains_of([I])
+    ch[0].expk_inv = None
+    say("[gpu] inv_sum without expk_inv -> SDQ_EINVAL")
+    with pytest.raises(sdq.SdqError) as e:
+        ctx.greens_tdisp(ch, [0, 5], scheme=sdq.SCHEME_PLAIN)
+    assert e.value.status == sdq.SDQ_EINVAL
+    big = chains_of(wl.hubbard_ising(12, 1.0, 1, 1, seed=wl.BASE_SEED + 931))
+    say("[gpu] inv_sum at n=144 -> SDQ_EUNSUPPORTED")
+    with pytest.raises(sdq.SdqError) as e:
+        ctx.greens_tdisp(big, [0, 5], scheme=sdq.SCHEME_PLAIN)
+    assert e.value.status == sdq.SDQ_EUNSUPPORTED
+    # the Loh call on the same context still works afterwards
+    gts, _, _, _, st = ctx.greens_tdisp(chains_of([I]), [0, 5])
+    torch.cuda.synchronize()
+    ref = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, 5)
+    assert st.item() == 0 and relF(gts[0][1].cpu().numpy(), ref) <= TOL
