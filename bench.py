@@ -71,6 +71,10 @@ def main():
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
                          "(log|det| + gradient) and the L=16 batch (G + G(tau,0) at every slice)")
+    ap.add_argument("--scheme", default="loh", choices=["loh", "plain"],
+                    help="inversion scheme of the time-displaced workloads: Loh's split (default) or "
+                         "the single-decomposition inv_sum, which also reports its deviation from "
+                         "the split scheme at every tau")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -103,6 +107,10 @@ def main():
             "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
+    plain = args.scheme == "plain"
+    if plain and kind != "tdisp":
+        raise SystemExit("bench: --scheme plain applies to the time-displaced workloads")
+    scheme = sdq.SCHEME_PLAIN if plain else sdq.SCHEME_LOH
     print(f"[bench] {W.name}: {cnt} chains, n={sorted({I.n for I in insts})}, m={m}, k={k}, "
           f"{len(l_list)} G(tau,0) each", file=sys.stderr, flush=True)
 
@@ -119,7 +127,7 @@ def main():
     ctx = sdq.Context(0)
     # outputs preallocated once
     import ctypes
-    inst_arr = ctx._instances(chains, need_inv=(kind == "grad"))
+    inst_arr = ctx._instances(chains, need_inv=(kind == "grad" or plain))
     ls = (ctypes.c_int32 * max(len(l_list), 1))(*l_list)
     gts = [torch.empty(len(l_list), I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
         if kind == "tdisp" else []
@@ -135,7 +143,7 @@ def main():
 
     def step():
         if kind == "tdisp":
-            ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, ls, len(l_list),
+            ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, scheme, ls, len(l_list),
                                               gt_ptrs, g_ptrs, vp(ld), vp(sg), vp(st)))
         elif kind == "greens":
             ctx._chk(ctx.lib.sdq_greens(ctx.h, inst_arr, cnt, sdq.SCHEME_LOH, g_ptrs, vp(ld), vp(sg), vp(st)))
@@ -147,7 +155,7 @@ def main():
         step()
         torch.cuda.synchronize()
         print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    if int((st != 0).sum().item()) != 0:
+    if int((st != 0).sum().item()) != 0 and not plain:
         raise SystemExit("bench: nonzero status after warmup")
 
     ctx.set_profiling(True)
@@ -165,10 +173,15 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
           f"{n_sw}, pair {ms_pa / max(n_pa, 1):.3f} ms x {n_pa}", file=sys.stderr, flush=True)
     status_ok = int((st != 0).sum().item()) == 0
+    n_bad = int((st != 0).sum().item())
 
     sweeps_per_chain = 1 if kind == "greens" else 2
     f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
-    if kind == "tdisp":
+    if plain:
+        f_sweep = sum(plain_sweep_flops(I.n, I.m, I.k, l_list) for I in insts)
+        n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
+        f_pair = sum(plain_pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
+    elif kind == "tdisp":
         # l a multiple of k (or m) is a direct inversion, the others propagate
         n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
         f_pair = sum(pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
@@ -182,8 +195,10 @@ def main():
     achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
 
-    eq_rate = per_inst_rate = None
-    if not args.profile_only and kind == "tdisp":
+    eq_rate = per_inst_rate = scheme_check = None
+    if plain:
+        scheme_check = plain_vs_loh(ctx, chains, l_list, gts, torch)
+    if not args.profile_only and kind == "tdisp" and not plain:
         # equal-time only, same batch (one forward sweep per chain)
         ctx.greens(chains)
         torch.cuda.synchronize()
@@ -206,6 +221,8 @@ def main():
 
     if args.workload == "hubbard_L8_b40_batch512":
         metric = "stabilized Green's functions/sec (FP64, L=8, beta=40, batched)"
+        if plain:
+            metric = "stabilized Green's functions/sec (FP64, L=8, beta=40, batched, inv_sum)"
         unit = "chains/s (each: G + 40 G(tau,0))"
     elif kind == "tdisp":
         metric = f"stabilized Green's functions/sec (FP64, {W.name})"
@@ -233,7 +250,7 @@ def main():
         "config": {"workload": W.name, "chains": cnt, "n": sorted({I.n for I in insts}),
                    "m": sorted({I.m for I in insts}), "k": k, "beta": betas, "dtau": 0.1,
                    "l_list": (f"{l_list[0]},{l_list[1]},...,{l_list[-1]}" if len(l_list) > 2 else l_list),
-                   "scheme": "loh"},
+                   "scheme": args.scheme},
         "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA,
@@ -248,10 +265,54 @@ def main():
         "per_instance_loop_per_s": per_inst_rate,
         "status_ok": status_ok,
     }
+    if scheme_check is not None:
+        scheme_check["chains_flagged_nonfinite"] = n_bad
+        out["scheme_check"] = scheme_check
 
-    if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512":
+    if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def plain_sweep_flops(n, m, k, l_list):
+    """Sweeps of the single-decomposition G(tau,0): one forward sweep for the
+    equal-time G, and for every stage pair j with an output the chains
+    B_1^{-1}...B_{tau_j}^{-1} (ceil(tau_j/k) blocks) and B_m...B_{tau_j+1}
+    (nb - j blocks), at (2 slices + 11/3) N^3 per block as in sweep_flops."""
+    nb = math.ceil(m / k)
+    js = sorted({nb if l == m else l // k for l in l_list})
+    blocks = 0
+    for j in js:
+        tau = min(j * k, m)
+        blocks += math.ceil(tau / k) + (nb - j)
+    per_block = (2.0 * k + 11.0 / 3.0) * n ** 3
+    return sweep_flops(n, m, k) + blocks * per_block
+
+
+def plain_pair_flops(n, n_direct, n_prop):
+    """inv_sum per direct tau: X_R^{-1} by pivoted QR (4/3 + 2 + 1) N^3, the
+    products X_L X_R^{-1} and U_L^T U_R (4N^3), pivoted QR of the middle
+    matrix with its solve (4/3 + 2 + 1) N^3 and the final product (2N^3);
+    2N^3 per propagated slice."""
+    return n_direct * (2 * (4.0 / 3.0 + 2.0 + 1.0) + 4.0 + 2.0) * n ** 3 + n_prop * 2.0 * n ** 3
+
+
+def plain_vs_loh(ctx, chains, l_list, gts_plain, torch):
+    """Relative Frobenius deviation of the single-decomposition G(tau,0) from
+    Loh's split scheme on the same batch, per tau over all chains (Sec. 6.2:
+    inv_sum fails around beta/2)."""
+    from paper_2003_05286_amd import binding as sdq
+    gl, _, _, _, st = ctx.greens_tdisp(chains, l_list, want_g=False, scheme=sdq.SCHEME_LOH)
+    torch.cuda.synchronize()
+    dev = torch.stack([torch.linalg.matrix_norm(gp - g) / torch.linalg.matrix_norm(g)
+                       for gp, g in zip(gts_plain, gl)])  # [chains][n_l]
+    dev = torch.nan_to_num(dev, nan=float("inf")).cpu().numpy()
+    import numpy as np
+    half = l_list.index(max(l_list) // 2) if (max(l_list) // 2) in l_list else len(l_list) // 2
+    return {"relF_vs_loh_max_per_l": {str(l): float(dev[:, i].max()) for i, l in enumerate(l_list)},
+            "tau_half": {"l": l_list[half], "max": float(dev[:, half].max()),
+                         "median": float(np.median(dev[:, half])), "min": float(dev[:, half].min())},
+            "loh_status_ok": bool((st == 0).all().item())}
 
 
 def measured_traffic():
