@@ -196,6 +196,30 @@ __device__ __forceinline__ int pivot_col(double key) {
   return 127 - (int)(__double_as_longlong(key) & 0x7F);
 }
 
+// sqrt(q) for q in [2^-30, 2^3] (scaled squared norms): the hardware
+// reciprocal square root estimate refined by one Goldschmidt step
+// (y -> sqrt(q), h -> 1/(2 sqrt(q))) and one Newton correction of the
+// residual q - y^2; within about an ulp, and no special cases are needed in
+// that range
+__device__ __forceinline__ double sqrt_mid(double q) {
+  const double r = __builtin_amdgcn_rsq(q);
+  double y = q * r, h = 0.5 * r;
+  const double e = fma(-h, y, 0.5);
+  y = fma(y, e, y);
+  h = fma(h, e, h);
+  const double d = fma(-y, y, q);
+  return fma(d, h, y);
+}
+// 1/x for x in [2^-4, 2^4]: the hardware reciprocal estimate and two Newton
+// steps, within about an ulp
+__device__ __forceinline__ double rcp_mid(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // exact power-of-two scale that brings x near 1 (1 for 0, inf, nan)
 // its exact inverse (dividing by a power of two is a multiplication)
 __device__ __forceinline__ double pow2_unscale(double x) {
@@ -384,6 +408,11 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
     const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
     for (int j = 16 * TJ; j < jend; ++j) {
       const int jj = j - 16 * TJ, gj = jj & 3, rj = jj >> 2;
+      // row j of each column before this step's update (needed by the norm
+      // downdate; read here, off the step's dependency chain)
+      double ajc[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) ajc[c] = sum_col(L.g == gj ? pick4(A.v[c][TJ], rj) : 0.0);
       // ---- wave-local candidate (packed key), columns of this wave
       double key = -1.0;
 #pragma unroll
@@ -447,13 +476,14 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         // with q = ||x[j:]||^2 (scaled) and r = 1/sqrt(q):  beta = -sign(alpha) q r,
         // tau = (beta - alpha)/beta = 1 + |alpha| / ||x||, 1/(alpha - beta) =
         // sign(alpha) / (|alpha| + ||x||): one reciprocal square root and one
-        // division on the dependency chain instead of a square root and two
+        // reciprocal on the dependency chain instead of a square root and two
+        // divisions (|alpha| + ||x|| is within [2^-2, 2^3] after the scaling)
         const double q = fma(as, as, s);
         const double r = rsqrt(q);
         const double hq = q * r;  // ||x[j:]|| * sc
         beta = -copysign(hq * usc, alpha);
         tau = fma(fabs(as), r, 1.0);
-        inv = copysign(sc, alpha) / (fabs(as) + hq);
+        inv = copysign(sc, alpha) * rcp_mid(fabs(as) + hq);
       }
 #pragma unroll
       for (int ti = TJ; ti < NT; ++ti)
@@ -478,6 +508,9 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
 #pragma unroll
           for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
         const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * (upd ? tau : 0.0);
+        // row j after the update: the reflector is 1 there, so it is ajc - d
+        // exactly as the update below rounds it
+        const double rjv = fma(-d, 1.0, ajc[c]);
         if (is_piv) {
           // the pivot column becomes column j of R plus the reflector
 #pragma unroll
@@ -494,7 +527,6 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
 #pragma unroll
             for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
         }
-        const double rjv = sum_col(L.g == gj ? pick4(A.v[c][TJ], rj) : 0.0);
         if (upd && vn1[c] != 0.0) {
           // vn1^2 - r^2 = vn1^2 (1 - (r/vn1)^2); recompute when that falls to
           // sqrt(eps) vn2^2 or below (same test, no division), all scaled by
@@ -506,7 +538,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
             need = true;
             rec[c] = true;
           } else {
-            vn1[c] = sqrt(q) * iv2[c];
+            vn1[c] = sqrt_mid(q) * iv2[c];  // q in (sqrt(eps), 4]
           }
         }
       }
