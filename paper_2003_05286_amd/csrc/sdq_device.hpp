@@ -165,19 +165,27 @@ __device__ __forceinline__ double pl32_pair_max(double v) {
 __device__ __forceinline__ double sum_col(double v) { return pl32_pair_sum(pl16_pair_sum(v)); }
 __device__ __forceinline__ double max_col(double v) { return pl32_pair_max(pl16_pair_max(v)); }
 
-// rotate a double right by R lanes inside each 16-lane row (DPP row_ror)
+// rotate a double right by R lanes inside each 16-lane row (DPP row_ror;
+// every lane has a source, so no old value is needed)
 template <int R>
 __device__ __forceinline__ double row_ror(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), 0x120 + R, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), 0x120 + R, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)__double2loint(v), 0x120 + R, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)__double2hiint(v), 0x120 + R, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
-// max over the 16 lanes of each row (all of them get the result)
+// max of two pivot keys (never NaN): one v_max_f64, without the operand
+// canonicalization fmax() adds for NaN inputs
+__device__ __forceinline__ double key_max(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// max of pivot keys over the 16 lanes of each row (all of them get it)
 __device__ __forceinline__ double row_max16(double v) {
-  v = fmax(v, row_ror<8>(v));
-  v = fmax(v, row_ror<4>(v));
-  v = fmax(v, row_ror<2>(v));
-  v = fmax(v, row_ror<1>(v));
+  v = key_max(v, row_ror<8>(v));
+  v = key_max(v, row_ror<4>(v));
+  v = key_max(v, row_ror<2>(v));
+  v = key_max(v, row_ror<1>(v));
   return v;
 }
 
@@ -416,8 +424,10 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
       // ---- wave-local candidate (packed key), columns of this wave
       double key = -1.0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c)
-        if (ps[c] < 0) key = fmax(key, pivot_key(vn1[c], col_of<NT, P>(L, c)));
+      for (int c = 0; c < CT; ++c) {
+        const double kc = ps[c] < 0 ? pivot_key(vn1[c], col_of<NT, P>(L, c)) : -1.0;
+        key = c == 0 ? kc : key_max(key, kc);
+      }
       key = row_max16(key);  // the four rows hold the same columns
       const int bc = pivot_col(key);
 #pragma unroll
@@ -436,7 +446,7 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         // workgroup pivot: the owner wave follows from the column index
         pk = S.ckey[buf][0];
 #pragma unroll
-        for (int q = 1; q < P; ++q) pk = fmax(pk, S.ckey[buf][q]);
+        for (int q = 1; q < P; ++q) pk = key_max(pk, S.ckey[buf][q]);
       } else {
         // one wave: its own LDS writes are visible to its later reads
         __builtin_amdgcn_wave_barrier();
