@@ -126,6 +126,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // element r of a lane's 4-entry tile column, r wave-uniform
+// the double held by lane src (byte address 4 * src) of the wave
+__device__ __forceinline__ double lane_fetch(int src_addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src_addr, (int)__double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src_addr, (int)__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double pick4(const double (&a)[4], int r) {
   return r == 0 ? a[0] : (r == 1 ? a[1] : (r == 2 ? a[2] : a[3]));
 }
@@ -416,11 +423,12 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
     const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
     for (int j = 16 * TJ; j < jend; ++j) {
       const int jj = j - 16 * TJ, gj = jj & 3, rj = jj >> 2;
-      // row j of each column before this step's update (needed by the norm
-      // downdate; read here, off the step's dependency chain)
+      // row j of each column before this step's update, fetched from the
+      // lane group holding it (read here, off the step's dependency chain)
       double ajc[CT];
+      const int jsrc = ((gj << 4) | L.cl) << 2;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) ajc[c] = sum_col(L.g == gj ? pick4(A.v[c][TJ], rj) : 0.0);
+      for (int c = 0; c < CT; ++c) ajc[c] = lane_fetch(jsrc, pick4(A.v[c][TJ], rj));
       // ---- wave-local candidate (packed key), columns of this wave
       double key = -1.0;
 #pragma unroll
@@ -459,7 +467,9 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
       const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~0x7Fll);
 
       // ---- reflector (every wave computes the same one from the same data);
-      // rows <= j masked in tile TJ only, tiles below TJ never touched
+      // rows <= j masked in tile TJ only, tiles below TJ never touched.
+      // v keeps y = the pivot column below row j times sc (exact: sc is a
+      // power of two); the Householder vector is e_j + w y.
       const double sc = pow2_scale(vpiv), usc = pow2_unscale(vpiv);
       double v[NT][4];
       double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
@@ -475,33 +485,27 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         for (int r = 0; r < 4; ++r) {
           double x = v[ti][r];
           if (ti == TJ && L.g + 4 * r <= jj) x = 0.0;
-          v[ti][r] = x;
           const double y = x * sc;
+          v[ti][r] = y;
           sp[r] = fma(y, y, sp[r]);
         }
       double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
       const double as = alpha * sc;
-      double tau = 0.0, beta = alpha, inv = 0.0;
+      double tau = 0.0, beta = alpha, w = 0.0;
       if (s != 0.0) {
         // with q = ||x[j:]||^2 (scaled) and r = 1/sqrt(q):  beta = -sign(alpha) q r,
         // tau = (beta - alpha)/beta = 1 + |alpha| / ||x||, 1/(alpha - beta) =
-        // sign(alpha) / (|alpha| + ||x||): one reciprocal square root and one
-        // reciprocal on the dependency chain instead of a square root and two
-        // divisions (|alpha| + ||x|| is within [2^-2, 2^3] after the scaling)
+        // sign(alpha) / (|alpha| + ||x||), which is w / sc: one reciprocal
+        // square root and one reciprocal on the dependency chain instead of a
+        // square root and two divisions (|alpha| + ||x|| is within [2^-2, 2^3]
+        // after the scaling)
         const double q = fma(as, as, s);
         const double r = rsqrt(q);
         const double hq = q * r;  // ||x[j:]|| * sc
         beta = -copysign(hq * usc, alpha);
         tau = fma(fabs(as), r, 1.0);
-        inv = copysign(sc, alpha) * rcp_mid(fabs(as) + hq);
+        w = copysign(rcp_mid(fabs(as) + hq), alpha);
       }
-#pragma unroll
-      for (int ti = TJ; ti < NT; ++ti)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double x = v[ti][r] * inv;
-          v[ti][r] = (ti == TJ && L.g + 4 * r == jj) ? 1.0 : x;
-        }
 
       // ---- apply H_j to the other live columns, downdate their norms
       bool need = false;
@@ -517,10 +521,10 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
         for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
           for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
-        const double d = sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])) * (upd ? tau : 0.0);
-        // row j after the update: the reflector is 1 there, so it is ajc - d
-        // exactly as the update below rounds it
-        const double rjv = fma(-d, 1.0, ajc[c]);
+        // (e_j + w y)^T a_c = a_jc + w (y^T a_c)
+        const double d = fma(w, sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])), ajc[c]) * (upd ? tau : 0.0);
+        // row j after the update
+        const double rjv = ajc[c] - d;
         if (is_piv) {
           // the pivot column becomes column j of R plus the reflector
 #pragma unroll
@@ -528,14 +532,19 @@ __device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int q = L.g + 4 * r;
-              if (ti > TJ || q > jj) A.v[c][ti][r] = v[ti][r];
+              if (ti > TJ || q > jj) A.v[c][ti][r] = w * v[ti][r];
               else if (q == jj) A.v[c][ti][r] = beta;
             }
         } else {
+          // rows below j: a -= (d w) y; row j: a_jc - d; rows above j: y = 0
+          const double dw = d * w;
 #pragma unroll
           for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-d, v[ti][r], A.v[c][ti][r]);
+            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-dw, v[ti][r], A.v[c][ti][r]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (L.g + 4 * r == jj) A.v[c][TJ][r] = rjv;
         }
         if (upd && vn1[c] != 0.0) {
           // vn1^2 - r^2 = vn1^2 (1 - (r/vn1)^2); recompute when that falls to
