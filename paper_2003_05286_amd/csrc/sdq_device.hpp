@@ -83,6 +83,16 @@ struct Smem {
   int item;
 };
 
+// Device memory seen as the global address space: loads and stores through
+// these compile to global instructions.  Through plain (flat) pointers the
+// compiler must order every store against the spill slots in scratch memory
+// (a wait for all earlier memory operations before each one) and counts
+// loads against LDS waits.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 template <int NT, int P>
 struct RM {  // register-resident n x n matrix, column split (see header)
   double v[Geo<NT, P>::CT][NT][4];
@@ -330,26 +340,33 @@ __device__ __forceinline__ void load_rm(const Lane& L, RM<NT, P>& A, const doubl
         const int row = row_of(L, ti, r);
         double x;
         if (src == nullptr) x = (row == col) ? 1.0 : 0.0;
-        else if (row < n && col < n && tile_ok<NT, P>(L, c)) x = trans ? src[col * n + row] : src[row * n + col];
+        else if (row < n && col < n && tile_ok<NT, P>(L, c))
+          x = trans ? gmem(src)[col * n + row] : gmem(src)[row * n + col];
         else x = 0.0;
         A.v[c][ti][r] = x;
       }
   }
 }
 
-// store the leading n x n block of a register matrix (row-major)
+// store the leading n x n block of a register matrix (row-major): one base
+// address per lane (row L.g of its column) plus a wave-uniform row offset
+// per register, so no per-element address is kept live
 template <int NT, int P>
 __device__ __forceinline__ void store_rm(const Lane& L, const RM<NT, P>& A, double* dst, int n) {
 #pragma unroll
   for (int c = 0; c < Geo<NT, P>::CT; ++c) {
     const int col = col_of<NT, P>(L, c);
     if (!tile_ok<NT, P>(L, c) || col >= n) continue;
+    // rows L.g + 4k, k = 4 ti + r: the address advances by 4 rows per
+    // register; the row test is wave-uniform except in a ragged last tile
+    auto* p = gmem(dst) + (size_t)L.g * n + col;
+    const size_t step = 4 * (size_t)n;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        if (row < n) dst[row * n + col] = A.v[c][ti][r];
+        if (16 * ti + 4 * r + 3 < n || row_of(L, ti, r) < n) *p = A.v[c][ti][r];
+        p += step;
       }
   }
 }
@@ -892,7 +909,7 @@ __device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, cons
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = row_of(L, ti, r);
-        if (s < n) dst[S.perm[s] * n + col] = Z.v[c][ti][r];
+        if (s < n) gmem(dst)[S.perm[s] * n + col] = Z.v[c][ti][r];
       }
   }
 }
@@ -909,7 +926,7 @@ __device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, c
   for (int idx = L.t; idx < cnt * G::NP; idx += G::THREADS) {
     const int s = idx / G::NP, row = idx - s * G::NP;
     const int q = q0 + dir * s;
-    S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * I.field[(size_t)(q - 1) * I.n + row]) : 1.0;
+    S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * gmem(I.field)[(size_t)(q - 1) * I.n + row]) : 1.0;
   }
   __syncthreads();
 }
@@ -937,7 +954,7 @@ struct EOp {
   int lane;
   __device__ double operator()(int ti, int tk, int r, int, int) const {
     if (ELDS) return sE[((ti * NT + tk) * 4 + r) * 64 + lane];
-    return esw[((ti * NT + tk) * 4 + r) * 64 + lane];
+    return gmem(esw)[((ti * NT + tk) * 4 + r) * 64 + lane];
   }
 };
 
@@ -945,7 +962,7 @@ template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, P, ELDS>& S, const double* esw) {
   using G = Geo<NT, P>;
   if (!ELDS) return;
-  for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) S.E[idx] = esw[idx];
+  for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) S.E[idx] = gmem(esw)[idx];
   // visibility: the next fill_vbuf begins with a barrier
 }
 
@@ -956,8 +973,8 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
                                             double* dst) {
   store_rm<NT, P>(L, U, dst, n);
   store_rm<NT, P>(L, T, dst + (size_t)n * n, n);
-  for (int t = L.t; t < n; t += Geo<NT, P>::THREADS) dst[2 * (size_t)n * n + t] = S.dnew[t];
-  if (L.t == 0) dst[2 * (size_t)n * n + n] = sgn_u;
+  for (int t = L.t; t < n; t += Geo<NT, P>::THREADS) gmem(dst)[2 * (size_t)n * n + t] = S.dnew[t];
+  if (L.t == 0) gmem(dst)[2 * (size_t)n * n + n] = sgn_u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,7 +1067,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   if (flags & SW_FINAL) {
     store_rm<NT, P>(L, W, I.u_out, n);
     store_rm<NT, P>(L, T, I.t_out, n);
-    for (int t = L.t; t < n; t += G::THREADS) I.d_out[t] = S.dnew[t];
+    for (int t = L.t; t < n; t += G::THREADS) gmem(I.d_out)[t] = S.dnew[t];
   }
   if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 }
@@ -1067,11 +1084,11 @@ __device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   __syncthreads();
   int bad = 0;
   for (int t = L.t; t < G::NP; t += G::THREADS) {
-    const double d = t < n ? F[2 * (size_t)n * n + t] : 1.0;
+    const double d = t < n ? gmem(F)[2 * (size_t)n * n + t] : 1.0;
     if (!isfinite(d) || !(d > 0.0)) bad = 1;
     S.dcur[t] = d;
   }
-  const double sgn_u = F[2 * (size_t)n * n + n];
+  const double sgn_u = gmem(F)[2 * (size_t)n * n + n];
   double ld, sg;
   if (I.scheme == 0)
     inv_one_plus<NT, P, ELDS, true>(L, n, S, U, T, sgn_u, Z, &ld, &sg);
@@ -1115,7 +1132,7 @@ __device__ __forceinline__ void stage_mat(const Lane& L, Smem<NT, P, ELDS>& S, c
     for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
       const int i = idx / G::NP, k = idx - i * G::NP;
       double x = 0.0;
-      if (i < n && k < n) x = src ? src[i * n + k] : (i == k ? 1.0 : 0.0);
+      if (i < n && k < n) x = src ? gmem(src)[i * n + k] : (i == k ? 1.0 : 0.0);
       S.E[i * G::LDR + k] = x;
     }
   }
@@ -1145,7 +1162,7 @@ __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I
                               RM<NT, P>& Gm);
 
 // ---------------------------------------------------------------------------
-// Time-displaced G(tau_j, 0) from forward stage F[j] = U1 D1 T1 (of
+// Time-displaced G(tau_j, 0) from forward stage gmem(F)[j] = U1 D1 T1 (of
 // B(tau_j, 0)) and backward stage A[j] = U2 D2 T2 (of B(beta, tau_j)^T),
 // Sec. 6.1 inv_sum_loh with
 //   U_L D_L X_L = B(tau,0)^{-1} = T1^{-1} D1^{-1} U1^T,
@@ -1194,14 +1211,14 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
     gemm_rb<NT, P>(L,
                    [&](int, int, int, int i, int kk) -> double {
                      if (i >= n || kk >= n) return 0.0;
-                     return U1 ? U1[kk * n + i] : (i == kk ? 1.0 : 0.0);
+                     return U1 ? gmem(U1)[kk * n + i] : (i == kk ? 1.0 : 0.0);
                    },
                    B, P1);
     load_rm<NT, P>(L, B, T2, n, true);
     gemm_rb<NT, P>(L,
                    [&](int, int, int, int i, int kk) -> double {
                      if (i >= n || kk >= n) return 0.0;
-                     return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                     return T1 ? gmem(T1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
                    },
                    B, P2);
   }
@@ -1211,14 +1228,14 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     const int col = col_of<NT, P>(L, c);
-    d2c[c] = (D2 && col < n) ? D2[col] : 1.0;
+    d2c[c] = (D2 && col < n) ? gmem(D2)[col] : 1.0;
   }
 #pragma unroll
   for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row_of(L, ti, r);
-      const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+      const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
       const double lm = 1.0 / (d1 > 1.0 ? d1 : 1.0);   // D_Lm
       const double lpi = d1 < 1.0 ? d1 : 1.0;           // D_Lp^{-1}
 #pragma unroll
@@ -1238,14 +1255,14 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row_of(L, ti, r);
-      const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+      const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
       const double lpi = d1 < 1.0 ? d1 : 1.0;  // D_Lp^{-1}
 #pragma unroll
       for (int c = 0; c < CT; ++c) Y.v[c][ti][r] *= lpi;
     }
   apply_qt<NT, P, ELDS>(L, n, S, Y);
   back_subst<NT, P, ELDS>(L, n, S, Y);
-  // G = U2 D_Rp^{-1} P Z :  A(i, s) = U2[i][perm s] / max(D2[perm s], 1)
+  // G = U2 D_Rp^{-1} P Z :  A(i, s) = gmem(U2)[i][perm s] / max(gmem(D2)[perm s], 1)
   RM<NT, P> Gm;
   if constexpr (ELDS) {
     // stage U2 D_Rp^{-1} (columns scaled), then gather its columns by perm
@@ -1253,8 +1270,8 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
       const int i = idx / G::NP, kk = idx - i * G::NP;
       double x = 0.0;
       if (i < n && kk < n) {
-        const double d2 = D2 ? D2[kk] : 1.0;
-        x = (U2 ? U2[i * n + kk] : (i == kk ? 1.0 : 0.0)) / (d2 > 1.0 ? d2 : 1.0);
+        const double d2 = D2 ? gmem(D2)[kk] : 1.0;
+        x = (U2 ? gmem(U2)[i * n + kk] : (i == kk ? 1.0 : 0.0)) / (d2 > 1.0 ? d2 : 1.0);
       }
       S.E[i * G::LDR + kk] = x;
     }
@@ -1269,8 +1286,8 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
                    [&](int, int, int, int i, int s) -> double {
                      if (i >= n || s >= n) return 0.0;
                      const int p = S.perm[s];
-                     const double d2 = D2 ? D2[p] : 1.0;
-                     const double u = U2 ? U2[i * n + p] : (i == p ? 1.0 : 0.0);
+                     const double d2 = D2 ? gmem(D2)[p] : 1.0;
+                     const double u = U2 ? gmem(U2)[i * n + p] : (i == p ? 1.0 : 0.0);
                      return u / (d2 > 1.0 ? d2 : 1.0);
                    },
                    Y, Gm);
@@ -1357,28 +1374,28 @@ __device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst
   gemm_rb<NT, P>(L,
                  [&](int, int, int, int i, int kk) -> double {
                    if (i >= n || kk >= n) return 0.0;
-                   return XL ? XL[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                   return XL ? gmem(XL)[i * n + kk] : (i == kk ? 1.0 : 0.0);
                  },
                  B, P1);
   load_rm<NT, P>(L, B, UR, n, false);
   gemm_rb<NT, P>(L,
                  [&](int, int, int, int i, int kk) -> double {
                    if (i >= n || kk >= n) return 0.0;
-                   return UL ? UL[kk * n + i] : (i == kk ? 1.0 : 0.0);
+                   return UL ? gmem(UL)[kk * n + i] : (i == kk ? 1.0 : 0.0);
                  },
                  B, P2);
   double drc[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     const int col = col_of<NT, P>(L, c);
-    drc[c] = (DR && col < n) ? DR[col] : 1.0;
+    drc[c] = (DR && col < n) ? gmem(DR)[col] : 1.0;
   }
 #pragma unroll
   for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row_of(L, ti, r);
-      const double dl = (DL && row < n) ? DL[row] : 1.0;
+      const double dl = (DL && row < n) ? gmem(DL)[row] : 1.0;
 #pragma unroll
       for (int c = 0; c < CT; ++c) P1.v[c][ti][r] = dl * P1.v[c][ti][r] + P2.v[c][ti][r] * drc[c];
     }
@@ -1395,7 +1412,7 @@ __device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst
                  [&](int, int, int, int i, int s) -> double {
                    if (i >= n || s >= n) return 0.0;
                    const int p = S.perm[s];
-                   return XRi ? XRi[i * n + p] : (i == p ? 1.0 : 0.0);
+                   return XRi ? gmem(XRi)[i * n + p] : (i == p ? 1.0 : 0.0);
                  },
                  Y, Gm);
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
@@ -1439,20 +1456,20 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     gemm_rb<NT, P>(L,
                    [&](int, int, int, int i, int kk) -> double {
                      if (i >= n || kk >= n) return 0.0;
-                     return T1 ? T1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                     return T1 ? gmem(T1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
                    },
                    B, Mm);
   }
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     const int col = col_of<NT, P>(L, c);
-    const double d2 = (D2 && col < n) ? D2[col] : 1.0;
+    const double d2 = (D2 && col < n) ? gmem(D2)[col] : 1.0;
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
-        const double d1 = (D1 && row < n) ? D1[row] : 1.0;
+        const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
         Mm.v[c][ti][r] *= d1 * d2;
       }
   }
@@ -1486,7 +1503,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     gemm_rb<NT, P>(L,
                    [&](int, int, int, int i, int kk) -> double {
                      if (i >= n || kk >= n) return 0.0;
-                     return U1 ? U1[i * n + kk] : (i == kk ? 1.0 : 0.0);
+                     return U1 ? gmem(U1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
                    },
                    u, Um);
   }
@@ -1515,7 +1532,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   for (int t = L.t; t < n; t += G::THREADS) {
     const double gii = S.R[t * G::LDR + t];
     bad |= !isfinite(gii);
-    I.grad[(size_t)(l0 - 1) * n + t] = I.alpha * (1.0 - gii);
+    gmem(I.grad)[(size_t)(l0 - 1) * n + t] = I.alpha * (1.0 - gii);
   }
   for (int l = l0; l < l1; ++l) {
     // G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar
@@ -1531,7 +1548,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
           const int row = row_of(L, ti, r);
           double x = 0.0;
           if (row < n && col < n && tile_ok<NT, P>(L, c))
-            x = I.expk_inv[row * n + col] * exp(-I.alpha * fl[row]);
+            x = I.expk_inv[row * n + col] * exp(-I.alpha * gmem(fl)[row]);
           Bi.v[c][ti][r] = x;
         }
     }
@@ -1541,7 +1558,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
-        const double v = row < n ? exp(I.alpha * fl[row]) : 0.0;
+        const double v = row < n ? exp(I.alpha * gmem(fl)[row]) : 0.0;
 #pragma unroll
         for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
       }
@@ -1560,7 +1577,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     for (int t = L.t; t < n; t += G::THREADS) {
       const double gii = S.R[t * G::LDR + t];
       bad |= !isfinite(gii);
-      I.grad[(size_t)l * n + t] = I.alpha * (1.0 - gii);
+      gmem(I.grad)[(size_t)l * n + t] = I.alpha * (1.0 - gii);
     }
   }
   if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
