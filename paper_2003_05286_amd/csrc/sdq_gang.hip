@@ -167,6 +167,14 @@ __device__ __forceinline__ unsigned long long tag_key(unsigned long long k, int 
 }
 __device__ __forceinline__ int key_tag(unsigned long long k) { return (int)((k >> 11) & 31); }
 
+// Device memory seen as the global address space: accesses through these
+// compile to global instructions (flat ones would also count against LDS
+// waits and be ordered against the spill slots).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---- gang barrier ----------------------------------------------------------
 __device__ bool gang_sync(GC& c) {
   __syncthreads();
@@ -174,18 +182,18 @@ __device__ bool gang_sync(GC& c) {
   if (c.t == 0) {
     __threadfence();
     const unsigned target = c.epoch * (unsigned)c.geo.G;
-    atomicAdd(&c.bar[0], 1u);
+    __hip_atomic_fetch_add(gmem(&c.bar[0]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int good = 1;
     const unsigned long long t0 = wall_clock64();
     for (;;) {
-      const unsigned v = __hip_atomic_load(&c.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned v = __hip_atomic_load(gmem(&c.bar[0]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (v >= target) break;
-      if (__hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      if (__hip_atomic_load(gmem(&c.bar[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
         good = 0;
         break;
       }
       if (wall_clock64() - t0 > kSpinTicks) {
-        atomicExch(&c.bar[1], 1u);
+        __hip_atomic_exchange(gmem(&c.bar[1]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = 0;
         break;
       }
@@ -204,16 +212,17 @@ __device__ bool gang_sync(GC& c) {
 // atomic stores and loads: they are performed at the device coherence point,
 // so no cache write-back or invalidation is needed (see wait_keys).
 __device__ __forceinline__ void st_coh(double* p, double x) {
-  __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gmem(p), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_coh(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gmem(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh_u64(double* p, unsigned long long x) {
-  __hip_atomic_store((unsigned long long*)p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gmem((unsigned long long*)p), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ unsigned long long ld_coh_u64(const double* p) {
-  return __hip_atomic_load((unsigned long long*)const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gmem((unsigned long long*)const_cast<double*>(p)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- slab products -----------------------------------------------------------
@@ -222,7 +231,10 @@ __device__ __forceinline__ unsigned long long ld_coh_u64(const double* p) {
 // (16 ti + l%16, 16 tk + 4 r + l/16) for lane l.  Output tiles (ti, ct)
 // are spread over the 16 waves; ends with a barrier.
 template <class AF, class PRE, class POST>
-__device__ void slab_gemm(GC& c, AF A, PRE pre, POST post) {
+__device__ void slab_gemm(GC& c_in, AF A, PRE pre, POST post) {
+  // a register copy of the context (these functions are not always inlined,
+  // and through the reference every field read would be a memory load)
+  const GC c = c_in;
   const int nrt = c.geo.npad / 16, nct = c.geo.w / 16, np = nrt * nct, ldr = c.geo.ldr;
   int ti[kPairs], ct[kPairs];
   bool on[kPairs];
@@ -275,14 +287,14 @@ struct ASwz {  // swizzled zero-padded copy (launch_swizzle order)
   const double* e;
   int nt;
   __device__ double operator()(int ti, int tk, int r, int l) const {
-    return e[((int64_t)(ti * nt + tk) * 4 + r) * 64 + l];
+    return gmem(e)[((int64_t)(ti * nt + tk) * 4 + r) * 64 + l];
   }
 };
 struct AColMajor {  // A[i][k] = M[k*ld + i], buffer zero padded to ld x ld
   const double* M;
   int ld;
   __device__ double operator()(int ti, int tk, int r, int l) const {
-    return M[(int64_t)(16 * tk + 4 * r + (l >> 4)) * ld + 16 * ti + (l & 15)];
+    return gmem(M)[(int64_t)(16 * tk + 4 * r + (l >> 4)) * ld + 16 * ti + (l & 15)];
   }
 };
 // A[i][k] = M[i*n + k] * cs(k) (row-major n x n, identity if M is null)
@@ -294,7 +306,7 @@ struct ARowMajor {
   __device__ double operator()(int ti, int tk, int r, int l) const {
     const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
     if (i >= n || k >= n) return 0.0;
-    const double x = M ? M[(int64_t)i * n + k] : (i == k ? 1.0 : 0.0);
+    const double x = M ? gmem(M)[(int64_t)i * n + k] : (i == k ? 1.0 : 0.0);
     return x * cs(k);
   }
 };
@@ -305,7 +317,7 @@ struct ARowMajorT {
   __device__ double operator()(int ti, int tk, int r, int l) const {
     const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
     if (i >= n || k >= n) return 0.0;
-    return M ? M[(int64_t)k * n + i] : (i == k ? 1.0 : 0.0);
+    return M ? gmem(M)[(int64_t)k * n + i] : (i == k ? 1.0 : 0.0);
   }
 };
 
@@ -338,7 +350,7 @@ __device__ void slab_store_rowmajor(GC& c, double* dst) {
   const int w = c.geo.w, ldr = c.geo.ldr, n = c.n;
   for (int idx = c.t; idx < n * w; idx += kGangThreads) {
     const int i = idx / w, cc = idx - i * w, gc = c.c0 + cc;
-    if (gc < n) dst[(int64_t)i * n + gc] = L.S[cc * ldr + i];
+    if (gc < n) gmem(dst)[(int64_t)i * n + gc] = L.S[cc * ldr + i];
   }
   __syncthreads();
 }
@@ -349,7 +361,7 @@ __device__ void slab_store_rowmajor_perm(GC& c, double* dst) {
     const int q = idx / w, cc = idx - q * w, gc = c.c0 + cc;
     int row = L.piv[q];
     row = row < 0 ? 0 : (row >= n ? n - 1 : row);
-    if (gc < n) dst[(int64_t)row * n + gc] = L.S[cc * ldr + q];
+    if (gc < n) gmem(dst)[(int64_t)row * n + gc] = L.S[cc * ldr + q];
   }
   __syncthreads();
 }
@@ -359,7 +371,7 @@ __device__ void slab_store_colmajor(GC& c, double* dst) {
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
     const int cc = idx / np, i = idx - cc * np;
     const int gc = c.c0 + cc;
-    if (gc < np) dst[(int64_t)gc * np + i] = L.S[cc * ldr + i];
+    if (gc < np) gmem(dst)[(int64_t)gc * np + i] = L.S[cc * ldr + i];
   }
   __syncthreads();
 }
@@ -412,9 +424,10 @@ __device__ unsigned long long wait_keys(GC& c, const double* cb, int p) {
       here = key_tag(k) == (p & 31);
     }
     if (__all(here) || !c.ok) return wave_max_u64(k);
-    const bool abort = __hip_atomic_load(&c.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    const bool abort = __hip_atomic_load(gmem(&c.bar[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
     if (abort || wall_clock64() - t0 > kSpinTicks) {
-      if (!abort && c.l == 0) __hip_atomic_exchange(&c.bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!abort && c.l == 0)
+        __hip_atomic_exchange(gmem(&c.bar[1]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       c.ok = false;
       return wave_max_u64(k);
     }
@@ -442,7 +455,8 @@ __device__ double col_norm(const double* col, int lo, int n, int l) {
 // gc = reflector of that step, rows below it, unit entry implied), both
 // column-major npad x npad, visible to the whole gang.
 template <int kRL>
-__device__ void cpqr_gang(GC& c) {
+__device__ void cpqr_gang(GC& c_io) {
+  GC c = c_io;  // register copy, written back at the end
   const int n = c.n, ldr = c.geo.ldr;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
   // Reset this member's two key slots to tag 31 (the slots may hold keys of
@@ -596,11 +610,12 @@ __device__ void cpqr_gang(GC& c) {
       if (gc >= np) continue;
       const int sc = gc < n ? L.posl[cc] : -1;
       const double x = L.S[cc * ldr + i];
-      R[(int64_t)gc * np + i] = (gc < n && i <= sc) ? x : 0.0;
-      V[(int64_t)gc * np + i] = (gc < n && i > sc && i < n) ? x : 0.0;
+      gmem(R)[(int64_t)gc * np + i] = (gc < n && i <= sc) ? x : 0.0;
+      gmem(V)[(int64_t)gc * np + i] = (gc < n && i > sc && i < n) ? x : 0.0;
     }
   }
   gang_sync(c);
+  c_io = c;
 }
 
 // Row q of a column distributed over the wave (row i in lane i % 64, slot
@@ -623,7 +638,8 @@ __device__ __forceinline__ double row_of_col(const double (&y)[RL], int q) {
 // of them), reads each reflector once from sc_V (the next one while the
 // current one is applied) and applies it to all of them.
 template <bool ASC, int kRL>
-__device__ void apply_reflectors(GC& c, bool identity_cols) {
+__device__ void apply_reflectors(GC& c_in, bool identity_cols) {
+  const GC c = c_in;  // register copy
   constexpr int CM = 16 / kRL;
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* V = sc_V(c);
@@ -650,7 +666,7 @@ __device__ void apply_reflectors(GC& c, bool identity_cols) {
 #pragma unroll
       for (int r = 0; r < kRL; ++r) {
         const int i = c.l + 64 * r;
-        v[r] = (r < nrl && i > j && i < n) ? vc[i] : (i == j ? 1.0 : 0.0);
+        v[r] = (r < nrl && i > j && i < n) ? gmem(vc)[i] : (i == j ? 1.0 : 0.0);
       }
     };
     double vn[kRL], tn = 0.0;
@@ -694,7 +710,8 @@ __device__ void apply_reflectors(GC& c, bool identity_cols) {
 // S <- R^{-1} S (R upper triangular in pivot order: R[i][q] = sc_R[piv[q]][i]),
 // own columns in registers as above, each column of R read once per wave.
 template <int kRL>
-__device__ void back_subst(GC& c) {
+__device__ void back_subst(GC& c_in) {
+  const GC c = c_in;  // register copy
   constexpr int CM = 16 / kRL;
   const int n = c.n, ldr = c.geo.ldr, np = c.geo.npad;
   const double* R = sc_R(c);
@@ -718,7 +735,7 @@ __device__ void back_subst(GC& c) {
 #pragma unroll
       for (int r = 0; r < kRL; ++r) {
         const int i = c.l + 64 * r;
-        rv[r] = (r < nrl && i < q) ? rc[i] : 0.0;
+        rv[r] = (r < nrl && i < q) ? gmem(rc)[i] : 0.0;
       }
     };
     double rn[kRL];
@@ -790,7 +807,7 @@ __device__ double refl_sign(GC& c) {
 // ---- stage loop ----------------------------------------------------------------
 __device__ void load_slice_scale(GC& c, const Inst& I, int q) {
   const double* f = I.field + (int64_t)(q - 1) * I.n;
-  for (int i = c.t; i < c.geo.npad; i += kGangThreads) L.tau[i] = i < c.n ? exp(I.alpha * f[i]) : 0.0;
+  for (int i = c.t; i < c.geo.npad; i += kGangThreads) L.tau[i] = i < c.n ? exp(I.alpha * gmem(f)[i]) : 0.0;
   __syncthreads();
 }
 
@@ -812,7 +829,7 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
   auto copy_t = [&](double* dst) {
     for (int idx = c.t; idx < n * c.geo.w; idx += kGangThreads) {
       const int i = idx / c.geo.w, gc = c.c0 + (idx - i * c.geo.w);
-      if (gc < n) dst[(int64_t)i * n + gc] = Tg[(int64_t)i * n + gc];
+      if (gc < n) gmem(dst)[(int64_t)i * n + gc] = gmem(Tg)[(int64_t)i * n + gc];
     }
   };
   for (int s = 0; s < nb; ++s) {
@@ -834,7 +851,7 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
     }
     cpqr_gang<kRL>(c);
     // T <- D^{-1} R P^T T with D = |diag R|
-    slab_fill_rows(c, [&](int i, int gc) { return Tg[(int64_t)i * n + gc]; });
+    slab_fill_rows(c, [&](int i, int gc) { return gmem(Tg)[(int64_t)i * n + gc]; });
     __syncthreads();
     slab_gemm(c, AColMajor{sc_R(c), np}, One{},
               [&](int row) { return row < n ? 1.0 / fabs(L.beta[row]) : 0.0; });
@@ -851,8 +868,8 @@ __device__ void sweep_gang(GC& c, const Inst& I, int flags) {
       slab_store_rowmajor(c, dst);
       copy_t(dst + (int64_t)n * n);
       if (c.g == 0) {
-        for (int i = c.t; i < n; i += kGangThreads) dst[2 * (int64_t)n * n + i] = fabs(L.beta[i]);
-        if (c.t == 0) dst[2 * (int64_t)n * n + n] = sgn_u;
+        for (int i = c.t; i < n; i += kGangThreads) gmem(dst)[2 * (int64_t)n * n + i] = fabs(L.beta[i]);
+        if (c.t == 0) gmem(dst)[2 * (int64_t)n * n + n] = sgn_u;
       }
     }
   }
@@ -881,19 +898,19 @@ __device__ void equal_gang(GC& c, const Inst& I) {
   const double* U = I.fin;
   const double* T = I.fin + (int64_t)n * n;
   const double* D = I.fin + 2 * (int64_t)n * n;
-  const double sgn_u = I.fin[2 * (int64_t)n * n + n];
+  const double sgn_u = gmem(I.fin)[2 * (int64_t)n * n + n];
   const bool loh = I.scheme == 0;
-  auto dp = [&](int i) { const double d = D[i]; return (loh && d > 1.0) ? d : 1.0; };
-  auto dm = [&](int i) { const double d = D[i]; return (loh && d > 1.0) ? 1.0 : d; };
-  slab_fill_rows(c, [&](int i, int gc) { return dm(i) * T[(int64_t)i * n + gc]; });
+  auto dp = [&](int i) { const double d = gmem(D)[i]; return (loh && d > 1.0) ? d : 1.0; };
+  auto dm = [&](int i) { const double d = gmem(D)[i]; return (loh && d > 1.0) ? 1.0 : d; };
+  slab_fill_rows(c, [&](int i, int gc) { return dm(i) * gmem(T)[(int64_t)i * n + gc]; });
   __syncthreads();
   for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
     const int cc = idx / c.geo.npad, i = idx - cc * c.geo.npad, gc = c.c0 + cc;
-    if (i < n && gc < n) L.S[cc * c.geo.ldr + i] += U[(int64_t)gc * n + i] / dp(i);
+    if (i < n && gc < n) L.S[cc * c.geo.ldr + i] += gmem(U)[(int64_t)gc * n + i] / dp(i);
   }
   __syncthreads();
   cpqr_gang<kRL>(c);
-  slab_fill_cols(c, [&](int i, int gc) { return U[(int64_t)gc * n + i] / dp(i); });
+  slab_fill_cols(c, [&](int i, int gc) { return gmem(U)[(int64_t)gc * n + i] / dp(i); });
   __syncthreads();
   apply_reflectors<true, kRL>(c, false);
   back_subst<kRL>(c);
@@ -907,7 +924,7 @@ __device__ void equal_gang(GC& c, const Inst& I) {
   if (c.g == 0 && c.w == 0) {
     double ls = 0.0, ng = 0.0;
     for (int i = c.l; i < n; i += 64) {
-      const double d = D[i];
+      const double d = gmem(D)[i];
       if (!isfinite(d) || !(d > 0.0)) bad = 1;
       ls += log(dp(i)) + log(fabs(L.beta[i]));  // dp = 1 without the split
       ng += L.beta[i] < 0.0 ? 1.0 : 0.0;
@@ -944,16 +961,16 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
   const double* U2 = A;
   const double* T2 = A ? A + (int64_t)n * n : nullptr;
   const double* D2 = A ? A + 2 * (int64_t)n * n : nullptr;
-  auto d1 = [&](int i) { return D1 ? D1[i] : 1.0; };
-  auto d2 = [&](int i) { return D2 ? D2[i] : 1.0; };
+  auto d1 = [&](int i) { return D1 ? gmem(D1)[i] : 1.0; };
+  auto d2 = [&](int i) { return D2 ? gmem(D2)[i] : 1.0; };
   double* Xg = sc_X(c);
   // P2 = T1 T2^T (slab columns), kept in HBM while P1 = U1^T U2 is formed
-  slab_fill_cols(c, [&](int i, int gc) { return T2 ? T2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  slab_fill_cols(c, [&](int i, int gc) { return T2 ? gmem(T2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
   __syncthreads();
   slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, One{});
   slab_store_colmajor(c, Xg);
   __syncthreads();
-  slab_fill_rows(c, [&](int i, int gc) { return U2 ? U2[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0); });
+  slab_fill_rows(c, [&](int i, int gc) { return U2 ? gmem(U2)[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0); });
   __syncthreads();
   slab_gemm(c, ARowMajorT{U1, n}, One{}, One{});
   // Mid
@@ -966,14 +983,14 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
     const double rpi = 1.0 / (b > 1.0 ? b : 1.0);  // D_Rp^{-1}
     const double rm = b < 1.0 ? b : 1.0;            // D_Rm
     double* e = &L.S[cc * c.geo.ldr + i];
-    *e = lm * (*e) * rpi + lpi * Xg[(int64_t)gc * np + i] * rm;
+    *e = lm * (*e) * rpi + lpi * gmem(Xg)[(int64_t)gc * np + i] * rm;
   }
   __syncthreads();
   cpqr_gang<kRL>(c);
   // Y = D_Lp^{-1} T1 -> Q^T Y -> R^{-1} (pivot order)
   slab_fill_rows(c, [&](int i, int gc) {
     const double a = d1(i);
-    return (T1 ? T1[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0)) * (a < 1.0 ? a : 1.0);
+    return (T1 ? gmem(T1)[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0)) * (a < 1.0 ? a : 1.0);
   });
   __syncthreads();
   apply_reflectors<true, kRL>(c, false);
@@ -985,19 +1002,19 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
     if (q < n) {
       int row = L.piv[q];
       row = row < 0 ? 0 : (row >= n ? n - 1 : row);
-      Xg[(int64_t)gc * np + row] = gc < n ? L.S[cc * c.geo.ldr + q] : 0.0;
+      gmem(Xg)[(int64_t)gc * np + row] = gc < n ? L.S[cc * c.geo.ldr + q] : 0.0;
     } else {
-      Xg[(int64_t)gc * np + q] = 0.0;
+      gmem(Xg)[(int64_t)gc * np + q] = 0.0;
     }
   }
   __syncthreads();
-  slab_fill_cols(c, [&](int i, int gc) { return Xg[(int64_t)gc * np + i]; });
+  slab_fill_cols(c, [&](int i, int gc) { return gmem(Xg)[(int64_t)gc * np + i]; });
   __syncthreads();
   // G = (U2 D_Rp^{-1}) X
   struct RP {
     const double* D2;
     __device__ double operator()(int kk) const {
-      const double b = D2 ? D2[kk] : 1.0;
+      const double b = D2 ? gmem(D2)[kk] : 1.0;
       return 1.0 / (b > 1.0 ? b : 1.0);
     }
   };
@@ -1042,17 +1059,17 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   double* Ug = sc_U(c);
   double* Tg = sc_T(c);
   // D1 (T1 T2^T) D2
-  slab_fill_cols(c, [&](int i, int gc) { return T2 ? T2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  slab_fill_cols(c, [&](int i, int gc) { return T2 ? gmem(T2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
   __syncthreads();
-  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, [&](int row) { return D1 && row < n ? D1[row] : 1.0; });
+  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, [&](int row) { return D1 && row < n ? gmem(D1)[row] : 1.0; });
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
     const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    if (gc < n && D2) L.S[cc * ldr + i] *= D2[gc];
+    if (gc < n && D2) L.S[cc * ldr + i] *= gmem(D2)[gc];
   }
   __syncthreads();
   cpqr_gang<kRL>(c);
   // T = d^{-1} (R P^T) U2^T  (slab columns), to HBM
-  slab_fill_cols(c, [&](int i, int gc) { return U2 ? U2[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
+  slab_fill_cols(c, [&](int i, int gc) { return U2 ? gmem(U2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
   __syncthreads();
   slab_gemm(c, AColMajor{sc_R(c), np}, One{},
             [&](int row) { return row < n ? 1.0 / fabs(L.beta[row]) : 0.0; });
@@ -1066,20 +1083,20 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   // D of the combined factorization: |beta| (kept in L.red-free storage: HBM)
   double* Dg = sc_X(c);
   if (c.g == 0)
-    for (int i = c.t; i < n; i += kGangThreads) Dg[i] = fabs(L.beta[i]);
+    for (int i = c.t; i < n; i += kGangThreads) gmem(Dg)[i] = fabs(L.beta[i]);
   gang_sync(c);
   // M = Dp^{-1} U^T + Dm T
-  auto dp = [&](int i) { const double d = Dg[i]; return d > 1.0 ? d : 1.0; };
-  auto dm = [&](int i) { const double d = Dg[i]; return d < 1.0 ? d : 1.0; };
-  slab_fill_rows(c, [&](int i, int gc) { return Ug[(int64_t)i * np + gc] / dp(i); });
+  auto dp = [&](int i) { const double d = gmem(Dg)[i]; return d > 1.0 ? d : 1.0; };
+  auto dm = [&](int i) { const double d = gmem(Dg)[i]; return d < 1.0 ? d : 1.0; };
+  slab_fill_rows(c, [&](int i, int gc) { return gmem(Ug)[(int64_t)i * np + gc] / dp(i); });
   __syncthreads();
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
     const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    if (i < n && gc < n) L.S[cc * ldr + i] += dm(i) * Tg[(int64_t)gc * np + i];
+    if (i < n && gc < n) L.S[cc * ldr + i] += dm(i) * gmem(Tg)[(int64_t)gc * np + i];
   }
   __syncthreads();
   cpqr_gang<kRL>(c);
-  slab_fill_rows(c, [&](int i, int gc) { return Ug[(int64_t)i * np + gc] / dp(i); });
+  slab_fill_rows(c, [&](int i, int gc) { return gmem(Ug)[(int64_t)i * np + gc] / dp(i); });
   __syncthreads();
   apply_reflectors<true, kRL>(c, false);
   back_subst<kRL>(c);
@@ -1091,18 +1108,18 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
     if (q < n) {
       int row = L.piv[q];
       row = row < 0 ? 0 : (row >= n ? n - 1 : row);
-      Gb[0][(int64_t)gc * np + row] = gc < n ? L.S[cc * ldr + q] : 0.0;
+      gmem(Gb[0])[(int64_t)gc * np + row] = gc < n ? L.S[cc * ldr + q] : 0.0;
     } else {
-      Gb[0][(int64_t)gc * np + q] = 0.0;
+      gmem(Gb[0])[(int64_t)gc * np + q] = 0.0;
     }
   }
   gang_sync(c);
   const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
   bool bad = false;
   for (int gc = c.c0 + c.t; gc < c.c0 + c.geo.w && gc < n; gc += kGangThreads) {
-    const double gii = Gb[0][(int64_t)gc * np + gc];
+    const double gii = gmem(Gb[0])[(int64_t)gc * np + gc];
     bad |= !isfinite(gii);
-    I.grad[(int64_t)(l0 - 1) * n + gc] = I.alpha * (1.0 - gii);
+    gmem(I.grad)[(int64_t)(l0 - 1) * n + gc] = I.alpha * (1.0 - gii);
   }
   const ASwz aop{I.esw, np / 16};
   int cur = 0;
@@ -1117,7 +1134,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
     for (int gc = c.c0 + c.t; gc < c.c0 + c.geo.w && gc < n; gc += kGangThreads) {
       const double gii = L.S[(gc - c.c0) * ldr + gc];
       bad |= !isfinite(gii);
-      I.grad[(int64_t)l * n + gc] = I.alpha * (1.0 - gii);
+      gmem(I.grad)[(int64_t)l * n + gc] = I.alpha * (1.0 - gii);
     }
     cur ^= 1;
     gang_sync(c);
@@ -1130,7 +1147,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
 template <int kRL>
 __device__ void udt_gang(GC& c, const double* w, double* u, double* d, double* t) {
   const int n = c.n, np = c.geo.npad;
-  slab_fill_rows(c, [&](int i, int gc) { return w[(int64_t)i * n + gc]; });
+  slab_fill_rows(c, [&](int i, int gc) { return gmem(w)[(int64_t)i * n + gc]; });
   __syncthreads();
   cpqr_gang<kRL>(c);
   // T = D^{-1} R P^T
