@@ -671,12 +671,14 @@ __device__ __forceinline__ void load_reflector(const Lane& L, const Smem<NT, P, 
   }
 }
 
-// X <- H_j X for all column blocks (tiles below TJ untouched)
+// X <- H_j X for all column blocks (tiles below TJ untouched); column
+// tiles whose columns all lie left of `cmin` are skipped
 template <int TJ, int NT, int P>
 __device__ __forceinline__ void apply_reflector(const Lane& L, double tau, const double (&v)[NT][4],
-                                                RM<NT, P>& X) {
+                                                RM<NT, P>& X, int cmin = 0) {
 #pragma unroll
   for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    if (16 * (L.w + P * c) + 15 < cmin) continue;  // wave-uniform
     double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ti = TJ; ti < NT; ++ti)
@@ -691,19 +693,24 @@ __device__ __forceinline__ void apply_reflector(const Lane& L, double tau, const
 }
 
 // Q = H_0 H_1 ... H_{n-1} into registers (reflectors applied last to first,
-// tile by tile)
+// tile by tile).  When H_j is applied, the columns left of j are still unit
+// vectors e_c (c < j) that H_j leaves as they are, so a wave whose columns
+// all lie left of j skips it.
 template <int NT, int P, bool ELDS>
 __device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& X) {
   set_identity<NT, P>(L, X);
+  // rightmost column this wave holds
+  const int cmax = 16 * (L.w + P * (Geo<NT, P>::CT - 1)) + 15;
   static_for<NT>([&](auto kc) {
     constexpr int TJ = NT - 1 - decltype(kc)::value;
     const int jhi = (16 * TJ + 15 < n - 1 ? 16 * TJ + 15 : n - 1);
-    for (int j = jhi; j >= 16 * TJ; --j) {
+    const int jtop = jhi < cmax ? jhi : cmax;
+    for (int j = jtop; j >= 16 * TJ; --j) {
       const double tau = S.tau[j];
       if (tau == 0.0) continue;
       double v[NT][4];
       load_reflector<TJ, NT, P, ELDS>(L, S, j, v);
-      apply_reflector<TJ, NT, P>(L, tau, v, X);
+      apply_reflector<TJ, NT, P>(L, tau, v, X, j);
     }
   });
 }
