@@ -200,3 +200,31 @@ def test_gang_large_config_sampled(ctx):
         for l in checks:
             ref = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l)
             assert relF(gts[a][ls.index(l)].cpu().numpy(), ref) <= TOL_G, (a, l)
+
+
+def test_gang_n1024_beta40_all_tau():
+    """The large-instance shape with its L = 32 chain: n = 1024, beta = 40
+    (M = 400, k = 10), G(tau_l, 0) at every l = 0..400 in one call.  The oracle
+    cannot run at this size, so the check is on relations that hold exactly:
+    G(0,0) = G and G(beta,0) = 1 - G (both routes computed independently of
+    each other), and G(tau_20,0) (computed directly from the stage pair at
+    tau = 20 slices) = B_20 G(tau_19,0) (propagated nine slices from tau = 10)."""
+    ctx = sdq.Context(0)
+    I = wl.hubbard_ising(32, 40.0, 1, 1, seed=wl.BASE_SEED + 790)[0]
+    ls = list(range(0, 401))
+    say("[gpu] sdq_greens_tdisp n=1024 m=400, all 401 tau")
+    gts, gs, ld, sg, st = ctx.greens_tdisp(chains_of([I]), ls)
+    torch.cuda.synchronize()
+    assert st.item() == 0
+    g = gs[0].cpu().numpy()
+    g0 = gts[0][0].cpu().numpy()
+    gb = gts[0][400].cpu().numpy()
+    g19 = gts[0][19].cpu().numpy()
+    g20 = gts[0][20].cpu().numpy()
+    assert np.isfinite(ld.item()) and sg.item() in (-1.0, 1.0)
+    e0, eb = relF(g0, g), relF(gb, np.eye(1024) - g)
+    b20 = I.expk * np.exp(I.alpha * I.field[19])[None, :]
+    ep = relF(b20 @ g19, g20)
+    say(f"[gpu]   relF: G(0,0) vs G {e0:.2e}, G(beta,0) vs 1-G {eb:.2e}, B_20 G(19) vs G(20) {ep:.2e}")
+    assert e0 <= TOL_G and eb <= TOL_G and ep <= TOL_G
+    ctx.close()
