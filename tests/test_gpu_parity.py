@@ -197,6 +197,21 @@ def test_grad_L8_beta20_sampled(ctx):
             assert relF(g[l - 1], ref[r]) <= TOL_G, (a, l, relF(g[l - 1], ref[r]))
 
 
+def test_logdet_matches_det_of_g(ctx):
+    """The GPU's log|det(1+B)| and sign against the determinant of its own G
+    (det G det(1+B) = 1), where G is well conditioned (small beta)."""
+    insts = wl.hubbard_ising(4, 2.0, 1, 2, seed=wl.BASE_SEED + 964) + \
+        wl.hubbard_ising(8, 1.0, 1, 2, seed=wl.BASE_SEED + 968)
+    say("[gpu] det(G) det(1+B) = 1, L=4 beta=2 and L=8 beta=1")
+    gs, ld, sg, st = ctx.greens(chains_of(insts))
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for a in range(len(insts)):
+        s2, l2 = np.linalg.slogdet(gs[a].cpu().numpy())
+        assert abs(l2 + ld[a].item()) <= 1e-12 * abs(ld[a].item()), (a, l2, ld[a].item())
+        assert s2 == sg[a].item()
+
+
 def test_status_flags_nonfinite_field(ctx):
     I = wl.hubbard_ising(4, 2.0, 1, 1, seed=1)[0]
     f = I.field.copy()

@@ -305,6 +305,21 @@ def test_ill_conditioned_chain_k1_reference():
 # --------------------------------------------------------------------------
 # identities
 
+@pytest.mark.parametrize("L,beta", [(4, 2.0), (6, 1.0), (8, 1.0)])
+def test_det_g_times_det_one_plus_b(L, beta):
+    """det(G) det(1 + B_M..B_1) = 1 in log form: log|det G| + log|det(1+B)| = 0
+    and the signs agree, with det G taken by LU of the oracle's G.  Checked
+    where G is well conditioned (cond(G) <= 1e7 here); at beta >= 10 the
+    determinant of G itself cannot be formed in FP64 (cond(G) ~ 1e17 and up),
+    which is why the method returns log|det(1+B)| from its factorization."""
+    for f in wl.hubbard_ising(L, beta, 1, 2, seed=wl.BASE_SEED + 960 + L):
+        G, ld, sg = oracle.greens(f.expk, f.field, f.alpha, f.k)
+        assert np.linalg.cond(G) <= 1e7
+        s2, l2 = np.linalg.slogdet(G)
+        assert abs(l2 + ld) <= 1e-12 * abs(ld), (l2, ld)
+        assert s2 == sg
+
+
 def test_flavour_particle_hole_identity():
     """Even L, mu = 0: with Lambda = diag((-1)^(x+y)), Lambda K Lambda = -K,
     so B_dn(beta,0) = Lambda B_up(beta,0)^{-T} Lambda and
