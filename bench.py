@@ -79,8 +79,8 @@ def main():
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the path shards by independent chains, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path would shard by independent chains, each GPU taking a share)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -45,3 +45,15 @@ def test_instance_struct_layout():
     # matches sdq_instance: 4 int32, 3 pointers, 1 double
     assert ctypes.sizeof(binding._Instance) == 16 + 3 * 8 + 8
     assert binding._Instance.alpha.offset == 40
+
+
+def test_bench_rejects_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with status 2
+    and says so, before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
