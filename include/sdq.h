@@ -157,6 +157,21 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
                          double* d, double* t);
 
+/* M <- left * M * right for `count` n x n row-major device matrices: mats is
+ * a host array [count] of device pointers (updated in place; the entries
+ * must not overlap), left and right are device n x n matrices shared by the
+ * batch.  1 <= n <= 128 (SDQ_EUNSUPPORTED above).
+ * Use: the paper's slice is the symmetric Trotter form
+ * B_l = E^{1/2} diag(exp(alpha f_l)) E^{1/2} (Sec. 2, E^{1/2} = exp(-dtau K/2));
+ * its chain is E^{-1/2} (B'_M ... B'_1) E^{1/2} with the slices
+ * B'_l = E diag(exp(alpha f_l)) every other call uses (expk = E).  So log|det|,
+ * its sign and the field gradient are the same for both forms, and the
+ * symmetric form's G and G(tau,0) are E^{-1/2} X E^{1/2} of the results X of
+ * sdq_greens / sdq_greens_tdisp: call this with left = E^{-1/2},
+ * right = E^{1/2} on them. */
+sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,
+                          const double* right, double* const* mats);
+
 /* Time every kernel variant for each n of n_list[count] (host) on the
  * device, keep the fastest per n in ctx, and if cache_path is not NULL
  * append the choices to that JSON-lines file (read back by later contexts

@@ -48,6 +48,8 @@ def lib():
         L.or_logdet_grad.argtypes = [c_int, c_int, c_int, d, d, c_double, i, c_int, d]
         L.or_greens_naive.argtypes = [c_int, c_int, c_int, d, d, c_double, d]
         L.or_chain.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, c_int, c_int, d, d, d]
+        L.or_greens_sym.argtypes = [c_int, c_int, c_int, d, d, c_double, d, d, d]
+        L.or_greens_tdisp_sym.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, d]
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
@@ -93,6 +95,27 @@ def greens_tdisp(expk, expk_inv, field, alpha, k, l, scheme=SCHEME_LOH):
     G = np.zeros((n, n))
     _chk(lib().or_greens_tdisp(n, m, k, _p(expk), _p(expk_inv), _p(field), float(alpha),
                                int(l), scheme, _p(G)))
+    return G
+
+
+def greens_sym(expk_half, field, alpha, k):
+    """G, log|det(1+B_M..B_1)| and sign for the symmetric Trotter slices
+    B_l = H diag(exp(alpha f_l)) H with H = expk_half = exp(-dtau K / 2)."""
+    expk_half, field = _c(expk_half), _c(field)
+    m, n = field.shape
+    G = np.zeros((n, n))
+    ld, sg = np.zeros(1), np.zeros(1)
+    _chk(lib().or_greens_sym(n, m, k, _p(expk_half), _p(field), float(alpha), _p(G), _p(ld), _p(sg)))
+    return G, float(ld[0]), float(sg[0])
+
+
+def greens_tdisp_sym(expk_half, expk_half_inv, field, alpha, k, l):
+    """G(tau_l, 0) = B_l..B_1 G for the symmetric Trotter slices."""
+    expk_half, expk_half_inv, field = _c(expk_half), _c(expk_half_inv), _c(field)
+    m, n = field.shape
+    G = np.zeros((n, n))
+    _chk(lib().or_greens_tdisp_sym(n, m, k, _p(expk_half), _p(expk_half_inv), _p(field),
+                                   float(alpha), int(l), _p(G)))
     return G
 
 

@@ -27,6 +27,8 @@
  *   inv_sum            Sec. 6.1, scheme inv_sum
  *   or_greens_slice    App. A.1 (combining two stack elements into G_l),
  *                      G_l defined in Sec. 6 (equal-time G at slice l)
+ *   or_greens_sym,     the same for the symmetric Trotter slice
+ *   or_greens_tdisp_sym  B_l = E^{1/2} diag(v_l) E^{1/2} of Sec. 2
  *   or_logdet_grad     d log|det(1+B_M..B_1)| / d f_{l,i} = alpha (1-G_l)_ii
  *                      (Jacobi's formula; see the function comment)
  *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
@@ -322,13 +324,14 @@ static void qr_inverse(int n, const double* M, double* Minv, double* logabsdet, 
 
 typedef struct {
   int n, m, k;
-  const double* expk;
-  const double* expk_inv;
+  const double* expk;      /* E, or H = E^{1/2} when sym is set */
+  const double* expk_inv;  /* E^{-1}, or H^{-1} when sym is set */
   const double* field;
   double alpha;
+  int sym;                 /* 1: the symmetric Trotter slice H diag(v) H (Sec. 2) */
 } problem;
 
-enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2 };
+enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4 };
 
 /* W <- X_q W with X_q = B_q, B_q^{-1} or B_q^T (q is 1-based). */
 static void apply_slice(const problem* P, int kind, int q, double* W, double* tmp) {
@@ -344,6 +347,15 @@ static void apply_slice(const problem* P, int kind, int q, double* W, double* tm
     for (int i = 0; i < n; ++i) v[i] = 1.0 / v[i];
     scale_rows(n, tmp, v);
     mat_copy(n, tmp, W);
+  } else if (kind == SLICE_BSYM) {   /* B_q = H diag(v) H, H = E^{1/2} */
+    mat_mul(n, P->expk, W, tmp);
+    scale_rows(n, tmp, v);
+    mat_mul(n, P->expk, tmp, W);
+  } else if (kind == SLICE_BSYMINV) {  /* B_q^{-1} = H^{-1} diag(1/v) H^{-1} */
+    mat_mul(n, P->expk_inv, W, tmp);
+    for (int i = 0; i < n; ++i) v[i] = 1.0 / v[i];
+    scale_rows(n, tmp, v);
+    mat_mul(n, P->expk_inv, tmp, W);
   } else {                           /* B_q^T = diag(v) E^T */
     mat_mul_tn(n, P->expk, W, tmp);
     scale_rows(n, tmp, v);
@@ -386,7 +398,7 @@ static void chain_fwd(const problem* P, int a, int b, double* U, double* D, doub
   const int cnt = b >= a ? b - a + 1 : 0;
   int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
   for (int s = 0; s < cnt; ++s) order[s] = a + s;
-  chain_udt(P, SLICE_B, order, cnt, U, D, T);
+  chain_udt(P, P->sym ? SLICE_BSYM : SLICE_B, order, cnt, U, D, T);
   free(order);
 }
 
@@ -395,7 +407,7 @@ static void chain_inv(const problem* P, int a, int b, double* U, double* D, doub
   const int cnt = b >= a ? b - a + 1 : 0;
   int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
   for (int s = 0; s < cnt; ++s) order[s] = b - s;
-  chain_udt(P, SLICE_BINV, order, cnt, U, D, T);
+  chain_udt(P, P->sym ? SLICE_BSYMINV : SLICE_BINV, order, cnt, U, D, T);
   free(order);
 }
 
@@ -581,6 +593,40 @@ int or_greens_tdisp(int n, int m, int k, const double* expk, const double* expk_
     inv_sum(n, UL, DL, XL, UR, DR, XR, Gt);
   else
     inv_sum_loh(n, UL, DL, XL, UR, DR, XR, Gt);
+  free(UL); free(XL); free(UR); free(XR); free(DL); free(DR);
+  return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
+}
+
+/* The same two quantities for the symmetric Trotter slices of Sec. 2,
+ *   B_l = H diag(exp(alpha f_l)) H,  H = exp(-dtau K / 2)  (expk_half),
+ * multiplied out slice by slice in that form (no similarity transform is
+ * used): G and log|det|, sign by inv_one_plus_loh; G(tau_l, 0) by the two
+ * chains of B^{-1} = H^{-1} diag(1/v) H^{-1} and B, and inv_sum_loh. */
+int or_greens_sym(int n, int m, int k, const double* expk_half, const double* field, double alpha,
+                  double* G, double* logdet, double* sign) {
+  int st = check(n, m, k, expk_half, field);
+  if (st) return st;
+  problem P = {n, m, k, expk_half, NULL, field, alpha, 1};
+  double* U = mat_new(n);
+  double* T = mat_new(n);
+  double* D = (double*)malloc(sizeof(double) * n);
+  chain_fwd(&P, 1, m, U, D, T);
+  inv_one_plus_loh(n, U, D, T, G, logdet, sign);
+  free(U); free(T); free(D);
+  return finite_all(n, G) ? OR_OK : OR_ERANGE;
+}
+
+int or_greens_tdisp_sym(int n, int m, int k, const double* expk_half, const double* expk_half_inv,
+                        const double* field, double alpha, int l, double* Gt) {
+  int st = check(n, m, k, expk_half, field);
+  if (st) return st;
+  if (!expk_half_inv || l < 0 || l > m) return OR_EINVAL;
+  problem P = {n, m, k, expk_half, expk_half_inv, field, alpha, 1};
+  double *UL = mat_new(n), *XL = mat_new(n), *UR = mat_new(n), *XR = mat_new(n);
+  double *DL = malloc(sizeof(double) * n), *DR = malloc(sizeof(double) * n);
+  chain_inv(&P, 1, l, UL, DL, XL);
+  chain_fwd(&P, l + 1, m, UR, DR, XR);
+  inv_sum_loh(n, UL, DL, XL, UR, DR, XR, Gt);
   free(UL); free(XL); free(UR); free(XR); free(DL); free(DR);
   return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
 }

@@ -27,7 +27,7 @@ SCHEME_LOH, SCHEME_PLAIN = 0, 1
 EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_greens",
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
-           "sdq_kernel_stats", "sdq_sync")
+           "sdq_kernel_stats", "sdq_sync", "sdq_similarity")
 
 
 class SdqError(RuntimeError):
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_set_profiling.argtypes = [vp, ctypes.c_int]
     L.sdq_kernel_stats.argtypes = [vp, ctypes.c_char_p, P(i64), P(dbl)]
     L.sdq_sync.argtypes = [vp]
+    L.sdq_similarity.argtypes = [vp, i32, i32, vp, vp, P(vp)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -236,6 +237,25 @@ class Context:
         u, t, d = self._empty(cnt, n, n), self._empty(cnt, n, n), self._empty(cnt, n)
         self._chk(self.lib.sdq_chain_udt(self.h, inst, cnt, _ptr(u), _ptr(d), _ptr(t)))
         return u, d, t
+
+    def similarity(self, mats, left, right):
+        """M <- left @ M @ right in place for every n x n matrix of `mats` (a
+        list of device tensors whose last two dims are n x n; every matrix of
+        each is transformed).  With left = E^{-1/2}, right = E^{1/2} this maps
+        G and G(tau,0) of the slices E diag(v) to those of the symmetric
+        slices E^{1/2} diag(v) E^{1/2}."""
+        n = left.shape[0]
+        _check_tensor(left, "left", (n, n), self.tdev)
+        _check_tensor(right, "right", (n, n), self.tdev)
+        ptrs = []
+        for t in mats:
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.tdev or \
+                    t.dim() < 2 or tuple(t.shape[-2:]) != (n, n):
+                raise ValueError(f"mats: need contiguous float64 (..., {n}, {n}) tensors on {self.tdev}")
+            for b in range(t.numel() // (n * n)):
+                ptrs.append(t.data_ptr() + b * n * n * 8)
+        arr = (ctypes.c_void_p * max(len(ptrs), 1))(*ptrs)
+        self._chk(self.lib.sdq_similarity(self.h, n, len(ptrs), _ptr(left), _ptr(right), arr))
 
     def tune(self, n_list, cache_path=None):
         arr = (ctypes.c_int32 * len(n_list))(*n_list)

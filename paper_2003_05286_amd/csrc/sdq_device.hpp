@@ -1640,6 +1640,39 @@ __global__ __launch_bounds__(64 * P) void k_udt(int n, int count, const double* 
 }
 
 // ---------------------------------------------------------------------------
+// M <- left * M * right for `count` n x n row-major matrices given by a
+// device table of pointers (used to turn results for the slices E diag(v_l)
+// into those of the symmetric slices E^{1/2} diag(v_l) E^{1/2}, Sec. 2).
+// One workgroup per matrix in a grid-stride loop; `right` stays in registers
+// for the whole launch.
+template <int NT, int P>
+__global__ __launch_bounds__(64 * P) void k_similarity(int n, int count, double* const* __restrict__ mats,
+                                                       const double* __restrict__ left,
+                                                       const double* __restrict__ right) {
+  const Lane L = lane_id();
+  RM<NT, P> R, X, Y;
+  load_rm<NT, P>(L, R, right, n, false);
+  for (int b = blockIdx.x; b < count; b += gridDim.x) {
+    double* M = gmem(mats)[b];
+    // X = M right
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int k) -> double {
+                     return (i < n && k < n) ? gmem(M)[(size_t)i * n + k] : 0.0;
+                   },
+                   R, X);
+    // every wave has read all of M before any wave writes it back
+    __syncthreads();
+    // Y = left X
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int k) -> double {
+                     return (i < n && k < n) ? gmem(left)[(size_t)i * n + k] : 0.0;
+                   },
+                   X, Y);
+    store_rm<NT, P>(L, Y, M, n);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // per-tile-count launchers (instantiated once per NT in sdq_nt.hip)
 
 // waves per chain: one per 16-column tile, at most four
@@ -1674,6 +1707,12 @@ struct Launch {
                          l_list, q);
     else
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_EQUAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
+    return hipGetLastError();
+  }
+  static hipError_t similarity(int n, int count, double* const* mats, const double* left,
+                               const double* right, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_similarity<NT, P>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, n, count,
+                       mats, left, right);
     return hipGetLastError();
   }
   static hipError_t udt(int n, int count, const double* w, double* u, double* d, double* t,

@@ -9,6 +9,7 @@ namespace sdq {
   hipError_t launch_pair_nt##N(int, const Inst*, const PairItem*, int, const int32_t*, Queue*, int, \
                                hipStream_t);                                                     \
   hipError_t launch_udt_nt##N(int, int, const double*, double*, double*, double*, hipStream_t);  \
+  hipError_t launch_sim_nt##N(int, int, double* const*, const double*, const double*, int, hipStream_t); \
   hipError_t kernel_info_nt##N(int, int, KernelInfo*);
 SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL(7) SDQ_DECL(8)
 #undef SDQ_DECL
@@ -48,6 +49,12 @@ hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, doub
 #undef C
 }
 
+hipError_t launch_similarity(int nt, int n, int count, double* const* mats, const double* left,
+                             const double* right, int grid, hipStream_t s) {
+#define C(N) launch_sim_nt##N(n, count, mats, left, right, grid, s)
+  SDQ_SWITCH(C)
+#undef C
+}
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
 #define C(N) kernel_info_nt##N(kind, variant, out)
   SDQ_SWITCH(C)

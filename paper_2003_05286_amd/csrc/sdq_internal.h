@@ -106,6 +106,9 @@ hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const Pa
                        int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s);
 hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, double* d, double* t,
                       hipStream_t s);
+// M <- left M right for count n x n matrices (device pointer table), n <= 128
+hipError_t launch_similarity(int nt, int n, int count, double* const* mats, const double* left,
+                             const double* right, int grid, hipStream_t s);
 
 enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2 };
 

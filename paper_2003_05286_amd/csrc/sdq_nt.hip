@@ -25,6 +25,10 @@ hipError_t SDQ_CAT(launch_udt_nt, SDQ_NT)(int n, int count, const double* w, dou
                                          double* t, hipStream_t s) {
   return Launch<SDQ_NT>::udt(n, count, w, u, d, t, s);
 }
+hipError_t SDQ_CAT(launch_sim_nt, SDQ_NT)(int n, int count, double* const* mats, const double* left,
+                                         const double* right, int grid, hipStream_t s) {
+  return Launch<SDQ_NT>::similarity(n, count, mats, left, right, grid, s);
+}
 hipError_t SDQ_CAT(kernel_info_nt, SDQ_NT)(int kind, int variant, KernelInfo* out) {
   return Launch<SDQ_NT>::info(kind, variant, out);
 }

@@ -74,6 +74,7 @@ struct sdq_ctx {
   int num_cu = 256;
   DevBuf d_upload, d_ck, d_swz, d_fin;
   DevBuf d_gang;  // per-gang scratch of the n > 128 kernels (bars first)
+  DevBuf d_ptrs;  // matrix pointer table of sdq_similarity
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   void* h_stage = nullptr;
   size_t h_cap = 0;
@@ -649,6 +650,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
   if (ctx->d_fin.p) (void)hipFree(ctx->d_fin.p);
   if (ctx->d_gang.p) (void)hipFree(ctx->d_gang.p);
+  if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
@@ -931,6 +933,31 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
     });
   }
   return timed(ctx, "udt", [&] { return sdq::launch_udt(nt, n, count, w, u, d, t, ctx->stream); });
+}
+
+sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,
+                          const double* right, double* const* mats) {
+  if (!ctx) return SDQ_EINVAL;
+  if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
+  if (n > 16 * sdq::kMaxNT) return fail(ctx, SDQ_EUNSUPPORTED, "sdq_similarity supports n <= 128");
+  if (count == 0) return SDQ_OK;
+  if (!left || !right || !mats) return fail(ctx, SDQ_EINVAL, "null pointer");
+  for (int i = 0; i < count; ++i)
+    if (!mats[i]) return fail(ctx, SDQ_EINVAL, "mats entry is NULL");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  ctx->err.clear();
+  HIP_TRY(grow(ctx->d_ptrs, (size_t)count * sizeof(double*)), "hipMalloc(pointer table)");
+  // stream-ordered after any earlier launch that read the table; the source
+  // is pageable, so it may be reused once this returns
+  HIP_TRY(hipMemcpyAsync(ctx->d_ptrs.p, mats, (size_t)count * sizeof(double*), hipMemcpyHostToDevice,
+                         ctx->stream),
+          "hipMemcpyAsync(pointer table)");
+  const int nt = nt_of(n);
+  const int grid = std::min(count, ctx->num_cu * 4);
+  return timed(ctx, "similarity", [&] {
+    return sdq::launch_similarity(nt, n, count, (double* const*)ctx->d_ptrs.p, left, right, grid,
+                                  ctx->stream);
+  });
 }
 
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,

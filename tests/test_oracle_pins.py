@@ -383,3 +383,69 @@ def test_oracle_rejects_bad_arguments():
     f[2, 1] = np.nan
     with pytest.raises(oracle.OracleError):
         oracle.greens(E, f, 0.1, 2)
+
+
+def _halves(L, dtau=0.1):
+    K = wl.hopping_matrix(L)
+    return wl.expk_pair(K, dtau / 2), wl.expk_pair(K, dtau)
+
+
+def test_symmetric_slices_naive_products():
+    """The symmetric Trotter slice of Sec. 2, B_l = H diag(v_l) H with
+    H = exp(-dtau K / 2), at beta = 1 where plain products and a plain inverse
+    are exact enough: G and G(tau_l,0) of the oracle's stabilized chain equal
+    (1 + prod B)^{-1} and B_l..B_1 G formed naively.  (V H H or H H V in
+    place of H V H changes the result: V is diagonal, not a multiple of 1.)"""
+    I = wl.hubbard_ising(4, 1.0, 1, 1, seed=wl.BASE_SEED + 974)[0]
+    (H, Hi), _ = _halves(4)
+    n = 16
+    prods = [np.eye(n)]
+    for l in range(I.m):
+        prods.append(H @ np.diag(np.exp(I.alpha * I.field[l])) @ H @ prods[-1])
+    Gn = np.linalg.inv(np.eye(n) + prods[-1])
+    G, ld, sg = oracle.greens_sym(H, I.field, I.alpha, I.k)
+    assert np.linalg.norm(G - Gn) <= 1e-12 * np.linalg.norm(Gn)
+    s2, l2 = np.linalg.slogdet(np.eye(n) + prods[-1])
+    assert abs(ld - l2) <= 1e-12 * abs(l2) and sg == s2
+    for l in (0, 3, 7, 10):
+        gt = oracle.greens_tdisp_sym(H, Hi, I.field, I.alpha, I.k, l)
+        ref = prods[l] @ Gn
+        assert np.linalg.norm(gt - ref) <= 1e-12 * np.linalg.norm(ref), l
+
+
+@pytest.mark.parametrize("beta", [10.0, 40.0])
+def test_symmetric_slices_similarity_relation(beta):
+    """At low temperature (no naive reference): the symmetric chain is
+    H^{-1} (E V_M ... E V_1) H, so its G and G(tau,0) are H^{-1} X H of the
+    oracle's results X for the slices E diag(v) (pinned against brute force
+    above), and log|det| and sign agree; both sides are stabilized chains of
+    their own slices."""
+    I = wl.hubbard_ising(4, beta, 1, 1, seed=wl.BASE_SEED + 974)[0]
+    (H, Hi), (E, Ei) = _halves(4)
+    Gs, lds, sgs = oracle.greens_sym(H, I.field, I.alpha, I.k)
+    Ga, lda, sga = oracle.greens(E, I.field, I.alpha, I.k)
+    assert np.linalg.norm(Hi @ Ga @ H - Gs) <= 1e-11 * np.linalg.norm(Gs)
+    assert abs(lds - lda) <= 1e-13 * abs(lda) and sgs == sga
+    for l in (0, 10, I.m // 2, I.m):
+        gs = oracle.greens_tdisp_sym(H, Hi, I.field, I.alpha, I.k, l)
+        ga = oracle.greens_tdisp(E, Ei, I.field, I.alpha, I.k, l)
+        assert np.linalg.norm(Hi @ ga @ H - gs) <= 1e-11 * np.linalg.norm(gs), l
+
+
+def test_symmetric_slices_same_gradient():
+    """d log|det(1+B_M..B_1)| / d f_{l,i} is the same for the symmetric and
+    the E diag(v) slices: central differences of the symmetric oracle's
+    log|det| against alpha (1 - G_l)_ii of the E diag(v) oracle."""
+    I = wl.hubbard_continuous(4, 2.0, 1, seed=wl.BASE_SEED + 975)[0]
+    (H, _), (E, _) = _halves(4)
+    rng = np.random.default_rng(wl.BASE_SEED + 976)
+    ls = sorted(set(int(x) for x in rng.integers(1, I.m + 1, 6)))
+    grad = oracle.logdet_grad(E, I.field, I.alpha, I.k, ls)
+    h = 1e-5
+    for a, l in enumerate(ls):
+        i = int(rng.integers(0, 16))
+        fp, fm = I.field.copy(), I.field.copy()
+        fp[l - 1, i] += h
+        fm[l - 1, i] -= h
+        d = (oracle.greens_sym(H, fp, I.alpha, I.k)[1] - oracle.greens_sym(H, fm, I.alpha, I.k)[1]) / (2 * h)
+        assert abs(d - grad[a, i]) <= 1e-7 * max(1.0, abs(grad[a, i])), (l, i, d, grad[a, i])
