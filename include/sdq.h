@@ -157,6 +157,31 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
                          double* d, double* t);
 
+/* One Metropolis step with global proposals for `count` chains of `nf`
+ * flavours each (Sec. 2: the weight of a field configuration is
+ * exp(-S_B) prod_f |det(1 + B_f)|, and the step accepts with probability
+ * min(1, exp(-dS) prod_f |det(1 + B'_f)| / |det(1 + B_f)|)).
+ *   cur, prop  host arrays [count * nf]; flavour f of chain c at c * nf + f.
+ *              cur[i].field is the current field (device, m x n, overwritten
+ *              by prop[i].field when the chain accepts; flavours may share a
+ *              field, which is then copied once); prop[i] is the proposal
+ *              (same n and m, its own field array).  Only prop is evaluated.
+ *   dS      device [count]: S_B(proposed) - S_B(current) (0 for the
+ *           discrete Hirsch field of Sec. 3, whose bosonic weight is constant)
+ *   u       device [count]: uniform numbers in (0, 1); the step accepts when
+ *           log u < -dS + sum_f (log|det(1+B'_f)| - log|det(1+B_f)|)
+ *   logdet, sign  device [count * nf]: log|det(1 + B_f)| and its sign for the
+ *           current fields on entry (e.g. from sdq_logdet); replaced by the
+ *           proposal's where the chain accepts
+ *   accept  device [count]: 1 accepted, 0 rejected
+ *   status  device [count * nf] or NULL: status of each proposal's
+ *           evaluation; a chain with a nonzero one rejects
+ * The sign is not part of the acceptance (|weight| is sampled; the sign is
+ * returned for reweighting). */
+sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_instance* prop,
+                          int32_t count, int32_t nf, const double* dS, const double* u, double* logdet,
+                          double* sign, int32_t* accept, int32_t* status);
+
 /* M <- left * M * right for `count` n x n row-major device matrices: mats is
  * a host array [count] of device pointers (updated in place; the entries
  * must not overlap), left and right are device n x n matrices shared by the

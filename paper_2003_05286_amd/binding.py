@@ -27,7 +27,7 @@ SCHEME_LOH, SCHEME_PLAIN = 0, 1
 EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_greens",
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
-           "sdq_kernel_stats", "sdq_sync", "sdq_similarity")
+           "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis")
 
 
 class SdqError(RuntimeError):
@@ -76,6 +76,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_kernel_stats.argtypes = [vp, ctypes.c_char_p, P(i64), P(dbl)]
     L.sdq_sync.argtypes = [vp]
     L.sdq_similarity.argtypes = [vp, i32, i32, vp, vp, P(vp)]
+    L.sdq_metropolis.argtypes = [vp, P(_Instance), P(_Instance), i32, i32, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -237,6 +238,26 @@ class Context:
         u, t, d = self._empty(cnt, n, n), self._empty(cnt, n, n), self._empty(cnt, n)
         self._chk(self.lib.sdq_chain_udt(self.h, inst, cnt, _ptr(u), _ptr(d), _ptr(t)))
         return u, d, t
+
+    def metropolis(self, cur, prop, nf, dS, u, logdet, sign):
+        """One global-update Metropolis step (sdq_metropolis).  cur / prop:
+        lists of Chain, count * nf entries, flavour f of chain c at c * nf + f;
+        dS, u: device [count]; logdet, sign: device [count * nf], the current
+        fields' values, updated in place.  Returns (accept [count] int32,
+        status [count * nf] int32)."""
+        total = len(cur)
+        if len(prop) != total or nf < 1 or total % nf:
+            raise ValueError("cur and prop need count * nf entries each")
+        count = total // nf
+        for t, name, shape in ((dS, "dS", (count,)), (u, "u", (count,)), (logdet, "logdet", (total,)),
+                               (sign, "sign", (total,))):
+            _check_tensor(t, name, shape, self.tdev)
+        ci, pi = self._instances(cur), self._instances(prop)
+        acc = torch.empty(count, dtype=torch.int32, device=self.tdev)
+        st = torch.empty(total, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_metropolis(self.h, ci, pi, count, nf, _ptr(dS), _ptr(u), _ptr(logdet),
+                                          _ptr(sign), _ptr(acc), _ptr(st)))
+        return acc, st
 
     def similarity(self, mats, left, right):
         """M <- left @ M @ right in place for every n x n matrix of `mats` (a

@@ -95,6 +95,56 @@ hipError_t launch_swizzle(const double* e, int n, int trans, double* out, hipStr
   return hipGetLastError();
 }
 
+// Metropolis acceptance of a global proposal (Sec. 2): the weight of a field
+// is exp(-S_B) prod_f |det(1 + B_f)|, so the step accepts when
+//   log u < -dS + sum_f (log|det(1+B'_f)| - log|det(1+B_f)|),
+// with u uniform in (0, 1); a proposal whose evaluation failed (nonzero
+// status) is rejected.  On acceptance the proposed fields are copied over the
+// current ones (a field shared by several flavours of the chain is copied
+// once) and the chain's log|det| and signs replaced.
+__global__ void k_metropolis(int count, int nf, const MetroField* __restrict__ fields,
+                             const double* __restrict__ ld_prop, const double* __restrict__ sg_prop,
+                             const int32_t* __restrict__ st_prop, const double* __restrict__ dS,
+                             const double* __restrict__ u, double* logdet, double* sign,
+                             int32_t* accept) {
+  __shared__ int acc;
+  const int c = blockIdx.x;
+  if (c >= count) return;
+  if (threadIdx.x == 0) {
+    double delta = -dS[c];
+    bool ok = true;
+    for (int f = 0; f < nf; ++f) {
+      const int i = c * nf + f;
+      delta += ld_prop[i] - logdet[i];
+      ok = ok && st_prop[i] == 0 && isfinite(ld_prop[i]);
+    }
+    acc = (ok && log(u[c]) < delta) ? 1 : 0;
+    accept[c] = acc;
+  }
+  __syncthreads();
+  if (!acc) return;
+  for (int f = 0; f < nf; ++f) {
+    const MetroField F = fields[c * nf + f];
+    bool seen = false;
+    for (int g = 0; g < f; ++g) seen = seen || fields[c * nf + g].cur == F.cur;
+    if (seen) continue;
+    for (int64_t t = threadIdx.x; t < F.len; t += blockDim.x) F.cur[t] = F.prop[t];
+  }
+  if (threadIdx.x < nf) {
+    const int i = c * nf + threadIdx.x;
+    logdet[i] = ld_prop[i];
+    sign[i] = sg_prop[i];
+  }
+}
+hipError_t launch_metropolis(int count, int nf, const MetroField* fields, const double* ld_prop,
+                             const double* sg_prop, const int32_t* st_prop, const double* dS,
+                             const double* u, double* logdet, double* sign, int32_t* accept,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_metropolis, dim3(count), dim3(256), 0, s, count, nf, fields, ld_prop, sg_prop,
+                     st_prop, dS, u, logdet, sign, accept);
+  return hipGetLastError();
+}
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset, dim3((nq + 63) / 64), dim3(64), 0, s, q, nq);

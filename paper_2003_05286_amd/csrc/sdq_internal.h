@@ -95,6 +95,19 @@ struct KernelInfo {
 
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out);
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s);
+// One flavour of a chain in a Metropolis step: its current field (updated on
+// acceptance) and the proposed one, m * n doubles each.
+struct MetroField {
+  double* cur;
+  const double* prop;
+  int64_t len;
+};
+// Global-update Metropolis decisions for `count` chains of nf flavours each
+// (see sdq_metropolis); one workgroup per chain.
+hipError_t launch_metropolis(int count, int nf, const MetroField* fields, const double* ld_prop,
+                             const double* sg_prop, const int32_t* st_prop, const double* dS,
+                             const double* u, double* logdet, double* sign, int32_t* accept,
+                             hipStream_t s);
 // Copy the n x n row-major matrix e (or its transpose) into the MFMA
 // A-operand order used by the kernels: for NT = ceil(n/16), block
 // b = (ti*NT + tk)*4 + r holds at position l the entry

@@ -75,6 +75,7 @@ struct sdq_ctx {
   DevBuf d_upload, d_ck, d_swz, d_fin;
   DevBuf d_gang;  // per-gang scratch of the n > 128 kernels (bars first)
   DevBuf d_ptrs;  // matrix pointer table of sdq_similarity
+  DevBuf d_metro;  // sdq_metropolis: field table, proposed log|det|, signs and status
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   void* h_stage = nullptr;
   size_t h_cap = 0;
@@ -651,6 +652,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_fin.p) (void)hipFree(ctx->d_fin.p);
   if (ctx->d_gang.p) (void)hipFree(ctx->d_gang.p);
   if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
+  if (ctx->d_metro.p) (void)hipFree(ctx->d_metro.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
@@ -933,6 +935,51 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
     });
   }
   return timed(ctx, "udt", [&] { return sdq::launch_udt(nt, n, count, w, u, d, t, ctx->stream); });
+}
+
+sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_instance* prop,
+                          int32_t count, int32_t nf, const double* dS, const double* u, double* logdet,
+                          double* sign, int32_t* accept, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
+  if (count == 0) return SDQ_OK;
+  if (!cur || !prop || !dS || !u || !logdet || !sign || !accept)
+    return fail(ctx, SDQ_EINVAL, "null pointer");
+  const int total = count * nf;
+  sdq_status st = validate(ctx, prop, total, false);
+  if (st) return st;
+  for (int i = 0; i < total; ++i) {
+    if (!cur[i].field || cur[i].n != prop[i].n || cur[i].m != prop[i].m)
+      return fail(ctx, SDQ_EINVAL, "cur and prop differ in n or m (or cur field is NULL)");
+    if (cur[i].field == prop[i].field) return fail(ctx, SDQ_EINVAL, "cur and prop share a field");
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  // device layout: fields [total] | ld_prop [total] | sg_prop [total] | st_prop [total]
+  const size_t o_ld = ((size_t)total * sizeof(sdq::MetroField) + 255) & ~(size_t)255;
+  const size_t o_sg = o_ld + (((size_t)total * sizeof(double) + 255) & ~(size_t)255);
+  const size_t o_st = o_sg + (((size_t)total * sizeof(double) + 255) & ~(size_t)255);
+  const size_t bytes = o_st + (size_t)total * sizeof(int32_t);
+  HIP_TRY(grow(ctx->d_metro, bytes), "hipMalloc(metropolis)");
+  char* base = (char*)ctx->d_metro.p;
+  std::vector<sdq::MetroField> tab(total);
+  for (int i = 0; i < total; ++i)
+    tab[i] = sdq::MetroField{const_cast<double*>(cur[i].field), prop[i].field,
+                             (int64_t)prop[i].m * prop[i].n};
+  // the proposed log|det| and signs (the stabilized sweep and the equal-time
+  // inversion of every proposed instance), then the decisions
+  double* ld_p = (double*)(base + o_ld);
+  double* sg_p = (double*)(base + o_sg);
+  int32_t* st_p = status ? status : (int32_t*)(base + o_st);
+  st = sdq_logdet(ctx, prop, total, ld_p, sg_p, st_p, nullptr);
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(base, tab.data(), (size_t)total * sizeof(sdq::MetroField), hipMemcpyHostToDevice,
+                         ctx->stream),
+          "hipMemcpyAsync(field table)");
+  ctx->err.clear();
+  return timed(ctx, "metropolis", [&] {
+    return sdq::launch_metropolis(count, nf, (const sdq::MetroField*)base, ld_p, sg_p, st_p, dS, u,
+                                  logdet, sign, accept, ctx->stream);
+  });
 }
 
 sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,
