@@ -67,6 +67,7 @@ def main():
                     help="time the batched step only (no equal-time / per-chain extras); for profiler runs")
     ap.add_argument("--workload", default="hubbard_L8_b40_batch512",
                     choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
+                             "hubbard_L8_b40_metropolis256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L16_b40_batch128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
@@ -104,7 +105,8 @@ def main():
     insts = W.instances
     l_list = W.l_list or []
     kind = {"hubbard_L8_b40_batch512": "tdisp", "hubbard_L16_b40_batch128": "tdisp",
-            "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad"}[args.workload]
+            "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad",
+            "hubbard_L8_b40_metropolis256": "metropolis"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
     plain = args.scheme == "plain"
@@ -141,8 +143,38 @@ def main():
     gr_ptrs = ctx._ptr_array(grads) if grads else None
     vp = lambda t: ctypes.c_void_p(t.data_ptr())
 
+    if kind == "metropolis":
+        # both flavours of a chain share its field: current fields in one
+        # tensor, proposals (the spins of one random time slice flipped) in
+        # another, dS = 0 for the Hirsch field
+        assert all(insts[2 * c].field is insts[2 * c + 1].field for c in range(cnt // 2))
+        C = cnt // 2
+        Fc = torch.from_numpy(np.stack([insts[2 * c].field for c in range(C)])).to(dev)
+        Fp = torch.empty_like(Fc)
+        cur_ch, prop_ch = [], []
+        for c in range(C):
+            for I in (insts[2 * c], insts[2 * c + 1]):
+                cur_ch.append(sdq.Chain(dev_of(I.expk), Fc[c], I.alpha, I.k, dev_of(I.expk_inv)))
+                prop_ch.append(sdq.Chain(dev_of(I.expk), Fp[c], I.alpha, I.k, dev_of(I.expk_inv)))
+        ci, pi = ctx._instances(cur_ch), ctx._instances(prop_ch)
+        ld_m, sg_m, _, _ = ctx.logdet(cur_ch)
+        dS = torch.zeros(C, dtype=torch.float64, device=dev)
+        acc = torch.zeros(C, dtype=torch.int32, device=dev)
+        idx = torch.arange(C, device=dev)
+        mgen = torch.Generator(device=dev)
+        mgen.manual_seed(wl.BASE_SEED + 2000)
+        acc_sum = torch.zeros(C, dtype=torch.int64, device=dev)
+
     def step():
-        if kind == "tdisp":
+        if kind == "metropolis":
+            Fp.copy_(Fc)
+            rows = torch.randint(0, m, (C,), device=dev, generator=mgen)
+            Fp[idx, rows] *= -1.0
+            u = torch.rand(C, device=dev, dtype=torch.float64, generator=mgen).clamp_min_(1e-300)
+            ctx._chk(ctx.lib.sdq_metropolis(ctx.h, ci, pi, C, 2, vp(dS), vp(u), vp(ld_m), vp(sg_m), vp(acc),
+                                            vp(st)))
+            acc_sum.add_(acc)
+        elif kind == "tdisp":
             ctx._chk(ctx.lib.sdq_greens_tdisp(ctx.h, inst_arr, cnt, scheme, ls, len(l_list),
                                               gt_ptrs, g_ptrs, vp(ld), vp(sg), vp(st)))
         elif kind == "greens":
@@ -175,7 +207,7 @@ def main():
     status_ok = int((st != 0).sum().item()) == 0
     n_bad = int((st != 0).sum().item())
 
-    sweeps_per_chain = 1 if kind == "greens" else 2
+    sweeps_per_chain = 1 if kind in ("greens", "metropolis") else 2
     f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
     if plain:
         f_sweep = sum(plain_sweep_flops(I.n, I.m, I.k, l_list) for I in insts)
@@ -230,13 +262,17 @@ def main():
     elif kind == "greens":
         metric = f"equal-time Green's functions/sec (FP64, {W.name})"
         unit = "chains/s (each: G, log|det|, sign)"
+    elif kind == "metropolis":
+        metric = "global Metropolis updates/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
+        unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
+                "field, one time slice flipped, and the accept step)")
     else:
         metric = f"log|det| + adjoint gradients/sec (FP64, {W.name})"
         unit = "chains/s (each: log|det| and its gradient over all M x N field entries)"
     betas = sorted({round(I.m * I.dtau, 6) for I in insts})
     out = {
         "metric": metric,
-        "value": cnt / (ms_step * 1e-3),
+        "value": (cnt // 2 if kind == "metropolis" else cnt) / (ms_step * 1e-3),
         "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
@@ -260,15 +296,20 @@ def main():
                         "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
         "equal_kernel": {"launch_ms": ms_eq / max(n_eq, 1)},
         "step_tflops": total_flops / (ms_step * 1e-3) / 1e12,
-        "green_matrices_per_s": (cnt * (1 + len(l_list)) / (ms_step * 1e-3)) if kind != "grad" else None,
+        "green_matrices_per_s": (cnt * (1 + len(l_list)) / (ms_step * 1e-3))
+        if kind in ("tdisp", "greens") else None,
         "equal_time_only_per_s": eq_rate,
         "per_instance_loop_per_s": per_inst_rate,
         "status_ok": status_ok,
     }
+    if kind == "metropolis":
+        out["acceptance"] = float(acc_sum.sum().item()) / (C * (args.warmup + args.steps))
     if scheme_check is not None:
         scheme_check["chains_flagged_nonfinite"] = n_bad
         out["scheme_check"] = scheme_check
 
+    if not args.no_cpu and kind == "metropolis":
+        out["cpu_baseline"] = cpu_baseline_metropolis(insts, args.cpu_sample)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -331,6 +372,30 @@ def measured_traffic():
         return None
     m = re.search(r"bench traffic line: sweep ([0-9.eE+-]+)", text)
     return float(m.group(1)) if m else None
+
+
+def cpu_baseline_metropolis(insts, nchains):
+    """The oracle on the same step for a bounded sample: `nchains` chains,
+    each: log|det(1+B)| of both flavours of a field with one time slice
+    flipped (the decision itself is negligible), one oracle call per thread."""
+    import numpy as np
+    import oracle
+
+    rng = np.random.default_rng(1)
+    jobs = []
+    for c in range(min(nchains, len(insts) // 2)):
+        f = insts[2 * c].field.copy()
+        f[rng.integers(0, f.shape[0])] *= -1.0
+        for I in (insts[2 * c], insts[2 * c + 1]):
+            jobs.append((I, f))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda j: oracle.greens(j[0].expk, j[1], j[0].alpha, j[0].k), jobs))
+    dt = time.perf_counter() - t0
+    return {"value": (len(jobs) // 2) / dt, "unit": "chain updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(jobs) // 2} chains x 2 flavours of the batch, one oracle log|det| per "
+                      f"flavour of a proposed field; {dt:.1f} s wall"}
 
 
 def cpu_baseline(insts, l_list, nchains):
