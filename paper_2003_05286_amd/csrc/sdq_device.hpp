@@ -74,12 +74,12 @@ struct Smem {
   double tau[G::NP];
   double dnew[G::NP];                        // |diag R| of the last QR
   double dcur[G::NP];                        // D of the current factorization
-  double ckey[2][4];
-  double red[2][8];
-  int ccol[2][4];
+  double ckey[2][G::P];
+  double red[2][G::P];
+  int ccol[2][G::P];
   int perm[G::NP];                           // perm[j] = column pivoted at step j
   int sinv[G::NP];                           // sinv[c] = step at which c was pivoted
-  int ired[8];
+  int ired[2 * G::P];
   int item;
 };
 
@@ -887,7 +887,7 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, c
   }
   if (L.l == 0) {
     S.red[0][L.w] = lsum;
-    S.ired[4 + L.w] = neg;
+    S.ired[G::P + L.w] = neg;
   }
   const double sq = refl_sign<NT, P, ELDS>(L, n, S);
   const double sp = perm_sign<NT, P, ELDS>(L, n, S);  // its barrier makes S.red visible
@@ -895,7 +895,7 @@ __device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, c
   int ng = 0;
   for (int q = 0; q < G::P; ++q) {
     ld += S.red[0][q];
-    ng += S.ired[4 + q];
+    ng += S.ired[G::P + q];
   }
   *logdet = ld;
   *sign = sgn_u * sq * sp * ((ng & 1) ? -1.0 : 1.0);
