@@ -157,6 +157,26 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
                          double* d, double* t);
 
+/* One sweep of local updates over the field of `count` chains of `nf`
+ * flavours each (nf = 1 or 2; the flavours of a chain are consecutive in
+ * inst and share its field, n, m and k; e.g. spin up and down of the Hubbard
+ * model with alpha = +lambda, -lambda).  Sites are visited slice by slice,
+ * l = 1..m, and within a slice i = 0..n-1; flipping f_{l,i} -> -f_{l,i}
+ * changes det(1 + B_m...B_1) of flavour f by the ratio
+ * R_f = 1 + (exp(-2 alpha_f f_{l,i}) - 1) (1 - G_l)_{ii} (Sec. 2: local updates
+ * need only this ratio), and the flip is accepted when
+ * u[c][l-1][i] < |prod_f R_f|.  G_l is kept current by rank-one updates after
+ * every accepted flip and G_{l+1} = B_l G_l B_l^{-1} between slices, and is
+ * recomputed from stabilized factorizations (the forward one rebuilt from the
+ * updated field, Sec. 4.1 / App. A.1) at the start of every block of k
+ * slices.
+ *   unif      device [count][m][n] uniform numbers in [0, 1)
+ *   accepted  device [count]: number of accepted flips of each chain
+ *   status    device [count * nf] or NULL
+ * The field arrays are updated in place.  Requires expk_inv; n <= 128. */
+sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf,
+                           const double* unif, int32_t* accepted, int32_t* status);
+
 /* One Metropolis step with global proposals for `count` chains of `nf`
  * flavours each (Sec. 2: the weight of a field configuration is
  * exp(-S_B) prod_f |det(1 + B_f)|, and the step accepts with probability

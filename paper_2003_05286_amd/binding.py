@@ -27,7 +27,8 @@ SCHEME_LOH, SCHEME_PLAIN = 0, 1
 EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_greens",
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
-           "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis")
+           "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
+           "sdq_local_sweep")
 
 
 class SdqError(RuntimeError):
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_sync.argtypes = [vp]
     L.sdq_similarity.argtypes = [vp, i32, i32, vp, vp, P(vp)]
     L.sdq_metropolis.argtypes = [vp, P(_Instance), P(_Instance), i32, i32, vp, vp, vp, vp, vp, vp]
+    L.sdq_local_sweep.argtypes = [vp, P(_Instance), i32, i32, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -257,6 +259,23 @@ class Context:
         st = torch.empty(total, dtype=torch.int32, device=self.tdev)
         self._chk(self.lib.sdq_metropolis(self.h, ci, pi, count, nf, _ptr(dS), _ptr(u), _ptr(logdet),
                                           _ptr(sign), _ptr(acc), _ptr(st)))
+        return acc, st
+
+    def local_sweep(self, chains, nf, unif):
+        """One sweep of local updates (sdq_local_sweep): chains = count * nf
+        Chains (flavours of a chain consecutive, sharing its field tensor,
+        which is updated in place); unif: device [count, m, n].  Returns
+        (accepted [count] int32, status [count * nf] int32)."""
+        total = len(chains)
+        if nf < 1 or total % nf:
+            raise ValueError("chains must hold count * nf entries")
+        count = total // nf
+        c0 = chains[0]
+        _check_tensor(unif, "unif", (count, c0.m, c0.n), self.tdev)
+        inst = self._instances(chains, need_inv=True)
+        acc = torch.empty(count, dtype=torch.int32, device=self.tdev)
+        st = torch.empty(total, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_local_sweep(self.h, inst, count, nf, _ptr(unif), _ptr(acc), _ptr(st)))
         return acc, st
 
     def similarity(self, mats, left, right):

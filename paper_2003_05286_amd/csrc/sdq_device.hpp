@@ -1005,20 +1005,33 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const bool left = (flags & SW_LEFT) != 0, right = (flags & SW_RIGHT) != 0;
+  const bool block = (flags & SW_BLOCK) != 0;
   const bool adj = (flags & SW_ADJ) != 0;
   const int64_t sd = stage_doubles(n);
   const int tauj = jpair * k < m ? jpair * k : m;
-  const int s_lo = right ? jpair : 0;
-  const int s_hi = left ? (tauj + k - 1) / k : nb;
+  const int s_lo = (right || block) ? jpair : 0;
+  const int s_hi = left ? (tauj + k - 1) / k : (block ? jpair + 1 : nb);
   const double* e_op = left ? I.eswi : (adj ? I.eswt : I.esw);
   stage_e<NT, P, ELDS>(L, S, e_op);
   // W holds U between blocks and the block product inside a block
   RM<NT, P> T, W;
-  set_identity<NT, P>(L, W);
-  set_identity<NT, P>(L, T);
   double dcol[CT];
+  if (block && jpair > 0) {
+    // continue from forward stage jpair: W = U, T, column scales D
+    const double* F0 = I.ckf + (size_t)(jpair - 1) * sd;
+    load_rm<NT, P>(L, W, F0, n, false);
+    load_rm<NT, P>(L, T, F0 + (size_t)n * n, n, false);
 #pragma unroll
-  for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
+    for (int c = 0; c < CT; ++c) {
+      const int col = col_of<NT, P>(L, c);
+      dcol[c] = col < n ? gmem(F0)[2 * (size_t)n * n + col] : 1.0;
+    }
+  } else {
+    set_identity<NT, P>(L, W);
+    set_identity<NT, P>(L, T);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
+  }
   const EOp<NT, P, ELDS> eop{S.E, e_op, L.l};
 
   for (int s = s_lo; s < s_hi; ++s) {
@@ -1062,6 +1075,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
     else if (left && s == s_hi - 1) dst = I.ckf + (size_t)(jpair - 1) * sd;
     else if (right && s == nb - 1) dst = I.cka + (size_t)jpair * sd;
+    else if (block) dst = I.ckf + (size_t)jpair * sd;
     if (dst) store_stage<NT, P, ELDS>(L, n, S, W, T, sgn_u, dst);
     __syncthreads();
   }
@@ -1426,17 +1440,15 @@ __device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst
   tdisp_outputs<NT, P, ELDS>(L, S, I, j, ilo, ihi, l_list, Gm);
 }
 
-// Gradient rows for slices l = j*k+1 .. min((j+1)k, m):
-//   G_{jk+1} = [1 + B(tau_j,0) B(beta,tau_j)]^{-1}
-//            = [1 + U1 (D1 (T1 T2^T) D2) U2^T]^{-1}                  (App. A.1)
-// with udt(D1 (T1 T2^T) D2) = u d t, U = U1 u, T = t U2^T and Loh's
-// equal-time inversion; then G_{l+1} = B_l G_l B_l^{-1} and
-//   grad[l-1][i] = alpha (1 - G_l)_ii.
+// G_{jk+1} = [1 + B(tau_j,0) B(beta,tau_j)]^{-1} from forward stage j and
+// backward stage j (App. A.1): udt(D1 (T1 T2^T) D2) = u d t, U = U1 u,
+// T = t U2^T, then Loh's equal-time inversion; written to S.R row-major
+// ([row][col], padding as identity), ends with a barrier.
 template <int NT, int P, bool ELDS>
-__device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+__device__ void block_start_g(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
-  const int n = I.n, m = I.m, k = I.k, nb = I.nb;
+  const int n = I.n, nb = I.nb;
   const int64_t sd = stage_doubles(n);
   const double* F = j > 0 ? I.ckf + (size_t)(j - 1) * sd : nullptr;
   const double* A = j < nb ? I.cka + (size_t)j * sd : nullptr;
@@ -1534,6 +1546,17 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       }
   }
   __syncthreads();
+}
+
+// Gradient rows for slices l = j*k+1 .. min((j+1)k, m): G_{jk+1} from the
+// stage pair (block_start_g), then G_{l+1} = B_l G_l B_l^{-1} and
+//   grad[l-1][i] = alpha (1 - G_l)_ii.
+template <int NT, int P, bool ELDS>
+__device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  const int n = I.n, m = I.m, k = I.k;
+  block_start_g<NT, P, ELDS>(L, S, I, j);
   const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
   bool bad = false;
   for (int t = L.t; t < n; t += G::THREADS) {
@@ -1591,6 +1614,176 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Local updates (the determinant ratios of single flips, Sec. 2): block j of
+// a sweep over the slices l = jk+1 .. min((j+1)k, m) and, in each, the sites
+// i = 0 .. n-1 in order.  Flipping f_{l,i} -> -f_{l,i} multiplies B_l by
+// 1 + Delta e_i e_i^T, Delta = exp(-2 alpha f_{l,i}) - 1, and det(1 + ...)
+// of the chain whose rightmost factor is B_l by R = 1 + Delta (1 - G_l)_ii;
+// the flip is accepted when u_{l,i} < |prod_flavours R| (the flavours share
+// the field) and then every flavour's G_l becomes
+//   G - (e_i - G e_i) (Delta / R) (e_i^T G)        (Sherman-Morrison),
+// the field entry is negated, and after the last site of slice l
+// G_{l+1} = B_l G_l B_l^{-1} with the updated B_l.  G_{jk+1} comes from the
+// stage pair (block_start_g): forward stages rebuilt from the updated field
+// (SW_BLOCK), backward stages of the slices after the block (untouched so
+// far in the sweep).  Both flavours' G stay in registers; the owner of
+// column i publishes that column of each through LDS, one barrier per site,
+// and every wave takes the same decision from the same values.
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void rm_from_lds_rows(const Lane& L, const Smem<NT, P, ELDS>& S, RM<NT, P>& A) {
+  using G = Geo<NT, P>;
+#pragma unroll
+  for (int c = 0; c < G::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        A.v[c][ti][r] = tile_ok<NT, P>(L, c) ? S.R[row * G::LDR + col] : (row == col ? 1.0 : 0.0);
+      }
+  }
+}
+
+// G <- E diag(v_l) G diag(1/v_l) E^{-1} (v_l of the current field row)
+template <int NT, int P, bool ELDS>
+__device__ void wrap_g(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int l, RM<NT, P>& Gx) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  const int n = I.n;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.R[row_of(L, ti, r) * G::LDR + col] = Gx.v[c][ti][r];
+  }
+  __syncthreads();
+  const double* fl = I.field + (size_t)(l - 1) * n;
+  RM<NT, P> Bi, Yr;
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        double x = 0.0;
+        if (row < n && col < n && tile_ok<NT, P>(L, c))
+          x = gmem(I.expk_inv)[row * n + col] * exp(-I.alpha * gmem(fl)[row]);
+        Bi.v[c][ti][r] = x;
+      }
+  }
+  gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      const double v = row < n ? exp(I.alpha * gmem(fl)[row]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
+    }
+  gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gx);
+}
+
+// G <- G - (e_i - G e_i) coef (e_i^T G); col = column i of G before the update
+template <int NT, int P>
+__device__ __forceinline__ void flip_update(const Lane& L, RM<NT, P>& Gx, const double* col, int i, double coef) {
+  constexpr int CT = Geo<NT, P>::CT;
+  double y[CT];
+#pragma unroll
+  for (int c = 0; c < CT; ++c) y[c] = row_value<NT, P>(L, Gx, c, i) * coef;  // G[i][b] coef
+  double x[NT][4];
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row_of(L, ti, r);
+      x[ti][r] = (row == i ? 1.0 : 0.0) - col[row];
+    }
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gx.v[c][ti][r] = fma(-x[ti][r], y[c], Gx.v[c][ti][r]);
+}
+
+template <int NT, int P, bool ELDS>
+__device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, const Inst& I1, const int nf,
+                           const int j) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  const int n = I0.n, m = I0.m, k = I0.k;
+  const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
+  RM<NT, P> Ga, Gb;
+  block_start_g<NT, P, ELDS>(L, S, I0, j);
+  rm_from_lds_rows<NT, P, ELDS>(L, S, Ga);
+  __syncthreads();
+  if (nf > 1) {
+    block_start_g<NT, P, ELDS>(L, S, I1, j);
+    rm_from_lds_rows<NT, P, ELDS>(L, S, Gb);
+    __syncthreads();
+  } else {
+    set_identity<NT, P>(L, Gb);
+  }
+  double* fld = const_cast<double*>(I0.field);
+  double* ca = S.cand[0][0];
+  double* cb = S.cand[1][0];
+  int nacc = 0;
+  bool bad = false;
+  for (int l = l0; l <= l1; ++l) {
+    for (int i = 0; i < n; ++i) {
+      // the lanes holding column i publish it (both flavours)
+      const int ct = i >> 4;
+      if (L.w == ct % P && L.cl == (i & 15)) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          if (c == ct / P) {
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                ca[row_of(L, ti, r)] = Ga.v[c][ti][r];
+                cb[row_of(L, ti, r)] = Gb.v[c][ti][r];
+              }
+          }
+      }
+      __syncthreads();
+      const size_t e = (size_t)(l - 1) * n + i;
+      const double s = gmem(fld)[e];
+      const double da = exp(-2.0 * I0.alpha * s) - 1.0;
+      const double ra = 1.0 + da * (1.0 - ca[i]);
+      double rb = 1.0, db = 0.0;
+      if (nf > 1) {
+        db = exp(-2.0 * I1.alpha * s) - 1.0;
+        rb = 1.0 + db * (1.0 - cb[i]);
+      }
+      bad = bad || !isfinite(ra) || !isfinite(rb);
+      if (gmem(I0.unif)[e] < fabs(ra * rb)) {
+        flip_update<NT, P>(L, Ga, ca, i, da / ra);
+        if (nf > 1) flip_update<NT, P>(L, Gb, cb, i, db / rb);
+        if (L.t == 0) gmem(fld)[e] = -s;
+        ++nacc;
+      }
+      __syncthreads();  // the column buffers and the field entry are reused
+    }
+    if (l < l1) {
+      wrap_g<NT, P, ELDS>(L, S, I0, l, Ga);
+      if (nf > 1) wrap_g<NT, P, ELDS>(L, S, I1, l, Gb);
+    }
+  }
+  if (L.t == 0 && I0.nacc) atomicAdd(I0.nacc, nacc);
+  if (bad && L.t == 0 && I0.status) atomicOr(I0.status, kStatusRange);
+  __syncthreads();
+}
+
 template <int NT, int P, bool ELDS, int MODE>
 __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     const Inst* __restrict__ insts, const PairItem* __restrict__ items, int count,
@@ -1605,6 +1798,11 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     if (it >= count) break;
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
+    if constexpr (MODE == PAIR_LOCAL) {
+      const Inst I1 = wi.ilo > 1 ? insts[wi.inst + 1] : I;
+      pair_local<NT, P, ELDS>(L, S, I, I1, wi.ilo, wi.j);
+      continue;
+    }
     if constexpr (MODE == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
     else if constexpr (MODE == PAIR_TDISP_PLAIN)
       pair_tdisp_plain<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
@@ -1705,6 +1903,8 @@ struct Launch {
     else if (mode == PAIR_TDISP_PLAIN)
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_TDISP_PLAIN>), dim3(grid), b, 0, s, inst, items, count,
                          l_list, q);
+    else if (mode == PAIR_LOCAL)
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_LOCAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     else
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_EQUAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     return hipGetLastError();

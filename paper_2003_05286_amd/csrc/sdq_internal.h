@@ -43,6 +43,8 @@ struct Inst {
   const double* eswt;      // expk^T, same layout (see launch_swizzle)
   double* fin;             // final forward stage (read by the equal-time inversion)
   const double* eswi;      // expk_inv in the layout of esw, or null
+  const double* unif;      // local updates: uniform numbers [m][n] of the chain
+  int32_t* nacc;           // local updates: accepted flips of the chain
 };
 
 enum SweepFlags : int32_t {
@@ -54,6 +56,10 @@ enum SweepFlags : int32_t {
   // started at tau_j = min(jk, m) and stabilized every k slices from there:
   SW_LEFT = 16,   // B_1^{-1} ... B_{tau_j}^{-1}, stored at ckf[j-1]   (j >= 1)
   SW_RIGHT = 32,  // B_m ... B_{tau_j+1},         stored at cka[j]     (j < nb)
+  // block j of the forward chain from forward stage j (ckf[j-1], identity
+  // for j = 0), stored at ckf[j]: rebuilds the stages as a local-update
+  // sweep changes the field
+  SW_BLOCK = 64,
 };
 
 struct SweepItem {
@@ -63,12 +69,15 @@ struct SweepItem {
   int32_t pad;
 };
 
-enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2, PAIR_TDISP_PLAIN = 3 };
-constexpr int kPairModes = 4;
+enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2, PAIR_TDISP_PLAIN = 3,
+                          PAIR_LOCAL = 4 };
+constexpr int kPairModes = 5;
 
 // tdisp: stage pair j, outputs for l_list[ilo..ihi) (PAIR_TDISP_PLAIN: the
 //        same from the SW_LEFT / SW_RIGHT chains)
 // grad:  stage pair j (slices j*k+1 .. min((j+1)k, m))
+// local: block j of a local-update sweep; inst = the chain's first flavour,
+//        ilo = number of flavours (1 or 2, consecutive instances)
 // equal: the final forward stage -> G, logdet, sign
 struct PairItem {
   int32_t inst;

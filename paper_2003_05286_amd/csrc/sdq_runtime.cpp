@@ -388,7 +388,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
   }
   const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_TDISP_PLAIN,
-                                      sdq::PAIR_GRAD};
+                                      sdq::PAIR_GRAD, sdq::PAIR_LOCAL};
   for (int oi = 0; oi < sdq::kPairModes; ++oi) {
     const int md = order[oi];
     for (const auto& r : P.pair_ranges[md]) {
@@ -444,7 +444,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   }
   const Inst* d_inst = (const Inst*)(d + B.o_inst);
   const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
-  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair"};
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local"};
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
     auto go = [&]() -> hipError_t {
@@ -935,6 +935,87 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
     });
   }
   return timed(ctx, "udt", [&] { return sdq::launch_udt(nt, n, count, w, u, d, t, ctx->stream); });
+}
+
+sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf,
+                           const double* unif, int32_t* accepted, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0 || nf < 1 || nf > 2) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf in {1, 2}");
+  if (count == 0) return SDQ_OK;
+  if (!unif || !accepted) return fail(ctx, SDQ_EINVAL, "null pointer");
+  const int total = count * nf;
+  sdq_status st = validate(ctx, inst, total, true);
+  if (st) return st;
+  for (int c = 0; c < count; ++c) {
+    const sdq_instance& a = inst[c * nf];
+    if (a.n > 16 * sdq::kMaxNT)
+      return fail(ctx, SDQ_EUNSUPPORTED, "local updates are implemented for n <= 128");
+    for (int f = 1; f < nf; ++f) {
+      const sdq_instance& b = inst[c * nf + f];
+      if (b.field != a.field || b.n != a.n || b.m != a.m || b.k != a.k)
+        return fail(ctx, SDQ_EINVAL, "the flavours of a chain must share field, n, m and k");
+    }
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<int64_t> off;
+  st = alloc_stages(ctx, ctx->d_ck, inst, total, 2, off);
+  if (st) return st;
+  double* ck = (double*)ctx->d_ck.p;
+  std::vector<Inst> base;
+  size_t uoff = 0;
+  for (int c = 0; c < count; ++c) {
+    for (int f = 0; f < nf; ++f) {
+      const int i = c * nf + f;
+      Inst I = base_inst(inst[i]);
+      const int64_t one = (int64_t)I.nb * sdq::stage_doubles(I.n);
+      I.ckf = ck + off[i];
+      I.cka = ck + off[i] + one;
+      I.status = status ? status + i : nullptr;
+      I.unif = unif + uoff;
+      I.nacc = accepted + c;
+      base.push_back(I);
+    }
+    uoff += (size_t)inst[c * nf].m * inst[c * nf].n;
+  }
+  HIP_TRY(sdq::launch_fill_i32(accepted, count, 0, ctx->stream), "fill(accepted)");
+  ctx->err.clear();
+  // backward stages of the current field: the slices after each block stay
+  // unchanged until the sweep reaches them
+  {
+    Plan P;
+    P.inst = base;
+    for (int i = 0; i < total; ++i) P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ, 0, 0});
+    order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
+      const Inst& I = P.inst[w.inst];
+      return sweep_cost(I.n, I.m, I.k);
+    });
+    st = run_plan(ctx, P, status, total);
+    if (st) return st;
+  }
+  int nbmax = 0;
+  for (const Inst& I : base) nbmax = std::max(nbmax, I.nb);
+  for (int j = 0; j < nbmax; ++j) {
+    Plan P;
+    P.inst = base;
+    for (int c = 0; c < count; ++c)
+      if (j < base[c * nf].nb) P.pair[sdq::PAIR_LOCAL].push_back(PairItem{c * nf, j, nf, 0});
+    order_all_pairs(P);
+    st = run_plan(ctx, P, nullptr, 0);
+    if (st) return st;
+    // forward stage j+1 from the updated field of block j
+    Plan Q;
+    Q.inst = base;
+    for (int i = 0; i < total; ++i)
+      if (j + 1 < base[i].nb) Q.sweep.push_back(SweepItem{i, sdq::SW_BLOCK, j, 0});
+    if (Q.sweep.empty()) continue;
+    order_items(Q.inst, Q.sweep, Q.sweep_ranges, [&](const SweepItem& w) {
+      const Inst& I = Q.inst[w.inst];
+      return (double)I.n * I.n * I.n;
+    });
+    st = run_plan(ctx, Q, nullptr, 0);
+    if (st) return st;
+  }
+  return SDQ_OK;
 }
 
 sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_instance* prop,
