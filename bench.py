@@ -67,7 +67,7 @@ def main():
                     help="time the batched step only (no equal-time / per-chain extras); for profiler runs")
     ap.add_argument("--workload", default="hubbard_L8_b40_batch512",
                     choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
-                             "hubbard_L8_b40_metropolis256",
+                             "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L16_b40_batch128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
@@ -106,7 +106,8 @@ def main():
     l_list = W.l_list or []
     kind = {"hubbard_L8_b40_batch512": "tdisp", "hubbard_L16_b40_batch128": "tdisp",
             "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad",
-            "hubbard_L8_b40_metropolis256": "metropolis"}[args.workload]
+            "hubbard_L8_b40_metropolis256": "metropolis",
+            "hubbard_L8_b40_local256": "local"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
     plain = args.scheme == "plain"
@@ -165,8 +166,29 @@ def main():
         mgen.manual_seed(wl.BASE_SEED + 2000)
         acc_sum = torch.zeros(C, dtype=torch.int64, device=dev)
 
+    if kind == "local":
+        # one sweep of single-site flips over every chain's field (both
+        # flavours share it); uniform numbers drawn on the device per step
+        assert all(insts[2 * c].field is insts[2 * c + 1].field for c in range(cnt // 2))
+        C = cnt // 2
+        Fc = torch.from_numpy(np.stack([insts[2 * c].field for c in range(C)])).to(dev)
+        loc_ch = []
+        for c in range(C):
+            for I in (insts[2 * c], insts[2 * c + 1]):
+                loc_ch.append(sdq.Chain(dev_of(I.expk), Fc[c], I.alpha, I.k, dev_of(I.expk_inv)))
+        li = ctx._instances(loc_ch, need_inv=True)
+        acc = torch.zeros(C, dtype=torch.int32, device=dev)
+        acc_sum = torch.zeros(C, dtype=torch.int64, device=dev)
+        ugen = torch.Generator(device=dev)
+        ugen.manual_seed(wl.BASE_SEED + 2100)
+        ubuf = torch.empty(C, m, n, dtype=torch.float64, device=dev)
+
     def step():
-        if kind == "metropolis":
+        if kind == "local":
+            ubuf.uniform_(generator=ugen)
+            ctx._chk(ctx.lib.sdq_local_sweep(ctx.h, li, C, 2, vp(ubuf), vp(acc), vp(st)))
+            acc_sum.add_(acc)
+        elif kind == "metropolis":
             Fp.copy_(Fc)
             rows = torch.randint(0, m, (C,), device=dev, generator=mgen)
             Fp[idx, rows] *= -1.0
@@ -200,6 +222,7 @@ def main():
     n_sw, ms_sw = ctx.kernel_stats("sweep")
     n_pa, ms_pa = ctx.kernel_stats("grad" if kind == "grad" else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
+    n_lo, ms_lo = ctx.kernel_stats("local")
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
@@ -207,7 +230,7 @@ def main():
     status_ok = int((st != 0).sum().item()) == 0
     n_bad = int((st != 0).sum().item())
 
-    sweeps_per_chain = 1 if kind in ("greens", "metropolis") else 2
+    sweeps_per_chain = 1 if kind in ("greens", "metropolis") else 2  # local: backward + rebuilt forward
     f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
     if plain:
         f_sweep = sum(plain_sweep_flops(I.n, I.m, I.k, l_list) for I in insts)
@@ -223,6 +246,11 @@ def main():
         f_pair = 0.0
     f_equal = sum((4.0 / 3.0 + 2.0 + 1.0 + 2.0) * I.n ** 3 for I in insts)
     sweep_avg_s = ms_sw / max(n_sw, 1) * 1e-3
+    if kind == "local":
+        # a step launches one backward sweep and nb-1 single-block forward
+        # rebuilds: the roofline takes the step's sweep flops over its sweep time
+        f_sweep = sum(2.0 * sweep_flops(I.n, I.m, I.k) for I in insts)
+        sweep_avg_s = ms_sw / max(args.steps, 1) * 1e-3
     pair_avg_s = ms_pa / max(n_pa, 1) * 1e-3
     achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
@@ -262,6 +290,10 @@ def main():
     elif kind == "greens":
         metric = f"equal-time Green's functions/sec (FP64, {W.name})"
         unit = "chains/s (each: G, log|det|, sign)"
+    elif kind == "local":
+        metric = "local-update sweeps/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
+        unit = ("chain sweeps/s (each: M x N = 25600 single-flip proposals with both flavours' "
+                "determinant ratios, rank-one updates, wrapping and per-block recomputation)")
     elif kind == "metropolis":
         metric = "global Metropolis updates/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
         unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
@@ -272,7 +304,7 @@ def main():
     betas = sorted({round(I.m * I.dtau, 6) for I in insts})
     out = {
         "metric": metric,
-        "value": (cnt // 2 if kind == "metropolis" else cnt) / (ms_step * 1e-3),
+        "value": (cnt // 2 if kind in ("metropolis", "local") else cnt) / (ms_step * 1e-3),
         "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
@@ -304,12 +336,27 @@ def main():
     }
     if kind == "metropolis":
         out["acceptance"] = float(acc_sum.sum().item()) / (C * (args.warmup + args.steps))
+    if kind == "local":
+        out["acceptance"] = float(acc_sum.sum().item()) / (C * m * n * (args.warmup + args.steps))
+        # algorithmic flops of the local kernel per step: per flavour the
+        # block-start G (about 20 N^3 per block, as in the gradient), 4 N^3 per
+        # wrap, 2 N^2 per accepted flip
+        flips = float(acc_sum.sum().item()) / (args.warmup + args.steps)
+        nbk = (m + k - 1) // k
+        f_local = C * 2 * (nbk * 20.0 + (m - nbk) * 4.0) * n ** 3 + flips * 2 * 2.0 * n ** 2
+        out["local_kernel"] = {"launches_per_step": n_lo / max(args.steps, 1),
+                               "ms_per_step": ms_lo / max(args.steps, 1),
+                               "flops_per_step": f_local,
+                               "achieved_tflops": f_local / (ms_lo / max(args.steps, 1) * 1e-3) / 1e12
+                               if ms_lo > 0 else None}
     if scheme_check is not None:
         scheme_check["chains_flagged_nonfinite"] = n_bad
         out["scheme_check"] = scheme_check
 
     if not args.no_cpu and kind == "metropolis":
         out["cpu_baseline"] = cpu_baseline_metropolis(insts, args.cpu_sample)
+    if not args.no_cpu and kind == "local":
+        out["cpu_baseline"] = cpu_baseline_local(insts)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -372,6 +419,31 @@ def measured_traffic():
         return None
     m = re.search(r"bench traffic line: sweep ([0-9.eE+-]+)", text)
     return float(m.group(1)) if m else None
+
+
+def cpu_baseline_local(insts, nsites=1024):
+    """The oracle's local update as it stands (the ratio of one flip from two
+    stabilized log|det| per flavour), on a bounded sample of `nsites` flips of
+    one chain on the host threads, scaled to chain sweeps (M x N flips)."""
+    import numpy as np
+    import oracle
+
+    I0, I1 = insts[0], insts[1]
+    m, n = I0.field.shape
+    rng = np.random.default_rng(2)
+    jobs = []
+    for _ in range(nsites):
+        f = I0.field.copy()
+        f[rng.integers(0, m), rng.integers(0, n)] *= -1.0
+        jobs += [(I0, f), (I1, f)]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda j: oracle.greens(j[0].expk, j[1], j[0].alpha, j[0].k), jobs))
+    dt = time.perf_counter() - t0
+    return {"value": nsites / dt / (m * n), "unit": "chain sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsites} flips of one chain (2 flavours, one oracle log|det| each), {dt:.1f} s "
+                      f"wall, scaled to {m * n} flips per sweep"}
 
 
 def cpu_baseline_metropolis(insts, nchains):

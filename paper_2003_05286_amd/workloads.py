@@ -181,6 +181,10 @@ def workload(name: str, scale: float = 1.0) -> Workload:
         return Workload(name, hubbard_ising(8, 40.0, nb(256), 2, seed=BASE_SEED + 5),
                         notes="L=8 (N=64), beta=40, M=400, k=10, 256 chains x 2 flavours sharing "
                               "their field; global Metropolis steps flipping one time slice")
+    if name == "hubbard_L8_b40_local256":
+        return Workload(name, hubbard_ising(8, 40.0, nb(256), 2, seed=BASE_SEED + 6),
+                        notes="L=8 (N=64), beta=40, M=400, k=10, 256 chains x 2 flavours sharing "
+                              "their field; one sweep of single-site flips per step")
     if name == "hubbard_uneven_batch512":
         return Workload(name, uneven_batch(nb(512)),
                         notes="L in {6,8,10,12}, beta in {10,20,40}, k=10, U=4")
