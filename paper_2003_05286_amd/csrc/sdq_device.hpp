@@ -1736,9 +1736,22 @@ __device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, 
   double* fld = const_cast<double*>(I0.field);
   double* ca = S.cand[0][0];
   double* cb = S.cand[1][0];
+  // Delta takes two values per flavour (f = +-1 for Hirsch's field; any
+  // other value falls back to the exponential)
+  const double dap = exp(-2.0 * I0.alpha) - 1.0, dam = exp(2.0 * I0.alpha) - 1.0;
+  const double dbp = exp(-2.0 * I1.alpha) - 1.0, dbm = exp(2.0 * I1.alpha) - 1.0;
+  // the slice's field row and uniform numbers, staged in LDS (S.vbuf rows 0, 1)
+  double* frow = S.vbuf[0];
+  double* urow = S.vbuf[1];
   int nacc = 0;
   bool bad = false;
   for (int l = l0; l <= l1; ++l) {
+    __syncthreads();
+    for (int t = L.t; t < n; t += G::THREADS) {
+      frow[t] = gmem(fld)[(size_t)(l - 1) * n + t];
+      urow[t] = gmem(I0.unif)[(size_t)(l - 1) * n + t];
+    }
+    __syncthreads();
     for (int i = 0; i < n; ++i) {
       // the lanes holding column i publish it (both flavours)
       const int ct = i >> 4;
@@ -1756,23 +1769,25 @@ __device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, 
           }
       }
       __syncthreads();
-      const size_t e = (size_t)(l - 1) * n + i;
-      const double s = gmem(fld)[e];
-      const double da = exp(-2.0 * I0.alpha * s) - 1.0;
+      const double s = frow[i];
+      const double da = s == 1.0 ? dap : (s == -1.0 ? dam : exp(-2.0 * I0.alpha * s) - 1.0);
       const double ra = 1.0 + da * (1.0 - ca[i]);
       double rb = 1.0, db = 0.0;
       if (nf > 1) {
-        db = exp(-2.0 * I1.alpha * s) - 1.0;
+        db = s == 1.0 ? dbp : (s == -1.0 ? dbm : exp(-2.0 * I1.alpha * s) - 1.0);
         rb = 1.0 + db * (1.0 - cb[i]);
       }
       bad = bad || !isfinite(ra) || !isfinite(rb);
-      if (gmem(I0.unif)[e] < fabs(ra * rb)) {
+      if (urow[i] < fabs(ra * rb)) {
         flip_update<NT, P>(L, Ga, ca, i, da / ra);
         if (nf > 1) flip_update<NT, P>(L, Gb, cb, i, db / rb);
-        if (L.t == 0) gmem(fld)[e] = -s;
+        if (L.t == 0) {
+          gmem(fld)[(size_t)(l - 1) * n + i] = -s;
+          frow[i] = -s;
+        }
         ++nacc;
       }
-      __syncthreads();  // the column buffers and the field entry are reused
+      __syncthreads();  // the column buffers and the field row are reused
     }
     if (l < l1) {
       wrap_g<NT, P, ELDS>(L, S, I0, l, Ga);
