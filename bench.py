@@ -223,6 +223,7 @@ def main():
     n_pa, ms_pa = ctx.kernel_stats("grad" if kind == "grad" else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
     n_lo, ms_lo = ctx.kernel_stats("local")
+    n_bs, ms_bs = ctx.kernel_stats("bstart")
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
@@ -338,17 +339,18 @@ def main():
         out["acceptance"] = float(acc_sum.sum().item()) / (C * (args.warmup + args.steps))
     if kind == "local":
         out["acceptance"] = float(acc_sum.sum().item()) / (C * m * n * (args.warmup + args.steps))
-        # algorithmic flops of the local kernel per step: per flavour the
-        # block-start G (about 20 N^3 per block, as in the gradient), 4 N^3 per
-        # wrap, 2 N^2 per accepted flip
+        # algorithmic flops of the local kernels per step: per flavour the
+        # block-start G (about 20 N^3 per block, as in the gradient; its own
+        # launch), 4 N^3 per wrap, 2 N^2 per accepted flip
         flips = float(acc_sum.sum().item()) / (args.warmup + args.steps)
         nbk = (m + k - 1) // k
         f_local = C * 2 * (nbk * 20.0 + (m - nbk) * 4.0) * n ** 3 + flips * 2 * 2.0 * n ** 2
-        out["local_kernel"] = {"launches_per_step": n_lo / max(args.steps, 1),
-                               "ms_per_step": ms_lo / max(args.steps, 1),
+        ms_both = (ms_lo + ms_bs) / max(args.steps, 1)
+        out["local_kernel"] = {"launches_per_step": (n_lo + n_bs) / max(args.steps, 1),
+                               "ms_per_step": ms_both,
+                               "block_start_ms_per_step": ms_bs / max(args.steps, 1),
                                "flops_per_step": f_local,
-                               "achieved_tflops": f_local / (ms_lo / max(args.steps, 1) * 1e-3) / 1e12
-                               if ms_lo > 0 else None}
+                               "achieved_tflops": f_local / (ms_both * 1e-3) / 1e12 if ms_both > 0 else None}
     if scheme_check is not None:
         scheme_check["chains_flagged_nonfinite"] = n_bad
         out["scheme_check"] = scheme_check

@@ -52,7 +52,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // sweep and the equal-time inversion at n <= 64 (they fit 256 registers per
 // lane with little or no spilling), one otherwise
 constexpr int minb_for(int nt) { return nt <= 4 ? 2 : 1; }
-constexpr int minb_pair(int nt, int mode) { return mode == 1 ? 1 : minb_for(nt); }
+// (the gradient and the site loop of the local updates keep more state in
+// registers: one)
+constexpr int minb_pair(int nt, int mode) { return mode == 1 || mode == 4 ? 1 : minb_for(nt); }
 
 template <int NT, int P_>
 struct Geo {
@@ -1445,7 +1447,7 @@ __device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst
 // T = t U2^T, then Loh's equal-time inversion; written to S.R row-major
 // ([row][col], padding as identity), ends with a barrier.
 template <int NT, int P, bool ELDS>
-__device__ void block_start_g(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+__device__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, nb = I.nb;
@@ -1625,71 +1627,46 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
 //   G - (e_i - G e_i) (Delta / R) (e_i^T G)        (Sherman-Morrison),
 // the field entry is negated, and after the last site of slice l
 // G_{l+1} = B_l G_l B_l^{-1} with the updated B_l.  G_{jk+1} comes from the
-// stage pair (block_start_g): forward stages rebuilt from the updated field
+// stage pair (block_start_g, in its own launch with one workgroup per
+// flavour, PAIR_BSTART): forward stages rebuilt from the updated field
 // (SW_BLOCK), backward stages of the slices after the block (untouched so
 // far in the sweep).  Both flavours' G stay in registers; the owner of
 // column i publishes that column of each through LDS, one barrier per site,
 // and every wave takes the same decision from the same values.
-template <int NT, int P, bool ELDS>
-__device__ __forceinline__ void rm_from_lds_rows(const Lane& L, const Smem<NT, P, ELDS>& S, RM<NT, P>& A) {
-  using G = Geo<NT, P>;
-#pragma unroll
-  for (int c = 0; c < G::CT; ++c) {
-    const int col = col_of<NT, P>(L, c);
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        A.v[c][ti][r] = tile_ok<NT, P>(L, c) ? S.R[row * G::LDR + col] : (row == col ? 1.0 : 0.0);
-      }
-  }
-}
 
-// G <- E diag(v_l) G diag(1/v_l) E^{-1} (v_l of the current field row)
+// G <- E (diag(v) G diag(1/v)) E^{-1}: the wrap of G across one slice
+// B = E diag(v), v = exp(alpha f) of the slice's field (v at vv[0..NP),
+// 1/v at vv[NP..2NP), staged in LDS, 1 in the padding); G in registers is
+// scaled, parked in LDS as the left operand of G E^{-1} (E^{-1} in registers,
+// zero padded), and E comes from its swizzled copy, staged in S.E when
+// `staged` (ELDS), else read from global memory.  Starts with a barrier (the
+// caller's staging of vv and S.E, and any earlier reader of S.R).
 template <int NT, int P, bool ELDS>
-__device__ void wrap_g(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int l, RM<NT, P>& Gx) {
+__device__ void wrap_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const double* vv,
+                           const RM<NT, P>& Einv, bool staged, RM<NT, P>& Gx) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
-  const int n = I.n;
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     if (!tile_ok<NT, P>(L, c)) continue;
     const int col = col_of<NT, P>(L, c);
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) S.R[row_of(L, ti, r) * G::LDR + col] = Gx.v[c][ti][r];
-  }
-  __syncthreads();
-  const double* fl = I.field + (size_t)(l - 1) * n;
-  RM<NT, P> Bi, Yr;
-#pragma unroll
-  for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT, P>(L, c);
+    const double sc = vv[G::NP + col];
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
-        double x = 0.0;
-        if (row < n && col < n && tile_ok<NT, P>(L, c))
-          x = gmem(I.expk_inv)[row * n + col] * exp(-I.alpha * gmem(fl)[row]);
-        Bi.v[c][ti][r] = x;
+        S.R[row * G::LDR + col] = Gx.v[c][ti][r] * vv[row] * sc;
       }
   }
-  gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row_of(L, ti, r);
-      const double v = row < n ? exp(I.alpha * gmem(fl)[row]) : 0.0;
-#pragma unroll
-      for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
-    }
-  gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gx);
+  __syncthreads();
+  RM<NT, P> Yr;
+  gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Einv, Yr);
+  if (ELDS && staged)
+    gemm_rb<NT, P>(L, EOp<NT, P, ELDS>{S.E, I.esw, L.l}, Yr, Gx);
+  else
+    gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gx);
 }
 
 // G <- G - (e_i - G e_i) coef (e_i^T G); col = column i of G before the update
@@ -1722,37 +1699,49 @@ __device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, 
   constexpr int CT = G::CT;
   const int n = I0.n, m = I0.m, k = I0.k;
   const int l0 = j * k + 1, l1 = (j + 1) * k < m ? (j + 1) * k : m;
-  RM<NT, P> Ga, Gb;
-  block_start_g<NT, P, ELDS>(L, S, I0, j);
-  rm_from_lds_rows<NT, P, ELDS>(L, S, Ga);
-  __syncthreads();
+  // G at the block start (PAIR_BSTART, one workgroup per flavour) and E^{-1}
+  // of each flavour, held in registers for the block
+  RM<NT, P> Ga, Gb, Eia, Eib;
+  load_rm<NT, P>(L, Ga, I0.g, n, false);
+  load_rm<NT, P>(L, Eia, I0.expk_inv, n, false);
   if (nf > 1) {
-    block_start_g<NT, P, ELDS>(L, S, I1, j);
-    rm_from_lds_rows<NT, P, ELDS>(L, S, Gb);
-    __syncthreads();
+    load_rm<NT, P>(L, Gb, I1.g, n, false);
+    load_rm<NT, P>(L, Eib, I1.expk_inv, n, false);
   } else {
     set_identity<NT, P>(L, Gb);
+    set_identity<NT, P>(L, Eib);
   }
+  // E of the first flavour staged in LDS (read by the wraps after a barrier);
+  // the second flavour shares it when its E is the same array
+  stage_e<NT, P, ELDS>(L, S, I0.esw);
+  const bool eb_staged = I1.esw == I0.esw;
   double* fld = const_cast<double*>(I0.field);
-  double* ca = S.cand[0][0];
-  double* cb = S.cand[1][0];
   // Delta takes two values per flavour (f = +-1 for Hirsch's field; any
   // other value falls back to the exponential)
   const double dap = exp(-2.0 * I0.alpha) - 1.0, dam = exp(2.0 * I0.alpha) - 1.0;
   const double dbp = exp(-2.0 * I1.alpha) - 1.0, dbm = exp(2.0 * I1.alpha) - 1.0;
-  // the slice's field row and uniform numbers, staged in LDS (S.vbuf rows 0, 1)
-  double* frow = S.vbuf[0];
-  double* urow = S.vbuf[1];
+  // the slice's field row and uniform numbers, staged in LDS (S.vbuf rows 0,
+  // 1); the column of site i goes to rows 2 + 2 (i % 2) and 3 + 2 (i % 2):
+  // with two buffers one barrier per site suffices (site i + 1 writes the
+  // other buffer, and site i + 2 writes this one only after every wave has
+  // passed the barrier of site i + 1, that is, finished reading site i).
+  // Row 6 receives the field after the decisions (written by thread 0, read
+  // only after the slice)
+  const double* frow = S.vbuf[0];
+  const double* urow = S.vbuf[1];
+  double* fnew = S.vbuf[6];
   int nacc = 0;
   bool bad = false;
   for (int l = l0; l <= l1; ++l) {
     __syncthreads();
     for (int t = L.t; t < n; t += G::THREADS) {
-      frow[t] = gmem(fld)[(size_t)(l - 1) * n + t];
-      urow[t] = gmem(I0.unif)[(size_t)(l - 1) * n + t];
+      S.vbuf[0][t] = gmem(fld)[(size_t)(l - 1) * n + t];
+      S.vbuf[1][t] = gmem(I0.unif)[(size_t)(l - 1) * n + t];
     }
     __syncthreads();
     for (int i = 0; i < n; ++i) {
+      double* ca = S.vbuf[2 + 2 * (i & 1)];
+      double* cb = S.vbuf[3 + 2 * (i & 1)];
       // the lanes holding column i publish it (both flavours)
       const int ct = i >> 4;
       if (L.w == ct % P && L.cl == (i & 15)) {
@@ -1778,20 +1767,29 @@ __device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, 
         rb = 1.0 + db * (1.0 - cb[i]);
       }
       bad = bad || !isfinite(ra) || !isfinite(rb);
-      if (urow[i] < fabs(ra * rb)) {
+      const bool acc = urow[i] < fabs(ra * rb);
+      if (acc) {
         flip_update<NT, P>(L, Ga, ca, i, da / ra);
         if (nf > 1) flip_update<NT, P>(L, Gb, cb, i, db / rb);
-        if (L.t == 0) {
-          gmem(fld)[(size_t)(l - 1) * n + i] = -s;
-          frow[i] = -s;
-        }
+        if (L.t == 0) gmem(fld)[(size_t)(l - 1) * n + i] = -s;
         ++nacc;
       }
-      __syncthreads();  // the column buffers and the field row are reused
+      if (L.t == 0) fnew[i] = acc ? -s : s;
     }
     if (l < l1) {
-      wrap_g<NT, P, ELDS>(L, S, I0, l, Ga);
-      if (nf > 1) wrap_g<NT, P, ELDS>(L, S, I1, l, Gb);
+      __syncthreads();  // fnew complete, the column buffers free
+      double* va = S.vbuf[2];
+      double* vb = S.vbuf[4];
+      for (int t = L.t; t < G::NP; t += G::THREADS) {
+        const double f = t < n ? fnew[t] : 0.0;
+        const double ea = exp(I0.alpha * f), eb = exp(I1.alpha * f);
+        va[t] = ea;
+        va[G::NP + t] = 1.0 / ea;
+        vb[t] = eb;
+        vb[G::NP + t] = 1.0 / eb;
+      }
+      wrap_local<NT, P, ELDS>(L, S, I0, va, Eia, true, Ga);
+      if (nf > 1) wrap_local<NT, P, ELDS>(L, S, I1, vb, Eib, eb_staged, Gb);
     }
   }
   if (L.t == 0 && I0.nacc) atomicAdd(I0.nacc, nacc);
@@ -1816,6 +1814,14 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     if constexpr (MODE == PAIR_LOCAL) {
       const Inst I1 = wi.ilo > 1 ? insts[wi.inst + 1] : I;
       pair_local<NT, P, ELDS>(L, S, I, I1, wi.ilo, wi.j);
+      continue;
+    }
+    if constexpr (MODE == PAIR_BSTART) {
+      // G at the start of block j (row-major in S.R) -> I.g
+      block_start_g<NT, P, ELDS>(L, S, I, wi.j);
+      const int n = I.n;
+      for (int t = L.t; t < n * n; t += Geo<NT, P>::THREADS)
+        gmem(I.g)[t] = S.R[(t / n) * Geo<NT, P>::LDR + t % n];
       continue;
     }
     if constexpr (MODE == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
@@ -1920,6 +1926,8 @@ struct Launch {
                          l_list, q);
     else if (mode == PAIR_LOCAL)
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_LOCAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
+    else if (mode == PAIR_BSTART)
+      hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_BSTART>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     else
       hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_EQUAL>), dim3(grid), b, 0, s, inst, items, count, l_list, q);
     return hipGetLastError();

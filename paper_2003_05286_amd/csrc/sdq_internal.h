@@ -28,7 +28,7 @@ struct Inst {
   int32_t n, m, k, nb;     // nb = ceil(m / k) stabilization blocks
   int32_t scheme;          // 0: Loh's split scales (Sec. 5.1, 6.1), 1: single decomposition
   int32_t pad0;
-  double* g;               // equal-time G [n][n] or null
+  double* g;               // equal-time G [n][n] or null (local updates: G at the block start)
   double* gt;              // time-displaced outputs [n_l][n][n] or null
   double* grad;            // [m][n] or null
   double* logdet;          // scalar or null
@@ -70,14 +70,15 @@ struct SweepItem {
 };
 
 enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2, PAIR_TDISP_PLAIN = 3,
-                          PAIR_LOCAL = 4 };
-constexpr int kPairModes = 5;
+                          PAIR_LOCAL = 4, PAIR_BSTART = 5 };
+constexpr int kPairModes = 6;
 
 // tdisp: stage pair j, outputs for l_list[ilo..ihi) (PAIR_TDISP_PLAIN: the
 //        same from the SW_LEFT / SW_RIGHT chains)
 // grad:  stage pair j (slices j*k+1 .. min((j+1)k, m))
 // local: block j of a local-update sweep; inst = the chain's first flavour,
 //        ilo = number of flavours (1 or 2, consecutive instances)
+// bstart: G at the start of block j of a local-update sweep -> Inst::g
 // equal: the final forward stage -> G, logdet, sign
 struct PairItem {
   int32_t inst;

@@ -76,6 +76,7 @@ struct sdq_ctx {
   DevBuf d_gang;  // per-gang scratch of the n > 128 kernels (bars first)
   DevBuf d_ptrs;  // matrix pointer table of sdq_similarity
   DevBuf d_metro;  // sdq_metropolis: field table, proposed log|det|, signs and status
+  DevBuf d_gloc;   // sdq_local_sweep: G at the block start, n x n per instance
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   void* h_stage = nullptr;
   size_t h_cap = 0;
@@ -388,7 +389,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
   }
   const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_TDISP_PLAIN,
-                                      sdq::PAIR_GRAD, sdq::PAIR_LOCAL};
+                                      sdq::PAIR_GRAD, sdq::PAIR_BSTART, sdq::PAIR_LOCAL};
   for (int oi = 0; oi < sdq::kPairModes; ++oi) {
     const int md = order[oi];
     for (const auto& r : P.pair_ranges[md]) {
@@ -444,7 +445,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   }
   const Inst* d_inst = (const Inst*)(d + B.o_inst);
   const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
-  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local"};
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local", "bstart"};
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
     auto go = [&]() -> hipError_t {
@@ -653,6 +654,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_gang.p) (void)hipFree(ctx->d_gang.p);
   if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
   if (ctx->d_metro.p) (void)hipFree(ctx->d_metro.p);
+  if (ctx->d_gloc.p) (void)hipFree(ctx->d_gloc.p);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
@@ -961,6 +963,10 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
   st = alloc_stages(ctx, ctx->d_ck, inst, total, 2, off);
   if (st) return st;
   double* ck = (double*)ctx->d_ck.p;
+  size_t gdoubles = 0;
+  for (int i = 0; i < total; ++i) gdoubles += (size_t)inst[i].n * inst[i].n;
+  HIP_TRY(grow(ctx->d_gloc, gdoubles * sizeof(double)), "hipMalloc(local G)");
+  double* gl = (double*)ctx->d_gloc.p;
   std::vector<Inst> base;
   size_t uoff = 0;
   for (int c = 0; c < count; ++c) {
@@ -970,6 +976,8 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
       const int64_t one = (int64_t)I.nb * sdq::stage_doubles(I.n);
       I.ckf = ck + off[i];
       I.cka = ck + off[i] + one;
+      I.g = gl;
+      gl += (size_t)I.n * I.n;
       I.status = status ? status + i : nullptr;
       I.unif = unif + uoff;
       I.nacc = accepted + c;
@@ -995,6 +1003,14 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
   int nbmax = 0;
   for (const Inst& I : base) nbmax = std::max(nbmax, I.nb);
   for (int j = 0; j < nbmax; ++j) {
+    // G at the block start, one item per flavour, then the block's sites
+    Plan B;
+    B.inst = base;
+    for (int i = 0; i < total; ++i)
+      if (j < base[i].nb) B.pair[sdq::PAIR_BSTART].push_back(PairItem{i, j, 0, 0});
+    order_all_pairs(B);
+    st = run_plan(ctx, B, nullptr, 0);
+    if (st) return st;
     Plan P;
     P.inst = base;
     for (int c = 0; c < count; ++c)
