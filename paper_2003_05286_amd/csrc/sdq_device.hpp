@@ -282,13 +282,6 @@ __device__ __forceinline__ double reg_at(const double (&a)[NT][4], int tj, int r
   return rj == 0 ? t[0] : rj == 1 ? t[1] : rj == 2 ? t[2] : t[3];
 }
 
-// value of row j of column block c, from the lane group that holds it,
-// broadcast to the four lanes of the column
-template <int NT, int P>
-__device__ __forceinline__ double row_value(const Lane& L, const RM<NT, P>& A, int c, int j) {
-  const double s = reg_at<NT>(A.v[c], j >> 4, (j >> 2) & 3);
-  return sum_col(L.g == (j & 3) ? s : 0.0);
-}
 
 // ---------------------------------------------------------------------------
 // C = A * B on FP64 MFMA.  A(ti, tk, r, i, k) is any callable returning the
@@ -1669,32 +1662,9 @@ __device__ void wrap_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
     gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gx);
 }
 
-// G <- G - (e_i - G e_i) coef (e_i^T G); col = column i of G before the update
-template <int NT, int P>
-__device__ __forceinline__ void flip_update(const Lane& L, RM<NT, P>& Gx, const double* col, int i, double coef) {
-  constexpr int CT = Geo<NT, P>::CT;
-  double y[CT];
-#pragma unroll
-  for (int c = 0; c < CT; ++c) y[c] = row_value<NT, P>(L, Gx, c, i) * coef;  // G[i][b] coef
-  double x[NT][4];
-#pragma unroll
-  for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row_of(L, ti, r);
-      x[ti][r] = (row == i ? 1.0 : 0.0) - col[row];
-    }
-#pragma unroll
-  for (int c = 0; c < CT; ++c)
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Gx.v[c][ti][r] = fma(-x[ti][r], y[c], Gx.v[c][ti][r]);
-}
-
 template <int NT, int P, bool ELDS>
-__device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, const Inst& I1, const int nf,
-                           const int j) {
+__device__ __forceinline__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, const Inst& I1,
+                                           const int nf, const int j) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I0.n, m = I0.m, k = I0.k;
@@ -1739,43 +1709,86 @@ __device__ void pair_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I0, 
       S.vbuf[1][t] = gmem(I0.unif)[(size_t)(l - 1) * n + t];
     }
     __syncthreads();
-    for (int i = 0; i < n; ++i) {
-      double* ca = S.vbuf[2 + 2 * (i & 1)];
-      double* cb = S.vbuf[3 + 2 * (i & 1)];
-      // the lanes holding column i publish it (both flavours)
-      const int ct = i >> 4;
-      if (L.w == ct % P && L.cl == (i & 15)) {
+    // site i = 16 ti + 4 r + g sits in register [.][ti][r] of lane group g:
+    // ti and r unrolled, so every register index below is static
+    static_for<NT>([&](auto tic) {
+      constexpr int ti = decltype(tic)::value;
+      static_for<4>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+#pragma unroll 1
+        for (int g = 0; g < 4; ++g) {
+          const int i = 16 * ti + 4 * r + g;
+          if (i >= n) break;
+          double* ca = S.vbuf[2 + 2 * (g & 1)];
+          double* cb = S.vbuf[3 + 2 * (g & 1)];
+          // the lanes holding column i publish G e_i - e_i (both flavours):
+          // then x = e_i - G e_i is minus the published column and 1 - G_ii
+          // minus its entry i
+          if (L.w == ti % P && L.cl == 4 * r + g) {
+            constexpr int c = ti / P;
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-          if (c == ct / P) {
+            for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-            for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                ca[row_of(L, ti, r)] = Ga.v[c][ti][r];
-                cb[row_of(L, ti, r)] = Gb.v[c][ti][r];
+              for (int rr = 0; rr < 4; ++rr) {
+                const double dg = (tt == ti && rr == r && L.g == g) ? 1.0 : 0.0;
+                ca[row_of(L, tt, rr)] = Ga.v[c][tt][rr] - dg;
+                cb[row_of(L, tt, rr)] = Gb.v[c][tt][rr] - dg;
               }
           }
-      }
-      __syncthreads();
-      const double s = frow[i];
-      const double da = s == 1.0 ? dap : (s == -1.0 ? dam : exp(-2.0 * I0.alpha * s) - 1.0);
-      const double ra = 1.0 + da * (1.0 - ca[i]);
-      double rb = 1.0, db = 0.0;
-      if (nf > 1) {
-        db = s == 1.0 ? dbp : (s == -1.0 ? dbm : exp(-2.0 * I1.alpha * s) - 1.0);
-        rb = 1.0 + db * (1.0 - cb[i]);
-      }
-      bad = bad || !isfinite(ra) || !isfinite(rb);
-      const bool acc = urow[i] < fabs(ra * rb);
-      if (acc) {
-        flip_update<NT, P>(L, Ga, ca, i, da / ra);
-        if (nf > 1) flip_update<NT, P>(L, Gb, cb, i, db / rb);
-        if (L.t == 0) gmem(fld)[(size_t)(l - 1) * n + i] = -s;
-        ++nacc;
-      }
-      if (L.t == 0) fnew[i] = acc ? -s : s;
-    }
+          // row i of G on this wave's columns (y), while the column is in flight
+          double ya[CT], yb[CT];
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            ya[c] = sum_col(L.g == g ? Ga.v[c][ti][r] : 0.0);
+            yb[c] = nf > 1 ? sum_col(L.g == g ? Gb.v[c][ti][r] : 0.0) : 0.0;
+          }
+          __syncthreads();
+          // every LDS value of the site, read at once
+          const double s = frow[i], u = urow[i], omga = -ca[i], omgb = -cb[i];
+          double xa[NT][4], xb[NT][4];
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              xa[tt][rr] = ca[row_of(L, tt, rr)];
+              xb[tt][rr] = cb[row_of(L, tt, rr)];
+            }
+          double da = s == 1.0 ? dap : dam, db = s == 1.0 ? dbp : dbm;
+          if (s != 1.0 && s != -1.0) {  // the same branch in every lane
+            da = exp(-2.0 * I0.alpha * s) - 1.0;
+            db = exp(-2.0 * I1.alpha * s) - 1.0;
+          }
+          const double ra = 1.0 + da * omga;
+          double rb = 1.0;
+          if (nf > 1)
+            rb = 1.0 + db * omgb;
+          else
+            db = 0.0;
+          bad = bad || !isfinite(ra) || !isfinite(rb);
+          const bool acc = u < fabs(ra * rb);
+          // G <- G - x (Delta / R) y^T (Sherman-Morrison) when accepted; the
+          // coefficient is an exact zero otherwise, which leaves G unchanged
+          const double qa = acc ? da / ra : 0.0;
+          const double qb = acc && nf > 1 ? db / rb : 0.0;
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            const double ya_c = ya[c] * qa, yb_c = yb[c] * qb;
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+              for (int rr = 0; rr < 4; ++rr) {
+                Ga.v[c][tt][rr] = fma(xa[tt][rr], ya_c, Ga.v[c][tt][rr]);
+                Gb.v[c][tt][rr] = fma(xb[tt][rr], yb_c, Gb.v[c][tt][rr]);
+              }
+          }
+          if (L.t == 0) {
+            if (acc) gmem(fld)[(size_t)(l - 1) * n + i] = -s;
+            fnew[i] = acc ? -s : s;
+          }
+          nacc += acc ? 1 : 0;
+        }
+      });
+    });
     if (l < l1) {
       __syncthreads();  // fnew complete, the column buffers free
       double* va = S.vbuf[2];

@@ -63,6 +63,10 @@ struct Plan {
   };
   std::vector<Range> sweep_ranges, pair_ranges[sdq::kPairModes];
   bool swz_inv = false;  // also lay out expk_inv (chains of B^{-1} slices)
+  // the swizzled copies are in place already: an earlier plan of the same
+  // call, over the same instances, made them (the layout is a function of
+  // the instances, so the pointers come out the same)
+  bool swz_ready = false;
 };
 
 }  // namespace
@@ -78,10 +82,19 @@ struct sdq_ctx {
   DevBuf d_metro;  // sdq_metropolis: field table, proposed log|det|, signs and status
   DevBuf d_gloc;   // sdq_local_sweep: G at the block start, n x n per instance
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
-  void* h_stage = nullptr;
-  size_t h_cap = 0;
-  hipEvent_t stage_ev = nullptr;
-  bool stage_pending = false;
+  // pinned staging of plan images, a ring: the host waits for the plan
+  // kStageSlots back, not the previous one, so it builds and enqueues the
+  // next plans while the device runs (the device buffer they are copied to is
+  // reused in stream order)
+  static constexpr int kStageSlots = 4;
+  struct StageSlot {
+    void* h = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+  };
+  StageSlot stage[kStageSlots];
+  int stage_next = 0;
   std::map<uint64_t, Handle> handles;
   uint64_t next_handle = 1;
   Tune tune[sdq::kMaxNT + 1];
@@ -351,6 +364,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   {
     sdq_status st = prepare_swizzle(ctx, P, B.swz);
     if (st) return st;
+    if (P.swz_ready) B.swz.clear();
   }
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   int nq = (int)P.sweep_ranges.size();
@@ -534,24 +548,26 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
     hipGraphExec_t exec = hit->exec;
     return timed(ctx, "graph", [&] { return hipGraphLaunch(exec, ctx->stream); });
   }
-  if (ctx->stage_pending) {
-    HIP_TRY(hipEventSynchronize(ctx->stage_ev), "hipEventSynchronize(staging)");
-    ctx->stage_pending = false;
+  sdq_ctx::StageSlot& sl = ctx->stage[ctx->stage_next];
+  ctx->stage_next = (ctx->stage_next + 1) % sdq_ctx::kStageSlots;
+  if (sl.pending) {
+    HIP_TRY(hipEventSynchronize(sl.ev), "hipEventSynchronize(staging)");
+    sl.pending = false;
   }
   const size_t total = B.image.size();
-  if (total > ctx->h_cap) {
-    if (ctx->h_stage) HIP_TRY(hipHostFree(ctx->h_stage), "hipHostFree");
-    ctx->h_stage = nullptr;
-    ctx->h_cap = 0;
-    HIP_TRY(hipHostMalloc(&ctx->h_stage, total * 2, hipHostMallocDefault), "hipHostMalloc");
-    ctx->h_cap = total * 2;
+  if (total > sl.cap) {
+    if (sl.h) HIP_TRY(hipHostFree(sl.h), "hipHostFree");
+    sl.h = nullptr;
+    sl.cap = 0;
+    HIP_TRY(hipHostMalloc(&sl.h, total * 2, hipHostMallocDefault), "hipHostMalloc");
+    sl.cap = total * 2;
   }
-  memcpy(ctx->h_stage, B.image.data(), total);
+  memcpy(sl.h, B.image.data(), total);
   HIP_TRY(grow(ctx->d_upload, total), "hipMalloc(upload)");
-  st = enqueue_built(ctx, B, ctx->stream, (char*)ctx->d_upload.p, (const char*)ctx->h_stage, true);
+  st = enqueue_built(ctx, B, ctx->stream, (char*)ctx->d_upload.p, (const char*)sl.h, true);
   if (st) return st;
-  HIP_TRY(hipEventRecord(ctx->stage_ev, ctx->stream), "hipEventRecord");
-  ctx->stage_pending = true;
+  HIP_TRY(hipEventRecord(sl.ev, ctx->stream), "hipEventRecord");
+  sl.pending = true;
   return SDQ_OK;
 }
 
@@ -614,7 +630,12 @@ sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream) {
   if (!ctx) return SDQ_ENOMEM;
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
-  if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming) != hipSuccess) {
+  bool ok = hipSetDevice(device) == hipSuccess;
+  for (auto& sl : ctx->stage)
+    ok = ok && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    for (auto& sl : ctx->stage)
+      if (sl.ev) (void)hipEventDestroy(sl.ev);
     delete ctx;
     return SDQ_EHIP;
   }
@@ -655,14 +676,16 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
   if (ctx->d_metro.p) (void)hipFree(ctx->d_metro.p);
   if (ctx->d_gloc.p) (void)hipFree(ctx->d_gloc.p);
-  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  for (auto& sl : ctx->stage)
+    if (sl.h) (void)hipHostFree(sl.h);
   for (auto& kv : ctx->stats)
     for (auto& pr : kv.second.pending) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->stage_ev) (void)hipEventDestroy(ctx->stage_ev);
+  for (auto& sl : ctx->stage)
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
   delete ctx;
 }
 
@@ -1006,6 +1029,7 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
     // G at the block start, one item per flavour, then the block's sites
     Plan B;
     B.inst = base;
+    B.swz_ready = true;
     for (int i = 0; i < total; ++i)
       if (j < base[i].nb) B.pair[sdq::PAIR_BSTART].push_back(PairItem{i, j, 0, 0});
     order_all_pairs(B);
@@ -1013,6 +1037,7 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
     if (st) return st;
     Plan P;
     P.inst = base;
+    P.swz_ready = true;
     for (int c = 0; c < count; ++c)
       if (j < base[c * nf].nb) P.pair[sdq::PAIR_LOCAL].push_back(PairItem{c * nf, j, nf, 0});
     order_all_pairs(P);
@@ -1021,6 +1046,7 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
     // forward stage j+1 from the updated field of block j
     Plan Q;
     Q.inst = base;
+    Q.swz_ready = true;
     for (int i = 0; i < total; ++i)
       if (j + 1 < base[i].nb) Q.sweep.push_back(SweepItem{i, sdq::SW_BLOCK, j, 0});
     if (Q.sweep.empty()) continue;
