@@ -38,9 +38,13 @@ def oracle_sweep(E, field, alphas, k, u):
     return f, acc
 
 
+# L = 3, 4: one wave per chain; L = 6, 8, 10 (N = 36, 64, 100): several waves
+# exchanging columns through LDS, ragged last tiles at N = 36 and 100
 @pytest.mark.parametrize("L,beta,k,nf,chains", [(4, 2.0, 10, 2, 3), (4, 4.0, 10, 2, 2),
                                                 (4, 2.5, 10, 2, 2), (3, 3.0, 7, 1, 2),
-                                                (4, 10.0, 10, 2, 1)])
+                                                (4, 10.0, 10, 2, 1), (6, 1.5, 5, 2, 1),
+                                                (8, 1.0, 10, 2, 2), (8, 1.5, 5, 2, 1),
+                                                (10, 0.5, 5, 2, 1)])
 def test_local_sweep_matches_sequential_metropolis(ctx, L, beta, k, nf, chains):
     dtau, U = 0.1, 4.0
     E, Ei = wl.expk_pair(wl.hopping_matrix(L), dtau)
