@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--workload", default="hubbard_L8_b40_batch512",
                     choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
                              "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
-                             "hubbard_L8_b20_phi_batch128", "hubbard_L16_b40_batch128"],
+                             "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
+                             "hubbard_L16_b40_batch128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
                          "(log|det| + gradient) and the L=16 batch (G + G(tau,0) at every slice)")
@@ -107,7 +108,8 @@ def main():
     kind = {"hubbard_L8_b40_batch512": "tdisp", "hubbard_L16_b40_batch128": "tdisp",
             "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad",
             "hubbard_L8_b40_metropolis256": "metropolis",
-            "hubbard_L8_b40_local256": "local"}[args.workload]
+            "hubbard_L8_b40_local256": "local",
+            "hubbard_L8_b20_phi_langevin128": "langevin"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
     plain = args.scheme == "plain"
@@ -130,11 +132,12 @@ def main():
     ctx = sdq.Context(0)
     # outputs preallocated once
     import ctypes
-    inst_arr = ctx._instances(chains, need_inv=(kind == "grad" or plain))
+    inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin") or plain))
     ls = (ctypes.c_int32 * max(len(l_list), 1))(*l_list)
     gts = [torch.empty(len(l_list), I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
         if kind == "tdisp" else []
-    gs = [torch.empty(I.n, I.n, dtype=torch.float64, device=dev) for I in insts] if kind != "grad" else []
+    gs = [torch.empty(I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
+        if kind not in ("grad", "langevin") else []
     grads = [torch.empty(I.m, I.n, dtype=torch.float64, device=dev) for I in insts] if kind == "grad" else []
     ld = torch.empty(cnt, dtype=torch.float64, device=dev)
     sg = torch.empty(cnt, dtype=torch.float64, device=dev)
@@ -166,6 +169,18 @@ def main():
         mgen.manual_seed(wl.BASE_SEED + 2000)
         acc_sum = torch.zeros(C, dtype=torch.int64, device=dev)
 
+    if kind == "langevin":
+        # one Langevin step of every chain's field per step (Gaussian weight
+        # of unit variance, step 0.01); the normal numbers are drawn on the
+        # device per step
+        Fl = torch.from_numpy(np.stack([I.field for I in insts])).to(dev)
+        lg_ch = [sdq.Chain(dev_of(I.expk), Fl[c], I.alpha, I.k, dev_of(I.expk_inv)) for c, I in enumerate(insts)]
+        lgi = ctx._instances(lg_ch, need_inv=True)
+        ngen = torch.Generator(device=dev)
+        ngen.manual_seed(wl.BASE_SEED + 2200)
+        nbuf = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
+        frc = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
+
     if kind == "local":
         # one sweep of single-site flips over every chain's field (both
         # flavours share it); uniform numbers drawn on the device per step
@@ -184,7 +199,11 @@ def main():
         ubuf = torch.empty(C, m, n, dtype=torch.float64, device=dev)
 
     def step():
-        if kind == "local":
+        if kind == "langevin":
+            nbuf.normal_(generator=ngen)
+            ctx._chk(ctx.lib.sdq_langevin(ctx.h, lgi, cnt, 1, 0.01, 1.0, vp(nbuf), vp(frc), vp(ld), vp(sg),
+                                          vp(st)))
+        elif kind == "local":
             ubuf.uniform_(generator=ugen)
             ctx._chk(ctx.lib.sdq_local_sweep(ctx.h, li, C, 2, vp(ubuf), vp(acc), vp(st)))
             acc_sum.add_(acc)
@@ -220,10 +239,11 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_sw, ms_sw = ctx.kernel_stats("sweep")
-    n_pa, ms_pa = ctx.kernel_stats("grad" if kind == "grad" else "pair")
+    n_pa, ms_pa = ctx.kernel_stats("grad" if kind in ("grad", "langevin") else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
     n_lo, ms_lo = ctx.kernel_stats("local")
     n_bs, ms_bs = ctx.kernel_stats("bstart")
+    n_lv, ms_lv = ctx.kernel_stats("langevin")
     ctx.set_profiling(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; sweep {ms_sw / max(n_sw, 1):.3f} ms x "
@@ -241,7 +261,7 @@ def main():
         # l a multiple of k (or m) is a direct inversion, the others propagate
         n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
         f_pair = sum(pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
-    elif kind == "grad":
+    elif kind in ("grad", "langevin"):
         f_pair = sum(grad_flops(I.n, I.m, I.k) for I in insts)
     else:
         f_pair = 0.0
@@ -299,6 +319,10 @@ def main():
         metric = "global Metropolis updates/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
         unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
                 "field, one time slice flipped, and the accept step)")
+    elif kind == "langevin":
+        metric = "Langevin steps/sec (FP64, L=8, beta=20, 128 chains, continuous field)"
+        unit = ("chain steps/s (each: log|det| and its adjoint gradient over all M x N field entries, "
+                "then phi <- phi - eps dS/dphi + sqrt(2 eps) eta)")
     else:
         metric = f"log|det| + adjoint gradients/sec (FP64, {W.name})"
         unit = "chains/s (each: log|det| and its gradient over all M x N field entries)"
@@ -351,6 +375,14 @@ def main():
                                "block_start_ms_per_step": ms_bs / max(args.steps, 1),
                                "flops_per_step": f_local,
                                "achieved_tflops": f_local / (ms_both * 1e-3) / 1e12 if ms_both > 0 else None}
+    if kind == "langevin":
+        # the update itself: read phi, the gradient and the noise, write phi
+        # and the force (5 x 8 B per entry)
+        b_upd = 5 * 8.0 * sum(I.m * I.n for I in insts)
+        ms_u = ms_lv / max(n_lv, 1)
+        out["langevin_kernel"] = {"launches_per_step": n_lv / max(args.steps, 1), "launch_ms": ms_u,
+                                  "bytes_per_launch": b_upd,
+                                  "achieved_gbs": b_upd / (ms_u * 1e-3) / 1e9 if ms_u > 0 else None}
     if scheme_check is not None:
         scheme_check["chains_flagged_nonfinite"] = n_bad
         out["scheme_check"] = scheme_check
@@ -359,6 +391,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline_metropolis(insts, args.cpu_sample)
     if not args.no_cpu and kind == "local":
         out["cpu_baseline"] = cpu_baseline_local(insts)
+    if not args.no_cpu and kind == "langevin":
+        out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -446,6 +480,31 @@ def cpu_baseline_local(insts, nsites=1024):
     return {"value": nsites / dt / (m * n), "unit": "chain sweeps/s", "cores": threads, "kind": "oracle",
             "sample": f"{nsites} flips of one chain (2 flavours, one oracle log|det| each), {dt:.1f} s "
                       f"wall, scaled to {m * n} flips per sweep"}
+
+
+def cpu_baseline_langevin(insts, nchains):
+    """The oracle as it stands, on a bounded sample: the gradient of `nchains`
+    chains (every slice's G from its stabilized chain, the slices of a chain
+    split over the host threads) and the step's update."""
+    import numpy as np
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    print(f"[bench] cpu oracle: Langevin steps of {nchains} chains on {threads} threads", file=sys.stderr,
+          flush=True)
+    rng = np.random.default_rng(7)
+    t0 = time.perf_counter()
+    for I in insts[:nchains]:
+        parts = [p for p in np.array_split(np.arange(1, I.m + 1, dtype=np.int32), threads) if len(p)]
+        with cf.ThreadPoolExecutor(threads) as ex:
+            g = np.concatenate(list(ex.map(lambda ls: oracle.logdet_grad(I.expk, I.field, I.alpha, I.k, ls),
+                                           parts)))
+        eta = rng.normal(size=I.field.shape)
+        _ = I.field - 0.01 * (I.field - g) + np.sqrt(0.02) * eta
+    dt = time.perf_counter() - t0
+    return {"value": nchains / dt, "unit": "chain steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nchains} of the 128 chains, each: the oracle's gradient over all "
+                      f"{insts[0].m} x {insts[0].n} entries and the update; {dt:.1f} s wall"}
 
 
 def cpu_baseline_metropolis(insts, nchains):

@@ -202,6 +202,28 @@ sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_insta
                           int32_t count, int32_t nf, const double* dS, const double* u, double* logdet,
                           double* sign, int32_t* accept, int32_t* status);
 
+/* One Langevin step (Euler-Maruyama) of a continuous field, driven by the
+ * gradient of sdq_logdet_grad.  The field's weight is exp(-S) with
+ *   S = inv_var/2 sum_{l,i} phi_{l,i}^2 - sum_f log|det(1 + B_f)|
+ * (Sec. 2: a Gaussian bosonic weight times the flavours' determinants, whose
+ * absolute value is sampled), and the step is
+ *   F   = dS/dphi = inv_var phi - sum_f grad_f     (grad_f as in sdq_logdet_grad)
+ *   phi <- phi - eps F + sqrt(2 eps) noise.
+ *   inst     host array [count * nf]; flavour f of chain c at c * nf + f, all
+ *            flavours of a chain on the same field array (device, m x n,
+ *            updated in place) with the same n and m; needs expk_inv
+ *   eps      step size, > 0; inv_var >= 0 (0: no bosonic term)
+ *   noise    device: the chains' [m][n] blocks of standard normal numbers,
+ *            back to back in chain order
+ *   force    device, same layout as noise, receives F; or NULL
+ *   logdet, sign  device [count * nf] or NULL: of the field before the step
+ *   status   device [count * nf] or NULL; a chain with a nonzero status of
+ *            any flavour keeps its field
+ * The gradients go through library memory (m * n doubles per instance). */
+sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
+                        double inv_var, const double* noise, double* force, double* logdet, double* sign,
+                        int32_t* status);
+
 /* M <- left * M * right for `count` n x n row-major device matrices: mats is
  * a host array [count] of device pointers (updated in place; the entries
  * must not overlap), left and right are device n x n matrices shared by the

@@ -28,7 +28,7 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
-           "sdq_local_sweep")
+           "sdq_local_sweep", "sdq_langevin")
 
 
 class SdqError(RuntimeError):
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_similarity.argtypes = [vp, i32, i32, vp, vp, P(vp)]
     L.sdq_metropolis.argtypes = [vp, P(_Instance), P(_Instance), i32, i32, vp, vp, vp, vp, vp, vp]
     L.sdq_local_sweep.argtypes = [vp, P(_Instance), i32, i32, vp, vp, vp]
+    L.sdq_langevin.argtypes = [vp, P(_Instance), i32, i32, dbl, dbl, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -260,6 +261,28 @@ class Context:
         self._chk(self.lib.sdq_metropolis(self.h, ci, pi, count, nf, _ptr(dS), _ptr(u), _ptr(logdet),
                                           _ptr(sign), _ptr(acc), _ptr(st)))
         return acc, st
+
+    def langevin(self, chains, nf, eps, inv_var, noise, force=True):
+        """One Langevin step (sdq_langevin): chains = count * nf Chains
+        (flavours of a chain consecutive, sharing its field tensor, which is
+        updated in place); noise: device [count, m, n] standard normals.
+        Returns (force [count, m, n] or None, logdet [count * nf], sign
+        [count * nf], status [count * nf] int32), logdet and sign of the
+        field before the step."""
+        total = len(chains)
+        if nf < 1 or total % nf:
+            raise ValueError("chains must hold count * nf entries")
+        count = total // nf
+        c0 = chains[0]
+        _check_tensor(noise, "noise", (count, c0.m, c0.n), self.tdev)
+        inst = self._instances(chains, need_inv=True)
+        frc = torch.empty(count, c0.m, c0.n, dtype=torch.float64, device=self.tdev) if force else None
+        ld, sg = self._empty(total), self._empty(total)
+        st = torch.empty(total, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_langevin(self.h, inst, count, nf, float(eps), float(inv_var), _ptr(noise),
+                                        _ptr(frc) if frc is not None else None, _ptr(ld), _ptr(sg),
+                                        _ptr(st)))
+        return frc, ld, sg, st
 
     def local_sweep(self, chains, nf, unif):
         """One sweep of local updates (sdq_local_sweep): chains = count * nf

@@ -145,6 +145,30 @@ hipError_t launch_metropolis(int count, int nf, const MetroField* fields, const 
                      st_prop, dS, u, logdet, sign, accept);
   return hipGetLastError();
 }
+// Euler-Maruyama step of Langevin dynamics for the field: blockIdx.y is the
+// chain, the x blocks stride over its m * n entries.  The force reads the
+// field before this thread overwrites the same entry, and no other thread
+// touches that entry.
+__global__ void k_langevin(int nf, const LangevinChain* __restrict__ chains, double eps, double inv_var) {
+  const LangevinChain C = chains[blockIdx.y];
+  for (int g = 0; g < nf; ++g)
+    if (C.status[g] != 0) return;
+  const double amp = sqrt(2.0 * eps);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < C.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double phi = C.phi[t];
+    double f = inv_var * phi;
+    for (int g = 0; g < nf; ++g) f -= C.grad[(int64_t)g * C.len + t];
+    C.phi[t] = phi - eps * f + amp * C.noise[t];
+    if (C.force) C.force[t] = f;
+  }
+}
+hipError_t launch_langevin(int count, int nf, const LangevinChain* chains, double eps, double inv_var,
+                           int grid_per_chain, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_langevin, dim3(grid_per_chain, count), dim3(256), 0, s, nf, chains, eps, inv_var);
+  return hipGetLastError();
+}
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset, dim3((nq + 63) / 64), dim3(64), 0, s, q, nq);

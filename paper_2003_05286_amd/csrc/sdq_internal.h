@@ -118,6 +118,22 @@ hipError_t launch_metropolis(int count, int nf, const MetroField* fields, const 
                              const double* sg_prop, const int32_t* st_prop, const double* dS,
                              const double* u, double* logdet, double* sign, int32_t* accept,
                              hipStream_t s);
+// One chain of a Langevin step: its field (updated in place), the gradients
+// of its nf flavours (consecutive, len doubles apart), its noise block and
+// the force output (or null), len = m * n doubles each.
+struct LangevinChain {
+  double* phi;
+  const double* grad;
+  const double* noise;
+  double* force;
+  const int32_t* status;  // the flavours' statuses (nf consecutive)
+  int64_t len;
+};
+// phi <- phi - eps F + sqrt(2 eps) noise, F = inv_var phi - sum_f grad_f
+// (see sdq_langevin), for chains whose flavours all have status 0 (the
+// others keep their field); grid-stride over the chains' entries.
+hipError_t launch_langevin(int count, int nf, const LangevinChain* chains, double eps, double inv_var,
+                           int grid_per_chain, hipStream_t s);
 // Copy the n x n row-major matrix e (or its transpose) into the MFMA
 // A-operand order used by the kernels: for NT = ceil(n/16), block
 // b = (ti*NT + tk)*4 + r holds at position l the entry

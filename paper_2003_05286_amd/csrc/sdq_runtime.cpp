@@ -81,6 +81,8 @@ struct sdq_ctx {
   DevBuf d_ptrs;  // matrix pointer table of sdq_similarity
   DevBuf d_metro;  // sdq_metropolis: field table, proposed log|det|, signs and status
   DevBuf d_gloc;   // sdq_local_sweep: G at the block start, n x n per instance
+  DevBuf d_lgrad;  // sdq_langevin: gradients of every instance, then statuses
+  DevBuf d_ltab;   // sdq_langevin: chain table
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   // pinned staging of plan images, a ring: the host waits for the plan
   // kStageSlots back, not the previous one, so it builds and enqueues the
@@ -676,6 +678,8 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
   if (ctx->d_metro.p) (void)hipFree(ctx->d_metro.p);
   if (ctx->d_gloc.p) (void)hipFree(ctx->d_gloc.p);
+  if (ctx->d_lgrad.p) (void)hipFree(ctx->d_lgrad.p);
+  if (ctx->d_ltab.p) (void)hipFree(ctx->d_ltab.p);
   for (auto& sl : ctx->stage)
     if (sl.h) (void)hipHostFree(sl.h);
   for (auto& kv : ctx->stats)
@@ -1103,6 +1107,76 @@ sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_insta
     return sdq::launch_metropolis(count, nf, (const sdq::MetroField*)base, ld_p, sg_p, st_p, dS, u,
                                   logdet, sign, accept, ctx->stream);
   });
+}
+
+sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
+                        double inv_var, const double* noise, double* force, double* logdet, double* sign,
+                        int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
+  if (count == 0) return SDQ_OK;
+  if (!noise) return fail(ctx, SDQ_EINVAL, "noise is NULL");
+  if (!(eps > 0.0) || !std::isfinite(eps) || !(inv_var >= 0.0) || !std::isfinite(inv_var))
+    return fail(ctx, SDQ_EINVAL, "need eps > 0 and a finite inv_var >= 0");
+  const int total = count * nf;
+  sdq_status st = validate(ctx, inst, total, true);
+  if (st) return st;
+  for (int c = 0; c < count; ++c) {
+    const sdq_instance& a = inst[c * nf];
+    for (int f = 1; f < nf; ++f) {
+      const sdq_instance& b = inst[c * nf + f];
+      if (b.field != a.field || b.n != a.n || b.m != a.m)
+        return fail(ctx, SDQ_EINVAL, "the flavours of a chain must share field, n and m");
+    }
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  // the gradient of every instance (and the statuses, when the caller keeps
+  // none) in the context's scratch, back to back
+  size_t gtot = 0;
+  int64_t lmax = 0;
+  for (int i = 0; i < total; ++i) {
+    gtot += (size_t)inst[i].m * inst[i].n;
+    lmax = std::max<int64_t>(lmax, (int64_t)inst[i].m * inst[i].n);
+  }
+  const size_t o_st = (gtot * sizeof(double) + 255) & ~(size_t)255;
+  HIP_TRY(grow(ctx->d_lgrad, o_st + (size_t)total * sizeof(int32_t)), "hipMalloc(langevin)");
+  int32_t* stp = status ? status : (int32_t*)((char*)ctx->d_lgrad.p + o_st);
+  std::vector<double*> gp(total);
+  double* g = (double*)ctx->d_lgrad.p;
+  for (int i = 0; i < total; ++i) {
+    gp[i] = g;
+    g += (size_t)inst[i].m * inst[i].n;
+  }
+  st = sdq_logdet_grad(ctx, 0, inst, total, gp.data(), logdet, sign, stp);
+  if (st) return st;
+  std::vector<sdq::LangevinChain> tab(count);
+  size_t noff = 0;
+  for (int c = 0; c < count; ++c) {
+    const sdq_instance& a = inst[c * nf];
+    const int64_t len = (int64_t)a.m * a.n;
+    tab[c] = sdq::LangevinChain{const_cast<double*>(a.field), gp[c * nf], noise + noff,
+                                force ? force + noff : nullptr, stp + c * nf, len};
+    noff += (size_t)len;
+  }
+  HIP_TRY(grow(ctx->d_ltab, (size_t)count * sizeof(sdq::LangevinChain)), "hipMalloc(langevin table)");
+  // stream-ordered after the previous step's update read the table; the
+  // source is pageable, so it may be reused once this returns
+  HIP_TRY(hipMemcpyAsync(ctx->d_ltab.p, tab.data(), (size_t)count * sizeof(sdq::LangevinChain),
+                         hipMemcpyHostToDevice, ctx->stream),
+          "hipMemcpyAsync(langevin table)");
+  ctx->err.clear();
+  // about four workgroups per CU over the batch, at least one per chain
+  const int per = (int)std::max<int64_t>(1, std::min<int64_t>((lmax + 255) / 256,
+                                                               (4LL * ctx->num_cu + count - 1) / count));
+  const auto* d_tab = (const sdq::LangevinChain*)ctx->d_ltab.p;
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const int cn = std::min(count - c0, 65535);
+    st = timed(ctx, "langevin", [&] {
+      return sdq::launch_langevin(cn, nf, d_tab + c0, eps, inv_var, per, ctx->stream);
+    });
+    if (st) return st;
+  }
+  return SDQ_OK;
 }
 
 sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,
