@@ -69,6 +69,7 @@ def main():
                     choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
                              "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
+                             "hubbard_L8_b20_phi_hmc128",
                              "hubbard_L16_b40_batch128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
@@ -109,7 +110,8 @@ def main():
             "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad",
             "hubbard_L8_b40_metropolis256": "metropolis",
             "hubbard_L8_b40_local256": "local",
-            "hubbard_L8_b20_phi_langevin128": "langevin"}[args.workload]
+            "hubbard_L8_b20_phi_langevin128": "langevin",
+            "hubbard_L8_b20_phi_hmc128": "hmc"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
     plain = args.scheme == "plain"
@@ -132,12 +134,12 @@ def main():
     ctx = sdq.Context(0)
     # outputs preallocated once
     import ctypes
-    inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin") or plain))
+    inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin", "hmc") or plain))
     ls = (ctypes.c_int32 * max(len(l_list), 1))(*l_list)
     gts = [torch.empty(len(l_list), I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
         if kind == "tdisp" else []
     gs = [torch.empty(I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
-        if kind not in ("grad", "langevin") else []
+        if kind not in ("grad", "langevin", "hmc") else []
     grads = [torch.empty(I.m, I.n, dtype=torch.float64, device=dev) for I in insts] if kind == "grad" else []
     ld = torch.empty(cnt, dtype=torch.float64, device=dev)
     sg = torch.empty(cnt, dtype=torch.float64, device=dev)
@@ -181,6 +183,21 @@ def main():
         nbuf = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
         frc = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
 
+    HMC_EPS, HMC_STEPS = 0.05, 10
+    if kind == "hmc":
+        # one trajectory of every chain per step; momenta and uniform numbers
+        # drawn on the device per step
+        Fh = torch.from_numpy(np.stack([I.field for I in insts])).to(dev)
+        hm_ch = [sdq.Chain(dev_of(I.expk), Fh[c], I.alpha, I.k, dev_of(I.expk_inv)) for c, I in enumerate(insts)]
+        hmi = ctx._instances(hm_ch, need_inv=True)
+        hgen = torch.Generator(device=dev)
+        hgen.manual_seed(wl.BASE_SEED + 2300)
+        mbuf = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
+        ubuf_h = torch.empty(cnt, dtype=torch.float64, device=dev)
+        acc = torch.zeros(cnt, dtype=torch.int32, device=dev)
+        acc_sum = torch.zeros(cnt, dtype=torch.int64, device=dev)
+        dHb = torch.empty(cnt, dtype=torch.float64, device=dev)
+
     if kind == "local":
         # one sweep of single-site flips over every chain's field (both
         # flavours share it); uniform numbers drawn on the device per step
@@ -199,7 +216,13 @@ def main():
         ubuf = torch.empty(C, m, n, dtype=torch.float64, device=dev)
 
     def step():
-        if kind == "langevin":
+        if kind == "hmc":
+            mbuf.normal_(generator=hgen)
+            ubuf_h.uniform_(generator=hgen)
+            ctx._chk(ctx.lib.sdq_hmc(ctx.h, hmi, cnt, 1, HMC_EPS, HMC_STEPS, 1.0, vp(mbuf), vp(ubuf_h), vp(ld),
+                                     vp(sg), vp(acc), vp(dHb), vp(st)))
+            acc_sum.add_(acc)
+        elif kind == "langevin":
             nbuf.normal_(generator=ngen)
             ctx._chk(ctx.lib.sdq_langevin(ctx.h, lgi, cnt, 1, 0.01, 1.0, vp(nbuf), vp(frc), vp(ld), vp(sg),
                                           vp(st)))
@@ -239,7 +262,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_sw, ms_sw = ctx.kernel_stats("sweep")
-    n_pa, ms_pa = ctx.kernel_stats("grad" if kind in ("grad", "langevin") else "pair")
+    n_pa, ms_pa = ctx.kernel_stats("grad" if kind in ("grad", "langevin", "hmc") else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
     n_lo, ms_lo = ctx.kernel_stats("local")
     n_bs, ms_bs = ctx.kernel_stats("bstart")
@@ -261,7 +284,7 @@ def main():
         # l a multiple of k (or m) is a direct inversion, the others propagate
         n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
         f_pair = sum(pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
-    elif kind in ("grad", "langevin"):
+    elif kind in ("grad", "langevin", "hmc"):
         f_pair = sum(grad_flops(I.n, I.m, I.k) for I in insts)
     else:
         f_pair = 0.0
@@ -275,6 +298,9 @@ def main():
     pair_avg_s = ms_pa / max(n_pa, 1) * 1e-3
     achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
+    if kind == "hmc":
+        # HMC_STEPS + 1 gradient evaluations per trajectory, log|det| at two
+        total_flops = (HMC_STEPS + 1) * (f_sweep + f_pair) + 2 * f_equal
 
     eq_rate = per_inst_rate = scheme_check = None
     if plain:
@@ -319,6 +345,10 @@ def main():
         metric = "global Metropolis updates/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
         unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
                 "field, one time slice flipped, and the accept step)")
+    elif kind == "hmc":
+        metric = "HMC trajectories/sec (FP64, L=8, beta=20, 128 chains, continuous field)"
+        unit = (f"chain trajectories/s (each: {HMC_STEPS} leapfrog steps of {HMC_EPS}, {HMC_STEPS + 1} "
+                "evaluations of log|det| and its adjoint gradient, the Metropolis test on the energy)")
     elif kind == "langevin":
         metric = "Langevin steps/sec (FP64, L=8, beta=20, 128 chains, continuous field)"
         unit = ("chain steps/s (each: log|det| and its adjoint gradient over all M x N field entries, "
@@ -361,6 +391,8 @@ def main():
     }
     if kind == "metropolis":
         out["acceptance"] = float(acc_sum.sum().item()) / (C * (args.warmup + args.steps))
+    if kind == "hmc":
+        out["acceptance"] = float(acc_sum.sum().item()) / (cnt * (args.warmup + args.steps))
     if kind == "local":
         out["acceptance"] = float(acc_sum.sum().item()) / (C * m * n * (args.warmup + args.steps))
         # algorithmic flops of the local kernels per step: per flavour the
@@ -393,6 +425,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline_local(insts)
     if not args.no_cpu and kind == "langevin":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
+    if not args.no_cpu and kind == "hmc":
+        out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -482,28 +516,32 @@ def cpu_baseline_local(insts, nsites=1024):
                       f"wall, scaled to {m * n} flips per sweep"}
 
 
-def cpu_baseline_langevin(insts, nchains):
-    """The oracle as it stands, on a bounded sample: the gradient of `nchains`
-    chains (every slice's G from its stabilized chain, the slices of a chain
-    split over the host threads) and the step's update."""
+def cpu_baseline_langevin(insts, nchains, nevals=1):
+    """The oracle as it stands, on a bounded sample: `nevals` gradients of each
+    of `nchains` chains (every slice's G from its stabilized chain, the slices
+    of a chain split over the host threads) and the step's update; for a
+    trajectory (nevals > 1) the log|det| at its ends is not timed (it is
+    small beside the gradients)."""
     import numpy as np
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
-    print(f"[bench] cpu oracle: Langevin steps of {nchains} chains on {threads} threads", file=sys.stderr,
-          flush=True)
+    print(f"[bench] cpu oracle: {nevals} gradient(s) of each of {nchains} chain(s) on {threads} threads",
+          file=sys.stderr, flush=True)
     rng = np.random.default_rng(7)
     t0 = time.perf_counter()
     for I in insts[:nchains]:
         parts = [p for p in np.array_split(np.arange(1, I.m + 1, dtype=np.int32), threads) if len(p)]
-        with cf.ThreadPoolExecutor(threads) as ex:
-            g = np.concatenate(list(ex.map(lambda ls: oracle.logdet_grad(I.expk, I.field, I.alpha, I.k, ls),
-                                           parts)))
+        for _ in range(nevals):
+            with cf.ThreadPoolExecutor(threads) as ex:
+                g = np.concatenate(list(ex.map(lambda ls: oracle.logdet_grad(I.expk, I.field, I.alpha, I.k, ls),
+                                               parts)))
         eta = rng.normal(size=I.field.shape)
         _ = I.field - 0.01 * (I.field - g) + np.sqrt(0.02) * eta
     dt = time.perf_counter() - t0
-    return {"value": nchains / dt, "unit": "chain steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nchains} of the 128 chains, each: the oracle's gradient over all "
+    what = "steps" if nevals == 1 else "trajectories"
+    return {"value": nchains / dt, "unit": f"chain {what}/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nchains} of the 128 chains, each: {nevals} x the oracle's gradient over all "
                       f"{insts[0].m} x {insts[0].n} entries and the update; {dt:.1f} s wall"}
 
 

@@ -224,6 +224,32 @@ sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, i
                         double inv_var, const double* noise, double* force, double* logdet, double* sign,
                         int32_t* status);
 
+/* One hybrid Monte Carlo trajectory of a continuous field per chain, on the
+ * same weight exp(-S) as sdq_langevin (S = inv_var/2 sum phi^2 -
+ * sum_f log|det(1 + B_f)|, Sec. 2), with momenta p and
+ * H = S + 1/2 sum p^2: leapfrog steps
+ *   p -= eps/2 F(phi); then nsteps times { phi += eps p; p -= eps F(phi) }
+ *   with the last kick halved,   F = dS/dphi (the adjoint gradient),
+ * then acceptance when log u < H(start) - H(end); a rejected chain gets its
+ * start field back.  nsteps + 1 gradient evaluations per trajectory.
+ *   inst     host array [count * nf]; flavour f of chain c at c * nf + f, all
+ *            flavours of a chain on the same field array (device, m x n,
+ *            updated in place) with the same n and m; needs expk_inv
+ *   eps > 0, nsteps >= 1, inv_var >= 0
+ *   mom      device: the chains' initial momenta, [m][n] blocks of standard
+ *            normal numbers back to back in chain order
+ *   u        device [count]: uniform numbers in (0, 1)
+ *   logdet, sign  device [count * nf] or NULL: of each chain's field after
+ *            the step (the end field if accepted, else the start field)
+ *   accept   device [count]: 1 accepted, 0 rejected
+ *   dH       device [count] or NULL: H(end) - H(start)
+ *   status   device [count * nf] or NULL: the first nonzero status of the
+ *            trajectory's evaluations; a chain with one rejects
+ * Scratch (gradients, start fields, momenta) is library memory. */
+sdq_status sdq_hmc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
+                   int32_t nsteps, double inv_var, const double* mom, const double* u, double* logdet,
+                   double* sign, int32_t* accept, double* dH, int32_t* status);
+
 /* M <- left * M * right for `count` n x n row-major device matrices: mats is
  * a host array [count] of device pointers (updated in place; the entries
  * must not overlap), left and right are device n x n matrices shared by the

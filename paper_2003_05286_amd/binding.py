@@ -28,7 +28,7 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
-           "sdq_local_sweep", "sdq_langevin")
+           "sdq_local_sweep", "sdq_langevin", "sdq_hmc")
 
 
 class SdqError(RuntimeError):
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_metropolis.argtypes = [vp, P(_Instance), P(_Instance), i32, i32, vp, vp, vp, vp, vp, vp]
     L.sdq_local_sweep.argtypes = [vp, P(_Instance), i32, i32, vp, vp, vp]
     L.sdq_langevin.argtypes = [vp, P(_Instance), i32, i32, dbl, dbl, vp, vp, vp, vp, vp]
+    L.sdq_hmc.argtypes = [vp, P(_Instance), i32, i32, dbl, i32, dbl, vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -283,6 +284,29 @@ class Context:
                                         _ptr(frc) if frc is not None else None, _ptr(ld), _ptr(sg),
                                         _ptr(st)))
         return frc, ld, sg, st
+
+    def hmc(self, chains, nf, eps, nsteps, inv_var, mom, u):
+        """One hybrid Monte Carlo trajectory per chain (sdq_hmc): chains =
+        count * nf Chains (flavours of a chain consecutive, sharing its field
+        tensor, updated in place); mom: device [count, m, n] standard normals;
+        u: device [count] uniforms.  Returns (accept [count] int32, dH
+        [count], logdet [count * nf], sign [count * nf], status [count * nf]
+        int32), logdet and sign of the field the chain ends on."""
+        total = len(chains)
+        if nf < 1 or total % nf:
+            raise ValueError("chains must hold count * nf entries")
+        count = total // nf
+        c0 = chains[0]
+        _check_tensor(mom, "mom", (count, c0.m, c0.n), self.tdev)
+        _check_tensor(u, "u", (count,), self.tdev)
+        inst = self._instances(chains, need_inv=True)
+        acc = torch.empty(count, dtype=torch.int32, device=self.tdev)
+        dh = self._empty(count)
+        ld, sg = self._empty(total), self._empty(total)
+        st = torch.empty(total, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_hmc(self.h, inst, count, nf, float(eps), int(nsteps), float(inv_var), _ptr(mom),
+                                   _ptr(u), _ptr(ld), _ptr(sg), _ptr(acc), _ptr(dh), _ptr(st)))
+        return acc, dh, ld, sg, st
 
     def local_sweep(self, chains, nf, unif):
         """One sweep of local updates (sdq_local_sweep): chains = count * nf

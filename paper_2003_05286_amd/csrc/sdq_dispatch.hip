@@ -169,6 +169,110 @@ hipError_t launch_langevin(int count, int nf, const LangevinChain* chains, doubl
   hipLaunchKernelGGL(k_langevin, dim3(grid_per_chain, count), dim3(256), 0, s, nf, chains, eps, inv_var);
   return hipGetLastError();
 }
+// sum over the workgroup of one double per thread (256 threads), in a fixed
+// order; every thread gets the total
+__device__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double t = red[0];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_hmc_begin(const HmcChain* __restrict__ chains, double inv_var,
+                                                    double* e0) {
+  __shared__ double red[256];
+  const HmcChain C = chains[blockIdx.x];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < C.len; t += 256) {
+    const double phi = C.phi[t], p = C.mom[t];
+    C.phi0[t] = phi;
+    C.p[t] = p;
+    acc += 0.5 * inv_var * phi * phi + 0.5 * p * p;
+  }
+  const double e = block_sum256(acc, red);
+  if (threadIdx.x == 0) e0[blockIdx.x] = e;
+}
+hipError_t launch_hmc_begin(int count, const HmcChain* chains, double inv_var, double* e0, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hmc_begin, dim3(count), dim3(256), 0, s, chains, inv_var, e0);
+  return hipGetLastError();
+}
+
+// each thread owns its entries: the force reads phi before the drift writes it
+__global__ void k_hmc_step(int nf, const HmcChain* __restrict__ chains, double kick, double eps,
+                           double inv_var) {
+  const HmcChain C = chains[blockIdx.y];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < C.len;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double phi = C.phi[t];
+    double f = inv_var * phi;
+    for (int g = 0; g < nf; ++g) f -= C.grad[(int64_t)g * C.len + t];
+    const double p = C.p[t] - kick * f;
+    C.p[t] = p;
+    C.phi[t] = phi + eps * p;
+  }
+}
+hipError_t launch_hmc_step(int count, int nf, const HmcChain* chains, double kick, double eps, double inv_var,
+                           int grid_per_chain, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hmc_step, dim3(grid_per_chain, count), dim3(256), 0, s, nf, chains, kick, eps, inv_var);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_hmc_end(int nf, int total, const HmcChain* __restrict__ chains,
+                                                  double half_kick, double inv_var, HmcEnd a) {
+  __shared__ double red[256];
+  __shared__ int acc_s;
+  const int c = blockIdx.x;
+  const HmcChain C = chains[c];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < C.len; t += 256) {
+    const double phi = C.phi[t];
+    double f = inv_var * phi;
+    for (int g = 0; g < nf; ++g) f -= C.grad[(int64_t)g * C.len + t];
+    const double p = C.p[t] - half_kick * f;
+    acc += 0.5 * inv_var * phi * phi + 0.5 * p * p;
+  }
+  const double e1 = block_sum256(acc, red);
+  if (threadIdx.x == 0) {
+    double h0 = a.e0[c], h1 = e1;
+    bool ok = true;
+    for (int g = 0; g < nf; ++g) {
+      const int i = c * nf + g;
+      h0 -= a.ld0[i];
+      h1 -= a.ld1[i];
+      int32_t st = 0;
+      for (int e = 0; e < a.n_eval; ++e) st = st ? st : a.st_all[(int64_t)e * total + i];
+      ok = ok && st == 0;
+      if (a.status) a.status[i] = st;
+    }
+    ok = ok && isfinite(h1);
+    const int take = (ok && log(a.u[c]) < h0 - h1) ? 1 : 0;
+    acc_s = take;
+    a.accept[c] = take;
+    if (a.dH) a.dH[c] = h1 - h0;
+    for (int g = 0; g < nf; ++g) {
+      const int i = c * nf + g;
+      if (a.logdet) a.logdet[i] = take ? a.ld1[i] : a.ld0[i];
+      if (a.sign) a.sign[i] = take ? a.sg1[i] : a.sg0[i];
+    }
+  }
+  __syncthreads();
+  if (acc_s) return;
+  for (int64_t t = threadIdx.x; t < C.len; t += 256) C.phi[t] = C.phi0[t];
+}
+hipError_t launch_hmc_end(int count, int nf, const HmcChain* chains, double half_kick, double inv_var,
+                          const HmcEnd& a, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hmc_end, dim3(count), dim3(256), 0, s, nf, count * nf, chains, half_kick, inv_var, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(Queue* q, int nq, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset, dim3((nq + 63) / 64), dim3(64), 0, s, q, nq);

@@ -134,6 +134,43 @@ struct LangevinChain {
 // others keep their field); grid-stride over the chains' entries.
 hipError_t launch_langevin(int count, int nf, const LangevinChain* chains, double eps, double inv_var,
                            int grid_per_chain, hipStream_t s);
+// One chain of a hybrid Monte Carlo trajectory: its field (in place), the
+// saved start field, the momenta (scratch) and the initial momenta (input),
+// the gradients of its nf flavours (consecutive, len apart), len = m * n.
+struct HmcChain {
+  double* phi;
+  double* phi0;
+  double* p;
+  const double* mom;
+  const double* grad;
+  int64_t len;
+};
+// Start of a trajectory: phi0 = phi, p = mom, e0[c] = inv_var/2 |phi|^2 +
+// 1/2 |p|^2; one workgroup per chain (fixed reduction order).
+hipError_t launch_hmc_begin(int count, const HmcChain* chains, double inv_var, double* e0, hipStream_t s);
+// Kick and drift: p -= kick F(phi), phi += eps p, F = inv_var phi - sum_f grad_f.
+hipError_t launch_hmc_step(int count, int nf, const HmcChain* chains, double kick, double eps, double inv_var,
+                           int grid_per_chain, hipStream_t s);
+// End of a trajectory: the last half kick, e1 = inv_var/2 |phi|^2 + 1/2 |p|^2,
+// H = e - sum_f log|det|, the Metropolis test on exp(-(H1 - H0)) (status of
+// every evaluation zero), outputs, and phi <- phi0 on rejection.
+struct HmcEnd {
+  const double* e0;
+  const double* ld0;
+  const double* sg0;
+  const double* ld1;
+  const double* sg1;
+  const int32_t* st_all;  // [n_eval][count * nf]
+  int n_eval;
+  const double* u;
+  double* logdet;  // or null
+  double* sign;    // or null
+  int32_t* accept;
+  double* dH;        // or null
+  int32_t* status;   // or null
+};
+hipError_t launch_hmc_end(int count, int nf, const HmcChain* chains, double half_kick, double inv_var,
+                          const HmcEnd& a, hipStream_t s);
 // Copy the n x n row-major matrix e (or its transpose) into the MFMA
 // A-operand order used by the kernels: for NT = ceil(n/16), block
 // b = (ti*NT + tk)*4 + r holds at position l the entry

@@ -83,6 +83,8 @@ struct sdq_ctx {
   DevBuf d_gloc;   // sdq_local_sweep: G at the block start, n x n per instance
   DevBuf d_lgrad;  // sdq_langevin: gradients of every instance, then statuses
   DevBuf d_ltab;   // sdq_langevin: chain table
+  DevBuf d_hmc;    // sdq_hmc: gradients, start fields, momenta, energies, statuses
+  DevBuf d_htab;   // sdq_hmc: chain table
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   // pinned staging of plan images, a ring: the host waits for the plan
   // kStageSlots back, not the previous one, so it builds and enqueues the
@@ -680,6 +682,8 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_gloc.p) (void)hipFree(ctx->d_gloc.p);
   if (ctx->d_lgrad.p) (void)hipFree(ctx->d_lgrad.p);
   if (ctx->d_ltab.p) (void)hipFree(ctx->d_ltab.p);
+  if (ctx->d_hmc.p) (void)hipFree(ctx->d_hmc.p);
+  if (ctx->d_htab.p) (void)hipFree(ctx->d_htab.p);
   for (auto& sl : ctx->stage)
     if (sl.h) (void)hipHostFree(sl.h);
   for (auto& kv : ctx->stats)
@@ -1177,6 +1181,108 @@ sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, i
     if (st) return st;
   }
   return SDQ_OK;
+}
+
+sdq_status sdq_hmc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
+                   int32_t nsteps, double inv_var, const double* mom, const double* u, double* logdet,
+                   double* sign, int32_t* accept, double* dH, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
+  if (count == 0) return SDQ_OK;
+  if (!mom || !u || !accept) return fail(ctx, SDQ_EINVAL, "null pointer");
+  if (!(eps > 0.0) || !std::isfinite(eps) || !(inv_var >= 0.0) || !std::isfinite(inv_var) || nsteps < 1)
+    return fail(ctx, SDQ_EINVAL, "need eps > 0, nsteps >= 1 and a finite inv_var >= 0");
+  const int total = count * nf;
+  sdq_status st = validate(ctx, inst, total, true);
+  if (st) return st;
+  for (int c = 0; c < count; ++c) {
+    const sdq_instance& a = inst[c * nf];
+    for (int f = 1; f < nf; ++f) {
+      const sdq_instance& b = inst[c * nf + f];
+      if (b.field != a.field || b.n != a.n || b.m != a.m)
+        return fail(ctx, SDQ_EINVAL, "the flavours of a chain must share field, n and m");
+    }
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  // scratch: gradients [total] | start fields [count] | momenta [count] |
+  // e0 [count] | ld0, sg0, ld1, sg1 [total] | statuses [nsteps + 1][total]
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t gl = 0, cl = 0;
+  int64_t lmax = 0;
+  for (int i = 0; i < total; ++i) gl += (size_t)inst[i].m * inst[i].n;
+  for (int c = 0; c < count; ++c) {
+    const int64_t len = (int64_t)inst[c * nf].m * inst[c * nf].n;
+    cl += (size_t)len;
+    lmax = std::max(lmax, len);
+  }
+  const int n_eval = nsteps + 1;
+  const size_t o_phi0 = al(gl * sizeof(double));
+  const size_t o_p = o_phi0 + al(cl * sizeof(double));
+  const size_t o_e0 = o_p + al(cl * sizeof(double));
+  const size_t o_ld = o_e0 + al((size_t)count * sizeof(double));
+  const size_t o_st = o_ld + 4 * al((size_t)total * sizeof(double));
+  const size_t bytes = o_st + (size_t)n_eval * total * sizeof(int32_t);
+  HIP_TRY(grow(ctx->d_hmc, bytes), "hipMalloc(hmc)");
+  char* base = (char*)ctx->d_hmc.p;
+  std::vector<double*> gp(total);
+  {
+    double* g = (double*)base;
+    for (int i = 0; i < total; ++i) {
+      gp[i] = g;
+      g += (size_t)inst[i].m * inst[i].n;
+    }
+  }
+  double* e0 = (double*)(base + o_e0);
+  double* ld0 = (double*)(base + o_ld);
+  double* sg0 = (double*)(base + o_ld + al((size_t)total * sizeof(double)));
+  double* ld1 = (double*)(base + o_ld + 2 * al((size_t)total * sizeof(double)));
+  double* sg1 = (double*)(base + o_ld + 3 * al((size_t)total * sizeof(double)));
+  int32_t* st_all = (int32_t*)(base + o_st);
+  std::vector<sdq::HmcChain> tab(count);
+  {
+    double* phi0 = (double*)(base + o_phi0);
+    double* pm = (double*)(base + o_p);
+    size_t off = 0;
+    for (int c = 0; c < count; ++c) {
+      const sdq_instance& a = inst[c * nf];
+      const int64_t len = (int64_t)a.m * a.n;
+      tab[c] = sdq::HmcChain{const_cast<double*>(a.field), phi0 + off, pm + off, mom + off, gp[c * nf], len};
+      off += (size_t)len;
+    }
+  }
+  HIP_TRY(grow(ctx->d_htab, (size_t)count * sizeof(sdq::HmcChain)), "hipMalloc(hmc table)");
+  // stream-ordered after the previous trajectory's kernels read the table;
+  // the source is pageable, so it may be reused once this returns
+  HIP_TRY(hipMemcpyAsync(ctx->d_htab.p, tab.data(), (size_t)count * sizeof(sdq::HmcChain),
+                         hipMemcpyHostToDevice, ctx->stream),
+          "hipMemcpyAsync(hmc table)");
+  const auto* d_tab = (const sdq::HmcChain*)ctx->d_htab.p;
+  const int per = (int)std::max<int64_t>(1, std::min<int64_t>((lmax + 255) / 256,
+                                                               (4LL * ctx->num_cu + count - 1) / count));
+  ctx->err.clear();
+  st = timed(ctx, "hmc", [&] { return sdq::launch_hmc_begin(count, d_tab, inv_var, e0, ctx->stream); });
+  if (st) return st;
+  // leapfrog: half kick, then (drift, kick) nsteps times with the last kick
+  // halved; the force needs the gradient at every field on the way
+  for (int e = 0; e < n_eval; ++e) {
+    const bool first = e == 0, last = e == nsteps;
+    st = sdq_logdet_grad(ctx, 0, inst, total, gp.data(), first ? ld0 : last ? ld1 : nullptr,
+                         first ? sg0 : last ? sg1 : nullptr, st_all + (size_t)e * total);
+    if (st) return st;
+    if (last) break;
+    const double kick = first ? 0.5 * eps : eps;
+    for (int c0 = 0; c0 < count; c0 += 65535) {
+      const int cn = std::min(count - c0, 65535);
+      st = timed(ctx, "hmc", [&] {
+        return sdq::launch_hmc_step(cn, nf, d_tab + c0, kick, eps, inv_var, per, ctx->stream);
+      });
+      if (st) return st;
+    }
+  }
+  sdq::HmcEnd a{e0, ld0, sg0, ld1, sg1, st_all, n_eval, u, logdet, sign, accept, dH, status};
+  return timed(ctx, "hmc", [&] {
+    return sdq::launch_hmc_end(count, nf, d_tab, 0.5 * eps, inv_var, a, ctx->stream);
+  });
 }
 
 sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,

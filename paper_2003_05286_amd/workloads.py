@@ -195,6 +195,11 @@ def workload(name: str, scale: float = 1.0) -> Workload:
         return Workload(name, hubbard_continuous(8, 20.0, nb(128), seed=BASE_SEED + 3),
                         notes="L=8, beta=20, M=200, continuous phi ~ N(0,1) at the start, g=1, k=10; "
                               "one Langevin step of every chain per step")
+    if name == "hubbard_L8_b20_phi_hmc128":
+        return Workload(name, hubbard_continuous(8, 20.0, nb(128), seed=BASE_SEED + 3),
+                        notes="L=8, beta=20, M=200, continuous phi ~ N(0,1) at the start, g=1, k=10; "
+                              "one hybrid Monte Carlo trajectory (10 leapfrog steps of 0.05) per chain "
+                              "per step")
     if name == "hubbard_L16_b40_batch128":
         return Workload(name, hubbard_ising(16, 40.0, nb(64), 2, seed=BASE_SEED + 4),
                         l_list=list(range(1, 401)),
