@@ -50,6 +50,9 @@ def lib():
         L.or_chain.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, c_int, c_int, d, d, d]
         L.or_greens_sym.argtypes = [c_int, c_int, c_int, d, d, c_double, d, d, d]
         L.or_greens_tdisp_sym.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, d]
+        L.or_greens_stab.argtypes = [c_int, c_int, c_int, d, d, c_double, c_int, c_int, d, d, d]
+        L.or_greens_tdisp_stab.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, c_int, c_int, d]
+        L.or_svd.argtypes = [c_int, d, d, d, d]
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
@@ -157,6 +160,39 @@ def chain(expk, expk_inv, field, alpha, k, kind, a, b):
     _chk(lib().or_chain(n, m, k, _p(expk), _p(expk_inv), _p(field), float(alpha), kind, a, b,
                         _p(U), _p(D), _p(T)))
     return U, D, T
+
+
+STAB_QR, STAB_SVD = 0, 1
+
+
+def greens_stab(expk, field, alpha, k, stab, scheme=SCHEME_LOH):
+    """greens() with the stabilizer chosen: STAB_QR or STAB_SVD (Jacobi)."""
+    expk, field = _c(expk), _c(field)
+    m, n = field.shape
+    G = np.zeros((n, n))
+    ld, sg = np.zeros(1), np.zeros(1)
+    _chk(lib().or_greens_stab(n, m, k, _p(expk), _p(field), float(alpha), scheme, stab, _p(G), _p(ld),
+                              _p(sg)))
+    return G, float(ld[0]), float(sg[0])
+
+
+def greens_tdisp_stab(expk, expk_inv, field, alpha, k, l, stab, scheme=SCHEME_LOH):
+    """greens_tdisp() with the stabilizer chosen."""
+    expk, expk_inv, field = _c(expk), _c(expk_inv), _c(field)
+    m, n = field.shape
+    G = np.zeros((n, n))
+    _chk(lib().or_greens_tdisp_stab(n, m, k, _p(expk), _p(expk_inv), _p(field), float(alpha),
+                                    int(l), scheme, stab, _p(G)))
+    return G
+
+
+def svd(W):
+    """One-sided Jacobi SVD: W = U diag(s) V^T (s unsorted); returns U, s, V, sweeps."""
+    W = _c(W)
+    n = W.shape[0]
+    U, V, sv = np.zeros((n, n)), np.zeros((n, n)), np.zeros(n)
+    sweeps = lib().or_svd(n, _p(W), _p(U), _p(sv), _p(V))
+    return U, sv, V, sweeps
 
 
 def cpqr(A):

@@ -32,9 +32,13 @@
  *   or_logdet_grad     d log|det(1+B_M..B_1)| / d f_{l,i} = alpha (1-G_l)_ii
  *                      (Jacobi's formula; see the function comment)
  *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
+ *   jacobi_svd,        Sec. 4.2 (the Jacobi SVD the paper compares with the
+ *   or_greens_stab     QR; one-sided, Hestenes), as an independent stabilizer
+ *                      of the same chain: a cross-check of the QR path
  * Readings of passages that are ambiguous or garbled in the paper are noted
  * where they are used.
  */
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -246,6 +250,70 @@ static void udt(int n, const double* W, double* U, double* D, double* T) {
   free(jpvt);
 }
 
+/* One-sided Jacobi SVD (Hestenes; the stabilizer the paper compares with
+ * the QR decomposition in Sec. 4.2 and finds accurate with either inversion
+ * scheme): column pairs (p, q) of A are rotated, in cyclic order p < q,
+ * until every pair is orthogonal to working accuracy,
+ * |a_p . a_q| <= n eps ||a_p|| ||a_q||.  Then A_in V = A_out with V the
+ * product of the rotations, the columns of A_out have norms sigma_j, and
+ * A_in = U diag(sigma) V^T with U = A_out diag(1/sigma).  The rotation that
+ * makes a pair orthogonal:  zeta = (a_q.a_q - a_p.a_p) / (2 a_p.a_q),
+ * t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
+ * a_p <- c a_p - s a_q, a_q <- s a_p + c a_q.  Returns the number of sweeps,
+ * or -1 without convergence in 60 sweeps.  Row-major n x n A and V. */
+static int jacobi_svd(int n, double* A, double* V) {
+  const double tol = n * DBL_EPSILON;
+  mat_eye(n, V);
+  for (int sweep = 1; sweep <= 60; ++sweep) {
+    int rotated = 0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const double x = A[(size_t)i * n + p], y = A[(size_t)i * n + q];
+          app += x * x;
+          aqq += y * y;
+          apq += x * y;
+        }
+        if (app == 0.0 || aqq == 0.0) continue;
+        if (fabs(apq) <= tol * sqrt(app) * sqrt(aqq)) continue;
+        rotated = 1;
+        const double zeta = (aqq - app) / (2.0 * apq);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < n; ++i) {
+          double* a = A + (size_t)i * n;
+          const double x = a[p], y = a[q];
+          a[p] = c * x - sn * y;
+          a[q] = sn * x + c * y;
+          double* v = V + (size_t)i * n;
+          const double vx = v[p], vy = v[q];
+          v[p] = c * vx - sn * vy;
+          v[q] = sn * vx + c * vy;
+        }
+      }
+    if (!rotated) return sweep;
+  }
+  return -1;
+}
+
+/* UDT by the SVD: W = U diag(D) T with D = sigma (unsorted), T = V^T. */
+static int udt_svd(int n, const double* W, double* U, double* D, double* T) {
+  double* A = mat_new(n);
+  double* V = mat_new(n);
+  mat_copy(n, W, A);
+  const int sweeps = jacobi_svd(n, A, V);
+  for (int j = 0; j < n; ++j) {
+    D[j] = nrm2(n, A + j, n);
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + j] = D[j] > 0.0 ? A[(size_t)i * n + j] / D[j] : 0.0;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T[(size_t)i * n + j] = V[(size_t)j * n + i];
+  free(A);
+  free(V);
+  return sweeps;
+}
+
 /* Inverse with log|det| and sign of det via Gaussian elimination with
  * partial pivoting (Gauss-Jordan on [A | I]). */
 static void lu_inverse(int n, const double* A, double* Ainv, double* logabsdet, double* sgn) {
@@ -329,6 +397,7 @@ typedef struct {
   const double* field;
   double alpha;
   int sym;                 /* 1: the symmetric Trotter slice H diag(v) H (Sec. 2) */
+  int svd;                 /* 1: stabilize with the Jacobi SVD instead of the QR */
 } problem;
 
 enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4 };
@@ -385,7 +454,10 @@ static void chain_udt(const problem* P, int kind, const int* order, int count,
     mat_copy(n, U, W);
     for (int s = pos; s < end; ++s) apply_slice(P, kind, order[s], W, tmp);
     scale_cols(n, W, D);
-    udt(n, W, U, D, Tp);
+    if (P->svd)
+      udt_svd(n, W, U, D, Tp);
+    else
+      udt(n, W, U, D, Tp);
     mat_mul(n, Tp, T, T2);
     mat_copy(n, T2, T);
     pos = end;
@@ -716,6 +788,54 @@ int or_chain(int n, int m, int k, const double* expk, const double* expk_inv,
 
 /* Pivoted QR exposed for the tests: A (row-major n x n) is overwritten with
  * R in the upper triangle; Q and jpvt returned. */
+/* or_greens and or_greens_tdisp with the stabilizer chosen: stab = 0 the
+ * pivoted QR, 1 the one-sided Jacobi SVD. */
+int or_greens_stab(int n, int m, int k, const double* expk, const double* field, double alpha,
+                   int scheme, int stab, double* G, double* logdet, double* sign) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  problem P = {n, m, k, expk, NULL, field, alpha, 0, stab};
+  double* U = mat_new(n);
+  double* T = mat_new(n);
+  double* D = (double*)malloc(sizeof(double) * n);
+  chain_fwd(&P, 1, m, U, D, T);
+  if (scheme == OR_SCHEME_PLAIN)
+    inv_one_plus(n, U, D, T, G, logdet, sign);
+  else
+    inv_one_plus_loh(n, U, D, T, G, logdet, sign);
+  free(U); free(T); free(D);
+  return finite_all(n, G) ? OR_OK : OR_ERANGE;
+}
+
+int or_greens_tdisp_stab(int n, int m, int k, const double* expk, const double* expk_inv,
+                         const double* field, double alpha, int l, int scheme, int stab, double* Gt) {
+  int st = check(n, m, k, expk, field);
+  if (st) return st;
+  if (!expk_inv || l < 0 || l > m) return OR_EINVAL;
+  problem P = {n, m, k, expk, expk_inv, field, alpha, 0, stab};
+  double *UL = mat_new(n), *XL = mat_new(n), *UR = mat_new(n), *XR = mat_new(n);
+  double *DL = malloc(sizeof(double) * n), *DR = malloc(sizeof(double) * n);
+  chain_inv(&P, 1, l, UL, DL, XL);
+  chain_fwd(&P, l + 1, m, UR, DR, XR);
+  if (scheme == OR_SCHEME_PLAIN)
+    inv_sum(n, UL, DL, XL, UR, DR, XR, Gt);
+  else
+    inv_sum_loh(n, UL, DL, XL, UR, DR, XR, Gt);
+  free(UL); free(XL); free(UR); free(XR); free(DL); free(DR);
+  return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
+}
+
+/* The Jacobi SVD of one matrix: W = U diag(s) V^T (s unsorted); returns the
+ * number of sweeps (-1: no convergence). */
+int or_svd(int n, const double* W, double* U, double* s, double* V) {
+  double* T = mat_new(n);
+  const int sweeps = udt_svd(n, W, U, s, T);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[(size_t)i * n + j] = T[(size_t)j * n + i];
+  free(T);
+  return sweeps;
+}
+
 int or_cpqr(int n, double* A, double* Q, int* jpvt) {
   double* tau = (double*)malloc(sizeof(double) * n);
   cpqr(n, A, jpvt, tau);

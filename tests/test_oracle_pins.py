@@ -449,3 +449,44 @@ def test_symmetric_slices_same_gradient():
         fm[l - 1, i] -= h
         d = (oracle.greens_sym(H, fp, I.alpha, I.k)[1] - oracle.greens_sym(H, fm, I.alpha, I.k)[1]) / (2 * h)
         assert abs(d - grad[a, i]) <= 1e-7 * max(1.0, abs(grad[a, i])), (l, i, d, grad[a, i])
+
+
+# ---------------------------------------------------------------------------
+# An independent stabilizer: the one-sided Jacobi SVD (the decomposition the
+# paper compares with the QR in Sec. 4.2 and 5.2).  The QR-stabilized chain
+# and the SVD-stabilized chain share only the slice products and the
+# inversion formulas; their G, G(tau,0), log det and sign must agree.
+
+def test_jacobi_svd_factors():
+    rng = np.random.default_rng(5)
+    W = rng.normal(size=(24, 24))
+    U, s, V, sweeps = oracle.svd(W)
+    assert 0 < sweeps <= 20
+    assert np.abs(U @ np.diag(s) @ V.T - W).max() <= 1e-13 * np.abs(W).max()
+    assert np.abs(U.T @ U - np.eye(24)).max() <= 1e-13
+    assert np.abs(V.T @ V - np.eye(24)).max() <= 1e-13
+    assert np.allclose(np.sort(s)[::-1], np.linalg.svd(W, compute_uv=False), rtol=1e-13, atol=0)
+    # graded columns (the shape of B U D in the chain): the factors still
+    # reproduce every column to its own scale
+    d = 10.0 ** np.linspace(-90, 90, 24)
+    Wg = rng.normal(size=(24, 24)) * d
+    U, s, V, sweeps = oracle.svd(Wg)
+    assert sweeps > 0
+    col_err = np.abs(U @ np.diag(s) @ V.T - Wg).max(axis=0) / np.abs(Wg).max(axis=0)
+    assert col_err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("L,beta", [(4, 10.0), (4, 40.0), (6, 20.0)])
+def test_svd_stabilized_chain_agrees_with_qr(L, beta):
+    E, Ei = wl.expk_pair(wl.hopping_matrix(L), 0.1)
+    lam = wl.hirsch_lambda(4.0, 0.1)
+    m = int(round(beta / 0.1))
+    f = 2.0 * np.random.default_rng(L * 100 + int(beta)).integers(0, 2, (m, L * L)) - 1.0
+    Gq, lq, sq = oracle.greens(E, f, lam, 10)
+    Gs, ls, ss = oracle.greens_stab(E, f, lam, 10, oracle.STAB_SVD)
+    assert relF(Gs, Gq) <= 1e-10
+    assert abs(ls - lq) <= 1e-10 * abs(lq) and ss == sq
+    for l in (10, m // 2, m - 10):
+        Aq = oracle.greens_tdisp(E, Ei, f, lam, 10, l)
+        As = oracle.greens_tdisp_stab(E, Ei, f, lam, 10, l, oracle.STAB_SVD)
+        assert relF(As, Aq) <= 1e-10
