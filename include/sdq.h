@@ -69,6 +69,13 @@ typedef enum {
                         (SDQ_EUNSUPPORTED above).                                 */
 } sdq_scheme;
 
+/* Decomposition that stabilizes the slice products every k slices (Sec. 4.2). */
+typedef enum {
+  SDQ_STAB_QR = 0,  /* column-pivoted Householder QR (default)                    */
+  SDQ_STAB_SVD = 1  /* one-sided Jacobi SVD: slower, an independent cross-check;
+                       n <= 80 (SDQ_EUNSUPPORTED above)                             */
+} sdq_stab;
+
 typedef struct sdq_ctx sdq_ctx;
 
 /* One Markov chain / spin flavour.  B_l = expk * diag(exp(alpha * field[l-1][:])). */
@@ -249,6 +256,15 @@ sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, i
 sdq_status sdq_hmc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
                    int32_t nsteps, double inv_var, const double* mom, const double* u, double* logdet,
                    double* sign, int32_t* accept, double* dH, int32_t* status);
+
+/* Choose the stabilizer of every later sweep of ctx (sdq_stab, Sec. 4.2):
+ * the pivoted QR (default) or the one-sided Jacobi SVD, whose UDT is
+ * U = A diag(1/sigma), D = sigma, T = V^T T_previous (A = W V with
+ * orthogonal columns, sigma their norms; at most 60 Jacobi sweeps per
+ * decomposition, SDQ_ERANGE in status without convergence).  Every result
+ * (G, G(tau,0), log|det|, sign, gradient) is the same up to rounding; the
+ * SVD takes several times as long.  Returns SDQ_EINVAL for another value. */
+sdq_status sdq_set_stabilizer(sdq_ctx* ctx, int32_t stab);
 
 /* M <- left * M * right for `count` n x n row-major device matrices: mats is
  * a host array [count] of device pointers (updated in place; the entries

@@ -22,13 +22,14 @@ LIB_PATH = os.path.join(PKG, "libsdq.so")
 
 SDQ_OK, SDQ_EINVAL, SDQ_ENOMEM, SDQ_EHIP, SDQ_ERANGE, SDQ_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SCHEME_LOH, SCHEME_PLAIN = 0, 1
+STAB_QR, STAB_SVD = 0, 1
 
 # every symbol include/sdq.h declares
 EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_greens",
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
-           "sdq_local_sweep", "sdq_langevin", "sdq_hmc")
+           "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer")
 
 
 class SdqError(RuntimeError):
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_local_sweep.argtypes = [vp, P(_Instance), i32, i32, vp, vp, vp]
     L.sdq_langevin.argtypes = [vp, P(_Instance), i32, i32, dbl, dbl, vp, vp, vp, vp, vp]
     L.sdq_hmc.argtypes = [vp, P(_Instance), i32, i32, dbl, i32, dbl, vp, vp, vp, vp, vp, vp, vp]
+    L.sdq_set_stabilizer.argtypes = [vp, i32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -262,6 +264,10 @@ class Context:
         self._chk(self.lib.sdq_metropolis(self.h, ci, pi, count, nf, _ptr(dS), _ptr(u), _ptr(logdet),
                                           _ptr(sign), _ptr(acc), _ptr(st)))
         return acc, st
+
+    def set_stabilizer(self, stab):
+        """STAB_QR (default) or STAB_SVD for every later sweep (sdq_set_stabilizer)."""
+        self._chk(self.lib.sdq_set_stabilizer(self.h, int(stab)))
 
     def langevin(self, chains, nf, eps, inv_var, noise, force=True):
         """One Langevin step (sdq_langevin): chains = count * nf Chains

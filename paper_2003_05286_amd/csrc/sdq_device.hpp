@@ -993,10 +993,130 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
 //   SW_LEFT:   B_1^{-1} ... B_{tau_j}^{-1}: W <- B_q^{-1} W for q = tau_j
 //              down to 1, B_q^{-1} = diag(exp(-alpha f_q)) expk^{-1}, folded
 //              in every k slices counted from tau_j.
-template <int NT, int P, bool ELDS>
+// UDT of W by the one-sided Jacobi SVD (Hestenes), the stabilizer the paper
+// compares with the QR (Sec. 4.2): column pairs (p, q) of A = W are rotated
+// until every pair is orthogonal to working accuracy,
+// |a_p . a_q| <= n eps ||a_p|| ||a_q||, with the rotation
+//   zeta = (a_q.a_q - a_p.a_p) / (2 a_p.a_q),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1 / sqrt(1 + t^2),  s = c t,  a_p <- c a_p - s a_q,  a_q <- s a_p + c a_q,
+// and the same rotation applied to rows p, q of T (T <- V^T T).  Then
+// D = column norms (S.dnew), U = A D^{-1} (into W).  A sits in S.R by column,
+// T in S.E by row; the pairs of a round follow the circle method over the
+// NP columns (each column in one pair per round, NP - 1 rounds per sweep),
+// one pair per group of 8 lanes, one barrier per round; at most 60 sweeps.
+// det U = +1: every slice has a positive determinant and the rotations have
+// determinant one, so the sign of det W (that of the previous U) carries
+// over.  Returns 0, or 1 without convergence.
+template <int NT, int P>
+__device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT, P>& W, RM<NT, P>& T) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  constexpr int GS = 8;                      // lanes per column pair
+  constexpr int NG = G::THREADS / GS;        // pair groups
+  constexpr int RPL = G::NP / GS;            // rows (of A) / columns (of T) per lane
+  const int grp = L.t / GS, gl = L.t % GS;
+  const double tol = n * 2.220446049250313e-16;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        S.R[col * G::LDR + row] = W.v[c][ti][r];
+        S.E[row * G::LDR + col] = T.v[c][ti][r];
+      }
+  }
+  int failed = 1;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (L.t == 0) S.ired[0] = 0;
+    __syncthreads();
+    for (int rd = 0; rd < G::NP - 1; ++rd) {
+      for (int pk = grp; pk < G::NP / 2; pk += NG) {
+        int p = pk == 0 ? G::NP - 1 : (rd + pk) % (G::NP - 1);
+        int q = pk == 0 ? rd : (rd - pk + G::NP - 1) % (G::NP - 1);
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        if (q >= n) continue;  // padding columns are zero
+        double* ap = &S.R[p * G::LDR];
+        double* aq = &S.R[q * G::LDR];
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const double x = ap[gl + GS * i], y = aq[gl + GS * i];
+          app = fma(x, x, app);
+          aqq = fma(y, y, aqq);
+          apq = fma(x, y, apq);
+        }
+#pragma unroll
+        for (int o = 1; o < GS; o <<= 1) {
+          app += __shfl_xor(app, o);
+          aqq += __shfl_xor(aqq, o);
+          apq += __shfl_xor(apq, o);
+        }
+        if (app == 0.0 || aqq == 0.0 || fabs(apq) <= tol * sqrt(app) * sqrt(aqq)) continue;
+        const double zeta = (aqq - app) / (2.0 * apq);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        double* tp = &S.E[p * G::LDR];
+        double* tq = &S.E[q * G::LDR];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int e = gl + GS * i;
+          const double x = ap[e], y = aq[e];
+          ap[e] = cs * x - sn * y;
+          aq[e] = sn * x + cs * y;
+          const double u = tp[e], v = tq[e];
+          tp[e] = cs * u - sn * v;
+          tq[e] = sn * u + cs * v;
+        }
+        if (gl == 0) S.ired[0] = 1;
+      }
+      __syncthreads();
+    }
+    const int rotated = S.ired[0];
+    __syncthreads();
+    if (!rotated) {
+      failed = 0;
+      break;
+    }
+  }
+  // D = column norms, U = A D^{-1}, T back to registers (padding: identity)
+  for (int t = L.t; t < G::NP; t += G::THREADS) {
+    double ss = 0.0;
+    if (t < n)
+      for (int i = 0; i < G::NP; ++i) ss = fma(S.R[t * G::LDR + i], S.R[t * G::LDR + i], ss);
+    S.dnew[t] = t < n ? sqrt(ss) : 1.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        const bool ok = tile_ok<NT, P>(L, c);
+        W.v[c][ti][r] = (ok && col < n) ? S.R[col * G::LDR + row] / S.dnew[col] : (row == col ? 1.0 : 0.0);
+        T.v[c][ti][r] = ok ? S.E[row * G::LDR + col] : (row == col ? 1.0 : 0.0);
+      }
+  }
+  return failed;
+}
+
+template <int NT, int P, bool ELDS, bool SVD = false>
 __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
                           const int jpair) {
   using G = Geo<NT, P>;
+  // the SVD stabilizer keeps T in S.E, so E is read from its global copy
+  constexpr bool EST = ELDS && !SVD;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const bool left = (flags & SW_LEFT) != 0, right = (flags & SW_RIGHT) != 0;
@@ -1007,7 +1127,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   const int s_lo = (right || block) ? jpair : 0;
   const int s_hi = left ? (tauj + k - 1) / k : (block ? jpair + 1 : nb);
   const double* e_op = left ? I.eswi : (adj ? I.eswt : I.esw);
-  stage_e<NT, P, ELDS>(L, S, e_op);
+  if constexpr (EST) stage_e<NT, P, ELDS>(L, S, e_op);
   // W holds U between blocks and the block product inside a block
   RM<NT, P> T, W;
   double dcol[CT];
@@ -1027,7 +1147,8 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
 #pragma unroll
     for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
   }
-  const EOp<NT, P, ELDS> eop{S.E, e_op, L.l};
+  const EOp<NT, P, EST> eop{S.E, e_op, L.l};
+  int svd_failed = 0;
 
   for (int s = s_lo; s < s_hi; ++s) {
     const int b = adj ? nb - 1 - s : s;
@@ -1058,11 +1179,16 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
-    cpqr<NT, P, ELDS>(L, n, W, S);
-    diag_r<NT, P, ELDS>(L, n, S);
-    const double sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
-    form_q<NT, P, ELDS>(L, n, S, W);
-    update_t<NT, P, ELDS>(L, S, T);
+    double sgn_u = 1.0;
+    if constexpr (SVD) {
+      svd_failed |= jsvd_udt<NT, P>(L, n, S, W, T);
+    } else {
+      cpqr<NT, P, ELDS>(L, n, W, S);
+      diag_r<NT, P, ELDS>(L, n, S);
+      sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
+      form_q<NT, P, ELDS>(L, n, S, W);
+      update_t<NT, P, ELDS>(L, S, T);
+    }
 #pragma unroll
     for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT, P>(L, c)];
     double* dst = nullptr;
@@ -1085,7 +1211,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     store_rm<NT, P>(L, T, I.t_out, n);
     for (int t = L.t; t < n; t += G::THREADS) gmem(I.d_out)[t] = S.dnew[t];
   }
-  if (__any(bad) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
+  if ((__any(bad) || svd_failed) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
 }
 
 // Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1).
@@ -1120,7 +1246,7 @@ __device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   __syncthreads();
 }
 
-template <int NT, int P, bool ELDS>
+template <int NT, int P, bool ELDS, bool SVD = false>
 __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
                                                             int count, Queue* q) {
@@ -1134,7 +1260,7 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, P, ELDS>(L, S, I, wi.flags, wi.j);
+    sweep_one<NT, P, ELDS, SVD>(L, S, I, wi.flags, wi.j);
   }
 }
 
@@ -1917,8 +2043,17 @@ struct Launch {
   static constexpr int P = waves_for(NT);
   static constexpr bool kLds = lds_variant(NT);
   static constexpr bool kPairLds = NT <= 5;  // operand staging buffer fits beside the factor store
+  static constexpr bool kSvd = NT <= 5;  // A and T of the Jacobi SVD both fit in LDS
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {
+    if (variant == 2) {
+      if constexpr (kSvd) {
+        hipLaunchKernelGGL((k_sweep<NT, P, true, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
+                           items, count, q);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    }
     if (variant == 1 && kLds)
       hipLaunchKernelGGL((k_sweep<NT, P, kLds>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
                          items, count, q);
@@ -1969,6 +2104,8 @@ struct Launch {
   }
   static hipError_t info(int kind, int variant, KernelInfo* out) {
     if (kind == KK_SWEEP) {
+      if constexpr (kSvd)
+        if (variant == 2) return info_of(k_sweep<NT, P, true, true>, (int)sizeof(Smem<NT, P, true>), out);
       if (variant == 1 && kLds)
         return info_of(k_sweep<NT, P, kLds>, (int)sizeof(Smem<NT, P, kLds>), out);
       return info_of(k_sweep<NT, P, false>, (int)sizeof(Smem<NT, P, false>), out);

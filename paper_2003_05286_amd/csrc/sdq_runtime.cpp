@@ -84,6 +84,7 @@ struct sdq_ctx {
   DevBuf d_lgrad;  // sdq_langevin: gradients of every instance, then statuses
   DevBuf d_ltab;   // sdq_langevin: chain table
   DevBuf d_hmc;    // sdq_hmc: gradients, start fields, momenta, energies, statuses
+  int stab = 0;    // stabilizer of every sweep: 0 pivoted QR, 1 Jacobi SVD
   DevBuf d_htab;   // sdq_hmc: chain table
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   // pinned staging of plan images, a ring: the host waits for the plan
@@ -194,6 +195,10 @@ sdq_status validate(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, bool 
     if (need_inv && !I.expk_inv) {
       snprintf(buf, sizeof buf, "instance %d: expk_inv is NULL", i);
       return fail(ctx, SDQ_EINVAL, buf);
+    }
+    if (ctx->stab == SDQ_STAB_SVD && I.n > 80) {
+      snprintf(buf, sizeof buf, "instance %d: the Jacobi SVD stabilizer supports n <= 80 (n = %d)", i, I.n);
+      return fail(ctx, SDQ_EUNSUPPORTED, buf);
     }
     if (!std::isfinite(I.alpha)) {
       snprintf(buf, sizeof buf, "instance %d: alpha is not finite", i);
@@ -401,7 +406,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   B.count = count;
   int qi = 0;
   for (const auto& r : P.sweep_ranges) {
-    const int variant = is_gang(r.nt) ? 0 : ctx->tune[r.nt].variant;
+    const int variant = is_gang(r.nt) ? 0 : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
     const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
@@ -1283,6 +1288,13 @@ sdq_status sdq_hmc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_
   return timed(ctx, "hmc", [&] {
     return sdq::launch_hmc_end(count, nf, d_tab, 0.5 * eps, inv_var, a, ctx->stream);
   });
+}
+
+sdq_status sdq_set_stabilizer(sdq_ctx* ctx, int32_t stab) {
+  if (!ctx) return SDQ_EINVAL;
+  if (stab != SDQ_STAB_QR && stab != SDQ_STAB_SVD) return fail(ctx, SDQ_EINVAL, "unknown stabilizer");
+  ctx->stab = stab;
+  return SDQ_OK;
 }
 
 sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,

@@ -1,0 +1,94 @@
+"""The Jacobi SVD stabilizer (sdq_set_stabilizer(SDQ_STAB_SVD), the
+decomposition the paper compares with the QR in Sec. 4.2): G, log|det|,
+sign and G(tau,0) against the oracle's SVD-stabilized chain (a code of its
+own, pinned against the QR chain on the CPU) and against the library's QR
+path, at the benchmark's L = 8 and up to beta = 40; the size limit and the
+argument check."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_05286_amd import binding as sdq
+from paper_2003_05286_amd import workloads as wl
+from _gpu import DEV, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx_svd():
+    c = sdq.Context(0)
+    c.set_stabilizer(sdq.STAB_SVD)
+    return c
+
+
+@pytest.fixture(scope="module")
+def ctx_qr():
+    return sdq.Context(0)
+
+
+def relf(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def hubbard(L, beta, chains, seed):
+    E, Ei = wl.expk_pair(wl.hopping_matrix(L), 0.1)
+    lam = wl.hirsch_lambda(4.0, 0.1)
+    m = int(round(beta / 0.1))
+    F = 2.0 * np.random.default_rng(seed).integers(0, 2, (chains, m, L * L)) - 1.0
+    return E, Ei, lam, F
+
+
+@pytest.mark.parametrize("L,beta", [(4, 10.0), (4, 40.0), (6, 20.0), (8, 10.0), (8, 40.0)])
+def test_svd_greens_matches_oracle(ctx_svd, ctx_qr, L, beta):
+    E, Ei, lam, F = hubbard(L, beta, 2, wl.BASE_SEED + 1500 + L + int(beta))
+    E_d, Ei_d = torch.from_numpy(E).to(DEV), torch.from_numpy(Ei).to(DEV)
+    Fd = torch.from_numpy(F).to(DEV)
+    ch = [sdq.Chain(E_d, Fd[c], a, 10, Ei_d) for c in range(2) for a in (lam, -lam)]
+    say(f"[gpu] sdq_greens with the Jacobi SVD stabilizer, L={L} beta={beta}")
+    gs, ld, sg, st = ctx_svd.greens(ch)
+    gq, ldq, _, _ = ctx_qr.greens(ch)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for i, c in enumerate(ch):
+        Go, ldo, sgo = oracle.greens_stab(E, F[i // 2], c.alpha, 10, oracle.STAB_SVD)
+        g = gs[i].cpu().numpy()
+        e_o, e_q = relf(g, Go), relf(g, gq[i].cpu().numpy())
+        say(f"[gpu]   instance {i}: relF vs oracle SVD chain {e_o:.2e}, vs library QR path {e_q:.2e}")
+        assert e_o <= 1e-10 and e_q <= 1e-10
+        assert abs(ld[i].item() - ldo) <= 1e-10 * abs(ldo)
+        assert abs(ld[i].item() - ldq[i].item()) <= 1e-10 * abs(ldo)
+        assert sg[i].item() == sgo
+
+
+def test_svd_tdisp_matches_oracle(ctx_svd):
+    L, beta = 4, 40.0
+    E, Ei, lam, F = hubbard(L, beta, 1, wl.BASE_SEED + 1550)
+    E_d, Ei_d = torch.from_numpy(E).to(DEV), torch.from_numpy(Ei).to(DEV)
+    Fd = torch.from_numpy(F).to(DEV)
+    ch = [sdq.Chain(E_d, Fd[0], lam, 10, Ei_d)]
+    ls = [10, 200, 390, 400]
+    say("[gpu] sdq_greens_tdisp with the Jacobi SVD stabilizer, L=4 beta=40")
+    gts, _, _, _, st = ctx_svd.greens_tdisp(ch, ls)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for j, l in enumerate(ls):
+        Ao = oracle.greens_tdisp_stab(E, Ei, F[0], lam, 10, l, oracle.STAB_SVD)
+        e = relf(gts[0][j].cpu().numpy(), Ao)
+        say(f"[gpu]   l={l}: relF {e:.2e}")
+        assert e <= 1e-10
+
+
+def test_svd_limits(ctx_svd):
+    E, Ei, lam, F = hubbard(10, 1.0, 1, 7)
+    E_d = torch.from_numpy(E).to(DEV)
+    Fd = torch.from_numpy(F).to(DEV)
+    say("[gpu] Jacobi SVD stabilizer at n = 100 -> SDQ_EUNSUPPORTED; unknown stabilizer -> SDQ_EINVAL")
+    with pytest.raises(sdq.SdqError) as e:
+        ctx_svd.greens([sdq.Chain(E_d, Fd[0], lam, 10)])
+    assert e.value.status == sdq.SDQ_EUNSUPPORTED
+    c = sdq.Context(0)
+    with pytest.raises(sdq.SdqError) as e:
+        c.set_stabilizer(7)
+    assert e.value.status == sdq.SDQ_EINVAL
