@@ -78,6 +78,10 @@ def main():
                     help="inversion scheme of the time-displaced workloads: Loh's split (default) or "
                          "the single-decomposition inv_sum, which also reports its deviation from "
                          "the split scheme at every tau")
+    ap.add_argument("--stab", default="qr", choices=["qr", "svd"],
+                    help="stabilizer of the sweeps: the pivoted QR (default) or the one-sided Jacobi SVD "
+                         "(n <= 80); the roofline keeps the QR method's flop count, so with the SVD it "
+                         "reads as the rate of the QR-equivalent work")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -132,6 +136,8 @@ def main():
 
     chains = [sdq.Chain(dev_of(I.expk), dev_of(I.field), I.alpha, I.k, dev_of(I.expk_inv)) for I in insts]
     ctx = sdq.Context(0)
+    if args.stab == "svd":
+        ctx.set_stabilizer(sdq.STAB_SVD)
     # outputs preallocated once
     import ctypes
     inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin", "hmc") or plain))
@@ -373,7 +379,7 @@ def main():
         "config": {"workload": W.name, "chains": cnt, "n": sorted({I.n for I in insts}),
                    "m": sorted({I.m for I in insts}), "k": k, "beta": betas, "dtau": 0.1,
                    "l_list": (f"{l_list[0]},{l_list[1]},...,{l_list[-1]}" if len(l_list) > 2 else l_list),
-                   "scheme": args.scheme},
+                   "scheme": args.scheme, "stabilizer": args.stab},
         "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA,
@@ -427,7 +433,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
     if not args.no_cpu and kind == "hmc":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
-    if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain:
+    if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain and args.stab == "qr":
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

@@ -297,20 +297,39 @@ static int jacobi_svd(int n, double* A, double* V) {
   return -1;
 }
 
-/* UDT by the SVD: W = U diag(D) T with D = sigma (unsorted), T = V^T. */
+/* UDT by the SVD: W = U diag(D) T with D = sigma in descending order (as
+ * LAPACK's gesvj returns them), T = V^T. */
 static int udt_svd(int n, const double* W, double* U, double* D, double* T) {
   double* A = mat_new(n);
   double* V = mat_new(n);
+  double* sg = (double*)malloc(sizeof(double) * n);
+  int* ord = (int*)malloc(sizeof(int) * n);
   mat_copy(n, W, A);
   const int sweeps = jacobi_svd(n, A, V);
   for (int j = 0; j < n; ++j) {
-    D[j] = nrm2(n, A + j, n);
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + j] = D[j] > 0.0 ? A[(size_t)i * n + j] / D[j] : 0.0;
+    sg[j] = nrm2(n, A + j, n);
+    ord[j] = j;
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) T[(size_t)i * n + j] = V[(size_t)j * n + i];
+  /* insertion sort of the column order by decreasing sigma (stable) */
+  for (int a = 1; a < n; ++a) {
+    const int c = ord[a];
+    int b = a - 1;
+    while (b >= 0 && sg[ord[b]] < sg[c]) {
+      ord[b + 1] = ord[b];
+      --b;
+    }
+    ord[b + 1] = c;
+  }
+  for (int j = 0; j < n; ++j) {
+    const int c = ord[j];
+    D[j] = sg[c];
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + j] = sg[c] > 0.0 ? A[(size_t)i * n + c] / sg[c] : 0.0;
+    for (int i = 0; i < n; ++i) T[(size_t)j * n + i] = V[(size_t)i * n + c];
+  }
   free(A);
   free(V);
+  free(sg);
+  free(ord);
   return sweeps;
 }
 

@@ -1000,15 +1000,20 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
 //   zeta = (a_q.a_q - a_p.a_p) / (2 a_p.a_q),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //   c = 1 / sqrt(1 + t^2),  s = c t,  a_p <- c a_p - s a_q,  a_q <- s a_p + c a_q,
 // and the same rotation applied to rows p, q of T (T <- V^T T).  Then
-// D = column norms (S.dnew), U = A D^{-1} (into W).  A sits in S.R by column,
+// D = column norms in descending order (S.dnew; as LAPACK's gesvj returns
+// them, which keeps the single-decomposition schemes' middle matrices graded
+// in order), U = A D^{-1} with its columns and T with its rows in that
+// order (into W and T).  A sits in S.R by column,
 // T in S.E by row; the pairs of a round follow the circle method over the
 // NP columns (each column in one pair per round, NP - 1 rounds per sweep),
 // one pair per group of 8 lanes, one barrier per round; at most 60 sweeps.
-// det U = +1: every slice has a positive determinant and the rotations have
-// determinant one, so the sign of det W (that of the previous U) carries
-// over.  Returns 0, or 1 without convergence.
+// Sign of det U: every slice has a positive determinant and the rotations
+// have determinant one, so det U has the sign of det W (that of the
+// previous U) times that of the ordering permutation, which is returned in
+// *psign.  Returns 0, or 1 without convergence.
 template <int NT, int P>
-__device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT, P>& W, RM<NT, P>& T) {
+__device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT, P>& W, RM<NT, P>& T,
+                        double* psign) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   constexpr int GS = 8;                      // lanes per column pair
@@ -1087,14 +1092,40 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
       break;
     }
   }
-  // D = column norms, U = A D^{-1}, T back to registers (padding: identity)
+  // column norms (S.tau, free here), their descending order (ties by
+  // index: S.sinv[rank] = column), D = S.dnew in that order, then
+  // U = A D^{-1} and T back to registers in that order (padding: identity)
   for (int t = L.t; t < G::NP; t += G::THREADS) {
     double ss = 0.0;
     if (t < n)
       for (int i = 0; i < G::NP; ++i) ss = fma(S.R[t * G::LDR + i], S.R[t * G::LDR + i], ss);
-    S.dnew[t] = t < n ? sqrt(ss) : 1.0;
+    S.tau[t] = t < n ? sqrt(ss) : 1.0;
   }
   __syncthreads();
+  for (int t = L.t; t < G::NP; t += G::THREADS) {
+    int rk = t;
+    if (t < n) {
+      const double st = S.tau[t];
+      rk = 0;
+      for (int i = 0; i < n; ++i) rk += (S.tau[i] > st || (S.tau[i] == st && i < t)) ? 1 : 0;
+    }
+    S.sinv[rk] = t;
+    S.dnew[rk] = S.tau[t];
+  }
+  __syncthreads();
+  // parity of the ordering: (-1)^(n - number of cycles), one thread
+  if (L.t == 0) {
+    unsigned long long seen[(G::NP + 63) / 64] = {};
+    int cycles = 0;
+    for (int a = 0; a < n; ++a) {
+      if (seen[a >> 6] & (1ull << (a & 63))) continue;
+      ++cycles;
+      for (int b = a; !(seen[b >> 6] & (1ull << (b & 63))); b = S.sinv[b]) seen[b >> 6] |= 1ull << (b & 63);
+    }
+    S.red[0][0] = ((n - cycles) & 1) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  *psign = S.red[0][0];
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
     const int col = col_of<NT, P>(L, c);
@@ -1104,8 +1135,9 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
         const bool ok = tile_ok<NT, P>(L, c);
-        W.v[c][ti][r] = (ok && col < n) ? S.R[col * G::LDR + row] / S.dnew[col] : (row == col ? 1.0 : 0.0);
-        T.v[c][ti][r] = ok ? S.E[row * G::LDR + col] : (row == col ? 1.0 : 0.0);
+        W.v[c][ti][r] = (ok && col < n) ? S.R[S.sinv[col] * G::LDR + row] / S.dnew[col]
+                                        : (row == col ? 1.0 : 0.0);
+        T.v[c][ti][r] = ok ? S.E[S.sinv[row] * G::LDR + col] : (row == col ? 1.0 : 0.0);
       }
   }
   return failed;
@@ -1149,6 +1181,8 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   }
   const EOp<NT, P, EST> eop{S.E, e_op, L.l};
   int svd_failed = 0;
+  // sign of det U of the current factorization (the SVD path carries it)
+  double sgn_run = (block && jpair > 0) ? gmem(I.ckf + (size_t)(jpair - 1) * sd)[2 * (size_t)n * n + n] : 1.0;
 
   for (int s = s_lo; s < s_hi; ++s) {
     const int b = adj ? nb - 1 - s : s;
@@ -1181,7 +1215,10 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
         for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
     double sgn_u = 1.0;
     if constexpr (SVD) {
-      svd_failed |= jsvd_udt<NT, P>(L, n, S, W, T);
+      double ps = 1.0;
+      svd_failed |= jsvd_udt<NT, P>(L, n, S, W, T, &ps);
+      sgn_u = sgn_run * ps;
+      sgn_run = sgn_u;
     } else {
       cpqr<NT, P, ELDS>(L, n, W, S);
       diag_r<NT, P, ELDS>(L, n, S);

@@ -92,3 +92,25 @@ def test_svd_limits(ctx_svd):
     with pytest.raises(sdq.SdqError) as e:
         c.set_stabilizer(7)
     assert e.value.status == sdq.SDQ_EINVAL
+
+
+def test_svd_with_inv_sum_near_the_ends(ctx_svd):
+    """The single-decomposition inv_sum on SVD-stabilized chains: accurate
+    near tau = 0 and tau = beta (against the oracle's same scheme on its SVD
+    chain), like the QR; both fail around beta/2 (Sec. 6.2)."""
+    L, beta = 4, 40.0
+    E, Ei, lam, F = hubbard(L, beta, 1, wl.BASE_SEED + 1560)
+    E_d, Ei_d = torch.from_numpy(E).to(DEV), torch.from_numpy(Ei).to(DEV)
+    Fd = torch.from_numpy(F).to(DEV)
+    ch = [sdq.Chain(E_d, Fd[0], lam, 10, Ei_d)]
+    ls = [10, 390, 400]
+    say("[gpu] sdq_greens_tdisp, Jacobi SVD stabilizer with inv_sum, L=4 beta=40, l near 0 and beta")
+    gts, _, _, _, st = ctx_svd.greens_tdisp(ch, ls, scheme=sdq.SCHEME_PLAIN)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    for j, l in enumerate(ls):
+        Ao = oracle.greens_tdisp_stab(E, Ei, F[0], lam, 10, l, oracle.STAB_SVD, oracle.SCHEME_PLAIN)
+        Aq = oracle.greens_tdisp(E, Ei, F[0], lam, 10, l)
+        e, eq = relf(gts[0][j].cpu().numpy(), Ao), relf(Ao, Aq)
+        say(f"[gpu]   l={l}: relF vs oracle (SVD, inv_sum) {e:.2e}; oracle SVD+inv_sum vs QR+inv_sum_loh {eq:.2e}")
+        assert e <= 1e-9 and eq <= 1e-9
