@@ -114,3 +114,29 @@ def test_svd_with_inv_sum_near_the_ends(ctx_svd):
         e, eq = relf(gts[0][j].cpu().numpy(), Ao), relf(Ao, Aq)
         say(f"[gpu]   l={l}: relF vs oracle (SVD, inv_sum) {e:.2e}; oracle SVD+inv_sum vs QR+inv_sum_loh {eq:.2e}")
         assert e <= 1e-9 and eq <= 1e-9
+
+
+def test_svd_gradient_and_local_sweep(ctx_svd):
+    """The consumers of the sweeps on SVD stages: the adjoint gradient against
+    the oracle's, and a local-update sweep (its forward stages rebuilt with
+    the SVD) against sequential Metropolis on the oracle's ratios."""
+    from test_gpu_local import oracle_sweep
+    L, beta = 4, 2.0
+    E, Ei, lam, F = hubbard(L, beta, 1, wl.BASE_SEED + 1570)
+    m = F.shape[1]
+    E_d, Ei_d = torch.from_numpy(E).to(DEV), torch.from_numpy(Ei).to(DEV)
+    Fd = torch.from_numpy(F[0].copy()).to(DEV)
+    say("[gpu] sdq_logdet_grad and sdq_local_sweep with the Jacobi SVD stabilizer, L=4 beta=2")
+    grads, _, _, st = ctx_svd.logdet_grad([sdq.Chain(E_d, Fd, lam, 10, Ei_d)])
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    go = oracle.logdet_grad(E, F[0], lam, 10, np.arange(1, m + 1, dtype=np.int32))
+    assert relf(grads[0].cpu().numpy(), go) <= 1e-10
+    u = np.random.default_rng(11).uniform(0.0, 1.0, (1, m, L * L))
+    ch = [sdq.Chain(E_d, Fd, a, 10, Ei_d) for a in (lam, -lam)]
+    acc, st = ctx_svd.local_sweep(ch, 2, torch.from_numpy(u).to(DEV))
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    fo, ao = oracle_sweep(E, F[0], (lam, -lam), 10, u[0])
+    assert int(acc[0].item()) == ao
+    assert np.array_equal(Fd.cpu().numpy(), fo)
