@@ -25,8 +25,10 @@ def relf(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# L = 12 (N = 144) takes the gradient through the gang kernels
 @pytest.mark.parametrize("L,beta,k,nf,chains", [(4, 2.0, 10, 1, 3), (4, 2.0, 10, 2, 2),
-                                                (6, 1.5, 5, 2, 1), (8, 2.0, 10, 1, 2)])
+                                                (6, 1.5, 5, 2, 1), (8, 2.0, 10, 1, 2),
+                                                (12, 1.0, 10, 1, 1)])
 def test_langevin_matches_oracle_step(ctx, L, beta, k, nf, chains):
     dtau, g, eps, inv_var = 0.1, 1.0, 0.01, 1.0
     E, Ei = wl.expk_pair(wl.hopping_matrix(L), dtau)
