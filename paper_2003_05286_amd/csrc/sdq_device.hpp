@@ -1722,35 +1722,31 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     bad |= !isfinite(gii);
     gmem(I.grad)[(size_t)(l0 - 1) * n + t] = I.alpha * (1.0 - gii);
   }
+  // the wraps G_{l+1} = E (diag(v_l) G_l diag(1/v_l)) E^{-1}: E^{-1} in
+  // registers and E staged in LDS once per item, v = exp(alpha f_l) once per
+  // row; G stays in S.R (row-major) between slices
+  RM<NT, P> Ei;
+  if (l0 < l1) {
+    load_rm<NT, P>(L, Ei, I.expk_inv, n, false);
+    stage_e<NT, P, ELDS>(L, S, I.esw);  // visible after the first barrier below
+  }
   for (int l = l0; l < l1; ++l) {
-    // G_{l+1} = E diag(v_l) G_l diag(1/v_l) Ebar
-    RM<NT, P> Bi, Yr, Gn;
     const double* fl = I.field + (size_t)(l - 1) * n;
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int col = col_of<NT, P>(L, c);
-#pragma unroll
-      for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = row_of(L, ti, r);
-          double x = 0.0;
-          if (row < n && col < n && tile_ok<NT, P>(L, c))
-            x = I.expk_inv[row * n + col] * exp(-I.alpha * gmem(fl)[row]);
-          Bi.v[c][ti][r] = x;
-        }
+    __syncthreads();  // the previous slice's readers of S.R and S.vbuf are done
+    for (int t = L.t; t < G::NP; t += G::THREADS) {
+      const double e = t < n ? exp(I.alpha * gmem(fl)[t]) : 1.0;
+      S.vbuf[0][t] = e;
+      S.vbuf[1][t] = 1.0 / e;
     }
-    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Bi, Yr);
-#pragma unroll
-    for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        const double v = row < n ? exp(I.alpha * gmem(fl)[row]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < CT; ++c) Yr.v[c][ti][r] *= v;
-      }
-    gemm_rb<NT, P>(L, EOp<NT, P, false>{nullptr, I.esw, L.l}, Yr, Gn);
+    __syncthreads();
+    for (int idx = L.t; idx < n * n; idx += G::THREADS) {
+      const int r = idx / n, c = idx - r * n;
+      S.R[r * G::LDR + c] *= S.vbuf[0][r] * S.vbuf[1][c];
+    }
+    __syncthreads();
+    RM<NT, P> Yr, Gn;
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[i * G::LDR + kk]; }, Ei, Yr);
+    gemm_rb<NT, P>(L, EOp<NT, P, ELDS>{S.E, I.esw, L.l}, Yr, Gn);
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
