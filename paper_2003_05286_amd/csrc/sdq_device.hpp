@@ -52,9 +52,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // sweep and the equal-time inversion at n <= 64 (they fit 256 registers per
 // lane with little or no spilling), one otherwise
 constexpr int minb_for(int nt) { return nt <= 4 ? 2 : 1; }
-// (the gradient and the site loop of the local updates keep more state in
+// (the site loop of the local updates keeps both flavours' G and E^-1 in
 // registers: one)
-constexpr int minb_pair(int nt, int mode) { return mode == 1 || mode == 4 ? 1 : minb_for(nt); }
+constexpr int minb_pair(int nt, int mode) { return mode == 4 ? 1 : minb_for(nt); }
 
 template <int NT, int P_>
 struct Geo {
