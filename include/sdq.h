@@ -113,6 +113,25 @@ const char* sdq_version(void);
 sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                       double* const* g, double* logdet, double* sign, int32_t* status);
 
+/* A chain whose slices are given as dense real matrices (models whose B_l
+ * is not expk * diag(exp(alpha f_l))): slice l (1-based) is the row-major
+ * n x n device matrix slices + (l-1) n n. */
+typedef struct {
+  int32_t n;              /* 1 <= n <= 128                                         */
+  int32_t m;              /* slices, m >= 1                                         */
+  int32_t k;              /* stabilization interval, 1 <= k <= m (Sec. 4.1)        */
+  int32_t pad_;
+  const double* slices;   /* [m][n][n]                                              */
+} sdq_dense_instance;
+
+/* Equal-time G = (1 + B_m ... B_1)^{-1}, log|det(1 + B_m ... B_1)| and its
+ * sign for chains of dense slices: the same stabilized product (Sec. 4.1,
+ * pivoted-QR UDT every k slices, Sec. 4.2.2) and Loh's split inversion
+ * (Sec. 5.1) as sdq_greens, with B_l read as given.  g, logdet, sign, status
+ * as in sdq_greens.  n > 128 and the SVD stabilizer return SDQ_EUNSUPPORTED. */
+sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count, double* const* g,
+                            double* logdet, double* sign, int32_t* status);
+
 /* Time-displaced Green's functions G(tau_l, 0) = B_l ... B_1 G (Sec. 6) for
  * every l of the host list l_list[n_l] (ascending, each 0 <= l <= m of every
  * chain), computed directly at multiples of k by the time-displaced scheme

@@ -53,6 +53,7 @@ def lib():
         L.or_greens_stab.argtypes = [c_int, c_int, c_int, d, d, c_double, c_int, c_int, d, d, d]
         L.or_greens_tdisp_stab.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, c_int, c_int, d]
         L.or_svd.argtypes = [c_int, d, d, d, d]
+        L.or_greens_dense.argtypes = [c_int, c_int, c_int, d, d, d, d]
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
@@ -186,8 +187,18 @@ def greens_tdisp_stab(expk, expk_inv, field, alpha, k, l, stab, scheme=SCHEME_LO
     return G
 
 
+def greens_dense(slices, k):
+    """Equal-time G, log|det| and sign for dense slices [m][n][n] (B_l = slices[l-1])."""
+    sl = _c(slices)
+    m, n = sl.shape[0], sl.shape[1]
+    G = np.zeros((n, n))
+    ld, sg = np.zeros(1), np.zeros(1)
+    _chk(lib().or_greens_dense(n, m, k, _p(sl), _p(G), _p(ld), _p(sg)))
+    return G, float(ld[0]), float(sg[0])
+
+
 def svd(W):
-    """One-sided Jacobi SVD: W = U diag(s) V^T (s unsorted); returns U, s, V, sweeps."""
+    """One-sided Jacobi SVD: W = U diag(s) V^T (s descending); returns U, s, V, sweeps."""
     W = _c(W)
     n = W.shape[0]
     U, V, sv = np.zeros((n, n)), np.zeros((n, n)), np.zeros(n)

@@ -32,6 +32,8 @@
  *   or_logdet_grad     d log|det(1+B_M..B_1)| / d f_{l,i} = alpha (1-G_l)_ii
  *                      (Jacobi's formula; see the function comment)
  *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
+ *   or_greens_dense    the same chain and inversion for slices given as dense
+ *                      matrices (generalized slices)
  *   jacobi_svd,        Sec. 4.2 (the Jacobi SVD the paper compares with the
  *   or_greens_stab     QR; one-sided, Hestenes), as an independent stabilizer
  *                      of the same chain: a cross-check of the QR path
@@ -417,13 +419,19 @@ typedef struct {
   double alpha;
   int sym;                 /* 1: the symmetric Trotter slice H diag(v) H (Sec. 2) */
   int svd;                 /* 1: stabilize with the Jacobi SVD instead of the QR */
+  const double* dense;     /* dense slices [m][n][n] (B_q at dense + (q-1) n n), or NULL */
 } problem;
 
-enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4 };
+enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4, SLICE_DENSE = 5 };
 
 /* W <- X_q W with X_q = B_q, B_q^{-1} or B_q^T (q is 1-based). */
 static void apply_slice(const problem* P, int kind, int q, double* W, double* tmp) {
   const int n = P->n;
+  if (kind == SLICE_DENSE) {         /* B_q as given */
+    mat_mul(n, P->dense + (size_t)(q - 1) * n * n, W, tmp);
+    mat_copy(n, tmp, W);
+    return;
+  }
   double* v = (double*)malloc(sizeof(double) * n);
   for (int i = 0; i < n; ++i) v[i] = exp(P->alpha * P->field[(size_t)(q - 1) * n + i]);
   if (kind == SLICE_B) {             /* B_q = E diag(v) */
@@ -489,7 +497,7 @@ static void chain_fwd(const problem* P, int a, int b, double* U, double* D, doub
   const int cnt = b >= a ? b - a + 1 : 0;
   int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
   for (int s = 0; s < cnt; ++s) order[s] = a + s;
-  chain_udt(P, P->sym ? SLICE_BSYM : SLICE_B, order, cnt, U, D, T);
+  chain_udt(P, P->dense ? SLICE_DENSE : (P->sym ? SLICE_BSYM : SLICE_B), order, cnt, U, D, T);
   free(order);
 }
 
@@ -844,7 +852,23 @@ int or_greens_tdisp_stab(int n, int m, int k, const double* expk, const double* 
   return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
 }
 
-/* The Jacobi SVD of one matrix: W = U diag(s) V^T (s unsorted); returns the
+/* Equal-time G, log|det| and sign for dense slices (B_l given as matrices;
+ * generalized slices): the same chain and inv_one_plus_loh. */
+int or_greens_dense(int n, int m, int k, const double* slices, double* G, double* logdet, double* sign) {
+  if (n <= 0 || m <= 0 || k <= 0 || !slices) return OR_EINVAL;
+  for (size_t i = 0; i < (size_t)m * n * n; ++i)
+    if (!isfinite(slices[i])) return OR_EINVAL;
+  problem P = {n, m, k, NULL, NULL, NULL, 0.0, 0, 0, slices};
+  double* U = mat_new(n);
+  double* T = mat_new(n);
+  double* D = (double*)malloc(sizeof(double) * n);
+  chain_fwd(&P, 1, m, U, D, T);
+  inv_one_plus_loh(n, U, D, T, G, logdet, sign);
+  free(U); free(T); free(D);
+  return finite_all(n, G) ? OR_OK : OR_ERANGE;
+}
+
+/* The Jacobi SVD of one matrix: W = U diag(s) V^T (s descending); returns the
  * number of sweeps (-1: no convergence). */
 int or_svd(int n, const double* W, double* U, double* s, double* V) {
   double* T = mat_new(n);

@@ -1143,12 +1143,14 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
   return failed;
 }
 
-template <int NT, int P, bool ELDS, bool SVD = false>
+// DENSE: the slices are the dense matrices I.dense (forward sweeps only),
+// staged through S.E one at a time when ELDS, else read from global memory.
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
 __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
                           const int jpair) {
   using G = Geo<NT, P>;
   // the SVD stabilizer keeps T in S.E, so E is read from its global copy
-  constexpr bool EST = ELDS && !SVD;
+  constexpr bool EST = ELDS && !SVD && !DENSE;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k, nb = I.nb;
   const bool left = (flags & SW_LEFT) != 0, right = (flags & SW_RIGHT) != 0;
@@ -1192,7 +1194,27 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       q0 = q1 - k + 1 > 1 ? q1 - k + 1 : 1;
     }
     const int cnt = q1 - q0 + 1;
-    for (int c0 = 0; c0 < cnt; c0 += G::KB) {
+    if constexpr (DENSE) {
+      for (int q = q0; q <= q1; ++q) {
+        const double* Bq = I.dense + (size_t)(q - 1) * n * n;
+        if constexpr (ELDS) {
+          __syncthreads();  // the previous slice's readers of S.E are done
+          for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
+            const int i = idx / G::NP, kk = idx - i * G::NP;
+            S.E[i * G::LDR + kk] = (i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+          }
+          __syncthreads();
+          gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
+        } else {
+          gemm_rb<NT, P>(L,
+                         [&](int, int, int, int i, int kk) -> double {
+                           return (i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+                         },
+                         W, W);
+        }
+      }
+    }
+    for (int c0 = 0; c0 < (DENSE ? 0 : cnt); c0 += G::KB) {
       const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
       if (left) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn, -1.0);
       else if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
@@ -1283,7 +1305,7 @@ __device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   __syncthreads();
 }
 
-template <int NT, int P, bool ELDS, bool SVD = false>
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
 __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
                                                             int count, Queue* q) {
@@ -1297,7 +1319,7 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, P, ELDS, SVD>(L, S, I, wi.flags, wi.j);
+    sweep_one<NT, P, ELDS, SVD, DENSE>(L, S, I, wi.flags, wi.j);
   }
 }
 
@@ -2077,8 +2099,14 @@ struct Launch {
   static constexpr bool kLds = lds_variant(NT);
   static constexpr bool kPairLds = NT <= 5;  // operand staging buffer fits beside the factor store
   static constexpr bool kSvd = NT <= 5;  // A and T of the Jacobi SVD both fit in LDS
+  static constexpr bool kDenseLds = NT <= 5;  // a dense slice staged beside the factor store
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {
+    if (variant == 3) {
+      hipLaunchKernelGGL((k_sweep<NT, P, kDenseLds, false, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s,
+                         inst, items, count, q);
+      return hipGetLastError();
+    }
     if (variant == 2) {
       if constexpr (kSvd) {
         hipLaunchKernelGGL((k_sweep<NT, P, true, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
@@ -2137,6 +2165,8 @@ struct Launch {
   }
   static hipError_t info(int kind, int variant, KernelInfo* out) {
     if (kind == KK_SWEEP) {
+      if (variant == 3)
+        return info_of(k_sweep<NT, P, kDenseLds, false, true>, (int)sizeof(Smem<NT, P, kDenseLds>), out);
       if constexpr (kSvd)
         if (variant == 2) return info_of(k_sweep<NT, P, true, true>, (int)sizeof(Smem<NT, P, true>), out);
       if (variant == 1 && kLds)

@@ -45,6 +45,7 @@ struct Inst {
   const double* eswi;      // expk_inv in the layout of esw, or null
   const double* unif;      // local updates: uniform numbers [m][n] of the chain
   int32_t* nacc;           // local updates: accepted flips of the chain
+  const double* dense;     // dense slices [m][n][n] (B_l at dense + (l-1) n n) or null
 };
 
 enum SweepFlags : int32_t {

@@ -67,6 +67,7 @@ struct Plan {
   // call, over the same instances, made them (the layout is a function of
   // the instances, so the pointers come out the same)
   bool swz_ready = false;
+  bool dense = false;  // every instance has dense slices (sweep variant 3)
 };
 
 }  // namespace
@@ -334,12 +335,14 @@ sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
     tot += 2 * np * np;
   };
   for (const Inst& I : P.inst) {
+    if (!I.expk) continue;  // dense slices
     add(I.expk, I.n);
     if (P.swz_inv && I.expk_inv) add(I.expk_inv, I.n);
   }
   HIP_TRY(grow(ctx->d_swz, (size_t)std::max<int64_t>(tot, 1) * sizeof(double)), "hipMalloc(swizzle)");
   double* base = (double*)ctx->d_swz.p;
   for (Inst& I : P.inst) {
+    if (!I.expk) continue;
     const int64_t off = seen[std::make_pair(I.expk, I.n)];
     const int64_t np = 16LL * nt_of(I.n);
     I.esw = base + off;
@@ -406,7 +409,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   B.count = count;
   int qi = 0;
   for (const auto& r : P.sweep_ranges) {
-    const int variant = is_gang(r.nt) ? 0 : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
+    const int variant = is_gang(r.nt) ? 0 : P.dense ? 3 : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
     const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
@@ -721,6 +724,57 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
     I.scheme = scheme == SDQ_INV_PLAIN ? 1 : 0;
+    I.g = g ? g[i] : nullptr;
+    I.logdet = logdet ? logdet + i : nullptr;
+    I.sign = sign ? sign + i : nullptr;
+    I.status = status ? status + i : nullptr;
+    I.fin = (double*)ctx->d_fin.p + off[i];
+    P.inst.push_back(I);
+    P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
+    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+  }
+  order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
+    const Inst& I = P.inst[w.inst];
+    return sweep_cost(I.n, I.m, I.k);
+  });
+  order_all_pairs(P);
+  ctx->err.clear();
+  return run_plan(ctx, P, status, count);
+}
+
+sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count, double* const* g,
+                            double* logdet, double* sign, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
+  if (count == 0) return SDQ_OK;
+  if (!inst) return fail(ctx, SDQ_EINVAL, "inst is NULL");
+  if (ctx->stab != SDQ_STAB_QR) return fail(ctx, SDQ_EUNSUPPORTED, "dense slices use the QR stabilizer");
+  std::vector<sdq_instance> shape(count);
+  for (int i = 0; i < count; ++i) {
+    const sdq_dense_instance& d = inst[i];
+    char buf[160];
+    if (d.n < 1 || d.n > 16 * sdq::kMaxNT) {
+      snprintf(buf, sizeof buf, "instance %d: dense slices need 1 <= n <= 128 (n = %d)", i, d.n);
+      return fail(ctx, d.n < 1 ? SDQ_EINVAL : SDQ_EUNSUPPORTED, buf);
+    }
+    if (d.m < 1 || d.k < 1 || d.k > d.m || !d.slices) {
+      snprintf(buf, sizeof buf, "instance %d: need m >= 1, 1 <= k <= m and slices", i);
+      return fail(ctx, SDQ_EINVAL, buf);
+    }
+    memset(&shape[i], 0, sizeof(sdq_instance));
+    shape[i].n = d.n;
+    shape[i].m = d.m;
+    shape[i].k = d.k;
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<int64_t> off;
+  sdq_status st = alloc_fin(ctx, shape.data(), count, off);
+  if (st) return st;
+  Plan P;
+  P.dense = true;
+  for (int i = 0; i < count; ++i) {
+    Inst I = base_inst(shape[i]);
+    I.dense = inst[i].slices;
     I.g = g ? g[i] : nullptr;
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;

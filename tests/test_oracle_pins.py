@@ -490,3 +490,35 @@ def test_svd_stabilized_chain_agrees_with_qr(L, beta):
         Aq = oracle.greens_tdisp(E, Ei, f, lam, 10, l)
         As = oracle.greens_tdisp_stab(E, Ei, f, lam, 10, l, oracle.STAB_SVD)
         assert relF(As, Aq) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Dense slices (B_l given as matrices): the Hubbard slices written out give
+# the Hubbard result, and non-symmetric random slices at small beta give the
+# plain definition.
+
+def test_dense_slices_reproduce_the_hubbard_chain():
+    L, beta = 4, 10.0
+    E, _ = wl.expk_pair(wl.hopping_matrix(L), 0.1)
+    lam = wl.hirsch_lambda(4.0, 0.1)
+    m = int(round(beta / 0.1))
+    f = 2.0 * np.random.default_rng(31).integers(0, 2, (m, L * L)) - 1.0
+    slices = np.stack([E * np.exp(lam * f[l])[None, :] for l in range(m)])
+    Gd, ldd, sgd = oracle.greens_dense(slices, 10)
+    Gh, ldh, sgh = oracle.greens(E, f, lam, 10)
+    assert relF(Gd, Gh) <= 1e-12
+    assert abs(ldd - ldh) <= 1e-12 * abs(ldh) and sgd == sgh
+
+
+def test_dense_slices_plain_definition():
+    n, m = 12, 6
+    rng = np.random.default_rng(32)
+    slices = np.stack([np.eye(n) + 0.3 * rng.normal(size=(n, n)) for _ in range(m)])
+    prod = np.eye(n)
+    for l in range(m):
+        prod = slices[l] @ prod
+    A = np.eye(n) + prod
+    G, ld, sg = oracle.greens_dense(slices, 2)
+    assert relF(G, np.linalg.inv(A)) <= 1e-12
+    s_ref, ld_ref = np.linalg.slogdet(A)
+    assert abs(ld - ld_ref) <= 1e-12 * max(1.0, abs(ld_ref)) and sg == s_ref
