@@ -69,7 +69,7 @@ def main():
                     choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
                              "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
-                             "hubbard_L8_b20_phi_hmc128",
+                             "hubbard_L8_b20_phi_hmc128", "hubbard_L8_b40_dense128",
                              "hubbard_L16_b40_batch128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
@@ -115,7 +115,8 @@ def main():
             "hubbard_L8_b40_metropolis256": "metropolis",
             "hubbard_L8_b40_local256": "local",
             "hubbard_L8_b20_phi_langevin128": "langevin",
-            "hubbard_L8_b20_phi_hmc128": "hmc"}[args.workload]
+            "hubbard_L8_b20_phi_hmc128": "hmc",
+            "hubbard_L8_b40_dense128": "dense"}[args.workload]
     n, m, k = insts[0].n, insts[0].m, insts[0].k
     cnt = len(insts)
     plain = args.scheme == "plain"
@@ -189,6 +190,14 @@ def main():
         nbuf = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
         frc = torch.empty(cnt, m, n, dtype=torch.float64, device=dev)
 
+    if kind == "dense":
+        # the slices E diag(exp(alpha f_l)) of every chain written out as
+        # dense matrices on the device (input preparation, not timed)
+        dense_t = [(dev_of(I.expk)[None, :, :] * torch.exp(I.alpha * dev_of(I.field))[:, None, :]).contiguous()
+                   for I in insts]
+        dense_arr = (sdq._DenseInstance * cnt)()
+        for i, t in enumerate(dense_t):
+            dense_arr[i] = sdq._DenseInstance(n, m, k, 0, t.data_ptr())
     HMC_EPS, HMC_STEPS = 0.05, 10
     if kind == "hmc":
         # one trajectory of every chain per step; momenta and uniform numbers
@@ -222,7 +231,9 @@ def main():
         ubuf = torch.empty(C, m, n, dtype=torch.float64, device=dev)
 
     def step():
-        if kind == "hmc":
+        if kind == "dense":
+            ctx._chk(ctx.lib.sdq_greens_dense(ctx.h, dense_arr, cnt, g_ptrs, vp(ld), vp(sg), vp(st)))
+        elif kind == "hmc":
             mbuf.normal_(generator=hgen)
             ubuf_h.uniform_(generator=hgen)
             ctx._chk(ctx.lib.sdq_hmc(ctx.h, hmi, cnt, 1, HMC_EPS, HMC_STEPS, 1.0, vp(mbuf), vp(ubuf_h), vp(ld),
@@ -280,7 +291,7 @@ def main():
     status_ok = int((st != 0).sum().item()) == 0
     n_bad = int((st != 0).sum().item())
 
-    sweeps_per_chain = 1 if kind in ("greens", "metropolis") else 2  # local: backward + rebuilt forward
+    sweeps_per_chain = 1 if kind in ("greens", "metropolis", "dense") else 2  # local: backward + rebuilt forward
     f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
     if plain:
         f_sweep = sum(plain_sweep_flops(I.n, I.m, I.k, l_list) for I in insts)
@@ -351,6 +362,9 @@ def main():
         metric = "global Metropolis updates/sec (FP64, L=8, beta=40, 256 chains x 2 flavours)"
         unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
                 "field, one time slice flipped, and the accept step)")
+    elif kind == "dense":
+        metric = "equal-time Green's functions/sec of dense-slice chains (FP64, L=8, beta=40, 128 chains)"
+        unit = "chains/s (each: G, log|det|, sign; slices read as dense matrices)"
     elif kind == "hmc":
         metric = "HMC trajectories/sec (FP64, L=8, beta=20, 128 chains, continuous field)"
         unit = (f"chain trajectories/s (each: {HMC_STEPS} leapfrog steps of {HMC_EPS}, {HMC_STEPS + 1} "
@@ -431,6 +445,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline_local(insts)
     if not args.no_cpu and kind == "langevin":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
+    if not args.no_cpu and kind == "dense":
+        out["cpu_baseline"] = cpu_baseline_dense(insts, args.cpu_sample)
     if not args.no_cpu and kind == "hmc":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain and args.stab == "qr":
@@ -520,6 +536,25 @@ def cpu_baseline_local(insts, nsites=1024):
     return {"value": nsites / dt / (m * n), "unit": "chain sweeps/s", "cores": threads, "kind": "oracle",
             "sample": f"{nsites} flips of one chain (2 flavours, one oracle log|det| each), {dt:.1f} s "
                       f"wall, scaled to {m * n} flips per sweep"}
+
+
+def cpu_baseline_dense(insts, nchains):
+    """The oracle as it stands on a bounded sample: the dense-slice chain of
+    `nchains` chains (their slices written out on the host), one chain per
+    host thread."""
+    import numpy as np
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sample = insts[:nchains]
+    dense = [np.ascontiguousarray(I.expk[None, :, :] * np.exp(I.alpha * I.field)[:, None, :]) for I in sample]
+    print(f"[bench] cpu oracle: {len(sample)} dense-slice chains on {threads} threads", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda d: oracle.greens_dense(d, sample[0].k), dense))
+    dt = time.perf_counter() - t0
+    return {"value": len(sample) / dt, "unit": "chains/s (each: G, log|det|, sign)", "cores": threads,
+            "kind": "oracle", "sample": f"{len(sample)} of the 128 chains; {dt:.1f} s wall"}
 
 
 def cpu_baseline_langevin(insts, nchains, nevals=1):

@@ -1195,15 +1195,31 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     }
     const int cnt = q1 - q0 + 1;
     if constexpr (DENSE) {
+      // ELDS: each slice goes through registers into S.E; the next one is
+      // loaded while the current product runs
+      constexpr int PER = (G::NP * G::NP + G::THREADS - 1) / G::THREADS;
+      double nxt[PER];
+      auto fetch = [&](int q) {
+        const double* Bq = I.dense + (size_t)(q - 1) * n * n;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int idx = L.t + e * G::THREADS;
+          const int i = idx / G::NP, kk = idx - i * G::NP;
+          nxt[e] = (idx < G::NP * G::NP && i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+        }
+      };
+      if constexpr (ELDS) fetch(q0);
       for (int q = q0; q <= q1; ++q) {
         const double* Bq = I.dense + (size_t)(q - 1) * n * n;
         if constexpr (ELDS) {
           __syncthreads();  // the previous slice's readers of S.E are done
-          for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
-            const int i = idx / G::NP, kk = idx - i * G::NP;
-            S.E[i * G::LDR + kk] = (i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+#pragma unroll
+          for (int e = 0; e < PER; ++e) {
+            const int idx = L.t + e * G::THREADS;
+            if (idx < G::NP * G::NP) S.E[(idx / G::NP) * G::LDR + idx % G::NP] = nxt[e];
           }
           __syncthreads();
+          if (q < q1) fetch(q + 1);
           gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
         } else {
           gemm_rb<NT, P>(L,

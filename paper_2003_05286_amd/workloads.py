@@ -200,6 +200,10 @@ def workload(name: str, scale: float = 1.0) -> Workload:
                         notes="L=8, beta=20, M=200, continuous phi ~ N(0,1) at the start, g=1, k=10; "
                               "one hybrid Monte Carlo trajectory (10 leapfrog steps of 0.05) per chain "
                               "per step")
+    if name == "hubbard_L8_b40_dense128":
+        return Workload(name, hubbard_ising(8, 40.0, nb(128), 1, seed=BASE_SEED + 7),
+                        notes="L=8 (N=64), beta=40, M=400, k=10, 128 chains whose slices "
+                              "E diag(exp(lambda s_l)) are handed over as dense matrices")
     if name == "hubbard_L16_b40_batch128":
         return Workload(name, hubbard_ising(16, 40.0, nb(64), 2, seed=BASE_SEED + 4),
                         l_list=list(range(1, 401)),
