@@ -53,6 +53,8 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     for nt in NTS:
         tasks.append((os.path.join(CSRC, "sdq_nt.hip"), os.path.join(BUILD, f"sdq_nt{nt}.o"),
                       [f"-DSDQ_NT={nt}"]))
+        tasks.append((os.path.join(CSRC, "sdq_nt_dense.hip"), os.path.join(BUILD, f"sdq_nt_dense{nt}.o"),
+                      [f"-DSDQ_NT={nt}"]))
     tasks.append((os.path.join(CSRC, "sdq_dispatch.hip"), os.path.join(BUILD, "sdq_dispatch.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_gang.hip"), os.path.join(BUILD, "sdq_gang.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_runtime.cpp"), os.path.join(BUILD, "sdq_runtime.o"), []))

@@ -1143,7 +1143,8 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
   return failed;
 }
 
-// DENSE: the slices are the dense matrices I.dense (forward sweeps only),
+// DENSE: the slices are the dense matrices at I.field (B_q at
+// field + (q-1) n n; forward sweeps only),
 // staged through S.E one at a time when ELDS, else read from global memory.
 template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
 __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
@@ -1200,7 +1201,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       constexpr int PER = (G::NP * G::NP + G::THREADS - 1) / G::THREADS;
       double nxt[PER];
       auto fetch = [&](int q) {
-        const double* Bq = I.dense + (size_t)(q - 1) * n * n;
+        const double* Bq = I.field + (size_t)(q - 1) * n * n;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
           const int idx = L.t + e * G::THREADS;
@@ -1210,7 +1211,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       };
       if constexpr (ELDS) fetch(q0);
       for (int q = q0; q <= q1; ++q) {
-        const double* Bq = I.dense + (size_t)(q - 1) * n * n;
+        const double* Bq = I.field + (size_t)(q - 1) * n * n;
         if constexpr (ELDS) {
           __syncthreads();  // the previous slice's readers of S.E are done
 #pragma unroll
@@ -1229,19 +1230,20 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
                          W, W);
         }
       }
-    }
-    for (int c0 = 0; c0 < (DENSE ? 0 : cnt); c0 += G::KB) {
-      const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
-      if (left) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn, -1.0);
-      else if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
-      else fill_vbuf<NT, P, ELDS>(L, S, I, q0 + c0, +1, cn);
-      for (int s2 = 0; s2 < cn; ++s2) {
-        if (!adj && !left) {
-          scale_rows<NT, P>(L, W, S.vbuf[s2]);
-          gemm_rb<NT, P>(L, eop, W, W);
-        } else {
-          gemm_rb<NT, P>(L, eop, W, W);
-          scale_rows<NT, P>(L, W, S.vbuf[s2]);
+    } else {
+      for (int c0 = 0; c0 < cnt; c0 += G::KB) {
+        const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
+        if (left) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn, -1.0);
+        else if (adj) fill_vbuf<NT, P, ELDS>(L, S, I, q1 - c0, -1, cn);
+        else fill_vbuf<NT, P, ELDS>(L, S, I, q0 + c0, +1, cn);
+        for (int s2 = 0; s2 < cn; ++s2) {
+          if (!adj && !left) {
+            scale_rows<NT, P>(L, W, S.vbuf[s2]);
+            gemm_rb<NT, P>(L, eop, W, W);
+          } else {
+            gemm_rb<NT, P>(L, eop, W, W);
+            scale_rows<NT, P>(L, W, S.vbuf[s2]);
+          }
         }
       }
     }
@@ -2115,14 +2117,20 @@ struct Launch {
   static constexpr bool kLds = lds_variant(NT);
   static constexpr bool kPairLds = NT <= 5;  // operand staging buffer fits beside the factor store
   static constexpr bool kSvd = NT <= 5;  // A and T of the Jacobi SVD both fit in LDS
+  // the dense-slice sweep (variant 3) is instantiated in its own translation
+  // unit (sdq_nt_dense.hip), so that it leaves the code of these alone
   static constexpr bool kDenseLds = NT <= 5;  // a dense slice staged beside the factor store
+  static hipError_t dense_sweep(const Inst* inst, const SweepItem* items, int count, Queue* q, int grid,
+                                hipStream_t s) {
+    hipLaunchKernelGGL((k_sweep<NT, P, kDenseLds, false, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s,
+                       inst, items, count, q);
+    return hipGetLastError();
+  }
+  static hipError_t dense_info(KernelInfo* out) {
+    return info_of(k_sweep<NT, P, kDenseLds, false, true>, (int)sizeof(Smem<NT, P, kDenseLds>), out);
+  }
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {
-    if (variant == 3) {
-      hipLaunchKernelGGL((k_sweep<NT, P, kDenseLds, false, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s,
-                         inst, items, count, q);
-      return hipGetLastError();
-    }
     if (variant == 2) {
       if constexpr (kSvd) {
         hipLaunchKernelGGL((k_sweep<NT, P, true, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
@@ -2181,8 +2189,6 @@ struct Launch {
   }
   static hipError_t info(int kind, int variant, KernelInfo* out) {
     if (kind == KK_SWEEP) {
-      if (variant == 3)
-        return info_of(k_sweep<NT, P, kDenseLds, false, true>, (int)sizeof(Smem<NT, P, kDenseLds>), out);
       if constexpr (kSvd)
         if (variant == 2) return info_of(k_sweep<NT, P, true, true>, (int)sizeof(Smem<NT, P, true>), out);
       if (variant == 1 && kLds)

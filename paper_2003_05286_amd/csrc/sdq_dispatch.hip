@@ -10,7 +10,9 @@ namespace sdq {
                                hipStream_t);                                                     \
   hipError_t launch_udt_nt##N(int, int, const double*, double*, double*, double*, hipStream_t);  \
   hipError_t launch_sim_nt##N(int, int, double* const*, const double*, const double*, int, hipStream_t); \
-  hipError_t kernel_info_nt##N(int, int, KernelInfo*);
+  hipError_t kernel_info_nt##N(int, int, KernelInfo*);                                            \
+  hipError_t launch_dense_sweep_nt##N(const Inst*, const SweepItem*, int, Queue*, int, hipStream_t); \
+  hipError_t dense_info_nt##N(KernelInfo*);
 SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL(7) SDQ_DECL(8)
 #undef SDQ_DECL
 
@@ -29,6 +31,11 @@ SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL
 
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
                         Queue* q, int grid, hipStream_t s) {
+  if (variant == 3) {
+#define C(N) launch_dense_sweep_nt##N(inst, items, count, q, grid, s)
+    SDQ_SWITCH(C)
+#undef C
+  }
 #define C(N) launch_sweep_nt##N(variant, inst, items, count, q, grid, s)
   SDQ_SWITCH(C)
 #undef C
@@ -56,6 +63,11 @@ hipError_t launch_similarity(int nt, int n, int count, double* const* mats, cons
 #undef C
 }
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
+  if (kind == KK_SWEEP && variant == 3) {
+#define C(N) dense_info_nt##N(out)
+    SDQ_SWITCH(C)
+#undef C
+  }
 #define C(N) kernel_info_nt##N(kind, variant, out)
   SDQ_SWITCH(C)
 #undef C

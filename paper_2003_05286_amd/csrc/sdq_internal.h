@@ -23,7 +23,7 @@ __host__ __device__ inline int64_t stage_doubles(int n) {
 struct Inst {
   const double* expk;      // [n][n]
   const double* expk_inv;  // [n][n] or null
-  const double* field;     // [m][n]
+  const double* field;     // [m][n]; dense-slice chains: the slices [m][n][n]
   double alpha;
   int32_t n, m, k, nb;     // nb = ceil(m / k) stabilization blocks
   int32_t scheme;          // 0: Loh's split scales (Sec. 5.1, 6.1), 1: single decomposition
@@ -45,7 +45,6 @@ struct Inst {
   const double* eswi;      // expk_inv in the layout of esw, or null
   const double* unif;      // local updates: uniform numbers [m][n] of the chain
   int32_t* nacc;           // local updates: accepted flips of the chain
-  const double* dense;     // dense slices [m][n][n] (B_l at dense + (l-1) n n) or null
 };
 
 enum SweepFlags : int32_t {

@@ -1,0 +1,21 @@
+// sdq_nt_dense.hip -- the dense-slice sweep of sdq_device.hpp for one tile
+// count SDQ_NT (compiled once per NT = 1..8, like sdq_nt.hip, but apart from
+// it: the other kernels' code does not depend on this instantiation).
+#include "sdq_device.hpp"
+
+#ifndef SDQ_NT
+#error "define SDQ_NT"
+#endif
+
+#define SDQ_CAT2(a, b) a##b
+#define SDQ_CAT(a, b) SDQ_CAT2(a, b)
+
+namespace sdq {
+
+hipError_t SDQ_CAT(launch_dense_sweep_nt, SDQ_NT)(const Inst* inst, const SweepItem* items, int count, Queue* q,
+                                                 int grid, hipStream_t s) {
+  return Launch<SDQ_NT>::dense_sweep(inst, items, count, q, grid, s);
+}
+hipError_t SDQ_CAT(dense_info_nt, SDQ_NT)(KernelInfo* out) { return Launch<SDQ_NT>::dense_info(out); }
+
+}  // namespace sdq

@@ -774,7 +774,7 @@ sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_
   P.dense = true;
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(shape[i]);
-    I.dense = inst[i].slices;
+    I.field = inst[i].slices;  // read as the dense slices by the dense sweep
     I.g = g ? g[i] : nullptr;
     I.logdet = logdet ? logdet + i : nullptr;
     I.sign = sign ? sign + i : nullptr;
