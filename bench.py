@@ -144,7 +144,7 @@ def main():
     inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin", "hmc") or plain))
     ls = (ctypes.c_int32 * max(len(l_list), 1))(*l_list)
     gts = [torch.empty(len(l_list), I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
-        if kind == "tdisp" else []
+        if kind in ("tdisp", "dense") else []
     gs = [torch.empty(I.n, I.n, dtype=torch.float64, device=dev) for I in insts] \
         if kind not in ("grad", "langevin", "hmc") else []
     grads = [torch.empty(I.m, I.n, dtype=torch.float64, device=dev) for I in insts] if kind == "grad" else []
@@ -232,7 +232,8 @@ def main():
 
     def step():
         if kind == "dense":
-            ctx._chk(ctx.lib.sdq_greens_dense(ctx.h, dense_arr, cnt, g_ptrs, vp(ld), vp(sg), vp(st)))
+            ctx._chk(ctx.lib.sdq_greens_tdisp_dense(ctx.h, dense_arr, cnt, ls, len(l_list), gt_ptrs, g_ptrs,
+                                                    vp(ld), vp(sg), vp(st)))
         elif kind == "hmc":
             mbuf.normal_(generator=hgen)
             ubuf_h.uniform_(generator=hgen)
@@ -291,13 +292,13 @@ def main():
     status_ok = int((st != 0).sum().item()) == 0
     n_bad = int((st != 0).sum().item())
 
-    sweeps_per_chain = 1 if kind in ("greens", "metropolis", "dense") else 2  # local: backward + rebuilt forward
+    sweeps_per_chain = 1 if kind in ("greens", "metropolis") else 2  # local: backward + rebuilt forward
     f_sweep = sum(sweeps_per_chain * sweep_flops(I.n, I.m, I.k) for I in insts)
     if plain:
         f_sweep = sum(plain_sweep_flops(I.n, I.m, I.k, l_list) for I in insts)
         n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
         f_pair = sum(plain_pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
-    elif kind == "tdisp":
+    elif kind in ("tdisp", "dense"):
         # l a multiple of k (or m) is a direct inversion, the others propagate
         n_direct = sum(1 for l in l_list if l % k == 0 or l == m)
         f_pair = sum(pair_flops(I.n, n_direct, len(l_list) - n_direct) for I in insts)
@@ -363,8 +364,8 @@ def main():
         unit = ("chain updates/s (each: the stabilized log|det(1+B)| of both flavours of a proposed "
                 "field, one time slice flipped, and the accept step)")
     elif kind == "dense":
-        metric = "equal-time Green's functions/sec of dense-slice chains (FP64, L=8, beta=40, 128 chains)"
-        unit = "chains/s (each: G, log|det|, sign; slices read as dense matrices)"
+        metric = "stabilized Green's functions/sec of dense-slice chains (FP64, L=8, beta=40, 128 chains)"
+        unit = "chains/s (each: G + 40 G(tau,0); slices read as dense matrices)"
     elif kind == "hmc":
         metric = "HMC trajectories/sec (FP64, L=8, beta=20, 128 chains, continuous field)"
         unit = (f"chain trajectories/s (each: {HMC_STEPS} leapfrog steps of {HMC_EPS}, {HMC_STEPS + 1} "
@@ -446,7 +447,7 @@ def main():
     if not args.no_cpu and kind == "langevin":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
     if not args.no_cpu and kind == "dense":
-        out["cpu_baseline"] = cpu_baseline_dense(insts, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline_dense(insts, 4, l_list)
     if not args.no_cpu and kind == "hmc":
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain and args.stab == "qr":
@@ -538,22 +539,29 @@ def cpu_baseline_local(insts, nsites=1024):
                       f"wall, scaled to {m * n} flips per sweep"}
 
 
-def cpu_baseline_dense(insts, nchains):
-    """The oracle as it stands on a bounded sample: the dense-slice chain of
-    `nchains` chains (their slices written out on the host), one chain per
-    host thread."""
+def cpu_baseline_dense(insts, nchains, l_list):
+    """The oracle as it stands on a bounded sample: `nchains` dense-slice
+    chains (their slices written out on the host), each with its G and all
+    G(tau_l, 0), one oracle call per host thread."""
     import numpy as np
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
     sample = insts[:nchains]
     dense = [np.ascontiguousarray(I.expk[None, :, :] * np.exp(I.alpha * I.field)[:, None, :]) for I in sample]
-    print(f"[bench] cpu oracle: {len(sample)} dense-slice chains on {threads} threads", file=sys.stderr, flush=True)
+    jobs = [(d, None) for d in dense] + [(d, l) for d in dense for l in l_list]
+    k = sample[0].k
+    print(f"[bench] cpu oracle: {len(jobs)} dense-slice calls on {threads} threads", file=sys.stderr, flush=True)
+
+    def run(job):
+        d, l = job
+        return oracle.greens_dense(d, k) if l is None else oracle.greens_tdisp_dense(d, k, l)
+
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
-        list(ex.map(lambda d: oracle.greens_dense(d, sample[0].k), dense))
+        list(ex.map(run, jobs))
     dt = time.perf_counter() - t0
-    return {"value": len(sample) / dt, "unit": "chains/s (each: G, log|det|, sign)", "cores": threads,
+    return {"value": len(sample) / dt, "unit": f"chains/s (each: G + {len(l_list)} G(tau,0))", "cores": threads,
             "kind": "oracle", "sample": f"{len(sample)} of the 128 chains; {dt:.1f} s wall"}
 
 

@@ -54,6 +54,7 @@ def lib():
         L.or_greens_tdisp_stab.argtypes = [c_int, c_int, c_int, d, d, d, c_double, c_int, c_int, c_int, d]
         L.or_svd.argtypes = [c_int, d, d, d, d]
         L.or_greens_dense.argtypes = [c_int, c_int, c_int, d, d, d, d]
+        L.or_greens_tdisp_dense.argtypes = [c_int, c_int, c_int, d, c_int, d]
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
@@ -195,6 +196,15 @@ def greens_dense(slices, k):
     ld, sg = np.zeros(1), np.zeros(1)
     _chk(lib().or_greens_dense(n, m, k, _p(sl), _p(G), _p(ld), _p(sg)))
     return G, float(ld[0]), float(sg[0])
+
+
+def greens_tdisp_dense(slices, k, l):
+    """G(tau_l, 0) for dense slices [m][n][n]."""
+    sl = _c(slices)
+    m, n = sl.shape[0], sl.shape[1]
+    G = np.zeros((n, n))
+    _chk(lib().or_greens_tdisp_dense(n, m, k, _p(sl), int(l), _p(G)))
+    return G
 
 
 def svd(W):

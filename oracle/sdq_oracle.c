@@ -32,8 +32,8 @@
  *   or_logdet_grad     d log|det(1+B_M..B_1)| / d f_{l,i} = alpha (1-G_l)_ii
  *                      (Jacobi's formula; see the function comment)
  *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
- *   or_greens_dense    the same chain and inversion for slices given as dense
- *                      matrices (generalized slices)
+ *   or_greens_dense,   the same chains and inversions for slices given as
+ *   or_greens_tdisp_dense  dense matrices (generalized slices)
  *   jacobi_svd,        Sec. 4.2 (the Jacobi SVD the paper compares with the
  *   or_greens_stab     QR; one-sided, Hestenes), as an independent stabilizer
  *                      of the same chain: a cross-check of the QR path
@@ -422,7 +422,8 @@ typedef struct {
   const double* dense;     /* dense slices [m][n][n] (B_q at dense + (q-1) n n), or NULL */
 } problem;
 
-enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4, SLICE_DENSE = 5 };
+enum { SLICE_B = 0, SLICE_BINV = 1, SLICE_BT = 2, SLICE_BSYM = 3, SLICE_BSYMINV = 4, SLICE_DENSE = 5,
+       SLICE_DENSEINV = 6 };
 
 /* W <- X_q W with X_q = B_q, B_q^{-1} or B_q^T (q is 1-based). */
 static void apply_slice(const problem* P, int kind, int q, double* W, double* tmp) {
@@ -430,6 +431,14 @@ static void apply_slice(const problem* P, int kind, int q, double* W, double* tm
   if (kind == SLICE_DENSE) {         /* B_q as given */
     mat_mul(n, P->dense + (size_t)(q - 1) * n * n, W, tmp);
     mat_copy(n, tmp, W);
+    return;
+  }
+  if (kind == SLICE_DENSEINV) {      /* B_q^{-1} by Gauss-Jordan */
+    double* Bi = mat_new(n);
+    lu_inverse(n, P->dense + (size_t)(q - 1) * n * n, Bi, NULL, NULL);
+    mat_mul(n, Bi, W, tmp);
+    mat_copy(n, tmp, W);
+    free(Bi);
     return;
   }
   double* v = (double*)malloc(sizeof(double) * n);
@@ -506,7 +515,7 @@ static void chain_inv(const problem* P, int a, int b, double* U, double* D, doub
   const int cnt = b >= a ? b - a + 1 : 0;
   int* order = (int*)malloc(sizeof(int) * (cnt ? cnt : 1));
   for (int s = 0; s < cnt; ++s) order[s] = b - s;
-  chain_udt(P, P->sym ? SLICE_BSYMINV : SLICE_BINV, order, cnt, U, D, T);
+  chain_udt(P, P->dense ? SLICE_DENSEINV : (P->sym ? SLICE_BSYMINV : SLICE_BINV), order, cnt, U, D, T);
   free(order);
 }
 
@@ -866,6 +875,20 @@ int or_greens_dense(int n, int m, int k, const double* slices, double* G, double
   inv_one_plus_loh(n, U, D, T, G, logdet, sign);
   free(U); free(T); free(D);
   return finite_all(n, G) ? OR_OK : OR_ERANGE;
+}
+
+/* G(tau_l, 0) for dense slices: the chain B_1^{-1}..B_l^{-1} (each slice
+ * inverted by Gauss-Jordan) and B_M..B_{l+1}, combined by inv_sum_loh. */
+int or_greens_tdisp_dense(int n, int m, int k, const double* slices, int l, double* Gt) {
+  if (n <= 0 || m <= 0 || k <= 0 || !slices || l < 0 || l > m) return OR_EINVAL;
+  problem P = {n, m, k, NULL, NULL, NULL, 0.0, 0, 0, slices};
+  double *UL = mat_new(n), *XL = mat_new(n), *UR = mat_new(n), *XR = mat_new(n);
+  double *DL = malloc(sizeof(double) * n), *DR = malloc(sizeof(double) * n);
+  chain_inv(&P, 1, l, UL, DL, XL);
+  chain_fwd(&P, l + 1, m, UR, DR, XR);
+  inv_sum_loh(n, UL, DL, XL, UR, DR, XR, Gt);
+  free(UL); free(XL); free(UR); free(XR); free(DL); free(DR);
+  return finite_all(n, Gt) ? OR_OK : OR_ERANGE;
 }
 
 /* The Jacobi SVD of one matrix: W = U diag(s) V^T (s descending); returns the

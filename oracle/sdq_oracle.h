@@ -34,6 +34,7 @@ int or_greens_tdisp_stab(int n, int m, int k, const double* expk, const double* 
                          const double* field, double alpha, int l, int scheme, int stab, double* Gt);
 int or_svd(int n, const double* W, double* U, double* s, double* V);
 int or_greens_dense(int n, int m, int k, const double* slices, double* G, double* logdet, double* sign);
+int or_greens_tdisp_dense(int n, int m, int k, const double* slices, int l, double* Gt);
 int or_cpqr(int n, double* A, double* Q, int* jpvt);
 int or_udt(int n, const double* W, double* U, double* D, double* T);
 int or_expk_planewave(int L, double t, double dtau, double s, double* out);

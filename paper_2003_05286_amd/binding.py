@@ -29,7 +29,8 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_greens_tdisp", "sdq_logdet", "sdq_logdet_grad", "sdq_release", "sdq_udt",
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
-           "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense")
+           "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense",
+           "sdq_greens_tdisp_dense")
 
 
 class SdqError(RuntimeError):
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_hmc.argtypes = [vp, P(_Instance), i32, i32, dbl, i32, dbl, vp, vp, vp, vp, vp, vp, vp]
     L.sdq_set_stabilizer.argtypes = [vp, i32]
     L.sdq_greens_dense.argtypes = [vp, P(_DenseInstance), i32, P(vp), vp, vp, vp]
+    L.sdq_greens_tdisp_dense.argtypes = [vp, P(_DenseInstance), i32, P(i32), i32, P(vp), P(vp), vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("sdq_destroy", "sdq_last_error", "sdq_version"):
@@ -271,22 +273,41 @@ class Context:
                                           _ptr(sign), _ptr(acc), _ptr(st)))
         return acc, st
 
-    def greens_dense(self, slices, k):
-        """Equal-time G, log|det(1+B)|, sign and status for chains of dense
-        slices (sdq_greens_dense): slices is a list of device [m, n, n]
-        float64 tensors, B_l = slices[c][l-1]."""
-        cnt = len(slices)
-        arr = (_DenseInstance * max(cnt, 1))()
+    def _dense(self, slices, k):
+        arr = (_DenseInstance * max(len(slices), 1))()
         for i, t in enumerate(slices):
             if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.tdev or t.dim() != 3 \
                     or t.shape[1] != t.shape[2]:
                 raise ValueError(f"slices[{i}]: need a contiguous float64 [m, n, n] tensor on {self.tdev}")
             arr[i] = _DenseInstance(t.shape[2], t.shape[0], int(k), 0, t.data_ptr())
+        return arr
+
+    def greens_dense(self, slices, k):
+        """Equal-time G, log|det(1+B)|, sign and status for chains of dense
+        slices (sdq_greens_dense): slices is a list of device [m, n, n]
+        float64 tensors, B_l = slices[c][l-1]."""
+        cnt = len(slices)
+        arr = self._dense(slices, k)
         gs = [self._empty(t.shape[2], t.shape[2]) for t in slices]
         ld, sg = self._empty(cnt), self._empty(cnt)
         st = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
         self._chk(self.lib.sdq_greens_dense(self.h, arr, cnt, self._ptr_array(gs), _ptr(ld), _ptr(sg), _ptr(st)))
         return gs, ld, sg, st
+
+    def greens_tdisp_dense(self, slices, k, l_list):
+        """G(tau_l, 0) ([n_l, n, n] per chain), G, log|det|, sign, status for
+        chains of dense slices (sdq_greens_tdisp_dense); every l a multiple of
+        k or m."""
+        cnt = len(slices)
+        arr = self._dense(slices, k)
+        ls = (ctypes.c_int32 * max(len(l_list), 1))(*[int(x) for x in l_list])
+        gts = [self._empty(len(l_list), t.shape[2], t.shape[2]) for t in slices]
+        gs = [self._empty(t.shape[2], t.shape[2]) for t in slices]
+        ld, sg = self._empty(cnt), self._empty(cnt)
+        st = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_greens_tdisp_dense(self.h, arr, cnt, ls, len(l_list), self._ptr_array(gts),
+                                                  self._ptr_array(gs), _ptr(ld), _ptr(sg), _ptr(st)))
+        return gts, gs, ld, sg, st
 
     def set_stabilizer(self, stab):
         """STAB_QR (default) or STAB_SVD for every later sweep (sdq_set_stabilizer)."""

@@ -1144,7 +1144,7 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
 }
 
 // DENSE: the slices are the dense matrices at I.field (B_q at
-// field + (q-1) n n; forward sweeps only),
+// field + (q-1) n n; forward sweeps, and backward ones over B_q^T),
 // staged through S.E one at a time when ELDS, else read from global memory.
 template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
 __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
@@ -1209,8 +1209,11 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
           nxt[e] = (idx < G::NP * G::NP && i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
         }
       };
-      if constexpr (ELDS) fetch(q0);
-      for (int q = q0; q <= q1; ++q) {
+      // forward: W <- B_q W for q = q0..q1; backward: W <- B_q^T W, q = q1..q0
+      const int qa = adj ? q1 : q0, qs = adj ? -1 : 1;
+      if constexpr (ELDS) fetch(qa);
+      for (int t = 0; t < cnt; ++t) {
+        const int q = qa + t * qs;
         const double* Bq = I.field + (size_t)(q - 1) * n * n;
         if constexpr (ELDS) {
           __syncthreads();  // the previous slice's readers of S.E are done
@@ -1220,12 +1223,16 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
             if (idx < G::NP * G::NP) S.E[(idx / G::NP) * G::LDR + idx % G::NP] = nxt[e];
           }
           __syncthreads();
-          if (q < q1) fetch(q + 1);
-          gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
+          if (t + 1 < cnt) fetch(q + qs);
+          if (adj)
+            gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[kk * G::LDR + i]; }, W, W);
+          else
+            gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
         } else {
           gemm_rb<NT, P>(L,
                          [&](int, int, int, int i, int kk) -> double {
-                           return (i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+                           if (i >= n || kk >= n) return 0.0;
+                           return adj ? gmem(Bq)[(size_t)kk * n + i] : gmem(Bq)[(size_t)i * n + kk];
                          },
                          W, W);
         }

@@ -742,14 +742,14 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   return run_plan(ctx, P, status, count);
 }
 
-sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count, double* const* g,
-                            double* logdet, double* sign, int32_t* status) {
-  if (!ctx) return SDQ_EINVAL;
-  if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
-  if (count == 0) return SDQ_OK;
-  if (!inst) return fail(ctx, SDQ_EINVAL, "inst is NULL");
+namespace {
+// checks of dense-slice instances; shape[i] gets their n, m, k (other fields
+// zero) for the helpers that size library memory by instance
+sdq_status validate_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count,
+                          std::vector<sdq_instance>& shape) {
+  if (count > 0 && !inst) return fail(ctx, SDQ_EINVAL, "inst is NULL");
   if (ctx->stab != SDQ_STAB_QR) return fail(ctx, SDQ_EUNSUPPORTED, "dense slices use the QR stabilizer");
-  std::vector<sdq_instance> shape(count);
+  shape.assign(count, sdq_instance{});
   for (int i = 0; i < count; ++i) {
     const sdq_dense_instance& d = inst[i];
     char buf[160];
@@ -761,11 +761,22 @@ sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_
       snprintf(buf, sizeof buf, "instance %d: need m >= 1, 1 <= k <= m and slices", i);
       return fail(ctx, SDQ_EINVAL, buf);
     }
-    memset(&shape[i], 0, sizeof(sdq_instance));
     shape[i].n = d.n;
     shape[i].m = d.m;
     shape[i].k = d.k;
   }
+  return SDQ_OK;
+}
+}  // namespace
+
+sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count, double* const* g,
+                            double* logdet, double* sign, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
+  std::vector<sdq_instance> shape;
+  sdq_status st0 = validate_dense(ctx, inst, count, shape);
+  if (st0) return st0;
+  if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   std::vector<int64_t> off;
   sdq_status st = alloc_fin(ctx, shape.data(), count, off);
@@ -783,6 +794,68 @@ sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_
     P.inst.push_back(I);
     P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
     P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+  }
+  order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
+    const Inst& I = P.inst[w.inst];
+    return sweep_cost(I.n, I.m, I.k);
+  });
+  order_all_pairs(P);
+  ctx->err.clear();
+  return run_plan(ctx, P, status, count);
+}
+
+sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count,
+                                  const int32_t* l_list, int32_t n_l, double* const* gt, double* const* g,
+                                  double* logdet, double* sign, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
+  std::vector<sdq_instance> shape;
+  sdq_status st = validate_dense(ctx, inst, count, shape);
+  if (st) return st;
+  if (n_l < 0 || (n_l > 0 && (!l_list || !gt))) return fail(ctx, SDQ_EINVAL, "bad l_list / gt");
+  for (int a = 0; a < n_l; ++a) {
+    if (l_list[a] < 0) return fail(ctx, SDQ_EINVAL, "l_list entry < 0");
+    if (a > 0 && l_list[a] <= l_list[a - 1]) return fail(ctx, SDQ_EINVAL, "l_list must be strictly ascending");
+  }
+  for (int i = 0; i < count; ++i) {
+    if (n_l > 0 && l_list[n_l - 1] > shape[i].m) return fail(ctx, SDQ_EINVAL, "l_list entry > m");
+    if (n_l > 0 && !gt[i]) return fail(ctx, SDQ_EINVAL, "gt entry is NULL");
+    for (int a = 0; a < n_l; ++a)
+      if (l_list[a] % shape[i].k != 0 && l_list[a] != shape[i].m)
+        return fail(ctx, SDQ_EUNSUPPORTED, "dense slices: l must be a multiple of k or m (no propagation)");
+  }
+  if (count == 0) return SDQ_OK;
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  std::vector<int64_t> off;
+  st = alloc_stages(ctx, ctx->d_ck, shape.data(), count, 2, off);
+  if (st) return st;
+  double* ck = (double*)ctx->d_ck.p;
+  Plan P;
+  P.dense = true;
+  P.llist.assign(l_list, l_list + n_l);
+  for (int i = 0; i < count; ++i) {
+    Inst I = base_inst(shape[i]);
+    I.field = inst[i].slices;  // read as the dense slices by the dense sweeps
+    I.g = g ? g[i] : nullptr;
+    I.gt = n_l > 0 ? gt[i] : nullptr;
+    I.logdet = logdet ? logdet + i : nullptr;
+    I.sign = sign ? sign + i : nullptr;
+    I.status = status ? status + i : nullptr;
+    const int64_t sd = sdq::stage_doubles(I.n);
+    const int64_t one = (int64_t)I.nb * sd;
+    I.ckf = ck + off[i];
+    I.cka = ck + off[i] + one;
+    I.fin = I.ckf + (I.nb - 1) * sd;
+    P.inst.push_back(I);
+    P.sweep.push_back(SweepItem{i, sdq::SW_STORE, 0, 0});
+    P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ, 0, 0});
+    if (I.g || I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+    // one stage pair per l (every l is a stage boundary)
+    for (int a = 0; a < n_l; ++a) {
+      const int l = l_list[a];
+      const int j = (l == I.m) ? I.nb : l / I.k;
+      P.pair[sdq::PAIR_TDISP].push_back(PairItem{i, j, a, a + 1});
+    }
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];

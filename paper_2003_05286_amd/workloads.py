@@ -202,8 +202,10 @@ def workload(name: str, scale: float = 1.0) -> Workload:
                               "per step")
     if name == "hubbard_L8_b40_dense128":
         return Workload(name, hubbard_ising(8, 40.0, nb(128), 1, seed=BASE_SEED + 7),
+                        l_list=list(range(10, 401, 10)),
                         notes="L=8 (N=64), beta=40, M=400, k=10, 128 chains whose slices "
-                              "E diag(exp(lambda s_l)) are handed over as dense matrices")
+                              "E diag(exp(lambda s_l)) are handed over as dense matrices; "
+                              "G and G(tau,0) at every 10th slice")
     if name == "hubbard_L16_b40_batch128":
         return Workload(name, hubbard_ising(16, 40.0, nb(64), 2, seed=BASE_SEED + 4),
                         l_list=list(range(1, 401)),

@@ -70,3 +70,30 @@ def test_dense_limits():
     with pytest.raises(sdq.SdqError) as e:
         c.greens_dense([torch.zeros(10, 16, 16, dtype=torch.float64, device=DEV)], 10)
     assert e.value.status == sdq.SDQ_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("L,beta,perturb", [(4, 40.0, 0.0), (4, 40.0, 0.02), (8, 20.0, 0.02), (10, 10.0, 0.02)])
+def test_dense_tdisp_matches_oracle(ctx, L, beta, perturb):
+    E, Ei, lam, f, B = slices_for(L, beta, wl.BASE_SEED + 1650 + L + int(beta), perturb)
+    m = B.shape[0]
+    ls = [0, 10, m // 2, m - 10, m]
+    Bd = torch.from_numpy(B).to(DEV)
+    say(f"[gpu] sdq_greens_tdisp_dense L={L} beta={beta} perturbation={perturb} l={ls}")
+    gts, gs, ld, _, st = ctx.greens_tdisp_dense([Bd], 10, ls)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    Go, ldo, _ = oracle.greens_dense(B, 10)
+    assert relf(gs[0].cpu().numpy(), Go) <= 1e-10
+    for j, l in enumerate(ls):
+        Ao = oracle.greens_tdisp_dense(B, 10, l)
+        e = relf(gts[0][j].cpu().numpy(), Ao)
+        say(f"[gpu]   l={l}: relF {e:.2e}")
+        assert e <= 1e-10
+
+
+def test_dense_tdisp_needs_stage_boundaries(ctx):
+    B = torch.zeros(20, 16, 16, dtype=torch.float64, device=DEV)
+    say("[gpu] sdq_greens_tdisp_dense at l = 5 (not a multiple of k) -> SDQ_EUNSUPPORTED")
+    with pytest.raises(sdq.SdqError) as e:
+        ctx.greens_tdisp_dense([B], 10, [5])
+    assert e.value.status == sdq.SDQ_EUNSUPPORTED

@@ -522,3 +522,26 @@ def test_dense_slices_plain_definition():
     assert relF(G, np.linalg.inv(A)) <= 1e-12
     s_ref, ld_ref = np.linalg.slogdet(A)
     assert abs(ld - ld_ref) <= 1e-12 * max(1.0, abs(ld_ref)) and sg == s_ref
+
+
+def test_dense_slices_time_displaced():
+    """G(tau_l, 0) of dense slices: the Hubbard slices written out give the
+    Hubbard result at beta = 40, and random non-symmetric slices at small
+    beta give B_l..B_1 (1 + B_M..B_1)^{-1}."""
+    L, beta = 4, 40.0
+    E, Ei = wl.expk_pair(wl.hopping_matrix(L), 0.1)
+    lam = wl.hirsch_lambda(4.0, 0.1)
+    m = int(round(beta / 0.1))
+    f = 2.0 * np.random.default_rng(33).integers(0, 2, (m, L * L)) - 1.0
+    slices = np.stack([E * np.exp(lam * f[l])[None, :] for l in range(m)])
+    for l in (0, 10, 200, 390, 400):
+        assert relF(oracle.greens_tdisp_dense(slices, 10, l), oracle.greens_tdisp(E, Ei, f, lam, 10, l)) <= 1e-11
+    n, m = 12, 6
+    rng = np.random.default_rng(34)
+    sl = np.stack([np.eye(n) + 0.3 * rng.normal(size=(n, n)) for _ in range(m)])
+    prod = [np.eye(n)]
+    for l in range(m):
+        prod.append(sl[l] @ prod[-1])
+    G = np.linalg.inv(np.eye(n) + prod[m])
+    for l in (0, 2, 4, 6):
+        assert relF(oracle.greens_tdisp_dense(sl, 2, l), prod[l] @ G) <= 1e-12
