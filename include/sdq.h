@@ -135,9 +135,10 @@ sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_
 /* G(tau_l, 0) = B_l ... B_1 G for chains of dense slices, by the
  * time-displaced scheme of sdq_greens_tdisp (Sec. 6.1, inv_sum_loh) from the
  * forward stages of B_l...B_1 and the backward stages of the transposed
- * chain.  Every l of l_list must be a multiple of k or equal to m (stage
- * boundaries: the propagation form is not offered here, SDQ_EUNSUPPORTED
- * otherwise).  Arguments as in sdq_greens_tdisp. */
+ * chain, at multiples of k and at l = m; any other l is reached by at most
+ * k-1 further products with the dense slices from the nearest lower multiple
+ * of k (Sec. 6, propagation form).  Arguments as in sdq_greens_tdisp (l_list
+ * ascending, 0 <= l <= m of every chain). */
 sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count,
                                   const int32_t* l_list, int32_t n_l, double* const* gt, double* const* g,
                                   double* logdet, double* sign, int32_t* status);

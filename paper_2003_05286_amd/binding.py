@@ -296,8 +296,8 @@ class Context:
 
     def greens_tdisp_dense(self, slices, k, l_list):
         """G(tau_l, 0) ([n_l, n, n] per chain), G, log|det|, sign, status for
-        chains of dense slices (sdq_greens_tdisp_dense); every l a multiple of
-        k or m."""
+        chains of dense slices (sdq_greens_tdisp_dense); l ascending in
+        [0, m]."""
         cnt = len(slices)
         arr = self._dense(slices, k)
         ls = (ctypes.c_int32 * max(len(l_list), 1))(*[int(x) for x in l_list])

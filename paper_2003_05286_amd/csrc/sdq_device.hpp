@@ -1382,7 +1382,7 @@ __device__ __forceinline__ void load_rm_staged(const Lane& L, const Smem<NT, P, 
   }
 }
 
-template <int NT, int P, bool ELDS>
+template <int NT, int P, bool ELDS, bool DENSE = false>
 __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                               const int ilo, const int ihi, const int32_t* __restrict__ l_list,
                               RM<NT, P>& Gm);
@@ -1398,7 +1398,7 @@ __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I
 //   G(tau,0) = U2 D_Rp^{-1} Mid^{-1} D_Lp^{-1} T1.
 // Then, for requested l inside the block, G(tau_l, 0) = B_l ... G(tau_j, 0)
 // (Sec. 6, propagation form), never across more than k-1 slices.
-template <int NT, int P, bool ELDS>
+template <int NT, int P, bool ELDS, bool DENSE = false>
 __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                            const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
   using G = Geo<NT, P>;
@@ -1519,13 +1519,14 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
                    Y, Gm);
   }
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
-  tdisp_outputs<NT, P, ELDS>(L, S, I, j, ilo, ihi, l_list, Gm);
+  tdisp_outputs<NT, P, ELDS, DENSE>(L, S, I, j, ilo, ihi, l_list, Gm);
 }
 
 // Outputs of stage pair j from Gm = G(tau_j, 0): l_list[ilo..ihi), ascending,
 // each in [tau_j, tau_j + k), G(tau_l, 0) = B_l ... B_{tau_j + 1} G(tau_j, 0)
-// (Sec. 6, propagation form).
-template <int NT, int P, bool ELDS>
+// (Sec. 6, propagation form).  DENSE: B_q is the n x n row-major matrix at
+// I.field + (q - 1) n^2, staged through LDS (or read from HBM without it).
+template <int NT, int P, bool ELDS, bool DENSE>
 __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                               const int ilo, const int ihi, const int32_t* __restrict__ l_list,
                               RM<NT, P>& Gm) {
@@ -1533,6 +1534,31 @@ __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I
   const int n = I.n, m = I.m, k = I.k;
   const int tj = j * k < m ? j * k : m;
   int lc = tj;
+  if constexpr (DENSE) {
+    for (int idx = ilo; idx < ihi; ++idx) {
+      const int l = l_list[idx];
+      for (int q = lc + 1; q <= l; ++q) {
+        const double* Bq = I.field + (size_t)(q - 1) * n * n;
+        if constexpr (ELDS) {
+          __syncthreads();
+          stage_mat<NT, P, ELDS>(L, S, Bq, n);
+          __syncthreads();
+          gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, Gm,
+                         Gm);
+        } else {
+          gemm_rb<NT, P>(L,
+                         [&](int, int, int, int i, int kk) -> double {
+                           return (i < n && kk < n) ? gmem(Bq)[i * n + kk] : 0.0;
+                         },
+                         Gm, Gm);
+        }
+      }
+      lc = l;
+      store_rm<NT, P>(L, Gm, I.gt + (size_t)idx * n * n, n);
+    }
+    __syncthreads();
+    return;
+  }
   if (ELDS && ihi > ilo && l_list[ihi - 1] > tj) {
     // propagation ahead: stage the swizzled slice exponential in LDS
     __syncthreads();
@@ -2044,6 +2070,8 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
       continue;
     }
     if constexpr (MODE == PAIR_TDISP) pair_tdisp<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
+    else if constexpr (MODE == PAIR_TDISP_DENSE)
+      pair_tdisp<NT, P, ELDS, true>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
     else if constexpr (MODE == PAIR_TDISP_PLAIN)
       pair_tdisp_plain<NT, P, ELDS>(L, S, I, wi.j, wi.ilo, wi.ihi, l_list);
     else if constexpr (MODE == PAIR_GRAD) pair_grad<NT, P, ELDS>(L, S, I, wi.j);
@@ -2135,6 +2163,17 @@ struct Launch {
   }
   static hipError_t dense_info(KernelInfo* out) {
     return info_of(k_sweep<NT, P, kDenseLds, false, true>, (int)sizeof(Smem<NT, P, kDenseLds>), out);
+  }
+  // G(tau,0) of dense-slice chains (propagation over the dense slices), also
+  // instantiated in sdq_nt_dense.hip only
+  static hipError_t dense_pair(const Inst* inst, const PairItem* items, int count, const int32_t* l_list,
+                               Queue* q, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_pair<NT, P, kPairLds, PAIR_TDISP_DENSE>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s,
+                       inst, items, count, l_list, q);
+    return hipGetLastError();
+  }
+  static hipError_t dense_pair_info(KernelInfo* out) {
+    return info_of(k_pair<NT, P, kPairLds, PAIR_TDISP_DENSE>, (int)sizeof(Smem<NT, P, kPairLds>), out);
   }
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
                           int grid, hipStream_t s) {

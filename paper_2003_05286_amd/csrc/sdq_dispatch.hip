@@ -12,7 +12,10 @@ namespace sdq {
   hipError_t launch_sim_nt##N(int, int, double* const*, const double*, const double*, int, hipStream_t); \
   hipError_t kernel_info_nt##N(int, int, KernelInfo*);                                            \
   hipError_t launch_dense_sweep_nt##N(const Inst*, const SweepItem*, int, Queue*, int, hipStream_t); \
-  hipError_t dense_info_nt##N(KernelInfo*);
+  hipError_t dense_info_nt##N(KernelInfo*);                                                      \
+  hipError_t launch_dense_pair_nt##N(const Inst*, const PairItem*, int, const int32_t*, Queue*, int, \
+                                     hipStream_t);                                               \
+  hipError_t dense_pair_info_nt##N(KernelInfo*);
 SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL(7) SDQ_DECL(8)
 #undef SDQ_DECL
 
@@ -44,6 +47,11 @@ hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* 
 hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
                        int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
   (void)variant;
+  if (mode == PAIR_TDISP_DENSE) {
+#define C(N) launch_dense_pair_nt##N(inst, items, count, l_list, q, grid, s)
+    SDQ_SWITCH(C)
+#undef C
+  }
 #define C(N) launch_pair_nt##N(mode, inst, items, count, l_list, q, grid, s)
   SDQ_SWITCH(C)
 #undef C
@@ -65,6 +73,11 @@ hipError_t launch_similarity(int nt, int n, int count, double* const* mats, cons
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
   if (kind == KK_SWEEP && variant == 3) {
 #define C(N) dense_info_nt##N(out)
+    SDQ_SWITCH(C)
+#undef C
+  }
+  if (kind == KK_PAIR && variant == 3) {
+#define C(N) dense_pair_info_nt##N(out)
     SDQ_SWITCH(C)
 #undef C
   }

@@ -70,8 +70,8 @@ struct SweepItem {
 };
 
 enum PairMode : int32_t { PAIR_TDISP = 0, PAIR_GRAD = 1, PAIR_EQUAL = 2, PAIR_TDISP_PLAIN = 3,
-                          PAIR_LOCAL = 4, PAIR_BSTART = 5 };
-constexpr int kPairModes = 6;
+                          PAIR_LOCAL = 4, PAIR_BSTART = 5, PAIR_TDISP_DENSE = 6 };
+constexpr int kPairModes = 7;
 
 // tdisp: stage pair j, outputs for l_list[ilo..ihi) (PAIR_TDISP_PLAIN: the
 //        same from the SW_LEFT / SW_RIGHT chains)

@@ -1,4 +1,4 @@
-// sdq_nt_dense.hip -- the dense-slice sweep of sdq_device.hpp for one tile
+// sdq_nt_dense.hip -- the dense-slice sweep and G(tau,0) of sdq_device.hpp for one tile
 // count SDQ_NT (compiled once per NT = 1..8, like sdq_nt.hip, but apart from
 // it: the other kernels' code does not depend on this instantiation).
 #include "sdq_device.hpp"
@@ -17,5 +17,10 @@ hipError_t SDQ_CAT(launch_dense_sweep_nt, SDQ_NT)(const Inst* inst, const SweepI
   return Launch<SDQ_NT>::dense_sweep(inst, items, count, q, grid, s);
 }
 hipError_t SDQ_CAT(dense_info_nt, SDQ_NT)(KernelInfo* out) { return Launch<SDQ_NT>::dense_info(out); }
+hipError_t SDQ_CAT(launch_dense_pair_nt, SDQ_NT)(const Inst* inst, const PairItem* items, int count,
+                                                const int32_t* l_list, Queue* q, int grid, hipStream_t s) {
+  return Launch<SDQ_NT>::dense_pair(inst, items, count, l_list, q, grid, s);
+}
+hipError_t SDQ_CAT(dense_pair_info_nt, SDQ_NT)(KernelInfo* out) { return Launch<SDQ_NT>::dense_pair_info(out); }
 
 }  // namespace sdq

@@ -415,11 +415,13 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
   }
   const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_TDISP_PLAIN,
-                                      sdq::PAIR_GRAD, sdq::PAIR_BSTART, sdq::PAIR_LOCAL};
+                                      sdq::PAIR_TDISP_DENSE, sdq::PAIR_GRAD, sdq::PAIR_BSTART,
+                                      sdq::PAIR_LOCAL};
   for (int oi = 0; oi < sdq::kPairModes; ++oi) {
     const int md = order[oi];
     for (const auto& r : P.pair_ranges[md]) {
-      const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, 0, r.count);
+      // variant 3: the dense-slice G(tau,0) kernel (occupancy of its own)
+      const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, md == sdq::PAIR_TDISP_DENSE ? 3 : 0, r.count);
       B.launches.push_back(LaunchRec{sdq::KK_PAIR, r.nt, 0, md, grid, r.count,
                                      o_pa[md] + r.off * sizeof(PairItem), o_q + (qi++) * sizeof(Queue)});
     }
@@ -471,7 +473,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   }
   const Inst* d_inst = (const Inst*)(d + B.o_inst);
   const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
-  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local", "bstart"};
+  static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local", "bstart", "pair"};
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
     auto go = [&]() -> hipError_t {
@@ -820,9 +822,6 @@ sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, 
   for (int i = 0; i < count; ++i) {
     if (n_l > 0 && l_list[n_l - 1] > shape[i].m) return fail(ctx, SDQ_EINVAL, "l_list entry > m");
     if (n_l > 0 && !gt[i]) return fail(ctx, SDQ_EINVAL, "gt entry is NULL");
-    for (int a = 0; a < n_l; ++a)
-      if (l_list[a] % shape[i].k != 0 && l_list[a] != shape[i].m)
-        return fail(ctx, SDQ_EUNSUPPORTED, "dense slices: l must be a multiple of k or m (no propagation)");
   }
   if (count == 0) return SDQ_OK;
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -850,11 +849,19 @@ sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, 
     P.sweep.push_back(SweepItem{i, sdq::SW_STORE, 0, 0});
     P.sweep.push_back(SweepItem{i, sdq::SW_STORE | sdq::SW_ADJ, 0, 0});
     if (I.g || I.logdet || I.sign) P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
-    // one stage pair per l (every l is a stage boundary)
-    for (int a = 0; a < n_l; ++a) {
+    // group l by stage pair j (l == m -> nb, else l / k); the l inside a
+    // block are reached from its start by multiplying with the dense slices
+    for (int a = 0; a < n_l;) {
       const int l = l_list[a];
       const int j = (l == I.m) ? I.nb : l / I.k;
-      P.pair[sdq::PAIR_TDISP].push_back(PairItem{i, j, a, a + 1});
+      int b = a + 1;
+      while (b < n_l) {
+        const int l2 = l_list[b];
+        if (((l2 == I.m) ? I.nb : l2 / I.k) != j) break;
+        ++b;
+      }
+      P.pair[sdq::PAIR_TDISP_DENSE].push_back(PairItem{i, j, a, b});
+      a = b;
     }
   }
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {

@@ -2,7 +2,8 @@
 and sign against the oracle's same chain on the same dense matrices, for the
 Hubbard slices written out (also against the library's own Hubbard path) and
 for non-symmetric perturbed slices, at N = 16, 36, 64 and 100 up to
-beta = 40; the limits."""
+beta = 40; G(tau,0) at stage boundaries and inside blocks, also with a short
+last block; the limits."""
 import numpy as np
 import pytest
 import torch
@@ -76,7 +77,8 @@ def test_dense_limits():
 def test_dense_tdisp_matches_oracle(ctx, L, beta, perturb):
     E, Ei, lam, f, B = slices_for(L, beta, wl.BASE_SEED + 1650 + L + int(beta), perturb)
     m = B.shape[0]
-    ls = [0, 10, m // 2, m - 10, m]
+    # stage boundaries and l inside blocks (propagation over the dense slices)
+    ls = sorted({0, 3, 10, 19, m // 2, m // 2 + 7, m - 10, m - 1, m})
     Bd = torch.from_numpy(B).to(DEV)
     say(f"[gpu] sdq_greens_tdisp_dense L={L} beta={beta} perturbation={perturb} l={ls}")
     gts, gs, ld, _, st = ctx.greens_tdisp_dense([Bd], 10, ls)
@@ -91,9 +93,26 @@ def test_dense_tdisp_matches_oracle(ctx, L, beta, perturb):
         assert e <= 1e-10
 
 
-def test_dense_tdisp_needs_stage_boundaries(ctx):
+@pytest.mark.parametrize("n,m,k", [(16, 25, 10), (36, 7, 3), (64, 1, 1)])
+def test_dense_tdisp_ragged_blocks(ctx, n, m, k):
+    """m not a multiple of k (a short last block), every l from 0 to m."""
+    rng = np.random.default_rng(wl.BASE_SEED + 1700 + n + m)
+    B = np.stack([1.2 * np.eye(n) + (0.5 / np.sqrt(n)) * rng.normal(size=(n, n)) for _ in range(m)])
+    ls = list(range(m + 1))
+    say(f"[gpu] sdq_greens_tdisp_dense n={n} m={m} k={k} l=0..{m}")
+    gts, gs, _, _, st = ctx.greens_tdisp_dense([torch.from_numpy(B).to(DEV)], k, ls)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    worst = 0.0
+    for j, l in enumerate(ls):
+        worst = max(worst, relf(gts[0][j].cpu().numpy(), oracle.greens_tdisp_dense(B, k, l)))
+    say(f"[gpu]   worst relF {worst:.2e}")
+    assert worst <= 1e-10
+
+
+def test_dense_tdisp_rejects_l_beyond_m(ctx):
     B = torch.zeros(20, 16, 16, dtype=torch.float64, device=DEV)
-    say("[gpu] sdq_greens_tdisp_dense at l = 5 (not a multiple of k) -> SDQ_EUNSUPPORTED")
+    say("[gpu] sdq_greens_tdisp_dense at l = 21 > m -> SDQ_EINVAL")
     with pytest.raises(sdq.SdqError) as e:
-        ctx.greens_tdisp_dense([B], 10, [5])
-    assert e.value.status == sdq.SDQ_EUNSUPPORTED
+        ctx.greens_tdisp_dense([B], 10, [21])
+    assert e.value.status == sdq.SDQ_EINVAL
