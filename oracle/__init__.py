@@ -57,6 +57,7 @@ def lib():
         L.or_greens_tdisp_dense.argtypes = [c_int, c_int, c_int, d, c_int, d]
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
+        L.or_udt_complex.argtypes = [c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
         _lib = L
     return _lib
@@ -231,6 +232,16 @@ def udt(W):
     n = W.shape[0]
     U, T, D = np.zeros((n, n)), np.zeros((n, n)), np.zeros(n)
     _chk(lib().or_udt(n, _p(W), _p(U), _p(D), _p(T)))
+    return U, D, T
+
+
+def udt_complex(W):
+    """Complex UDT W P = Q R: U = Q, D = |diag R|, T = D^-1 R P^T (complex128)."""
+    W = np.ascontiguousarray(W, dtype=np.complex128)
+    n = W.shape[0]
+    U, T, D = np.zeros((n, n), np.complex128), np.zeros((n, n), np.complex128), np.zeros(n)
+    _chk(lib().or_udt_complex(n, _p(W.view(np.float64)), _p(U.view(np.float64)), _p(D),
+                              _p(T.view(np.float64))))
     return U, D, T
 
 

@@ -34,12 +34,15 @@
  *   or_greens_naive    Sec. 3 (the unstabilized product, negative control)
  *   or_greens_dense,   the same chains and inversions for slices given as
  *   or_greens_tdisp_dense  dense matrices (generalized slices)
+ *   or_udt_complex     Sec. 4.2.2 over the complex numbers (complex slices,
+ *                      App. B): complex column-pivoted Householder QR
  *   jacobi_svd,        Sec. 4.2 (the Jacobi SVD the paper compares with the
  *   or_greens_stab     QR; one-sided, Hestenes), as an independent stabilizer
  *                      of the same chain: a cross-check of the QR path
  * Readings of passages that are ambiguous or garbled in the paper are noted
  * where they are used.
  */
+#include <complex.h>
 #include <float.h>
 #include <math.h>
 #include <stdlib.h>
@@ -914,6 +917,137 @@ int or_cpqr(int n, double* A, double* Q, int* jpvt) {
 
 int or_udt(int n, const double* W, double* U, double* D, double* T) {
   udt(n, W, U, D, T);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Complex UDT (the complex slices of App. B need the decomposition of
+ * Sec. 4.2.2 over the complex numbers).  Row-major n x n matrices of
+ * double complex (interleaved re, im).                                      */
+
+/* 2-norm of the m entries x[0], x[inc], ... without overflow */
+static double cnrm2(int m, const double complex* x, int inc) {
+  double scale = 0.0, ssq = 1.0;
+  for (int i = 0; i < m; ++i) {
+    const double part[2] = {creal(x[(size_t)i * inc]), cimag(x[(size_t)i * inc])};
+    for (int h = 0; h < 2; ++h) {
+      const double a = fabs(part[h]);
+      if (a == 0.0) continue;
+      if (scale < a) {
+        ssq = 1.0 + ssq * (scale / a) * (scale / a);
+        scale = a;
+      } else {
+        ssq += (a / scale) * (a / scale);
+      }
+    }
+  }
+  return scale * sqrt(ssq);
+}
+
+/* Column-pivoted Householder QR over the complex numbers, in place:
+ * A_in P = Q R with Q = H_0 ... H_{n-1}, H_j = I - tau_j v_j v_j^H (unit
+ * leading entry of v_j implied; v_j stored below the diagonal).  The same
+ * pivot rule and norm downdating as the real cpqr.  Reflector of x = A[j:, j]
+ * with alpha = x_0: beta = -sign(Re alpha) ||x|| (real), tau = (beta -
+ * alpha) / beta, v = x / (alpha - beta), so that H^H x = beta e_0 and the
+ * diagonal of R is real; tau = 0 when x_1.. = 0 and alpha is real.  H_j^H is
+ * applied to the trailing columns: a <- a - conj(tau) v (v^H a). */
+static void cpqr_c(int n, double complex* A, int* jpvt, double complex* tau) {
+  double* vn1 = (double*)malloc(sizeof(double) * n);
+  double* vn2 = (double*)malloc(sizeof(double) * n);
+  const double tol3z = sqrt(2.220446049250313e-16);
+  for (int j = 0; j < n; ++j) {
+    jpvt[j] = j;
+    vn1[j] = cnrm2(n, A + j, n);
+    vn2[j] = vn1[j];
+  }
+  for (int i = 0; i < n; ++i) {
+    int p = i;
+    for (int j = i + 1; j < n; ++j)
+      if (vn1[j] > vn1[p]) p = j;
+    if (p != i) {
+      for (int r = 0; r < n; ++r) {
+        const double complex t = A[(size_t)r * n + i];
+        A[(size_t)r * n + i] = A[(size_t)r * n + p];
+        A[(size_t)r * n + p] = t;
+      }
+      int tj = jpvt[i]; jpvt[i] = jpvt[p]; jpvt[p] = tj;
+      vn1[p] = vn1[i];
+      vn2[p] = vn2[i];
+    }
+    const double complex alpha = A[(size_t)i * n + i];
+    const double xnorm = (i + 1 < n) ? cnrm2(n - i - 1, A + (size_t)(i + 1) * n + i, n) : 0.0;
+    double complex t_i = 0.0;
+    if (xnorm != 0.0 || cimag(alpha) != 0.0) {
+      const double beta = -copysign(hypot(hypot(creal(alpha), cimag(alpha)), xnorm), creal(alpha));
+      t_i = (beta - alpha) / beta;
+      const double complex s = 1.0 / (alpha - beta);
+      for (int r = i + 1; r < n; ++r) A[(size_t)r * n + i] *= s;
+      A[(size_t)i * n + i] = beta;
+    }
+    tau[i] = t_i;
+    if (t_i != 0.0) {
+      for (int j = i + 1; j < n; ++j) {
+        double complex w = A[(size_t)i * n + j];
+        for (int r = i + 1; r < n; ++r) w += conj(A[(size_t)r * n + i]) * A[(size_t)r * n + j];
+        w *= conj(t_i);
+        A[(size_t)i * n + j] -= w;
+        for (int r = i + 1; r < n; ++r) A[(size_t)r * n + j] -= w * A[(size_t)r * n + i];
+      }
+    }
+    for (int j = i + 1; j < n; ++j) {
+      if (vn1[j] == 0.0) continue;
+      double temp = cabs(A[(size_t)i * n + j]) / vn1[j];
+      temp = 1.0 - temp * temp;
+      if (temp < 0.0) temp = 0.0;
+      const double ratio = vn1[j] / vn2[j];
+      const double temp2 = temp * ratio * ratio;
+      if (temp2 <= tol3z) {
+        vn1[j] = (i + 1 < n) ? cnrm2(n - i - 1, A + (size_t)(i + 1) * n + j, n) : 0.0;
+        vn2[j] = vn1[j];
+      } else {
+        vn1[j] *= sqrt(temp);
+      }
+    }
+  }
+  free(vn1);
+  free(vn2);
+}
+
+/* Complex UDT: W P = Q R, U = Q (unitary), D = |diag R| (diag R is real),
+ * T = D^{-1} R P^T (a row with D_i = 0 is left undivided). */
+int or_udt_complex(int n, const double* Wd, double* Ud, double* D, double* Td) {
+  if (n < 1 || !Wd || !Ud || !D || !Td) return OR_EINVAL;
+  const double complex* W = (const double complex*)Wd;
+  double complex* U = (double complex*)Ud;
+  double complex* T = (double complex*)Td;
+  double complex* F = (double complex*)malloc(sizeof(double complex) * (size_t)n * n);
+  double complex* tau = (double complex*)malloc(sizeof(double complex) * n);
+  int* jpvt = (int*)malloc(sizeof(int) * n);
+  memcpy(F, W, sizeof(double complex) * (size_t)n * n);
+  cpqr_c(n, F, jpvt, tau);
+  /* Q = H_0 (H_1 (... H_{n-1} I)) */
+  for (size_t e = 0; e < (size_t)n * n; ++e) U[e] = 0.0;
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (tau[i] == 0.0) continue;
+    for (int j = 0; j < n; ++j) {
+      double complex w = U[(size_t)i * n + j];
+      for (int r = i + 1; r < n; ++r) w += conj(F[(size_t)r * n + i]) * U[(size_t)r * n + j];
+      w *= tau[i];
+      U[(size_t)i * n + j] -= w;
+      for (int r = i + 1; r < n; ++r) U[(size_t)r * n + j] -= w * F[(size_t)r * n + i];
+    }
+  }
+  for (size_t e = 0; e < (size_t)n * n; ++e) T[e] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    D[i] = fabs(creal(F[(size_t)i * n + i]));
+    const double s = D[i] > 0.0 ? 1.0 / D[i] : 1.0;
+    for (int j = i; j < n; ++j) T[(size_t)i * n + jpvt[j]] = F[(size_t)i * n + j] * s;
+  }
+  free(F);
+  free(tau);
+  free(jpvt);
   return OR_OK;
 }
 

@@ -37,6 +37,8 @@ int or_greens_dense(int n, int m, int k, const double* slices, double* G, double
 int or_greens_tdisp_dense(int n, int m, int k, const double* slices, int l, double* Gt);
 int or_cpqr(int n, double* A, double* Q, int* jpvt);
 int or_udt(int n, const double* W, double* U, double* D, double* T);
+/* complex UDT; W, U, T interleaved (re, im) n x n, D real n */
+int or_udt_complex(int n, const double* W, double* U, double* D, double* T);
 int or_expk_planewave(int L, double t, double dtau, double s, double* out);
 
 #endif

@@ -545,3 +545,59 @@ def test_dense_slices_time_displaced():
     G = np.linalg.inv(np.eye(n) + prod[m])
     for l in (0, 2, 4, 6):
         assert relF(oracle.greens_tdisp_dense(sl, 2, l), prod[l] @ G) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# complex UDT (Sec. 4.2.2 over the complex numbers, for the complex slices of
+# App. B): pinned by LAPACK's complex pivoted QR (zgeqp3, through scipy) with
+# the same reflector convention, by the real UDT on real input, and by the
+# properties of a pivoted QR.
+def _cmat(n, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return scale * (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 33])
+def test_complex_udt_matches_lapack_pivoted_qr(n):
+    import scipy.linalg as sl
+    W = _cmat(n, 4100 + n)
+    U, D, T = oracle.udt_complex(W)
+    Q, R, piv = sl.qr(W, pivoting=True)
+    assert np.array_equal(np.argsort(-np.abs(np.diag(R)), kind="stable"), np.arange(n)) or n == 1
+    Dl = np.abs(np.diag(R))
+    Tl = np.zeros((n, n), complex)
+    Tl[:, piv] = R / Dl[:, None]
+    assert np.allclose(D, Dl, rtol=1e-12, atol=0)
+    assert np.linalg.norm(U - Q) <= 1e-12 * np.sqrt(n)
+    assert np.linalg.norm(T - Tl) <= 1e-12 * np.linalg.norm(Tl)
+
+
+@pytest.mark.parametrize("n,scale", [(8, 1.0), (24, 1e-150), (40, 1e150)])
+def test_complex_udt_properties(n, scale):
+    W = _cmat(n, 4200 + n, scale)
+    U, D, T = oracle.udt_complex(W)
+    assert np.linalg.norm(U.conj().T @ U - np.eye(n)) <= 1e-13 * n
+    assert np.linalg.norm(U @ (D[:, None] * T) - W) <= 1e-13 * n * np.linalg.norm(W)
+    assert np.all(D[:-1] >= D[1:] * (1 - 1e-12))  # pivoting: |R_ii| non-increasing
+    assert abs(np.sum(np.log(D)) - np.linalg.slogdet(W)[1]) <= 1e-10 * n
+    # each row of T has one entry of modulus 1 (the diagonal of R, real, / D)
+    assert np.allclose(np.sort(np.abs(T), axis=1)[:, -1] >= 1 - 1e-12, True)
+
+
+def test_complex_udt_of_real_input_is_the_real_udt():
+    W = np.random.default_rng(4300).normal(size=(20, 20))
+    Uc, Dc, Tc = oracle.udt_complex(W.astype(complex))
+    U, D, T = oracle.udt(W)
+    assert np.abs(Uc.imag).max() == 0 and np.abs(Tc.imag).max() == 0
+    assert np.allclose(Uc.real, U, rtol=0, atol=1e-14) and np.allclose(Dc, D, rtol=1e-14, atol=0)
+    assert np.allclose(Tc.real, T, rtol=0, atol=1e-13)
+
+
+def test_complex_udt_of_a_diagonal_phase_matrix():
+    # W = diag(e^{i theta_j} s_j): a permutation and phases only
+    s = np.array([0.5, 3.0, 1.0, 2.0])
+    th = np.array([0.3, -1.2, 2.0, 3.1])
+    W = np.diag(s * np.exp(1j * th))
+    U, D, T = oracle.udt_complex(W)
+    assert np.allclose(D, [3.0, 2.0, 1.0, 0.5], rtol=1e-15)
+    assert np.allclose(U @ (D[:, None] * T), W, atol=1e-15)
