@@ -70,7 +70,7 @@ def main():
                              "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
                              "hubbard_L8_b20_phi_hmc128", "hubbard_L8_b40_dense128",
-                             "hubbard_L16_b40_batch128"],
+                             "hubbard_L16_b40_batch128", "udt_complex_n64_batch4096"],
                     help="the default is the headline workload; the others time the same library "
                          "on the mixed-size batch (equal-time G), the continuous-field batch "
                          "(log|det| + gradient) and the L=16 batch (G + G(tau,0) at every slice)")
@@ -107,6 +107,8 @@ def main():
         print(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written",
               file=sys.stderr, flush=True)
         del src, dst
+    if args.workload == "udt_complex_n64_batch4096":
+        return run_udt_complex(args, dev, sdq, wl)
     W = wl.workload(args.workload, scale=args.scale)
     insts = W.instances
     l_list = W.l_list or []
@@ -452,6 +454,73 @@ def main():
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain and args.stab == "qr":
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def udt_complex_flops(n):
+    """Real flops of one complex UDT: the Householder QR (16/3 n^3) and the
+    formation of Q (16/3 n^3); a complex multiply-add is 8 real flops."""
+    return 32.0 / 3.0 * n ** 3
+
+
+def run_udt_complex(args, dev, sdq, wl):
+    """Complex UDT of 4096 graded complex 64 x 64 matrices per step (the
+    decomposition complex slices need, Sec. 4.2.2 / App. B)."""
+    import numpy as np
+    import torch
+
+    count, n = 4096, 64
+    Wh = wl.complex_batch(count, n)
+    Wd = torch.from_numpy(Wh).to(dev)
+    ctx = sdq.Context(0)
+    print(f"[bench] udt_complex_n64_batch4096: {count} complex matrices, n={n}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        u, d, t = ctx.udt_complex(Wd)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        u, d, t = ctx.udt_complex(Wd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_k, ms_k = ctx.kernel_stats("udt_complex")
+    ctx.set_profiling(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    launch_s = ms_k / max(n_k, 1) * 1e-3
+    flops = count * udt_complex_flops(n)
+    # the FP64 vector peak (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz)
+    peak_valu = 78.6e12
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; kernel {launch_s * 1e3:.3f} ms x {n_k}",
+          file=sys.stderr, flush=True)
+    ok = bool(torch.isfinite(d).all().item())
+    out = {
+        "metric": "complex UDT factorizations/sec (FP64, n=64, 4096 per batch)",
+        "value": count / (ms_step * 1e-3),
+        "unit": "matrices/s (each: complex pivoted QR, U, D, T)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "udt_complex_n64_batch4096", "matrices": count, "n": n,
+                   "inputs": "complex Gaussian columns scaled over 30 decades, random column order"},
+        "roofline": {"kernel": "udt_complex", "bound": "alu", "achieved": flops / launch_s / 1e12,
+                     "peak": peak_valu / 1e12, "unit": "TFLOP/s", "frac": flops / launch_s / peak_valu,
+                     "traffic": None, "flops_per_launch": flops, "launch_ms": launch_s * 1e3,
+                     "bytes_per_launch": count * n * n * 16 * 3 + count * n * 8},
+        "status_ok": ok,
+    }
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        sample = [Wh[b] for b in range(256)]
+        print(f"[bench] cpu oracle: {len(sample)} complex UDTs on {threads} threads", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(oracle.udt_complex, sample))
+        dt = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "matrices/s", "cores": threads,
+                               "kind": "oracle", "sample": f"256 of the 4096 matrices; {dt:.1f} s wall"}
     print(json.dumps(out), flush=True)
 
 

@@ -188,6 +188,17 @@ sdq_status sdq_release(sdq_ctx* ctx, uint64_t ckpt_handle);
 sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u,
                    double* d, double* t);
 
+/* Complex UDT (Sec. 4.2.2 over the complex numbers, for complex slices such
+ * as those of App. B): W P = Q R by column-pivoted Householder QR with real
+ * diag R, U = Q (unitary), D = |diag R|, T = D^{-1} R P^T (a row with
+ * D_i = 0 is left undivided), for `count` complex n x n matrices stored back
+ * to back in w.  w, u, t: [count][n][n] complex, each entry two doubles
+ * (re, im), row-major, device; d: [count][n] real, device.  The caller owns
+ * all buffers; the call is ordered on the context's stream.  1 <= n <= 64
+ * (SDQ_EUNSUPPORTED above); SDQ_EINVAL for a NULL buffer or count < 0. */
+sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u,
+                           double* d, double* t);
+
 /* Stabilized chain of one instance set (Sec. 4.1): the UDT factors of
  * B_m...B_1 for each chain, u, t [count][n][n], d [count][n] (device).
  * All chains must share n. */

@@ -30,7 +30,7 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
            "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense",
-           "sdq_greens_tdisp_dense")
+           "sdq_greens_tdisp_dense", "sdq_udt_complex")
 
 
 class SdqError(RuntimeError):
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_logdet_grad.argtypes = [vp, ctypes.c_uint64, P(_Instance), i32, P(vp), vp, vp, vp]
     L.sdq_release.argtypes = [vp, ctypes.c_uint64]
     L.sdq_udt.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.sdq_udt_complex.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.sdq_chain_udt.argtypes = [vp, P(_Instance), i32, vp, vp, vp]
     L.sdq_tune.argtypes = [vp, P(i32), i32, ctypes.c_char_p]
     L.sdq_set_graphs.argtypes = [vp, ctypes.c_int]
@@ -243,6 +244,19 @@ class Context:
         _check_tensor(w, "w", (cnt, n, n), self.tdev)
         u, t, d = self._empty(cnt, n, n), self._empty(cnt, n, n), self._empty(cnt, n)
         self._chk(self.lib.sdq_udt(self.h, n, cnt, _ptr(w), _ptr(u), _ptr(d), _ptr(t)))
+        return u, d, t
+
+    def udt_complex(self, w):
+        """w: complex128 [count, n, n] -> U [count,n,n] complex, D [count,n] real,
+        T [count,n,n] complex (sdq_udt_complex)."""
+        cnt, n, _ = w.shape
+        if w.dtype != torch.complex128 or not w.is_contiguous() or w.device != self.tdev:
+            raise ValueError(f"w: need a contiguous complex128 tensor on {self.tdev}, got {w.dtype} on {w.device}")
+        u = torch.empty(cnt, n, n, dtype=torch.complex128, device=self.tdev)
+        t = torch.empty(cnt, n, n, dtype=torch.complex128, device=self.tdev)
+        d = self._empty(cnt, n)
+        self._chk(self.lib.sdq_udt_complex(self.h, n, cnt, _ptr(torch.view_as_real(w)),
+                                           _ptr(torch.view_as_real(u)), _ptr(d), _ptr(torch.view_as_real(t))))
         return u, d, t
 
     def chain_udt(self, chains):

@@ -1,0 +1,242 @@
+// sdq_complex.hip -- complex UDT of independent matrices (Sec. 4.2.2 over the
+// complex numbers, as the complex slices of App. B need it):
+//   W P = Q R (column-pivoted Householder QR), U = Q, D = |diag R|,
+//   T = D^{-1} R P^T.
+// One workgroup (four wave64s) per matrix, the matrix resident in LDS as
+// interleaved (re, im) pairs, n <= 64.  Reflector convention: for x = A[i:, i]
+// with alpha = x_0, beta = -sign(Re alpha) ||x|| is real, tau = (beta -
+// alpha) / beta, v = x / (alpha - beta); H = I - tau v v^H, H^H x = beta e_0,
+// so the diagonal of R is real.  Pivot: the first column of largest remaining
+// norm, norms downdated with an exact recompute when cancellation threatens
+// (Drmac & Bujanovic).  Q is formed in place from the reflectors after R has
+// been written out (backward accumulation, Q = H_0 H_1 ... H_{n-1}).
+#include <hip/hip_runtime.h>
+
+#include "sdq_internal.h"
+
+namespace sdq {
+namespace {
+
+constexpr int kCN = 64;           // largest n
+constexpr int kCLD = kCN + 1;     // LDS row stride (in complex entries)
+constexpr int kCThreads = 256;    // four waves: wave w takes rows w, w+4, ...
+
+struct cplx {
+  double x, y;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// conj(a) * b
+__device__ __forceinline__ cplx cjmul(cplx a, cplx b) { return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x}; }
+
+struct CSmem {
+  cplx a[kCN * kCLD];
+  cplx red[4][kCN];
+  cplx tau[kCN];
+  double vn1[kCN], vn2[kCN];
+  int jpvt[kCN], ipiv[kCN];
+  int piv;
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// 2-norm of A[r0..n-1][c] by one lane (max-scaled, so no overflow)
+__device__ double col_norm(const CSmem& S, int r0, int n, int c) {
+  double mx = 0.0;
+  for (int r = r0; r < n; ++r) mx = fmax(mx, fmax(fabs(S.a[r * kCLD + c].x), fabs(S.a[r * kCLD + c].y)));
+  if (mx == 0.0) return 0.0;
+  const double inv = 1.0 / mx;
+  double s = 0.0;
+  for (int r = r0; r < n; ++r) {
+    const double p = S.a[r * kCLD + c].x * inv, q = S.a[r * kCLD + c].y * inv;
+    s += p * p + q * q;
+  }
+  return mx * sqrt(s);
+}
+
+// A[i:, c] <- (I - t v v^H) A[i:, c] for the columns c0 <= c < n, v = A[i:, i]
+// with v_i = 1 implied (vi1) or stored; four waves split the rows.
+__device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane;
+  cplx part = {0.0, 0.0};
+  if (c >= c0 && c < n) {
+    for (int r = i + w; r < n; r += 4) {
+      const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
+      const cplx p = cjmul(v, S.a[r * kCLD + c]);
+      part.x += p.x;
+      part.y += p.y;
+    }
+  }
+  S.red[w][c] = part;
+  __syncthreads();
+  if (c >= c0 && c < n) {
+    cplx s = {S.red[0][c].x + S.red[1][c].x + S.red[2][c].x + S.red[3][c].x,
+              S.red[0][c].y + S.red[1][c].y + S.red[2][c].y + S.red[3][c].y};
+    s = cmul(t, s);
+    for (int r = i + w; r < n; r += 4) {
+      const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
+      const cplx d = cmul(v, s);
+      S.a[r * kCLD + c].x -= d.x;
+      S.a[r * kCLD + c].y -= d.y;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, const double* __restrict__ w,
+                                                           double* __restrict__ u, double* __restrict__ d,
+                                                           double* __restrict__ t) {
+  __shared__ CSmem S;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double tol3z = sqrt(2.220446049250313e-16);
+  for (int b = blockIdx.x; b < count; b += gridDim.x) {
+    const size_t off = (size_t)b * n * n;
+    const cplx* W = reinterpret_cast<const cplx*>(w) + off;
+    for (int e = tid; e < n * n; e += kCThreads) S.a[(e / n) * kCLD + e % n] = W[e];
+    __syncthreads();
+    if (tid < n) {
+      S.jpvt[tid] = tid;
+      S.vn1[tid] = col_norm(S, 0, n, tid);
+      S.vn2[tid] = S.vn1[tid];
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+      // pivot: first column of largest remaining norm (wave 0)
+      if (wv == 0) {
+        double v = (lane >= i && lane < n) ? S.vn1[lane] : -1.0;
+        int p = lane;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double v2 = __shfl_xor(v, o);
+          const int p2 = __shfl_xor(p, o);
+          if (v2 > v || (v2 == v && p2 < p)) {
+            v = v2;
+            p = p2;
+          }
+        }
+        if (lane == 0) S.piv = p;
+      }
+      __syncthreads();
+      const int p = S.piv;
+      if (p != i) {
+        if (tid < n) {
+          const cplx x = S.a[tid * kCLD + i];
+          S.a[tid * kCLD + i] = S.a[tid * kCLD + p];
+          S.a[tid * kCLD + p] = x;
+        }
+        if (tid == 0) {
+          const int tj = S.jpvt[i];
+          S.jpvt[i] = S.jpvt[p];
+          S.jpvt[p] = tj;
+          S.vn1[p] = S.vn1[i];
+          S.vn2[p] = S.vn2[i];
+        }
+        __syncthreads();
+      }
+      // reflector of A[i:, i] (wave 0; lane handles row i + 1 + lane)
+      if (wv == 0) {
+        const int r = i + 1 + lane;
+        const cplx x = r < n ? S.a[r * kCLD + i] : cplx{0.0, 0.0};
+        const double mx = wave_max(fmax(fabs(x.x), fabs(x.y)));
+        double xnorm = 0.0;
+        if (mx > 0.0) {
+          const double p0 = x.x / mx, q0 = x.y / mx;
+          xnorm = mx * sqrt(wave_sum(p0 * p0 + q0 * q0));
+        }
+        const cplx al = S.a[i * kCLD + i];
+        cplx ti = {0.0, 0.0};
+        if (xnorm != 0.0 || al.y != 0.0) {
+          const double nrm = hypot(hypot(al.x, al.y), xnorm);
+          const double beta = -copysign(nrm, al.x);
+          ti = {(beta - al.x) / beta, -al.y / beta};
+          // s = 1 / (alpha - beta), scaled so that no square overflows
+          const cplx dn = {al.x - beta, al.y};
+          const double sm = fmax(fabs(dn.x), fabs(dn.y));
+          const double ax = dn.x / sm, ay = dn.y / sm, den = (ax * ax + ay * ay) * sm;
+          const cplx s = {ax / den, -ay / den};
+          if (r < n) S.a[r * kCLD + i] = cmul(x, s);
+          if (lane == 0) S.a[i * kCLD + i] = {beta, 0.0};
+        }
+        if (lane == 0) S.tau[i] = ti;
+      }
+      __syncthreads();
+      const cplx ti = S.tau[i];
+      if (ti.x != 0.0 || ti.y != 0.0) apply_reflector(S, n, i, i + 1, cplx{ti.x, -ti.y}, true);
+      // downdate the remaining norms (wave 0, lane = column)
+      if (wv == 0 && lane > i && lane < n && S.vn1[lane] != 0.0) {
+        const cplx aij = S.a[i * kCLD + lane];
+        double tmp = hypot(aij.x, aij.y) / S.vn1[lane];
+        tmp = 1.0 - tmp * tmp;
+        if (tmp < 0.0) tmp = 0.0;
+        const double ratio = S.vn1[lane] / S.vn2[lane];
+        if (tmp * ratio * ratio <= tol3z) {
+          S.vn1[lane] = i + 1 < n ? col_norm(S, i + 1, n, lane) : 0.0;
+          S.vn2[lane] = S.vn1[lane];
+        } else {
+          S.vn1[lane] *= sqrt(tmp);
+        }
+      }
+      __syncthreads();
+    }
+    // D = |diag R| (real), T = D^{-1} R P^T (rows with D = 0 undivided)
+    if (tid < n) {
+      d[(size_t)b * n + tid] = fabs(S.a[tid * kCLD + tid].x);
+      S.ipiv[S.jpvt[tid]] = tid;
+    }
+    __syncthreads();
+    cplx* T = reinterpret_cast<cplx*>(t) + off;
+    for (int e = tid; e < n * n; e += kCThreads) {
+      const int r = e / n, col = e % n, c = S.ipiv[col];
+      cplx v = {0.0, 0.0};
+      if (c >= r) {
+        const double dr = fabs(S.a[r * kCLD + r].x);
+        const double sc = dr > 0.0 ? 1.0 / dr : 1.0;
+        v = {S.a[r * kCLD + c].x * sc, S.a[r * kCLD + c].y * sc};
+      }
+      T[e] = v;
+    }
+    __syncthreads();
+    // Q in place: for i = n-1 .. 0, apply H_i to columns i+1.. and turn
+    // column i into H_i e_i
+    for (int i = n - 1; i >= 0; --i) {
+      const cplx ti = S.tau[i];
+      if (i < n - 1 && (ti.x != 0.0 || ti.y != 0.0)) apply_reflector(S, n, i, i + 1, ti, true);
+      if (tid < n) {
+        if (tid > i) {
+          const cplx v = S.a[tid * kCLD + i];
+          S.a[tid * kCLD + i] = cplx{-(ti.x * v.x - ti.y * v.y), -(ti.x * v.y + ti.y * v.x)};
+        } else if (tid == i) {
+          S.a[tid * kCLD + i] = cplx{1.0 - ti.x, -ti.y};
+        } else {
+          S.a[tid * kCLD + i] = cplx{0.0, 0.0};
+        }
+      }
+      __syncthreads();
+    }
+    cplx* U = reinterpret_cast<cplx*>(u) + off;
+    for (int e = tid; e < n * n; e += kCThreads) U[e] = S.a[(e / n) * kCLD + e % n];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int complex_udt_max_n() { return kCN; }
+
+hipError_t launch_udt_complex(int n, int count, const double* w, double* u, double* d, double* t, int grid,
+                              hipStream_t s) {
+  if (n < 1 || n > kCN || count < 1 || grid < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_udt_complex, dim3(grid), dim3(kCThreads), 0, s, n, count, w, u, d, t);
+  return hipGetLastError();
+}
+
+}  // namespace sdq

@@ -180,6 +180,11 @@ hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* 
                         Queue* q, int grid, hipStream_t s);
 hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
                        int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s);
+// complex UDT of independent matrices (sdq_complex.hip): w, u, t interleaved
+// (re, im) [count][n][n], d [count][n]; 1 <= n <= complex_udt_max_n()
+int complex_udt_max_n();
+hipError_t launch_udt_complex(int n, int count, const double* w, double* u, double* d, double* t, int grid,
+                              hipStream_t s);
 hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, double* d, double* t,
                       hipStream_t s);
 // M <- left M right for count n x n matrices (device pointer table), n <= 128

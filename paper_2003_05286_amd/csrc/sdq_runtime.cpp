@@ -1109,6 +1109,21 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
   return timed(ctx, "udt", [&] { return sdq::launch_udt(nt, n, count, w, u, d, t, ctx->stream); });
 }
 
+sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u, double* d,
+                           double* t) {
+  if (!ctx) return SDQ_EINVAL;
+  if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
+  if (n > sdq::complex_udt_max_n()) return fail(ctx, SDQ_EUNSUPPORTED, "complex UDT: n > 64 is not supported");
+  if (count == 0) return SDQ_OK;
+  if (!w || !u || !d || !t) return fail(ctx, SDQ_EINVAL, "null pointer");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  ctx->err.clear();
+  // two workgroups per CU (73 KB of LDS each), grid-stride over the matrices
+  const int grid = std::max(1, std::min(count, 2 * ctx->num_cu));
+  return timed(ctx, "udt_complex",
+               [&] { return sdq::launch_udt_complex(n, count, w, u, d, t, grid, ctx->stream); });
+}
+
 sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf,
                            const double* unif, int32_t* accepted, int32_t* status) {
   if (!ctx) return SDQ_EINVAL;

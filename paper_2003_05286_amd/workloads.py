@@ -164,6 +164,19 @@ def uneven_batch(count: int = 512, Ls=(6, 8, 10, 12), betas=(10, 20, 40),
     return out
 
 
+def complex_batch(count: int, n: int, seed: int = BASE_SEED + 8, decades: float = 30.0) -> np.ndarray:
+    """Seeded complex n x n matrices shaped like the products a stabilized
+    chain factorizes: X diag(s) with X complex Gaussian and column scales s
+    spanning `decades` orders of magnitude, the columns in random order
+    (so the pivoting has work to do).  [count, n, n] complex128."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(count, n, n)) + 1j * rng.normal(size=(count, n, n))
+    s = 10.0 ** (-np.linspace(0.0, decades, n))
+    for b in range(count):
+        X[b] *= s[rng.permutation(n)][None, :]
+    return X
+
+
 def workload(name: str, scale: float = 1.0) -> Workload:
     """Named workloads.  `scale` < 1 shrinks the batch (never the shapes)."""
     def nb(x):
