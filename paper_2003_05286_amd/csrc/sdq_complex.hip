@@ -34,7 +34,6 @@ struct CSmem {
   cplx tau[kCN];
   double vn1[kCN], vn2[kCN];
   int jpvt[kCN], ipiv[kCN];
-  int piv;
 };
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -62,6 +61,41 @@ __device__ double col_norm(const CSmem& S, int r0, int n, int c) {
   return mx * sqrt(s);
 }
 
+// orders the LDS accesses of one wave's lanes around it (compiler fence)
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 2-norm of the wave's 64 complex values: the plain sum of squares where it
+// neither overflows nor underflows, else max-scaled
+__device__ __forceinline__ double wave_norm(cplx x) {
+  const double ss = wave_sum(x.x * x.x + x.y * x.y);
+  if (ss > 1e-280 && ss < 1e280) return sqrt(ss);
+  const double mx = wave_max(fmax(fabs(x.x), fabs(x.y)));
+  if (mx == 0.0) return 0.0;
+  const double p0 = x.x / mx, q0 = x.y / mx;
+  return mx * sqrt(wave_sum(p0 * p0 + q0 * q0));
+}
+
+// norm downdate of column `lane` after step i (exact recompute when the
+// downdated value has lost too many digits)
+__device__ __forceinline__ void downdate(CSmem& S, int n, int i, int lane, double tol3z) {
+  if (lane > i && lane < n && S.vn1[lane] != 0.0) {
+    const cplx aij = S.a[i * kCLD + lane];
+    double tmp = hypot(aij.x, aij.y) / S.vn1[lane];
+    tmp = 1.0 - tmp * tmp;
+    if (tmp < 0.0) tmp = 0.0;
+    const double ratio = S.vn1[lane] / S.vn2[lane];
+    if (tmp * ratio * ratio <= tol3z) {
+      S.vn1[lane] = i + 1 < n ? col_norm(S, i + 1, n, lane) : 0.0;
+      S.vn2[lane] = S.vn1[lane];
+    } else {
+      S.vn1[lane] *= sqrt(tmp);
+    }
+  }
+}
+
 // A[i:, c] <- (I - t v v^H) A[i:, c] for the columns c0 <= c < n, v = A[i:, i]
 // with v_i = 1 implied (vi1) or stored; four waves split the rows.
 __device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1) {
@@ -69,6 +103,8 @@ __device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1
   const int c = lane;
   cplx part = {0.0, 0.0};
   if (c >= c0 && c < n) {
+    // unrolled so that the LDS loads of several rows are in flight at once
+#pragma unroll 8
     for (int r = i + w; r < n; r += 4) {
       const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
       const cplx p = cjmul(v, S.a[r * kCLD + c]);
@@ -82,6 +118,7 @@ __device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1
     cplx s = {S.red[0][c].x + S.red[1][c].x + S.red[2][c].x + S.red[3][c].x,
               S.red[0][c].y + S.red[1][c].y + S.red[2][c].y + S.red[3][c].y};
     s = cmul(t, s);
+#pragma unroll 8
     for (int r = i + w; r < n; r += 4) {
       const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
       const cplx d = cmul(v, s);
@@ -110,8 +147,12 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
     }
     __syncthreads();
     for (int i = 0; i < n; ++i) {
-      // pivot: first column of largest remaining norm (wave 0)
+      // wave 0 alone, lane-synchronous (LDS operations of one wave complete
+      // in order): the norm downdate of step i-1, the pivot, the column swap
+      // and the reflector of step i; the other waves wait at the barrier
       if (wv == 0) {
+        if (i > 0) downdate(S, n, i - 1, lane, tol3z);
+        wave_fence();
         double v = (lane >= i && lane < n) ? S.vn1[lane] : -1.0;
         int p = lane;
 #pragma unroll
@@ -123,35 +164,25 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
             p = p2;
           }
         }
-        if (lane == 0) S.piv = p;
-      }
-      __syncthreads();
-      const int p = S.piv;
-      if (p != i) {
-        if (tid < n) {
-          const cplx x = S.a[tid * kCLD + i];
-          S.a[tid * kCLD + i] = S.a[tid * kCLD + p];
-          S.a[tid * kCLD + p] = x;
+        if (p != i) {
+          if (lane < n) {
+            const cplx x = S.a[lane * kCLD + i];
+            S.a[lane * kCLD + i] = S.a[lane * kCLD + p];
+            S.a[lane * kCLD + p] = x;
+          }
+          if (lane == 0) {
+            const int tj = S.jpvt[i];
+            S.jpvt[i] = S.jpvt[p];
+            S.jpvt[p] = tj;
+            S.vn1[p] = S.vn1[i];
+            S.vn2[p] = S.vn2[i];
+          }
         }
-        if (tid == 0) {
-          const int tj = S.jpvt[i];
-          S.jpvt[i] = S.jpvt[p];
-          S.jpvt[p] = tj;
-          S.vn1[p] = S.vn1[i];
-          S.vn2[p] = S.vn2[i];
-        }
-        __syncthreads();
-      }
-      // reflector of A[i:, i] (wave 0; lane handles row i + 1 + lane)
-      if (wv == 0) {
+        wave_fence();
+        // reflector of A[i:, i]; lane handles row i + 1 + lane
         const int r = i + 1 + lane;
         const cplx x = r < n ? S.a[r * kCLD + i] : cplx{0.0, 0.0};
-        const double mx = wave_max(fmax(fabs(x.x), fabs(x.y)));
-        double xnorm = 0.0;
-        if (mx > 0.0) {
-          const double p0 = x.x / mx, q0 = x.y / mx;
-          xnorm = mx * sqrt(wave_sum(p0 * p0 + q0 * q0));
-        }
+        const double xnorm = wave_norm(x);
         const cplx al = S.a[i * kCLD + i];
         cplx ti = {0.0, 0.0};
         if (xnorm != 0.0 || al.y != 0.0) {
@@ -162,8 +193,9 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
           const cplx dn = {al.x - beta, al.y};
           const double sm = fmax(fabs(dn.x), fabs(dn.y));
           const double ax = dn.x / sm, ay = dn.y / sm, den = (ax * ax + ay * ay) * sm;
-          const cplx s = {ax / den, -ay / den};
-          if (r < n) S.a[r * kCLD + i] = cmul(x, s);
+          const cplx sc = {ax / den, -ay / den};
+          if (r < n) S.a[r * kCLD + i] = cmul(x, sc);
+          wave_fence();
           if (lane == 0) S.a[i * kCLD + i] = {beta, 0.0};
         }
         if (lane == 0) S.tau[i] = ti;
@@ -171,21 +203,6 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
       __syncthreads();
       const cplx ti = S.tau[i];
       if (ti.x != 0.0 || ti.y != 0.0) apply_reflector(S, n, i, i + 1, cplx{ti.x, -ti.y}, true);
-      // downdate the remaining norms (wave 0, lane = column)
-      if (wv == 0 && lane > i && lane < n && S.vn1[lane] != 0.0) {
-        const cplx aij = S.a[i * kCLD + lane];
-        double tmp = hypot(aij.x, aij.y) / S.vn1[lane];
-        tmp = 1.0 - tmp * tmp;
-        if (tmp < 0.0) tmp = 0.0;
-        const double ratio = S.vn1[lane] / S.vn2[lane];
-        if (tmp * ratio * ratio <= tol3z) {
-          S.vn1[lane] = i + 1 < n ? col_norm(S, i + 1, n, lane) : 0.0;
-          S.vn2[lane] = S.vn1[lane];
-        } else {
-          S.vn1[lane] *= sqrt(tmp);
-        }
-      }
-      __syncthreads();
     }
     // D = |diag R| (real), T = D^{-1} R P^T (rows with D = 0 undivided)
     if (tid < n) {
