@@ -36,15 +36,69 @@ struct CSmem {
   int jpvt[kCN], ipiv[kCN];
 };
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+// Cross-lane reductions over the wave on the DPP paths of the VALU (no LDS
+// round trips): swap neighbours (quad_perm 1,0,3,2 and 2,3,0,1), mirror
+// within 8 and 16 lanes, then broadcast lane 15 of each row into the next
+// and lane 31 into the upper half; lane 63 then holds the result, which
+// readlane makes uniform.  A lane outside a step's row mask keeps `old`.
+constexpr int kDppSteps[6] = {0xB1, 0x4E, 0x141, 0x140, 0x142, 0x143};
+constexpr int kDppRows[6] = {0xf, 0xf, 0xf, 0xf, 0xa, 0xc};
+
+template <int S>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, kDppSteps[S], kDppRows[S], 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), kDppSteps[S], kDppRows[S], 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+template <int S>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, kDppSteps[S], kDppRows[S], 0xf, false);
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, 63), hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int S = 0>
+__device__ __forceinline__ double wave_sum_(double v) {
+  if constexpr (S == 6) {
+    return lane63(v);
+  } else {
+    return wave_sum_<S + 1>(v + dpp_d<S>(0.0, v));
+  }
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_<0>(v); }
+
+// for values >= 0
+template <int S = 0>
+__device__ __forceinline__ double wave_max_(double v) {
+  if constexpr (S == 6) {
+    return lane63(v);
+  } else {
+    return wave_max_<S + 1>(fmax(v, dpp_d<S>(0.0, v)));
+  }
+}
+__device__ __forceinline__ double wave_max(double v) { return wave_max_<0>(v); }
+
+// (value, index) of the largest value, the lowest index among equal ones;
+// the result is the same for every reduction order
+template <int S = 0>
+__device__ __forceinline__ void wave_argmax_(double& v, int& p) {
+  if constexpr (S < 6) {
+    const double v2 = dpp_d<S>(v, v);
+    const int p2 = dpp_i<S>(p, p);
+    if (v2 > v || (v2 == v && p2 < p)) {
+      v = v2;
+      p = p2;
+    }
+    wave_argmax_<S + 1>(v, p);
+  }
+}
+__device__ __forceinline__ int wave_argmax(double v, int p) {
+  wave_argmax_<0>(v, p);
+  return __builtin_amdgcn_readlane(p, 63);
 }
 
 // 2-norm of A[r0..n-1][c] by one lane (max-scaled, so no overflow)
@@ -153,17 +207,7 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
       if (wv == 0) {
         if (i > 0) downdate(S, n, i - 1, lane, tol3z);
         wave_fence();
-        double v = (lane >= i && lane < n) ? S.vn1[lane] : -1.0;
-        int p = lane;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const double v2 = __shfl_xor(v, o);
-          const int p2 = __shfl_xor(p, o);
-          if (v2 > v || (v2 == v && p2 < p)) {
-            v = v2;
-            p = p2;
-          }
-        }
+        const int p = wave_argmax((lane >= i && lane < n) ? S.vn1[lane] : -1.0, lane);
         if (p != i) {
           if (lane < n) {
             const cplx x = S.a[lane * kCLD + i];
