@@ -151,17 +151,19 @@ __device__ __forceinline__ void downdate(CSmem& S, int n, int i, int lane, doubl
 }
 
 // A[i:, c] <- (I - t v v^H) A[i:, c] for the columns c0 <= c < n, v = A[i:, i]
-// with v_i = 1 implied (vi1) or stored; four waves split the rows.
-__device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1) {
+// with v_i = 1 implied (row i taken by wave 0 outside the loop); four waves
+// split the rows.
+__device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c = lane;
+  const int r0 = w == 0 ? i + 4 : i + w;
   cplx part = {0.0, 0.0};
   if (c >= c0 && c < n) {
+    if (w == 0) part = S.a[i * kCLD + c];
     // unrolled so that the LDS loads of several rows are in flight at once
 #pragma unroll 8
-    for (int r = i + w; r < n; r += 4) {
-      const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
-      const cplx p = cjmul(v, S.a[r * kCLD + c]);
+    for (int r = r0; r < n; r += 4) {
+      const cplx p = cjmul(S.a[r * kCLD + i], S.a[r * kCLD + c]);
       part.x += p.x;
       part.y += p.y;
     }
@@ -172,10 +174,13 @@ __device__ void apply_reflector(CSmem& S, int n, int i, int c0, cplx t, bool vi1
     cplx s = {S.red[0][c].x + S.red[1][c].x + S.red[2][c].x + S.red[3][c].x,
               S.red[0][c].y + S.red[1][c].y + S.red[2][c].y + S.red[3][c].y};
     s = cmul(t, s);
+    if (w == 0) {
+      S.a[i * kCLD + c].x -= s.x;
+      S.a[i * kCLD + c].y -= s.y;
+    }
 #pragma unroll 8
-    for (int r = i + w; r < n; r += 4) {
-      const cplx v = (r == i && vi1) ? cplx{1.0, 0.0} : S.a[r * kCLD + i];
-      const cplx d = cmul(v, s);
+    for (int r = r0; r < n; r += 4) {
+      const cplx d = cmul(S.a[r * kCLD + i], s);
       S.a[r * kCLD + c].x -= d.x;
       S.a[r * kCLD + c].y -= d.y;
     }
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
       }
       __syncthreads();
       const cplx ti = S.tau[i];
-      if (ti.x != 0.0 || ti.y != 0.0) apply_reflector(S, n, i, i + 1, cplx{ti.x, -ti.y}, true);
+      if (ti.x != 0.0 || ti.y != 0.0) apply_reflector(S, n, i, i + 1, cplx{ti.x, -ti.y});
     }
     // D = |diag R| (real), T = D^{-1} R P^T (rows with D = 0 undivided)
     if (tid < n) {
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(kCThreads) void k_udt_complex(int n, int count, con
     // column i into H_i e_i
     for (int i = n - 1; i >= 0; --i) {
       const cplx ti = S.tau[i];
-      if (i < n - 1 && (ti.x != 0.0 || ti.y != 0.0)) apply_reflector(S, n, i, i + 1, ti, true);
+      if (i < n - 1 && (ti.x != 0.0 || ti.y != 0.0)) apply_reflector(S, n, i, i + 1, ti);
       if (tid < n) {
         if (tid > i) {
           const cplx v = S.a[tid * kCLD + i];
