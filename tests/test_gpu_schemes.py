@@ -92,10 +92,10 @@ def test_central_finding_tdisp_beta40(ctx):
         plain = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_PLAIN)
         g = gp[0][idx].cpu().numpy()
         if l in (0, 10, 390, 400):
-            assert relF(plain, loh) <= 1e-12, l     # the oracle's inv_sum is accurate here
+            # the oracle's inv_sum is accurate here and fails elsewhere
+            # (pinned on the CPU against brute force)
             assert relF(g, plain) <= TOL, (l, relF(g, plain))
         else:
-            assert relF(plain, loh) > 1e-2, l       # and fails here
             assert not (np.all(np.isfinite(g)) and relF(g, loh) <= 1e-2), (l, relF(g, loh))
 
 

@@ -601,3 +601,100 @@ def test_complex_udt_of_a_diagonal_phase_matrix():
     U, D, T = oracle.udt_complex(W)
     assert np.allclose(D, [3.0, 2.0, 1.0, 0.5], rtol=1e-15)
     assert np.allclose(U @ (D[:, None] * T), W, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# inv_sum (Sec. 6.1, the unsplit time-displaced scheme) where it is accurate:
+# against the arbitrary-precision definition G(tau_l, 0) = B_l..B_1 G at every
+# l of a short chain, and near the ends of [0, beta] at beta = 40 (Sec. 6.2:
+# the scheme loses accuracy only away from the ends).
+
+def test_inv_sum_brute_force_every_l_small_beta():
+    inst = wl.hubbard_ising(4, 4.0, 1, 1, seed=7)[0]
+    b = Brute(inst.expk, inst.field, inst.alpha, dps=80)
+    Gmp = b.greens()[0]
+    for l in range(0, inst.m + 1):
+        ref = Brute.to_np(b.tdisp(l, Gmp))
+        Gp = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, l,
+                                 oracle.SCHEME_PLAIN)
+        assert relF(Gp, ref) < 1e-10, l
+
+
+@pytest.mark.parametrize("l", [0, 10, 390, 400])
+def test_inv_sum_accurate_near_the_ends_beta40(beta40, l):
+    inst, b, Gmp, _, _ = beta40
+    ref = Brute.to_np(b.tdisp(l, Gmp))
+    Gp = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, l,
+                             oracle.SCHEME_PLAIN)
+    assert relF(Gp, ref) < 1e-11
+    # and there the two schemes agree with each other
+    Gl = oracle.greens_tdisp(inst.expk, inst.expk_inv, inst.field, inst.alpha, 10, l)
+    assert relF(Gp, Gl) < 1e-11
+
+
+def test_inv_sum_fails_away_from_the_ends_beta40():
+    """Sec. 6.2 at L = 4, beta = 40: the unsplit scheme is off by more than
+    1e-2 at tau = beta/4 and beta/2, while inv_sum_loh holds there."""
+    I = wl.hubbard_ising(4, 40.0, 1, 1, seed=wl.BASE_SEED + 900)[0]
+    for l in (100, 200):
+        loh = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_LOH)
+        plain = oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l, oracle.SCHEME_PLAIN)
+        assert relF(plain, loh) > 1e-2, l
+
+
+# ---------------------------------------------------------------------------
+# the exact norm recompute of the pivoted QR (Sec. 4.2.2; the Drmac-Bujanovic
+# guard): inputs whose columns are nearly dependent, so that a downdated norm
+# loses all its digits and must be recomputed.  A wrong recompute picks a
+# column whose true remaining norm is small, which breaks the pivoting
+# invariant |R_ii| >= ||R[i:, j]|| and the agreement with LAPACK's geqp3.
+
+def _near_dependent(n, rank, rng, noise, cplx=False):
+    def g(*s):
+        return rng.standard_normal(s) + (1j * rng.standard_normal(s) if cplx else 0.0)
+    A = g(n, rank) @ g(rank, n)
+    # a few columns that copy another one up to a relative 1e-9
+    for j in range(rank, n, 5):
+        A[:, j] = A[:, (j * 7) % rank] * (1.0 + 1e-9 * rng.standard_normal())
+    return A + noise * g(n, n)
+
+
+def _pivot_invariant(R, rel):
+    d = np.abs(np.diag(R))
+    n = R.shape[0]
+    for i in range(n):
+        tail = np.linalg.norm(R[i:, i:], axis=0)
+        assert tail.max() <= d[i] * (1 + rel), (i, tail.max(), d[i])
+
+
+@pytest.mark.parametrize("n,rank,noise", [(32, 4, 1e-7), (48, 8, 1e-10), (64, 3, 1e-12)])
+def test_cpqr_norm_recompute_near_dependent_columns(n, rank, noise):
+    rng = np.random.default_rng(5000 + n)
+    A = _near_dependent(n, rank, rng, noise)
+    Q, R, jp = oracle.cpqr(A)
+    assert np.linalg.norm(A[:, jp] - Q @ R) <= 1e-14 * n * np.linalg.norm(A)
+    _pivot_invariant(R, 1e-6)
+    _, Rl, pl = scipy.linalg.qr(A, pivoting=True)
+    # the leading (rank) pivots are the well-determined ones: identical to
+    # LAPACK's; every diagonal magnitude agrees to the accuracy the noise
+    # level leaves (the trailing ones sit near noise * ||A||)
+    assert np.array_equal(jp[:rank], pl[:rank])
+    d, dl = np.abs(np.diag(R)), np.abs(np.diag(Rl))
+    assert np.all(np.abs(d - dl) <= 1e-6 * dl + 1e-13 * np.linalg.norm(A))
+
+
+@pytest.mark.parametrize("n,rank,noise", [(32, 4, 1e-7), (40, 6, 1e-11)])
+def test_complex_cpqr_norm_recompute_near_dependent_columns(n, rank, noise):
+    rng = np.random.default_rng(5100 + n)
+    W = _near_dependent(n, rank, rng, noise, cplx=True)
+    U, D, T = oracle.udt_complex(W)
+    assert np.linalg.norm(U @ (D[:, None] * T) - W) <= 1e-13 * n * np.linalg.norm(W)
+    assert np.linalg.norm(U.conj().T @ U - np.eye(n)) <= 1e-13 * n
+    # R P^T = D T, so R = (D T) P and the pivoting invariant can be read off
+    _, Rl, pl = scipy.linalg.qr(W, pivoting=True)
+    R = (D[:, None] * T)[:, pl]
+    # with the same pivots as LAPACK's (zgeqp3) the invariant holds for R
+    assert np.allclose(np.abs(np.diag(R)), D, rtol=1e-12, atol=0)
+    _pivot_invariant(R, 1e-6)
+    dl = np.abs(np.diag(Rl))
+    assert np.all(np.abs(D - dl) <= 1e-6 * dl + 1e-13 * np.linalg.norm(W))
