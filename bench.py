@@ -66,14 +66,18 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="time the batched step only (no equal-time / per-chain extras); for profiler runs")
     ap.add_argument("--workload", default="hubbard_L8_b40_batch512",
-                    choices=["hubbard_L8_b40_batch512", "hubbard_uneven_batch512",
+                    choices=["hubbard_L8_b40_batch512", "hubbard_L4_b10_single", "hubbard_uneven_batch512",
                              "hubbard_L8_b40_metropolis256", "hubbard_L8_b40_local256",
                              "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
                              "hubbard_L8_b20_phi_hmc128", "hubbard_L8_b40_dense128",
-                             "hubbard_L16_b40_batch128", "udt_complex_n64_batch4096"],
+                             "hubbard_L16_b40_batch128", "hubbard_L32_b40_single",
+                             "udt_complex_n64_batch4096"],
                     help="the default is the headline workload; the others time the same library "
-                         "on the mixed-size batch (equal-time G), the continuous-field batch "
-                         "(log|det| + gradient) and the L=16 batch (G + G(tau,0) at every slice)")
+                         "on the single small chain (latency of one G), the mixed-size batch "
+                         "(equal-time G), the continuous-field batch (log|det| + gradient), the "
+                         "L=16 batch and the L=32 chain (G + G(tau,0) at every slice)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the step from a captured HIP graph (sdq_set_graphs)")
     ap.add_argument("--scheme", default="loh", choices=["loh", "plain"],
                     help="inversion scheme of the time-displaced workloads: Loh's split (default) or "
                          "the single-decomposition inv_sum, which also reports its deviation from "
@@ -113,6 +117,7 @@ def main():
     insts = W.instances
     l_list = W.l_list or []
     kind = {"hubbard_L8_b40_batch512": "tdisp", "hubbard_L16_b40_batch128": "tdisp",
+            "hubbard_L32_b40_single": "tdisp", "hubbard_L4_b10_single": "greens",
             "hubbard_uneven_batch512": "greens", "hubbard_L8_b20_phi_batch128": "grad",
             "hubbard_L8_b40_metropolis256": "metropolis",
             "hubbard_L8_b40_local256": "local",
@@ -141,6 +146,8 @@ def main():
     ctx = sdq.Context(0)
     if args.stab == "svd":
         ctx.set_stabilizer(sdq.STAB_SVD)
+    if args.graphs:
+        ctx.set_graphs(True)
     # outputs preallocated once
     import ctypes
     inst_arr = ctx._instances(chains, need_inv=(kind in ("grad", "langevin", "hmc") or plain))
@@ -281,6 +288,13 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    names = ctx.kernel_names()
+    per_class = {}
+    for nm in names:
+        if "/nt" in nm:
+            nl, ms = ctx.kernel_stats(nm)
+            per_class[nm] = (nl, ms)
+    n_gr, ms_gr = ctx.kernel_stats("graph")
     n_sw, ms_sw = ctx.kernel_stats("sweep")
     n_pa, ms_pa = ctx.kernel_stats("grad" if kind in ("grad", "langevin", "hmc") else "pair")
     n_eq, ms_eq = ctx.kernel_stats("equal")
@@ -309,14 +323,36 @@ def main():
     else:
         f_pair = 0.0
     f_equal = sum((4.0 / 3.0 + 2.0 + 1.0 + 2.0) * I.n ** 3 for I in insts)
-    sweep_avg_s = ms_sw / max(n_sw, 1) * 1e-3
+    # the step's sweep flops over the step's summed sweep-launch time: equal
+    # to flops per launch over the mean launch time when a step launches the
+    # sweep once, and still the kernel's own rate when a step launches it
+    # several times (one launch per size class, or per block of a local
+    # sweep); launches of different classes may overlap in wall time
+    sweep_launches_per_step = n_sw / max(args.steps, 1)
+    sweep_avg_s = ms_sw / max(args.steps, 1) * 1e-3
     if kind == "local":
-        # a step launches one backward sweep and nb-1 single-block forward
-        # rebuilds: the roofline takes the step's sweep flops over its sweep time
+        # one backward sweep and nb-1 single-block forward rebuilds per step
         f_sweep = sum(2.0 * sweep_flops(I.n, I.m, I.k) for I in insts)
-        sweep_avg_s = ms_sw / max(args.steps, 1) * 1e-3
-    pair_avg_s = ms_pa / max(n_pa, 1) * 1e-3
-    achieved = f_sweep / sweep_avg_s if sweep_avg_s > 0 else 0.0
+    pair_avg_s = ms_pa / max(args.steps, 1) * 1e-3
+    evals = HMC_STEPS + 1 if kind == "hmc" else 1  # gradient evaluations per step
+    f_sweep_step, f_pair_step = evals * f_sweep, evals * f_pair
+    # per size class: launches and device time per step, algorithmic flops,
+    # rate (the sweeps of a class: its chains' sweep flops)
+    classes = {}
+    for nm, (nl, ms) in sorted(per_class.items()):
+        kname, nt = nm.split("/nt")
+        nt = int(nt)
+        members = [I for I in insts if (I.n + 15) // 16 == nt]
+        row = {"launches_per_step": nl / max(args.steps, 1), "ms_per_step": ms / max(args.steps, 1),
+               "chains": len(members), "n": sorted({I.n for I in members})}
+        if kname == "sweep" and not plain:
+            spc = 1 if kind in ("greens", "metropolis") else 2
+            fl = evals * sum(spc * sweep_flops(I.n, I.m, I.k) for I in members)
+            row["flops_per_step"] = fl
+            row["tflops"] = fl / (row["ms_per_step"] * 1e-3) / 1e12 if ms > 0 else None
+            row["frac_fp64_peak"] = fl / (row["ms_per_step"] * 1e-3) / PEAK_FP64_MFMA if ms > 0 else None
+        classes[nm] = row
+    achieved = f_sweep_step / sweep_avg_s if sweep_avg_s > 0 else 0.0
     total_flops = f_sweep + f_pair + f_equal
     if kind == "hmc":
         # HMC_STEPS + 1 gradient evaluations per trajectory, log|det| at two
@@ -379,16 +415,23 @@ def main():
     else:
         metric = f"log|det| + adjoint gradients/sec (FP64, {W.name})"
         unit = "chains/s (each: log|det| and its gradient over all M x N field entries)"
+    value = (cnt // 2 if kind in ("metropolis", "local") else cnt) / (ms_step * 1e-3)
+    higher = True
+    if args.workload == "hubbard_L4_b10_single":
+        # one small chain: a latency, not a throughput
+        metric = "equal-time Green's function latency (FP64, L=4, beta=10, one chain)"
+        unit = "us per G (one sdq_greens call: G, log|det|, sign)"
+        value, higher = ms_step * 1e3, False
     betas = sorted({round(I.m * I.dtau, 6) for I in insts})
     out = {
         "metric": metric,
-        "value": (cnt // 2 if kind in ("metropolis", "local") else cnt) / (ms_step * 1e-3),
+        "value": value,
         "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
-        "higher_is_better": True,
+        "higher_is_better": higher,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
@@ -401,10 +444,16 @@ def main():
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA,
                      "traffic": measured_traffic() if args.workload == "hubbard_L8_b40_batch512" else None,
-                     "flops_per_launch": f_sweep, "launch_ms": sweep_avg_s * 1e3},
-        "pair_kernel": {"launch_ms": pair_avg_s * 1e3, "flops_per_launch": f_pair,
-                        "achieved_tflops": (f_pair / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
+                     "flops_per_step": f_sweep_step, "launches_per_step": sweep_launches_per_step,
+                     "device_ms_per_step": sweep_avg_s * 1e3,
+                     "flops_per_launch": f_sweep_step / max(sweep_launches_per_step, 1e-30),
+                     "launch_ms": ms_sw / max(n_sw, 1)},
+        "pair_kernel": {"launches_per_step": n_pa / max(args.steps, 1), "device_ms_per_step": pair_avg_s * 1e3,
+                        "flops_per_step": f_pair_step,
+                        "achieved_tflops": (f_pair_step / pair_avg_s / 1e12) if pair_avg_s > 0 else None},
         "equal_kernel": {"launch_ms": ms_eq / max(n_eq, 1)},
+        "classes": classes,
+        "graphs": bool(args.graphs),
         "step_tflops": total_flops / (ms_step * 1e-3) / 1e12,
         "green_matrices_per_s": (cnt * (1 + len(l_list)) / (ms_step * 1e-3))
         if kind in ("tdisp", "greens") else None,
@@ -454,6 +503,23 @@ def main():
         out["cpu_baseline"] = cpu_baseline_langevin(insts, 1, HMC_STEPS + 1)
     if not args.no_cpu and args.workload == "hubbard_L8_b40_batch512" and not plain and args.stab == "qr":
         out["cpu_baseline"] = cpu_baseline(insts, l_list, args.cpu_sample)
+    if not args.no_cpu and args.workload == "hubbard_L4_b10_single":
+        out["cpu_baseline"] = cpu_baseline_single(insts[0])
+    if not args.no_cpu and args.workload == "hubbard_uneven_batch512":
+        out["cpu_baseline"] = cpu_baseline_uneven(insts)
+    if not args.no_cpu and args.workload == "hubbard_L8_b20_phi_batch128":
+        out["cpu_baseline"] = cpu_baseline_langevin(insts, 2)
+        out["cpu_baseline"]["unit"] = "chains/s (each: log|det| and its gradient)"
+    if not args.no_cpu and args.workload == "hubbard_L16_b40_batch128":
+        out["cpu_baseline"] = cpu_baseline_tdisp_sampled(insts[0], l_list, [1, 200, 400], len(insts))
+    if not args.no_cpu and args.workload == "hubbard_L32_b40_single":
+        out["cpu_baseline"] = cpu_baseline_n1024(insts[0], l_list)
+    if "cpu_baseline" in out:
+        out["cpu_baseline"].update(host_cpu()[0])
+    # release the context's device memory, streams and graphs while the HIP
+    # runtime (and a profiler, if attached) is still up
+    torch.cuda.synchronize()
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 
@@ -512,7 +578,7 @@ def run_udt_complex(args, dev, sdq, wl):
     }
     if not args.no_cpu:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = host_cpu()[1]
         sample = [Wh[b] for b in range(count)]
         print(f"[bench] cpu oracle: {len(sample)} complex UDTs on {threads} threads", file=sys.stderr, flush=True)
         c0 = time.perf_counter()
@@ -521,6 +587,14 @@ def run_udt_complex(args, dev, sdq, wl):
         dt = time.perf_counter() - c0
         out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "matrices/s", "cores": threads,
                                "kind": "oracle", "sample": f"all 4096 matrices; {dt:.1f} s wall"}
+        c1 = time.perf_counter()
+        for W1 in sample[:256]:
+            oracle.udt_complex(W1)
+        d1 = time.perf_counter() - c1
+        out["cpu_baseline"]["one_core"] = {"value": 256 / d1, "sample": f"256 matrices on one thread; {d1:.1f} s"}
+        out["cpu_baseline"].update(host_cpu()[0])
+    torch.cuda.synchronize()
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 
@@ -598,7 +672,7 @@ def cpu_baseline_local(insts, nsites=1024):
         f = I0.field.copy()
         f[rng.integers(0, m), rng.integers(0, n)] *= -1.0
         jobs += [(I0, f), (I1, f)]
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cpu()[1]
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
         list(ex.map(lambda j: oracle.greens(j[0].expk, j[1], j[0].alpha, j[0].k), jobs))
@@ -615,7 +689,7 @@ def cpu_baseline_dense(insts, nchains, l_list):
     import numpy as np
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cpu()[1]
     sample = insts[:nchains]
     dense = [np.ascontiguousarray(I.expk[None, :, :] * np.exp(I.alpha * I.field)[:, None, :]) for I in sample]
     jobs = [(d, None) for d in dense] + [(d, l) for d in dense for l in l_list]
@@ -643,7 +717,7 @@ def cpu_baseline_langevin(insts, nchains, nevals=1):
     import numpy as np
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cpu()[1]
     print(f"[bench] cpu oracle: {nevals} gradient(s) of each of {nchains} chain(s) on {threads} threads",
           file=sys.stderr, flush=True)
     rng = np.random.default_rng(7)
@@ -677,7 +751,7 @@ def cpu_baseline_metropolis(insts, nchains):
         f[rng.integers(0, f.shape[0])] *= -1.0
         for I in (insts[2 * c], insts[2 * c + 1]):
             jobs.append((I, f))
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cpu()[1]
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
         list(ex.map(lambda j: oracle.greens(j[0].expk, j[1], j[0].alpha, j[0].k), jobs))
@@ -699,7 +773,7 @@ def cpu_baseline(insts, l_list, nchains):
         jobs.append(("g", I, 0))
         for l in l_list:
             jobs.append(("t", I, l))
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_cpu()[1]
 
     def run(job):
         kind, I, l = job
@@ -713,10 +787,142 @@ def cpu_baseline(insts, l_list, nchains):
     with cf.ThreadPoolExecutor(threads) as ex:
         list(ex.map(run, jobs))
     dt = time.perf_counter() - t0
+    # one core: the first chain of the sample, serially
+    one = [j for j in jobs if j[1] is sample[0]]
+    t1 = time.perf_counter()
+    for j in one:
+        run(j)
+    d1 = time.perf_counter() - t1
     return {"value": len(sample) / dt, "unit": "chains/s (each: G + 40 G(tau,0))", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(sample)} of the 512 chains, each: oracle G plus oracle G(tau_l,0) for all "
-                      f"{len(l_list)} l; {dt:.1f} s wall"}
+                      f"{len(l_list)} l; {dt:.1f} s wall",
+            "one_core": {"value": 1.0 / d1, "sample": f"1 chain (G + {len(l_list)} G(tau,0)) on one thread; "
+                                                      f"{d1:.1f} s"}}
+
+
+def host_cpu():
+    """The host's CPU as the baselines use it: ({nproc, affinity, cpu_model},
+    threads).  The baselines run on the CPUs this process may use, at most 16
+    (the host share that comes with one GPU)."""
+    nproc = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = nproc
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": nproc, "affinity": aff, "cpu_model": model}, max(1, min(16, aff))
+
+
+def cpu_baseline_single(I, reps=40):
+    """The oracle's G, log|det|, sign of the one chain, on one thread."""
+    import oracle
+    oracle.greens(I.expk, I.field, I.alpha, I.k)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.greens(I.expk, I.field, I.alpha, I.k)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": dt * 1e6, "unit": "us per G", "cores": 1, "kind": "oracle",
+            "sample": f"the chain itself, {reps} calls on one thread"}
+
+
+def cpu_baseline_uneven(insts, nchains=24):
+    """The oracle's G of a bounded sample of the mixed-size batch (every
+    21st chain, so sizes and lengths are represented), on the host threads,
+    scaled to chains per second; one core: the first 4 of them."""
+    import oracle
+    threads = host_cpu()[1]
+    sample = insts[::max(1, len(insts) // nchains)][:nchains]
+
+    def run(I):
+        oracle.greens(I.expk, I.field, I.alpha, I.k)
+
+    print(f"[bench] cpu oracle: {len(sample)} chains on {threads} threads", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, sample))
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for I in sample[:4]:
+        run(I)
+    d1 = time.perf_counter() - t1
+    return {"value": len(sample) / dt, "unit": "chains/s (each: G, log|det|, sign)", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(sample)} chains of the batch (every {max(1, len(insts) // nchains)}th, n = "
+                      f"{sorted({I.n for I in sample})}); {dt:.1f} s wall",
+            "one_core": {"value": 4 / d1, "sample": f"the first 4 of them on one thread; {d1:.1f} s"}}
+
+
+def cpu_baseline_tdisp_sampled(I, l_list, l_sample, nchains):
+    """The oracle on one chain: its G and G(tau_l, 0) at the sampled l, one
+    call per thread; scaled (labelled extrapolation) to one chain with all of
+    l_list, as chains per second.  The oracle builds each G(tau_l, 0) from
+    scratch, so its cost per l is about the same for every l."""
+    import oracle
+    threads = host_cpu()[1]
+    jobs = [None] + list(l_sample)
+
+    def run(l):
+        if l is None:
+            oracle.greens(I.expk, I.field, I.alpha, I.k)
+        else:
+            oracle.greens_tdisp(I.expk, I.expk_inv, I.field, I.alpha, I.k, l)
+
+    print(f"[bench] cpu oracle: G + {len(l_sample)} G(tau,0) of one n={I.n} chain on {threads} threads",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, jobs))
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    run(l_sample[0])
+    d1 = time.perf_counter() - t1
+    per_chain = d1 * (1 + len(l_list))  # serial cost of one chain, extrapolated
+    return {"value": min(threads, 1 + len(l_list)) / per_chain, "unit": f"chains/s (each: G + {len(l_list)} G(tau,0))",
+            "cores": threads, "kind": "oracle",
+            "sample": f"one chain: G and G(tau_l,0) at l = {l_sample} ({dt:.1f} s wall on {threads} threads); "
+                      f"one G(tau,0) on one thread took {d1:.1f} s; extrapolated to {1 + len(l_list)} "
+                      f"matrices per chain with the threads working on separate matrices",
+            "extrapolated": True,
+            "one_core": {"value": 1.0 / per_chain, "sample": "extrapolated from the one-thread G(tau,0)"}}
+
+
+def cpu_baseline_n1024(I, l_list):
+    """The oracle at N = 1024 is far beyond a bounded sample (each of its
+    G(tau_l, 0) multiplies out both chains again: about 400 slice products of
+    2 N^3 flops).  Timed here: one slice product and one UDT of the oracle at
+    this N on one thread (one slice of the chain and one stabilization), then
+    scaled to the oracle's work for G plus all G(tau_l, 0) (extrapolation)."""
+    import numpy as np
+    import oracle
+    n, m, k = I.n, I.m, I.k
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((n, n))
+    print(f"[bench] cpu oracle: one slice product and one UDT at n={n}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    oracle.chain(I.expk, I.expk_inv, I.field[:1], I.alpha, 1, 0, 1, 1)
+    t_slice_udt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.udt(W)
+    t_udt = time.perf_counter() - t1
+    t_slice = max(t_slice_udt - t_udt, 0.0)
+    nb = (m + k - 1) // k
+    # oracle work: G (m slices, nb UDTs) and per l the two chains (m slices,
+    # about nb + 1 UDTs) and the inversion (a few UDT-sized factorizations)
+    per_chain = (1 + len(l_list)) * (m * t_slice + (nb + 3) * t_udt)
+    return {"value": 1.0 / per_chain, "unit": f"chains/s (each: G + {len(l_list)} G(tau,0))", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one slice product ({t_slice:.1f} s) and one UDT ({t_udt:.1f} s) at n={n} on one thread, "
+                      f"scaled to {1 + len(l_list)} matrices x ({m} slices + {nb + 3} UDTs)",
+            "extrapolated": True}
 
 
 if __name__ == "__main__":

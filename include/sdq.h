@@ -33,8 +33,14 @@
  * Supported sizes: 1 <= n <= 1024, 1 <= k <= m.  n <= 128 runs one
  * workgroup per chain with its matrices in registers and LDS; 128 < n <= 1024
  * runs a gang of workgroups per chain (a column slab of the matrix in each
- * one's LDS, pivot candidates and operands exchanged through HBM) in a
- * cooperative launch.  n > 1024 returns SDQ_EUNSUPPORTED.
+ * one's LDS, pivot candidates and operands exchanged through HBM), with no
+ * more workgroups than the device holds at once.  n > 1024 returns
+ * SDQ_EUNSUPPORTED.
+ * Chains of different size classes (16-wide tile counts) in one call run
+ * concurrently: each class of the one-workgroup kernels on a stream of its
+ * own forked from the context's stream, the gang classes on the context's
+ * stream; all of them are joined back into the context's stream before the
+ * call's work ends, so callers see ordinary stream order.
  */
 #ifndef SDQ_H
 #define SDQ_H
@@ -333,18 +339,28 @@ sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const ch
 /* Capture later batched calls in HIP graphs and replay them when the same
  * batch (every pointer, shape, list and scheme) is seen again (enable = 1),
  * or launch directly (enable = 0, the default).  A replay runs on the
- * context's stream; at most 16 graphs are kept (oldest evicted).  Batches
- * with a chain of n > 128 (cooperative launches) always launch directly. */
+ * context's stream; at most 16 graphs are kept (oldest evicted).  Mixed-size
+ * batches and chains of n > 128 are captured like any other. */
 sdq_status sdq_set_graphs(sdq_ctx* ctx, int enable);
 
-/* Record HIP events around every kernel launch (enable = 1); the per-kernel
- * launch count and summed device milliseconds are then read with
- * sdq_kernel_stats (names: "sweep" for the stabilized sweeps, "equal" for
- * the equal-time inversions, "pair" for the time-displaced inversions,
- * "grad" for the gradient, "udt", and "graph" for a replayed graph).
- * Resets the counters. */
+/* Record HIP events around every kernel launch (enable = 1), on the stream
+ * the launch runs on; the per-kernel launch count and summed device
+ * milliseconds are then read with sdq_kernel_stats.  Names: "sweep" for the
+ * stabilized sweeps, "equal" for the equal-time inversions, "pair" for the
+ * time-displaced inversions, "grad" for the gradient, "local" and "bstart"
+ * for local updates, "udt", "udt_complex", and "graph" for a replayed graph.
+ * The batched kernels are also kept per size class as "<name>/nt<T>" (T =
+ * ceil(n/16), above 8 a gang class): sdq_kernel_stats("sweep") sums all
+ * classes, sdq_kernel_stats("sweep/nt7") reads one; sdq_kernel_names lists
+ * every name recorded.  Launches of different classes may overlap in time,
+ * so a sum over classes is device time, not wall time.  Resets the
+ * counters. */
 sdq_status sdq_set_profiling(sdq_ctx* ctx, int enable);
 sdq_status sdq_kernel_stats(sdq_ctx* ctx, const char* name, int64_t* launches, double* ms);
+/* The names recorded since profiling was enabled, comma separated, into the
+ * host buffer buf of cap bytes (NUL terminated); SDQ_EINVAL if it is too
+ * small. */
+sdq_status sdq_kernel_names(sdq_ctx* ctx, char* buf, int32_t cap);
 
 /* Wait for all work enqueued by ctx and report an asynchronous HIP error. */
 sdq_status sdq_sync(sdq_ctx* ctx);

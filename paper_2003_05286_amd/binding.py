@@ -11,8 +11,10 @@ with expk, expk_inv ([n, n]) and field ([m, n]) float64 CUDA tensors.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -30,7 +32,7 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
            "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense",
-           "sdq_greens_tdisp_dense", "sdq_udt_complex")
+           "sdq_greens_tdisp_dense", "sdq_udt_complex", "sdq_kernel_names")
 
 
 class SdqError(RuntimeError):
@@ -83,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_set_graphs.argtypes = [vp, ctypes.c_int]
     L.sdq_set_profiling.argtypes = [vp, ctypes.c_int]
     L.sdq_kernel_stats.argtypes = [vp, ctypes.c_char_p, P(i64), P(dbl)]
+    L.sdq_kernel_names.argtypes = [vp, ctypes.c_char_p, i32]
     L.sdq_sync.argtypes = [vp]
     L.sdq_similarity.argtypes = [vp, i32, i32, vp, vp, P(vp)]
     L.sdq_metropolis.argtypes = [vp, P(_Instance), P(_Instance), i32, i32, vp, vp, vp, vp, vp, vp]
@@ -131,6 +134,21 @@ def _check_tensor(t, name, shape, device):
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
+# Contexts still open when the interpreter exits are closed by an atexit
+# hook, while the HIP runtime (and any profiler attached to it) is still up,
+# rather than by a finalizer during teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_live):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """An sdq context bound to one device and to torch's current stream."""
 
@@ -147,8 +165,11 @@ class Context:
             raise SdqError(st, "sdq_create failed")
         self.h = h
         self._keep = []
+        _live.add(self)
 
     def close(self):
+        """Wait for the context's work and release its device memory, streams
+        and graphs (sdq_destroy).  Idempotent."""
         if getattr(self, "h", None):
             self.lib.sdq_destroy(self.h)
             self.h = None
@@ -249,6 +270,8 @@ class Context:
     def udt_complex(self, w):
         """w: complex128 [count, n, n] -> U [count,n,n] complex, D [count,n] real,
         T [count,n,n] complex (sdq_udt_complex)."""
+        if w.dim() != 3 or w.shape[1] != w.shape[2]:
+            raise ValueError(f"w: need shape [count, n, n], got {tuple(w.shape)}")
         cnt, n, _ = w.shape
         if w.dtype != torch.complex128 or not w.is_contiguous() or w.device != self.tdev:
             raise ValueError(f"w: need a contiguous complex128 tensor on {self.tdev}, got {w.dtype} on {w.device}")
@@ -424,6 +447,11 @@ class Context:
         ms = ctypes.c_double(0)
         self._chk(self.lib.sdq_kernel_stats(self.h, name.encode(), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def kernel_names(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._chk(self.lib.sdq_kernel_names(self.h, buf, len(buf)))
+        return [x for x in buf.value.decode().split(",") if x]
 
     def sync(self):
         self._chk(self.lib.sdq_sync(self.h))

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "sdq_internal.h"
@@ -949,14 +950,27 @@ __device__ __forceinline__ void scale_rows(const Lane& L, RM<NT, P>& A, const do
 // zero-padded order, whose block ((ti*NT + tk)*4 + r) holds exactly the 64
 // A-operand values of one MFMA step: read from the LDS copy (ELDS; one base
 // address, immediate offsets) or from HBM (one coalesced 512-byte load).
+// The HBM copy is read through a buffer resource: the block offset is a
+// compile-time constant that goes into the instruction's scalar offset, so
+// no per-block 64-bit address is kept in vector registers (with NT^2 * 4
+// blocks such addresses would be hoisted out of the slice loop and spilled).
 template <int NT, int P, bool ELDS>
 struct EOp {
-  const double* sE;   // staged swizzled copy in LDS (ELDS)
-  const double* esw;  // swizzled copy in HBM
-  int lane;
+  const double* sE;            // staged swizzled copy in LDS (ELDS)
+  __amdgpu_buffer_rsrc_t rsw;  // swizzled copy in HBM
+  int lane8;                   // byte offset of this lane in a block
+  __device__ EOp(const double* s, const double* esw, int lane) : sE(s), lane8(lane * 8) {
+    // the copy's address is the same for the whole workgroup
+    const unsigned long long a = (unsigned long long)esw;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    rsw = __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0,
+                                            NT * NT * 4 * 512, 0x00020000);
+  }
   __device__ double operator()(int ti, int tk, int r, int, int) const {
-    if (ELDS) return sE[((ti * NT + tk) * 4 + r) * 64 + lane];
-    return gmem(esw)[((ti * NT + tk) * 4 + r) * 64 + lane];
+    if (ELDS) return sE[((ti * NT + tk) * 4 + r) * 64 + (lane8 >> 3)];
+    return __builtin_bit_cast(
+        double, __builtin_amdgcn_raw_buffer_load_b64(rsw, lane8, ((ti * NT + tk) * 4 + r) * 512, 0));
   }
 };
 
@@ -966,6 +980,31 @@ __device__ __forceinline__ void stage_e(const Lane& L, Smem<NT, P, ELDS>& S, con
   if (!ELDS) return;
   for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) S.E[idx] = gmem(esw)[idx];
   // visibility: the next fill_vbuf begins with a barrier
+}
+
+// A register matrix kept in a workgroup's private global scratch between
+// uses: register [c][ti][r] of lane l of wave w at ((c NT + ti) 4 + r) 64 P +
+// 64 w + l, so every access of a wave is one contiguous 512-byte block.  Each
+// lane reads back only what it wrote itself.
+template <int NT, int P>
+__device__ __forceinline__ void scr_store(const Lane& L, const RM<NT, P>& A, double* p) {
+  auto* q = gmem(p) + L.w * 64 + L.l;
+#pragma unroll
+  for (int c = 0; c < Geo<NT, P>::CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) q[((c * NT + ti) * 4 + r) * 64 * P] = A.v[c][ti][r];
+}
+template <int NT, int P>
+__device__ __forceinline__ void scr_load(const Lane& L, RM<NT, P>& A, const double* p) {
+  const auto* q = gmem(p) + L.w * 64 + L.l;
+#pragma unroll
+  for (int c = 0; c < Geo<NT, P>::CT; ++c)
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A.v[c][ti][r] = q[((c * NT + ti) * 4 + r) * 64 * P];
 }
 
 // store one stage U | T | D | extra
@@ -1146,9 +1185,15 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
 // DENSE: the slices are the dense matrices at I.field (B_q at
 // field + (q-1) n n; forward sweeps, and backward ones over B_q^T),
 // staged through S.E one at a time when ELDS, else read from global memory.
-template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
+// TG: T is not held in registers across the block's slice products and
+// QR; it lives in the workgroup's scratch `tscr` between blocks and is in
+// registers only for its update (after the QR, before Q is formed, while
+// the working matrix is parked in LDS), which frees one register matrix.
+struct NoT {};
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false>
 __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
-                          const int jpair) {
+                          const int jpair, double* tscr = nullptr) {
+  static_assert(!(TG && SVD), "the SVD stabilizer keeps T in registers");
   using G = Geo<NT, P>;
   // the SVD stabilizer keeps T in S.E, so E is read from its global copy
   constexpr bool EST = ELDS && !SVD && !DENSE;
@@ -1164,13 +1209,18 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   const double* e_op = left ? I.eswi : (adj ? I.eswt : I.esw);
   if constexpr (EST) stage_e<NT, P, ELDS>(L, S, e_op);
   // W holds U between blocks and the block product inside a block
-  RM<NT, P> T, W;
+  RM<NT, P> W;
+  std::conditional_t<TG, NoT, RM<NT, P>> T;
+  // TG: where the next T update finds T (0 identity, 1 forward stage
+  // jpair, 2 the scratch)
+  int tsrc = 0;
   double dcol[CT];
   if (block && jpair > 0) {
     // continue from forward stage jpair: W = U, T, column scales D
     const double* F0 = I.ckf + (size_t)(jpair - 1) * sd;
     load_rm<NT, P>(L, W, F0, n, false);
-    load_rm<NT, P>(L, T, F0 + (size_t)n * n, n, false);
+    if constexpr (TG) tsrc = 1;
+    else load_rm<NT, P>(L, T, F0 + (size_t)n * n, n, false);
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int col = col_of<NT, P>(L, c);
@@ -1178,7 +1228,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     }
   } else {
     set_identity<NT, P>(L, W);
-    set_identity<NT, P>(L, T);
+    if constexpr (!TG) set_identity<NT, P>(L, T);
 #pragma unroll
     for (int c = 0; c < CT; ++c) dcol[c] = 1.0;
   }
@@ -1260,12 +1310,35 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
       for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= dcol[c];
+    double* dst = nullptr;
+    if (flags & SW_STORE) dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
+    else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
+    else if (left && s == s_hi - 1) dst = I.ckf + (size_t)(jpair - 1) * sd;
+    else if (right && s == nb - 1) dst = I.cka + (size_t)jpair * sd;
+    else if (block) dst = I.ckf + (size_t)jpair * sd;
     double sgn_u = 1.0;
     if constexpr (SVD) {
       double ps = 1.0;
       svd_failed |= jsvd_udt<NT, P>(L, n, S, W, T, &ps);
       sgn_u = sgn_run * ps;
       sgn_run = sgn_u;
+    } else if constexpr (TG) {
+      cpqr<NT, P, ELDS>(L, n, W, S);
+      diag_r<NT, P, ELDS>(L, n, S);
+      sgn_u = refl_sign<NT, P, ELDS>(L, n, S);
+      {
+        // W is parked in LDS: T takes its place in registers for the update
+        RM<NT, P> Tr;
+        if (tsrc == 2) scr_load<NT, P>(L, Tr, tscr);
+        else if (tsrc == 1) load_rm<NT, P>(L, Tr, I.ckf + (size_t)(jpair - 1) * sd + (size_t)n * n, n, false);
+        else set_identity<NT, P>(L, Tr);
+        update_t<NT, P, ELDS>(L, S, Tr);
+        if (s + 1 < s_hi) scr_store<NT, P>(L, Tr, tscr);
+        tsrc = 2;
+        if (dst) store_rm<NT, P>(L, Tr, dst + (size_t)n * n, n);
+        if ((flags & SW_FINAL) && s + 1 == s_hi) store_rm<NT, P>(L, Tr, I.t_out, n);
+      }
+      form_q<NT, P, ELDS>(L, n, S, W);
     } else {
       cpqr<NT, P, ELDS>(L, n, W, S);
       diag_r<NT, P, ELDS>(L, n, S);
@@ -1275,13 +1348,15 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) dcol[c] = S.dnew[col_of<NT, P>(L, c)];
-    double* dst = nullptr;
-    if (flags & SW_STORE) dst = adj ? (I.cka + (size_t)b * sd) : (I.ckf + (size_t)s * sd);
-    else if ((flags & SW_LAST) && s == nb - 1) dst = I.fin;
-    else if (left && s == s_hi - 1) dst = I.ckf + (size_t)(jpair - 1) * sd;
-    else if (right && s == nb - 1) dst = I.cka + (size_t)jpair * sd;
-    else if (block) dst = I.ckf + (size_t)jpair * sd;
-    if (dst) store_stage<NT, P, ELDS>(L, n, S, W, T, sgn_u, dst);
+    if (dst) {
+      if constexpr (TG) {
+        store_rm<NT, P>(L, W, dst, n);
+        for (int t = L.t; t < n; t += G::THREADS) gmem(dst)[2 * (size_t)n * n + t] = S.dnew[t];
+        if (L.t == 0) gmem(dst)[2 * (size_t)n * n + n] = sgn_u;
+      } else {
+        store_stage<NT, P, ELDS>(L, n, S, W, T, sgn_u, dst);
+      }
+    }
     __syncthreads();
   }
 
@@ -1292,7 +1367,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
   }
   if (flags & SW_FINAL) {
     store_rm<NT, P>(L, W, I.u_out, n);
-    store_rm<NT, P>(L, T, I.t_out, n);
+    if constexpr (!TG) store_rm<NT, P>(L, T, I.t_out, n);
     for (int t = L.t; t < n; t += G::THREADS) gmem(I.d_out)[t] = S.dnew[t];
   }
   if ((__any(bad) || svd_failed) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
@@ -1330,21 +1405,25 @@ __device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   __syncthreads();
 }
 
-template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false>
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false>
 __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
-                                                            int count, Queue* q) {
+                                                            int count, Queue* q, double* tscr) {
   __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
+  // this workgroup's T scratch (TG): one register matrix, lanes contiguous
+  double* ts = TG ? tscr + (size_t)blockIdx.x * (Geo<NT, P>::CT * P * NT * 256) : nullptr;
   for (;;) {
     __syncthreads();
     if (L.t == 0) S.item = atomicAdd(&q->next, 1);
     __syncthreads();
-    const int it = S.item;
+    // the item is the same for the whole workgroup: scalar loads of the item,
+    // its instance and every pointer in it
+    const int it = __builtin_amdgcn_readfirstlane(S.item);
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, P, ELDS, SVD, DENSE>(L, S, I, wi.flags, wi.j);
+    sweep_one<NT, P, ELDS, SVD, DENSE, TG>(L, S, I, wi.flags, wi.j, ts);
   }
 }
 
@@ -2052,7 +2131,9 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     __syncthreads();
     if (L.t == 0) S.item = atomicAdd(&q->next, 1);
     __syncthreads();
-    const int it = S.item;
+    // the item is the same for the whole workgroup: scalar loads of the item,
+    // its instance and every pointer in it
+    const int it = __builtin_amdgcn_readfirstlane(S.item);
     if (it >= count) break;
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
@@ -2158,7 +2239,7 @@ struct Launch {
   static hipError_t dense_sweep(const Inst* inst, const SweepItem* items, int count, Queue* q, int grid,
                                 hipStream_t s) {
     hipLaunchKernelGGL((k_sweep<NT, P, kDenseLds, false, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s,
-                       inst, items, count, q);
+                       inst, items, count, q, (double*)nullptr);
     return hipGetLastError();
   }
   static hipError_t dense_info(KernelInfo* out) {
@@ -2175,22 +2256,36 @@ struct Launch {
   static hipError_t dense_pair_info(KernelInfo* out) {
     return info_of(k_pair<NT, P, kPairLds, PAIR_TDISP_DENSE>, (int)sizeof(Smem<NT, P, kPairLds>), out);
   }
+  // variants 4 and 5: one wave per 16-column tile (PT = NT waves), T in the
+  // per-workgroup scratch between blocks
+  static constexpr int PT = NT;
   static hipError_t sweep(int variant, const Inst* inst, const SweepItem* items, int count, Queue* q,
-                          int grid, hipStream_t s) {
+                          int grid, double* tscr, hipStream_t s) {
+    double* const none = nullptr;
     if (variant == 2) {
       if constexpr (kSvd) {
         hipLaunchKernelGGL((k_sweep<NT, P, true, true>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
-                           items, count, q);
+                           items, count, q, none);
         return hipGetLastError();
       }
       return hipErrorInvalidValue;
     }
+    if (variant == 4 || variant == 5) {
+      if (!tscr) return hipErrorInvalidValue;
+      if (variant == 5 && kLds)
+        hipLaunchKernelGGL((k_sweep<NT, PT, kLds, false, false, true>), dim3(grid), dim3(Geo<NT, PT>::THREADS), 0,
+                           s, inst, items, count, q, tscr);
+      else
+        hipLaunchKernelGGL((k_sweep<NT, PT, false, false, false, true>), dim3(grid), dim3(Geo<NT, PT>::THREADS),
+                           0, s, inst, items, count, q, tscr);
+      return hipGetLastError();
+    }
     if (variant == 1 && kLds)
       hipLaunchKernelGGL((k_sweep<NT, P, kLds>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
-                         items, count, q);
+                         items, count, q, none);
     else
       hipLaunchKernelGGL((k_sweep<NT, P, false>), dim3(grid), dim3(Geo<NT, P>::THREADS), 0, s, inst,
-                         items, count, q);
+                         items, count, q, none);
     return hipGetLastError();
   }
   static hipError_t pair(int mode, const Inst* inst, const PairItem* items, int count,
@@ -2224,16 +2319,21 @@ struct Launch {
                        d, t);
     return hipGetLastError();
   }
-  template <class KF>
+  template <int PW = P, class KF>
   static hipError_t info_of(KF kern, int lds, KernelInfo* out) {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, Geo<NT, P>::THREADS, 0);
-    out->threads = Geo<NT, P>::THREADS;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, Geo<NT, PW>::THREADS, 0);
+    out->threads = Geo<NT, PW>::THREADS;
     out->lds_bytes = lds;
     out->blocks_per_cu = nb;
     return e;
   }
   static hipError_t info(int kind, int variant, KernelInfo* out) {
+    if (kind == KK_SWEEP && (variant == 4 || variant == 5)) {
+      if (variant == 5 && kLds)
+        return info_of<PT>(k_sweep<NT, PT, kLds, false, false, true>, (int)sizeof(Smem<NT, PT, kLds>), out);
+      return info_of<PT>(k_sweep<NT, PT, false, false, false, true>, (int)sizeof(Smem<NT, PT, false>), out);
+    }
     if (kind == KK_SWEEP) {
       if constexpr (kSvd)
         if (variant == 2) return info_of(k_sweep<NT, P, true, true>, (int)sizeof(Smem<NT, P, true>), out);

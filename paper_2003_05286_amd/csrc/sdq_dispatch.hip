@@ -5,7 +5,7 @@
 namespace sdq {
 
 #define SDQ_DECL(N)                                                                              \
-  hipError_t launch_sweep_nt##N(int, const Inst*, const SweepItem*, int, Queue*, int, hipStream_t); \
+  hipError_t launch_sweep_nt##N(int, const Inst*, const SweepItem*, int, Queue*, int, double*, hipStream_t); \
   hipError_t launch_pair_nt##N(int, const Inst*, const PairItem*, int, const int32_t*, Queue*, int, \
                                hipStream_t);                                                     \
   hipError_t launch_udt_nt##N(int, int, const double*, double*, double*, double*, hipStream_t);  \
@@ -33,13 +33,13 @@ SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL
   }
 
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
-                        Queue* q, int grid, hipStream_t s) {
+                        Queue* q, int grid, double* tscr, hipStream_t s) {
   if (variant == 3) {
 #define C(N) launch_dense_sweep_nt##N(inst, items, count, q, grid, s)
     SDQ_SWITCH(C)
 #undef C
   }
-#define C(N) launch_sweep_nt##N(variant, inst, items, count, q, grid, s)
+#define C(N) launch_sweep_nt##N(variant, inst, items, count, q, grid, tscr, s)
   SDQ_SWITCH(C)
 #undef C
 }

@@ -26,10 +26,13 @@
 // loads, and the published keys (tagged with the step) are the barrier:
 // every wave polls the G keys until all carry the current tag.  Bulk data
 // (R P^T, reflectors, G) is exchanged with normal stores behind a barrier on
-// a monotonic counter in HBM with device-scope fences.  The launch is
-// cooperative, so all members of every gang are resident; a wait still gives
-// up after a few seconds (abort flag, status SDQ_ERANGE) instead of spinning
-// forever.
+// a monotonic counter in HBM with device-scope fences.  The grid never holds
+// more workgroups than the device keeps resident at once (gang_capacity), so
+// every member of every gang becomes resident, at the latest when kernels of
+// other streams sharing the device have drained their workgroups; the launch
+// is an ordinary one, so it can be captured in a HIP graph and overlap the
+// one-workgroup kernels of other size classes.  A wait gives up after a few
+// seconds (abort flag, status SDQ_ERANGE) instead of spinning forever.
 //
 // Paper passages: slice products and stage loop Sec. 4.1; pivoted QR and
 // UDT Sec. 4.2.2; equal-time inversion Sec. 5.1 (Loh's split, mirror form);
@@ -1238,7 +1241,7 @@ hipError_t coop_launch(K kern, GangArgs a, hipStream_t s, Args... args) {
   const GangGeom g = gang_geom(a.nt);
   if (g.G == 0 || a.ngangs < 1) return hipErrorInvalidValue;
   void* ptrs[] = {(void*)&args..., (void*)&a};
-  return hipLaunchCooperativeKernel((const void*)kern, dim3(a.ngangs * g.G), dim3(kGangThreads), ptrs, 0, s);
+  return hipLaunchKernel((const void*)kern, dim3(a.ngangs * g.G), dim3(kGangThreads), ptrs, 0, s);
 }
 
 }  // namespace

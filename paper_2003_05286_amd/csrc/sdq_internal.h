@@ -176,8 +176,23 @@ hipError_t launch_hmc_end(int count, int nf, const HmcChain* chains, double half
 // b = (ti*NT + tk)*4 + r holds at position l the entry
 // (16 ti + l%16, 16 tk + l/16 + 4 r) of the zero-padded matrix.
 hipError_t launch_swizzle(const double* e, int n, int trans, double* out, hipStream_t s);
+// Sweep kernel variants (per tile count nt, chosen by sdq_tune or the
+// defaults of sdq_create):
+//   0  slice exponential read from its swizzled HBM copy, T in registers
+//   1  slice exponential staged in LDS (3 <= nt <= 5), T in registers
+//   2  Jacobi SVD stabilizer          3  dense slices
+//   4  one wave per 16-column tile, T kept in a per-workgroup HBM scratch
+//      between blocks (frees a register matrix), exponential from HBM
+//   5  as 4 with the exponential staged in LDS (3 <= nt <= 5)
+constexpr int kSweepVariants = 6;
+__host__ __device__ constexpr bool sweep_variant_tg(int variant) { return variant == 4 || variant == 5; }
+// doubles of T scratch per workgroup of a variant-4/5 sweep (0 otherwise):
+// one 16 x 16 FP64 tile = 256 doubles per (wave, tile column, tile row)
+__host__ __device__ inline int64_t sweep_tscr_doubles(int nt, int variant) {
+  return sweep_variant_tg(variant) ? (int64_t)nt * nt * 256 : 0;
+}
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
-                        Queue* q, int grid, hipStream_t s);
+                        Queue* q, int grid, double* tscr, hipStream_t s);
 hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
                        int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s);
 // complex UDT of independent matrices (sdq_complex.hip): w, u, t interleaved

@@ -13,8 +13,8 @@
 namespace sdq {
 
 hipError_t SDQ_CAT(launch_sweep_nt, SDQ_NT)(int variant, const Inst* inst, const SweepItem* items,
-                                           int count, Queue* q, int grid, hipStream_t s) {
-  return Launch<SDQ_NT>::sweep(variant, inst, items, count, q, grid, s);
+                                           int count, Queue* q, int grid, double* tscr, hipStream_t s) {
+  return Launch<SDQ_NT>::sweep(variant, inst, items, count, q, grid, tscr, s);
 }
 hipError_t SDQ_CAT(launch_pair_nt, SDQ_NT)(int mode, const Inst* inst, const PairItem* items,
                                           int count, const int32_t* l_list, Queue* q, int grid,

@@ -78,6 +78,7 @@ struct sdq_ctx {
   std::string err;
   int num_cu = 256;
   DevBuf d_upload, d_ck, d_swz, d_fin;
+  DevBuf d_tscr;  // per-workgroup T scratch of the variant-4/5 sweeps
   DevBuf d_gang;  // per-gang scratch of the n > 128 kernels (bars first)
   DevBuf d_ptrs;  // matrix pointer table of sdq_similarity
   DevBuf d_metro;  // sdq_metropolis: field table, proposed log|det|, signs and status
@@ -110,6 +111,12 @@ struct sdq_ctx {
   std::vector<hipEvent_t> ev_pool;
   bool graphs = false;
   hipStream_t cap_stream = nullptr;  // non-null stream used only for graph capture
+  // side streams of a batch whose tile classes run concurrently (created on
+  // first use, default priority), with the fork event and their join events
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSide] = {};
   struct GraphEntry {
     std::vector<char> key;
     hipGraphExec_t exec = nullptr;
@@ -297,22 +304,27 @@ hipEvent_t take_event(sdq_ctx* ctx) {
   return e;
 }
 
-// launch with optional event bracketing
+// launch on stream s with optional event bracketing (the events are
+// recorded on s, so they time this launch even when other streams run)
 template <class F>
-sdq_status timed(sdq_ctx* ctx, const char* name, F launch) {
+sdq_status timed_on(sdq_ctx* ctx, const std::string& name, hipStream_t s, F launch) {
   hipEvent_t a = nullptr, b = nullptr;
   if (ctx->profiling) {
     a = take_event(ctx);
     b = take_event(ctx);
-    if (a) HIP_TRY(hipEventRecord(a, ctx->stream), "hipEventRecord");
+    if (a) HIP_TRY(hipEventRecord(a, s), "hipEventRecord");
   }
   hipError_t e = launch();
-  if (e != hipSuccess) return hip_fail(ctx, e, name);
+  if (e != hipSuccess) return hip_fail(ctx, e, name.c_str());
   if (ctx->profiling && a && b) {
-    HIP_TRY(hipEventRecord(b, ctx->stream), "hipEventRecord");
+    HIP_TRY(hipEventRecord(b, s), "hipEventRecord");
     ctx->stats[name].pending.push_back({a, b});
   }
   return SDQ_OK;
+}
+template <class F>
+sdq_status timed(sdq_ctx* ctx, const char* name, F launch) {
+  return timed_on(ctx, std::string(name), ctx->stream, launch);
 }
 
 // Swizzled, zero-padded copies of every distinct slice exponential of the
@@ -360,6 +372,7 @@ struct LaunchRec {
   int nt, variant, mode, grid, count;
   size_t items_off;  // byte offset of the first item
   size_t queue_off;  // byte offset of this launch's queue counter
+  size_t tscr_off;   // doubles into the T scratch (variant-4/5 sweeps)
 };
 
 struct Built {
@@ -368,6 +381,7 @@ struct Built {
   std::vector<LaunchRec> launches;
   std::vector<SwzJob> swz;
   size_t o_inst = 0, o_ll = 0;
+  size_t tscr_doubles = 0;  // T scratch of all variant-4/5 sweep launches
   int32_t* status = nullptr;
   int count = 0;
 };
@@ -411,8 +425,11 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   for (const auto& r : P.sweep_ranges) {
     const int variant = is_gang(r.nt) ? 0 : P.dense ? 3 : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
     const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
+    // classes may run concurrently: each launch gets its own T scratch
+    const size_t toff = B.tscr_doubles;
+    if (!is_gang(r.nt)) B.tscr_doubles += (size_t)grid * (size_t)sdq::sweep_tscr_doubles(r.nt, variant);
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
-                                   o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue)});
+                                   o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue), toff});
   }
   const int order[sdq::kPairModes] = {sdq::PAIR_EQUAL, sdq::PAIR_TDISP, sdq::PAIR_TDISP_PLAIN,
                                       sdq::PAIR_TDISP_DENSE, sdq::PAIR_GRAD, sdq::PAIR_BSTART,
@@ -423,7 +440,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
       // variant 3: the dense-slice G(tau,0) kernel (occupancy of its own)
       const int grid = grid_for(ctx, sdq::KK_PAIR, r.nt, md == sdq::PAIR_TDISP_DENSE ? 3 : 0, r.count);
       B.launches.push_back(LaunchRec{sdq::KK_PAIR, r.nt, 0, md, grid, r.count,
-                                     o_pa[md] + r.off * sizeof(PairItem), o_q + (qi++) * sizeof(Queue)});
+                                     o_pa[md] + r.off * sizeof(PairItem), o_q + (qi++) * sizeof(Queue), 0});
     }
   }
   return SDQ_OK;
@@ -474,23 +491,63 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   const Inst* d_inst = (const Inst*)(d + B.o_inst);
   const int32_t* d_ll = (const int32_t*)(d + B.o_ll);
   static const char* names[sdq::kPairModes] = {"pair", "grad", "equal", "pair", "local", "bstart", "pair"};
+  // Stream of each launch.  The items of different tile classes belong to
+  // different chains, so the classes are independent: each class of the
+  // one-workgroup kernels runs in order on a side stream of its own, forked
+  // from s after the upload and joined back into s, and the gang classes
+  // (which share the gang scratch) run in order on s.  A batch of one class
+  // stays on s.
+  std::vector<int> cls;  // distinct one-workgroup tile classes, first-seen order
+  bool any_gang = false;
+  for (const LaunchRec& L : B.launches) {
+    if (is_gang(L.nt)) any_gang = true;
+    else if (std::find(cls.begin(), cls.end(), L.nt) == cls.end()) cls.push_back(L.nt);
+  }
+  const bool fork = (int)cls.size() + (any_gang ? 1 : 0) > 1;
+  int nside = 0;
+  if (fork) {
+    nside = std::min((int)cls.size(), (int)sdq_ctx::kSide);
+    for (int i = 0; i < nside; ++i) {
+      if (!ctx->side[i])
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking), "hipStreamCreate(side)");
+      if (!ctx->ev_join[i])
+        HIP_TRY(hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming), "hipEventCreate(join)");
+    }
+    if (!ctx->ev_fork) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipEventRecord(ctx->ev_fork, s), "hipEventRecord(fork)");
+    for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(ctx->side[i], ctx->ev_fork, 0), "hipStreamWaitEvent");
+  }
+  auto stream_of = [&](const LaunchRec& L) -> hipStream_t {
+    if (!fork || is_gang(L.nt)) return s;
+    const int c = (int)(std::find(cls.begin(), cls.end(), L.nt) - cls.begin());
+    return ctx->side[c % nside];
+  };
   for (const LaunchRec& L : B.launches) {
     Queue* q = (Queue*)(d + L.queue_off);
+    hipStream_t ls = stream_of(L);
     auto go = [&]() -> hipError_t {
-      if (is_gang(L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, s);
+      if (is_gang(L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
       if (L.kind == sdq::KK_SWEEP)
         return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
-                                 q, L.grid, s);
+                                 q, L.grid, (double*)ctx->d_tscr.p + L.tscr_off, ls);
       return sdq::launch_pair(L.nt, 0, L.mode, d_inst, (const PairItem*)(d + L.items_off), L.count,
-                              d_ll, q, L.grid, s);
+                              d_ll, q, L.grid, ls);
     };
-    const char* nm = L.kind == sdq::KK_SWEEP ? "sweep" : names[L.mode];
+    // per-class name "<kernel>/nt<tiles>": sdq_kernel_stats("<kernel>") sums the classes
+    std::string nm = std::string(L.kind == sdq::KK_SWEEP ? "sweep" : names[L.mode]) + "/nt" +
+                     std::to_string(L.nt);
     if (timing) {
-      sdq_status st = timed(ctx, nm, go);
+      sdq_status st = timed_on(ctx, nm, ls, go);
       if (st) return st;
     } else {
       hipError_t e = go();
-      if (e != hipSuccess) return hip_fail(ctx, e, nm);
+      if (e != hipSuccess) return hip_fail(ctx, e, nm.c_str());
+    }
+  }
+  if (fork) {
+    for (int i = 0; i < nside; ++i) {
+      HIP_TRY(hipEventRecord(ctx->ev_join[i], ctx->side[i]), "hipEventRecord(join)");
+      HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join[i], 0), "hipStreamWaitEvent(join)");
     }
   }
   return SDQ_OK;
@@ -522,9 +579,15 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
     hipError_t e = grow(ctx->d_gang, need);
     if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "gang scratch: " + std::string(hipGetErrorString(e)));
   }
-  // cooperative launches (n > 128) are not captured: such batches run directly
-  if (ctx->graphs && !B.gang) {
+  if (B.tscr_doubles) {
+    hipError_t e = grow(ctx->d_tscr, B.tscr_doubles * sizeof(double));
+    if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "T scratch: " + std::string(hipGetErrorString(e)));
+  }
+  if (ctx->graphs) {
     std::vector<char> key = graph_key(B);
+    // the gang and T scratch areas are not part of the image: their addresses are
+    const void* gp[2] = {B.gang ? ctx->d_gang.p : nullptr, B.tscr_doubles ? ctx->d_tscr.p : nullptr};
+    key.insert(key.end(), (const char*)gp, (const char*)gp + sizeof gp);
     sdq_ctx::GraphEntry* hit = nullptr;
     for (auto& g : ctx->graph_cache)
       if (g.key == key) hit = &g;
@@ -658,8 +721,10 @@ sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream) {
     ctx->num_cu = prop.multiProcessorCount;
   for (int nt = 0; nt <= sdq::kMaxNT; ++nt) {
     ctx->tune[nt] = Tune{};
-    // default: slice exponential staged in LDS where that variant exists
-    ctx->tune[nt].variant = (nt >= 3 && nt <= 5) ? 1 : 0;
+    // defaults (sdq_tune measures them): the slice exponential staged in LDS
+    // where that variant exists; above 80 sites one wave per tile with T in
+    // scratch (with four waves the register matrices of n > 80 spill)
+    ctx->tune[nt].variant = nt >= 6 ? 4 : ((nt >= 3 && nt <= 5) ? 1 : 0);
   }
   // debug overrides (environment): SDQ_SWEEP_VARIANT, SDQ_BLOCKS_PER_CU
   if (const char* v = getenv("SDQ_SWEEP_VARIANT"))
@@ -682,10 +747,17 @@ void sdq_destroy(sdq_ctx* ctx) {
     if (g.d) (void)hipFree(g.d);
   }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (int i = 0; i < sdq_ctx::kSide; ++i) {
+    if (ctx->side[i]) (void)hipStreamSynchronize(ctx->side[i]);
+    if (ctx->side[i]) (void)hipStreamDestroy(ctx->side[i]);
+    if (ctx->ev_join[i]) (void)hipEventDestroy(ctx->ev_join[i]);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->d_upload.p) (void)hipFree(ctx->d_upload.p);
   if (ctx->d_ck.p) (void)hipFree(ctx->d_ck.p);
   if (ctx->d_swz.p) (void)hipFree(ctx->d_swz.p);
   if (ctx->d_fin.p) (void)hipFree(ctx->d_fin.p);
+  if (ctx->d_tscr.p) (void)hipFree(ctx->d_tscr.p);
   if (ctx->d_gang.p) (void)hipFree(ctx->d_gang.p);
   if (ctx->d_ptrs.p) (void)hipFree(ctx->d_ptrs.p);
   if (ctx->d_metro.p) (void)hipFree(ctx->d_metro.p);
@@ -1581,9 +1653,14 @@ sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const ch
     std::vector<sdq_instance> inst(chains);
     for (int c = 0; c < chains; ++c)
       inst[c] = sdq_instance{n, m, k, 0, dE, nullptr, dF + (size_t)c * m * n, 0.65};
+    // the sweep variants (exponential in LDS or HBM; T in registers with
+    // min(nt, 4) waves, or in scratch with one wave per tile) and the
+    // occupancy cap (one workgroup per CU, or the kernel's limit)
     std::vector<Tune> cands;
-    for (int v = 0; v <= ((nt >= 3 && nt <= 5) ? 1 : 0); ++v)
-      for (int b : {1, 0}) cands.push_back(Tune{v, b});
+    const bool lds = nt >= 3 && nt <= 5;
+    for (int v : {0, 1, 4, 5})
+      if ((v != 1 && v != 5) || lds)
+        for (int b : {1, 0}) cands.push_back(Tune{v, b});
     double best = 1e300;
     Tune bt = ctx->tune[nt];
     for (const Tune& c : cands) {
@@ -1641,25 +1718,39 @@ sdq_status sdq_set_profiling(sdq_ctx* ctx, int enable) {
 
 sdq_status sdq_kernel_stats(sdq_ctx* ctx, const char* name, int64_t* launches, double* ms) {
   if (!ctx || !name) return SDQ_EINVAL;
-  auto it = ctx->stats.find(name);
-  if (it == ctx->stats.end()) {
-    if (launches) *launches = 0;
-    if (ms) *ms = 0.0;
-    return SDQ_OK;
+  const std::string want(name), pre = want + "/";
+  int64_t nl = 0;
+  double tot = 0.0;
+  for (auto& kv : ctx->stats) {
+    if (kv.first != want && kv.first.compare(0, pre.size(), pre) != 0) continue;
+    KStat& k = kv.second;
+    for (auto& pr : k.pending) {
+      HIP_TRY(hipEventSynchronize(pr.second), "hipEventSynchronize");
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second), "hipEventElapsedTime");
+      k.ms += t;
+      k.launches += 1;
+      ctx->ev_pool.push_back(pr.first);
+      ctx->ev_pool.push_back(pr.second);
+    }
+    k.pending.clear();
+    nl += k.launches;
+    tot += k.ms;
   }
-  KStat& k = it->second;
-  for (auto& pr : k.pending) {
-    HIP_TRY(hipEventSynchronize(pr.second), "hipEventSynchronize");
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second), "hipEventElapsedTime");
-    k.ms += t;
-    k.launches += 1;
-    ctx->ev_pool.push_back(pr.first);
-    ctx->ev_pool.push_back(pr.second);
+  if (launches) *launches = nl;
+  if (ms) *ms = tot;
+  return SDQ_OK;
+}
+
+sdq_status sdq_kernel_names(sdq_ctx* ctx, char* buf, int32_t cap) {
+  if (!ctx || !buf || cap < 1) return SDQ_EINVAL;
+  std::string all;
+  for (auto& kv : ctx->stats) {
+    if (!all.empty()) all += ",";
+    all += kv.first;
   }
-  k.pending.clear();
-  if (launches) *launches = k.launches;
-  if (ms) *ms = k.ms;
+  if ((int64_t)all.size() + 1 > cap) return fail(ctx, SDQ_EINVAL, "buffer too small for the kernel names");
+  memcpy(buf, all.c_str(), all.size() + 1);
   return SDQ_OK;
 }
 

@@ -219,6 +219,11 @@ def workload(name: str, scale: float = 1.0) -> Workload:
                         notes="L=8 (N=64), beta=40, M=400, k=10, 128 chains whose slices "
                               "E diag(exp(lambda s_l)) are handed over as dense matrices; "
                               "G and G(tau,0) at every 10th slice")
+    if name == "hubbard_L32_b40_single":
+        return Workload(name, hubbard_ising(32, 40.0, 1, 1, seed=BASE_SEED + 9),
+                        l_list=list(range(1, 401)),
+                        notes="L=32 (N=1024), beta=40, M=400, k=10, one chain, sigma=+1; "
+                              "G and G(tau_l,0) for l = 1..400")
     if name == "hubbard_L16_b40_batch128":
         return Workload(name, hubbard_ising(16, 40.0, nb(64), 2, seed=BASE_SEED + 4),
                         l_list=list(range(1, 401)),

@@ -82,3 +82,60 @@ def test_complex_udt_limits(ctx):
     assert e.value.status == sdq.SDQ_EUNSUPPORTED
     u, d, t = ctx.udt_complex(torch.zeros(0, 8, 8, dtype=torch.complex128, device=DEV))
     assert u.shape == (0, 8, 8)
+
+
+def test_complex_udt_rejects_a_non_square_batch(ctx):
+    say("[gpu] sdq_udt_complex binding: [count, n, m] with m != n -> ValueError")
+    for shape in ((2, 8, 4), (2, 4, 8), (8, 8)):
+        with pytest.raises(ValueError):
+            ctx.udt_complex(torch.zeros(*shape, dtype=torch.complex128, device=DEV))
+
+
+def test_complex_udt_graded_benchmark_batch(ctx):
+    # the benchmark's inputs: columns graded over 30 decades, random order
+    W = wl.complex_batch(96, 64)
+    say("[gpu] sdq_udt_complex on the graded benchmark batch, n=64 count=96 (sampled)")
+    assert check(ctx, W, sample=range(0, 96, 5)) <= 1e-10
+    W = wl.complex_batch(40, 37, seed=wl.BASE_SEED + 1880)
+    say("[gpu] sdq_udt_complex on a graded batch, n=37 count=40")
+    assert check(ctx, W) <= 1e-10
+
+
+def _near_dependent(count, n, rank, noise, seed):
+    rng = np.random.default_rng(seed)
+
+    def g(*s):
+        return rng.normal(size=s) + 1j * rng.normal(size=s)
+    out = []
+    for _ in range(count):
+        A = g(n, rank) @ g(rank, n)
+        for j in range(rank, n, 5):
+            A[:, j] = A[:, (j * 7) % rank] * (1.0 + 1e-9 * rng.normal())
+        out.append(A + noise * g(n, n))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("n,rank,noise", [(32, 4, 1e-7), (64, 6, 1e-11)])
+def test_complex_udt_near_dependent_columns(ctx, n, rank, noise):
+    """Nearly dependent columns drive downdated norms below the
+    Drmac-Bujanovic guard, so the exact norm recompute runs.  Unique parts:
+    the leading `rank` rows of T and columns of U (well-determined) against
+    the oracle; D against the oracle to the accuracy the noise level leaves;
+    reconstruction and unitarity of the GPU's own factors."""
+    import scipy.linalg as sl
+    W = _near_dependent(3, n, rank, noise, wl.BASE_SEED + 1890 + n)
+    Wd = torch.from_numpy(np.ascontiguousarray(W)).to(DEV)
+    say(f"[gpu] sdq_udt_complex near-dependent columns n={n} rank={rank} noise={noise:g}")
+    u, d, t = ctx.udt_complex(Wd)
+    torch.cuda.synchronize()
+    u, d, t = u.cpu().numpy(), d.cpu().numpy(), t.cpu().numpy()
+    for b in range(W.shape[0]):
+        Uo, Do, To = oracle.udt_complex(W[b])
+        nW = np.linalg.norm(W[b])
+        assert np.all(np.abs(d[b] - Do) <= 1e-6 * Do + 1e-13 * nW), b
+        dl = np.abs(np.diag(sl.qr(W[b], pivoting=True)[1]))
+        assert np.all(np.abs(d[b] - dl) <= 1e-6 * dl + 1e-13 * nW), b
+        assert relf(u[b][:, :rank], Uo[:, :rank]) <= 1e-10
+        assert relf(t[b][:rank], To[:rank]) <= 1e-10
+        assert np.linalg.norm(u[b] @ (d[b][:, None] * t[b]) - W[b]) <= 1e-13 * n * nW
+        assert np.linalg.norm(u[b].conj().T @ u[b] - np.eye(n)) <= 1e-13 * n

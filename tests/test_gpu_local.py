@@ -69,6 +69,70 @@ def test_local_sweep_matches_sequential_metropolis(ctx, L, beta, k, nf, chains):
         assert np.array_equal(Fg[c], fo)
 
 
+def check_decisions_in_parallel(E, F0, Fg, alphas, k, u, threads=16):
+    """Every site is visited once per sweep, so the sites whose sign changed
+    are exactly the accepted flips, and the field before each proposal is
+    known from the decisions before it.  Each decision is then checked on its
+    own against the oracle's ratio exp(sum_f log|det(1+B'_f)| -
+    log|det(1+B_f)|) (one oracle log|det| per flavour and proposal, in
+    parallel).  If every decision agrees, the library followed the sequential
+    Metropolis path exactly."""
+    import concurrent.futures as cf
+    m, n = F0.shape
+    acc = (Fg != F0)
+    states = []
+    f = F0.copy()
+    for l in range(m):
+        for i in range(n):
+            g = f.copy()
+            g[l, i] = -g[l, i]
+            states.append(g)
+            if acc[l, i]:
+                f = g
+    assert np.array_equal(f, Fg)
+
+    def ld_of(fld):
+        return sum(oracle.greens(E, fld, a, k)[1] for a in alphas)
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        ldp = list(ex.map(ld_of, states))
+    cur = ld_of(F0)
+    t = 0
+    for l in range(m):
+        for i in range(n):
+            p = np.exp(ldp[t] - cur)
+            assert abs(u[l, i] - p) > 1e-9, "a decision within rounding of its threshold"
+            assert bool(u[l, i] < p) == bool(acc[l, i]), (l, i, u[l, i], p)
+            if acc[l, i]:
+                cur = ldp[t]
+            t += 1
+    return int(acc.sum())
+
+
+@pytest.mark.parametrize("L,beta,k", [(8, 4.0, 10), (6, 6.0, 10)])
+def test_local_sweep_longer_chains(ctx, L, beta, k):
+    """The benchmark's lattice (N = 64) at beta = 4 (M = 40, four blocks of
+    wrapping and recomputation) and N = 36 at beta = 6, both flavours."""
+    dtau, U = 0.1, 4.0
+    E, Ei = wl.expk_pair(wl.hopping_matrix(L), dtau)
+    lam = wl.hirsch_lambda(U, dtau)
+    m, n = int(round(beta / dtau)), L * L
+    rng = np.random.default_rng(wl.BASE_SEED + 1200 + L)
+    F0 = 2.0 * rng.integers(0, 2, (1, m, n)) - 1.0
+    u = rng.uniform(0.0, 1.0, (1, m, n))
+    alphas = (lam, -lam)
+    E_d, Ei_d = torch.from_numpy(E).to(DEV), torch.from_numpy(Ei).to(DEV)
+    Fd = torch.from_numpy(F0).to(DEV)
+    ch = [sdq.Chain(E_d, Fd[0], a, k, Ei_d) for a in alphas]
+    say(f"[gpu] sdq_local_sweep L={L} beta={beta} k={k}, decisions checked against the oracle")
+    acc, st = ctx.local_sweep(ch, 2, torch.from_numpy(u).to(DEV))
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    na = check_decisions_in_parallel(E, F0[0], Fd[0].cpu().numpy(), alphas, k, u[0])
+    say(f"[gpu]   accepted {na} of {m * n}")
+    assert acc.cpu().numpy()[0] == na
+
+
 def test_local_sweep_then_greens(ctx):
     """After a sweep the field is a valid configuration: the library's G of
     the updated field equals the oracle's, and a second sweep from there

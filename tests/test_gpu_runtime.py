@@ -61,7 +61,7 @@ def test_autotune_cache_and_parity(tmp_path):
     ctx.tune([36, 64], path)
     lines = [json.loads(l) for l in open(path)]
     assert {l["n"] for l in lines} == {36, 64}
-    assert all(l["variant"] in (0, 1) and l["blocks_per_cu"] in (0, 1) for l in lines)
+    assert all(l["variant"] in (0, 1, 4, 5) and l["blocks_per_cu"] in (0, 1) for l in lines)
     # a second call reads the cache and adds nothing
     ctx.tune([36, 64], path)
     assert len(open(path).read().splitlines()) == 2
