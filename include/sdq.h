@@ -119,6 +119,29 @@ const char* sdq_version(void);
 sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                       double* const* g, double* logdet, double* sign, int32_t* status);
 
+/* sdq_greens for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, but nothing is allocated; everything the kernels
+ * need beyond the caller's buffers (the plan, the swizzled slice
+ * exponentials, the final stage of every chain, scratch) lives in one fixed
+ * device array of 64 MiB per device, reserved when the library is loaded and
+ * held until the process ends.  Arguments as in sdq_greens, with these limits:
+ *   * every chain has n <= 128 (SDQ_EUNSUPPORTED otherwise: larger chains
+ *     need the gang scratch);
+ *   * the batch must fit the 64 MiB (about (2 n^2 + n) * 8 bytes per chain,
+ *     e.g. some 900 chains of n = 64): SDQ_EINVAL with the size otherwise,
+ *     nothing enqueued;
+ *   * all chains of the call run on the context's stream (no side streams),
+ *     and nothing is timed by sdq_set_profiling.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap in time on one device (other streams,
+ * other contexts, other host threads) race with each other and must be
+ * ordered by the caller; calls on one context's stream are ordered by it.
+ * Before reusing its host-side copy of the plan the call waits for the
+ * previous call's upload on the same context to complete. */
+sdq_status sdq_greens_noalloc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
+                              double* const* g, double* logdet, double* sign, int32_t* status);
+
 /* A chain whose slices are given as dense real matrices (models whose B_l
  * is not expk * diag(exp(alpha f_l))): slice l (1-based) is the row-major
  * n x n device matrix slices + (l-1) n n. */

@@ -32,7 +32,7 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
            "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense",
-           "sdq_greens_tdisp_dense", "sdq_udt_complex", "sdq_kernel_names")
+           "sdq_greens_tdisp_dense", "sdq_udt_complex", "sdq_kernel_names", "sdq_greens_noalloc")
 
 
 class SdqError(RuntimeError):
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_version.argtypes = []
     L.sdq_version.restype = ctypes.c_char_p
     L.sdq_greens.argtypes = [vp, P(_Instance), i32, ctypes.c_int, P(vp), vp, vp, vp]
+    L.sdq_greens_noalloc.argtypes = [vp, P(_Instance), i32, ctypes.c_int, P(vp), vp, vp, vp]
     L.sdq_greens_tdisp.argtypes = [vp, P(_Instance), i32, ctypes.c_int, P(i32), i32, P(vp), P(vp),
                                    vp, vp, vp]
     L.sdq_logdet.argtypes = [vp, P(_Instance), i32, vp, vp, vp, P(ctypes.c_uint64)]
@@ -221,6 +222,21 @@ class Context:
         self._chk(self.lib.sdq_greens(self.h, inst, cnt, scheme, self._ptr_array(gs),
                                       _ptr(ld), _ptr(sg), _ptr(stt)))
         return gs, ld, sg, stt
+
+    def greens_noalloc(self, chains, gs, ld, sg, stt, scheme=SCHEME_LOH):
+        """sdq_greens_noalloc into caller-provided outputs: gs (list of [n, n]
+        float64 tensors or None), ld, sg ([count] float64), stt ([count] int32)."""
+        cnt = len(chains)
+        inst = self._instances(chains)
+        for t, name, shape in ((ld, "logdet", (cnt,)), (sg, "sign", (cnt,))):
+            _check_tensor(t, name, shape, self.tdev)
+        if stt.dtype != torch.int32 or tuple(stt.shape) != (cnt,) or stt.device != self.tdev:
+            raise ValueError("status: need an int32 tensor of shape [count] on the context's device")
+        for c, g in zip(chains, gs):
+            if g is not None:
+                _check_tensor(g, "g", (c.n, c.n), self.tdev)
+        self._chk(self.lib.sdq_greens_noalloc(self.h, inst, cnt, scheme, self._ptr_array(gs),
+                                              _ptr(ld), _ptr(sg), _ptr(stt)))
 
     def greens_tdisp(self, chains, l_list, want_g=True, scheme=SCHEME_LOH):
         """G(tau_l, 0) for l in l_list ([n_l, n, n] per chain), G, logdet, sign, status."""

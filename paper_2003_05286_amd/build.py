@@ -58,6 +58,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     tasks.append((os.path.join(CSRC, "sdq_dispatch.hip"), os.path.join(BUILD, "sdq_dispatch.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_gang.hip"), os.path.join(BUILD, "sdq_gang.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_complex.hip"), os.path.join(BUILD, "sdq_complex.o"), []))
+    tasks.append((os.path.join(CSRC, "sdq_noalloc.hip"), os.path.join(BUILD, "sdq_noalloc.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_runtime.cpp"), os.path.join(BUILD, "sdq_runtime.o"), []))
     jobs = jobs or min(len(tasks), os.cpu_count() or 4, 16)
     # the largest instantiations first

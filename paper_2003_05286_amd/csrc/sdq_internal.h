@@ -208,6 +208,13 @@ hipError_t launch_similarity(int nt, int n, int count, double* const* mats, cons
 
 enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2 };
 
+// ---- the fixed scratch of sdq_greens_noalloc (sdq_noalloc.hip) -------------
+constexpr size_t kNoAllocBytes = 64ull << 20;  // per device
+constexpr int kNoAllocMaxDevices = 64;
+// Device address of that device's scratch (hipGetSymbolAddress, looked up
+// once per device and cached); call with `device` current.
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // ---- chains with n > 128: gang kernels (sdq_gang.hip) --------------------
 // A chain is owned by a gang of G workgroups of kGangThreads threads; member
 // g keeps columns [g*w, (g+1)*w) of the working matrix in LDS, column-major

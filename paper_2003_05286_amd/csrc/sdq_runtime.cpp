@@ -124,6 +124,14 @@ struct sdq_ctx {
     void* d = nullptr;  // device upload buffer of the graph
   };
   std::vector<GraphEntry> graph_cache;
+  // sdq_greens_noalloc: this device's fixed scratch (looked up at
+  // sdq_create), the host copy of the last plan image and an event after its
+  // upload (the copy is kept until that upload has completed)
+  void* na_scratch = nullptr;
+  std::string na_err;
+  std::vector<char> na_image;
+  hipEvent_t na_ev = nullptr;
+  bool na_pending = false;
 };
 
 namespace {
@@ -335,7 +343,10 @@ struct SwzJob {
   int64_t off;
 };
 
-sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
+// `fixed`: lay the copies out there (the caller has sized it by
+// swizzle_doubles) instead of in the context's growing buffer.
+sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs, double*& base_out,
+                           double* fixed = nullptr) {
   std::map<std::pair<const double*, int>, int64_t> seen;
   int64_t tot = 0;
   auto add = [&](const double* e, int n) {
@@ -351,8 +362,10 @@ sdq_status prepare_swizzle(sdq_ctx* ctx, Plan& P, std::vector<SwzJob>& jobs) {
     add(I.expk, I.n);
     if (P.swz_inv && I.expk_inv) add(I.expk_inv, I.n);
   }
-  HIP_TRY(grow(ctx->d_swz, (size_t)std::max<int64_t>(tot, 1) * sizeof(double)), "hipMalloc(swizzle)");
-  double* base = (double*)ctx->d_swz.p;
+  if (!fixed)
+    HIP_TRY(grow(ctx->d_swz, (size_t)std::max<int64_t>(tot, 1) * sizeof(double)), "hipMalloc(swizzle)");
+  double* base = fixed ? fixed : (double*)ctx->d_swz.p;
+  base_out = base;
   for (Inst& I : P.inst) {
     if (!I.expk) continue;
     const int64_t off = seen[std::make_pair(I.expk, I.n)];
@@ -382,13 +395,17 @@ struct Built {
   std::vector<SwzJob> swz;
   size_t o_inst = 0, o_ll = 0;
   size_t tscr_doubles = 0;  // T scratch of all variant-4/5 sweep launches
+  double* swz_base = nullptr;   // where the swizzled operands go
+  double* tscr_base = nullptr;  // T scratch (set by the caller of build_plan)
+  bool fork = true;             // size classes may run on side streams
   int32_t* status = nullptr;
   int count = 0;
 };
 
-sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& B) {
+sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& B,
+                      double* swz_fixed = nullptr) {
   {
-    sdq_status st = prepare_swizzle(ctx, P, B.swz);
+    sdq_status st = prepare_swizzle(ctx, P, B.swz, B.swz_base, swz_fixed);
     if (st) return st;
     if (P.swz_ready) B.swz.clear();
   }
@@ -480,11 +497,12 @@ hipError_t launch_gang_rec(sdq_ctx* ctx, const LaunchRec& L, const Inst* d_inst,
 // the swizzled operands, launch.  `timing` brackets launches with events.
 sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, const char* h_src,
                          bool timing) {
-  HIP_TRY(hipMemcpyAsync(d, h_src, B.image.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync(plan)");
+  // (h_src null: the caller has uploaded the image already)
+  if (h_src) HIP_TRY(hipMemcpyAsync(d, h_src, B.image.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync(plan)");
   if (B.status && B.count > 0) HIP_TRY(sdq::launch_fill_i32(B.status, B.count, 0, s), "fill(status)");
   for (const SwzJob& j : B.swz) {
     const int64_t np = 16LL * nt_of(j.n);
-    double* out = (double*)ctx->d_swz.p + j.off;
+    double* out = B.swz_base + j.off;
     HIP_TRY(sdq::launch_swizzle(j.e, j.n, 0, out, s), "swizzle");
     HIP_TRY(sdq::launch_swizzle(j.e, j.n, 1, out + np * np, s), "swizzle");
   }
@@ -503,7 +521,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
     if (is_gang(L.nt)) any_gang = true;
     else if (std::find(cls.begin(), cls.end(), L.nt) == cls.end()) cls.push_back(L.nt);
   }
-  const bool fork = (int)cls.size() + (any_gang ? 1 : 0) > 1;
+  const bool fork = B.fork && (int)cls.size() + (any_gang ? 1 : 0) > 1;
   int nside = 0;
   if (fork) {
     nside = std::min((int)cls.size(), (int)sdq_ctx::kSide);
@@ -529,7 +547,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
       if (is_gang(L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
       if (L.kind == sdq::KK_SWEEP)
         return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
-                                 q, L.grid, (double*)ctx->d_tscr.p + L.tscr_off, ls);
+                                 q, L.grid, B.tscr_base ? B.tscr_base + L.tscr_off : nullptr, ls);
       return sdq::launch_pair(L.nt, 0, L.mode, d_inst, (const PairItem*)(d + L.items_off), L.count,
                               d_ll, q, L.grid, ls);
     };
@@ -582,6 +600,7 @@ sdq_status run_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count) {
   if (B.tscr_doubles) {
     hipError_t e = grow(ctx->d_tscr, B.tscr_doubles * sizeof(double));
     if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "T scratch: " + std::string(hipGetErrorString(e)));
+    B.tscr_base = (double*)ctx->d_tscr.p;
   }
   if (ctx->graphs) {
     std::vector<char> key = graph_key(B);
@@ -719,6 +738,21 @@ sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cu = prop.multiProcessorCount;
+  // the fixed scratch of sdq_greens_noalloc on this device (device current)
+  {
+    void* p = nullptr;
+    hipError_t e = sdq::noalloc_scratch(device, &p);
+    if (e == hipSuccess) {
+      ctx->na_scratch = p;
+    } else {
+      (void)hipGetLastError();
+      ctx->na_err = std::string("device scratch lookup failed: ") + hipGetErrorString(e);
+    }
+    if (hipEventCreateWithFlags(&ctx->na_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->na_ev = nullptr;
+    }
+  }
   for (int nt = 0; nt <= sdq::kMaxNT; ++nt) {
     ctx->tune[nt] = Tune{};
     // defaults (sdq_tune measures them): the slice exponential staged in LDS
@@ -776,6 +810,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (auto& sl : ctx->stage)
     if (sl.ev) (void)hipEventDestroy(sl.ev);
+  if (ctx->na_ev) (void)hipEventDestroy(ctx->na_ev);
   delete ctx;
 }
 
@@ -814,6 +849,91 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   order_all_pairs(P);
   ctx->err.clear();
   return run_plan(ctx, P, status, count);
+}
+
+// sdq_greens without any allocation: every buffer the kernels need beyond
+// the caller's (the plan image, the swizzled slice exponentials, the final
+// stages, the T scratch) is carved out of this device's fixed scratch.
+sdq_status sdq_greens_noalloc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
+                              double* const* g, double* logdet, double* sign, int32_t* status) {
+  sdq_status st = validate(ctx, inst, count, false);
+  if (st) return st;
+  if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
+  for (int i = 0; i < count; ++i)
+    if (inst[i].n > 16 * sdq::kMaxNT)
+      return fail(ctx, SDQ_EUNSUPPORTED, "sdq_greens_noalloc: chains of n > 128 need the gang scratch");
+  if (count == 0) return SDQ_OK;
+  if (!ctx->na_scratch) return fail(ctx, SDQ_EHIP, "sdq_greens_noalloc: " + ctx->na_err);
+  if (!ctx->na_ev) return fail(ctx, SDQ_EHIP, "sdq_greens_noalloc: no upload event");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  // layout: [swizzled operands | final stages | T scratch | plan image]
+  size_t swz = 0;
+  {
+    std::vector<std::pair<const double*, int>> seen;
+    for (int i = 0; i < count; ++i) {
+      const auto key = std::make_pair(inst[i].expk, inst[i].n);
+      if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+      seen.push_back(key);
+      const size_t np = 16 * (size_t)nt_of(inst[i].n);
+      swz += 2 * np * np * sizeof(double);
+    }
+  }
+  std::vector<int64_t> off(count);
+  int64_t fin = 0;
+  for (int i = 0; i < count; ++i) {
+    off[i] = fin;
+    fin += (sdq::stage_doubles(inst[i].n) + 31) & ~(int64_t)31;
+  }
+  char* base = (char*)ctx->na_scratch;
+  const size_t o_fin = align(swz);
+  const size_t o_tscr = align(o_fin + (size_t)fin * sizeof(double));
+  if (o_tscr > sdq::kNoAllocBytes)
+    return fail(ctx, SDQ_EINVAL,
+                "sdq_greens_noalloc: the batch needs more than the " + std::to_string(sdq::kNoAllocBytes >> 20) +
+                    " MiB of fixed scratch (" + std::to_string(o_tscr) + " bytes before the plan); split it");
+  Plan P;
+  for (int i = 0; i < count; ++i) {
+    Inst I = base_inst(inst[i]);
+    I.scheme = scheme == SDQ_INV_PLAIN ? 1 : 0;
+    I.g = g ? g[i] : nullptr;
+    I.logdet = logdet ? logdet + i : nullptr;
+    I.sign = sign ? sign + i : nullptr;
+    I.status = status ? status + i : nullptr;
+    I.fin = (double*)(base + o_fin) + off[i];
+    P.inst.push_back(I);
+    P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
+    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+  }
+  order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
+    const Inst& I = P.inst[w.inst];
+    return sweep_cost(I.n, I.m, I.k);
+  });
+  order_all_pairs(P);
+  ctx->err.clear();
+  Built B;
+  st = build_plan(ctx, P, status, count, B, (double*)base);
+  if (st) return st;
+  const size_t o_img = align(o_tscr + B.tscr_doubles * sizeof(double));
+  if (o_img + B.image.size() > sdq::kNoAllocBytes)
+    return fail(ctx, SDQ_EINVAL,
+                "sdq_greens_noalloc: the batch needs " + std::to_string(o_img + B.image.size()) +
+                    " bytes of fixed scratch, more than " + std::to_string(sdq::kNoAllocBytes >> 20) +
+                    " MiB; split it");
+  B.tscr_base = B.tscr_doubles ? (double*)(base + o_tscr) : nullptr;
+  B.fork = false;  // side streams would be created on first use
+  // the host copy of the previous image must outlive its upload
+  if (ctx->na_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->na_ev), "hipEventSynchronize(noalloc)");
+    ctx->na_pending = false;
+  }
+  ctx->na_image = B.image;
+  HIP_TRY(hipMemcpyAsync(base + o_img, ctx->na_image.data(), ctx->na_image.size(), hipMemcpyHostToDevice,
+                         ctx->stream),
+          "hipMemcpyAsync(plan)");
+  HIP_TRY(hipEventRecord(ctx->na_ev, ctx->stream), "hipEventRecord(noalloc)");
+  ctx->na_pending = true;
+  return enqueue_built(ctx, B, ctx->stream, base + o_img, nullptr, false);
 }
 
 namespace {

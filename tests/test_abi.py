@@ -33,6 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_null_context_is_rejected():
     lib = binding.load_library()
     assert lib.sdq_greens(None, None, 0, 0, None, None, None, None) == binding.SDQ_EINVAL
+    assert lib.sdq_greens_noalloc(None, None, 0, 0, None, None, None, None) == binding.SDQ_EINVAL
     assert lib.sdq_sync(None) == binding.SDQ_EINVAL
     assert lib.sdq_last_error(None) == b"null context"
     out = ctypes.c_void_p()
