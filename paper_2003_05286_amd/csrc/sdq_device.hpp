@@ -771,6 +771,125 @@ __device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& 
   });
 }
 
+// Y <- A^{-1} Y for the register matrices A (n x n, padding zero) and Y, by
+// Gaussian elimination with column pivoting: at step j the pivot is the
+// live column of largest |A[j][c]| (ties: smallest column), its entries
+// below row j divided by the pivot are the multipliers l_r, and row j times
+// l_r is subtracted from every row r > j of the other live columns and of Y
+// (so Y becomes L^{-1} Y on the way; L itself is not kept).  This is Gaussian
+// elimination with partial pivoting applied to A^T, arranged like cpqr: the
+// rows are static per tile (row j of every column is fetched from a fixed
+// lane group), each wave offers its best column through LDS and one barrier
+// per step settles the pivot, and columns are never moved.  Then U (U[i][j]
+// = A[i][perm j], i <= j) is parked in S.R by original column, as cpqr parks
+// R, and Y <- U^{-1} Y by back substitution; the rows of the result are in
+// pivot order: A^{-1} Y [S.perm[s]][c] = Y[s][c].  A is destroyed.  A
+// singular A leaves non-finite entries in Y.
+template <int NT, int P, bool ELDS>
+__device__ void ge_solve(const Lane& L, const int n, RM<NT, P>& A, RM<NT, P>& Y, Smem<NT, P, ELDS>& S) {
+  using G = Geo<NT, P>;
+  constexpr int CT = G::CT;
+  int ps[CT];  // -1: live, not yet chosen; else the step (padding: own index)
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+    ps[c] = (tile_ok<NT, P>(L, c) && col < n) ? -1 : col;
+  }
+  int buf = 0;
+  static_for<NT>([&](auto tjc) {
+    constexpr int TJ = decltype(tjc)::value;
+    const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
+    for (int j = 16 * TJ; j < jend; ++j) {
+      const int jj = j - 16 * TJ, gj = jj & 3, rj = jj >> 2;
+      const int jsrc = ((gj << 4) | L.cl) << 2;
+      // row j of each column and of Y, from the lane group holding it
+      double ajc[CT], yjc[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        ajc[c] = lane_fetch(jsrc, pick4(A.v[c][TJ], rj));
+        yjc[c] = lane_fetch(jsrc, pick4(Y.v[c][TJ], rj));
+      }
+      // ---- wave-local candidate: largest |A[j][c]| of this wave's live columns
+      double key = -1.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const double kc = ps[c] < 0 ? pivot_key(fabs(ajc[c]), col_of<NT, P>(L, c)) : -1.0;
+        key = c == 0 ? kc : key_max(key, kc);
+      }
+      key = row_max16(key);
+      const int bc = pivot_col(key);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        if (key >= 0.0 && ps[c] < 0 && col_of<NT, P>(L, c) == bc) {
+#pragma unroll
+          for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S.cand[buf][L.w][row_of(L, ti, r)] = A.v[c][ti][r];
+        }
+      }
+      double pk = key;
+      if constexpr (P > 1) {
+        if (L.l == 0) S.ckey[buf][L.w] = key;
+        __syncthreads();
+        pk = S.ckey[buf][0];
+#pragma unroll
+        for (int q = 1; q < P; ++q) pk = key_max(pk, S.ckey[buf][q]);
+      } else {
+        __builtin_amdgcn_wave_barrier();
+      }
+      const int pc = pivot_col(pk);
+      const int pw = (pc >> 4) % P;
+      const double* xc = S.cand[buf][pw];
+      const double rinv = 1.0 / xc[j];
+      // multipliers of the rows below j (zero at and above j)
+      double ml[NT][4];
+#pragma unroll
+      for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ml[ti][r] = xc[row_of(L, ti, r)];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          ml[ti][r] = (ti > TJ || L.g + 4 * r > jj) ? ml[ti][r] * rinv : 0.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const bool upd = ps[c] < 0 && col_of<NT, P>(L, c) != pc;
+        const double a = upd ? ajc[c] : 0.0;
+#pragma unroll
+        for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            A.v[c][ti][r] = fma(-ml[ti][r], a, A.v[c][ti][r]);
+            Y.v[c][ti][r] = fma(-ml[ti][r], yjc[c], Y.v[c][ti][r]);
+          }
+        if (ps[c] < 0 && col_of<NT, P>(L, c) == pc) ps[c] = j;
+      }
+      if (L.t == 0) S.perm[j] = pc;
+      buf ^= 1;
+    }
+  });
+  // ---- park U in LDS by original column (rows <= its step), as cpqr does
+#pragma unroll
+  for (int c = 0; c < CT; ++c) {
+    if (!tile_ok<NT, P>(L, c)) continue;
+    const int col = col_of<NT, P>(L, c);
+    const bool live = col < n;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        S.R[col * G::LDR + row] = live ? A.v[c][ti][r] : (row == col ? 1.0 : 0.0);
+      }
+    if (L.g == 0) S.sinv[col] = ps[c];
+  }
+  for (int t = n + L.t; t < G::NP; t += G::THREADS) S.perm[t] = t;
+  __syncthreads();
+  back_subst<NT, P, ELDS>(L, n, S, Y);
+}
+
 // left operand of R P^T: column c, rows <= s_c
 template <int NT, int P, bool ELDS>
 struct RPtOp {
@@ -1551,8 +1670,9 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
         P1.v[c][ti][r] = lm * P1.v[c][ti][r] * rpi + lpi * P2.v[c][ti][r] * rm;
       }
     }
-  __syncthreads();
-  cpqr<NT, P, ELDS>(L, n, P1, S);
+  // Y = D_Lp^{-1} T1, then Y <- Mid^{-1} Y by Gaussian elimination with
+  // column pivoting (any backward-stable solve of the middle matrix serves,
+  // Sec. 6.1; the rows of the result come out in pivot order, S.perm)
   RM<NT, P> Y;
   load_rm<NT, P>(L, Y, T1, n, false);
 #pragma unroll
@@ -1565,8 +1685,8 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
 #pragma unroll
       for (int c = 0; c < CT; ++c) Y.v[c][ti][r] *= lpi;
     }
-  apply_qt<NT, P, ELDS>(L, n, S, Y);
-  back_subst<NT, P, ELDS>(L, n, S, Y);
+  __syncthreads();
+  ge_solve<NT, P, ELDS>(L, n, P1, Y, S);
   // G = U2 D_Rp^{-1} P Z :  A(i, s) = gmem(U2)[i][perm s] / max(gmem(D2)[perm s], 1)
   RM<NT, P> Gm;
   if constexpr (ELDS) {
