@@ -58,6 +58,7 @@ def lib():
         L.or_cpqr.argtypes = [c_int, d, d, i]
         L.or_udt.argtypes = [c_int, d, d, d, d]
         L.or_udt_complex.argtypes = [c_int, d, d, d, d]
+        L.or_greens_complex.argtypes = [c_int, c_int, c_int, d, d, d, d]
         L.or_expk_planewave.argtypes = [c_int, c_double, c_double, c_double, d]
         _lib = L
     return _lib
@@ -243,6 +244,18 @@ def udt_complex(W):
     _chk(lib().or_udt_complex(n, _p(W.view(np.float64)), _p(U.view(np.float64)), _p(D),
                               _p(T.view(np.float64))))
     return U, D, T
+
+
+def greens_complex(slices, k):
+    """Complex dense slices [m, n, n] (complex128): G (complex), log|det(1+B)|
+    and the phase det(1+B)/|det(1+B)| (complex)."""
+    sl = np.ascontiguousarray(slices, dtype=np.complex128)
+    m, n, _ = sl.shape
+    G = np.zeros((n, n), np.complex128)
+    ld, ph = np.zeros(1), np.zeros(2)
+    _chk(lib().or_greens_complex(n, m, int(k), _p(sl.view(np.float64)), _p(G.view(np.float64)),
+                                 _p(ld), _p(ph)))
+    return G, float(ld[0]), complex(ph[0], ph[1])
 
 
 def expk_planewave(L, t, dtau, s=1.0):

@@ -36,6 +36,8 @@
  *   or_greens_tdisp_dense  dense matrices (generalized slices)
  *   or_udt_complex     Sec. 4.2.2 over the complex numbers (complex slices,
  *                      App. B): complex column-pivoted Householder QR
+ *   or_greens_complex  Sec. 4.1, 4.2.2 and 5.1 (inv_one_plus_loh) for complex
+ *                      slices (App. B), with the phase of det(1 + B)
  *   jacobi_svd,        Sec. 4.2 (the Jacobi SVD the paper compares with the
  *   or_greens_stab     QR; one-sided, Hestenes), as an independent stabilizer
  *                      of the same chain: a cross-check of the QR path
@@ -1049,6 +1051,176 @@ int or_udt_complex(int n, const double* Wd, double* Ud, double* D, double* Td) {
   free(tau);
   free(jpvt);
   return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Complex slices (App. B: the slices of the spin-fermion model are complex
+ * matrices).  The chain of Sec. 4.1 with the complex UDT of Sec. 4.2.2 and
+ * the equal-time G by inv_one_plus_loh (Sec. 5.1), all over the complex
+ * numbers; det(1 + B_M...B_1) comes with a complex phase instead of a sign. */
+
+/* C = A B, complex n x n (C must not alias A or B) */
+static void cmat_mul(int n, const double complex* A, const double complex* B, double complex* C) {
+  for (int i = 0; i < n; ++i) {
+    double complex* c = C + (size_t)i * n;
+    for (int j = 0; j < n; ++j) c[j] = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const double complex a = A[(size_t)i * n + p];
+      const double complex* b = B + (size_t)p * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
+    }
+  }
+}
+
+/* complex UDT of W (the decomposition of or_udt_complex) */
+static void udt_c(int n, const double complex* W, double complex* U, double* D, double complex* T) {
+  double complex* F = (double complex*)malloc(sizeof(double complex) * (size_t)n * n);
+  double complex* tau = (double complex*)malloc(sizeof(double complex) * n);
+  int* jpvt = (int*)malloc(sizeof(int) * n);
+  memcpy(F, W, sizeof(double complex) * (size_t)n * n);
+  cpqr_c(n, F, jpvt, tau);
+  /* Q = H_0 (H_1 (... H_{n-1} I)) */
+  for (size_t e = 0; e < (size_t)n * n; ++e) U[e] = 0.0;
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+  for (int i = n - 1; i >= 0; --i) {
+    if (tau[i] == 0.0) continue;
+    for (int j = 0; j < n; ++j) {
+      double complex w = U[(size_t)i * n + j];
+      for (int r = i + 1; r < n; ++r) w += conj(F[(size_t)r * n + i]) * U[(size_t)r * n + j];
+      w *= tau[i];
+      U[(size_t)i * n + j] -= w;
+      for (int r = i + 1; r < n; ++r) U[(size_t)r * n + j] -= w * F[(size_t)r * n + i];
+    }
+  }
+  for (size_t e = 0; e < (size_t)n * n; ++e) T[e] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    D[i] = fabs(creal(F[(size_t)i * n + i]));
+    const double s = D[i] > 0.0 ? 1.0 / D[i] : 1.0;
+    for (int j = i; j < n; ++j) T[(size_t)i * n + jpvt[j]] = F[(size_t)i * n + j] * s;
+  }
+  free(F);
+  free(tau);
+  free(jpvt);
+}
+
+/* Inverse of a complex matrix by Gauss-Jordan elimination with partial
+ * pivoting on [A | I], with log|det A| and the phase det A / |det A|. */
+static void lu_inverse_c(int n, const double complex* A, double complex* Ainv, double* logabsdet,
+                         double complex* phase) {
+  double complex* W = (double complex*)malloc(sizeof(double complex) * (size_t)n * n);
+  memcpy(W, A, sizeof(double complex) * (size_t)n * n);
+  for (size_t e = 0; e < (size_t)n * n; ++e) Ainv[e] = 0.0;
+  for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + i] = 1.0;
+  double ld = 0.0;
+  double complex ph = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (cabs(W[(size_t)r * n + c]) > cabs(W[(size_t)p * n + c])) p = r;
+    if (p != c) {
+      for (int j = 0; j < n; ++j) {
+        double complex t = W[(size_t)c * n + j];
+        W[(size_t)c * n + j] = W[(size_t)p * n + j];
+        W[(size_t)p * n + j] = t;
+        t = Ainv[(size_t)c * n + j];
+        Ainv[(size_t)c * n + j] = Ainv[(size_t)p * n + j];
+        Ainv[(size_t)p * n + j] = t;
+      }
+      ph = -ph;
+    }
+    const double complex piv = W[(size_t)c * n + c];
+    const double ap = cabs(piv);
+    ld += log(ap);
+    ph *= piv / ap;
+    const double complex ip = 1.0 / piv;
+    for (int j = 0; j < n; ++j) {
+      W[(size_t)c * n + j] *= ip;
+      Ainv[(size_t)c * n + j] *= ip;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double complex f = W[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        W[(size_t)r * n + j] -= f * W[(size_t)c * n + j];
+        Ainv[(size_t)r * n + j] -= f * Ainv[(size_t)c * n + j];
+      }
+    }
+  }
+  if (logabsdet) *logabsdet = ld;
+  if (phase) *phase = ph / cabs(ph);
+  free(W);
+}
+
+/* Equal-time G = (1 + B_M ... B_1)^{-1} of complex dense slices (B_q the
+ * row-major n x n complex matrix at slices + (q-1) n n, interleaved re, im),
+ * log|det(1 + B_M ... B_1)| and its phase (phase[0] + i phase[1]).
+ *   chain (Sec. 4.1): U = 1, D = 1, T = 1; per block of k slices (the last
+ *     one shorter), W = (B_q1 ... B_q0) U multiplied out naively, W <- W D,
+ *     complex UDT W = U' D' T'' (Sec. 4.2.2), U <- U', D <- D', T <- T'' T;
+ *   inversion (Sec. 5.1, inv_one_plus_loh as printed): D_p = max(D, 1),
+ *     D_m = min(D, 1), M = T^{-1} D_p^{-1} + U D_m, G = T^{-1} D_p^{-1} M^{-1},
+ *     with T^{-1} and M^{-1} by Gauss-Jordan;
+ *   determinant: 1 + U D T = M D_p T, so log|det(1 + B)| = log|det M| +
+ *     sum log D_p + log|det T| and its phase is that of det M times that of
+ *     det T. */
+int or_greens_complex(int n, int m, int k, const double* slices, double* Gd, double* logdet, double* phase) {
+  if (n <= 0 || m <= 0 || k <= 0 || !slices || !Gd) return OR_EINVAL;
+  for (size_t i = 0; i < 2 * (size_t)m * n * n; ++i)
+    if (!isfinite(slices[i])) return OR_ERANGE;
+  const double complex* B = (const double complex*)slices;
+  double complex* G = (double complex*)Gd;
+  const size_t nn = (size_t)n * n;
+  double complex *U = malloc(sizeof(double complex) * nn), *T = malloc(sizeof(double complex) * nn);
+  double complex *W = malloc(sizeof(double complex) * nn), *tmp = malloc(sizeof(double complex) * nn);
+  double complex *U2 = malloc(sizeof(double complex) * nn), *T2 = malloc(sizeof(double complex) * nn);
+  double *D = malloc(sizeof(double) * n), *D2 = malloc(sizeof(double) * n);
+  for (size_t e = 0; e < nn; ++e) U[e] = T[e] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    U[(size_t)i * n + i] = T[(size_t)i * n + i] = 1.0;
+    D[i] = 1.0;
+  }
+  for (int q0 = 1; q0 <= m; q0 += k) {
+    const int q1 = q0 + k - 1 < m ? q0 + k - 1 : m;
+    memcpy(W, U, sizeof(double complex) * nn);
+    for (int q = q0; q <= q1; ++q) {
+      cmat_mul(n, B + (size_t)(q - 1) * nn, W, tmp);
+      memcpy(W, tmp, sizeof(double complex) * nn);
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) W[(size_t)i * n + j] *= D[j];
+    udt_c(n, W, U2, D2, T2);
+    cmat_mul(n, T2, T, tmp);
+    memcpy(T, tmp, sizeof(double complex) * nn);
+    memcpy(U, U2, sizeof(double complex) * nn);
+    memcpy(D, D2, sizeof(double) * n);
+  }
+  /* inv_one_plus_loh */
+  double complex *Ti = malloc(sizeof(double complex) * nn), *X = malloc(sizeof(double complex) * nn);
+  double complex *M = malloc(sizeof(double complex) * nn), *Mi = malloc(sizeof(double complex) * nn);
+  double ldT = 0.0, ldM = 0.0, ldp = 0.0;
+  double complex phT = 1.0, phM = 1.0;
+  lu_inverse_c(n, T, Ti, &ldT, &phT);
+  for (int i = 0; i < n; ++i) ldp += log(D[i] > 1.0 ? D[i] : 1.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double dpj = D[j] > 1.0 ? D[j] : 1.0, dmj = D[j] < 1.0 ? D[j] : 1.0;
+      X[(size_t)i * n + j] = Ti[(size_t)i * n + j] / dpj;                    /* T^{-1} D_p^{-1} */
+      M[(size_t)i * n + j] = X[(size_t)i * n + j] + U[(size_t)i * n + j] * dmj; /* + U D_m */
+    }
+  lu_inverse_c(n, M, Mi, &ldM, &phM);
+  cmat_mul(n, X, Mi, G);
+  const double complex ph = phM * phT;
+  if (logdet) *logdet = ldM + ldp + ldT;
+  if (phase) {
+    phase[0] = creal(ph);
+    phase[1] = cimag(ph);
+  }
+  int ok = isfinite(ldM + ldp + ldT);
+  for (size_t e = 0; e < nn && ok; ++e) ok = isfinite(creal(G[e])) && isfinite(cimag(G[e]));
+  free(U); free(T); free(W); free(tmp); free(U2); free(T2); free(D); free(D2);
+  free(Ti); free(X); free(M); free(Mi);
+  return ok ? OR_OK : OR_ERANGE;
 }
 
 /* exp(-s dtau K) for the periodic L x L square lattice with K_ij = -t on

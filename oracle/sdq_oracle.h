@@ -39,6 +39,8 @@ int or_cpqr(int n, double* A, double* Q, int* jpvt);
 int or_udt(int n, const double* W, double* U, double* D, double* T);
 /* complex UDT; W, U, T interleaved (re, im) n x n, D real n */
 int or_udt_complex(int n, const double* W, double* U, double* D, double* T);
+/* complex dense slices [m][n][n] interleaved: G (interleaved), log|det(1+B)|, phase[2] */
+int or_greens_complex(int n, int m, int k, const double* slices, double* G, double* logdet, double* phase);
 int or_expk_planewave(int L, double t, double dtau, double s, double* out);
 
 #endif

@@ -98,3 +98,31 @@ class Brute:
     @staticmethod
     def to_np(A):
         return np.array([[float(A[i, j]) for j in range(A.cols)] for i in range(A.rows)])
+
+
+class BruteDense:
+    """The plain definitions for dense slices (real or complex), multiplied
+    out at `dps` digits with no stabilization: G = (1 + B_M ... B_1)^{-1},
+    log|det(1 + B_M ... B_1)| and det / |det| (a complex phase)."""
+
+    def __init__(self, slices, dps=200):
+        self.ctx = mpmath.MPContext()
+        self.ctx.dps = dps
+        mp = self.ctx
+        sl = np.asarray(slices)
+        self.m, self.n, _ = sl.shape
+        self.B = [mp.matrix([[mp.mpc(complex(x)) for x in row] for row in s]) for s in sl]
+
+    def greens(self):
+        mp = self.ctx
+        P = mp.eye(self.n)
+        for q in range(self.m):
+            P = self.B[q] * P
+        A = P + mp.eye(self.n)
+        d = mp.det(A)
+        G = mp.inverse(A)
+        return G, mp.log(abs(d)), complex(d / abs(d))
+
+    @staticmethod
+    def to_np(A):
+        return np.array([[complex(A[i, j]) for j in range(A.cols)] for i in range(A.rows)])

@@ -698,3 +698,79 @@ def test_complex_cpqr_norm_recompute_near_dependent_columns(n, rank, noise):
     _pivot_invariant(R, 1e-6)
     dl = np.abs(np.diag(Rl))
     assert np.all(np.abs(D - dl) <= 1e-6 * dl + 1e-13 * np.linalg.norm(W))
+
+
+# ---------------------------------------------------------------------------
+# complex slices (App. B): the chain, the Loh inversion and the phase of
+# det(1 + B) over the complex numbers
+
+def _complex_hubbard_slices(L, beta, seed, phase_amp=0.3, k_nonsym=0.0):
+    """B_l = E diag(exp(lambda s_l + i phi_l)) (a complex auxiliary field),
+    optionally with a complex non-symmetric perturbation of E."""
+    inst = wl.hubbard_ising(L, beta, 1, 1, seed=seed)[0]
+    rng = np.random.default_rng(seed + 1)
+    phi = rng.uniform(-phase_amp, phase_amp, inst.field.shape)
+    E = inst.expk.astype(complex)
+    if k_nonsym:
+        E = E + k_nonsym * (rng.standard_normal(E.shape) + 1j * rng.standard_normal(E.shape))
+    return np.stack([E * np.exp(inst.alpha * inst.field[q] + 1j * phi[q])[None, :] for q in range(inst.m)])
+
+
+@pytest.mark.parametrize("beta,theta", [(10.0, 0.013), (40.0, 0.0071), (40.0, -0.02)])
+def test_complex_chain_imaginary_chemical_potential_closed_form(beta, theta):
+    """U = 0 with a uniform complex phase per slice, B_l = e^{i theta} E (an
+    imaginary chemical potential): B_M...B_1 = e^{i M theta} exp(-beta K), so
+    G = V diag(1 / (1 + e^{i M theta - beta eps})) V^T and
+    det(1 + B) = prod_k (1 + e^{i M theta - beta eps_k})."""
+    L, dtau = 4, 0.1
+    K = wl.hopping_matrix(L)
+    m = int(round(beta / dtau))
+    E, _ = wl.expk_pair(K, dtau)
+    sl = np.stack([np.exp(1j * theta) * E.astype(complex)] * m)
+    G, ld, ph = oracle.greens_complex(sl, 10)
+    eps, V = np.linalg.eigh(K)
+    z = np.exp(1j * m * theta - beta * eps)
+    Gc = (V / (1.0 + z)) @ V.T
+    # the slices carry the rounding of exp(-dtau K) and e^{i theta} M times
+    # over (a few 1e-13 relative in B_M...B_1), and |1 + z| reaches 0.3 on
+    # the zero modes of K: a few 1e-12 is the scheme's own accuracy here
+    assert relF(G, Gc) < 5e-12
+    assert ld == pytest.approx(np.sum(np.log(np.abs(1.0 + z))), rel=1e-13, abs=1e-12)
+    phc = np.prod((1.0 + z) / np.abs(1.0 + z))
+    assert abs(ph - phc) < 5e-12
+
+
+def test_complex_chain_of_real_slices_is_the_real_chain():
+    inst = wl.hubbard_ising(4, 10.0, 1, 1, seed=41)[0]
+    sl = np.stack([inst.expk * np.exp(inst.alpha * inst.field[q])[None, :] for q in range(inst.m)])
+    G, ld, ph = oracle.greens_complex(sl.astype(complex), 10)
+    Gr, ldr, sgr = oracle.greens_dense(sl, 10)
+    assert np.abs(G.imag).max() == 0.0
+    assert relF(G.real, Gr) < 1e-13
+    assert ld == pytest.approx(ldr, rel=1e-13)
+    assert ph == pytest.approx(sgr, abs=1e-15)
+
+
+@pytest.mark.parametrize("beta,k,nonsym", [(10.0, 10, 0.0), (4.0, 7, 0.02), (40.0, 10, 0.0)])
+def test_complex_chain_brute_force(beta, k, nonsym):
+    """Random complex auxiliary field (and a non-symmetric complex slice
+    exponential with k not dividing M): the oracle against the plain
+    definitions multiplied out at 250 digits."""
+    from _brute import BruteDense
+    sl = _complex_hubbard_slices(4, beta, 4700 + int(beta) + k, k_nonsym=nonsym)
+    G, ld, ph = oracle.greens_complex(sl, k)
+    b = BruteDense(sl, dps=250)
+    Gmp, ldmp, phmp = b.greens()
+    assert relF(G, BruteDense.to_np(Gmp)) < 1e-11
+    assert ld == pytest.approx(float(ldmp), rel=1e-12)
+    assert abs(ph - phmp) < 1e-10
+
+
+def test_complex_chain_conjugate_slices():
+    """Conjugating every slice conjugates G and the phase."""
+    sl = _complex_hubbard_slices(4, 4.0, 4800)
+    G, ld, ph = oracle.greens_complex(sl, 10)
+    Gc, ldc, phc = oracle.greens_complex(np.conj(sl), 10)
+    assert relF(Gc, np.conj(G)) < 1e-13
+    assert ldc == pytest.approx(ld, rel=1e-13)
+    assert abs(phc - np.conj(ph)) < 1e-13
