@@ -228,6 +228,32 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
 sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u,
                            double* d, double* t);
 
+/* A chain of complex slices (e.g. the spin-fermion model of App. B, whose
+ * slices are complex matrices): slice l (1-based) is the row-major n x n
+ * complex device matrix at slices + 2 (l-1) n n, entries as (re, im) pairs. */
+typedef struct {
+  int32_t n;              /* 1 <= n <= 64                                           */
+  int32_t m;              /* slices, m >= 1                                          */
+  int32_t k;              /* stabilization interval, 1 <= k <= m (Sec. 4.1)         */
+  int32_t pad_;
+  const double* slices;   /* [m][n][n] complex                                       */
+} sdq_complex_instance;
+
+/* Equal-time G = (1 + B_m ... B_1)^{-1} of chains of complex slices, with
+ * log|det(1 + B_m ... B_1)| and the phase det / |det| (App. B; for complex
+ * slices the determinant is complex, not just signed):  the stabilized
+ * product of Sec. 4.1 with the complex pivoted-QR UDT (Sec. 4.2.2,
+ * sdq_udt_complex's decomposition) every k slices, and Loh's split inversion
+ * (Sec. 5.1).  One workgroup per chain, matrices resident in LDS.
+ *   g       host array [count] of device pointers to [n][n] complex outputs
+ *           (entries may be NULL)
+ *   logdet  device [count] or NULL
+ *   phase   device [count][2] (re, im) or NULL
+ *   status  device [count] or NULL (SDQ_ERANGE: non-finite data or result)
+ * n > 64 returns SDQ_EUNSUPPORTED; chains of different n, m, k may be mixed. */
+sdq_status sdq_greens_complex(sdq_ctx* ctx, const sdq_complex_instance* inst, int32_t count, double* const* g,
+                              double* logdet, double* phase, int32_t* status);
+
 /* Stabilized chain of one instance set (Sec. 4.1): the UDT factors of
  * B_m...B_1 for each chain, u, t [count][n][n], d [count][n] (device).
  * All chains must share n. */

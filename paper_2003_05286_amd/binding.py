@@ -32,7 +32,8 @@ EXPORTS = ("sdq_create", "sdq_destroy", "sdq_last_error", "sdq_version", "sdq_gr
            "sdq_chain_udt", "sdq_tune", "sdq_set_graphs", "sdq_set_profiling",
            "sdq_kernel_stats", "sdq_sync", "sdq_similarity", "sdq_metropolis",
            "sdq_local_sweep", "sdq_langevin", "sdq_hmc", "sdq_set_stabilizer", "sdq_greens_dense",
-           "sdq_greens_tdisp_dense", "sdq_udt_complex", "sdq_kernel_names", "sdq_greens_noalloc")
+           "sdq_greens_tdisp_dense", "sdq_udt_complex", "sdq_kernel_names", "sdq_greens_noalloc",
+           "sdq_greens_complex")
 
 
 class SdqError(RuntimeError):
@@ -45,6 +46,11 @@ class _Instance(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("expk", ctypes.c_void_p), ("expk_inv", ctypes.c_void_p),
                 ("field", ctypes.c_void_p), ("alpha", ctypes.c_double)]
+
+
+class _ComplexInstance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("slices", ctypes.c_void_p)]
 
 
 class _DenseInstance(ctypes.Structure):
@@ -81,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     L.sdq_release.argtypes = [vp, ctypes.c_uint64]
     L.sdq_udt.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.sdq_udt_complex.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.sdq_greens_complex.argtypes = [vp, P(_ComplexInstance), i32, P(vp), vp, vp, vp]
     L.sdq_chain_udt.argtypes = [vp, P(_Instance), i32, vp, vp, vp]
     L.sdq_tune.argtypes = [vp, P(i32), i32, ctypes.c_char_p]
     L.sdq_set_graphs.argtypes = [vp, ctypes.c_int]
@@ -297,6 +304,29 @@ class Context:
         self._chk(self.lib.sdq_udt_complex(self.h, n, cnt, _ptr(torch.view_as_real(w)),
                                            _ptr(torch.view_as_real(u)), _ptr(d), _ptr(torch.view_as_real(t))))
         return u, d, t
+
+    def greens_complex(self, slices, k):
+        """Chains of complex slices (sdq_greens_complex).  slices: list of
+        complex128 tensors [m, n, n] (one per chain, B_l = slices[l-1]).
+        Returns (G list of complex [n, n], logdet [count], phase complex
+        [count], status [count] int32)."""
+        cnt = len(slices)
+        arr = (_ComplexInstance * max(cnt, 1))()
+        ks = k if isinstance(k, (list, tuple)) else [k] * cnt
+        gs = []
+        for i, sl in enumerate(slices):
+            if (sl.dim() != 3 or sl.shape[1] != sl.shape[2] or sl.dtype != torch.complex128
+                    or not sl.is_contiguous() or sl.device != self.tdev):
+                raise ValueError(f"slices[{i}]: need a contiguous complex128 [m, n, n] tensor on {self.tdev}")
+            m, n = sl.shape[0], sl.shape[1]
+            arr[i] = _ComplexInstance(n, m, int(ks[i]), 0, sl.data_ptr())
+            gs.append(torch.empty(n, n, dtype=torch.complex128, device=self.tdev))
+        ld = self._empty(cnt)
+        ph = self._empty(cnt, 2)
+        stt = torch.empty(cnt, dtype=torch.int32, device=self.tdev)
+        self._chk(self.lib.sdq_greens_complex(self.h, arr, cnt, self._ptr_array(gs), _ptr(ld), _ptr(ph),
+                                              _ptr(stt)))
+        return gs, ld, torch.view_as_complex(ph), stt
 
     def chain_udt(self, chains):
         cnt = len(chains)

@@ -202,6 +202,19 @@ hipError_t launch_udt_complex(int n, int count, const double* w, double* u, doub
                               hipStream_t s);
 hipError_t launch_udt(int nt, int n, int count, const double* w, double* u, double* d, double* t,
                       hipStream_t s);
+// One chain of complex dense slices (sdq_greens_complex): slices [m][n][n]
+// and g [n][n] interleaved (re, im); logdet a scalar, phase two doubles.
+struct CChain {
+  const double* slices;
+  double* g;
+  double* logdet;
+  double* phase;
+  int32_t* status;
+  int32_t n, m, k, pad;
+};
+// G, log|det(1+B)| and its phase for `count` chains, n <= complex_udt_max_n(),
+// one workgroup per chain (grid-stride)
+hipError_t launch_greens_complex(const CChain* tab, int count, int grid, hipStream_t s);
 // M <- left M right for count n x n matrices (device pointer table), n <= 128
 hipError_t launch_similarity(int nt, int n, int count, double* const* mats, const double* left,
                              const double* right, int grid, hipStream_t s);

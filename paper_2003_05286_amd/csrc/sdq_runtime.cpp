@@ -88,6 +88,7 @@ struct sdq_ctx {
   DevBuf d_hmc;    // sdq_hmc: gradients, start fields, momenta, energies, statuses
   int stab = 0;    // stabilizer of every sweep: 0 pivoted QR, 1 Jacobi SVD
   DevBuf d_htab;   // sdq_hmc: chain table
+  DevBuf d_ctab;   // sdq_greens_complex: chain table
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   // pinned staging of plan images, a ring: the host waits for the plan
   // kStageSlots back, not the previous one, so it builds and enqueues the
@@ -800,6 +801,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_ltab.p) (void)hipFree(ctx->d_ltab.p);
   if (ctx->d_hmc.p) (void)hipFree(ctx->d_hmc.p);
   if (ctx->d_htab.p) (void)hipFree(ctx->d_htab.p);
+  if (ctx->d_ctab.p) (void)hipFree(ctx->d_ctab.p);
   for (auto& sl : ctx->stage)
     if (sl.h) (void)hipHostFree(sl.h);
   for (auto& kv : ctx->stats)
@@ -1314,6 +1316,44 @@ sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double*
   const int grid = std::max(1, std::min(count, 2 * ctx->num_cu));
   return timed(ctx, "udt_complex",
                [&] { return sdq::launch_udt_complex(n, count, w, u, d, t, grid, ctx->stream); });
+}
+
+sdq_status sdq_greens_complex(sdq_ctx* ctx, const sdq_complex_instance* inst, int32_t count, double* const* g,
+                              double* logdet, double* phase, int32_t* status) {
+  if (!ctx) return SDQ_EINVAL;
+  if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
+  if (count == 0) return SDQ_OK;
+  if (!inst) return fail(ctx, SDQ_EINVAL, "inst is NULL");
+  std::vector<sdq::CChain> tab(count);
+  for (int i = 0; i < count; ++i) {
+    const sdq_complex_instance& c = inst[i];
+    char buf[160];
+    if (c.n < 1 || c.n > sdq::complex_udt_max_n()) {
+      snprintf(buf, sizeof buf, "instance %d: complex chains need 1 <= n <= %d (n = %d)", i,
+               sdq::complex_udt_max_n(), c.n);
+      return fail(ctx, c.n < 1 ? SDQ_EINVAL : SDQ_EUNSUPPORTED, buf);
+    }
+    if (c.m < 1 || c.k < 1 || c.k > c.m || !c.slices) {
+      snprintf(buf, sizeof buf, "instance %d: need m >= 1, 1 <= k <= m and slices", i);
+      return fail(ctx, SDQ_EINVAL, buf);
+    }
+    tab[i] = sdq::CChain{c.slices, g ? g[i] : nullptr, logdet ? logdet + i : nullptr,
+                         phase ? phase + 2 * i : nullptr, status ? status + i : nullptr, c.n, c.m, c.k, 0};
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  ctx->err.clear();
+  HIP_TRY(grow(ctx->d_ctab, (size_t)count * sizeof(sdq::CChain)), "hipMalloc(chain table)");
+  // stream-ordered after any earlier launch that read the table; the source
+  // is pageable, so it may be reused once this returns
+  HIP_TRY(hipMemcpyAsync(ctx->d_ctab.p, tab.data(), (size_t)count * sizeof(sdq::CChain), hipMemcpyHostToDevice,
+                         ctx->stream),
+          "hipMemcpyAsync(chain table)");
+  if (status) HIP_TRY(sdq::launch_fill_i32(status, count, 0, ctx->stream), "fill(status)");
+  // one workgroup per CU (148 KB of LDS), grid-stride over the chains
+  const int grid = std::max(1, std::min(count, ctx->num_cu));
+  return timed(ctx, "greens_complex", [&] {
+    return sdq::launch_greens_complex((const sdq::CChain*)ctx->d_ctab.p, count, grid, ctx->stream);
+  });
 }
 
 sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf,
