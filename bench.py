@@ -71,7 +71,7 @@ def main():
                              "hubbard_L8_b20_phi_batch128", "hubbard_L8_b20_phi_langevin128",
                              "hubbard_L8_b20_phi_hmc128", "hubbard_L8_b40_dense128",
                              "hubbard_L16_b40_batch128", "hubbard_L32_b40_single",
-                             "udt_complex_n64_batch4096"],
+                             "udt_complex_n64_batch4096", "hubbard_L8_b40_complex128"],
                     help="the default is the headline workload; the others time the same library "
                          "on the single small chain (latency of one G), the mixed-size batch "
                          "(equal-time G), the continuous-field batch (log|det| + gradient), the "
@@ -113,6 +113,8 @@ def main():
         del src, dst
     if args.workload == "udt_complex_n64_batch4096":
         return run_udt_complex(args, dev, sdq, wl)
+    if args.workload == "hubbard_L8_b40_complex128":
+        return run_greens_complex(args, dev, sdq, wl)
     W = wl.workload(args.workload, scale=args.scale)
     insts = W.instances
     l_list = W.l_list or []
@@ -592,6 +594,90 @@ def run_udt_complex(args, dev, sdq, wl):
             oracle.udt_complex(W1)
         d1 = time.perf_counter() - c1
         out["cpu_baseline"]["one_core"] = {"value": 256 / d1, "sample": f"256 matrices on one thread; {d1:.1f} s"}
+        out["cpu_baseline"].update(host_cpu()[0])
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def complex_chain_flops(n, m, k):
+    """Real flops of one chain of complex slices: 8 n^3 per complex slice
+    product, per stabilization the complex QR and Q (16/3 + 16/3) n^3 and the
+    T update (4 n^3), and the inversion (elimination 8/3 n^3, the n
+    right-hand sides 8 n^3)."""
+    nb = math.ceil(m / k)
+    return (8.0 * m + nb * (32.0 / 3.0 + 4.0) + 8.0 / 3.0 + 8.0) * n ** 3
+
+
+def run_greens_complex(args, dev, sdq, wl):
+    """Equal-time G, log|det| and phase of 128 chains of complex slices,
+    L = 8 (N = 64), beta = 40 (M = 400), k = 10 (App. B's complex slices)."""
+    import numpy as np
+    import torch
+
+    L, beta, chains, k = 8, 40.0, max(1, int(round(128 * args.scale))), 10
+    E, lam, s, phi = wl.complex_hubbard(L, beta, chains)
+    m, n = s.shape[1], s.shape[2]
+    Ed = torch.from_numpy(E).to(dev).to(torch.complex128)
+    # the dense slices, formed on the device (input preparation, not timed)
+    sls = []
+    for c in range(chains):
+        v = torch.exp(torch.from_numpy(lam * s[c] + 1j * phi[c]).to(dev))  # [m, n]
+        sls.append((Ed[None, :, :] * v[:, None, :]).contiguous())
+    torch.cuda.synchronize()
+    ctx = sdq.Context(0)
+    print(f"[bench] hubbard_L8_b40_complex128: {chains} chains of complex slices, n={n}, m={m}, k={k}",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        gs, ld, ph, st = ctx.greens_complex(sls, k)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        gs, ld, ph, st = ctx.greens_complex(sls, k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_k, ms_k = ctx.kernel_stats("greens_complex")
+    ctx.set_profiling(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    launch_s = ms_k / max(n_k, 1) * 1e-3
+    flops = chains * complex_chain_flops(n, m, k)
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step; kernel {launch_s * 1e3:.3f} ms x {n_k}",
+          file=sys.stderr, flush=True)
+    ok = bool((st == 0).all().item())
+    out = {
+        "metric": "stabilized Green's functions/sec of complex-slice chains (FP64, L=8, beta=40, 128 chains)",
+        "value": chains / (ms_step * 1e-3),
+        "unit": "chains/s (each: complex G, log|det|, phase)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "hubbard_L8_b40_complex128", "chains": chains, "n": n, "m": m, "k": k,
+                   "slices": "E diag(exp(lambda s + i phi)), s = +-1, phi ~ U(-0.3, 0.3), dense complex"},
+        "roofline": {"kernel": "greens_complex", "bound": "mfma", "achieved": flops / launch_s / 1e12,
+                     "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s", "frac": flops / launch_s / PEAK_FP64_MFMA,
+                     "traffic": None, "flops_per_launch": flops, "launch_ms": launch_s * 1e3},
+        "status_ok": ok,
+    }
+    if not args.no_cpu:
+        import oracle
+        threads = host_cpu()[1]
+        sample = list(range(min(chains, 128)))
+        host = [np.ascontiguousarray(sls[c].cpu().numpy()) for c in sample]
+        print(f"[bench] cpu oracle: {len(host)} chains on {threads} threads", file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda h: oracle.greens_complex(h, k), host))
+        dt = time.perf_counter() - c0
+        c1 = time.perf_counter()
+        for h in host[:2]:
+            oracle.greens_complex(h, k)
+        d1 = time.perf_counter() - c1
+        out["cpu_baseline"] = {"value": len(host) / dt, "unit": "chains/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{len(host)} of the chains; {dt:.1f} s wall",
+                               "one_core": {"value": 2 / d1, "sample": f"2 chains on one thread; {d1:.1f} s"}}
         out["cpu_baseline"].update(host_cpu()[0])
     torch.cuda.synchronize()
     ctx.close()

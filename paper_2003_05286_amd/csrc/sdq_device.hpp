@@ -396,7 +396,7 @@ __device__ __forceinline__ bool all_finite(const Lane& L, const RM<NT, P>& A) {
 // are stored as unit vectors with s_c = c.  One barrier per step; ends with
 // a barrier.
 template <int NT, int P, bool ELDS>
-__device__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>& S) {
+__device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, Smem<NT, P, ELDS>& S) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
@@ -693,7 +693,7 @@ __device__ __forceinline__ void apply_reflector(const Lane& L, double tau, const
 // vectors e_c (c < j) that H_j leaves as they are, so a wave whose columns
 // all lie left of j skips it.
 template <int NT, int P, bool ELDS>
-__device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& X) {
+__device__ __forceinline__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& X) {
   set_identity<NT, P>(L, X);
   // rightmost column this wave holds
   const int cmax = 16 * (L.w + P * (Geo<NT, P>::CT - 1)) + 15;
@@ -714,7 +714,7 @@ __device__ void form_q(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, R
 // Y <- Q^T Y = H_{n-1} ... H_0 Y.  Inside a tile the next reflector is read
 // from LDS while the current one is applied.
 template <int NT, int P, bool ELDS>
-__device__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
+__device__ __forceinline__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
   static_for<NT>([&](auto tjc) {
     constexpr int TJ = decltype(tjc)::value;
     const int jend = 16 * TJ + 16 < n ? 16 * TJ + 16 : n;
@@ -739,7 +739,7 @@ __device__ void apply_qt(const Lane& L, const int n, const Smem<NT, P, ELDS>& S,
 
 // Y <- R^{-1} Y (R in pivot order: R[i][j] = S.R[perm[j]*LDR + i], i <= j)
 template <int NT, int P, bool ELDS>
-__device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
+__device__ __forceinline__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& S, RM<NT, P>& Y) {
   using G = Geo<NT, P>;
   static_for<NT>([&](auto kc) {
     constexpr int TJ = NT - 1 - decltype(kc)::value;
@@ -786,7 +786,7 @@ __device__ void back_subst(const Lane& L, const int n, const Smem<NT, P, ELDS>& 
 // pivot order: A^{-1} Y [S.perm[s]][c] = Y[s][c].  A is destroyed.  A
 // singular A leaves non-finite entries in Y.
 template <int NT, int P, bool ELDS>
-__device__ void ge_solve(const Lane& L, const int n, RM<NT, P>& A, RM<NT, P>& Y, Smem<NT, P, ELDS>& S) {
+__device__ __forceinline__ void ge_solve(const Lane& L, const int n, RM<NT, P>& A, RM<NT, P>& Y, Smem<NT, P, ELDS>& S) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   int ps[CT];  // -1: live, not yet chosen; else the step (padding: own index)
@@ -924,7 +924,7 @@ __device__ __forceinline__ double refl_sign(const Lane& L, const int n, const Sm
 // parity of the pivot permutation (inversions of S.perm) as +-1.
 // Ends with a barrier.
 template <int NT, int P, bool ELDS>
-__device__ double perm_sign(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
+__device__ __forceinline__ double perm_sign(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
   using G = Geo<NT, P>;
   int inv = 0;
   for (int i = L.t; i < n; i += G::THREADS) {
@@ -952,7 +952,7 @@ __device__ double perm_sign(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
 // U, T: register matrices (padding: identity); D: S.dcur.  Returns Z with
 // G[S.perm[s]][c] = Z[s][c] (caller writes it out), and log|det|, sign.
 template <int NT, int P, bool ELDS, bool LOH = true>
-__device__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, const RM<NT, P>& U,
+__device__ __forceinline__ void inv_one_plus(const Lane& L, const int n, Smem<NT, P, ELDS>& S, const RM<NT, P>& U,
                              const RM<NT, P>& T, double sgn_u, RM<NT, P>& Z, double* logdet,
                              double* sign) {
   constexpr bool loh = LOH;
@@ -1170,7 +1170,7 @@ __device__ __forceinline__ void store_stage(const Lane& L, const int n, const Sm
 // previous U) times that of the ordering permutation, which is returned in
 // *psign.  Returns 0, or 1 without convergence.
 template <int NT, int P>
-__device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT, P>& W, RM<NT, P>& T,
+__device__ __forceinline__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT, P>& W, RM<NT, P>& T,
                         double* psign) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
@@ -1310,7 +1310,7 @@ __device__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, true>& S, RM<NT,
 // the working matrix is parked in LDS), which frees one register matrix.
 struct NoT {};
 template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false>
-__device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
+__device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
                           const int jpair, double* tscr = nullptr) {
   static_assert(!(TG && SVD), "the SVD stabilizer keeps T in registers");
   using G = Geo<NT, P>;
@@ -1494,7 +1494,7 @@ __device__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
 
 // Equal-time G, log|det| and sign from the final forward stage (Sec. 5.1).
 template <int NT, int P, bool ELDS>
-__device__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
+__device__ __forceinline__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I) {
   using G = Geo<NT, P>;
   const int n = I.n;
   const double* F = I.fin;
@@ -1581,7 +1581,7 @@ __device__ __forceinline__ void load_rm_staged(const Lane& L, const Smem<NT, P, 
 }
 
 template <int NT, int P, bool ELDS, bool DENSE = false>
-__device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+__device__ __forceinline__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                               const int ilo, const int ihi, const int32_t* __restrict__ l_list,
                               RM<NT, P>& Gm);
 
@@ -1597,7 +1597,7 @@ __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I
 // Then, for requested l inside the block, G(tau_l, 0) = B_l ... G(tau_j, 0)
 // (Sec. 6, propagation form), never across more than k-1 slices.
 template <int NT, int P, bool ELDS, bool DENSE = false>
-__device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+__device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                            const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
@@ -1726,7 +1726,7 @@ __device__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, c
 // (Sec. 6, propagation form).  DENSE: B_q is the n x n row-major matrix at
 // I.field + (q - 1) n^2, staged through LDS (or read from HBM without it).
 template <int NT, int P, bool ELDS, bool DENSE>
-__device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+__device__ __forceinline__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                               const int ilo, const int ihi, const int32_t* __restrict__ l_list,
                               RM<NT, P>& Gm) {
   using G = Geo<NT, P>;
@@ -1792,7 +1792,7 @@ __device__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I
 // item is the only reader of cka[j]).  Then the outputs of the pair as in
 // the split scheme.
 template <int NT, int P, bool ELDS>
-__device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
+__device__ __forceinline__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j,
                                  const int ilo, const int ihi, const int32_t* __restrict__ l_list) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
@@ -1875,7 +1875,7 @@ __device__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS>& S, const Inst
 // T = t U2^T, then Loh's equal-time inversion; written to S.R row-major
 // ([row][col], padding as identity), ends with a barrier.
 template <int NT, int P, bool ELDS>
-__device__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+__device__ __forceinline__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, nb = I.nb;
@@ -1982,7 +1982,7 @@ __device__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S, const Inst& I,
 // stage pair (block_start_g), then G_{l+1} = B_l G_l B_l^{-1} and
 //   grad[l-1][i] = alpha (1 - G_l)_ii.
 template <int NT, int P, bool ELDS>
-__device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
+__device__ __forceinline__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int j) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;
   const int n = I.n, m = I.m, k = I.k;
@@ -2066,7 +2066,7 @@ __device__ void pair_grad(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, co
 // `staged` (ELDS), else read from global memory.  Starts with a barrier (the
 // caller's staging of vv and S.E, and any earlier reader of S.R).
 template <int NT, int P, bool ELDS>
-__device__ void wrap_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const double* vv,
+__device__ __forceinline__ void wrap_local(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const double* vv,
                            const RM<NT, P>& Einv, bool staged, RM<NT, P>& Gx) {
   using G = Geo<NT, P>;
   constexpr int CT = G::CT;

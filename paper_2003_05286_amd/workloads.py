@@ -177,6 +177,26 @@ def complex_batch(count: int, n: int, seed: int = BASE_SEED + 8, decades: float 
     return X
 
 
+def complex_hubbard(L: int, beta: float, chains: int, phase_amp: float = 0.3, U: float = 4.0,
+                    dtau: float = 0.1, seed: int = BASE_SEED + 10):
+    """Inputs of chains of complex slices B_l = E diag(exp(lambda s_l + i phi_l)):
+    a Hubbard chain whose auxiliary field carries a seeded phase phi ~
+    U(-phase_amp, phase_amp) per site and slice (the paper's complex model of
+    App. B has parameters the paper does not give; these slices have its
+    shape: complex, dense after the product with E).  Returns (E, lambda,
+    s [chains, m, n], phi [chains, m, n]); the slices themselves are formed by
+    the caller (on the device for the benchmark)."""
+    m = int(round(beta / dtau))
+    n = L * L
+    e, _ = expk_for(L, dtau)
+    lam = hirsch_lambda(U, dtau)
+    s, phi = [], []
+    for rng in rng_streams(seed, chains):
+        s.append(ising_field(rng, m, n))
+        phi.append(rng.uniform(-phase_amp, phase_amp, (m, n)))
+    return e, lam, np.stack(s), np.stack(phi)
+
+
 def workload(name: str, scale: float = 1.0) -> Workload:
     """Named workloads.  `scale` < 1 shrinks the batch (never the shapes)."""
     def nb(x):
