@@ -40,7 +40,11 @@
  * concurrently: each class of the one-workgroup kernels on a stream of its
  * own forked from the context's stream, the gang classes on the context's
  * stream; all of them are joined back into the context's stream before the
- * call's work ends, so callers see ordinary stream order.
+ * call's work ends, so callers see ordinary stream order.  Every wait of a
+ * gang is bounded: its members must all be running within 60 s of the
+ * first one (other classes of the call may hold the CUs until they finish)
+ * and every wait inside a factorization ends after 4 s; a gang that gives
+ * up reports SDQ_ERANGE for its chains instead of hanging.
  */
 #ifndef SDQ_H
 #define SDQ_H

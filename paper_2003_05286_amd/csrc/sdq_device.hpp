@@ -323,24 +323,41 @@ __device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT, P>& B,
 }
 
 // load a row-major n x n global matrix (or its transpose) into registers,
-// zero padded; `src == nullptr` loads the identity
+// zero padded; `src == nullptr` loads the identity.  Every entry is loaded
+// unconditionally (padding positions read a clamped in-range address and
+// are zeroed afterwards): a load inside a per-element branch makes the
+// compiler wait for it before the next one, one memory latency per entry.
 template <int NT, int P>
 __device__ __forceinline__ void load_rm(const Lane& L, RM<NT, P>& A, const double* src, int n, bool trans) {
+  if (src == nullptr) {
+#pragma unroll
+    for (int c = 0; c < Geo<NT, P>::CT; ++c)
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A.v[c][ti][r] = row_of(L, ti, r) == col_of<NT, P>(L, c) ? 1.0 : 0.0;
+    return;
+  }
+  const auto* g = gmem(src);
 #pragma unroll
   for (int c = 0; c < Geo<NT, P>::CT; ++c) {
-    const int col = col_of<NT, P>(L, c);
+    const int cc = min(col_of<NT, P>(L, c), n - 1);
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        double x;
-        if (src == nullptr) x = (row == col) ? 1.0 : 0.0;
-        else if (row < n && col < n && tile_ok<NT, P>(L, c))
-          x = trans ? gmem(src)[col * n + row] : gmem(src)[row * n + col];
-        else x = 0.0;
-        A.v[c][ti][r] = x;
+        const int rr = min(row_of(L, ti, r), n - 1);
+        A.v[c][ti][r] = trans ? g[cc * n + rr] : g[rr * n + cc];
       }
+  }
+#pragma unroll
+  for (int c = 0; c < Geo<NT, P>::CT; ++c) {
+    const bool cok = tile_ok<NT, P>(L, c) && col_of<NT, P>(L, c) < n;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (!(cok && row_of(L, ti, r) < n)) A.v[c][ti][r] = 0.0;
   }
 }
 
@@ -1546,19 +1563,63 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
   }
 }
 
-// stage the n x n row-major global matrix src (identity if null) into S.E,
-// [row][col], zero padded; all threads, no barrier
+// stage the n x n row-major global matrix src (identity if null) into the
+// LDS matrix dst ([NP][LDR]: S.E or S.R), [row][col], zero padded; all
+// threads, no barrier.  The loads go out in batches of eight per thread
+// before any is stored (clamped in-range addresses, padding zeroed after
+// the load), so a batch costs one memory latency instead of eight.
+template <int NT, int P>
+__device__ __forceinline__ void stage_to(const Lane& L, double* dst, const double* src, int n) {
+  using G = Geo<NT, P>;
+  {
+    constexpr int TOT = G::NP * G::NP, IT = (TOT + G::THREADS - 1) / G::THREADS, CH = 8;
+    if (src == nullptr) {
+      for (int idx = L.t; idx < TOT; idx += G::THREADS) {
+        const int i = idx / G::NP, k = idx - i * G::NP;
+        dst[i * G::LDR + k] = (i == k && i < n) ? 1.0 : 0.0;
+      }
+      return;
+    }
+    const auto* g = gmem(src);
+#pragma unroll
+    for (int b = 0; b < IT; b += CH) {
+      double x[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int idx = L.t + (b + q) * G::THREADS;
+        const int i = idx / G::NP, k = idx - i * G::NP;
+        x[q] = (b + q < IT) ? g[min(i, n - 1) * n + min(k, n - 1)] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int idx = L.t + (b + q) * G::THREADS;
+        const int i = idx / G::NP, k = idx - i * G::NP;
+        if (b + q < IT && idx < TOT) dst[i * G::LDR + k] = (i < n && k < n) ? x[q] : 0.0;
+      }
+    }
+  }
+}
 template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void stage_mat(const Lane& L, Smem<NT, P, ELDS>& S, const double* src,
                                           int n) {
+  if constexpr (ELDS) stage_to<NT, P>(L, S.E, src, n);
+}
+
+// register matrix from an LDS matrix ([NP][LDR]): B[row][col] = a[row][col]
+// or its transpose
+template <int NT, int P>
+__device__ __forceinline__ void load_lds_rm(const Lane& L, const double* a, RM<NT, P>& B, bool trans) {
   using G = Geo<NT, P>;
-  if constexpr (ELDS) {
-    for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
-      const int i = idx / G::NP, k = idx - i * G::NP;
-      double x = 0.0;
-      if (i < n && k < n) x = src ? gmem(src)[i * n + k] : (i == k ? 1.0 : 0.0);
-      S.E[i * G::LDR + k] = x;
-    }
+#pragma unroll
+  for (int c = 0; c < G::CT; ++c) {
+    const int col = col_of<NT, P>(L, c);
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row_of(L, ti, r);
+        B.v[c][ti][r] = tile_ok<NT, P>(L, c) ? (trans ? a[col * G::LDR + row] : a[row * G::LDR + col]) : 0.0;
+      }
   }
 }
 
@@ -1612,23 +1673,29 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
   const double* T2 = A ? A + (size_t)n * n : nullptr;
   const double* D2 = A ? A + 2 * (size_t)n * n : nullptr;
 
-  RM<NT, P> B, P1, P2;
+  // D1 and D2 in LDS (their entries are read per row and per column below)
+  for (int t = L.t; t < G::NP; t += G::THREADS) {
+    S.dcur[t] = (D1 && t < n) ? gmem(D1)[t] : 1.0;
+    S.dnew[t] = (D2 && t < n) ? gmem(D2)[t] : 1.0;
+  }
+  RM<NT, P> B, P1, P2, Y;
   if constexpr (ELDS) {
-    // operands staged through LDS with coalesced loads
+    // operands staged through LDS with coalesced loads, two matrices per
+    // round (S.R is free until the solve parks its factor there)
     __syncthreads();
-    stage_mat<NT, P, ELDS>(L, S, T2, n);
+    stage_to<NT, P>(L, S.R, T2, n);
+    stage_to<NT, P>(L, S.E, T1, n);
     __syncthreads();
-    load_rm_staged<NT, P, ELDS>(L, S, B, true);  // T2^T
-    __syncthreads();
-    stage_mat<NT, P, ELDS>(L, S, T1, n);
-    __syncthreads();
+    load_lds_rm<NT, P>(L, S.R, B, true);  // T2^T
     gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, B,
                    P2);
+    load_lds_rm<NT, P>(L, S.E, Y, false);  // T1 (right-hand sides)
     __syncthreads();
-    stage_mat<NT, P, ELDS>(L, S, U1, n);
-    load_rm<NT, P>(L, B, U2, n, false);
+    stage_to<NT, P>(L, S.R, U1, n);
+    stage_to<NT, P>(L, S.E, U2, n);  // stays in S.E for the final product
     __syncthreads();
-    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[kk * G::LDR + i]; }, B,
+    load_lds_rm<NT, P>(L, S.E, B, false);  // U2
+    gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[kk * G::LDR + i]; }, B,
                    P1);
   } else {
     load_rm<NT, P>(L, B, U2, n, false);
@@ -1645,62 +1712,54 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
                      return T1 ? gmem(T1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
                    },
                    B, P2);
+    __syncthreads();  // S.dcur, S.dnew written
   }
-  // Mid (Y = D_Lp^{-1} T1 is rebuilt from HBM after the QR, so that it is
-  // not live in registers during it)
-  double d2c[CT];
-#pragma unroll
-  for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT, P>(L, c);
-    d2c[c] = (D2 && col < n) ? gmem(D2)[col] : 1.0;
-  }
+  // Mid = D_Lm (U1^T U2) D_Rp^{-1} + D_Lp^{-1} (T1 T2^T) D_Rm
 #pragma unroll
   for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row_of(L, ti, r);
-      const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
-      const double lm = 1.0 / (d1 > 1.0 ? d1 : 1.0);   // D_Lm
-      const double lpi = d1 < 1.0 ? d1 : 1.0;           // D_Lp^{-1}
+      const double d1 = S.dcur[row_of(L, ti, r)];
+      const double lm = 1.0 / (d1 > 1.0 ? d1 : 1.0);  // D_Lm
+      const double lpi = d1 < 1.0 ? d1 : 1.0;          // D_Lp^{-1}
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const double d2 = d2c[c];
+        const double d2 = S.dnew[col_of<NT, P>(L, c) < G::NP ? col_of<NT, P>(L, c) : 0];
         const double rpi = 1.0 / (d2 > 1.0 ? d2 : 1.0);  // D_Rp^{-1}
         const double rm = d2 < 1.0 ? d2 : 1.0;            // D_Rm
         P1.v[c][ti][r] = lm * P1.v[c][ti][r] * rpi + lpi * P2.v[c][ti][r] * rm;
       }
     }
-  // Y = D_Lp^{-1} T1, then Y <- Mid^{-1} Y by Gaussian elimination with
-  // column pivoting (any backward-stable solve of the middle matrix serves,
-  // Sec. 6.1; the rows of the result come out in pivot order, S.perm)
-  RM<NT, P> Y;
-  load_rm<NT, P>(L, Y, T1, n, false);
+  // Y = D_Lp^{-1} T1 (without LDS staging it is loaded here, after the
+  // products, so that it is not live in registers during them)
+  if constexpr (!ELDS) load_rm<NT, P>(L, Y, T1, n, false);
 #pragma unroll
   for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row_of(L, ti, r);
-      const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
+      const double d1 = S.dcur[row_of(L, ti, r)];
       const double lpi = d1 < 1.0 ? d1 : 1.0;  // D_Lp^{-1}
 #pragma unroll
       for (int c = 0; c < CT; ++c) Y.v[c][ti][r] *= lpi;
     }
+  // Y <- Mid^{-1} Y by Gaussian elimination with column pivoting (any
+  // backward-stable solve of the middle matrix serves, Sec. 6.1); the rows
+  // of the result come out in pivot order, S.perm
   __syncthreads();
   ge_solve<NT, P, ELDS>(L, n, P1, Y, S);
-  // G = U2 D_Rp^{-1} P Z :  A(i, s) = gmem(U2)[i][perm s] / max(gmem(D2)[perm s], 1)
+  // G = U2 D_Rp^{-1} P Z: row s of Z scaled by 1 / max(D2[perm s], 1), then
+  // the product with the columns of U2 gathered by perm
+#pragma unroll
+  for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double d2 = S.dnew[S.perm[row_of(L, ti, r)]];
+      const double rpi = 1.0 / (d2 > 1.0 ? d2 : 1.0);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) Y.v[c][ti][r] *= rpi;
+    }
   RM<NT, P> Gm;
   if constexpr (ELDS) {
-    // stage U2 D_Rp^{-1} (columns scaled), then gather its columns by perm
-    for (int idx = L.t; idx < G::NP * G::NP; idx += G::THREADS) {
-      const int i = idx / G::NP, kk = idx - i * G::NP;
-      double x = 0.0;
-      if (i < n && kk < n) {
-        const double d2 = D2 ? gmem(D2)[kk] : 1.0;
-        x = (U2 ? gmem(U2)[i * n + kk] : (i == kk ? 1.0 : 0.0)) / (d2 > 1.0 ? d2 : 1.0);
-      }
-      S.E[i * G::LDR + kk] = x;
-    }
-    __syncthreads();
     gemm_rb<NT, P>(L,
                    [&](int, int, int, int i, int s) -> double {
                      return s < n ? S.E[i * G::LDR + S.perm[s]] : 0.0;
@@ -1711,9 +1770,7 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
                    [&](int, int, int, int i, int s) -> double {
                      if (i >= n || s >= n) return 0.0;
                      const int p = S.perm[s];
-                     const double d2 = D2 ? gmem(D2)[p] : 1.0;
-                     const double u = U2 ? gmem(U2)[i * n + p] : (i == p ? 1.0 : 0.0);
-                     return u / (d2 > 1.0 ? d2 : 1.0);
+                     return U2 ? gmem(U2)[i * n + p] : (i == p ? 1.0 : 0.0);
                    },
                    Y, Gm);
   }

@@ -51,6 +51,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = kGangThreads / 64;  // 16
 constexpr int kPairs = 5;                  // MFMA output tiles per wave in a slab product
 constexpr unsigned long long kSpinTicks = 400000000ull;  // 4 s of the 100 MHz wall clock
+// The first rendezvous of a gang waits for all of its members to start.
+// Other kernels of the same call (size classes on side streams) may hold
+// the CUs a member needs until they finish, so this one wait is allowed
+// far longer (60 s) than the waits inside a factorization, which only ever
+// wait for members that are already running.
+constexpr unsigned long long kAssembleTicks = 6000000000ull;
 
 struct GLds {
   double S[kGangSlab];       // column slab, [col][row]
@@ -209,6 +215,36 @@ __device__ bool gang_sync(GC& c) {
   const bool good = L.ok != 0;
   c.ok = c.ok && good;
   return good;
+}
+
+// Start of a gang's work: every member counts itself in (word 2 of the
+// barrier record) and waits until all G have, or until another member gave
+// up, or kAssembleTicks.  After it every member is resident, so the bounded
+// waits of gang_sync and wait_keys measure work, not scheduling.
+__device__ void gang_assemble(GC& c) {
+  if (c.t == 0) {
+    __hip_atomic_fetch_add(gmem(&c.bar[2]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    const unsigned long long t0 = wall_clock64();
+    for (;;) {
+      if (__hip_atomic_load(gmem(&c.bar[2]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)c.geo.G)
+        break;
+      if (__hip_atomic_load(gmem(&c.bar[1]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        good = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > kAssembleTicks) {
+        __hip_atomic_exchange(gmem(&c.bar[1]), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    L.ok = good;
+  }
+  __syncthreads();
+  c.ok = c.ok && L.ok != 0;
+  __syncthreads();
 }
 
 // Data exchanged between members inside a QR step goes through device-scope
@@ -1201,6 +1237,7 @@ __global__ __launch_bounds__(kGangThreads, 1) void k_gang_sweep(const Inst* __re
                                                                  const SweepItem* __restrict__ items,
                                                                  int count, GangArgs a) {
   GC c = gang_ctx(a);
+  if (c.gang < count) gang_assemble(c);
   for (int it = c.gang; it < count; it += a.ngangs) {
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
@@ -1215,6 +1252,7 @@ __global__ __launch_bounds__(kGangThreads, 1) void k_gang_pair(const Inst* __res
                                                                 int count, const int32_t* __restrict__ l_list,
                                                                 GangArgs a) {
   GC c = gang_ctx(a);
+  if (c.gang < count) gang_assemble(c);
   for (int it = c.gang; it < count; it += a.ngangs) {
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
@@ -1230,6 +1268,7 @@ __global__ __launch_bounds__(kGangThreads, 1) void k_gang_udt(int n, int count, 
                                                                double* d, double* t, GangArgs a) {
   GC c = gang_ctx(a);
   c.n = n;
+  if (c.gang < count) gang_assemble(c);
   for (int it = c.gang; it < count; it += a.ngangs) {
     const int64_t off = (int64_t)it * n * n;
     udt_gang<RL>(c, w + off, u + off, d + (int64_t)it * n, t + off);

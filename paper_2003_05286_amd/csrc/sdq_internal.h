@@ -237,7 +237,7 @@ constexpr int kGangMaxN = 1024;
 constexpr int kGangThreads = 1024;
 constexpr int kGangSlab = 16640;  // doubles of the LDS column slab
 constexpr int kGangMaxW = 128;
-constexpr int kGangBarWords = 32;  // uint32 words per gang (counter, abort flag)
+constexpr int kGangBarWords = 32;  // uint32 words per gang (barrier counter, abort flag, arrivals)
 
 struct GangGeom {
   int npad;  // 16 * ceil(n / 16)
