@@ -372,6 +372,52 @@ __device__ __forceinline__ void cgemm(AF A, XF X, cd4 (&cr)[4], cd4 (&ci)[4]) {
   }
 }
 
+// C = B X as cgemm, with B the row-major n x n complex matrix at Bq in device
+// memory.  The sixteen B entries of a k tile are loaded at once, from
+// clamped in-range addresses (entries outside n x n zeroed after the load),
+// and the next tile's loads are in flight while the current tile's MFMAs
+// run: a load behind a per-entry branch would be waited for before the
+// next one.
+template <class XF>
+__device__ __forceinline__ void cgemm_hbm(const cplx* Bq, int n, XF X, cd4 (&cr)[4], cd4 (&ci)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  const auto* gB = (const __attribute__((address_space(1))) double*)Bq;
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti) cr[ti] = ci[ti] = cd4{0.0, 0.0, 0.0, 0.0};
+  cplx a[2][4][4];  // [buffer][r][ti]
+  auto load = [&](int tk, cplx (&dst)[4][4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const int i = 16 * ti + cl, kk = 16 * tk + g + 4 * r;
+        const size_t off = 2 * ((size_t)min(i, n - 1) * n + min(kk, n - 1));
+        dst[r][ti] = cplx{gB[off], gB[off + 1]};
+      }
+  };
+  load(0, a[0]);
+#pragma unroll
+  for (int tk = 0; tk < 4; ++tk) {
+    if (tk + 1 < 4) load(tk + 1, a[(tk + 1) & 1]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kk = 16 * tk + g + 4 * r;
+      const cplx b = X(kk, 16 * w + cl);
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti) {
+        const bool ok = 16 * ti + cl < n && kk < n;
+        const cplx av = a[tk & 1][r][ti];
+        const double ax = ok ? av.x : 0.0, ay = ok ? av.y : 0.0;
+        cr[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, b.x, cr[ti], 0, 0, 0);
+        cr[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, b.y, cr[ti], 0, 0, 0);
+        ci[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, b.y, ci[ti], 0, 0, 0);
+        ci[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, b.x, ci[ti], 0, 0, 0);
+      }
+    }
+  }
+}
+
 // write the accumulators of cgemm to an LDS matrix, each column scaled by
 // cs(c) and each row by rs(i)
 template <class CS, class RS>
@@ -411,8 +457,7 @@ __global__ __launch_bounds__(kCThreads) void k_greens_complex(const CChain* __re
       for (int q = q0; q <= q1; ++q) {
         const cplx* Bq = Bs + (size_t)(q - 1) * n * n;
         cd4 cr[4], ci[4];
-        cgemm([&](int i, int kk) -> cplx { return (i < n && kk < n) ? Bq[(size_t)i * n + kk] : cplx{0.0, 0.0}; },
-              [&](int kk, int c) -> cplx { return S.a[kk * kCLD + c]; }, cr, ci);
+        cgemm_hbm(Bq, n, [&](int kk, int c) -> cplx { return S.a[kk * kCLD + c]; }, cr, ci);
         __syncthreads();
         const bool last = q == q1;
         cstore(S.a, cr, ci, [&](int c) { return last ? S.d[c] : 1.0; }, [](int) { return 1.0; });

@@ -322,6 +322,54 @@ __device__ __forceinline__ void gemm_rb(const Lane& L, AF A, const RM<NT, P>& B,
       for (int r = 0; r < 4; ++r) C.v[c][ti][r] = acc[c][ti][r];
 }
 
+// C = M B (trans: M^T B) for the row-major n x n matrix M in device memory,
+// zero padded; a null M is the identity.  The loads are unconditional
+// (clamped in-range addresses, padding selected away afterwards): a load
+// behind a per-entry branch would be waited for before the next one.
+template <int NT, int P>
+__device__ __forceinline__ void gemm_gm(const Lane& L, const double* M, int n, bool trans, const RM<NT, P>& B,
+                                        RM<NT, P>& C) {
+  if (M == nullptr) {
+#pragma unroll
+    for (int c = 0; c < Geo<NT, P>::CT; ++c)
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C.v[c][ti][r] = row_of(L, ti, r) < n ? B.v[c][ti][r] : 0.0;
+    return;
+  }
+  const auto* g = gmem(M);
+  gemm_rb<NT, P>(L,
+                 [&](int, int, int, int i, int kk) -> double {
+                   const int a = min(i, n - 1), b = min(kk, n - 1);
+                   const double v = trans ? g[(size_t)b * n + a] : g[(size_t)a * n + b];
+                   return (i < n && kk < n) ? v : 0.0;
+                 },
+                 B, C);
+}
+// C = M[:, perm] B: the columns of M gathered by S-resident pivot order
+// (perm[s] for s < n), same conventions as gemm_gm
+template <int NT, int P>
+__device__ __forceinline__ void gemm_gm_perm(const Lane& L, const double* M, int n, const int* perm,
+                                             const RM<NT, P>& B, RM<NT, P>& C) {
+  if (M == nullptr) {
+    gemm_rb<NT, P>(L,
+                   [&](int, int, int, int i, int s) -> double {
+                     return (i < n && s < n && perm[s] == i) ? 1.0 : 0.0;
+                   },
+                   B, C);
+    return;
+  }
+  const auto* g = gmem(M);
+  gemm_rb<NT, P>(L,
+                 [&](int, int, int, int i, int s) -> double {
+                   const int p = perm[min(s, n - 1)];
+                   const double v = g[(size_t)min(i, n - 1) * n + p];
+                   return (i < n && s < n) ? v : 0.0;
+                 },
+                 B, C);
+}
+
 // load a row-major n x n global matrix (or its transpose) into registers,
 // zero padded; `src == nullptr` loads the identity.  Every entry is loaded
 // unconditionally (padding positions read a clamped in-range address and
@@ -1392,7 +1440,7 @@ __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, c
         for (int e = 0; e < PER; ++e) {
           const int idx = L.t + e * G::THREADS;
           const int i = idx / G::NP, kk = idx - i * G::NP;
-          nxt[e] = (idx < G::NP * G::NP && i < n && kk < n) ? gmem(Bq)[(size_t)i * n + kk] : 0.0;
+          nxt[e] = gmem(Bq)[(size_t)min(i, n - 1) * n + min(kk, n - 1)];
         }
       };
       // forward: W <- B_q W for q = q0..q1; backward: W <- B_q^T W, q = q1..q0
@@ -1406,7 +1454,8 @@ __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, c
 #pragma unroll
           for (int e = 0; e < PER; ++e) {
             const int idx = L.t + e * G::THREADS;
-            if (idx < G::NP * G::NP) S.E[(idx / G::NP) * G::LDR + idx % G::NP] = nxt[e];
+            const int i = idx / G::NP, kk = idx - i * G::NP;
+            if (idx < G::NP * G::NP) S.E[i * G::LDR + kk] = (i < n && kk < n) ? nxt[e] : 0.0;
           }
           __syncthreads();
           if (t + 1 < cnt) fetch(q + qs);
@@ -1415,12 +1464,7 @@ __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, c
           else
             gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
         } else {
-          gemm_rb<NT, P>(L,
-                         [&](int, int, int, int i, int kk) -> double {
-                           if (i >= n || kk >= n) return 0.0;
-                           return adj ? gmem(Bq)[(size_t)kk * n + i] : gmem(Bq)[(size_t)i * n + kk];
-                         },
-                         W, W);
+          gemm_gm<NT, P>(L, Bq, n, adj, W, W);
         }
       }
     } else {
@@ -1699,19 +1743,9 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
                    P1);
   } else {
     load_rm<NT, P>(L, B, U2, n, false);
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int kk) -> double {
-                     if (i >= n || kk >= n) return 0.0;
-                     return U1 ? gmem(U1)[kk * n + i] : (i == kk ? 1.0 : 0.0);
-                   },
-                   B, P1);
+    gemm_gm<NT, P>(L, U1, n, true, B, P1);
     load_rm<NT, P>(L, B, T2, n, true);
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int kk) -> double {
-                     if (i >= n || kk >= n) return 0.0;
-                     return T1 ? gmem(T1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
-                   },
-                   B, P2);
+    gemm_gm<NT, P>(L, T1, n, false, B, P2);
     __syncthreads();  // S.dcur, S.dnew written
   }
   // Mid = D_Lm (U1^T U2) D_Rp^{-1} + D_Lp^{-1} (T1 T2^T) D_Rm
@@ -1766,13 +1800,7 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
                    },
                    Y, Gm);
   } else {
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int s) -> double {
-                     if (i >= n || s >= n) return 0.0;
-                     const int p = S.perm[s];
-                     return U2 ? gmem(U2)[i * n + p] : (i == p ? 1.0 : 0.0);
-                   },
-                   Y, Gm);
+    gemm_gm_perm<NT, P>(L, U2, n, S.perm, Y, Gm);
   }
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
   tdisp_outputs<NT, P, ELDS, DENSE>(L, S, I, j, ilo, ihi, l_list, Gm);
@@ -1802,11 +1830,7 @@ __device__ __forceinline__ void tdisp_outputs(const Lane& L, Smem<NT, P, ELDS>& 
           gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, Gm,
                          Gm);
         } else {
-          gemm_rb<NT, P>(L,
-                         [&](int, int, int, int i, int kk) -> double {
-                           return (i < n && kk < n) ? gmem(Bq)[i * n + kk] : 0.0;
-                         },
-                         Gm, Gm);
+          gemm_gm<NT, P>(L, Bq, n, false, Gm, Gm);
         }
       }
       lc = l;
@@ -1879,19 +1903,9 @@ __device__ __forceinline__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS
   }
   // P1 = X_L X_R^{-1},  P2 = U_L^T U_R
   load_rm<NT, P>(L, B, XRi, n, false);
-  gemm_rb<NT, P>(L,
-                 [&](int, int, int, int i, int kk) -> double {
-                   if (i >= n || kk >= n) return 0.0;
-                   return XL ? gmem(XL)[i * n + kk] : (i == kk ? 1.0 : 0.0);
-                 },
-                 B, P1);
+  gemm_gm<NT, P>(L, XL, n, false, B, P1);
   load_rm<NT, P>(L, B, UR, n, false);
-  gemm_rb<NT, P>(L,
-                 [&](int, int, int, int i, int kk) -> double {
-                   if (i >= n || kk >= n) return 0.0;
-                   return UL ? gmem(UL)[kk * n + i] : (i == kk ? 1.0 : 0.0);
-                 },
-                 B, P2);
+  gemm_gm<NT, P>(L, UL, n, true, B, P2);
   double drc[CT];
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
@@ -1916,13 +1930,7 @@ __device__ __forceinline__ void pair_tdisp_plain(const Lane& L, Smem<NT, P, ELDS
   back_subst<NT, P, ELDS>(L, n, S, Y);
   // G = X_R^{-1} P Z:  A(i, s) = X_R^{-1}[i][perm s]
   RM<NT, P> Gm;
-  gemm_rb<NT, P>(L,
-                 [&](int, int, int, int i, int s) -> double {
-                   if (i >= n || s >= n) return 0.0;
-                   const int p = S.perm[s];
-                   return XRi ? gmem(XRi)[i * n + p] : (i == p ? 1.0 : 0.0);
-                 },
-                 Y, Gm);
+  gemm_gm_perm<NT, P>(L, XRi, n, S.perm, Y, Gm);
   if (!all_finite<NT, P>(L, Gm) && L.l == 0 && I.status) atomicOr(I.status, kStatusRange);
   tdisp_outputs<NT, P, ELDS>(L, S, I, j, ilo, ihi, l_list, Gm);
 }
@@ -1959,25 +1967,22 @@ __device__ __forceinline__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S
                    Mm);
   } else {
     load_rm<NT, P>(L, B, T2, n, true);
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int kk) -> double {
-                     if (i >= n || kk >= n) return 0.0;
-                     return T1 ? gmem(T1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
-                   },
-                   B, Mm);
+    gemm_gm<NT, P>(L, T1, n, false, B, Mm);
   }
+  // D1 (in S.tau) and D2 (in S.dcur), both free until the QR below
+  __syncthreads();
+  for (int t = L.t; t < G::NP; t += G::THREADS) {
+    S.tau[t] = (D1 && t < n) ? gmem(D1)[t] : 1.0;
+    S.dcur[t] = (D2 && t < n) ? gmem(D2)[t] : 1.0;
+  }
+  __syncthreads();
 #pragma unroll
   for (int c = 0; c < CT; ++c) {
-    const int col = col_of<NT, P>(L, c);
-    const double d2 = (D2 && col < n) ? gmem(D2)[col] : 1.0;
+    const double d2 = S.dcur[col_of<NT, P>(L, c) < G::NP ? col_of<NT, P>(L, c) : 0];
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row_of(L, ti, r);
-        const double d1 = (D1 && row < n) ? gmem(D1)[row] : 1.0;
-        Mm.v[c][ti][r] *= d1 * d2;
-      }
+      for (int r = 0; r < 4; ++r) Mm.v[c][ti][r] *= S.tau[row_of(L, ti, r)] * d2;
   }
   __syncthreads();
   cpqr<NT, P, ELDS>(L, n, Mm, S);
@@ -2006,12 +2011,7 @@ __device__ __forceinline__ void block_start_g(const Lane L, Smem<NT, P, ELDS>& S
     gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, u,
                    Um);
   } else {
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int kk) -> double {
-                     if (i >= n || kk >= n) return 0.0;
-                     return U1 ? gmem(U1)[i * n + kk] : (i == kk ? 1.0 : 0.0);
-                   },
-                   u, Um);
+    gemm_gm<NT, P>(L, U1, n, false, u, Um);
   }
   for (int t = L.t; t < G::NP; t += G::THREADS) S.dcur[t] = S.dnew[t];
   RM<NT, P> Z;
@@ -2379,19 +2379,11 @@ __global__ __launch_bounds__(64 * P) void k_similarity(int n, int count, double*
   for (int b = blockIdx.x; b < count; b += gridDim.x) {
     double* M = gmem(mats)[b];
     // X = M right
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int k) -> double {
-                     return (i < n && k < n) ? gmem(M)[(size_t)i * n + k] : 0.0;
-                   },
-                   R, X);
+    gemm_gm<NT, P>(L, M, n, false, R, X);
     // every wave has read all of M before any wave writes it back
     __syncthreads();
     // Y = left X
-    gemm_rb<NT, P>(L,
-                   [&](int, int, int, int i, int k) -> double {
-                     return (i < n && k < n) ? gmem(left)[(size_t)i * n + k] : 0.0;
-                   },
-                   X, Y);
+    gemm_gm<NT, P>(L, left, n, false, X, Y);
     store_rm<NT, P>(L, Y, M, n);
   }
 }

@@ -336,7 +336,10 @@ struct AColMajor {  // A[i][k] = M[k*ld + i], buffer zero padded to ld x ld
     return gmem(M)[(int64_t)(16 * tk + 4 * r + (l >> 4)) * ld + 16 * ti + (l & 15)];
   }
 };
-// A[i][k] = M[i*n + k] * cs(k) (row-major n x n, identity if M is null)
+// A[i][k] = M[i*n + k] * cs(k) (row-major n x n, M not null).  Device
+// memory operands are loaded unconditionally from clamped in-range
+// addresses and the padding is selected away afterwards: a load behind a
+// per-entry branch would be waited for before the next one.
 template <class CS>
 struct ARowMajor {
   const double* M;
@@ -344,20 +347,34 @@ struct ARowMajor {
   CS cs;
   __device__ double operator()(int ti, int tk, int r, int l) const {
     const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
-    if (i >= n || k >= n) return 0.0;
-    const double x = M ? gmem(M)[(int64_t)i * n + k] : (i == k ? 1.0 : 0.0);
-    return x * cs(k);
+    const int kc = min(k, n - 1);
+    const double x = gmem(M)[(int64_t)min(i, n - 1) * n + kc] * cs(kc);
+    return (i < n && k < n) ? x : 0.0;
   }
 };
-// A[i][k] = M[k*n + i] (the transpose of a row-major n x n matrix)
+// A[i][k] = M[k*n + i] (the transpose of a row-major n x n matrix, not null)
 struct ARowMajorT {
   const double* M;
   int n;
   __device__ double operator()(int ti, int tk, int r, int l) const {
     const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
-    if (i >= n || k >= n) return 0.0;
-    return M ? gmem(M)[(int64_t)k * n + i] : (i == k ? 1.0 : 0.0);
+    const double x = gmem(M)[(int64_t)min(k, n - 1) * n + min(i, n - 1)];
+    return (i < n && k < n) ? x : 0.0;
   }
+};
+// A[i][k] = (i == k) cs(k) for i, k < n: the stand-in for a null M
+template <class CS>
+struct AIdent {
+  int n;
+  CS cs;
+  __device__ double operator()(int ti, int tk, int r, int l) const {
+    const int i = 16 * ti + (l & 15), k = 16 * tk + 4 * r + (l >> 4);
+    return (i == k && i < n) ? cs(k) : 0.0;
+  }
+};
+// the LDS vector L.beta as a column or row scale
+struct BetaScale {
+  __device__ double operator()(int k) const { return L.beta[k]; }
 };
 
 // ---- slab loads and stores ---------------------------------------------------
@@ -365,24 +382,57 @@ struct ARowMajorT {
 // from that of the next writer of the slab).
 // S[cc][i] = f(i, gc) for every slab entry (zero outside n x n); row-wise so
 // that consecutive threads take consecutive columns of one row
-template <class F>
-__device__ void slab_fill_rows(GC& c, F f) {
-  const int w = c.geo.w, ldr = c.geo.ldr;
-  for (int idx = c.t; idx < c.geo.npad * w; idx += kGangThreads) {
-    const int i = idx / w, cc = idx - i * w, gc = c.c0 + cc;
-    L.S[cc * ldr + i] = (i < c.n && gc < c.n) ? f(i, gc) : 0.0;
+// f is evaluated at clamped indices (i, gc < n) for every entry, eight per
+// thread at a time before any is stored, so that its loads are in flight
+// together; entries outside n x n are stored as zero.
+template <bool ROWS, class F, class OP>
+__device__ void slab_for_each(GC& c, F f, OP op) {
+  const int w = c.geo.w, np = c.geo.npad, ldr = c.geo.ldr, n = c.n, tot = np * w;
+  constexpr int CH = 8;
+  for (int b = c.t; b < tot; b += CH * kGangThreads) {
+    double x[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int idx = min(b + q * kGangThreads, tot - 1);
+      const int i = ROWS ? idx / w : idx % np, cc = ROWS ? idx - i * w : idx / np;
+      x[q] = f(min(i, n - 1), min(c.c0 + cc, n - 1));
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int idx = b + q * kGangThreads;
+      if (idx >= tot) continue;
+      const int i = ROWS ? idx / w : idx % np, cc = ROWS ? idx - i * w : idx / np;
+      op(L.S[cc * ldr + i], i < n && c.c0 + cc < n, x[q]);
+    }
   }
   __syncthreads();
+}
+struct SetOrZero {
+  __device__ void operator()(double& e, bool in, double x) const { e = in ? x : 0.0; }
+};
+struct AddInside {
+  __device__ void operator()(double& e, bool in, double x) const {
+    if (in) e += x;
+  }
+};
+struct MulInside {
+  __device__ void operator()(double& e, bool in, double x) const {
+    if (in) e *= x;
+  }
+};
+struct SetInside {
+  __device__ void operator()(double& e, bool in, double x) const {
+    if (in) e = x;
+  }
+};
+template <class F>
+__device__ void slab_fill_rows(GC& c, F f) {
+  slab_for_each<true>(c, f, SetOrZero{});
 }
 // the same, column-wise (consecutive threads take consecutive rows)
 template <class F>
 __device__ void slab_fill_cols(GC& c, F f) {
-  const int np = c.geo.npad, ldr = c.geo.ldr;
-  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
-    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    L.S[cc * ldr + i] = (i < c.n && gc < c.n) ? f(i, gc) : 0.0;
-  }
-  __syncthreads();
+  slab_for_each<false>(c, f, SetOrZero{});
 }
 // dst[i*n + gc] = S[cc][i] for the leading n x n block
 __device__ void slab_store_rowmajor(GC& c, double* dst) {
@@ -533,7 +583,8 @@ __device__ void cpqr_gang(GC& c_io) {
 #pragma unroll
     for (int s = 0; s < kRL; ++s) {
       const int i = c.l + 64 * s;
-      v[s] = (s < nrl && i > p && i < n) ? ld_coh(xs + i) : 0.0;
+      const double x = ld_coh(xs + min(i, c.geo.npad - 1));
+      v[s] = (s < nrl && i > p && i < n) ? x : 0.0;
       am = fmax(am, fabs(v[s]));
     }
     am = wave_max(am);
@@ -705,7 +756,8 @@ __device__ void apply_reflectors(GC& c_in, bool identity_cols) {
 #pragma unroll
       for (int r = 0; r < kRL; ++r) {
         const int i = c.l + 64 * r;
-        v[r] = (r < nrl && i > j && i < n) ? gmem(vc)[i] : (i == j ? 1.0 : 0.0);
+        const double x = gmem(vc)[min(i, np - 1)];
+        v[r] = (r < nrl && i > j && i < n) ? x : (i == j ? 1.0 : 0.0);
       }
     };
     double vn[kRL], tn = 0.0;
@@ -774,7 +826,8 @@ __device__ void back_subst(GC& c_in) {
 #pragma unroll
       for (int r = 0; r < kRL; ++r) {
         const int i = c.l + 64 * r;
-        rv[r] = (r < nrl && i < q) ? gmem(rc)[i] : 0.0;
+        const double x = gmem(rc)[min(i, np - 1)];
+        rv[r] = (r < nrl && i < q) ? x : 0.0;
       }
     };
     double rn[kRL];
@@ -943,11 +996,7 @@ __device__ void equal_gang(GC& c, const Inst& I) {
   auto dm = [&](int i) { const double d = gmem(D)[i]; return (loh && d > 1.0) ? 1.0 : d; };
   slab_fill_rows(c, [&](int i, int gc) { return dm(i) * gmem(T)[(int64_t)i * n + gc]; });
   __syncthreads();
-  for (int idx = c.t; idx < c.geo.npad * c.geo.w; idx += kGangThreads) {
-    const int cc = idx / c.geo.npad, i = idx - cc * c.geo.npad, gc = c.c0 + cc;
-    if (i < n && gc < n) L.S[cc * c.geo.ldr + i] += gmem(U)[(int64_t)gc * n + i] / dp(i);
-  }
-  __syncthreads();
+  slab_for_each<false>(c, [&](int i, int gc) { return gmem(U)[(int64_t)gc * n + i] / dp(i); }, AddInside{});
   cpqr_gang<kRL>(c);
   slab_fill_cols(c, [&](int i, int gc) { return gmem(U)[(int64_t)gc * n + i] / dp(i); });
   __syncthreads();
@@ -1000,38 +1049,49 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
   const double* U2 = A;
   const double* T2 = A ? A + (int64_t)n * n : nullptr;
   const double* D2 = A ? A + 2 * (int64_t)n * n : nullptr;
-  auto d1 = [&](int i) { return D1 ? gmem(D1)[i] : 1.0; };
-  auto d2 = [&](int i) { return D2 ? gmem(D2)[i] : 1.0; };
   double* Xg = sc_X(c);
   // P2 = T1 T2^T (slab columns), kept in HBM while P1 = U1^T U2 is formed
-  slab_fill_cols(c, [&](int i, int gc) { return T2 ? gmem(T2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
-  __syncthreads();
-  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, One{});
+  // (a null stage is the identity; the null tests stay outside the loops
+  // so that the loads inside them are unconditional)
+  if (T2) slab_fill_cols(c, [&](int i, int gc) { return gmem(T2)[(int64_t)gc * n + i]; });
+  else slab_identity(c);
+  if (T1) slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, One{});
+  else slab_gemm(c, AIdent<One>{n, One{}}, One{}, One{});
   slab_store_colmajor(c, Xg);
   __syncthreads();
-  slab_fill_rows(c, [&](int i, int gc) { return U2 ? gmem(U2)[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0); });
-  __syncthreads();
-  slab_gemm(c, ARowMajorT{U1, n}, One{}, One{});
-  // Mid
-  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
-    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    if (i >= n || gc >= n) continue;
-    const double a = d1(i), b = d2(gc);
-    const double lm = 1.0 / (a > 1.0 ? a : 1.0);   // D_Lm
-    const double lpi = a < 1.0 ? a : 1.0;           // D_Lp^{-1}
-    const double rpi = 1.0 / (b > 1.0 ? b : 1.0);  // D_Rp^{-1}
-    const double rm = b < 1.0 ? b : 1.0;            // D_Rm
-    double* e = &L.S[cc * c.geo.ldr + i];
-    *e = lm * (*e) * rpi + lpi * gmem(Xg)[(int64_t)gc * np + i] * rm;
+  if (U2) slab_fill_rows(c, [&](int i, int gc) { return gmem(U2)[(int64_t)i * n + gc]; });
+  else slab_identity(c);
+  if (U1) slab_gemm(c, ARowMajorT{U1, n}, One{}, One{});
+  else slab_gemm(c, AIdent<One>{n, One{}}, One{}, One{});
+  // Mid, with D1 in L.tau and D2 in L.beta (both free until the QR)
+  for (int i = c.t; i < np; i += kGangThreads) {
+    L.tau[i] = (D1 && i < n) ? gmem(D1)[i] : 1.0;
+    L.beta[i] = (D2 && i < n) ? gmem(D2)[i] : 1.0;
   }
   __syncthreads();
+  slab_for_each<false>(c,
+                       [&](int i, int gc) {
+                         const double a = L.tau[i], b = L.beta[gc];
+                         const double lm = 1.0 / (a > 1.0 ? a : 1.0);   // D_Lm
+                         const double lpi = a < 1.0 ? a : 1.0;           // D_Lp^{-1}
+                         const double rpi = 1.0 / (b > 1.0 ? b : 1.0);  // D_Rp^{-1}
+                         const double rm = b < 1.0 ? b : 1.0;            // D_Rm
+                         // (gc is clamped to n - 1; for a slab wholly past n the read is
+                         // kept in range and its result is not stored)
+                         const double e = L.S[max(gc - c.c0, 0) * c.geo.ldr + i];
+                         return lm * e * rpi + lpi * gmem(Xg)[(int64_t)gc * np + i] * rm;
+                       },
+                       SetInside{});
   cpqr_gang<kRL>(c);
   // Y = D_Lp^{-1} T1 -> Q^T Y -> R^{-1} (pivot order)
-  slab_fill_rows(c, [&](int i, int gc) {
-    const double a = d1(i);
-    return (T1 ? gmem(T1)[(int64_t)i * n + gc] : (i == gc ? 1.0 : 0.0)) * (a < 1.0 ? a : 1.0);
-  });
-  __syncthreads();
+  if (T1) {
+    slab_fill_rows(c, [&](int i, int gc) {
+      const double a = gmem(D1)[i];
+      return gmem(T1)[(int64_t)i * n + gc] * (a < 1.0 ? a : 1.0);
+    });
+  } else {
+    slab_identity(c);
+  }
   apply_reflectors<true, kRL>(c, false);
   back_subst<kRL>(c);
   // undo the pivot order through HBM: X[piv[q]][:] = Z[q][:]
@@ -1049,15 +1109,14 @@ __device__ void tdisp_gang(GC& c, const Inst& I, int j, int ilo, int ihi,
   __syncthreads();
   slab_fill_cols(c, [&](int i, int gc) { return gmem(Xg)[(int64_t)gc * np + i]; });
   __syncthreads();
-  // G = (U2 D_Rp^{-1}) X
-  struct RP {
-    const double* D2;
-    __device__ double operator()(int kk) const {
-      const double b = D2 ? gmem(D2)[kk] : 1.0;
-      return 1.0 / (b > 1.0 ? b : 1.0);
-    }
-  };
-  slab_gemm(c, ARowMajor<RP>{U2, n, RP{D2}}, One{}, One{});
+  // G = (U2 D_Rp^{-1}) X, D_Rp^{-1} in L.beta (free after the solve)
+  for (int i = c.t; i < np; i += kGangThreads) {
+    const double b = (D2 && i < n) ? gmem(D2)[i] : 1.0;
+    L.beta[i] = 1.0 / (b > 1.0 ? b : 1.0);
+  }
+  __syncthreads();
+  if (U2) slab_gemm(c, ARowMajor<BetaScale>{U2, n, BetaScale{}}, One{}, One{});
+  else slab_gemm(c, AIdent<BetaScale>{n, BetaScale{}}, One{}, One{});
   int bad = 0;
   for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
     const int cc = idx / np, i = idx - cc * np;
@@ -1097,19 +1156,20 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   const double* D2 = A ? A + 2 * (int64_t)n * n : nullptr;
   double* Ug = sc_U(c);
   double* Tg = sc_T(c);
-  // D1 (T1 T2^T) D2
-  slab_fill_cols(c, [&](int i, int gc) { return T2 ? gmem(T2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
-  __syncthreads();
-  slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, [&](int row) { return D1 && row < n ? gmem(D1)[row] : 1.0; });
-  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
-    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    if (gc < n && D2) L.S[cc * ldr + i] *= gmem(D2)[gc];
+  // D1 (T1 T2^T) D2, with D1 in L.tau and D2 in L.beta (free until the QR)
+  for (int i = c.t; i < np; i += kGangThreads) {
+    L.tau[i] = (D1 && i < n) ? gmem(D1)[i] : 1.0;
+    L.beta[i] = (D2 && i < n) ? gmem(D2)[i] : 1.0;
   }
-  __syncthreads();
+  if (T2) slab_fill_cols(c, [&](int i, int gc) { return gmem(T2)[(int64_t)gc * n + i]; });
+  else slab_identity(c);
+  if (T1) slab_gemm(c, ARowMajor<One>{T1, n, One{}}, One{}, [&](int row) { return L.tau[row]; });
+  else slab_gemm(c, AIdent<One>{n, One{}}, One{}, [&](int row) { return L.tau[row]; });
+  slab_for_each<false>(c, [&](int, int gc) { return L.beta[gc]; }, MulInside{});
   cpqr_gang<kRL>(c);
   // T = d^{-1} (R P^T) U2^T  (slab columns), to HBM
-  slab_fill_cols(c, [&](int i, int gc) { return U2 ? gmem(U2)[(int64_t)gc * n + i] : (i == gc ? 1.0 : 0.0); });
-  __syncthreads();
+  if (U2) slab_fill_cols(c, [&](int i, int gc) { return gmem(U2)[(int64_t)gc * n + i]; });
+  else slab_identity(c);
   slab_gemm(c, AColMajor{sc_R(c), np}, One{},
             [&](int row) { return row < n ? 1.0 / fabs(L.beta[row]) : 0.0; });
   slab_store_colmajor(c, Tg);
@@ -1117,7 +1177,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   slab_identity(c);
   __syncthreads();
   apply_reflectors<false, kRL>(c, true);
-  slab_gemm(c, ARowMajor<One>{U1, n, One{}}, One{}, One{});
+  if (U1) slab_gemm(c, ARowMajor<One>{U1, n, One{}}, One{}, One{});
   slab_store_colmajor(c, Ug);
   // D of the combined factorization: |beta| (kept in L.red-free storage: HBM)
   double* Dg = sc_X(c);
@@ -1128,12 +1188,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   auto dp = [&](int i) { const double d = gmem(Dg)[i]; return d > 1.0 ? d : 1.0; };
   auto dm = [&](int i) { const double d = gmem(Dg)[i]; return d < 1.0 ? d : 1.0; };
   slab_fill_rows(c, [&](int i, int gc) { return gmem(Ug)[(int64_t)i * np + gc] / dp(i); });
-  __syncthreads();
-  for (int idx = c.t; idx < np * c.geo.w; idx += kGangThreads) {
-    const int cc = idx / np, i = idx - cc * np, gc = c.c0 + cc;
-    if (i < n && gc < n) L.S[cc * ldr + i] += dm(i) * gmem(Tg)[(int64_t)gc * np + i];
-  }
-  __syncthreads();
+  slab_for_each<false>(c, [&](int i, int gc) { return dm(i) * gmem(Tg)[(int64_t)gc * np + i]; }, AddInside{});
   cpqr_gang<kRL>(c);
   slab_fill_rows(c, [&](int i, int gc) { return gmem(Ug)[(int64_t)i * np + gc] / dp(i); });
   __syncthreads();
@@ -1165,7 +1220,7 @@ __device__ void grad_gang(GC& c, const Inst& I, int j) {
   for (int l = l0; l < l1; ++l) {
     // slab <- diag(1/v_l) Ebar [:, slab]; G_l diag(1/v_l) Ebar; E diag(v_l) (...)
     load_slice_scale(c, I, l);
-    slab_fill_rows(c, [&](int i, int gc) { return I.expk_inv[(int64_t)i * n + gc] / L.tau[i]; });
+    slab_fill_rows(c, [&](int i, int gc) { return gmem(I.expk_inv)[(int64_t)i * n + gc] / L.tau[i]; });
     __syncthreads();
     slab_gemm(c, AColMajor{Gb[cur], np}, One{}, One{});
     slab_gemm(c, aop, [&](int kk) { return L.tau[kk]; }, One{});
