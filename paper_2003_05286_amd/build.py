@@ -55,6 +55,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                       [f"-DSDQ_NT={nt}"]))
         tasks.append((os.path.join(CSRC, "sdq_nt_dense.hip"), os.path.join(BUILD, f"sdq_nt_dense{nt}.o"),
                       [f"-DSDQ_NT={nt}"]))
+    tasks.append((os.path.join(CSRC, "sdq_nt9.hip"), os.path.join(BUILD, "sdq_nt9.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_dispatch.hip"), os.path.join(BUILD, "sdq_dispatch.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_gang.hip"), os.path.join(BUILD, "sdq_gang.o"), []))
     tasks.append((os.path.join(CSRC, "sdq_complex.hip"), os.path.join(BUILD, "sdq_complex.o"), []))

@@ -70,7 +70,11 @@ struct Geo {
 template <int NT, int P, bool ELDS>
 struct Smem {
   using G = Geo<NT, P>;
-  double R[G::NP * G::LDR];                  // factor store, [col][row]
+  // Above 128 rows the n x n factor store (R and the reflectors) no longer
+  // fits in the CU's 160 KB of LDS beside the rest: it then lives in a
+  // per-workgroup area of device memory (rg), accessed through r_ld / r_st.
+  static constexpr bool RG = NT > kMaxNT;
+  double R[RG ? 1 : G::NP * G::LDR];         // factor store, [col][row]
   double E[ELDS ? G::NP * G::LDR : 1];       // staged operand (sweep: swizzled E; pair: [row][col])
   double cand[2][G::P][G::NP];               // pivot candidate columns
   double vbuf[G::KB][G::NP];                 // exp(alpha f) of the slices in flight
@@ -84,6 +88,7 @@ struct Smem {
   int sinv[G::NP];                           // sinv[c] = step at which c was pivoted
   int ired[2 * G::P];
   int item;
+  double* rg;  // the factor store in device memory (RG)
 };
 
 // Device memory seen as the global address space: loads and stores through
@@ -94,6 +99,20 @@ struct Smem {
 template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
   return (__attribute__((address_space(1))) T*)p;
+}
+
+// entry i of the factor store, [col][row] with stride LDR; within a
+// workgroup the device-memory copy is coherent through the CU's L1 once a
+// barrier has ordered the writes before the reads
+template <class SM>
+__device__ __forceinline__ double r_ld(const SM& S, int i) {
+  if constexpr (SM::RG) return gmem(S.rg)[i];
+  else return S.R[i];
+}
+template <class SM>
+__device__ __forceinline__ void r_st(SM& S, int i, double v) {
+  if constexpr (SM::RG) gmem(S.rg)[i] = v;
+  else S.R[i] = v;
 }
 
 template <int NT, int P>
@@ -209,20 +228,28 @@ __device__ __forceinline__ double row_max16(double v) {
   return v;
 }
 
-// Pivot key: the column norm with its 7 lowest mantissa bits replaced by
-// 127 - column, so that one max over doubles picks the largest norm and,
-// among norms equal to 2^-45 relative, the smallest column index.  A NaN or
-// infinite norm is clamped (never loses eligibility); -1 marks "not a
+// Pivot key: the column norm with its IB lowest mantissa bits replaced by
+// 2^IB - 1 - column, so that one max over doubles picks the largest norm
+// and, among norms equal to 2^-(52 - IB) relative, the smallest column
+// index (IB = 7 up to 128 columns: 2^-45; IB = 8 up to 256: 2^-44).  A NaN
+// or infinite norm is clamped (never loses eligibility); -1 marks "not a
 // candidate".
+template <int IB = 7>
 __device__ __forceinline__ double pivot_key(double norm, int col) {
+  constexpr unsigned long long M = (1ull << IB) - 1;
   double x = norm >= 0.0 ? norm : 0.0;  // NaN -> 0
   x = x < 1.0e300 ? x : 1.0e300;
-  const unsigned long long b = (__double_as_longlong(x) & ~0x7Full) | (unsigned long long)(127 - col);
+  const unsigned long long b = (__double_as_longlong(x) & ~M) | (unsigned long long)(M - col);
   return __longlong_as_double((long long)b);
 }
+template <int IB = 7>
 __device__ __forceinline__ int pivot_col(double key) {
-  return 127 - (int)(__double_as_longlong(key) & 0x7F);
+  constexpr unsigned long long M = (1ull << IB) - 1;
+  return (int)M - (int)(__double_as_longlong(key) & M);
 }
+// index bits of the pivot keys of an n x n register matrix
+template <int NT>
+constexpr int key_bits() { return 16 * NT > 128 ? 8 : 7; }
 
 // sqrt(q) for q in [2^-30, 2^3] (scaled squared norms): the hardware
 // reciprocal square root estimate refined by one Goldschmidt step
@@ -511,11 +538,11 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
       double key = -1.0;
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const double kc = ps[c] < 0 ? pivot_key(vn1[c], col_of<NT, P>(L, c)) : -1.0;
+        const double kc = ps[c] < 0 ? pivot_key<key_bits<NT>()>(vn1[c], col_of<NT, P>(L, c)) : -1.0;
         key = c == 0 ? kc : key_max(key, kc);
       }
       key = row_max16(key);  // the four rows hold the same columns
-      const int bc = pivot_col(key);
+      const int bc = pivot_col<key_bits<NT>()>(key);
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         if (key >= 0.0 && ps[c] < 0 && col_of<NT, P>(L, c) == bc) {
@@ -537,12 +564,12 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
         // one wave: its own LDS writes are visible to its later reads
         __builtin_amdgcn_wave_barrier();
       }
-      const int pc = pivot_col(pk);
+      const int pc = pivot_col<key_bits<NT>()>(pk);
       const int pw = (pc >> 4) % P;
       const double* xc = S.cand[buf][pw];
       const double alpha = xc[j];
       // norm estimate of the pivot column (key without the index bits)
-      const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~0x7Fll);
+      const double vpiv = __longlong_as_double(__double_as_longlong(pk) & ~((1ll << key_bits<NT>()) - 1));
 
       // ---- reflector (every wave computes the same one from the same data);
       // rows <= j masked in tile TJ only, tiles below TJ never touched.
@@ -692,7 +719,7 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row_of(L, ti, r);
-        S.R[col * G::LDR + row] = live ? A.v[c][ti][r] : (row == col ? 1.0 : 0.0);
+        r_st(S, col * G::LDR + row, live ? A.v[c][ti][r] : (row == col ? 1.0 : 0.0));
       }
     if (L.g == 0) S.sinv[col] = ps[c];
   }
@@ -708,7 +735,7 @@ template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void diag_r(const Lane& L, const int n, Smem<NT, P, ELDS>& S) {
   using G = Geo<NT, P>;
   for (int t = L.t; t < G::NP; t += G::THREADS)
-    S.dnew[t] = t < n ? fabs(S.R[S.perm[t] * G::LDR + t]) : 1.0;
+    S.dnew[t] = t < n ? fabs(r_ld(S, S.perm[t] * G::LDR + t)) : 1.0;
   __syncthreads();
 }
 
@@ -718,12 +745,12 @@ template <int TJ, int NT, int P, bool ELDS>
 __device__ __forceinline__ void load_reflector(const Lane& L, const Smem<NT, P, ELDS>& S, int j,
                                                double (&v)[NT][4]) {
   const int jj = j - 16 * TJ;
-  const double* vc = &S.R[S.perm[j] * Geo<NT, P>::LDR];
-  // all LDS reads first (one wait), then the masking of tile TJ
+  const int vc = S.perm[j] * Geo<NT, P>::LDR;
+  // all reads first (one wait), then the masking of tile TJ
 #pragma unroll
   for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[ti][r] = vc[row_of(L, ti, r)];
+    for (int r = 0; r < 4; ++r) v[ti][r] = r_ld(S, vc + row_of(L, ti, r));
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -960,7 +987,8 @@ template <int NT, int P, bool ELDS>
 struct RPtOp {
   const Smem<NT, P, ELDS>& S;
   __device__ double operator()(int, int, int, int i, int k) const {
-    return (i <= S.sinv[k]) ? S.R[k * Geo<NT, P>::LDR + i] : 0.0;
+    const double x = r_ld(S, k * Geo<NT, P>::LDR + i);  // read unconditionally, then masked
+    return (i <= S.sinv[k]) ? x : 0.0;
   }
 };
 
@@ -1109,11 +1137,22 @@ template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int q0,
                                           int dir, int cnt, double sgn = 1.0) {
   using G = Geo<NT, P>;
+  // every field value is loaded before any is used (clamped in-range
+  // indices, padding rows set to 1 afterwards), one memory latency per call
+  constexpr int IT = (G::KB * G::NP + G::THREADS - 1) / G::THREADS;
+  double f[IT];
+#pragma unroll
+  for (int e = 0; e < IT; ++e) {
+    const int idx = L.t + e * G::THREADS;
+    const int s = min(idx / G::NP, cnt - 1), row = min(idx % G::NP, I.n - 1);
+    f[e] = gmem(I.field)[(size_t)(q0 + dir * s - 1) * I.n + row];
+  }
   __syncthreads();
-  for (int idx = L.t; idx < cnt * G::NP; idx += G::THREADS) {
-    const int s = idx / G::NP, row = idx - s * G::NP;
-    const int q = q0 + dir * s;
-    S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * gmem(I.field)[(size_t)(q - 1) * I.n + row]) : 1.0;
+#pragma unroll
+  for (int e = 0; e < IT; ++e) {
+    const int idx = L.t + e * G::THREADS;
+    const int s = idx / G::NP, row = idx % G::NP;
+    if (s < cnt) S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * f[e]) : 1.0;
   }
   __syncthreads();
 }
@@ -1140,9 +1179,13 @@ __device__ __forceinline__ void scale_rows(const Lane& L, RM<NT, P>& A, const do
 // blocks such addresses would be hoisted out of the slice loop and spilled).
 template <int NT, int P, bool ELDS>
 struct EOp {
+  // up to two tiles per side the whole operand (at most 16 values per lane)
+  // is read once, when the operator is made, and kept in registers
+  static constexpr bool REG = !ELDS && NT <= 2;
   const double* sE;            // staged swizzled copy in LDS (ELDS)
   __amdgpu_buffer_rsrc_t rsw;  // swizzled copy in HBM
   int lane8;                   // byte offset of this lane in a block
+  double er[REG ? NT * NT * 4 : 1];
   __device__ EOp(const double* s, const double* esw, int lane) : sE(s), lane8(lane * 8) {
     // the copy's address is the same for the whole workgroup
     const unsigned long long a = (unsigned long long)esw;
@@ -1150,9 +1193,15 @@ struct EOp {
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
     rsw = __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0,
                                             NT * NT * 4 * 512, 0x00020000);
+    if constexpr (REG) {
+#pragma unroll
+      for (int b = 0; b < NT * NT * 4; ++b)
+        er[b] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rsw, lane8, b * 512, 0));
+    }
   }
   __device__ double operator()(int ti, int tk, int r, int, int) const {
     if (ELDS) return sE[((ti * NT + tk) * 4 + r) * 64 + (lane8 >> 3)];
+    if constexpr (REG) return er[(ti * NT + tk) * 4 + r];
     return __builtin_bit_cast(
         double, __builtin_amdgcn_raw_buffer_load_b64(rsw, lane8, ((ti * NT + tk) * 4 + r) * 512, 0));
   }
@@ -1591,8 +1640,15 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
                                                             int count, Queue* q, double* tscr) {
   __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
-  // this workgroup's T scratch (TG): one register matrix, lanes contiguous
-  double* ts = TG ? tscr + (size_t)blockIdx.x * (Geo<NT, P>::CT * P * NT * 256) : nullptr;
+  // this workgroup's T scratch (TG): one register matrix, lanes contiguous;
+  // for sizes whose factor store is in device memory, that store follows it
+  constexpr size_t tdoubles = (size_t)Geo<NT, P>::CT * P * NT * 256;
+  constexpr size_t rdoubles = Smem<NT, P, ELDS>::RG ? (size_t)Geo<NT, P>::NP * Geo<NT, P>::LDR : 0;
+  double* ts = TG ? tscr + (size_t)blockIdx.x * (tdoubles + rdoubles) : nullptr;
+  if constexpr (Smem<NT, P, ELDS>::RG) {
+    static_assert(TG, "the factor store in device memory needs the workgroup scratch");
+    if (L.t == 0) S.rg = ts + tdoubles;
+  }
   for (;;) {
     __syncthreads();
     if (L.t == 0) S.item = atomicAdd(&q->next, 1);

@@ -18,6 +18,9 @@ namespace sdq {
   hipError_t dense_pair_info_nt##N(KernelInfo*);
 SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL(7) SDQ_DECL(8)
 #undef SDQ_DECL
+// 128 < n <= 144: the one-workgroup sweep only (sdq_nt9.hip)
+hipError_t launch_sweep_nt9(int, const Inst*, const SweepItem*, int, Queue*, int, double*, hipStream_t);
+hipError_t kernel_info_nt9(int, int, KernelInfo*);
 
 #define SDQ_SWITCH(CALL)                                   \
   switch (nt) {                                            \
@@ -34,6 +37,7 @@ SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL
 
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
                         Queue* q, int grid, double* tscr, hipStream_t s) {
+  if (nt == kSweepMaxNT) return launch_sweep_nt9(variant, inst, items, count, q, grid, tscr, s);
   if (variant == 3) {
 #define C(N) launch_dense_sweep_nt##N(inst, items, count, q, grid, s)
     SDQ_SWITCH(C)
@@ -71,6 +75,7 @@ hipError_t launch_similarity(int nt, int n, int count, double* const* mats, cons
 #undef C
 }
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
+  if (nt == kSweepMaxNT) return kernel_info_nt9(kind, variant, out);
   if (kind == KK_SWEEP && variant == 3) {
 #define C(N) dense_info_nt##N(out)
     SDQ_SWITCH(C)

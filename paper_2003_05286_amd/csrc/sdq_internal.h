@@ -10,6 +10,10 @@ namespace sdq {
 // Largest number of 16-wide tiles per matrix dimension handled by the
 // LDS-resident kernels: n <= 16 * kMaxNT = 128.
 constexpr int kMaxNT = 8;
+// The stabilized sweep also runs as one workgroup for n <= 16 * kSweepMaxNT
+// = 144 (factor store in device memory); all other kernels of that size and
+// every kernel above it are gang kernels.
+constexpr int kSweepMaxNT = 9;
 
 // One stored UDT factorization ("stage") of a chain, kept in HBM:
 //   U [n*n] | T [n*n] | D [n] | extra [kStageExtra]
@@ -189,7 +193,9 @@ __host__ __device__ constexpr bool sweep_variant_tg(int variant) { return varian
 // doubles of T scratch per workgroup of a variant-4/5 sweep (0 otherwise):
 // one 16 x 16 FP64 tile = 256 doubles per (wave, tile column, tile row)
 __host__ __device__ inline int64_t sweep_tscr_doubles(int nt, int variant) {
-  return sweep_variant_tg(variant) ? (int64_t)nt * nt * 256 : 0;
+  if (!sweep_variant_tg(variant)) return 0;
+  // above kMaxNT tiles the factor store (16 nt x (16 nt + 1)) follows T
+  return (int64_t)nt * nt * 256 + (nt > kMaxNT ? (int64_t)16 * nt * (16 * nt + 1) : 0);
 }
 hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* items, int count,
                         Queue* q, int grid, double* tscr, hipStream_t s);

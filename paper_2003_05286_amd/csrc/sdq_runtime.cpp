@@ -273,6 +273,9 @@ const sdq::KernelInfo& info(sdq_ctx* ctx, int kind, int nt, int variant) {
 }
 
 bool is_gang(int nt) { return nt > sdq::kMaxNT; }
+// the stabilized sweep runs as one workgroup up to kSweepMaxNT tiles
+bool sweep_is_gang(int nt) { return nt > sdq::kSweepMaxNT; }
+bool launch_is_gang(int kind, int nt) { return kind == sdq::KK_SWEEP ? sweep_is_gang(nt) : is_gang(nt); }
 
 // gangs of tile count nt that fit the device at once (cached)
 int gang_slots(sdq_ctx* ctx, int nt) {
@@ -288,7 +291,7 @@ int gang_slots(sdq_ctx* ctx, int nt) {
 }
 
 int grid_for(sdq_ctx* ctx, int kind, int nt, int variant, int count) {
-  if (is_gang(nt)) {
+  if (launch_is_gang(kind, nt)) {
     // a multiple of 8 gangs where the device holds them (XCD-local gangs)
     const int cap = gang_slots(ctx, nt);
     int ng = std::max(1, std::min(count, cap));
@@ -434,18 +437,23 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   if (!P.llist.empty()) memcpy(h + o_ll, P.llist.data(), P.llist.size() * sizeof(int32_t));
   B.o_inst = o_inst;
   B.o_ll = o_ll;
-  for (const auto& r : P.sweep_ranges) B.gang |= is_gang(r.nt);
+  for (const auto& r : P.sweep_ranges) B.gang |= sweep_is_gang(r.nt);
   for (int md = 0; md < sdq::kPairModes; ++md)
     for (const auto& r : P.pair_ranges[md]) B.gang |= is_gang(r.nt);
   B.status = status;
   B.count = count;
   int qi = 0;
   for (const auto& r : P.sweep_ranges) {
-    const int variant = is_gang(r.nt) ? 0 : P.dense ? 3 : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
+    // (above kMaxNT tiles and up to kSweepMaxNT: the one-workgroup sweep with
+    // T and the factor store in workgroup scratch, variant 4)
+    const int variant = sweep_is_gang(r.nt) ? 0
+                        : r.nt > sdq::kMaxNT ? 4
+                        : P.dense ? 3
+                        : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
     const int grid = grid_for(ctx, sdq::KK_SWEEP, r.nt, variant, r.count);
     // classes may run concurrently: each launch gets its own T scratch
     const size_t toff = B.tscr_doubles;
-    if (!is_gang(r.nt)) B.tscr_doubles += (size_t)grid * (size_t)sdq::sweep_tscr_doubles(r.nt, variant);
+    if (!sweep_is_gang(r.nt)) B.tscr_doubles += (size_t)grid * (size_t)sdq::sweep_tscr_doubles(r.nt, variant);
     B.launches.push_back(LaunchRec{sdq::KK_SWEEP, r.nt, variant, 0, grid, r.count,
                                    o_sw + r.off * sizeof(SweepItem), o_q + (qi++) * sizeof(Queue), toff});
   }
@@ -476,7 +484,7 @@ size_t gang_bytes(int nt, int ngangs) {
 size_t gang_need(const Built& B) {
   size_t need = 0;
   for (const LaunchRec& L : B.launches)
-    if (is_gang(L.nt)) need = std::max(need, gang_bytes(L.nt, L.grid));
+    if (launch_is_gang(L.kind, L.nt)) need = std::max(need, gang_bytes(L.nt, L.grid));
   return need;
 }
 
@@ -513,13 +521,14 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   // Stream of each launch.  The items of different tile classes belong to
   // different chains, so the classes are independent: each class of the
   // one-workgroup kernels runs in order on a side stream of its own, forked
-  // from s after the upload and joined back into s, and the gang classes
-  // (which share the gang scratch) run in order on s.  A batch of one class
-  // stays on s.
+  // from s after the upload and joined back into s, and the classes above
+  // kMaxNT tiles (gang kernels, which share the gang scratch, and the
+  // one-workgroup sweeps whose stages the gang pair kernels read) run in
+  // order on s.  A batch of one class stays on s.
   std::vector<int> cls;  // distinct one-workgroup tile classes, first-seen order
   bool any_gang = false;
   for (const LaunchRec& L : B.launches) {
-    if (is_gang(L.nt)) any_gang = true;
+    if (L.nt > sdq::kMaxNT) any_gang = true;  // runs on s
     else if (std::find(cls.begin(), cls.end(), L.nt) == cls.end()) cls.push_back(L.nt);
   }
   const bool fork = B.fork && (int)cls.size() + (any_gang ? 1 : 0) > 1;
@@ -537,7 +546,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
     for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(ctx->side[i], ctx->ev_fork, 0), "hipStreamWaitEvent");
   }
   auto stream_of = [&](const LaunchRec& L) -> hipStream_t {
-    if (!fork || is_gang(L.nt)) return s;
+    if (!fork || L.nt > sdq::kMaxNT) return s;
     const int c = (int)(std::find(cls.begin(), cls.end(), L.nt) - cls.begin());
     return ctx->side[c % nside];
   };
@@ -545,7 +554,7 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
     Queue* q = (Queue*)(d + L.queue_off);
     hipStream_t ls = stream_of(L);
     auto go = [&]() -> hipError_t {
-      if (is_gang(L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
+      if (launch_is_gang(L.kind, L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
       if (L.kind == sdq::KK_SWEEP)
         return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
                                  q, L.grid, B.tscr_base ? B.tscr_base + L.tscr_off : nullptr, ls);
