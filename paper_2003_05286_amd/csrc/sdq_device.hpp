@@ -576,24 +576,43 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
       // v keeps y = the pivot column below row j times sc (exact: sc is a
       // power of two); the Householder vector is e_j + w y.
       const double sc = pow2_scale(vpiv), usc = pow2_unscale(vpiv);
-      double v[NT][4];
+      // Above kMaxNT tiles the register budget (three waves per SIMD) does
+      // not hold y beside the matrix: it is read again from LDS for each of
+      // its three uses (the compiler barriers keep the reads from merging)
+      // instead of being spilled.
+      constexpr bool VRELOAD = NT > kMaxNT;
+      auto yv = [&](int ti, int r) -> double {
+        const double x = xc[row_of(L, ti, r)];
+        return (ti == TJ && L.g + 4 * r <= jj) ? 0.0 : x * sc;
+      };
+      double v[VRELOAD ? 1 : NT][4];
       double sp[4] = {0.0, 0.0, 0.0, 0.0};  // four independent accumulation chains
-      // all LDS reads of the pivot column first, one wait for them
+      if constexpr (VRELOAD) {
 #pragma unroll
-      for (int ti = TJ; ti < NT; ++ti)
+        for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[ti][r] = xc[row_of(L, ti, r)];
-      __builtin_amdgcn_sched_barrier(0);
+          for (int r = 0; r < 4; ++r) {
+            const double y = yv(ti, r);
+            sp[r] = fma(y, y, sp[r]);
+          }
+      } else {
+        // all LDS reads of the pivot column first, one wait for them
 #pragma unroll
-      for (int ti = TJ; ti < NT; ++ti)
+        for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double x = v[ti][r];
-          if (ti == TJ && L.g + 4 * r <= jj) x = 0.0;
-          const double y = x * sc;
-          v[ti][r] = y;
-          sp[r] = fma(y, y, sp[r]);
-        }
+          for (int r = 0; r < 4; ++r) v[ti][r] = xc[row_of(L, ti, r)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ti = TJ; ti < NT; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double x = v[ti][r];
+            if (ti == TJ && L.g + 4 * r <= jj) x = 0.0;
+            const double y = x * sc;
+            v[ti][r] = y;
+            sp[r] = fma(y, y, sp[r]);
+          }
+      }
       double s = sum_col((sp[0] + sp[1]) + (sp[2] + sp[3]));
       const double as = alpha * sc;
       double tau = 0.0, beta = alpha, w = 0.0;
@@ -622,10 +641,15 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
         const bool upd = ps[c] < 0 && !is_piv;
         rec[c] = false;
         double dp[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (VRELOAD) asm volatile("" ::: "memory");
 #pragma unroll
         for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
+          for (int r = 0; r < 4; ++r) {
+            if constexpr (VRELOAD) dp[r] = fma(yv(ti, r), A.v[c][ti][r], dp[r]);
+            else dp[r] = fma(v[ti][r], A.v[c][ti][r], dp[r]);
+          }
+        if constexpr (VRELOAD) asm volatile("" ::: "memory");
         // (e_j + w y)^T a_c = a_jc + w (y^T a_c)
         const double d = fma(w, sum_col((dp[0] + dp[1]) + (dp[2] + dp[3])), ajc[c]) * (upd ? tau : 0.0);
         // row j after the update
@@ -637,7 +661,8 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int q = L.g + 4 * r;
-              if (ti > TJ || q > jj) A.v[c][ti][r] = w * v[ti][r];
+              const double y = VRELOAD ? yv(ti, r) : v[VRELOAD ? 0 : ti][r];
+              if (ti > TJ || q > jj) A.v[c][ti][r] = w * y;
               else if (q == jj) A.v[c][ti][r] = beta;
             }
         } else {
@@ -646,7 +671,8 @@ __device__ __forceinline__ void cpqr(const Lane& L, const int n, RM<NT, P>& A, S
 #pragma unroll
           for (int ti = TJ; ti < NT; ++ti)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) A.v[c][ti][r] = fma(-dw, v[ti][r], A.v[c][ti][r]);
+            for (int r = 0; r < 4; ++r)
+              A.v[c][ti][r] = fma(-dw, VRELOAD ? yv(ti, r) : v[VRELOAD ? 0 : ti][r], A.v[c][ti][r]);
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             if (L.g + 4 * r == jj) A.v[c][TJ][r] = rjv;
