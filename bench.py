@@ -456,7 +456,9 @@ def main():
         "roofline": {"kernel": "sweep", "bound": "mfma", "achieved": achieved / 1e12,
                      "peak": PEAK_FP64_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_MFMA,
-                     "traffic": measured_traffic() if args.workload == "hubbard_L8_b40_batch512" else None,
+                     # (the counters were taken on the default scheme and stabilizer)
+                     "traffic": measured_traffic() if (args.workload == "hubbard_L8_b40_batch512" and not plain
+                                                       and args.stab == "qr") else None,
                      "flops_per_step": f_sweep_step, "launches_per_step": sweep_launches_per_step,
                      "device_ms_per_step": sweep_avg_s * 1e3,
                      "flops_per_launch": f_sweep_step / max(sweep_launches_per_step, 1e-30),
