@@ -4,6 +4,7 @@
 // stored stage factorizations, per-kernel event timing, HIP graph capture of
 // repeated batches, and the autotune table.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -15,6 +16,19 @@
 #include <vector>
 
 #include "sdq.h"
+
+// A roctx range around every compute entry point (host timeline of the
+// call: argument checks, planning and enqueue), visible to tracing tools
+// (rocprofv3 --marker-trace); without a tool attached the calls do nothing.
+namespace {
+struct ApiRange {
+  explicit ApiRange(const char* name) { roctxRangePushA(name); }
+  ~ApiRange() { roctxRangePop(); }
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
+};
+}  // namespace
+#define SDQ_API_RANGE(name) ApiRange sdq_api_range_(name)
 #include "sdq_internal.h"
 
 namespace sdq {
@@ -832,6 +846,7 @@ const char* sdq_last_error(const sdq_ctx* ctx) {
 
 sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                       double* const* g, double* logdet, double* sign, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens");
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
   if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
@@ -867,6 +882,7 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
 // stages, the T scratch) is carved out of this device's fixed scratch.
 sdq_status sdq_greens_noalloc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                               double* const* g, double* logdet, double* sign, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens_noalloc");
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
   if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
@@ -976,6 +992,7 @@ sdq_status validate_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t 
 
 sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count, double* const* g,
                             double* logdet, double* sign, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens_dense");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
   std::vector<sdq_instance> shape;
@@ -1012,6 +1029,7 @@ sdq_status sdq_greens_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_
 sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, int32_t count,
                                   const int32_t* l_list, int32_t n_l, double* const* gt, double* const* g,
                                   double* logdet, double* sign, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens_tdisp_dense");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
   std::vector<sdq_instance> shape;
@@ -1079,6 +1097,7 @@ sdq_status sdq_greens_tdisp_dense(sdq_ctx* ctx, const sdq_dense_instance* inst, 
 sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                             const int32_t* l_list, int32_t n_l, double* const* gt,
                             double* const* g, double* logdet, double* sign, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens_tdisp");
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
   if (scheme != SDQ_INV_LOH && scheme != SDQ_INV_PLAIN) return fail(ctx, SDQ_EINVAL, "unknown scheme");
@@ -1164,6 +1183,7 @@ sdq_status sdq_greens_tdisp(sdq_ctx* ctx, const sdq_instance* inst, int32_t coun
 
 sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* logdet,
                       double* sign, int32_t* status, uint64_t* ckpt_handle) {
+  SDQ_API_RANGE("sdq_logdet");
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
   if (ckpt_handle) *ckpt_handle = 0;
@@ -1219,6 +1239,7 @@ sdq_status sdq_logdet(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, dou
 sdq_status sdq_logdet_grad(sdq_ctx* ctx, uint64_t ckpt_handle, const sdq_instance* inst,
                            int32_t count, double* const* grad, double* logdet, double* sign,
                            int32_t* status) {
+  SDQ_API_RANGE("sdq_logdet_grad");
   sdq_status st = validate(ctx, inst, count, true);
   if (st) return st;
   if (count > 0 && !grad) return fail(ctx, SDQ_EINVAL, "grad is NULL");
@@ -1287,6 +1308,7 @@ sdq_status sdq_release(sdq_ctx* ctx, uint64_t ckpt_handle) {
 
 sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u, double* d,
                    double* t) {
+  SDQ_API_RANGE("sdq_udt");
   if (!ctx) return SDQ_EINVAL;
   if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
   if (n > sdq::kGangMaxN) return fail(ctx, SDQ_EUNSUPPORTED, "n > 1024 is not supported");
@@ -1314,6 +1336,7 @@ sdq_status sdq_udt(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, doub
 
 sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double* w, double* u, double* d,
                            double* t) {
+  SDQ_API_RANGE("sdq_udt_complex");
   if (!ctx) return SDQ_EINVAL;
   if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
   if (n > sdq::complex_udt_max_n()) return fail(ctx, SDQ_EUNSUPPORTED, "complex UDT: n > 64 is not supported");
@@ -1329,6 +1352,7 @@ sdq_status sdq_udt_complex(sdq_ctx* ctx, int32_t n, int32_t count, const double*
 
 sdq_status sdq_greens_complex(sdq_ctx* ctx, const sdq_complex_instance* inst, int32_t count, double* const* g,
                               double* logdet, double* phase, int32_t* status) {
+  SDQ_API_RANGE("sdq_greens_complex");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0) return fail(ctx, SDQ_EINVAL, "count < 0");
   if (count == 0) return SDQ_OK;
@@ -1367,6 +1391,7 @@ sdq_status sdq_greens_complex(sdq_ctx* ctx, const sdq_complex_instance* inst, in
 
 sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf,
                            const double* unif, int32_t* accepted, int32_t* status) {
+  SDQ_API_RANGE("sdq_local_sweep");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || nf < 1 || nf > 2) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf in {1, 2}");
   if (count == 0) return SDQ_OK;
@@ -1466,6 +1491,7 @@ sdq_status sdq_local_sweep(sdq_ctx* ctx, const sdq_instance* inst, int32_t count
 sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_instance* prop,
                           int32_t count, int32_t nf, const double* dS, const double* u, double* logdet,
                           double* sign, int32_t* accept, int32_t* status) {
+  SDQ_API_RANGE("sdq_metropolis");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
   if (count == 0) return SDQ_OK;
@@ -1511,6 +1537,7 @@ sdq_status sdq_metropolis(sdq_ctx* ctx, const sdq_instance* cur, const sdq_insta
 sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
                         double inv_var, const double* noise, double* force, double* logdet, double* sign,
                         int32_t* status) {
+  SDQ_API_RANGE("sdq_langevin");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
   if (count == 0) return SDQ_OK;
@@ -1581,6 +1608,7 @@ sdq_status sdq_langevin(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, i
 sdq_status sdq_hmc(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, int32_t nf, double eps,
                    int32_t nsteps, double inv_var, const double* mom, const double* u, double* logdet,
                    double* sign, int32_t* accept, double* dH, int32_t* status) {
+  SDQ_API_RANGE("sdq_hmc");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || nf < 1) return fail(ctx, SDQ_EINVAL, "need count >= 0 and nf >= 1");
   if (count == 0) return SDQ_OK;
@@ -1689,6 +1717,7 @@ sdq_status sdq_set_stabilizer(sdq_ctx* ctx, int32_t stab) {
 
 sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* left,
                           const double* right, double* const* mats) {
+  SDQ_API_RANGE("sdq_similarity");
   if (!ctx) return SDQ_EINVAL;
   if (n < 1 || count < 0) return fail(ctx, SDQ_EINVAL, "bad n or count");
   if (n > 16 * sdq::kMaxNT) return fail(ctx, SDQ_EUNSUPPORTED, "sdq_similarity supports n <= 128");
@@ -1714,6 +1743,7 @@ sdq_status sdq_similarity(sdq_ctx* ctx, int32_t n, int32_t count, const double* 
 
 sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, double* u,
                          double* d, double* t) {
+  SDQ_API_RANGE("sdq_chain_udt");
   sdq_status st = validate(ctx, inst, count, false);
   if (st) return st;
   if (count == 0) return SDQ_OK;
@@ -1745,6 +1775,7 @@ sdq_status sdq_chain_udt(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, 
 // (one workgroup per CU or the occupancy limit), keep the fastest.  Results
 // are cached as JSON lines {"arch", "n", "variant", "blocks_per_cu", "ms"}.
 sdq_status sdq_tune(sdq_ctx* ctx, const int32_t* n_list, int32_t count, const char* cache_path) {
+  SDQ_API_RANGE("sdq_tune");
   if (!ctx) return SDQ_EINVAL;
   if (count < 0 || (count > 0 && !n_list)) return fail(ctx, SDQ_EINVAL, "bad n_list");
   for (int a = 0; a < count; ++a)

@@ -94,8 +94,12 @@ def test_hmc_matches_oracle_trajectory(ctx, L, beta, k, nf, chains, eps, nsteps)
         else:
             assert np.array_equal(phi1[c], phi0[c])
             ref_ld = ld0
+        # the start field comes back bit for bit on rejection (log det to the
+        # usual 1e-12); an accepted end field agrees with the oracle's
+        # trajectory to 1e-10 only, and its log det to the same order
+        tol = 1e-10 if take else 1e-12
         for f in range(len(alphas)):
-            assert abs(ld[c * len(alphas) + f] - ref_ld[f]) <= 1e-10 * max(1.0, abs(ref_ld[f]))
+            assert abs(ld[c * len(alphas) + f] - ref_ld[f]) <= tol * max(1.0, abs(ref_ld[f]))
 
 
 def test_hmc_energy_error_is_second_order(ctx):

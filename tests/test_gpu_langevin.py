@@ -51,7 +51,7 @@ def test_langevin_matches_oracle_step(ctx, L, beta, k, nf, chains):
         for f, a in enumerate(alphas):
             F = F - oracle.logdet_grad(E, phi0[c], a, k, ls)
             ldo = oracle.greens(E, phi0[c], a, k)[1]
-            assert abs(ld_g[c * nf + f] - ldo) <= 1e-10 * max(1.0, abs(ldo))
+            assert abs(ld_g[c * nf + f] - ldo) <= 1e-12 * max(1.0, abs(ldo))
         want = phi0[c] - eps * F + np.sqrt(2.0 * eps) * eta[c]
         e_f = relf(F_g[c], F)
         e_p = np.abs(phi1[c] - want).max() / (eps * np.abs(F).max())

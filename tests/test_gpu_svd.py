@@ -57,8 +57,10 @@ def test_svd_greens_matches_oracle(ctx_svd, ctx_qr, L, beta):
         e_o, e_q = relf(g, Go), relf(g, gq[i].cpu().numpy())
         say(f"[gpu]   instance {i}: relF vs oracle SVD chain {e_o:.2e}, vs library QR path {e_q:.2e}")
         assert e_o <= 1e-10 and e_q <= 1e-10
-        assert abs(ld[i].item() - ldo) <= 1e-10 * abs(ldo)
-        assert abs(ld[i].item() - ldq[i].item()) <= 1e-10 * abs(ldo)
+        say(f"[gpu]   log det {ld[i].item():.15g}: vs oracle {abs(ld[i].item() - ldo) / abs(ldo):.1e}, "
+            f"vs QR path {abs(ld[i].item() - ldq[i].item()) / abs(ldo):.1e} relative")
+        assert abs(ld[i].item() - ldo) <= 1e-12 * abs(ldo)
+        assert abs(ld[i].item() - ldq[i].item()) <= 1e-12 * abs(ldo)
         assert sg[i].item() == sgo
 
 
