@@ -3,7 +3,9 @@
 Compiles the per-tile-count kernel instantiations (n <= 128) and the gang
 kernels (n > 128) in parallel with hipcc and links them with the dispatch
 and runtime objects into
-paper_2003_05286_amd/libsdq.so.  Always recompiles.
+paper_2003_05286_amd/libsdq.so; then links tests/_bin/sdq_abi_check, the
+C-ABI driver over the same objects with the host runtime built under
+AddressSanitizer and UndefinedBehaviorSanitizer.  Always recompiles.
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ LIB = os.path.join(PKG, "libsdq.so")
 ARCH = "gfx950"
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 NTS = range(1, 9)
+# the sanitized C-ABI driver (a test program, built beside the library)
+ABI_CHECK = os.path.join(ROOT, "tests", "_bin", "sdq_abi_check")
 
 
 def hipcc() -> str:
@@ -74,9 +78,37 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_abi_check(objs)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", ABI_CHECK)
     return LIB
+
+
+def build_abi_check(objs) -> str:
+    """The C-ABI driver of tests/abi_check.cpp linked with the host runtime
+    compiled by g++ under AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; the HIP objects are the library's own, the sanitizer
+    runtimes are linked statically into the executable)."""
+    os.makedirs(os.path.dirname(ABI_CHECK), exist_ok=True)
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    cflags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__",
+              "-I", os.path.join(ROCM, "include"), "-I", os.path.join(ROOT, "include"), "-I", CSRC] + san
+    rt = os.path.join(BUILD, "sdq_runtime_san.o")
+    drv = os.path.join(BUILD, "abi_check_san.o")
+    jobs = [["g++"] + cflags + ["-c", os.path.join(CSRC, "sdq_runtime.cpp"), "-o", rt],
+            ["g++"] + cflags + ["-c", os.path.join(ROOT, "tests", "abi_check.cpp"), "-o", drv]]
+    with cf.ThreadPoolExecutor(2) as ex:
+        for cmd, r in zip(jobs, ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), jobs)):
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+    hip_objs = [o for o in objs if os.path.basename(o) != "sdq_runtime.o"]
+    cmd = ["g++"] + san + ["-static-libasan", "-static-libubsan", "-o", ABI_CHECK, drv, rt] + hip_objs + \
+        ["-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx",
+         "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    return ABI_CHECK
 
 
 if __name__ == "__main__":

@@ -2,6 +2,9 @@
 (gcc), and a cross-section of its pins run against that build in a child
 process: any out-of-bounds access, use after free, misaligned access,
 signed overflow or other undefined behaviour in the oracle aborts the run.
+Also the library's host runtime under the same sanitizers (the C-ABI driver
+tests/abi_check.cpp, built with the library): here, without a device, the
+paths that need none (a failing sdq_create, NULL contexts, the strings).
 CPU only."""
 import os
 import shutil
@@ -52,3 +55,35 @@ def test_oracle_pins_under_asan_and_ubsan(tmp_path):
     chk = subprocess.run([sys.executable, "-c", "import oracle; print(oracle.__file__)"], cwd=str(tmp_path),
                          env=env, capture_output=True, text=True)
     assert str(tmp_path) in chk.stdout
+
+
+ABI_CHECK = os.path.join(ROOT, "tests", "_bin", "sdq_abi_check")
+
+
+def abi_check_env():
+    env = dict(os.environ)
+    env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["LSAN_OPTIONS"] = "suppressions=" + os.path.join(ROOT, "tests", "lsan_rocm.supp")
+    return env
+
+
+def _abi_check_binary():
+    if os.path.exists(ABI_CHECK):
+        return ABI_CHECK
+    from paper_2003_05286_amd import build as B
+    objs = [os.path.join(B.BUILD, f) for f in sorted(os.listdir(B.BUILD))] if os.path.isdir(B.BUILD) else []
+    objs = [o for o in objs if o.endswith(".o") and "_san" not in os.path.basename(o)]
+    if not any(os.path.basename(o) == "sdq_dispatch.o" for o in objs):
+        pytest.skip("the library's objects are not built (run __graft_entry__.build())")
+    return B.build_abi_check(objs)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ needed")
+def test_c_abi_host_runtime_under_asan_and_ubsan_without_a_device():
+    exe = _abi_check_binary()
+    r = subprocess.run([exe], env=abi_check_env(), capture_output=True, text=True, timeout=300)
+    out = r.stdout + r.stderr
+    assert "AddressSanitizer" not in out and "runtime error:" not in out and "LeakSanitizer" not in out, out[-4000:]
+    assert r.returncode == 0, out[-4000:]
+    assert "checks passed" in out, out[-2000:]
