@@ -1159,12 +1159,14 @@ __device__ __forceinline__ void store_perm_rows(const Lane& L, const int n, cons
 // slice exponentials v_q = exp(sgn alpha f_q) for `cnt` slices into S.vbuf
 // (sgn = -1: the diagonal of B_q^{-1}).  Slice of buffer row s: q0 + dir*s.
 // Ends with a barrier.
-template <int NT, int P, bool ELDS>
-__device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int q0,
-                                          int dir, int cnt, double sgn = 1.0) {
+// vbuf[s][i] = exp(sgn alpha f_{q,i}) for the cnt slices q = q0, q0 + dir, ...
+// (1 on padding rows).  Every field value is loaded before any is used
+// (clamped in-range indices, padding set afterwards): one memory latency per
+// call.  All threads; barriers before the stores and after them.
+template <int NT, int P>
+__device__ __forceinline__ void fill_vbuf_to(const Lane& L, double (*vbuf)[Geo<NT, P>::NP], const Inst& I,
+                                             int q0, int dir, int cnt, double sgn) {
   using G = Geo<NT, P>;
-  // every field value is loaded before any is used (clamped in-range
-  // indices, padding rows set to 1 afterwards), one memory latency per call
   constexpr int IT = (G::KB * G::NP + G::THREADS - 1) / G::THREADS;
   double f[IT];
 #pragma unroll
@@ -1178,9 +1180,15 @@ __device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, c
   for (int e = 0; e < IT; ++e) {
     const int idx = L.t + e * G::THREADS;
     const int s = idx / G::NP, row = idx % G::NP;
-    if (s < cnt) S.vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * f[e]) : 1.0;
+    if (s < cnt) vbuf[s][row] = row < I.n ? exp(sgn * I.alpha * f[e]) : 1.0;
   }
   __syncthreads();
+}
+
+template <int NT, int P, bool ELDS>
+__device__ __forceinline__ void fill_vbuf(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, int q0,
+                                          int dir, int cnt, double sgn = 1.0) {
+  fill_vbuf_to<NT, P>(L, S.vbuf, I, q0, dir, cnt, sgn);
 }
 
 template <int NT, int P>
@@ -1449,9 +1457,10 @@ __device__ __forceinline__ int jsvd_udt(const Lane& L, const int n, Smem<NT, P, 
 // registers only for its update (after the QR, before Q is formed, while
 // the working matrix is parked in LDS), which frees one register matrix.
 struct NoT {};
-template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false>
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false, bool PSW = false>
 __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, const Inst& I, const int flags,
                           const int jpair, double* tscr = nullptr) {
+  static_assert(!PSW || (DENSE && !ELDS), "pre-swizzled slices are dense and read from device memory");
   static_assert(!(TG && SVD), "the SVD stabilizer keeps T in registers");
   using G = Geo<NT, P>;
   // the SVD stabilizer keeps T in S.E, so E is read from its global copy
@@ -1538,6 +1547,10 @@ __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, c
             gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[kk * G::LDR + i]; }, W, W);
           else
             gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, W, W);
+        } else if constexpr (PSW) {
+          // the slice in the swizzled, zero-padded operand layout (forward only)
+          const EOp<NT, P, false> bop{nullptr, I.field + (size_t)(q - 1) * G::NP * G::NP, L.l};
+          gemm_rb<NT, P>(L, bop, W, W);
         } else {
           gemm_gm<NT, P>(L, Bq, n, adj, W, W);
         }
@@ -1660,7 +1673,7 @@ __device__ __forceinline__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, 
   __syncthreads();
 }
 
-template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false>
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false, bool PSW = false>
 __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
                                                             const SweepItem* __restrict__ items,
                                                             int count, Queue* q, double* tscr) {
@@ -1685,7 +1698,82 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
-    sweep_one<NT, P, ELDS, SVD, DENSE, TG>(L, S, I, wi.flags, wi.j, ts);
+    sweep_one<NT, P, ELDS, SVD, DENSE, TG, PSW>(L, S, I, wi.flags, wi.j, ts);
+  }
+}
+
+// Block products of a chain's slices, P_j = B_{q1} ... B_{q0} for the k
+// slices q0 = jk + 1 .. q1 = min((j+1)k, m) of block j (the product of k
+// slices that the stabilized product of Sec. 4.1 then factorizes), each
+// written row-major to I.prod + j n n.  One workgroup per (chain, block)
+// item: P = E diag(v_q0) is E with its columns scaled, and every further
+// slice is W <- E diag(v_q) W as in the sweep (rows scaled, then the MFMA
+// product with the swizzled E from device memory).  A chain whose blocks
+// have been multiplied out this way runs its stabilized sweep over the P_j
+// with one factorization per product (dense slices, k = 1): the blocks'
+// slice products, independent of each other, then fill the device instead
+// of lying on the sweep's sequential path.
+template <int NT, int P>
+struct ProdSmem {
+  double vbuf[Geo<NT, P>::KB][Geo<NT, P>::NP];
+  int item;
+};
+
+template <int NT, int P>
+__global__ __launch_bounds__(64 * P, 2) void k_prod(const Inst* __restrict__ insts,
+                                                    const SweepItem* __restrict__ items, int count, Queue* q) {
+  using G = Geo<NT, P>;
+  __shared__ ProdSmem<NT, P> S;
+  const Lane L = lane_id();
+  for (;;) {
+    __syncthreads();
+    if (L.t == 0) S.item = atomicAdd(&q->next, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(S.item);
+    if (it >= count) break;
+    const SweepItem wi = items[it];
+    const Inst I = insts[wi.inst];
+    const int n = I.n, j = wi.j;
+    const int q0 = j * I.k + 1, q1 = (j + 1) * I.k < I.m ? (j + 1) * I.k : I.m;
+    const int cnt = q1 - q0 + 1;
+    const EOp<NT, P, false> eop{nullptr, I.esw, L.l};
+    RM<NT, P> W;
+    load_rm<NT, P>(L, W, I.expk, n, false);
+    for (int c0 = 0; c0 < cnt; c0 += G::KB) {
+      const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
+      fill_vbuf_to<NT, P>(L, S.vbuf, I, q0 + c0, +1, cn, 1.0);
+      for (int s2 = 0; s2 < cn; ++s2) {
+        if (c0 + s2 == 0) {
+#pragma unroll
+          for (int c = 0; c < G::CT; ++c) {
+            const double v = S.vbuf[0][col_of<NT, P>(L, c)];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) W.v[c][ti][r] *= v;
+          }
+        } else {
+          scale_rows<NT, P>(L, W, S.vbuf[s2]);
+          gemm_rb<NT, P>(L, eop, W, W);
+        }
+      }
+    }
+    // swizzled store: entry (i, kk) goes to block ((i/16) NT + kk/16) 4 + (kk%16)/4,
+    // lane (kk%4) 16 + i%16 (the lane that takes it as an MFMA A operand)
+    double* dst = I.prod + (size_t)j * G::NP * G::NP;
+#pragma unroll
+    for (int c = 0; c < G::CT; ++c) {
+      if (!tile_ok<NT, P>(L, c)) continue;
+      const int tc = L.w + P * c, kk = col_of<NT, P>(L, c);
+#pragma unroll
+      for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row_of(L, ti, r);
+          const int blk = ((ti * NT + tc) * 4 + (L.cl >> 2)) * 64 + (L.cl & 3) * 16 + (L.g + 4 * r);
+          gmem(dst)[blk] = (i < n && kk < n) ? W.v[c][ti][r] : 0.0;
+        }
+    }
   }
 }
 
@@ -2495,6 +2583,36 @@ struct Launch {
   }
   static hipError_t dense_info(KernelInfo* out) {
     return info_of(k_sweep<NT, P, kDenseLds, false, true>, (int)sizeof(Smem<NT, P, kDenseLds>), out);
+  }
+  // block products (k_prod) and the sweep over them (variant 6), one wave
+  // per tile, from kProdMinNT tiles up; also instantiated in sdq_nt_dense.hip
+  // only
+  static constexpr bool kProd = NT >= kProdMinNT;
+  static hipError_t prod(const Inst* inst, const SweepItem* items, int count, Queue* q, int grid, hipStream_t s) {
+    if constexpr (kProd) {
+      hipLaunchKernelGGL((k_prod<NT, NT>), dim3(grid), dim3(Geo<NT, NT>::THREADS), 0, s, inst, items, count, q);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t prod_info(KernelInfo* out) {
+    if constexpr (kProd) return info_of<NT>(k_prod<NT, NT>, (int)sizeof(ProdSmem<NT, NT>), out);
+    return hipErrorInvalidValue;
+  }
+  static hipError_t bprod_sweep(const Inst* inst, const SweepItem* items, int count, Queue* q, int grid,
+                                double* tscr, hipStream_t s) {
+    if constexpr (kProd) {
+      if (!tscr) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_sweep<NT, NT, false, false, true, true, true>), dim3(grid), dim3(Geo<NT, NT>::THREADS),
+                         0, s, inst, items, count, q, tscr);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t bprod_sweep_info(KernelInfo* out) {
+    if constexpr (kProd)
+      return info_of<NT>(k_sweep<NT, NT, false, false, true, true, true>, (int)sizeof(Smem<NT, NT, false>), out);
+    return hipErrorInvalidValue;
   }
   // G(tau,0) of dense-slice chains (propagation over the dense slices), also
   // instantiated in sdq_nt_dense.hip only

@@ -12,7 +12,11 @@ namespace sdq {
   hipError_t launch_sim_nt##N(int, int, double* const*, const double*, const double*, int, hipStream_t); \
   hipError_t kernel_info_nt##N(int, int, KernelInfo*);                                            \
   hipError_t launch_dense_sweep_nt##N(const Inst*, const SweepItem*, int, Queue*, int, hipStream_t); \
+  hipError_t launch_bprod_sweep_nt##N(const Inst*, const SweepItem*, int, Queue*, int, double*, hipStream_t); \
+  hipError_t bprod_sweep_info_nt##N(KernelInfo*);                                                \
   hipError_t dense_info_nt##N(KernelInfo*);                                                      \
+  hipError_t launch_prod_nt##N(const Inst*, const SweepItem*, int, Queue*, int, hipStream_t);    \
+  hipError_t prod_info_nt##N(KernelInfo*);                                                       \
   hipError_t launch_dense_pair_nt##N(const Inst*, const PairItem*, int, const int32_t*, Queue*, int, \
                                      hipStream_t);                                               \
   hipError_t dense_pair_info_nt##N(KernelInfo*);
@@ -21,6 +25,7 @@ SDQ_DECL(1) SDQ_DECL(2) SDQ_DECL(3) SDQ_DECL(4) SDQ_DECL(5) SDQ_DECL(6) SDQ_DECL
 // 128 < n <= 144: the one-workgroup sweep only (sdq_nt9.hip)
 hipError_t launch_sweep_nt9(int, const Inst*, const SweepItem*, int, Queue*, int, double*, hipStream_t);
 hipError_t kernel_info_nt9(int, int, KernelInfo*);
+hipError_t launch_prod_nt9(const Inst*, const SweepItem*, int, Queue*, int, hipStream_t);
 
 #define SDQ_SWITCH(CALL)                                   \
   switch (nt) {                                            \
@@ -43,7 +48,20 @@ hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* 
     SDQ_SWITCH(C)
 #undef C
   }
+  if (variant == 6) {
+#define C(N) launch_bprod_sweep_nt##N(inst, items, count, q, grid, tscr, s)
+    SDQ_SWITCH(C)
+#undef C
+  }
 #define C(N) launch_sweep_nt##N(variant, inst, items, count, q, grid, tscr, s)
+  SDQ_SWITCH(C)
+#undef C
+}
+
+hipError_t launch_prod(int nt, const Inst* inst, const SweepItem* items, int count, Queue* q, int grid,
+                       hipStream_t s) {
+  if (nt == kSweepMaxNT) return launch_prod_nt9(inst, items, count, q, grid, s);
+#define C(N) launch_prod_nt##N(inst, items, count, q, grid, s)
   SDQ_SWITCH(C)
 #undef C
 }
@@ -76,6 +94,16 @@ hipError_t launch_similarity(int nt, int n, int count, double* const* mats, cons
 }
 hipError_t kernel_info(int kind, int nt, int variant, KernelInfo* out) {
   if (nt == kSweepMaxNT) return kernel_info_nt9(kind, variant, out);
+  if (kind == KK_PROD) {
+#define C(N) prod_info_nt##N(out)
+    SDQ_SWITCH(C)
+#undef C
+  }
+  if (kind == KK_SWEEP && variant == 6) {
+#define C(N) bprod_sweep_info_nt##N(out)
+    SDQ_SWITCH(C)
+#undef C
+  }
   if (kind == KK_SWEEP && variant == 3) {
 #define C(N) dense_info_nt##N(out)
     SDQ_SWITCH(C)

@@ -49,6 +49,7 @@ struct Inst {
   const double* eswi;      // expk_inv in the layout of esw, or null
   const double* unif;      // local updates: uniform numbers [m][n] of the chain
   int32_t* nacc;           // local updates: accepted flips of the chain
+  double* prod;            // block products [nb][16 nt][16 nt], swizzled (k_prod output), or null
 };
 
 enum SweepFlags : int32_t {
@@ -189,7 +190,11 @@ hipError_t launch_swizzle(const double* e, int n, int trans, double* out, hipStr
 //      between blocks (frees a register matrix), exponential from HBM
 //   5  as 4 with the exponential staged in LDS (3 <= nt <= 5)
 constexpr int kSweepVariants = 6;
-__host__ __device__ constexpr bool sweep_variant_tg(int variant) { return variant == 4 || variant == 5; }
+// variant 6: the sweep over block products (k_prod) with one factorization
+// each, one wave per tile with T in the workgroup scratch like variant 4
+__host__ __device__ constexpr bool sweep_variant_tg(int variant) {
+  return variant == 4 || variant == 5 || variant == 6;
+}
 // doubles of T scratch per workgroup of a variant-4/5 sweep (0 otherwise):
 // one 16 x 16 FP64 tile = 256 doubles per (wave, tile column, tile row)
 __host__ __device__ inline int64_t sweep_tscr_doubles(int nt, int variant) {
@@ -201,6 +206,13 @@ hipError_t launch_sweep(int nt, int variant, const Inst* inst, const SweepItem* 
                         Queue* q, int grid, double* tscr, hipStream_t s);
 hipError_t launch_pair(int nt, int variant, int mode, const Inst* inst, const PairItem* items,
                        int count, const int32_t* l_list, Queue* q, int grid, hipStream_t s);
+// block products of the slices (k_prod): one item per (chain, block j),
+// written to Inst::prod + j (16 nt)^2 in the swizzled, zero-padded layout of
+// the slice exponential's copy (launch_swizzle); tile counts kProdMinNT ..
+// kSweepMaxNT
+constexpr int kProdMinNT = 7;
+hipError_t launch_prod(int nt, const Inst* inst, const SweepItem* items, int count, Queue* q, int grid,
+                       hipStream_t s);
 // complex UDT of independent matrices (sdq_complex.hip): w, u, t interleaved
 // (re, im) [count][n][n], d [count][n]; 1 <= n <= complex_udt_max_n()
 int complex_udt_max_n();
@@ -225,7 +237,7 @@ hipError_t launch_greens_complex(const CChain* tab, int count, int grid, hipStre
 hipError_t launch_similarity(int nt, int n, int count, double* const* mats, const double* left,
                              const double* right, int grid, hipStream_t s);
 
-enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2 };
+enum KernelKind { KK_SWEEP = 0, KK_PAIR = 1, KK_UDT = 2, KK_PROD = 3 };
 
 // ---- the fixed scratch of sdq_greens_noalloc (sdq_noalloc.hip) -------------
 constexpr size_t kNoAllocBytes = 64ull << 20;  // per device

@@ -82,6 +82,11 @@ struct Plan {
   // the instances, so the pointers come out the same)
   bool swz_ready = false;
   bool dense = false;  // every instance has dense slices (sweep variant 3)
+  // block products (k_prod) of the tile classes in bprod_mask (bit nt), run
+  // before those classes' sweeps, which are then variant 6
+  std::vector<SweepItem> prod;
+  std::vector<Range> prod_ranges;
+  unsigned bprod_mask = 0;
 };
 
 }  // namespace
@@ -103,6 +108,12 @@ struct sdq_ctx {
   int stab = 0;    // stabilizer of every sweep: 0 pivoted QR, 1 Jacobi SVD
   DevBuf d_htab;   // sdq_hmc: chain table
   DevBuf d_ctab;   // sdq_greens_complex: chain table
+  DevBuf d_prod;   // block products of the slices (k_prod)
+  // multiply the slice blocks out before the sweep (k_prod, tile classes
+  // kProdMinNT .. kSweepMaxNT of sdq_greens): 0 never, 1 for every such
+  // class, 2 for the class of the batch's longest chain when all its chains
+  // are resident at once
+  int bprod = 2;
   std::map<int, int> gang_cap;  // tile count -> gangs resident at once
   // pinned staging of plan images, a ring: the host waits for the plan
   // kStageSlots back, not the previous one, so it builds and enqueues the
@@ -289,7 +300,9 @@ const sdq::KernelInfo& info(sdq_ctx* ctx, int kind, int nt, int variant) {
 bool is_gang(int nt) { return nt > sdq::kMaxNT; }
 // the stabilized sweep runs as one workgroup up to kSweepMaxNT tiles
 bool sweep_is_gang(int nt) { return nt > sdq::kSweepMaxNT; }
-bool launch_is_gang(int kind, int nt) { return kind == sdq::KK_SWEEP ? sweep_is_gang(nt) : is_gang(nt); }
+bool launch_is_gang(int kind, int nt) {
+  return kind == sdq::KK_SWEEP || kind == sdq::KK_PROD ? sweep_is_gang(nt) : is_gang(nt);
+}
 
 // gangs of tile count nt that fit the device at once (cached)
 int gang_slots(sdq_ctx* ctx, int nt) {
@@ -428,12 +441,13 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
     if (P.swz_ready) B.swz.clear();
   }
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  int nq = (int)P.sweep_ranges.size();
+  int nq = (int)P.sweep_ranges.size() + (int)P.prod_ranges.size();
   for (int md = 0; md < sdq::kPairModes; ++md) nq += (int)P.pair_ranges[md].size();
   const size_t o_inst = 0;
   const size_t o_sw = align(o_inst + P.inst.size() * sizeof(Inst));
+  const size_t o_pr = align(o_sw + P.sweep.size() * sizeof(SweepItem));
   size_t o_pa[sdq::kPairModes];
-  size_t o = align(o_sw + P.sweep.size() * sizeof(SweepItem));
+  size_t o = align(o_pr + P.prod.size() * sizeof(SweepItem));
   for (int md = 0; md < sdq::kPairModes; ++md) {
     o_pa[md] = o;
     o = align(o + P.pair[md].size() * sizeof(PairItem));
@@ -445,6 +459,7 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   char* h = B.image.data();
   if (!P.inst.empty()) memcpy(h + o_inst, P.inst.data(), P.inst.size() * sizeof(Inst));
   if (!P.sweep.empty()) memcpy(h + o_sw, P.sweep.data(), P.sweep.size() * sizeof(SweepItem));
+  if (!P.prod.empty()) memcpy(h + o_pr, P.prod.data(), P.prod.size() * sizeof(SweepItem));
   for (int md = 0; md < sdq::kPairModes; ++md)
     if (!P.pair[md].empty())
       memcpy(h + o_pa[md], P.pair[md].data(), P.pair[md].size() * sizeof(PairItem));
@@ -457,10 +472,19 @@ sdq_status build_plan(sdq_ctx* ctx, Plan& P, int32_t* status, int count, Built& 
   B.status = status;
   B.count = count;
   int qi = 0;
+  // the block products first: each runs before its class's sweep, in order
+  // on the class's stream
+  for (const auto& r : P.prod_ranges) {
+    const int grid = grid_for(ctx, sdq::KK_PROD, r.nt, 0, r.count);
+    B.launches.push_back(LaunchRec{sdq::KK_PROD, r.nt, 0, 0, grid, r.count, o_pr + r.off * sizeof(SweepItem),
+                                   o_q + (qi++) * sizeof(Queue), 0});
+  }
   for (const auto& r : P.sweep_ranges) {
     // (above kMaxNT tiles and up to kSweepMaxNT: the one-workgroup sweep with
-    // T and the factor store in workgroup scratch, variant 4)
+    // T and the factor store in workgroup scratch, variant 4; over block
+    // products, variant 6)
     const int variant = sweep_is_gang(r.nt) ? 0
+                        : ((P.bprod_mask >> r.nt) & 1u) ? 6
                         : r.nt > sdq::kMaxNT ? 4
                         : P.dense ? 3
                         : (ctx->stab == SDQ_STAB_SVD ? 2 : ctx->tune[r.nt].variant);
@@ -569,6 +593,8 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
     hipStream_t ls = stream_of(L);
     auto go = [&]() -> hipError_t {
       if (launch_is_gang(L.kind, L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
+      if (L.kind == sdq::KK_PROD)
+        return sdq::launch_prod(L.nt, d_inst, (const SweepItem*)(d + L.items_off), L.count, q, L.grid, ls);
       if (L.kind == sdq::KK_SWEEP)
         return sdq::launch_sweep(L.nt, L.variant, d_inst, (const SweepItem*)(d + L.items_off), L.count,
                                  q, L.grid, B.tscr_base ? B.tscr_base + L.tscr_off : nullptr, ls);
@@ -576,7 +602,10 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
                               d_ll, q, L.grid, ls);
     };
     // per-class name "<kernel>/nt<tiles>": sdq_kernel_stats("<kernel>") sums the classes
-    std::string nm = std::string(L.kind == sdq::KK_SWEEP ? "sweep" : names[L.mode]) + "/nt" +
+    std::string nm = std::string(L.kind == sdq::KK_SWEEP  ? "sweep"
+                                 : L.kind == sdq::KK_PROD ? "prod"
+                                                          : names[L.mode]) +
+                     "/nt" +
                      std::to_string(L.nt);
     if (timing) {
       sdq_status st = timed_on(ctx, nm, ls, go);
@@ -789,6 +818,7 @@ sdq_status sdq_create(sdq_ctx** out, int device, void* hip_stream) {
     for (int nt = 0; nt <= sdq::kMaxNT; ++nt) ctx->tune[nt].variant = atoi(v);
   if (const char* v = getenv("SDQ_BLOCKS_PER_CU"))
     for (int nt = 0; nt <= sdq::kMaxNT; ++nt) ctx->tune[nt].blocks_per_cu = atoi(v);
+  if (const char* v = getenv("SDQ_BLOCK_PRODUCTS")) ctx->bprod = std::min(2, std::max(0, atoi(v)));
   *out = ctx;
   return SDQ_OK;
 }
@@ -825,6 +855,7 @@ void sdq_destroy(sdq_ctx* ctx) {
   if (ctx->d_hmc.p) (void)hipFree(ctx->d_hmc.p);
   if (ctx->d_htab.p) (void)hipFree(ctx->d_htab.p);
   if (ctx->d_ctab.p) (void)hipFree(ctx->d_ctab.p);
+  if (ctx->d_prod.p) (void)hipFree(ctx->d_prod.p);
   for (auto& sl : ctx->stage)
     if (sl.h) (void)hipHostFree(sl.h);
   for (auto& kv : ctx->stats)
@@ -856,6 +887,48 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
   st = alloc_fin(ctx, inst, count, off);
   if (st) return st;
   Plan P;
+  // Block products first (k_prod: every block of k slices of every chain
+  // multiplied out at once), then the sweep over them with one
+  // factorization each: the same stabilized product (Sec. 4.1), with the
+  // sequential part of a chain cut to its factorizations.  Automatically
+  // for the tile class (kProdMinNT .. kSweepMaxNT tiles) that holds the
+  // batch's longest chain, when all of its chains are resident at once (then
+  // that chain's sweep is the batch's critical path); for every such class
+  // by the context's setting.
+  if (ctx->bprod != 0 && ctx->stab == SDQ_STAB_QR) {
+    int cnt_nt[sdq::kSweepMaxNT + 1] = {};
+    double longest = 0.0;
+    int crit = -1;
+    for (int i = 0; i < count; ++i) {
+      const int nt = nt_of(inst[i].n);
+      if (nt >= sdq::kProdMinNT && nt <= sdq::kSweepMaxNT) cnt_nt[nt] += 1;
+      const double c = sweep_cost(inst[i].n, inst[i].m, inst[i].k);
+      if (c > longest) {
+        longest = c;
+        crit = nt;
+      }
+    }
+    for (int nt = sdq::kProdMinNT; nt <= sdq::kSweepMaxNT; ++nt) {
+      if (cnt_nt[nt] == 0) continue;
+      if (ctx->bprod == 1 ||
+          (nt == crit && cnt_nt[nt] <= grid_for(ctx, sdq::KK_SWEEP, nt, 6, 1 << 30)))
+        P.bprod_mask |= 1u << nt;
+    }
+  }
+  double* prod_base = nullptr;
+  std::vector<int64_t> poff(count, -1);
+  if (P.bprod_mask) {
+    int64_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+      const int nt = nt_of(inst[i].n);
+      if (!((P.bprod_mask >> nt) & 1u)) continue;
+      poff[i] = tot;
+      tot += (int64_t)nb_of(inst[i].m, inst[i].k) * 256 * nt * nt;
+    }
+    hipError_t e = grow(ctx->d_prod, (size_t)tot * sizeof(double));
+    if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "block products: " + std::string(hipGetErrorString(e)));
+    prod_base = (double*)ctx->d_prod.p;
+  }
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
     I.scheme = scheme == SDQ_INV_PLAIN ? 1 : 0;
@@ -864,10 +937,29 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
     I.sign = sign ? sign + i : nullptr;
     I.status = status ? status + i : nullptr;
     I.fin = (double*)ctx->d_fin.p + off[i];
+    if (poff[i] >= 0) {
+      // the products' instance (slices as given, outputs none) and the
+      // sweep's (one dense slice per block, k = 1)
+      Inst Ip = base_inst(inst[i]);
+      Ip.prod = prod_base + poff[i];
+      const int ip = (int)P.inst.size();
+      P.inst.push_back(Ip);
+      for (int j = 0; j < I.nb; ++j) P.prod.push_back(SweepItem{ip, 0, j, 0});
+      I.expk = nullptr;
+      I.expk_inv = nullptr;
+      I.field = Ip.prod;
+      I.m = I.nb;
+      I.k = 1;
+    }
+    const int id = (int)P.inst.size();
     P.inst.push_back(I);
-    P.sweep.push_back(SweepItem{i, sdq::SW_LAST, 0, 0});
-    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{i, I.nb, 0, 0});
+    P.sweep.push_back(SweepItem{id, sdq::SW_LAST, 0, 0});
+    P.pair[sdq::PAIR_EQUAL].push_back(PairItem{id, I.nb, 0, 0});
   }
+  order_items(P.inst, P.prod, P.prod_ranges, [&](const SweepItem& w) {
+    const Inst& I = P.inst[w.inst];
+    return (double)I.n * I.n * I.n * std::min(I.k, I.m - w.j * I.k);
+  });
   order_items(P.inst, P.sweep, P.sweep_ranges, [&](const SweepItem& w) {
     const Inst& I = P.inst[w.inst];
     return sweep_cost(I.n, I.m, I.k);
