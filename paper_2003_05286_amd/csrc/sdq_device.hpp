@@ -1813,6 +1813,48 @@ __device__ __forceinline__ void stage_to(const Lane& L, double* dst, const doubl
     }
   }
 }
+// stage_to for two matrices at once: every load of both goes out before any
+// store, so the pair costs one memory latency instead of one per batch of
+// eight (where the loads of both fit in 16 values per thread; else one after
+// the other, as for a null source)
+template <int NT, int P>
+__device__ __forceinline__ void stage_to2(const Lane& L, double* dst_a, const double* src_a, double* dst_b,
+                                          const double* src_b, int n) {
+  using G = Geo<NT, P>;
+  constexpr int TOT = G::NP * G::NP, IT = (TOT + G::THREADS - 1) / G::THREADS;
+  if constexpr (IT > 16) {
+    stage_to<NT, P>(L, dst_a, src_a, n);
+    stage_to<NT, P>(L, dst_b, src_b, n);
+  } else {
+    if (src_a == nullptr || src_b == nullptr) {
+      stage_to<NT, P>(L, dst_a, src_a, n);
+      stage_to<NT, P>(L, dst_b, src_b, n);
+      return;
+    }
+    const auto* ga = gmem(src_a);
+    const auto* gb = gmem(src_b);
+    double xa[IT], xb[IT];
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int idx = L.t + q * G::THREADS;
+      const int i = idx / G::NP, k = idx - i * G::NP;
+      const size_t o = (size_t)min(i, n - 1) * n + min(k, n - 1);
+      xa[q] = ga[o];
+      xb[q] = gb[o];
+    }
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int idx = L.t + q * G::THREADS;
+      const int i = idx / G::NP, k = idx - i * G::NP;
+      if (idx < TOT) {
+        const bool in = i < n && k < n;
+        dst_a[i * G::LDR + k] = in ? xa[q] : 0.0;
+        dst_b[i * G::LDR + k] = in ? xb[q] : 0.0;
+      }
+    }
+  }
+}
+
 template <int NT, int P, bool ELDS>
 __device__ __forceinline__ void stage_mat(const Lane& L, Smem<NT, P, ELDS>& S, const double* src,
                                           int n) {
@@ -1897,16 +1939,14 @@ __device__ __forceinline__ void pair_tdisp(const Lane& L, Smem<NT, P, ELDS>& S, 
     // operands staged through LDS with coalesced loads, two matrices per
     // round (S.R is free until the solve parks its factor there)
     __syncthreads();
-    stage_to<NT, P>(L, S.R, T2, n);
-    stage_to<NT, P>(L, S.E, T1, n);
+    stage_to2<NT, P>(L, S.R, T2, S.E, T1, n);
     __syncthreads();
     load_lds_rm<NT, P>(L, S.R, B, true);  // T2^T
     gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.E[i * G::LDR + kk]; }, B,
                    P2);
     load_lds_rm<NT, P>(L, S.E, Y, false);  // T1 (right-hand sides)
     __syncthreads();
-    stage_to<NT, P>(L, S.R, U1, n);
-    stage_to<NT, P>(L, S.E, U2, n);  // stays in S.E for the final product
+    stage_to2<NT, P>(L, S.R, U1, S.E, U2, n);  // U2 stays in S.E for the final product
     __syncthreads();
     load_lds_rm<NT, P>(L, S.E, B, false);  // U2
     gemm_rb<NT, P>(L, [&](int, int, int, int i, int kk) -> double { return S.R[kk * G::LDR + i]; }, B,
