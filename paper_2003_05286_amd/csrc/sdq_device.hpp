@@ -1673,10 +1673,10 @@ __device__ __forceinline__ void pair_equal(const Lane& L, Smem<NT, P, ELDS>& S, 
   __syncthreads();
 }
 
+// The sweep kernel's work loop: items from the queue until it is empty.
 template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false, bool PSW = false>
-__global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
-                                                            const SweepItem* __restrict__ items,
-                                                            int count, Queue* q, double* tscr) {
+__device__ __forceinline__ void sweep_items(const Inst* __restrict__ insts, const SweepItem* __restrict__ items,
+                                            int count, Queue* q, double* tscr) {
   __shared__ Smem<NT, P, ELDS> S;
   const Lane L = lane_id();
   // this workgroup's T scratch (TG): one register matrix, lanes contiguous;
@@ -1701,6 +1701,14 @@ __global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __re
     sweep_one<NT, P, ELDS, SVD, DENSE, TG, PSW>(L, S, I, wi.flags, wi.j, ts);
   }
 }
+
+template <int NT, int P, bool ELDS, bool SVD = false, bool DENSE = false, bool TG = false, bool PSW = false>
+__global__ __launch_bounds__(64 * P, minb_for(NT)) void k_sweep(const Inst* __restrict__ insts,
+                                                            const SweepItem* __restrict__ items,
+                                                            int count, Queue* q, double* tscr) {
+  sweep_items<NT, P, ELDS, SVD, DENSE, TG, PSW>(insts, items, count, q, tscr);
+}
+
 
 // Block products of a chain's slices, P_j = B_{q1} ... B_{q0} for the k
 // slices q0 = jk + 1 .. q1 = min((j+1)k, m) of block j (the product of k
