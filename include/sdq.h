@@ -119,7 +119,15 @@ const char* sdq_version(void);
  *           may be NULL: then only logdet/sign are produced for it)
  *   logdet, sign  device arrays [count] (may be NULL)
  *   status  device array [count] (may be NULL)
- * Chains of different n, m, k may be mixed in one call. */
+ * Chains of different n, m, k may be mixed in one call.  For the size class
+ * (97 <= n <= 144) of the batch's longest chain, when all of that class's
+ * chains are resident on the device at once, the products of each block of
+ * k slices are formed first, all at once, and the chain's stabilized product
+ * is taken over them (Sec. 4.1; the same product up to rounding); this uses
+ * ceil(m/k) (16 ceil(n/16))^2 doubles of library memory per such chain and
+ * is skipped when that memory cannot be allocated.  The environment variable
+ * SDQ_BLOCK_PRODUCTS (read by sdq_create: 0 never, 1 for every class of
+ * 97 <= n <= 144, 2 the default above) overrides the choice. */
 sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq_scheme scheme,
                       double* const* g, double* logdet, double* sign, int32_t* status);
 

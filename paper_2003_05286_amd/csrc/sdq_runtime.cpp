@@ -925,9 +925,15 @@ sdq_status sdq_greens(sdq_ctx* ctx, const sdq_instance* inst, int32_t count, sdq
       poff[i] = tot;
       tot += (int64_t)nb_of(inst[i].m, inst[i].k) * 256 * nt * nt;
     }
-    hipError_t e = grow(ctx->d_prod, (size_t)tot * sizeof(double));
-    if (e != hipSuccess) return fail(ctx, SDQ_ENOMEM, "block products: " + std::string(hipGetErrorString(e)));
-    prod_base = (double*)ctx->d_prod.p;
+    // the products only shorten the critical path: without memory for
+    // them the classes sweep over the slices as they are
+    if (grow(ctx->d_prod, (size_t)tot * sizeof(double)) == hipSuccess) {
+      prod_base = (double*)ctx->d_prod.p;
+    } else {
+      (void)hipGetLastError();
+      P.bprod_mask = 0;
+      std::fill(poff.begin(), poff.end(), -1);
+    }
   }
   for (int i = 0; i < count; ++i) {
     Inst I = base_inst(inst[i]);
