@@ -134,6 +134,22 @@ __device__ __forceinline__ Lane lane_id() {
   return L;
 }
 
+// The same indices, opaque to the optimizer: called once per work item of a
+// persistent loop, so that the addresses derived from them are recomputed
+// for each item (a few integer instructions) instead of being hoisted out of
+// the loop and kept, or spilled, across it.
+__device__ __forceinline__ Lane lane_id_per_item() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  Lane L;
+  L.t = t;
+  L.w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+  L.l = t & 63;
+  L.g = L.l >> 4;
+  L.cl = L.l & 15;
+  return L;
+}
+
 template <int NT, int P>
 __device__ __forceinline__ bool tile_ok(const Lane& L, int c) {
   return L.w + Geo<NT, P>::P * c < NT;
@@ -1506,6 +1522,7 @@ __device__ __forceinline__ void sweep_one(const Lane& L, Smem<NT, P, ELDS>& S, c
   double sgn_run = (block && jpair > 0) ? gmem(I.ckf + (size_t)(jpair - 1) * sd)[2 * (size_t)n * n + n] : 1.0;
 
   for (int s = s_lo; s < s_hi; ++s) {
+    const Lane L = lane_id_per_item();
     const int b = adj ? nb - 1 - s : s;
     int q0 = b * k + 1, q1 = (b + 1) * k < m ? (b + 1) * k : m;
     if (left) {
@@ -2521,10 +2538,9 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     const Inst* __restrict__ insts, const PairItem* __restrict__ items, int count,
     const int32_t* __restrict__ l_list, Queue* q) {
   __shared__ Smem<NT, P, ELDS> S;
-  const Lane L = lane_id();
   for (;;) {
     __syncthreads();
-    if (L.t == 0) S.item = atomicAdd(&q->next, 1);
+    if (threadIdx.x == 0) S.item = atomicAdd(&q->next, 1);
     __syncthreads();
     // the item is the same for the whole workgroup: scalar loads of the item,
     // its instance and every pointer in it
@@ -2532,6 +2548,7 @@ __global__ __launch_bounds__(64 * P, minb_pair(NT, MODE)) void k_pair(
     if (it >= count) break;
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
+    const Lane L = lane_id_per_item();
     if constexpr (MODE == PAIR_LOCAL) {
       const Inst I1 = wi.ilo > 1 ? insts[wi.inst + 1] : I;
       pair_local<NT, P, ELDS>(L, S, I, I1, wi.ilo, wi.j);

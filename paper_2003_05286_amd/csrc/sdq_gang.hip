@@ -1287,6 +1287,18 @@ __device__ GC gang_ctx(const GangArgs& a) {
   return c;
 }
 
+// The thread's indices in c, made opaque to the optimizer: called once per
+// item of a kernel's loop, so that the addresses derived from them are
+// recomputed for each item (a few integer instructions) instead of being
+// hoisted out of the loop and kept, or spilled, across it.
+__device__ __forceinline__ void gang_lanes_per_item(GC& c) {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  c.t = t;
+  c.w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+  c.l = t & 63;
+}
+
 template <int RL>
 __global__ __launch_bounds__(kGangThreads, 1) void k_gang_sweep(const Inst* __restrict__ insts,
                                                                  const SweepItem* __restrict__ items,
@@ -1297,6 +1309,7 @@ __global__ __launch_bounds__(kGangThreads, 1) void k_gang_sweep(const Inst* __re
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
     c.n = I.n;
+    gang_lanes_per_item(c);
     sweep_gang<RL>(c, I, wi.flags);
   }
 }
@@ -1312,6 +1325,7 @@ __global__ __launch_bounds__(kGangThreads, 1) void k_gang_pair(const Inst* __res
     const PairItem wi = items[it];
     const Inst I = insts[wi.inst];
     c.n = I.n;
+    gang_lanes_per_item(c);
     if (MODE == PAIR_EQUAL) equal_gang<RL>(c, I);
     else if (MODE == PAIR_TDISP) tdisp_gang<RL>(c, I, wi.j, wi.ilo, wi.ihi, l_list);
     else grad_gang<RL>(c, I, wi.j);
