@@ -1749,22 +1749,23 @@ __global__ __launch_bounds__(64 * P, 2) void k_prod(const Inst* __restrict__ ins
                                                     const SweepItem* __restrict__ items, int count, Queue* q) {
   using G = Geo<NT, P>;
   __shared__ ProdSmem<NT, P> S;
-  const Lane L = lane_id();
   for (;;) {
     __syncthreads();
-    if (L.t == 0) S.item = atomicAdd(&q->next, 1);
+    if (threadIdx.x == 0) S.item = atomicAdd(&q->next, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(S.item);
     if (it >= count) break;
     const SweepItem wi = items[it];
     const Inst I = insts[wi.inst];
+    const Lane L = lane_id_per_item();
     const int n = I.n, j = wi.j;
     const int q0 = j * I.k + 1, q1 = (j + 1) * I.k < I.m ? (j + 1) * I.k : I.m;
     const int cnt = q1 - q0 + 1;
-    const EOp<NT, P, false> eop{nullptr, I.esw, L.l};
     RM<NT, P> W;
     load_rm<NT, P>(L, W, I.expk, n, false);
     for (int c0 = 0; c0 < cnt; c0 += G::KB) {
+      const Lane L = lane_id_per_item();
+      const EOp<NT, P, false> eop{nullptr, I.esw, L.l};
       const int cn = (cnt - c0) < G::KB ? (cnt - c0) : G::KB;
       fill_vbuf_to<NT, P>(L, S.vbuf, I, q0 + c0, +1, cn, 1.0);
       for (int s2 = 0; s2 < cn; ++s2) {
