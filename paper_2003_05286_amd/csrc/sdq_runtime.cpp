@@ -559,10 +559,10 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   // Stream of each launch.  The items of different tile classes belong to
   // different chains, so the classes are independent: each class of the
   // one-workgroup kernels runs in order on a side stream of its own, forked
-  // from s after the upload and joined back into s, and the classes above
-  // kMaxNT tiles (gang kernels, which share the gang scratch, and the
-  // one-workgroup sweeps whose stages the gang pair kernels read) run in
-  // order on s.  A batch of one class stays on s.
+  // from s after the upload and the block products and joined back into s,
+  // and the classes above kMaxNT tiles (gang kernels, which share the gang
+  // scratch, and the one-workgroup sweeps whose stages the gang pair
+  // kernels read) run in order on s.  A batch of one class stays on s.
   std::vector<int> cls;  // distinct one-workgroup tile classes, first-seen order
   bool any_gang = false;
   for (const LaunchRec& L : B.launches) {
@@ -571,26 +571,13 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
   }
   const bool fork = B.fork && (int)cls.size() + (any_gang ? 1 : 0) > 1;
   int nside = 0;
-  if (fork) {
-    nside = std::min((int)cls.size(), (int)sdq_ctx::kSide);
-    for (int i = 0; i < nside; ++i) {
-      if (!ctx->side[i])
-        HIP_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking), "hipStreamCreate(side)");
-      if (!ctx->ev_join[i])
-        HIP_TRY(hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming), "hipEventCreate(join)");
-    }
-    if (!ctx->ev_fork) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
-    HIP_TRY(hipEventRecord(ctx->ev_fork, s), "hipEventRecord(fork)");
-    for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(ctx->side[i], ctx->ev_fork, 0), "hipStreamWaitEvent");
-  }
   auto stream_of = [&](const LaunchRec& L) -> hipStream_t {
     if (!fork || L.nt > sdq::kMaxNT) return s;
     const int c = (int)(std::find(cls.begin(), cls.end(), L.nt) - cls.begin());
     return ctx->side[c % nside];
   };
-  for (const LaunchRec& L : B.launches) {
+  auto launch_on = [&](const LaunchRec& L, hipStream_t ls) -> sdq_status {
     Queue* q = (Queue*)(d + L.queue_off);
-    hipStream_t ls = stream_of(L);
     auto go = [&]() -> hipError_t {
       if (launch_is_gang(L.kind, L.nt)) return launch_gang_rec(ctx, L, d_inst, d, d_ll, ls);
       if (L.kind == sdq::KK_PROD)
@@ -607,13 +594,35 @@ sdq_status enqueue_built(sdq_ctx* ctx, const Built& B, hipStream_t s, char* d, c
                                                           : names[L.mode]) +
                      "/nt" +
                      std::to_string(L.nt);
-    if (timing) {
-      sdq_status st = timed_on(ctx, nm, ls, go);
+    if (timing) return timed_on(ctx, nm, ls, go);
+    hipError_t e = go();
+    return e != hipSuccess ? hip_fail(ctx, e, nm.c_str()) : SDQ_OK;
+  };
+  // Block products first, on s and before the fork: they spread over the
+  // whole device, and the classes on side streams start after them instead
+  // of sharing the CUs with them (their class holds the batch's longest
+  // chains, so its sweep, after them, is the step's critical path).
+  for (const LaunchRec& L : B.launches)
+    if (L.kind == sdq::KK_PROD) {
+      sdq_status st = launch_on(L, s);
       if (st) return st;
-    } else {
-      hipError_t e = go();
-      if (e != hipSuccess) return hip_fail(ctx, e, nm.c_str());
     }
+  if (fork) {
+    nside = std::min((int)cls.size(), (int)sdq_ctx::kSide);
+    for (int i = 0; i < nside; ++i) {
+      if (!ctx->side[i])
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking), "hipStreamCreate(side)");
+      if (!ctx->ev_join[i])
+        HIP_TRY(hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming), "hipEventCreate(join)");
+    }
+    if (!ctx->ev_fork) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipEventRecord(ctx->ev_fork, s), "hipEventRecord(fork)");
+    for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(ctx->side[i], ctx->ev_fork, 0), "hipStreamWaitEvent");
+  }
+  for (const LaunchRec& L : B.launches) {
+    if (L.kind == sdq::KK_PROD) continue;
+    sdq_status st = launch_on(L, stream_of(L));
+    if (st) return st;
   }
   if (fork) {
     for (int i = 0; i < nside; ++i) {
