@@ -253,8 +253,26 @@ __device__ void gang_assemble(GC& c) {
 __device__ __forceinline__ void st_coh(double* p, double x) {
   __hip_atomic_store(gmem(p), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_coh(const double* p) {
-  return __hip_atomic_load(gmem(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Row p and rows lane + 64 s (s < RL) of a column published by another
+// member: device-scope coherent loads (the system-coherence bit, which is
+// what a relaxed device-scope atomic load is on this target) through a
+// buffer resource, all issued before any is used.  As atomic loads the
+// compiler waits for each one before issuing the next, which costs one
+// memory round trip per row slot.  col is wave-uniform; entries past npad
+// read as zero.
+template <int RL>
+__device__ __forceinline__ void ld_coh_col(const double* col, int npad, int l, int p, double& at_p,
+                                           double (&x)[RL]) {
+  constexpr int kCohSys = 16;  // cache policy: system-coherent scope
+  const unsigned long long a = (unsigned long long)col;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), (short)0, npad * 8, 0x00020000);
+  at_p = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, p * 8, 0, kCohSys));
+#pragma unroll
+  for (int s = 0; s < RL; ++s)
+    x[s] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (l + 64 * s) * 8, 0, kCohSys));
 }
 __device__ __forceinline__ void st_coh_u64(double* p, unsigned long long x) {
   __hip_atomic_store(gmem((unsigned long long*)p), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -579,12 +597,12 @@ __device__ void cpqr_gang(GC& c_io) {
     const double* xs = cb + (int64_t)owner * gang_cand_stride(c.geo);
     double v[kRL];  // the winner column below row p, then the reflector
     double am = 0.0;
-    const double al = ld_coh(xs + p);
+    double al;
+    ld_coh_col<kRL>(xs, c.geo.npad, c.l, p, al, v);
 #pragma unroll
     for (int s = 0; s < kRL; ++s) {
       const int i = c.l + 64 * s;
-      const double x = ld_coh(xs + min(i, c.geo.npad - 1));
-      v[s] = (s < nrl && i > p && i < n) ? x : 0.0;
+      v[s] = (s < nrl && i > p && i < n) ? v[s] : 0.0;
       am = fmax(am, fabs(v[s]));
     }
     am = wave_max(am);
