@@ -489,6 +489,7 @@ __device__ void slab_identity(GC& c) {
 // ---- column-pivoted QR of the gang's matrix --------------------------------
 // Publish this member's best live column (rows p..n-1) and its key into
 // candidate buffer p & 1.
+template <int RL>
 __device__ void publish_candidate(GC& c, int p) {
   unsigned long long best = 0;
   for (int cc = c.w; cc < c.geo.w; cc += kWaves)
@@ -506,7 +507,21 @@ __device__ void publish_candidate(GC& c, int p) {
       int cc = key_col(k) - c.c0;
       cc = cc < 0 ? 0 : (cc >= c.geo.w ? c.geo.w - 1 : cc);
       const double* col = L.S + cc * c.geo.ldr;
-      for (int i = p + c.l; i < c.n; i += 64) st_coh(out + i, col[i]);
+      if constexpr (RL <= 4) {
+        // all of the lane's rows read from LDS before any is stored (with
+        // more rows per lane the registers this takes cost more than the
+        // LDS waits it saves)
+        double x[RL];
+#pragma unroll
+        for (int s = 0; s < RL; ++s) x[s] = col[min(c.l + 64 * s, c.geo.npad - 1)];
+#pragma unroll
+        for (int s = 0; s < RL; ++s) {
+          const int i = c.l + 64 * s;
+          if (i >= p && i < c.n) st_coh(out + i, x[s]);
+        }
+      } else {
+        for (int i = p + c.l; i < c.n; i += 64) st_coh(out + i, col[i]);
+      }
     }
     // the column is complete at the coherence point before its key appears
     __builtin_amdgcn_s_waitcnt(0);
@@ -586,7 +601,7 @@ __device__ void cpqr_gang(GC& c_io) {
     }
   }
   __syncthreads();
-  publish_candidate(c, 0);
+  publish_candidate<kRL>(c, 0);
   const int nrl = (n + 63) / 64;
   for (int p = 0; p < n; ++p) {
     const double* cb = sc_cand(c, p & 1);
@@ -705,7 +720,7 @@ __device__ void cpqr_gang(GC& c_io) {
         L.vn2[cc] = n2;
       }
     }
-    if (p + 1 < n) publish_candidate(c, p + 1);
+    if (p + 1 < n) publish_candidate<kRL>(c, p + 1);
   }
   __syncthreads();
   // R P^T and the reflectors to HBM
