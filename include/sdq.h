@@ -38,9 +38,11 @@
  * SDQ_EUNSUPPORTED.
  * Chains of different size classes (16-wide tile counts) in one call run
  * concurrently: each class of the one-workgroup kernels on a stream of its
- * own forked from the context's stream, the gang classes on the context's
- * stream; all of them are joined back into the context's stream before the
- * call's work ends, so callers see ordinary stream order.  Every wait of a
+ * own forked from the context's stream (after the block products of
+ * sdq_greens, which run first, alone, on the context's stream), the gang
+ * classes on the context's stream; all of them are joined back into the
+ * context's stream before the call's work ends, so callers see ordinary
+ * stream order.  Every wait of a
  * gang is bounded: its members must all be running within 60 s of the
  * first one (other classes of the call may hold the CUs until they finish)
  * and every wait inside a factorization ends after 4 s; a gang that gives
